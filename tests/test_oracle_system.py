@@ -1,0 +1,157 @@
+"""Pins for the oracle's element integrals and dense system (Sec. 2, eqs. 6-9).
+
+Element level: the Struve closed form against adaptive quadrature, the
+Laplace limit of the self hypersingular term, the Maue identity against the
+directly integrated hypersingular kernel, and kernel derivatives against
+finite differences.  System level: the Mie series for one fibre in free space
+(first-order convergence under refinement), vanishing scattered field without
+contrast, block-size invariance of the periodic system and the flux balance
+over the propagating Bragg orders.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import hankel1
+
+import workloads as W
+from analytic import mie_scattered
+from oracle import elements as el
+from oracle import fields as fl
+from oracle import system as sy
+from oracle.kernels import grad_x_phi, kernels_sdkt, phi
+
+
+def test_int_h0_closed_form():
+    for x in (1e-4, 0.01, 0.3, 2.0, 7.5):
+        re = quad(lambda t: hankel1(0, t).real, 0, x, epsabs=1e-15, epsrel=1e-14, limit=200)[0]
+        im = quad(lambda t: hankel1(0, t).imag, 0, x, epsabs=1e-15, epsrel=1e-14, limit=200)[0]
+        assert abs(el.int_h0(x) - (re + 1j * im)) < 1e-12 * abs(re + 1j * im)
+
+
+def test_self_T_laplace_limit():
+    """kappa -> 0: the finite part of the Laplace hypersingular operator on a
+    straight chord at its midpoint is -2/(pi h)."""
+    h = 0.01
+    _, _, _, T = el.self_terms(1e-7, np.array([h]))
+    assert abs(T[0].real - (-2.0 / (math.pi * h))) < 1e-6 * 2.0 / (math.pi * h)
+
+
+def test_self_T_is_limit_off_element():
+    """T_self is the limit of the Maue form of T_e(x) as x approaches the midpoint."""
+    kap, h = 3.0, 0.02
+    a = np.array([-h / 2, 0.0])
+    b = np.array([h / 2, 0.0])
+    n_e = np.array([0.0, -1.0])           # tangent (1,0) -> normal (t_y, -t_x)
+    nu = n_e
+    vals = []
+    for eps in (1e-3 * h, 5e-4 * h):
+        x = np.array([0.0, 0.0]) + eps * nu
+        # exact S_e(x) by quadrature, gradients at the chord ends in closed form
+        Sre = quad(lambda s: phi(kap, x[0] - s, x[1]).real, -h / 2, h / 2, points=[0.0],
+                   epsabs=1e-16, epsrel=1e-13, limit=400)[0]
+        Sim = quad(lambda s: phi(kap, x[0] - s, x[1]).imag, -h / 2, h / 2, points=[0.0],
+                   epsabs=1e-16, epsrel=1e-13, limit=400)[0]
+        gb = np.array(grad_x_phi(kap, x[0] - b[0], x[1] - b[1]))
+        ga = np.array(grad_x_phi(kap, x[0] - a[0], x[1] - a[1]))
+        tau = np.array([-nu[1], nu[0]])
+        vals.append(kap ** 2 * (Sre + 1j * Sim) - tau @ (gb - ga))
+    ext = 2 * vals[1] - vals[0]            # linear extrapolation to eps = 0
+    _, _, _, T = el.self_terms(kap, np.array([h]))
+    assert abs(ext - T[0]) < 1e-5 * abs(T[0])
+
+
+def test_maue_identity_vs_direct_hypersingular_integral():
+    """Near pairs: integrating the T kernel equals the Maue form."""
+    kap = 2.5
+    wl = W.tiny()
+    pb = sy.problem_from_workload(wl, 2.0, 0.3, periodic=False)
+    bd = pb.bd
+    for tgt, src in ((10, 11), (10, 12), (40, 38)):
+        x, nu = bd.mid[tgt], bd.nrm[tgt]
+        nr = el.near_rule([kap], x[None], nu[None], bd.mid[[src]], bd.tan[[src]], bd.nrm[[src]],
+                          bd.h[[src]])
+        S, T = nr[0, 0, 0], nr[0, 3, 0]
+        gb = np.array(grad_x_phi(kap, *(x - bd.b_pt[src])))
+        ga = np.array(grad_x_phi(kap, *(x - bd.a_pt[src])))
+        tau = np.array([-nu[1], nu[0]])
+        maue = kap ** 2 * (nu @ bd.nrm[src]) * S - tau @ (gb - ga)
+        assert abs(maue - T) < 1e-11 * abs(T)
+
+
+def test_kernel_derivatives_finite_difference():
+    kap = 1.7
+    x = np.array([0.3, -0.2])
+    y = np.array([-0.1, 0.25])
+    nu = np.array([0.6, 0.8])
+    n = np.array([-0.28, 0.96])
+    eps = 1e-5
+    S, D, K, T = kernels_sdkt(kap, *(x - y), *nu, *n)
+    s = lambda xx, yy: phi(kap, *(xx - yy))
+    D_fd = (s(x, y + eps * n) - s(x, y - eps * n)) / (2 * eps)
+    K_fd = (s(x + eps * nu, y) - s(x - eps * nu, y)) / (2 * eps)
+    d = lambda xx: kernels_sdkt(kap, *(xx - y), *nu, *n)[1]
+    T_fd = (d(x + eps * nu) - d(x - eps * nu)) / (2 * eps)
+    assert abs(D - D_fd) < 1e-8 * abs(D)
+    assert abs(K - K_fd) < 1e-8 * abs(K)
+    assert abs(T - T_fd) < 1e-7 * abs(T)
+
+
+def _mie_error(N):
+    wl = W.tiny()
+    wl.n_elem = N
+    pb = sy.problem_from_workload(wl, 2.0, math.pi / 4, periodic=False)
+    psi, _, _ = sy.solve(pb)
+    c = pb.bd.centres[0]
+    ang = np.linspace(0, 2 * np.pi, 13)[:-1]
+    pts = c + 0.6 * np.stack([np.cos(ang), np.sin(ang)], 1)
+    us = sy.potential(pb, psi, pts)
+    um = mie_scattered(pb.k, pb.k1, 0.3, wl.rho_fiber, wl.rho_matrix, pb.theta, c, pts)
+    return np.max(np.abs(us - um)) / np.max(np.abs(um))
+
+
+def test_mie_series_first_order_convergence():
+    e = [_mie_error(N) for N in (64, 128, 256)]
+    assert e[2] < 8e-3
+    for a, b in zip(e, e[1:]):
+        assert 1.8 < a / b < 2.2
+
+
+def test_no_contrast_no_scattering():
+    wl = W.tiny()
+    wl.n_elem = 128
+    wl.rho_fiber, wl.c_fiber = wl.rho_matrix, wl.c_matrix
+    pb = sy.problem_from_workload(wl, 2.0, math.pi / 4)
+    psi, _, B = sy.solve(pb)
+    n, kap, gam, R, T = fl.bragg(pb, psi, 3)
+    prop = np.abs(gam.imag) < 1e-14
+    assert np.max(np.abs(R[prop])) < 1e-5 and np.max(np.abs(T[prop])) < 1e-5
+
+
+def test_block_size_invariance():
+    """The same crystal solved with M_H = 1 and M_H = 2: the second row of
+    fibres carries exactly alpha_a = exp(i k a sin theta) times the first."""
+    ka, th = 2.0, 0.35
+    w1 = W.small_square(1, 1, 64, 0.3, ka, th)
+    w2 = W.small_square(1, 2, 64, 0.3, ka, th)
+    p1 = sy.problem_from_workload(w1, ka, th)
+    p2 = sy.problem_from_workload(w2, ka, th)
+    s1, _, _ = sy.solve(p1)
+    s2, _, _ = sy.solve(p2)
+    n = 2 * 64
+    aa = np.exp(1j * ka * math.sin(th))
+    assert np.linalg.norm(s2[:n] - s1) < 1e-10 * np.linalg.norm(s1)
+    assert np.linalg.norm(s2[n:] - aa * s1) < 1e-10 * np.linalg.norm(s1)
+
+
+def test_energy_balance_converges():
+    res = []
+    for N in (64, 128):
+        wl = W.tiny()
+        wl.n_elem = N
+        pb = sy.problem_from_workload(wl, 2.0, math.pi / 4)
+        psi, _, _ = sy.solve(pb)
+        res.append(abs(fl.energy_residual(pb, psi)))
+    assert res[1] < 3e-3
+    assert 1.7 < res[0] / res[1] < 2.3
