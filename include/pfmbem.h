@@ -1,0 +1,191 @@
+/*
+ * pfmbem: periodic fast-multipole boundary element method for 2D acoustic
+ * transmission through periodic fibre media, on AMD MI355X (gfx950).
+ *
+ * Operation (Meng & Liu, "A periodic FM-BEM for solving the acoustic
+ * transmission problems in periodic media", Sec. 2 and 3):
+ *   A fundamental block of M = M_L x M_H fibres, periodic along y with period
+ *   H = M_H * a (eq. 3), quasi-periodic phase alpha = exp(i k H sin(theta)).
+ *   Each fibre boundary is cut into N straight chord elements with constant
+ *   densities and midpoint collocation.  The unknowns are the double-layer
+ *   density phi and the single-layer density varphi of the Kress
+ *   representation (eqs. 4-5), ordered per fibre as in eq. (9):
+ *       Psi = (phi_1[N], varphi_1[N], ..., phi_M[N], varphi_M[N]),
+ *   2*M*N complex128 values (interleaved re, im; 16 bytes each).
+ *   The library applies and solves (I - A) Psi = B of eq. (9), where the
+ *   exterior operators carry the infinite image sum (eqs. 7-8), by a fast
+ *   multipole method: quadtree per fibre, multipole moments with J_n, M2L
+ *   with H_n (Graf, eq. 10-13), and all far images folded into the top-level
+ *   local expansion by lattice sums (Sec. 3.3).
+ *
+ * Units: k = ka / a is the matrix wavenumber, k1 = k c_matrix / c_fibre the
+ * fibre wavenumber, varrho = rho_matrix / rho_fibre (eq. 6); theta is the
+ * incidence angle from +x, in radians; u_inc = exp(i k x.(cos th, sin th)).
+ *
+ * Conventions: every pointer argument named d_* is DEVICE memory owned by
+ * the caller (for example a torch tensor's data_ptr()); host arrays are
+ * owned by the caller as well.  The library owns only what it allocates in
+ * pfm_create / pfm_set_wave and frees it in pfm_destroy; pfm_matvec and
+ * pfm_solve allocate nothing.  All work is queued on the stream given to
+ * pfm_set_stream (default: the null stream); calls that return host values
+ * synchronise that stream.  Functions return PFM_OK or an error code; the
+ * message of the last error of a handle is returned by pfm_last_error.
+ * A handle is not thread-safe.
+ */
+#ifndef PFMBEM_H
+#define PFMBEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfm_problem pfm_problem;
+
+typedef enum {
+  PFM_OK = 0,
+  PFM_EINVAL = 1,       /* invalid argument (sizes, overlap, unsupported p) */
+  PFM_ENOMEM = 2,       /* device or host allocation failed */
+  PFM_EDEVICE = 3,      /* HIP runtime error */
+  PFM_ENOCONV = 4,      /* GMRES did not reach the tolerance; best iterate written */
+  PFM_EWOOD = 5,        /* too close to a Wood anomaly k H (1 +- sin th) = 2 pi n */
+  PFM_ENUMERIC = 6,     /* NaN/Inf in a residual norm */
+  PFM_ESTATE = 7        /* call order (e.g. matvec before pfm_set_wave) */
+} pfm_status;
+
+typedef enum { PFM_SQUARE = 0, PFM_HEXAGON = 1 } pfm_lattice;
+
+/* Fibre lattice (Sec. 2, Fig. 1).  Square: fibre (col i, row j) centred at
+ * ((i+1/2)a, (j+1/2)a).  Hexagon: ((i+1/2)(sqrt3/2)a, (j+1/2+(i mod 2)/2)a).
+ * Fibre index f = j*M_L + i.  radii: host array of M radii, or NULL to use r0
+ * for every fibre.  Boundary nodes c_f + r_f (cos t_e, sin t_e), t_e = 2 pi e/N. */
+typedef struct {
+  int lattice;
+  double a;
+  int M_L, M_H;
+  int n_elem;              /* N, elements per fibre, >= 8 */
+  const double* radii;     /* host, M entries, or NULL */
+  double r0;
+} pfm_geometry;
+
+/* Materials: fibre (rho_1, c_1), matrix (rho_2, c_2).  eta is the real
+ * coupling constant of eqs. (4)-(5); eta <= 0 selects eta = k. */
+typedef struct {
+  double rho_fiber, c_fiber, rho_matrix, c_matrix;
+  double eta;
+} pfm_material;
+
+/* Method settings.
+ *  p          expansion truncation -p..p; one of 8, 12, 16, 20, 24, 32, 40
+ *  leaf_max   maximum elements per quadtree leaf, 1..64
+ *  mac        admissibility ratio: cells D, C interact by M2L when
+ *             rho_D + rho_C <= mac * |O_D - O_C - m h|, 0 < mac < 1
+ *  g_far      Gauss-Legendre points per element for the far rule (4)
+ *  restart    GMRES restart length m (1..200); max_iter total iterations
+ *  tol        GMRES stop: true relative residual ||B - (I-A)Psi|| / ||B||
+ *  wood_margin  reject (PFM_EWOOD) when the distance of k H (1 +- sin th)/(2 pi)
+ *             to an integer is below this; 0 disables the check */
+typedef struct {
+  int p;
+  int leaf_max;
+  double mac;
+  int g_far;
+  int restart;
+  int max_iter;
+  double tol;
+  double wood_margin;
+} pfm_options;
+
+typedef struct {
+  int status;              /* pfm_status of the solve */
+  int iters;               /* GMRES iterations (matvecs inside Arnoldi) */
+  int matvecs;             /* total operator applications */
+  double rel_residual;     /* true relative residual of the returned Psi */
+  double t_solve_s;        /* wall time of the solve */
+} pfm_info;
+
+/* Sizes and counts of the built plan (for reports and tests). */
+typedef struct {
+  int M, N, E, n_unknowns;
+  int n_cells, n_leaves, depth;
+  int n_m2l_ext, n_m2l_int;    /* explicit M2L pairs, exterior / interior */
+  int n_near_pairs;            /* leaf pairs handled by P2P */
+  long long n_near_entries;    /* element pairs in P2P blocks */
+  long long n_near_cols;       /* sum over near leaf pairs of source elements */
+  int n_root_offsets;          /* distinct fibre offsets of the lattice M2L */
+  int n_m2l_offsets;           /* distinct M2L translation vectors */
+  double near_bytes;           /* bytes of the stored P2P blocks */
+  double k, k1, eta, varrho, theta;
+  int lattice_q;               /* direct images of the lattice sums, |m| <= q */
+} pfm_stats;
+
+/* Build the plan: discretisation (on the GPU), quadtrees and interaction
+ * lists (host).  Fills *out on success.  Errors: PFM_EINVAL for bad sizes,
+ * overlapping fibres (2 r >= lattice spacing) or unsupported options. */
+pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat,
+                      const pfm_options* opt, pfm_problem** out);
+
+/* Use this HIP stream (hipStream_t) for all later work; NULL = null stream. */
+pfm_status pfm_set_stream(pfm_problem* pb, void* hip_stream);
+
+/* Per-frequency setup for (ka, theta): P2P near blocks with the exact self and
+ * near element integrals, M2L/M2M/L2L translation tables at k and k1, and the
+ * lattice sums of the top-level M2L (Sec. 3.3).  Returns PFM_EWOOD before any
+ * work when the Wood margin test fails. */
+pfm_status pfm_set_wave(pfm_problem* pb, double ka, double theta);
+
+/* d_y = (I - A) d_psi, both 2*M*N complex128 on the device.  No allocation. */
+pfm_status pfm_matvec(pfm_problem* pb, const void* d_psi, void* d_y);
+
+/* d_b = B of eq. (9) for the current wave. */
+pfm_status pfm_rhs(pfm_problem* pb, void* d_b);
+
+/* Restarted GMRES for (I - A) Psi = B with the FMM apply.  d_b: right-hand
+ * side (NULL: B of eq. 9).  d_x: on entry the start vector when use_x0 != 0
+ * (else zero is used), on return the solution.  Returns PFM_ENOCONV when the
+ * tolerance is not met in max_iter iterations (d_x holds the best iterate). */
+pfm_status pfm_solve(pfm_problem* pb, const void* d_b, void* d_x, int use_x0,
+                     pfm_info* info);
+
+/* Reflected and transmitted Bragg amplitudes for orders -n_orders..n_orders
+ * (host arrays of 2*(2*n_orders+1) doubles, interleaved complex), the energy
+ * transmission coefficient of Sec. 4 and the flux-balance residual
+ * sum_prop gamma_n (|R_n|^2 + |delta_n0 + T_n|^2) / (k cos th) - 1. */
+pfm_status pfm_fields(pfm_problem* pb, const void* d_psi, int n_orders,
+                      double* R, double* T, double* etc, double* energy_residual);
+
+pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
+
+/* Mean duration (milliseconds) of each matvec stage over the last
+ * pfm_matvec_timed call: [P2M, M2M, M2L, lattice M2L, L2L, leaf (L2P+P2P)]. */
+pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
+                            int reps, double* stage_ms, double* total_ms);
+
+const char* pfm_last_error(const pfm_problem* pb);
+void pfm_destroy(pfm_problem* pb);
+
+/* ---- test hooks: expose single stages for parity tests ------------------ */
+
+/* Bessel J0, J1, Y0, Y1 of n arguments d_x > 0 on the device:
+ * d_out[4*i + (0..3)].  Special functions are written from DLMF 10.8
+ * (series), 10.17 (Hankel asymptotics), 10.23 (Neumann series) and Miller's
+ * backward recurrence (DLMF 3.6). */
+pfm_status pfm_test_bessel(const double* d_x, int n, double* d_out);
+
+/* Lattice sums of the current wave: host array [n_root_offsets][4p+1] complex,
+ * the offsets [n_root_offsets][2] and the excluded image range [m_lo, m_hi]. */
+pfm_status pfm_test_lattice(pfm_problem* pb, double* sums, double* offsets, int* mrange);
+
+/* Multipole moments of every cell for d_psi after the upward pass (P2M and
+ * M2M): host [n_cells][2 channels][2p+1] complex (channel 0: k, 1: k1), the
+ * cell centres [n_cells][2], per cell (level, fibre, first, end) into the
+ * tree-ordered element list, and that list (E natural element ids).
+ * Any output pointer may be NULL. */
+pfm_status pfm_test_moments(pfm_problem* pb, const void* d_psi, double* moments,
+                            double* centres, int* cellinfo, int* elem_order);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFMBEM_H */

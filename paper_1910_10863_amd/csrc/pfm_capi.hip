@@ -1,0 +1,659 @@
+// C ABI of the periodic FM-BEM library (declared in include/pfmbem.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pfm_kernels.hpp"
+
+using namespace pfm;
+
+struct pfm_problem {
+  Problem p;
+};
+
+namespace {
+
+const char* status_name(pfm_status s) {
+  switch (s) {
+    case PFM_OK: return "ok";
+    case PFM_EINVAL: return "invalid argument";
+    case PFM_ENOMEM: return "out of memory";
+    case PFM_EDEVICE: return "device error";
+    case PFM_ENOCONV: return "no convergence";
+    case PFM_EWOOD: return "Wood anomaly";
+    case PFM_ENUMERIC: return "non-finite value";
+    case PFM_ESTATE: return "call order";
+  }
+  return "?";
+}
+
+pfm_status fail(Problem& pb, pfm_status s, const std::string& msg) {
+  pb.err = std::string(status_name(s)) + ": " + msg;
+  return s;
+}
+
+#define HIPCHK(pb, call)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(pb, e_ == hipErrorOutOfMemory ? PFM_ENOMEM : PFM_EDEVICE,                  \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+template <typename T>
+hipError_t upload(T** d, const std::vector<T>& h) {
+  size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void**)d, bytes);
+  if (e != hipSuccess) return e;
+  if (!h.empty()) e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+template <typename T>
+void dfree(T*& d) {
+  if (d) (void)hipFree((void*)d);
+  d = nullptr;
+}
+
+void free_all(Problem& pb) {
+  dfree(pb.d_centres); dfree(pb.d_radii);
+  dfree(pb.d_mx); dfree(pb.d_my); dfree(pb.d_tx); dfree(pb.d_ty); dfree(pb.d_h);
+  dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of);
+  dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
+  dfree(pb.d_first_child); dfree(pb.d_n_child); dfree(pb.d_cell_joff); dfree(pb.d_parent);
+  dfree(pb.d_leaves); dfree(pb.d_root_of_fibre); dfree(pb.d_fibre_of_cell);
+  dfree(pb.d_m2l_ptr); dfree(pb.d_m2l_src); dfree(pb.d_m2l_off); dfree(pb.d_m2l_m);
+  dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
+  dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
+  dfree(pb.d_near_blk);
+  dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
+  dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
+  dfree(pb.d_near); dfree(pb.d_htab); dfree(pb.d_jtab); dfree(pb.d_lat); dfree(pb.d_alpha);
+  dfree(pb.d_srule);
+  dfree(pb.d_mpole); dfree(pb.d_local);
+  dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
+  dfree(pb.d_red); dfree(pb.d_hcol); dfree(pb.d_fields);
+  if (pb.h_hcol) (void)hipHostFree(pb.h_hcol);
+  pb.h_hcol = nullptr;
+  if (pb.events)
+    for (int i = 0; i < 16; ++i) (void)hipEventDestroy(pb.ev[i]);
+  pb.events = false;
+}
+
+double wood_distance(double k, double H, double th) {
+  double best = 1e300;
+  for (int s = -1; s <= 1; s += 2) {
+    double v = k * H * (1.0 + s * std::sin(th)) / (2.0 * PI);
+    best = std::min(best, std::fabs(v - std::nearbyint(v)));
+  }
+  return best;
+}
+
+// Composite Gauss-Legendre rule in s for the lattice-sum tails: panels
+// graded quadratically towards s = 0, where a near-Wood pole of
+// 1/(1 - e^{+-i beta - mu H}) sits, up to s_max where the Gaussian factor
+// exp(-((q+1)H - |Y|) s^2) has removed the integrand.
+void tail_rule(double k, double H, double gap, double xmax, int nu_max, std::vector<double>& rule) {
+  double smax = 1.0;
+  auto logmag = [&](double s) {
+    return -gap * s * s + std::sqrt(k) * xmax * s + nu_max * std::log(1.0 + (2.0 * s * s + k) / k);
+  };
+  while (logmag(smax) > -60.0) smax *= 1.2;
+  const int npan = 64, ng = 16;
+  std::vector<double> x, w;
+  gauss_legendre(ng, x, w);
+  rule.assign(2 * npan * ng, 0.0);
+  for (int p = 0; p < npan; ++p) {
+    double a = smax * std::pow((double)p / npan, 2.0);
+    double b = smax * std::pow((double)(p + 1) / npan, 2.0);
+    for (int g = 0; g < ng; ++g) {
+      rule[p * ng + g] = 0.5 * (a + b) + 0.5 * (b - a) * x[g];
+      rule[npan * ng + p * ng + g] = 0.5 * (b - a) * w[g];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pfm_options* opt,
+                      pfm_problem** out) {
+  if (!out) return PFM_EINVAL;
+  *out = nullptr;
+  pfm_problem* h = new (std::nothrow) pfm_problem();
+  if (!h) return PFM_ENOMEM;
+  Problem& pb = h->p;
+  auto bail = [&](pfm_status s) {
+    // keep the handle so that the caller can read the message
+    *out = h;
+    return s;
+  };
+  if (!geo || !mat || !opt) return bail(fail(pb, PFM_EINVAL, "null argument"));
+  if (geo->lattice != PFM_SQUARE && geo->lattice != PFM_HEXAGON)
+    return bail(fail(pb, PFM_EINVAL, "lattice must be square or hexagon"));
+  if (!(geo->a > 0) || geo->M_L < 1 || geo->M_H < 1 || geo->n_elem < 8)
+    return bail(fail(pb, PFM_EINVAL, "need a > 0, M_L >= 1, M_H >= 1, n_elem >= 8"));
+  if ((long long)geo->M_L * geo->M_H * geo->n_elem > (1LL << 26))
+    return bail(fail(pb, PFM_EINVAL, "too many elements"));
+  if (!supported_p(opt->p)) return bail(fail(pb, PFM_EINVAL, "p must be one of 8,12,16,20,24,32,40"));
+  if (opt->leaf_max < 1 || opt->leaf_max > 64) return bail(fail(pb, PFM_EINVAL, "leaf_max must be 1..64"));
+  if (!(opt->mac > 0.0 && opt->mac < 1.0)) return bail(fail(pb, PFM_EINVAL, "mac must be in (0,1)"));
+  if (opt->g_far < 1 || opt->g_far > 16) return bail(fail(pb, PFM_EINVAL, "g_far must be 1..16"));
+  if (opt->restart < 1 || opt->restart > 200 || opt->max_iter < 1 || !(opt->tol > 0))
+    return bail(fail(pb, PFM_EINVAL, "restart 1..200, max_iter >= 1, tol > 0"));
+  if (!(mat->rho_fiber > 0 && mat->c_fiber > 0 && mat->rho_matrix > 0 && mat->c_matrix > 0))
+    return bail(fail(pb, PFM_EINVAL, "materials must be positive"));
+
+  pb.lattice = geo->lattice;
+  pb.a = geo->a;
+  pb.ML = geo->M_L;
+  pb.MH = geo->M_H;
+  pb.M = pb.ML * pb.MH;
+  pb.N = geo->n_elem;
+  pb.E = pb.M * pb.N;
+  pb.opt = *opt;
+  pb.rho_f = mat->rho_fiber;
+  pb.c_f = mat->c_fiber;
+  pb.rho_m = mat->rho_matrix;
+  pb.c_m = mat->c_matrix;
+  pb.eta_user = mat->eta;
+  pb.radii.resize(pb.M);
+  for (int f = 0; f < pb.M; ++f) {
+    double r = geo->radii ? geo->radii[f] : geo->r0;
+    if (!(r > 0) || !(2.0 * r < pb.a))
+      return bail(fail(pb, PFM_EINVAL, "fibre radius must satisfy 0 < 2 r < a (fibres may not touch)"));
+    pb.radii[f] = r;
+  }
+  pb.centres.resize(2 * pb.M);
+  const double s3 = std::sqrt(3.0) / 2.0;
+  for (int j = 0; j < pb.MH; ++j)
+    for (int i = 0; i < pb.ML; ++i) {
+      int f = j * pb.ML + i;
+      if (pb.lattice == PFM_SQUARE) {
+        pb.centres[2 * f] = (i + 0.5) * pb.a;
+        pb.centres[2 * f + 1] = (j + 0.5) * pb.a;
+      } else {
+        pb.centres[2 * f] = (i + 0.5) * s3 * pb.a;
+        pb.centres[2 * f + 1] = (j + 0.5 + 0.5 * (i % 2)) * pb.a;
+      }
+    }
+  pb.L = pb.lattice == PFM_SQUARE ? pb.ML * pb.a : pb.ML * s3 * pb.a;
+  pb.H = pb.MH * pb.a;
+
+  // discretisation on the device
+  int E = pb.E;
+#define CK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) { free_all(pb); \
+    return bail(fail(pb, e_ == hipErrorOutOfMemory ? PFM_ENOMEM : PFM_EDEVICE, \
+                     std::string(#call) + ": " + hipGetErrorString(e_))); } } while (0)
+  CK(upload(&pb.d_centres, pb.centres));
+  CK(upload(&pb.d_radii, pb.radii));
+  CK(hipMalloc((void**)&pb.d_mx, E * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_my, E * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_tx, E * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_ty, E * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_h, E * sizeof(double)));
+  double* d_ends = nullptr;
+  CK(hipMalloc((void**)&d_ends, 4 * (size_t)E * sizeof(double)));
+  CK(launch_discretise(pb, d_ends));
+  std::vector<double> ends(4 * (size_t)E), mid(2 * (size_t)E), mx(E), my(E);
+  CK(hipMemcpy(ends.data(), d_ends, ends.size() * sizeof(double), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(mx.data(), pb.d_mx, E * sizeof(double), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(my.data(), pb.d_my, E * sizeof(double), hipMemcpyDeviceToHost));
+  (void)hipFree(d_ends);
+  for (int e = 0; e < E; ++e) {
+    mid[2 * e] = mx[e];
+    mid[2 * e + 1] = my[e];
+  }
+
+  if (!build_host_plan(pb, mid, ends)) {
+    free_all(pb);
+    return bail(fail(pb, PFM_EINVAL, "tree construction failed"));
+  }
+  const HostPlan& hp = pb.hp;
+  int nc = (int)hp.cells.size();
+  std::vector<double> cx(nc), cy(nc);
+  std::vector<int> eb(nc), ee(nc), fc(nc), nch(nc), par(nc), fib(nc);
+  for (int i = 0; i < nc; ++i) {
+    const Cell& c = hp.cells[i];
+    cx[i] = c.cx; cy[i] = c.cy; eb[i] = c.ebeg; ee[i] = c.eend;
+    fc[i] = c.first_child; nch[i] = c.n_child; par[i] = c.parent; fib[i] = c.fiber;
+  }
+  CK(upload(&pb.d_elem_of, hp.elem_of));
+  CK(upload(&pb.d_cx, cx)); CK(upload(&pb.d_cy, cy));
+  CK(upload(&pb.d_ebeg, eb)); CK(upload(&pb.d_eend, ee));
+  CK(upload(&pb.d_first_child, fc)); CK(upload(&pb.d_n_child, nch));
+  CK(upload(&pb.d_parent, par)); CK(upload(&pb.d_fibre_of_cell, fib));
+  CK(upload(&pb.d_cell_joff, hp.cell_joff));
+  CK(upload(&pb.d_leaves, hp.leaves));
+  CK(upload(&pb.d_root_of_fibre, hp.root_of_fibre));
+  CK(upload(&pb.d_m2l_ptr, hp.m2l_ptr)); CK(upload(&pb.d_m2l_src, hp.m2l_src));
+  CK(upload(&pb.d_m2l_off, hp.m2l_off)); CK(upload(&pb.d_m2l_m, hp.m2l_m));
+  CK(upload(&pb.d_m2li_ptr, hp.m2li_ptr)); CK(upload(&pb.d_m2li_src, hp.m2li_src));
+  CK(upload(&pb.d_m2li_off, hp.m2li_off));
+  CK(upload(&pb.d_near_ptr, hp.near_ptr)); CK(upload(&pb.d_near_src, hp.near_src));
+  CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
+  CK(upload(&pb.d_near_blk, hp.near_blk));
+  CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
+  CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
+  CK(upload(&pb.d_off_xy, hp.off_xy)); CK(upload(&pb.d_joff_xy, hp.joff_xy));
+  CK(upload(&pb.d_root_off_xy, hp.root_off_xy));
+  // quadrature rules: far rule, then 16-point near rule and 8-point field rule
+  {
+    std::vector<double> x, w, t;
+    gauss_legendre(pb.opt.g_far, x, w);
+    t = x;
+    t.insert(t.end(), w.begin(), w.end());
+    CK(upload(&pb.d_gl, t));
+    std::vector<double> x16, w16, x8, w8;
+    gauss_legendre(16, x16, w16);
+    gauss_legendre(8, x8, w8);
+    std::vector<double> u = x16;
+    u.insert(u.end(), w16.begin(), w16.end());
+    u.insert(u.end(), x8.begin(), x8.end());
+    u.insert(u.end(), w8.begin(), w8.end());
+    CK(upload(&pb.d_gl16, u));
+  }
+  const int NP = 2 * pb.opt.p + 1, NT = 4 * pb.opt.p + 1;
+  CK(hipMalloc((void**)&pb.d_mpole, (size_t)nc * 2 * NP * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_local, (size_t)nc * 2 * NP * sizeof(cd)));
+  CK(hipMemset(pb.d_mpole, 0, (size_t)nc * 2 * NP * sizeof(cd)));
+  CK(hipMemset(pb.d_local, 0, (size_t)nc * 2 * NP * sizeof(cd)));
+  size_t n_ent = std::max<long long>(1, hp.n_near_entries);
+  CK(hipMalloc((void**)&pb.d_near, 4 * n_ent * sizeof(cd)));
+  int n_off = std::max<int>(1, (int)hp.off_xy.size() / 2);
+  int n_joff = std::max<int>(1, (int)hp.joff_xy.size() / 2);
+  int n_roff = std::max<int>(1, (int)hp.root_off_xy.size() / 2);
+  CK(hipMalloc((void**)&pb.d_htab, (size_t)2 * n_off * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_lat, (size_t)n_roff * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_alpha, (size_t)(hp.m_max - hp.m_min + 1) * sizeof(cd)));
+  // GMRES workspace
+  size_t n = 2 * (size_t)E;
+  CK(hipMalloc((void**)&pb.d_V, (size_t)(pb.opt.restart + 1) * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_w, n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_r, n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_b, n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_tmp, n * sizeof(cd)));
+  pb.red_blocks = (int)std::min<size_t>(256, (n + 1023) / 1024);
+  CK(hipMalloc((void**)&pb.d_red, (size_t)pb.red_blocks * (2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipHostMalloc((void**)&pb.h_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_fields, (size_t)2 * 512 * sizeof(cd)));
+  for (int i = 0; i < 16; ++i) CK(hipEventCreate(&pb.ev[i]));
+  pb.events = true;
+#undef CK
+  *out = h;
+  return PFM_OK;
+}
+
+pfm_status pfm_set_stream(pfm_problem* h, void* stream) {
+  if (!h) return PFM_EINVAL;
+  h->p.stream = (hipStream_t)stream;
+  return PFM_OK;
+}
+
+pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
+  if (!h) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!(ka > 0) || !(std::fabs(theta) < 0.5 * PI))
+    return fail(pb, PFM_EINVAL, "need ka > 0 and |theta| < pi/2");
+  pb.wave_ready = false;
+  pb.k = ka / pb.a;
+  pb.k1 = pb.k * pb.c_m / pb.c_f;
+  pb.varrho = pb.rho_m / pb.rho_f;
+  pb.eta = pb.eta_user > 0 ? pb.eta_user : pb.k;
+  pb.theta = theta;
+  pb.beta = pb.k * pb.H * std::sin(theta);
+  double wd = wood_distance(pb.k, pb.H, theta);
+  if (pb.opt.wood_margin > 0 && wd < pb.opt.wood_margin)
+    return fail(pb, PFM_EWOOD, "k H (1 +- sin theta) / (2 pi) is " + std::to_string(wd) +
+                                   " from an integer");
+  const HostPlan& hp = pb.hp;
+  // alpha^m for the explicit images
+  std::vector<cd> al(hp.m_max - hp.m_min + 1);
+  for (int m = hp.m_min; m <= hp.m_max; ++m) al[m - hp.m_min] = mkc(std::cos(m * pb.beta), std::sin(m * pb.beta));
+  HIPCHK(pb, hipMemcpyAsync(pb.d_alpha, al.data(), al.size() * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+  // lattice-sum cut-off q: all excluded images inside |m| <= q, (q+1)H - |Y| >= H/2,
+  // and the contour factor exp(k X^2 / (4 ((q+1)H - |Y|))) held below e^2
+  double xmax = 0.0, ymax = 0.0;
+  int mex = 0;
+  int n_roff = (int)hp.root_off_xy.size() / 2;
+  for (int o = 0; o < n_roff; ++o) {
+    xmax = std::max(xmax, std::fabs(hp.root_off_xy[2 * o]));
+    ymax = std::max(ymax, std::fabs(hp.root_off_xy[2 * o + 1]));
+    if (hp.root_off_mrange[2 * o] <= hp.root_off_mrange[2 * o + 1])
+      mex = std::max(mex, std::max(std::abs(hp.root_off_mrange[2 * o]), std::abs(hp.root_off_mrange[2 * o + 1])));
+  }
+  int q = std::max(3, mex + 1);
+  while (true) {
+    double gap = (q + 1) * pb.H - ymax;
+    if (gap >= 0.5 * pb.H && pb.k * xmax * xmax / (4.0 * gap) <= 2.0) break;
+    ++q;
+  }
+  pb.lattice_q = q;
+  std::vector<double> rule;
+  tail_rule(pb.k, pb.H, (q + 1) * pb.H - ymax, xmax, 2 * pb.opt.p, rule);
+  dfree(pb.d_srule);
+  HIPCHK(pb, upload(&pb.d_srule, rule));
+  pb.n_srule = (int)rule.size() / 2;
+  HIPCHK(pb, launch_tables(pb));
+  HIPCHK(pb, launch_lattice_sums(pb));
+  HIPCHK(pb, launch_near_blocks(pb));
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  pb.wave_ready = true;
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec(pfm_problem* h, const void* d_psi, void* d_y) {
+  if (!h || !d_psi || !d_y) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, nullptr));
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_timed(pfm_problem* h, const void* d_psi, void* d_y, int reps, double* stage_ms,
+                            double* total_ms) {
+  if (!h || !d_psi || !d_y || reps < 1) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  double acc[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
+  for (int r = 0; r < reps; ++r) {
+    HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, pb.ev));
+    HIPCHK(pb, hipEventSynchronize(pb.ev[6]));
+    for (int s = 0; s < 6; ++s) {
+      float ms = 0.f;
+      HIPCHK(pb, hipEventElapsedTime(&ms, pb.ev[s], pb.ev[s + 1]));
+      acc[s] += ms;
+    }
+    float all = 0.f;
+    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[6]));
+    tot += all;
+  }
+  if (stage_ms)
+    for (int s = 0; s < 6; ++s) stage_ms[s] = acc[s] / reps;
+  if (total_ms) *total_ms = tot / reps;
+  return PFM_OK;
+}
+
+pfm_status pfm_rhs(pfm_problem* h, void* d_b) {
+  if (!h || !d_b) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  HIPCHK(pb, launch_rhs(pb, (cd*)d_b));
+  return PFM_OK;
+}
+
+pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* info) {
+  if (!h || !d_x_io) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = 2 * pb.E;
+  const long long ldv = n;
+  const int m = pb.opt.restart;
+  cd* x = (cd*)d_x_io;
+  cd* b = pb.d_b;
+  if (d_b_in) HIPCHK(pb, hipMemcpyAsync(b, d_b_in, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+  else HIPCHK(pb, launch_rhs(pb, b));
+  cd* V = pb.d_V;
+  cd* hc = pb.d_hcol;
+  cd* hh = pb.h_hcol;
+  int matvecs = 0, iters = 0;
+  auto dot_host = [&](const cd* u, const cd* v, cd* out) -> hipError_t {
+    hipError_t e = launch_dots(pb, u, ldv, 1, v, n, hc);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(hh, hc, sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(pb.stream);
+    *out = hh[0];
+    return e;
+  };
+  cd tmp;
+  HIPCHK(pb, dot_host(b, b, &tmp));
+  double bnorm = std::sqrt(std::max(0.0, tmp.x));
+  if (!std::isfinite(bnorm)) return fail(pb, PFM_ENUMERIC, "non-finite right-hand side");
+  cd* r = pb.d_r;
+  if (use_x0) {
+    HIPCHK(pb, apply_operator(pb, x, pb.d_w, nullptr));
+    ++matvecs;
+    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
+  } else {
+    HIPCHK(pb, hipMemsetAsync(x, 0, n * sizeof(cd), pb.stream));
+    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+  }
+  HIPCHK(pb, dot_host(r, r, &tmp));
+  double beta = std::sqrt(std::max(0.0, tmp.x));
+  pfm_status st = PFM_OK;
+  std::vector<std::complex<double>> Hm((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  if (bnorm == 0.0) beta = 0.0;
+  double best = bnorm > 0 ? beta / bnorm : 0.0;
+  while (true) {
+    if (!std::isfinite(beta)) { st = PFM_ENUMERIC; break; }
+    if (bnorm == 0.0 || beta / bnorm <= pb.opt.tol) { st = PFM_OK; break; }
+    if (iters >= pb.opt.max_iter) { st = PFM_ENOCONV; break; }
+    HIPCHK(pb, hipMemcpyAsync(V, r, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    HIPCHK(pb, launch_axpby(pb, V, mkc(0, 0), nullptr, mkc(1.0 / beta, 0), n));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jj = 0;
+    bool bad = false;
+    for (int j = 0; j < m; ++j) {
+      cd* vj = V + (size_t)j * n;
+      cd* w = V + (size_t)(j + 1) * n;
+      HIPCHK(pb, apply_operator(pb, vj, w, nullptr));
+      ++matvecs;
+      // classical Gram-Schmidt, twice
+      HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc));
+      HIPCHK(pb, launch_update(pb, w, V, ldv, j + 1, hc, n));
+      HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc + (j + 1)));
+      HIPCHK(pb, launch_update(pb, w, V, ldv, j + 1, hc + (j + 1), n));
+      HIPCHK(pb, launch_dots(pb, w, ldv, 1, w, n, hc + 2 * (j + 1)));
+      HIPCHK(pb, hipMemcpyAsync(hh, hc, (2 * (j + 1) + 1) * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
+      HIPCHK(pb, hipStreamSynchronize(pb.stream));
+      std::vector<std::complex<double>> col(j + 2);
+      for (int i = 0; i <= j; ++i)
+        col[i] = std::complex<double>(hh[i].x + hh[j + 1 + i].x, hh[i].y + hh[j + 1 + i].y);
+      double hn = std::sqrt(std::max(0.0, hh[2 * (j + 1)].x));
+      if (!std::isfinite(hn)) { bad = true; break; }
+      col[j + 1] = hn;
+      if (hn > 0) HIPCHK(pb, launch_axpby(pb, w, mkc(0, 0), nullptr, mkc(1.0 / hn, 0), n));
+      for (int i = 0; i < j; ++i) {
+        std::complex<double> a = col[i], bb = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * bb;
+        col[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
+      }
+      {
+        std::complex<double> a = col[j], bb = col[j + 1];
+        double t = std::sqrt(std::norm(a) + std::norm(bb));
+        if (std::abs(a) == 0.0) {
+          cs[j] = 0.0;
+          sn[j] = 1.0;
+          col[j] = bb;
+        } else {
+          std::complex<double> ph = a / std::abs(a);
+          cs[j] = std::abs(a) / t;
+          sn[j] = ph * std::conj(bb) / t;
+          col[j] = ph * t;
+        }
+        col[j + 1] = 0.0;
+        g[j + 1] = -std::conj(sn[j]) * g[j];
+        g[j] = cs[j] * g[j];
+      }
+      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = col[i];
+      ++iters;
+      jj = j + 1;
+      double est = std::abs(g[j + 1]) / bnorm;
+      if (est <= 0.7 * pb.opt.tol || iters >= pb.opt.max_iter || hn == 0.0) break;
+    }
+    if (bad) { st = PFM_ENUMERIC; break; }
+    // back substitution and update of x
+    for (int i = jj - 1; i >= 0; --i) {
+      std::complex<double> s = g[i];
+      for (int l = i + 1; l < jj; ++l) s -= Hm[(size_t)i * m + l] * y[l];
+      y[i] = s / Hm[(size_t)i * m + i];
+    }
+    for (int i = 0; i < jj; ++i) hh[i] = mkc(y[i].real(), y[i].imag());
+    HIPCHK(pb, hipMemcpyAsync(hc, hh, jj * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+    HIPCHK(pb, launch_gemv_acc(pb, x, V, ldv, jj, hc, n));
+    // true residual
+    HIPCHK(pb, apply_operator(pb, x, pb.d_w, nullptr));
+    ++matvecs;
+    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
+    HIPCHK(pb, dot_host(r, r, &tmp));
+    beta = std::sqrt(std::max(0.0, tmp.x));
+    if (std::isfinite(beta)) best = beta / bnorm;
+  }
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->status = st;
+    info->iters = iters;
+    info->matvecs = matvecs;
+    info->rel_residual = best;
+    info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+  }
+  if (st == PFM_ENOCONV) return fail(pb, st, "GMRES stopped at relative residual " + std::to_string(best));
+  if (st == PFM_ENUMERIC) return fail(pb, st, "non-finite residual norm");
+  return st;
+}
+
+pfm_status pfm_fields(pfm_problem* h, const void* d_psi, int n_orders, double* R, double* T, double* etc,
+                      double* energy_residual) {
+  if (!h || !d_psi || n_orders < 0 || n_orders > 255) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  int no = 2 * n_orders + 1;
+  HIPCHK(pb, launch_fields(pb, (const cd*)d_psi, n_orders, pb.d_fields));
+  std::vector<cd> v(2 * no);
+  HIPCHK(pb, hipMemcpyAsync(v.data(), pb.d_fields, 2 * no * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  double flux = 0.0;
+  std::vector<std::complex<double>> Tn(no), gam(no);
+  std::vector<double> kap(no);
+  for (int i = 0; i < no; ++i) {
+    int nn = i - n_orders;
+    if (R) { R[2 * i] = v[2 * i].x; R[2 * i + 1] = v[2 * i].y; }
+    if (T) { T[2 * i] = v[2 * i + 1].x; T[2 * i + 1] = v[2 * i + 1].y; }
+    kap[i] = pb.k * std::sin(pb.theta) + 2.0 * PI * nn / pb.H;
+    double g2 = pb.k * pb.k - kap[i] * kap[i];
+    gam[i] = g2 >= 0 ? std::complex<double>(std::sqrt(g2), 0) : std::complex<double>(0, std::sqrt(-g2));
+    Tn[i] = std::complex<double>(v[2 * i + 1].x, v[2 * i + 1].y) + (nn == 0 ? 1.0 : 0.0);
+    if (g2 >= 0) {
+      std::complex<double> Rn(v[2 * i].x, v[2 * i].y);
+      flux += std::sqrt(g2) * (std::norm(Rn) + std::norm(Tn[i]));
+    }
+  }
+  if (energy_residual) *energy_residual = flux / (pb.k * std::cos(pb.theta)) - 1.0;
+  if (etc) {
+    // (1/(kH)) int_0^H |du/dx1(L, x2)| dx2 on the modal expansion, trapezoid rule
+    const int npts = 512;
+    double s = 0.0;
+    for (int t = 0; t < npts; ++t) {
+      double x2 = t * pb.H / npts;
+      std::complex<double> du = 0.0;
+      for (int i = 0; i < no; ++i)
+        du += std::complex<double>(0, 1) * gam[i] * Tn[i] *
+              std::exp(std::complex<double>(0, 1) * (gam[i] * pb.L + kap[i] * x2));
+      s += std::abs(du);
+    }
+    *etc = s * (pb.H / npts) / (pb.k * pb.H);
+  }
+  return PFM_OK;
+}
+
+pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
+  if (!h || !st) return PFM_EINVAL;
+  const Problem& pb = h->p;
+  const HostPlan& hp = pb.hp;
+  std::memset(st, 0, sizeof(*st));
+  st->M = pb.M;
+  st->N = pb.N;
+  st->E = pb.E;
+  st->n_unknowns = 2 * pb.E;
+  st->n_cells = (int)hp.cells.size();
+  st->n_leaves = (int)hp.leaves.size();
+  st->depth = hp.depth;
+  st->n_m2l_ext = (int)hp.m2l_src.size();
+  st->n_m2l_int = (int)hp.m2li_src.size();
+  st->n_near_pairs = (int)hp.near_src.size();
+  st->n_near_entries = hp.n_near_entries;
+  for (size_t q = 0; q < hp.near_src.size(); ++q)
+    st->n_near_cols += hp.cells[hp.near_src[q]].eend - hp.cells[hp.near_src[q]].ebeg;
+  st->n_root_offsets = (int)hp.root_off_xy.size() / 2;
+  st->n_m2l_offsets = (int)hp.off_xy.size() / 2;
+  st->near_bytes = 4.0 * 16.0 * (double)hp.n_near_entries;
+  st->k = pb.k;
+  st->k1 = pb.k1;
+  st->eta = pb.eta;
+  st->varrho = pb.varrho;
+  st->theta = pb.theta;
+  st->lattice_q = pb.lattice_q;
+  return PFM_OK;
+}
+
+const char* pfm_last_error(const pfm_problem* h) { return h ? h->p.err.c_str() : "null handle"; }
+
+void pfm_destroy(pfm_problem* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  free_all(h->p);
+  delete h;
+}
+
+pfm_status pfm_test_bessel(const double* d_x, int n, double* d_out) {
+  if (!d_x || !d_out || n < 0) return PFM_EINVAL;
+  if (launch_bessel_test(d_x, n, d_out, nullptr) != hipSuccess) return PFM_EDEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return PFM_EDEVICE;
+  return PFM_OK;
+}
+
+pfm_status pfm_test_lattice(pfm_problem* h, double* sums, double* offsets, int* mrange) {
+  if (!h) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  const HostPlan& hp = pb.hp;
+  int n_roff = (int)hp.root_off_xy.size() / 2;
+  int NT = 4 * pb.opt.p + 1;
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  if (sums) HIPCHK(pb, hipMemcpy(sums, pb.d_lat, (size_t)n_roff * NT * sizeof(cd), hipMemcpyDeviceToHost));
+  if (offsets) std::memcpy(offsets, hp.root_off_xy.data(), hp.root_off_xy.size() * sizeof(double));
+  if (mrange) std::memcpy(mrange, hp.root_off_mrange.data(), hp.root_off_mrange.size() * sizeof(int));
+  return PFM_OK;
+}
+
+pfm_status pfm_test_moments(pfm_problem* h, const void* d_psi, double* moments, double* centres, int* levels,
+                            int* elem_order) {
+  if (!h || !d_psi) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  const HostPlan& hp = pb.hp;
+  int nc = (int)hp.cells.size();
+  int NP = 2 * pb.opt.p + 1;
+  HIPCHK(pb, apply_upward(pb, (const cd*)d_psi));
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  if (moments) HIPCHK(pb, hipMemcpy(moments, pb.d_mpole, (size_t)nc * 2 * NP * sizeof(cd), hipMemcpyDeviceToHost));
+  for (int i = 0; i < nc; ++i) {
+    if (centres) { centres[2 * i] = hp.cells[i].cx; centres[2 * i + 1] = hp.cells[i].cy; }
+    if (levels) {
+      levels[4 * i] = hp.cells[i].level;
+      levels[4 * i + 1] = hp.cells[i].fiber;
+      levels[4 * i + 2] = hp.cells[i].ebeg;
+      levels[4 * i + 3] = hp.cells[i].eend;
+    }
+  }
+  if (elem_order) std::memcpy(elem_order, hp.elem_of.data(), hp.elem_of.size() * sizeof(int));
+  return PFM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal plan of the periodic FMM: tree, interaction lists, device buffers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pfmbem.h"
+#include "pfm_math.hpp"
+
+namespace pfm {
+
+// One quadtree cell.  Cells of one fibre's tree are lattice-aligned squares:
+// the root is the square of side a centred on the fibre (the basic tree of
+// Sec. 3.1); children are quadrants.  rho is the tight radius: the largest
+// distance from the centre to a chord end point of an element in the cell.
+struct Cell {
+  double cx, cy, half, rho;
+  int level, fiber, parent;
+  int first_child, n_child;   // children are contiguous after renumbering
+  int ebeg, eend;             // range in the tree-ordered element list
+  int leaf;                   // 1 for a leaf
+  int leaf_index;             // index among leaves, or -1
+};
+
+struct M2LEntry { int tgt, src, off, m; };
+struct NearEntry { int tgt_leaf, src, m; };
+
+struct HostPlan {
+  std::vector<Cell> cells;              // level-major order
+  std::vector<int> level_beg;           // cells of level l: [level_beg[l], level_beg[l+1])
+  std::vector<int> elem_of;             // tree position -> natural element id
+  std::vector<int> leaves;              // leaf cell ids
+  std::vector<int> root_of_fibre;       // [M]
+  // M2L (exterior, all images) and interior (same fibre, m = 0) lists, CSR by target cell
+  std::vector<int> m2l_ptr, m2l_src, m2l_off, m2l_m;
+  std::vector<int> m2li_ptr, m2li_src, m2li_off;
+  std::vector<double> off_xy;           // unique M2L translation vectors [n_off][2]
+  std::vector<double> joff_xy;          // unique child-parent offsets [n_joff][2]
+  std::vector<int> cell_joff;           // per cell: index into joff_xy (-1 for roots)
+  // P2P near lists, CSR by target leaf
+  std::vector<int> near_ptr, near_src, near_m, near_tgt;
+  std::vector<long long> near_blk;      // block offset (entries) of each near pair
+  long long n_near_entries = 0;
+  // top-level lattice M2L
+  std::vector<double> root_off_xy;      // unique fibre offsets [n_roff][2]
+  std::vector<int> root_off_mrange;     // [n_roff][2]: explicit images m_lo..m_hi
+  std::vector<int> root_pair_off;       // [M*M]: offset id of (target i, source j)
+  int depth = 0;
+  int m_min = 0, m_max = 0;             // image range used by explicit entries
+};
+
+struct Problem {
+  // inputs
+  int lattice = 0;
+  double a = 1.0;
+  int ML = 1, MH = 1, M = 1, N = 8, E = 8;
+  std::vector<double> radii, centres;   // [M], [M][2]
+  double L = 1.0, H = 1.0;
+  double rho_f = 1, c_f = 1, rho_m = 1, c_m = 1, eta_user = 0;
+  pfm_options opt{};
+  // current wave
+  bool wave_ready = false;
+  double k = 0, k1 = 0, eta = 0, varrho = 0, theta = 0, beta = 0;
+  int lattice_q = 0;
+
+  hipStream_t stream = nullptr;
+  std::string err;
+  HostPlan hp;
+
+  // device buffers -----------------------------------------------------
+  // elements (natural order), SoA
+  double *d_centres = nullptr, *d_radii = nullptr;
+  double *d_mx = nullptr, *d_my = nullptr, *d_tx = nullptr, *d_ty = nullptr, *d_h = nullptr;
+  double *d_gl = nullptr;               // far-rule nodes [g_far], weights [g_far]
+  double *d_gl16 = nullptr;             // near-rule nodes [16], weights [16]
+  int *d_elem_of = nullptr;
+  // cells
+  double *d_cx = nullptr, *d_cy = nullptr;
+  int *d_ebeg = nullptr, *d_eend = nullptr, *d_first_child = nullptr, *d_n_child = nullptr;
+  int *d_cell_joff = nullptr, *d_parent = nullptr, *d_leaves = nullptr, *d_root_of_fibre = nullptr;
+  int *d_fibre_of_cell = nullptr;
+  // lists
+  int *d_m2l_ptr = nullptr, *d_m2l_src = nullptr, *d_m2l_off = nullptr, *d_m2l_m = nullptr;
+  int *d_m2li_ptr = nullptr, *d_m2li_src = nullptr, *d_m2li_off = nullptr;
+  int *d_near_ptr = nullptr, *d_near_src = nullptr, *d_near_m = nullptr, *d_near_tgt = nullptr;
+  long long *d_near_blk = nullptr;
+  int *d_root_pair_off = nullptr, *d_root_mrange = nullptr;
+  double *d_off_xy = nullptr, *d_joff_xy = nullptr, *d_root_off_xy = nullptr;
+  // per-wave data
+  cd *d_near = nullptr;                 // 4 planes of n_near_entries
+  cd *d_htab = nullptr;                 // [2 ch][n_off][4p+1]
+  cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
+  cd *d_lat = nullptr;                  // [n_roff][4p+1]
+  cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max
+  double *d_srule = nullptr;            // lattice tail rule: nodes, weights
+  int n_srule = 0;
+  // expansions
+  cd *d_mpole = nullptr;                // [n_cells][2][2p+1]
+  cd *d_local = nullptr;                // [n_cells][2][2p+1]
+  // GMRES workspace
+  cd *d_V = nullptr;                    // [restart+1][n]
+  cd *d_w = nullptr, *d_r = nullptr, *d_b = nullptr, *d_tmp = nullptr;
+  cd *d_red = nullptr;                  // reduction partials
+  cd *d_hcol = nullptr;                 // column of dots
+  cd *h_hcol = nullptr;                 // pinned host copy
+  int red_blocks = 0;
+  // fields
+  cd *d_fields = nullptr;
+  hipEvent_t ev[16];
+  bool events = false;
+};
+
+bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+}  // namespace pfm

@@ -1,0 +1,949 @@
+// Device kernels of the periodic FM-BEM (gfx950).
+//
+// Layouts: complex values are double2 (re, im).  Element data are SoA in
+// natural order (fibre-major).  Expansion coefficients of cell c, channel
+// ch (0: exterior wavenumber k, 1: interior wavenumber k1), order n in
+// [-p, p] live at [(c * 2 + ch) * (2p+1) + n + p].  Translation tables hold
+// orders nu in [-2p, 2p] at [nu + 2p].  P2P blocks are four planes
+// (B11, B12, B21, B22) of one complex value per (target, source) element
+// pair; inside a leaf pair the pairs are column-major (source column, then
+// target row) so that the lanes of a wavefront, which own target rows, read
+// consecutive addresses.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "pfm_kernels.hpp"
+
+namespace pfm {
+
+bool supported_p(int p) {
+  return p == 8 || p == 12 || p == 16 || p == 20 || p == 24 || p == 32 || p == 40;
+}
+
+// ---------------------------------------------------------------------------
+// discretisation: N chords per fibre between c + r(cos t_e, sin t_e)
+// ---------------------------------------------------------------------------
+__global__ void k_discretise(int E, int N, const double* __restrict__ centres,
+                             const double* __restrict__ radii, double* mx, double* my,
+                             double* tx, double* ty, double* h, double* ends) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int f = e / N, l = e - f * N;
+  double t0 = 2.0 * PI * l / N, t1 = 2.0 * PI * (l + 1) / N;
+  double cx = centres[2 * f], cy = centres[2 * f + 1], r = radii[f];
+  double ax = cx + r * cos(t0), ay = cy + r * sin(t0);
+  double bx = cx + r * cos(t1), by = cy + r * sin(t1);
+  double dx = bx - ax, dy = by - ay;
+  double hh = sqrt(dx * dx + dy * dy);
+  mx[e] = 0.5 * (ax + bx);
+  my[e] = 0.5 * (ay + by);
+  tx[e] = dx / hh;
+  ty[e] = dy / hh;
+  h[e] = hh;
+  if (ends) {
+    ends[4 * e + 0] = ax;
+    ends[4 * e + 1] = ay;
+    ends[4 * e + 2] = bx;
+    ends[4 * e + 3] = by;
+  }
+}
+
+hipError_t launch_discretise(Problem& pb, double* d_ends) {
+  int E = pb.E;
+  hipLaunchKernelGGL(k_discretise, dim3((E + 255) / 256), dim3(256), 0, pb.stream, E, pb.N,
+                     pb.d_centres, pb.d_radii, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, d_ends);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// kernels S, D, K, T of the layer operators at one point pair (Sec. 2)
+// ---------------------------------------------------------------------------
+__device__ inline void kern_sdkt(double kap, double dx, double dy, double nux, double nuy,
+                                 double nx, double ny, cd& S, cd& D, cd& K, cd& T) {
+  double r = sqrt(dx * dx + dy * dy);
+  cd H0, H1;
+  hankel01(kap * r, H0, H1);
+  double dnx = dx * nux + dy * nuy;      // d . nu_x
+  double dny = dx * nx + dy * ny;        // d . n_y
+  double nn = nux * nx + nuy * ny;
+  double ir = 1.0 / r;
+  S = mkc(-0.25 * H0.y, 0.25 * H0.x);                 // (i/4) H0
+  cd ikH1 = mkc(-0.25 * kap * H1.y, 0.25 * kap * H1.x);  // (i kap/4) H1
+  D = cscale(ikH1, dny * ir);
+  K = cscale(ikH1, -dnx * ir);
+  // (i kap/4) [ (kap H0/r - 2 H1/r^2) dnx dny / r + H1 nn / r ]
+  cd a = csub(cscale(H0, kap * ir), cscale(H1, 2.0 * ir * ir));
+  cd b = cadd(cscale(a, dnx * dny * ir), cscale(H1, nn * ir));
+  T = cscale(mkc(-b.y, b.x), 0.25 * kap);
+}
+
+// Self element at its midpoint: S = (i/4) 2 int_0^{h/2} H0(kap s) ds by the
+// term-wise integrated power series of J0 and Y0 (DLMF 10.8.1);
+// T = kap^2 S - (i kap/2) H1(kap h/2) (straight-element Maue identity); D = K = 0.
+__device__ inline void self_terms(double kap, double h, cd& S, cd& T) {
+  double X = 0.5 * kap * h;
+  double q = -0.25 * X * X;
+  double lg = log(0.5 * X) + EULER_GAMMA;
+  double ak = 1.0;        // (-1/4)^k / (k!)^2 * X^{2k}  (without the X factor)
+  double Hk = 0.0;        // harmonic number
+  double ij = 0.0, iy1 = 0.0, iy2 = 0.0;
+  for (int k = 0; k < 60; ++k) {
+    if (k > 0) {
+      ak *= q / ((double)k * (double)k);
+      Hk += 1.0 / k;
+    }
+    double inv = 1.0 / (2.0 * k + 1.0);
+    double t = ak * X * inv;            // a_k X^{2k+1} / (2k+1)
+    ij += t;
+    iy1 += t * (lg - inv);
+    iy2 += Hk * t;
+    if (k > 2 && fabs(t) < 1e-18 * fabs(ij)) break;
+  }
+  double iy = (2.0 / PI) * (iy1 - iy2);
+  // int_0^{h/2} H0(kap s) ds = (ij + i iy) / kap ; S = (i/2)(...)
+  S = mkc(-0.5 * iy / kap, 0.5 * ij / kap);
+  cd H0, H1;
+  hankel01(X, H0, H1);
+  T = csub(cscale(S, kap * kap), mkc(-0.5 * kap * H1.y, 0.5 * kap * H1.x));
+}
+
+// ---------------------------------------------------------------------------
+// near-field blocks (per wave): one workgroup per near leaf pair
+// ---------------------------------------------------------------------------
+struct NearArgs {
+  int N, g_far;
+  double k, k1, eta, varrho, H;
+  const double *mx, *my, *tx, *ty, *h, *gl, *gl16;
+  const int *elem_of, *ebeg, *eend, *leaves, *near_tgt, *near_src, *near_m;
+  const long long* near_blk;
+  const cd* alpha;
+  int m_min;
+  long long n_entries;
+  cd* out;
+};
+
+__device__ inline void far_rule(double kap, double x, double y, double nux, double nuy,
+                                double cxm, double cym, double tx, double ty, double hh,
+                                const double* gl, int G, cd& S, cd& D, cd& K, cd& T) {
+  S = D = K = T = mkc(0, 0);
+  double nx = ty, ny = -tx;
+  for (int g = 0; g < G; ++g) {
+    double s = 0.5 * hh * gl[g];
+    double w = 0.5 * hh * gl[G + g];
+    cd s_, d_, k_, t_;
+    kern_sdkt(kap, x - (cxm + s * tx), y - (cym + s * ty), nux, nuy, nx, ny, s_, d_, k_, t_);
+    S = cadd(S, cscale(s_, w));
+    D = cadd(D, cscale(d_, w));
+    K = cadd(K, cscale(k_, w));
+    T = cadd(T, cscale(t_, w));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_near_blocks(NearArgs A) {
+  int q = blockIdx.x;
+  int D = A.leaves[A.near_tgt[q]];
+  int C = A.near_src[q];
+  int m = A.near_m[q];
+  int db = A.ebeg[D], rows = A.eend[D] - db;
+  int cb = A.ebeg[C], cols = A.eend[C] - cb;
+  long long blk = A.near_blk[q];
+  cd ph = A.alpha[m - A.m_min];
+  cd c = mkc(0.0, -2.0 / (A.eta * (1.0 + A.varrho)));     // 2 / (i eta (1 + varrho))
+  cd mieta = mkc(0.0, -A.eta);                              // -i eta
+  for (int rc = threadIdx.x; rc < rows * cols; rc += blockDim.x) {
+    int col = rc / rows, row = rc - col * rows;
+    int ea = A.elem_of[db + row], eb = A.elem_of[cb + col];
+    double x = A.mx[ea], y = A.my[ea];
+    double nux = A.ty[ea], nuy = -A.tx[ea];
+    double sx = A.mx[eb], sy = A.my[eb] + m * A.H;
+    double tx = A.tx[eb], ty = A.ty[eb], hh = A.h[eb];
+    int fa = ea / A.N, fb = eb / A.N;
+    cd B11, B12, B21, B22;
+    if (fa == fb && m == 0) {
+      int dl = abs((ea - fa * A.N) - (eb - fb * A.N));
+      dl = min(dl, A.N - dl);
+      cd S2, D2, K2, T2, S1, D1, K1, T1;
+      if (dl == 0) {
+        self_terms(A.k, hh, S2, T2);
+        self_terms(A.k1, hh, S1, T1);
+        D2 = K2 = D1 = K1 = mkc(0, 0);
+      } else if (dl <= 2) {
+        far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S2, D2, K2, T2);
+        far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S1, D1, K1, T1);
+      } else {
+        far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
+        far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S1, D1, K1, T1);
+      }
+      B11 = csub(D2, D1);
+      B12 = cmul(mieta, csub(S2, S1));
+      B21 = cmul(c, csub(T2, cscale(T1, A.varrho)));
+      B22 = cmul(cmul(c, mieta), csub(K2, cscale(K1, A.varrho)));
+    } else {
+      cd S2, D2, K2, T2;
+      far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
+      B11 = cmul(ph, D2);
+      B12 = cmul(cmul(mieta, ph), S2);
+      B21 = cmul(cmul(c, ph), T2);
+      B22 = cmul(cmul(cmul(c, mieta), ph), K2);
+    }
+    long long idx = blk + (long long)col * rows + row;
+    A.out[idx] = B11;
+    A.out[A.n_entries + idx] = B12;
+    A.out[2 * A.n_entries + idx] = B21;
+    A.out[3 * A.n_entries + idx] = B22;
+  }
+}
+
+hipError_t launch_near_blocks(Problem& pb) {
+  const HostPlan& hp = pb.hp;
+  int npairs = (int)hp.near_src.size();
+  if (npairs == 0) return hipSuccess;
+  NearArgs A;
+  A.N = pb.N;
+  A.g_far = pb.opt.g_far;
+  A.k = pb.k;
+  A.k1 = pb.k1;
+  A.eta = pb.eta;
+  A.varrho = pb.varrho;
+  A.H = pb.H;
+  A.mx = pb.d_mx; A.my = pb.d_my; A.tx = pb.d_tx; A.ty = pb.d_ty; A.h = pb.d_h;
+  A.gl = pb.d_gl; A.gl16 = pb.d_gl16;
+  A.elem_of = pb.d_elem_of; A.ebeg = pb.d_ebeg; A.eend = pb.d_eend; A.leaves = pb.d_leaves;
+  A.near_tgt = pb.d_near_tgt; A.near_src = pb.d_near_src; A.near_m = pb.d_near_m;
+  A.near_blk = pb.d_near_blk;
+  A.alpha = pb.d_alpha;
+  A.m_min = hp.m_min;
+  A.n_entries = hp.n_near_entries;
+  A.out = pb.d_near;
+  hipLaunchKernelGGL(k_near_blocks, dim3(npairs), dim3(256), 0, pb.stream, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// translation tables (per wave): Hp_nu(kap d) for M2L offsets, Jp_nu(kap delta)
+// for child-parent offsets, nu = -2p..2p, both wavenumbers.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void k_htab(int n_off, const double* __restrict__ off, double k, double k1, cd* tab) {
+  constexpr int NT = 4 * P + 1;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * n_off) return;
+  int ch = i / n_off, o = i - ch * n_off;
+  double kap = ch ? k1 : k;
+  double dx = off[2 * o], dy = off[2 * o + 1];
+  double r = sqrt(dx * dx + dy * dy);
+  double x = kap * r;
+  cd e1 = mkc(dx / r, dy / r);             // e^{i theta}
+  cd Hm1, Hn;
+  hankel01(x, Hm1, Hn);                    // H_0, H_1
+  cd* out = tab + (size_t)i * NT + 2 * P;
+  out[0] = Hm1;
+  cd en = e1;                              // e^{i n theta}
+  cd Hprev = Hm1;
+  double sgn = -1.0;
+  for (int n = 1; n <= 2 * P; ++n) {
+    cd v = cmul(Hn, en);
+    out[n] = v;
+    out[-n] = cscale(cconj(cmul(cconj(Hn), en)), sgn);   // (-1)^n H_n e^{-i n theta}
+    cd Hnext = csub(cscale(Hn, 2.0 * n / x), Hprev);
+    Hprev = Hn;
+    Hn = Hnext;
+    en = cmul(en, e1);
+    sgn = -sgn;
+  }
+}
+
+template <int P>
+__global__ void k_jtab(int n_off, const double* __restrict__ off, double k, double k1, cd* tab) {
+  constexpr int NT = 4 * P + 1;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * n_off) return;
+  int ch = i / n_off, o = i - ch * n_off;
+  double kap = ch ? k1 : k;
+  cd jp[2 * P + 1];
+  jplus_seq<2 * P>(kap * off[2 * o], kap * off[2 * o + 1], jp);
+  cd* out = tab + (size_t)i * NT + 2 * P;
+  double sgn = 1.0;
+  for (int n = 0; n <= 2 * P; ++n) {
+    out[n] = jp[n];
+    out[-n] = cscale(cconj(jp[n]), sgn);
+    sgn = -sgn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// lattice sums of the top-level M2L (Sec. 3.3):
+//   S_nu(o) = sum_{m outside [m_lo, m_hi]} alpha^m Hp_nu(k (o - m h))
+// direct for |m| <= q, tails for |m| > q as contour integrals in s
+// (t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik, dt/mu = 2 ds / sqrt(s^2 - 2ik)),
+// one workgroup per fibre offset, one thread per order nu.
+// ---------------------------------------------------------------------------
+__global__ void k_lattice_sums(int P, int n_roff, const double* __restrict__ roff,
+                               const int* __restrict__ mrange, double k, double H,
+                               double beta, int q, const double* __restrict__ rule,
+                               int n_rule, cd* out) {
+  int o = blockIdx.x;
+  int NT = 4 * P + 1;
+  double ox = roff[2 * o], oy = roff[2 * o + 1];
+  int mlo = mrange[2 * o], mhi = mrange[2 * o + 1];
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+    int nu = t - 2 * P;
+    int an = nu < 0 ? -nu : nu;
+    cd acc = mkc(0, 0);
+    for (int m = -q; m <= q; ++m) {
+      if (m >= mlo && m <= mhi) continue;
+      double vx = ox, vy = oy - m * H;
+      double r = sqrt(vx * vx + vy * vy);
+      double x = k * r;
+      cd H0, H1;
+      hankel01(x, H0, H1);
+      cd Hn = H0;
+      if (an >= 1) {
+        cd Hp = H0, Hc = H1;
+        for (int n = 1; n < an; ++n) {
+          cd Hx = csub(cscale(Hc, 2.0 * n / x), Hp);
+          Hp = Hc;
+          Hc = Hx;
+        }
+        Hn = Hc;
+      }
+      double th = atan2(vy, vx);
+      double s, c;
+      sincos(nu * th, &s, &c);
+      cd v = cmul(Hn, mkc(c, s));
+      if (nu < 0 && (an & 1)) v = cscale(v, -1.0);
+      double sb, cb;
+      sincos(m * beta, &sb, &cb);
+      acc = cfma(mkc(cb, sb), v, acc);
+    }
+    // tails
+    cd tail = mkc(0, 0);
+    cd eib = mkc(cos(beta), sin(beta));
+    cd emib = cconj(eib);
+    double invk = 1.0 / k;
+    for (int i = 0; i < n_rule; ++i) {
+      double s = rule[i], w = rule[n_rule + i];
+      cd root = csqrt(mkc(s * s, -2.0 * k));
+      cd mu = mkc(s * s, -k);
+      cd jac = cdiv(mkc(2.0 * w, 0.0), root);
+      cd emh = cexp(mkc(-mu.x * H, -mu.y * H));          // e^{-mu H}
+      cd den_up = csub(mkc(1, 0), cmul(eib, emh));
+      cd den_dn = csub(mkc(1, 0), cmul(emib, emh));
+      for (int br = 0; br < 2; ++br) {
+        cd tt = cmul(root, mkc(br ? -s : s, 0.0));
+        cd itx = cmul_i(cscale(tt, ox));                  // i X t
+        // up tail: exp(i X t + mu Y + (q+1)(i beta - mu H)) / den_up
+        cd ex_up = cadd(itx, cadd(cscale(mu, oy), cscale(csub(mkc(0, beta), cscale(mu, H)), q + 1.0)));
+        cd ex_dn = cadd(itx, csub(cscale(mu, -oy), cscale(cadd(mkc(0, beta), cscale(mu, H)), q + 1.0)));
+        cd fu = cdiv(cexp(ex_up), den_up);
+        cd fd = cdiv(cexp(ex_dn), den_dn);
+        cd tpm = cadd(tt, mu), tmm = csub(tt, mu);
+        cd fac_up, fac_dn;
+        if (nu >= 0) {
+          // (-i (t +- mu) / k)^nu
+          fac_up = cpowi(cscale(mkc(tpm.y, -tpm.x), invk), an);
+          fac_dn = cpowi(cscale(mkc(tmm.y, -tmm.x), invk), an);
+        } else {
+          // (i (t -+ mu) / k)^|nu|
+          fac_up = cpowi(cscale(mkc(-tmm.y, tmm.x), invk), an);
+          fac_dn = cpowi(cscale(mkc(-tpm.y, tpm.x), invk), an);
+        }
+        tail = cadd(tail, cmul(jac, cadd(cmul(fu, fac_up), cmul(fd, fac_dn))));
+      }
+    }
+    // 1/(i pi) * tail
+    tail = mkc(tail.y / PI, -tail.x / PI);
+    out[(size_t)o * NT + t] = cadd(acc, tail);
+  }
+}
+
+hipError_t launch_lattice_sums(Problem& pb) {
+  int n_roff = (int)pb.hp.root_off_xy.size() / 2;
+  hipLaunchKernelGGL(k_lattice_sums, dim3(n_roff), dim3(128), 0, pb.stream, pb.opt.p, n_roff,
+                     pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, pb.beta, pb.lattice_q,
+                     pb.d_srule, pb.n_srule, pb.d_lat);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side B of eq. (9)
+// ---------------------------------------------------------------------------
+__global__ void k_rhs(int E, int N, const double* mx, const double* my, const double* tx,
+                      const double* ty, double k, double th, double eta, double varrho, cd* b) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double d1 = cos(th), d2 = sin(th);
+  double ph = k * (mx[e] * d1 + my[e] * d2);
+  cd u = mkc(cos(ph), sin(ph));
+  double dn = k * (ty[e] * d1 - tx[e] * d2);               // k (d . nu)
+  cd du = cscale(cmul_i(u), dn);                            // i k (d.nu) u
+  int f = e / N, l = e - f * N;
+  b[2 * f * N + l] = mkc(-u.x, -u.y);
+  double s = 2.0 / (eta * (1.0 + varrho));
+  b[2 * f * N + N + l] = cscale(cmul_i(du), s);             // 2i/(eta(1+varrho)) du
+}
+
+hipError_t launch_rhs(Problem& pb, cd* d_b) {
+  hipLaunchKernelGGL(k_rhs, dim3((pb.E + 255) / 256), dim3(256), 0, pb.stream, pb.E, pb.N, pb.d_mx,
+                     pb.d_my, pb.d_tx, pb.d_ty, pb.k, pb.theta, pb.eta, pb.varrho, d_b);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Bragg amplitudes: one workgroup per order, G = 8 Gauss points per element
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fields(int E, int N, int n_orders, const double* mx,
+                                                const double* my, const double* tx, const double* ty,
+                                                const double* h, const double* gl8, double k,
+                                                double th, double H, double eta, const cd* psi,
+                                                cd* out) {
+  int n = (int)blockIdx.x - n_orders;
+  double kap = k * sin(th) + 2.0 * PI * n / H;
+  double g2 = k * k - kap * kap;
+  cd gam = g2 >= 0 ? mkc(sqrt(g2), 0.0) : mkc(0.0, sqrt(-g2));
+  cd accT = mkc(0, 0), accR = mkc(0, 0);
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    int f = e / N, l = e - f * N;
+    cd ph = psi[2 * f * N + l], vp = psi[2 * f * N + N + l];
+    double n1 = ty[e], n2 = -tx[e];
+    for (int g = 0; g < 8; ++g) {
+      double s = 0.5 * h[e] * gl8[g], w = 0.5 * h[e] * gl8[8 + g];
+      double y1 = mx[e] + s * tx[e], y2 = my[e] + s * ty[e];
+      // T: e^{-i(gam y1 + kap y2)} [ (gam n1 + kap n2) phi + eta varphi ]
+      cd argT = cmul_i(mkc(-(gam.x * y1 + kap * y2), -gam.y * y1));
+      cd fT = cadd(cmul(mkc(gam.x * n1 + kap * n2, gam.y * n1), ph), cscale(vp, eta));
+      accT = cfma(cscale(cexp(argT), w), fT, accT);
+      // R: e^{i(gam y1 - kap y2)} [ -(gam n1 - kap n2) phi + eta varphi ]
+      cd argR = cmul_i(mkc(gam.x * y1 - kap * y2, gam.y * y1));
+      cd fR = cadd(cmul(mkc(-(gam.x * n1 - kap * n2), -gam.y * n1), ph), cscale(vp, eta));
+      accR = cfma(cscale(cexp(argR), w), fR, accR);
+    }
+  }
+  __shared__ cd sT[256], sR[256];
+  sT[threadIdx.x] = accT;
+  sR[threadIdx.x] = accR;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sT[threadIdx.x] = cadd(sT[threadIdx.x], sT[threadIdx.x + s]);
+      sR[threadIdx.x] = cadd(sR[threadIdx.x], sR[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cd den = cscale(gam, 2.0 * H);
+    out[2 * blockIdx.x] = cdiv(sR[0], den);
+    out[2 * blockIdx.x + 1] = cdiv(sT[0], den);
+  }
+}
+
+hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out) {
+  hipLaunchKernelGGL(k_fields, dim3(2 * n_orders + 1), dim3(256), 0, pb.stream, pb.E, pb.N, n_orders,
+                     pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl16 + 32, pb.k, pb.theta,
+                     pb.H, pb.eta, d_psi, d_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Bessel test hook
+// ---------------------------------------------------------------------------
+__global__ void k_bessel(const double* x, int n, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a, b, c, d;
+  bessel_jy01(x[i], a, b, c, d);
+  out[4 * i] = a;
+  out[4 * i + 1] = b;
+  out[4 * i + 2] = c;
+  out[4 * i + 3] = d;
+}
+
+hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bessel, dim3((n + 255) / 256), dim3(256), 0, s, d_x, n, d_out);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// The operator apply (hot path)
+// ===========================================================================
+
+// P2M: multipole moments at the leaves, both wavenumbers (Sec. 3.2, MM of
+// S-bar and D-bar combined as in the representation D phi - i eta S varphi):
+//   M_n(C) = (i/4) sum_{e in C} sum_g w_g [ dJm_n/dn_y phi_e - i eta Jm_n varphi_e ],
+//   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2.
+// One wavefront per (leaf, channel); lane = element; per-lane partial moments
+// are summed through LDS (row per lane, one column per order).
+template <int P>
+__global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
+                                            const int* __restrict__ eend, const int* __restrict__ elem_of,
+                                            const double* __restrict__ cx, const double* __restrict__ cy,
+                                            const double* __restrict__ mx, const double* __restrict__ my,
+                                            const double* __restrict__ tx, const double* __restrict__ ty,
+                                            const double* __restrict__ h, const double* __restrict__ gl,
+                                            int G, int N, double k, double k1, double eta,
+                                            const cd* __restrict__ psi, cd* __restrict__ mpole) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd red[64][NP];
+  int cell = leaves[blockIdx.x];
+  int ch = blockIdx.y;
+  double kap = ch ? k1 : k;
+  int lane = threadIdx.x;
+  for (int n = 0; n < NP; ++n) red[lane][n] = mkc(0, 0);
+  double ox = cx[cell], oy = cy[cell];
+  int b = ebeg[cell], e_ = eend[cell];
+  for (int t = b + lane; t < e_; t += 64) {
+    int e = elem_of[t];
+    int f = e / N, l = e - f * N;
+    cd phi = psi[2 * f * N + l], vphi = psi[2 * f * N + N + l];
+    double ex = mx[e], ey = my[e], etx = tx[e], ety = ty[e], hh = h[e];
+    cd nu = mkc(ety, -etx);
+    // i/4 [ (kap/2) conj(nu) phi , -(kap/2) nu phi, -i eta vphi ]
+    cd a_m = cmul(cscale(cconj(nu), 0.5 * kap), phi);      // multiplies Jm_{n-1}
+    cd a_p = cmul(cscale(nu, -0.5 * kap), phi);            // multiplies Jm_{n+1}
+    cd a_0 = cmul(mkc(0.0, -eta), vphi);                   // multiplies Jm_n
+    for (int g = 0; g < G; ++g) {
+      double s = 0.5 * hh * gl[g], w = 0.5 * hh * gl[G + g];
+      double vx = kap * (ex + s * etx - ox), vy = kap * (ey + s * ety - oy);
+      cd jp[P + 2];
+      jplus_seq<P + 1>(vx, vy, jp);
+      // Jm_n = conj(Jp_n) (n >= 0);  Jm_{-n} = (-1)^n Jp_n
+      cd wa_m = cscale(mkc(-a_m.y, a_m.x), 0.25 * w);    // (i/4) w a
+      cd wa_p = cscale(mkc(-a_p.y, a_p.x), 0.25 * w);
+      cd wa_0 = cscale(mkc(-a_0.y, a_0.x), 0.25 * w);
+#pragma unroll
+      for (int n = -P; n <= P; ++n) {
+        int an = n < 0 ? -n : n;
+        int am = (n - 1) < 0 ? -(n - 1) : (n - 1);
+        int ap = (n + 1) < 0 ? -(n + 1) : (n + 1);
+        cd j0 = n >= 0 ? cconj(jp[an]) : ((an & 1) ? cscale(jp[an], -1.0) : jp[an]);
+        cd jm = (n - 1) >= 0 ? cconj(jp[am]) : ((am & 1) ? cscale(jp[am], -1.0) : jp[am]);
+        cd jq = (n + 1) >= 0 ? cconj(jp[ap]) : ((ap & 1) ? cscale(jp[ap], -1.0) : jp[ap]);
+        cd v = cmul(wa_0, j0);
+        v = cfma(wa_m, jm, v);
+        v = cfma(wa_p, jq, v);
+        red[lane][n + P] = cadd(red[lane][n + P], v);
+      }
+    }
+  }
+  __syncthreads();
+  cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
+  for (int n = lane; n < NP; n += 64) {
+    cd s = mkc(0, 0);
+    for (int r = 0; r < 64; ++r) s = cadd(s, red[r][n]);
+    out[n] = s;
+  }
+}
+
+// M2M for the non-leaf cells of one level: M_n(C) = sum_l M_l(CS) Jm_{n-l}(kap (O_CS - O_C)).
+template <int P>
+__global__ void __launch_bounds__(64) k_m2m(int cbeg, const int* __restrict__ first_child,
+                                            const int* __restrict__ n_child, const int* __restrict__ joff,
+                                            const cd* __restrict__ jtab, int n_joff, cd* mpole) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+  __shared__ cd sm[NP], sj[NT];
+  int cell = cbeg + blockIdx.x;
+  int ch = blockIdx.y;
+  int nc = n_child[cell];
+  if (nc == 0) return;
+  int fc = first_child[cell];
+  cd acc[(NP + 63) / 64];
+  for (int i = 0; i < (NP + 63) / 64; ++i) acc[i] = mkc(0, 0);
+  for (int c = 0; c < nc; ++c) {
+    int child = fc + c;
+    const cd* src = mpole + ((size_t)child * 2 + ch) * NP;
+    const cd* tj = jtab + ((size_t)ch * n_joff + joff[child]) * NT;
+    for (int i = threadIdx.x; i < NP; i += 64) sm[i] = src[i];
+    for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
+    __syncthreads();
+    for (int i = 0; i < (NP + 63) / 64; ++i) {
+      int n = threadIdx.x + 64 * i - P;
+      if (n > P) break;
+      cd s = acc[i];
+      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[n - l + 2 * P], sm[l + P], s);
+      acc[i] = s;
+    }
+    __syncthreads();
+  }
+  cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
+  for (int i = 0; i < (NP + 63) / 64; ++i) {
+    int n = threadIdx.x + 64 * i;
+    if (n < NP) out[n] = acc[i];
+  }
+}
+
+// M2L over the explicit lists: L_l(D) = sum_{(C,m)} alpha^m sum_n Hp_{n-l}(kap d) M_n(C)
+// (eq. 13 with the index n - l).  Channel 0: exterior lists with images;
+// channel 1: interior lists.  Assigns L (cells without entries get zero).
+template <int P>
+__global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ ptr_e, const int* __restrict__ src_e,
+                                            const int* __restrict__ off_e, const int* __restrict__ m_e,
+                                            const int* __restrict__ ptr_i, const int* __restrict__ src_i,
+                                            const int* __restrict__ off_i, const cd* __restrict__ htab,
+                                            int n_off, const cd* __restrict__ alpha, int m_min,
+                                            const cd* __restrict__ mpole, cd* __restrict__ local) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+  __shared__ cd sm[NP], sh[NT];
+  int cell = blockIdx.x;
+  int ch = blockIdx.y;
+  const int* ptr = ch ? ptr_i : ptr_e;
+  const int* src = ch ? src_i : src_e;
+  const int* off = ch ? off_i : off_e;
+  int b = ptr[cell], e = ptr[cell + 1];
+  cd acc[(NP + 63) / 64];
+  for (int i = 0; i < (NP + 63) / 64; ++i) acc[i] = mkc(0, 0);
+  for (int q = b; q < e; ++q) {
+    int C = src[q];
+    const cd* ms = mpole + ((size_t)C * 2 + ch) * NP;
+    const cd* th = htab + ((size_t)ch * n_off + off[q]) * NT;
+    for (int i = threadIdx.x; i < NP; i += 64) sm[i] = ms[i];
+    for (int i = threadIdx.x; i < NT; i += 64) sh[i] = th[i];
+    cd ph = ch ? mkc(1, 0) : alpha[m_e[q] - m_min];
+    __syncthreads();
+    for (int i = 0; i < (NP + 63) / 64; ++i) {
+      int l = threadIdx.x + 64 * i - P;
+      if (l > P) break;
+      cd s = mkc(0, 0);
+      for (int n = -P; n <= P; ++n) s = cfma(sh[n - l + 2 * P], sm[n + P], s);
+      acc[i] = cfma(ph, s, acc[i]);
+    }
+    __syncthreads();
+  }
+  cd* out = local + ((size_t)cell * 2 + ch) * NP;
+  for (int i = 0; i < (NP + 63) / 64; ++i) {
+    int l = threadIdx.x + 64 * i;
+    if (l < NP) out[l] = acc[i];
+  }
+}
+
+// Lattice M2L at the roots: L_l(root_i) += sum_j sum_n S_{n-l}(c_i - c_j) M_n(root_j).
+template <int P>
+__global__ void __launch_bounds__(64) k_lattice_m2l(int M, const int* __restrict__ root_of_fibre,
+                                                    const int* __restrict__ pair_off,
+                                                    const cd* __restrict__ lat,
+                                                    const cd* __restrict__ mpole, cd* local) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+  __shared__ cd sm[NP], sh[NT];
+  int i = blockIdx.x;
+  int D = root_of_fibre[i];
+  cd acc[(NP + 63) / 64];
+  for (int u = 0; u < (NP + 63) / 64; ++u) acc[u] = mkc(0, 0);
+  for (int j = 0; j < M; ++j) {
+    int C = root_of_fibre[j];
+    const cd* ms = mpole + ((size_t)C * 2) * NP;
+    const cd* th = lat + (size_t)pair_off[(size_t)i * M + j] * NT;
+    for (int t = threadIdx.x; t < NP; t += 64) sm[t] = ms[t];
+    for (int t = threadIdx.x; t < NT; t += 64) sh[t] = th[t];
+    __syncthreads();
+    for (int u = 0; u < (NP + 63) / 64; ++u) {
+      int l = threadIdx.x + 64 * u - P;
+      if (l > P) break;
+      cd s = acc[u];
+      for (int n = -P; n <= P; ++n) s = cfma(sh[n - l + 2 * P], sm[n + P], s);
+      acc[u] = s;
+    }
+    __syncthreads();
+  }
+  cd* out = local + ((size_t)D * 2) * NP;
+  for (int u = 0; u < (NP + 63) / 64; ++u) {
+    int l = threadIdx.x + 64 * u;
+    if (l < NP) out[l] = cadd(out[l], acc[u]);
+  }
+}
+
+// L2L for the cells of one level: L_n(D) += sum_l L_l(DP) Jp_{l-n}(kap (O_D - O_DP)).
+template <int P>
+__global__ void __launch_bounds__(64) k_l2l(int cbeg, const int* __restrict__ parent,
+                                            const int* __restrict__ joff, const cd* __restrict__ jtab,
+                                            int n_joff, cd* local) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+  __shared__ cd sl[NP], sj[NT];
+  int cell = cbeg + blockIdx.x;
+  int ch = blockIdx.y;
+  int par = parent[cell];
+  const cd* lp = local + ((size_t)par * 2 + ch) * NP;
+  const cd* tj = jtab + ((size_t)ch * n_joff + joff[cell]) * NT;
+  for (int i = threadIdx.x; i < NP; i += 64) sl[i] = lp[i];
+  for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
+  __syncthreads();
+  cd* out = local + ((size_t)cell * 2 + ch) * NP;
+  for (int i = threadIdx.x; i < NP; i += 64) {
+    int n = i - P;
+    cd s = out[i];
+    for (int l = -P; l <= P; ++l) s = cfma(sl[l + P], sj[l - n + 2 * P], s);
+    out[i] = s;
+  }
+}
+
+// Leaf evaluation: L2P at both wavenumbers, P2P with the stored blocks, and
+// the rows of (I - A) (eq. 9):
+//   y1 = phi + u_ext - u_int
+//   y2 = varphi + 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int)
+// with u = sum_l L_l Jp_l(kap (x - O)),
+//      dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}).
+// One workgroup (4 wavefronts) per leaf; lane = target row; the wavefronts
+// split the source columns of the near blocks and meet in LDS.
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf(
+    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
+    const int* __restrict__ elem_of, const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ mx, const double* __restrict__ my, const double* __restrict__ tx,
+    const double* __restrict__ ty, int N, double k, double k1, double eta, double varrho,
+    const int* __restrict__ near_ptr, const int* __restrict__ near_src,
+    const long long* __restrict__ near_blk, const cd* __restrict__ blocks, long long n_entries,
+    const cd* __restrict__ local, const cd* __restrict__ psi, cd* __restrict__ y) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd sL[2][NP];
+  __shared__ cd r1[4][64], r2[4][64];
+  __shared__ cd su[2][64], sd[2][64];
+  int li = blockIdx.x;
+  int D = leaves[li];
+  int db = ebeg[D], rows = eend[D] - db;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < 2 * NP; i += 256) sL[i / NP][i % NP] = local[(size_t)D * 2 * NP + i];
+  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
+  const cd* B11 = blocks;
+  const cd* B12 = blocks + n_entries;
+  const cd* B21 = blocks + 2 * n_entries;
+  const cd* B22 = blocks + 3 * n_entries;
+  int qb = near_ptr[li], qe = near_ptr[li + 1];
+  for (int q = qb; q < qe; ++q) {
+    int C = near_src[q];
+    int cb = ebeg[C], cols = eend[C] - cb;
+    long long blk = near_blk[q];
+    for (int c = w; c < cols; c += 4) {
+      int ec = elem_of[cb + c];
+      int f = ec / N, l = ec - f * N;
+      cd ph = psi[2 * f * N + l], vp = psi[2 * f * N + N + l];
+      if (lane < rows) {
+        long long idx = blk + (long long)c * rows + lane;
+        a1 = cfma(B11[idx], ph, a1);
+        a1 = cfma(B12[idx], vp, a1);
+        a2 = cfma(B21[idx], ph, a2);
+        a2 = cfma(B22[idx], vp, a2);
+      }
+    }
+  }
+  r1[w][lane] = a1;
+  r2[w][lane] = a2;
+  __syncthreads();
+  if (w < 2 && lane < rows) {
+    int ch = w;
+    double kap = ch ? k1 : k;
+    int e = elem_of[db + lane];
+    double vx = kap * (mx[e] - cx[D]), vy = kap * (my[e] - cy[D]);
+    cd nu = mkc(ty[e], -tx[e]);
+    cd jp[P + 2];
+    jplus_seq<P + 1>(vx, vy, jp);
+    cd u = mkc(0, 0), dv = mkc(0, 0);
+#pragma unroll
+    for (int l = -P; l <= P; ++l) {
+      int al = l < 0 ? -l : l;
+      int am = (l - 1) < 0 ? -(l - 1) : (l - 1);
+      int ap = (l + 1) < 0 ? -(l + 1) : (l + 1);
+      // Jp_{-n} = (-1)^n conj(Jp_n)
+      cd j0 = l >= 0 ? jp[al] : ((al & 1) ? cscale(cconj(jp[al]), -1.0) : cconj(jp[al]));
+      cd jm = (l - 1) >= 0 ? jp[am] : ((am & 1) ? cscale(cconj(jp[am]), -1.0) : cconj(jp[am]));
+      cd jq = (l + 1) >= 0 ? jp[ap] : ((ap & 1) ? cscale(cconj(jp[ap]), -1.0) : cconj(jp[ap]));
+      cd Ll = sL[ch][l + P];
+      u = cfma(Ll, j0, u);
+      cd dj = csub(cmul(nu, jm), cmul(cconj(nu), jq));
+      dv = cfma(Ll, dj, dv);
+    }
+    su[ch][lane] = u;
+    sd[ch][lane] = cscale(dv, 0.5 * kap);
+  }
+  __syncthreads();
+  if (w == 0 && lane < rows) {
+    int e = elem_of[db + lane];
+    int f = e / N, l = e - f * N;
+    cd p1 = cadd(cadd(r1[0][lane], r1[1][lane]), cadd(r1[2][lane], r1[3][lane]));
+    cd p2 = cadd(cadd(r2[0][lane], r2[1][lane]), cadd(r2[2][lane], r2[3][lane]));
+    cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
+    cd y1 = cadd(psi[2 * f * N + l], csub(su[0][lane], su[1][lane]));
+    y1 = cadd(y1, p1);
+    cd dn = csub(sd[0][lane], cscale(sd[1][lane], varrho));
+    cd y2 = cfma(c, dn, psi[2 * f * N + N + l]);
+    y2 = cadd(y2, p2);
+    y[2 * f * N + l] = y1;
+    y[2 * f * N + N + l] = y2;
+  }
+}
+
+template <int P>
+static hipError_t tables_impl(Problem& pb) {
+  const HostPlan& hp = pb.hp;
+  int n_off = (int)hp.off_xy.size() / 2;
+  int n_joff = (int)hp.joff_xy.size() / 2;
+  if (n_off > 0)
+    hipLaunchKernelGGL(k_htab<P>, dim3((2 * n_off + 63) / 64), dim3(64), 0, pb.stream, n_off,
+                       pb.d_off_xy, pb.k, pb.k1, pb.d_htab);
+  if (n_joff > 0)
+    hipLaunchKernelGGL(k_jtab<P>, dim3((2 * n_joff + 63) / 64), dim3(64), 0, pb.stream, n_joff,
+                       pb.d_joff_xy, pb.k, pb.k1, pb.d_jtab);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
+  const HostPlan& hp = pb.hp;
+  int n_leaves = (int)hp.leaves.size();
+  int n_joff = (int)hp.joff_xy.size() / 2;
+  if (ev) (void)hipEventRecord(ev[0], pb.stream);
+  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(64), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+                     pb.d_eend, pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
+                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole);
+  if (ev) (void)hipEventRecord(ev[1], pb.stream);
+  for (int lv = hp.depth - 1; lv >= 0; --lv) {
+    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
+    if (ce > cb)
+      hipLaunchKernelGGL(k_m2m<P>, dim3(ce - cb, 2), dim3(64), 0, pb.stream, cb, pb.d_first_child,
+                         pb.d_n_child, pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_mpole);
+  }
+  if (ev) (void)hipEventRecord(ev[2], pb.stream);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  const HostPlan& hp = pb.hp;
+  int nc = (int)hp.cells.size();
+  int n_leaves = (int)hp.leaves.size();
+  int n_off = (int)hp.off_xy.size() / 2;
+  int n_joff = (int)hp.joff_xy.size() / 2;
+  hipError_t err = upward_impl<P>(pb, d_psi, ev);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_m2l<P>, dim3(nc, 2), dim3(64), 0, pb.stream, pb.d_m2l_ptr, pb.d_m2l_src,
+                     pb.d_m2l_off, pb.d_m2l_m, pb.d_m2li_ptr, pb.d_m2li_src, pb.d_m2li_off, pb.d_htab,
+                     n_off, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_local);
+  if (ev) (void)hipEventRecord(ev[3], pb.stream);
+  hipLaunchKernelGGL(k_lattice_m2l<P>, dim3(pb.M), dim3(64), 0, pb.stream, pb.M, pb.d_root_of_fibre,
+                     pb.d_root_pair_off, pb.d_lat, pb.d_mpole, pb.d_local);
+  if (ev) (void)hipEventRecord(ev[4], pb.stream);
+  for (int lv = 1; lv <= hp.depth; ++lv) {
+    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
+    if (ce > cb)
+      hipLaunchKernelGGL(k_l2l<P>, dim3(ce - cb, 2), dim3(64), 0, pb.stream, cb, pb.d_parent,
+                         pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_local);
+  }
+  if (ev) (void)hipEventRecord(ev[5], pb.stream);
+  hipLaunchKernelGGL(k_leaf<P>, dim3(n_leaves), dim3(256), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+                     pb.d_eend, pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
+                     pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_near_ptr, pb.d_near_src,
+                     pb.d_near_blk, pb.d_near, hp.n_near_entries, pb.d_local, d_psi, d_y);
+  if (ev) (void)hipEventRecord(ev[6], pb.stream);
+  return hipGetLastError();
+}
+
+#define PFM_DISPATCH(fn, ...)                        \
+  switch (pb.opt.p) {                                \
+    case 8: return fn<8>(__VA_ARGS__);               \
+    case 12: return fn<12>(__VA_ARGS__);             \
+    case 16: return fn<16>(__VA_ARGS__);             \
+    case 20: return fn<20>(__VA_ARGS__);             \
+    case 24: return fn<24>(__VA_ARGS__);             \
+    case 32: return fn<32>(__VA_ARGS__);             \
+    case 40: return fn<40>(__VA_ARGS__);             \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_tables(Problem& pb) { PFM_DISPATCH(tables_impl, pb) }
+hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  PFM_DISPATCH(apply_impl, pb, d_psi, d_y, ev)
+}
+hipError_t apply_upward(Problem& pb, const cd* d_psi) { PFM_DISPATCH(upward_impl, pb, d_psi, nullptr) }
+
+// ===========================================================================
+// GMRES building blocks
+// ===========================================================================
+constexpr int RED_THREADS = 256;
+
+// partial[i * nblk + blockIdx.x] = sum over this block's share of conj(V_i) w
+__global__ void __launch_bounds__(RED_THREADS) k_dots(const cd* __restrict__ V, long long ldv, int cnt,
+                                                      const cd* __restrict__ w, int n, cd* partial) {
+  __shared__ cd s[RED_THREADS];
+  int nblk = gridDim.x;
+  for (int i = 0; i < cnt; ++i) {
+    const cd* v = V + (size_t)i * ldv;
+    cd acc = mkc(0, 0);
+    for (int t = blockIdx.x * RED_THREADS + threadIdx.x; t < n; t += nblk * RED_THREADS)
+      acc = cfma_conj(v[t], w[t], acc);
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) s[threadIdx.x] = cadd(s[threadIdx.x], s[threadIdx.x + st]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)i * nblk + blockIdx.x] = s[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_dots_final(const cd* partial, int nblk, cd* out) {
+  __shared__ cd s[RED_THREADS];
+  int i = blockIdx.x;
+  cd acc = mkc(0, 0);
+  for (int b = threadIdx.x; b < nblk; b += RED_THREADS) acc = cadd(acc, partial[(size_t)i * nblk + b]);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] = cadd(s[threadIdx.x], s[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = s[0];
+}
+
+hipError_t launch_dots(Problem& pb, const cd* V, long long ldv, int cnt, const cd* w, int n, cd* d_out) {
+  int nblk = pb.red_blocks;
+  hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(RED_THREADS), 0, pb.stream, V, ldv, cnt, w, n, pb.d_red);
+  hipLaunchKernelGGL(k_dots_final, dim3(cnt), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, d_out);
+  return hipGetLastError();
+}
+
+// w -= sum_i h_i V_i
+__global__ void k_update(cd* w, const cd* __restrict__ V, long long ldv, int cnt,
+                         const cd* __restrict__ hcoef, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  cd acc = w[t];
+  for (int i = 0; i < cnt; ++i) {
+    cd hv = hcoef[i];
+    acc = csub(acc, cmul(hv, V[(size_t)i * ldv + t]));
+  }
+  w[t] = acc;
+}
+
+hipError_t launch_update(Problem& pb, cd* w, const cd* V, long long ldv, int cnt, const cd* d_h, int n) {
+  hipLaunchKernelGGL(k_update, dim3((n + 255) / 256), dim3(256), 0, pb.stream, w, V, ldv, cnt, d_h, n);
+  return hipGetLastError();
+}
+
+// x += sum_i c_i V_i
+__global__ void k_gemv_acc(cd* x, const cd* __restrict__ V, long long ldv, int cnt,
+                           const cd* __restrict__ c, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  cd acc = x[t];
+  for (int i = 0; i < cnt; ++i) acc = cfma(c[i], V[(size_t)i * ldv + t], acc);
+  x[t] = acc;
+}
+
+hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n) {
+  hipLaunchKernelGGL(k_gemv_acc, dim3((n + 255) / 256), dim3(256), 0, pb.stream, x, V, ldv, cnt, d_c, n);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(cd* y, cd a, const cd* __restrict__ x, cd b, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  cd yv = b.x == 0.0 && b.y == 0.0 ? mkc(0, 0) : cmul(b, y[t]);
+  y[t] = x ? cfma(a, x[t], yv) : yv;
+}
+
+hipError_t launch_axpby(Problem& pb, cd* y, cd a, const cd* x, cd b, int n) {
+  hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, pb.stream, y, a, x, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace pfm

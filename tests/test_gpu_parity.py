@@ -1,0 +1,160 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Stages: device Bessel functions, lattice sums of the top-level M2L, the
+upward pass (P2M + M2M) against direct moments, the full operator apply
+against the dense oracle matrix (square and hexagon blocks), and the GMRES
+solution against the dense LU solution.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy.special import j0, j1, y0, y1
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10863_amd import pfm as m
+    m.lib()
+    return m
+
+
+@functools.lru_cache(maxsize=8)
+def _oracle(key):
+    from oracle import system as sy
+    wl, ka, th = _WL[key]
+    pb = sy.problem_from_workload(wl, ka, th)
+    A = sy.dense_matrix(pb)
+    return pb, A, sy.rhs(pb)
+
+
+_WL = {
+    "tiny": (W.tiny(), 2.0, math.pi / 4),
+    "sq2x2": (W.small_square(2, 2, 64, 0.3, 2.0, math.pi / 6), 2.0, math.pi / 6),
+    "hex2x2": (W.small_square(2, 2, 64, 0.3, 3.0, 0.3, lattice=W.HEXAGON), 3.0, 0.3),
+    "sq3x1": (W.small_square(3, 1, 96, 0.25, 5.0, 0.2, radii=np.array([0.2, 0.3, 0.25])), 5.0, 0.2),
+}
+
+
+def _gpu_problem(pfm, key, p, leaf, **kw):
+    wl, ka, th = _WL[key]
+    prob = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, **kw)
+    prob.set_wave(ka, th)
+    return prob
+
+
+def test_device_bessel(pfm):
+    x = np.concatenate([np.logspace(-5, 1.9, 400), [24.9, 25.0, 25.1, 30.0]])
+    _say("bessel: n =", x.size)
+    out = pfm.bessel01(torch.tensor(x, dtype=torch.float64, device="cuda")).cpu().numpy()
+    for c, f in enumerate((j0, j1, y0, y1)):
+        ref = f(x)
+        err = np.abs(out[:, c] - ref) / np.maximum(np.abs(ref), 1e-3)
+        assert err.max() < 1e-12, (c, x[err.argmax()], err.max())
+
+
+@pytest.mark.parametrize("key,p", [("tiny", 24), ("sq2x2", 24), ("hex2x2", 24)])
+def test_lattice_sums_vs_oracle(pfm, key, p):
+    from oracle.lattice import lattice_sum_orders
+    wl, ka, th = _WL[key]
+    _say("lattice sums:", key, "p =", p)
+    prob = _gpu_problem(pfm, key, p, 32)
+    S, offs, mr = prob.lattice_sums()
+    k = ka / wl.a
+    H = wl.M_H * wl.a
+    for o in range(S.shape[0]):
+        ex = tuple(range(mr[o, 0], mr[o, 1] + 1))
+        ref = lattice_sum_orders(k, H, th, offs[o, 0], offs[o, 1], 2 * p, exclude=ex)
+        err = np.abs(S[o] - ref) / np.abs(ref)
+        assert err.max() < 1e-10, (o, offs[o], np.argmax(err) - 2 * p, err.max())
+
+
+@pytest.mark.parametrize("key,p,leaf", [("tiny", 24, 16), ("sq2x2", 20, 16)])
+def test_upward_pass_vs_direct_moments(pfm, key, p, leaf):
+    from oracle import fmmdefs
+    pb, A, B = _oracle(key)
+    wl, ka, th = _WL[key]
+    _say("moments:", key, "p =", p, "leaf =", leaf)
+    prob = _gpu_problem(pfm, key, p, leaf)
+    psi = W.random_density(prob.n, 11)
+    mom, cen, info, order = prob.moments(torch.tensor(psi, device="cuda"))
+    for c in range(mom.shape[0]):
+        elems = order[info[c, 2]:info[c, 3]]
+        for ch, kap in ((0, pb.k), (1, pb.k1)):
+            ref = fmmdefs.moments(pb, psi, cen[c], elems, kap, p)
+            err = np.max(np.abs(mom[c, ch] - ref)) / np.max(np.abs(ref))
+            assert err < 1e-11, (c, ch, info[c], err)
+
+
+def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
+    pb, A, B = _oracle(key)
+    prob = _gpu_problem(pfm, key, p, leaf, **kw)
+    psi = W.random_density(prob.n, seed)
+    y = prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy()
+    ref = A @ psi
+    return np.linalg.norm(y - ref) / np.linalg.norm(ref), prob
+
+
+@pytest.mark.parametrize("key,p,leaf,tol", [
+    ("tiny", 40, 32, 1e-10),
+    ("tiny", 16, 32, 1e-5),
+    ("sq2x2", 40, 16, 1e-10),
+    ("hex2x2", 40, 16, 1e-10),
+    ("sq3x1", 40, 16, 1e-10),
+])
+def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol):
+    _say("matvec:", key, "p =", p, "leaf =", leaf)
+    err, prob = _matvec_err(pfm, key, p, leaf)
+    _say("  rel err", err, prob.stats())
+    assert err < tol
+
+
+def test_matvec_error_decreases_with_p(pfm):
+    errs = [(_matvec_err(pfm, "sq2x2", p, 16)[0]) for p in (8, 16, 24, 32)]
+    _say("matvec error vs p:", errs)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a
+
+
+@pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2"])
+def test_solve_vs_dense_lu(pfm, key):
+    pb, A, B = _oracle(key)
+    ref = np.linalg.solve(A, B)
+    _say("solve:", key)
+    prob = _gpu_problem(pfm, key, 40, 16 if key != "tiny" else 32, tol=1e-12, restart=100)
+    b = prob.rhs().cpu().numpy()
+    assert np.linalg.norm(b - B) < 1e-13 * np.linalg.norm(B)
+    x, info = prob.solve()
+    _say("  ", info)
+    assert info["status"] == 0
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    _say("  rel err vs LU", err)
+    assert err < 1e-8
+
+
+def test_fields_vs_oracle(pfm):
+    from oracle import fields as fl
+    pb, A, B = _oracle("tiny")
+    psi = np.linalg.solve(A, B)
+    prob = _gpu_problem(pfm, "tiny", 24, 32)
+    R, T, etc, en = prob.fields(torch.tensor(psi, device="cuda"), 6)
+    n, kap, gam, Rr, Tr = fl.bragg(pb, psi, 6)
+    assert np.max(np.abs(R - Rr)) < 1e-12 * max(1.0, np.max(np.abs(Rr)))
+    assert np.max(np.abs(T - Tr)) < 1e-10 * np.max(np.abs(Tr))
+    assert abs(etc - fl.etc(pb, psi, n_orders=6)) < 1e-12
+    assert abs(en - fl.energy_residual(pb, psi, n_orders=6)) < 1e-12
