@@ -157,8 +157,11 @@ pfm_status pfm_fields(pfm_problem* pb, const void* d_psi, int n_orders,
 
 pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
 
-/* Mean duration (milliseconds) of each matvec stage over the last
- * pfm_matvec_timed call: [P2M, M2M, M2L, lattice M2L, L2L, leaf (L2P+P2P)]. */
+/* Apply the operator reps times with every stage in order on the bound
+ * stream and return the mean duration (milliseconds, HIP events) of each
+ * stage: stage_ms[7] = [P2M, M2M, M2L, lattice M2L, L2L, P2P, L2P], and of
+ * the whole apply in *total_ms.  (pfm_matvec overlaps the FMM chain with
+ * P2P on a second stream; this call does not.) */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);
 

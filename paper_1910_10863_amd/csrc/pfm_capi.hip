@@ -65,7 +65,7 @@ void dfree(T*& d) {
 void free_all(Problem& pb) {
   dfree(pb.d_centres); dfree(pb.d_radii);
   dfree(pb.d_mx); dfree(pb.d_my); dfree(pb.d_tx); dfree(pb.d_ty); dfree(pb.d_h);
-  dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of);
+  dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx); dfree(pb.d_latpart);
   dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
   dfree(pb.d_first_child); dfree(pb.d_n_child); dfree(pb.d_cell_joff); dfree(pb.d_parent);
   dfree(pb.d_leaves); dfree(pb.d_root_of_fibre); dfree(pb.d_fibre_of_cell);
@@ -82,9 +82,14 @@ void free_all(Problem& pb) {
   dfree(pb.d_red); dfree(pb.d_hcol); dfree(pb.d_fields);
   if (pb.h_hcol) (void)hipHostFree(pb.h_hcol);
   pb.h_hcol = nullptr;
-  if (pb.events)
+  if (pb.events) {
     for (int i = 0; i < 16; ++i) (void)hipEventDestroy(pb.ev[i]);
+    (void)hipEventDestroy(pb.ev_fork);
+    (void)hipEventDestroy(pb.ev_join);
+  }
   pb.events = false;
+  if (pb.side) (void)hipStreamDestroy(pb.side);
+  pb.side = nullptr;
 }
 
 double wood_distance(double k, double H, double th) {
@@ -227,6 +232,14 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     fc[i] = c.first_child; nch[i] = c.n_child; par[i] = c.parent; fib[i] = c.fiber;
   }
   CK(upload(&pb.d_elem_of, hp.elem_of));
+  {
+    std::vector<int> pidx(E);
+    for (int t = 0; t < E; ++t) {
+      int e = hp.elem_of[t], f = e / pb.N;
+      pidx[t] = 2 * f * pb.N + (e - f * pb.N);
+    }
+    CK(upload(&pb.d_psi_idx, pidx));
+  }
   CK(upload(&pb.d_cx, cx)); CK(upload(&pb.d_cy, cy));
   CK(upload(&pb.d_ebeg, eb)); CK(upload(&pb.d_eend, ee));
   CK(upload(&pb.d_first_child, fc)); CK(upload(&pb.d_n_child, nch));
@@ -274,6 +287,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_htab, (size_t)2 * n_off * NT * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_lat, (size_t)n_roff * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_latpart, (size_t)pb.M * ((pb.M + 3) / 4) * NP * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_alpha, (size_t)(hp.m_max - hp.m_min + 1) * sizeof(cd)));
   // GMRES workspace
   size_t n = 2 * (size_t)E;
@@ -288,7 +302,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipHostMalloc((void**)&pb.h_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_fields, (size_t)2 * 512 * sizeof(cd)));
   for (int i = 0; i < 16; ++i) CK(hipEventCreate(&pb.ev[i]));
+  CK(hipEventCreateWithFlags(&pb.ev_fork, hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&pb.ev_join, hipEventDisableTiming));
   pb.events = true;
+  CK(hipStreamCreateWithFlags(&pb.side, hipStreamNonBlocking));
 #undef CK
   *out = h;
   return PFM_OK;
@@ -365,21 +382,21 @@ pfm_status pfm_matvec_timed(pfm_problem* h, const void* d_psi, void* d_y, int re
   if (!h || !d_psi || !d_y || reps < 1) return PFM_EINVAL;
   Problem& pb = h->p;
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
-  double acc[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0}, tot = 0.0;
   for (int r = 0; r < reps; ++r) {
     HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, pb.ev));
-    HIPCHK(pb, hipEventSynchronize(pb.ev[6]));
-    for (int s = 0; s < 6; ++s) {
+    HIPCHK(pb, hipEventSynchronize(pb.ev[7]));
+    for (int s = 0; s < 7; ++s) {
       float ms = 0.f;
       HIPCHK(pb, hipEventElapsedTime(&ms, pb.ev[s], pb.ev[s + 1]));
       acc[s] += ms;
     }
     float all = 0.f;
-    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[6]));
+    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[7]));
     tot += all;
   }
   if (stage_ms)
-    for (int s = 0; s < 6; ++s) stage_ms[s] = acc[s] / reps;
+    for (int s = 0; s < 7; ++s) stage_ms[s] = acc[s] / reps;
   if (total_ms) *total_ms = tot / reps;
   return PFM_OK;
 }

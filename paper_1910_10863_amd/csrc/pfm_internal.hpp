@@ -76,6 +76,7 @@ struct Problem {
   double *d_gl = nullptr;               // far-rule nodes [g_far], weights [g_far]
   double *d_gl16 = nullptr;             // near-rule nodes [16], weights [16]
   int *d_elem_of = nullptr;
+  int *d_psi_idx = nullptr;             // tree position -> index of phi in Psi
   // cells
   double *d_cx = nullptr, *d_cy = nullptr;
   int *d_ebeg = nullptr, *d_eend = nullptr, *d_first_child = nullptr, *d_n_child = nullptr;
@@ -93,6 +94,7 @@ struct Problem {
   cd *d_htab = nullptr;                 // [2 ch][n_off][4p+1]
   cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
   cd *d_lat = nullptr;                  // [n_roff][4p+1]
+  cd *d_latpart = nullptr;              // lattice M2L partial sums [M][chunks][2p+1]
   cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights
   int n_srule = 0;
@@ -110,6 +112,8 @@ struct Problem {
   cd *d_fields = nullptr;
   hipEvent_t ev[16];
   bool events = false;
+  hipStream_t side = nullptr;           // FMM chain runs here, concurrent with P2P
+  hipEvent_t ev_fork, ev_join;
 };
 
 bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);

@@ -474,10 +474,13 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 //   M_n(C) = (i/4) sum_{e in C} sum_g w_g [ dJm_n/dn_y phi_e - i eta Jm_n varphi_e ],
 //   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2.
 // One wavefront per (leaf, channel); lane = element; per-lane partial moments
-// are summed through LDS (row per lane, one column per order).
+// are summed through LDS (row per lane, one column per order).  Orders are
+// walked by |n| with a window of three Jm values, so that only the scaled
+// Bessel sequence stays in registers.
 template <int P>
 __global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
                                             const int* __restrict__ eend, const int* __restrict__ elem_of,
+                                            const int* __restrict__ psi_idx,
                                             const double* __restrict__ cx, const double* __restrict__ cy,
                                             const double* __restrict__ mx, const double* __restrict__ my,
                                             const double* __restrict__ tx, const double* __restrict__ ty,
@@ -495,35 +498,52 @@ __global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, cons
   int b = ebeg[cell], e_ = eend[cell];
   for (int t = b + lane; t < e_; t += 64) {
     int e = elem_of[t];
-    int f = e / N, l = e - f * N;
-    cd phi = psi[2 * f * N + l], vphi = psi[2 * f * N + N + l];
+    int pi = psi_idx[t];
+    cd phi = psi[pi], vphi = psi[pi + N];
     double ex = mx[e], ey = my[e], etx = tx[e], ety = ty[e], hh = h[e];
     cd nu = mkc(ety, -etx);
-    // i/4 [ (kap/2) conj(nu) phi , -(kap/2) nu phi, -i eta vphi ]
     cd a_m = cmul(cscale(cconj(nu), 0.5 * kap), phi);      // multiplies Jm_{n-1}
     cd a_p = cmul(cscale(nu, -0.5 * kap), phi);            // multiplies Jm_{n+1}
     cd a_0 = cmul(mkc(0.0, -eta), vphi);                   // multiplies Jm_n
     for (int g = 0; g < G; ++g) {
       double s = 0.5 * hh * gl[g], w = 0.5 * hh * gl[G + g];
       double vx = kap * (ex + s * etx - ox), vy = kap * (ey + s * ety - oy);
-      cd jp[P + 2];
-      jplus_seq<P + 1>(vx, vy, jp);
-      // Jm_n = conj(Jp_n) (n >= 0);  Jm_{-n} = (-1)^n Jp_n
-      cd wa_m = cscale(mkc(-a_m.y, a_m.x), 0.25 * w);    // (i/4) w a
+      double gs[P + 2];
+      scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
+      // Jm_m(v) = (conj(v)/2)^m / m! g_m for m >= 0; Jm_{-m} = (-1)^m conj(Jm_m)
+      cd hv = mkc(0.5 * vx, -0.5 * vy);
+      cd wa_m = cscale(mkc(-a_m.y, a_m.x), 0.25 * w);      // (i/4) w a
       cd wa_p = cscale(mkc(-a_p.y, a_p.x), 0.25 * w);
       cd wa_0 = cscale(mkc(-a_0.y, a_0.x), 0.25 * w);
+      cd u = mkc(1.0, 0.0);
+      cd J0 = mkc(gs[0], 0.0);                             // Jm_m at m = 0
+      u = cmul(u, hv);
+      cd J1 = cscale(u, gs[1]);                            // Jm_1
+      cd Jprev = cscale(cconj(J1), -1.0);                  // Jm_{-1}
 #pragma unroll
-      for (int n = -P; n <= P; ++n) {
-        int an = n < 0 ? -n : n;
-        int am = (n - 1) < 0 ? -(n - 1) : (n - 1);
-        int ap = (n + 1) < 0 ? -(n + 1) : (n + 1);
-        cd j0 = n >= 0 ? cconj(jp[an]) : ((an & 1) ? cscale(jp[an], -1.0) : jp[an]);
-        cd jm = (n - 1) >= 0 ? cconj(jp[am]) : ((am & 1) ? cscale(jp[am], -1.0) : jp[am]);
-        cd jq = (n + 1) >= 0 ? cconj(jp[ap]) : ((ap & 1) ? cscale(jp[ap], -1.0) : jp[ap]);
-        cd v = cmul(wa_0, j0);
-        v = cfma(wa_m, jm, v);
-        v = cfma(wa_p, jq, v);
-        red[lane][n + P] = cadd(red[lane][n + P], v);
+      for (int m = 0; m <= P; ++m) {
+        // window: Jprev = Jm_{m-1}, J0 = Jm_m, J1 = Jm_{m+1}
+        cd v = cmul(wa_0, J0);
+        v = cfma(wa_m, Jprev, v);
+        v = cfma(wa_p, J1, v);
+        red[lane][P + m] = cadd(red[lane][P + m], v);
+        if (m > 0) {
+          // n = -m: Jm_{-m}, Jm_{-m-1}, Jm_{-m+1}
+          double sm = (m & 1) ? -1.0 : 1.0;
+          cd jn = cscale(cconj(J0), sm);
+          cd jnm = cscale(cconj(J1), -sm);
+          cd jnp = cscale(cconj(Jprev), -sm);
+          cd vn = cmul(wa_0, jn);
+          vn = cfma(wa_m, jnm, vn);
+          vn = cfma(wa_p, jnp, vn);
+          red[lane][P - m] = cadd(red[lane][P - m], vn);
+        }
+        if (m < P) {
+          u = cscale(cmul(u, hv), 1.0 / (double)(m + 2));
+          Jprev = J0;
+          J0 = J1;
+          J1 = cscale(u, gs[m + 2]);
+        }
       }
     }
   }
@@ -617,19 +637,23 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ ptr_e, const
   }
 }
 
-// Lattice M2L at the roots: L_l(root_i) += sum_j sum_n S_{n-l}(c_i - c_j) M_n(root_j).
+// Lattice M2L at the roots, split over chunks of LAT_CHUNK source fibres:
+//   part[i][chunk] = sum_{j in chunk} sum_n S_{n-l}(c_i - c_j) M_n(root_j),
+// then reduced in a fixed order and added to L(root_i).
+constexpr int LAT_CHUNK = 4;
+
 template <int P>
 __global__ void __launch_bounds__(64) k_lattice_m2l(int M, const int* __restrict__ root_of_fibre,
                                                     const int* __restrict__ pair_off,
                                                     const cd* __restrict__ lat,
-                                                    const cd* __restrict__ mpole, cd* local) {
+                                                    const cd* __restrict__ mpole, cd* __restrict__ part) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
   __shared__ cd sm[NP], sh[NT];
   int i = blockIdx.x;
-  int D = root_of_fibre[i];
+  int j0 = blockIdx.y * LAT_CHUNK, j1 = min(M, j0 + LAT_CHUNK);
   cd acc[(NP + 63) / 64];
   for (int u = 0; u < (NP + 63) / 64; ++u) acc[u] = mkc(0, 0);
-  for (int j = 0; j < M; ++j) {
+  for (int j = j0; j < j1; ++j) {
     int C = root_of_fibre[j];
     const cd* ms = mpole + ((size_t)C * 2) * NP;
     const cd* th = lat + (size_t)pair_off[(size_t)i * M + j] * NT;
@@ -645,10 +669,21 @@ __global__ void __launch_bounds__(64) k_lattice_m2l(int M, const int* __restrict
     }
     __syncthreads();
   }
-  cd* out = local + ((size_t)D * 2) * NP;
+  cd* out = part + ((size_t)i * gridDim.y + blockIdx.y) * NP;
   for (int u = 0; u < (NP + 63) / 64; ++u) {
     int l = threadIdx.x + 64 * u;
-    if (l < NP) out[l] = cadd(out[l], acc[u]);
+    if (l < NP) out[l] = acc[u];
+  }
+}
+
+__global__ void k_lattice_reduce(int NP, int nchunk, const int* __restrict__ root_of_fibre,
+                                 const cd* __restrict__ part, cd* local) {
+  int i = blockIdx.x;
+  cd* out = local + (size_t)root_of_fibre[i] * 2 * NP;
+  for (int l = threadIdx.x; l < NP; l += blockDim.x) {
+    cd s = out[l];
+    for (int c = 0; c < nchunk; ++c) s = cadd(s, part[((size_t)i * nchunk + c) * NP + l]);
+    out[l] = s;
   }
 }
 
@@ -676,98 +711,148 @@ __global__ void __launch_bounds__(64) k_l2l(int cbeg, const int* __restrict__ pa
   }
 }
 
-// Leaf evaluation: L2P at both wavenumbers, P2P with the stored blocks, and
-// the rows of (I - A) (eq. 9):
-//   y1 = phi + u_ext - u_int
-//   y2 = varphi + 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int)
-// with u = sum_l L_l Jp_l(kap (x - O)),
-//      dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}).
-// One workgroup (4 wavefronts) per leaf; lane = target row; the wavefronts
-// split the source columns of the near blocks and meet in LDS.
-template <int P>
-__global__ void __launch_bounds__(256) k_leaf(
+// P2P with the stored near blocks plus the identity of (I - A):
+//   y1 = phi + sum_b (B11 phi_b + B12 varphi_b),  y2 = varphi + sum_b (B21 phi_b + B22 varphi_b).
+// One workgroup (4 wavefronts) per target leaf, lane = target row; the
+// wavefronts take the source columns of the leaf's near blocks in turn and
+// meet in LDS.  Pure streaming of the blocks: the kernel is HBM-bound.
+constexpr int P2P_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
-    const int* __restrict__ elem_of, const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ mx, const double* __restrict__ my, const double* __restrict__ tx,
-    const double* __restrict__ ty, int N, double k, double k1, double eta, double varrho,
-    const int* __restrict__ near_ptr, const int* __restrict__ near_src,
-    const long long* __restrict__ near_blk, const cd* __restrict__ blocks, long long n_entries,
-    const cd* __restrict__ local, const cd* __restrict__ psi, cd* __restrict__ y) {
-  constexpr int NP = 2 * P + 1;
-  __shared__ cd sL[2][NP];
-  __shared__ cd r1[4][64], r2[4][64];
-  __shared__ cd su[2][64], sd[2][64];
+    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
+    const int* __restrict__ near_src, const long long* __restrict__ near_blk,
+    const cd* __restrict__ blocks, long long n_entries, const cd* __restrict__ psi, cd* __restrict__ y) {
+  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   int li = blockIdx.x;
   int D = leaves[li];
   int db = ebeg[D], rows = eend[D] - db;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < 2 * NP; i += 256) sL[i / NP][i % NP] = local[(size_t)D * 2 * NP + i];
   cd a1 = mkc(0, 0), a2 = mkc(0, 0);
   const cd* B11 = blocks;
   const cd* B12 = blocks + n_entries;
   const cd* B21 = blocks + 2 * n_entries;
   const cd* B22 = blocks + 3 * n_entries;
   int qb = near_ptr[li], qe = near_ptr[li + 1];
+  bool act = lane < rows;
   for (int q = qb; q < qe; ++q) {
     int C = near_src[q];
     int cb = ebeg[C], cols = eend[C] - cb;
-    long long blk = near_blk[q];
-    for (int c = w; c < cols; c += 4) {
-      int ec = elem_of[cb + c];
-      int f = ec / N, l = ec - f * N;
-      cd ph = psi[2 * f * N + l], vp = psi[2 * f * N + N + l];
-      if (lane < rows) {
-        long long idx = blk + (long long)c * rows + lane;
-        a1 = cfma(B11[idx], ph, a1);
-        a1 = cfma(B12[idx], vp, a1);
-        a2 = cfma(B21[idx], ph, a2);
-        a2 = cfma(B22[idx], vp, a2);
+    long long base = near_blk[q] + lane;
+    int c = w;
+    for (; c + P2P_WAVES < cols; c += 2 * P2P_WAVES) {
+      int pa = psi_idx[cb + c], pb_ = psi_idx[cb + c + P2P_WAVES];
+      cd ph0 = psi[pa], vp0 = psi[pa + N], ph1 = psi[pb_], vp1 = psi[pb_ + N];
+      if (act) {
+        long long i0 = base + (long long)c * rows;
+        long long i1 = i0 + (long long)P2P_WAVES * rows;
+        cd b110 = B11[i0], b120 = B12[i0], b210 = B21[i0], b220 = B22[i0];
+        cd b111 = B11[i1], b121 = B12[i1], b211 = B21[i1], b221 = B22[i1];
+        a1 = cfma(b110, ph0, a1);
+        a1 = cfma(b120, vp0, a1);
+        a2 = cfma(b210, ph0, a2);
+        a2 = cfma(b220, vp0, a2);
+        a1 = cfma(b111, ph1, a1);
+        a1 = cfma(b121, vp1, a1);
+        a2 = cfma(b211, ph1, a2);
+        a2 = cfma(b221, vp1, a2);
+      }
+    }
+    for (; c < cols; c += P2P_WAVES) {
+      int pa = psi_idx[cb + c];
+      cd ph0 = psi[pa], vp0 = psi[pa + N];
+      if (act) {
+        long long i0 = base + (long long)c * rows;
+        a1 = cfma(B11[i0], ph0, a1);
+        a1 = cfma(B12[i0], vp0, a1);
+        a2 = cfma(B21[i0], ph0, a2);
+        a2 = cfma(B22[i0], vp0, a2);
       }
     }
   }
   r1[w][lane] = a1;
   r2[w][lane] = a2;
   __syncthreads();
-  if (w < 2 && lane < rows) {
-    int ch = w;
-    double kap = ch ? k1 : k;
+  if (w == 0 && act) {
+    cd s1 = r1[0][lane], s2 = r2[0][lane];
+#pragma unroll
+    for (int v = 1; v < P2P_WAVES; ++v) {
+      s1 = cadd(s1, r1[v][lane]);
+      s2 = cadd(s2, r2[v][lane]);
+    }
+    int pi = psi_idx[db + lane];
+    y[pi] = cadd(psi[pi], s1);
+    y[pi + N] = cadd(psi[pi + N], s2);
+  }
+}
+
+// L2P at both wavenumbers and the far part of the rows of (I - A) (eq. 9):
+//   y1 += u_ext - u_int,  y2 += 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int),
+//   u = sum_l L_l Jp_l(kap (x - O)),  dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}).
+// One workgroup of two wavefronts (channels) per leaf, lane = target row.
+template <int P>
+__global__ void __launch_bounds__(128) k_l2p(
+    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
+    const int* __restrict__ elem_of, const int* __restrict__ psi_idx, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ mx, const double* __restrict__ my,
+    const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1,
+    double eta, double varrho, const cd* __restrict__ local, cd* __restrict__ y) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd sL[2][NP];
+  __shared__ cd su[64], sd[64];
+  int D = leaves[blockIdx.x];
+  int db = ebeg[D], rows = eend[D] - db;
+  int ch = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < 2 * NP; i += 128) sL[i / NP][i % NP] = local[(size_t)D * 2 * NP + i];
+  __syncthreads();
+  cd u = mkc(0, 0), dv = mkc(0, 0);
+  double kap = ch ? k1 : k;
+  if (lane < rows) {
     int e = elem_of[db + lane];
     double vx = kap * (mx[e] - cx[D]), vy = kap * (my[e] - cy[D]);
     cd nu = mkc(ty[e], -tx[e]);
-    cd jp[P + 2];
-    jplus_seq<P + 1>(vx, vy, jp);
-    cd u = mkc(0, 0), dv = mkc(0, 0);
+    cd nub = cconj(nu);
+    double gs[P + 2];
+    scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
+    cd hv = mkc(0.5 * vx, 0.5 * vy);
+    cd uu = cmul(mkc(1.0, 0.0), hv);
+    cd J0 = mkc(gs[0], 0.0);                 // Jp_0
+    cd J1 = cscale(uu, gs[1]);               // Jp_1
+    cd Jprev = cscale(cconj(J1), -1.0);      // Jp_{-1}
 #pragma unroll
-    for (int l = -P; l <= P; ++l) {
-      int al = l < 0 ? -l : l;
-      int am = (l - 1) < 0 ? -(l - 1) : (l - 1);
-      int ap = (l + 1) < 0 ? -(l + 1) : (l + 1);
-      // Jp_{-n} = (-1)^n conj(Jp_n)
-      cd j0 = l >= 0 ? jp[al] : ((al & 1) ? cscale(cconj(jp[al]), -1.0) : cconj(jp[al]));
-      cd jm = (l - 1) >= 0 ? jp[am] : ((am & 1) ? cscale(cconj(jp[am]), -1.0) : cconj(jp[am]));
-      cd jq = (l + 1) >= 0 ? jp[ap] : ((ap & 1) ? cscale(cconj(jp[ap]), -1.0) : cconj(jp[ap]));
-      cd Ll = sL[ch][l + P];
-      u = cfma(Ll, j0, u);
-      cd dj = csub(cmul(nu, jm), cmul(cconj(nu), jq));
-      dv = cfma(Ll, dj, dv);
+    for (int m = 0; m <= P; ++m) {
+      cd Lp = sL[ch][P + m];
+      u = cfma(Lp, J0, u);
+      dv = cfma(Lp, csub(cmul(nu, Jprev), cmul(nub, J1)), dv);
+      if (m > 0) {
+        // l = -m: Jp_{-m} = (-1)^m conj(Jp_m), Jp_{-m-1}, Jp_{-m+1}
+        double sm = (m & 1) ? -1.0 : 1.0;
+        cd jn = cscale(cconj(J0), sm);
+        cd jnm = cscale(cconj(J1), -sm);
+        cd jnp = cscale(cconj(Jprev), -sm);
+        cd Lm = sL[ch][P - m];
+        u = cfma(Lm, jn, u);
+        dv = cfma(Lm, csub(cmul(nu, jnm), cmul(nub, jnp)), dv);
+      }
+      if (m < P) {
+        uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
+        Jprev = J0;
+        J0 = J1;
+        J1 = cscale(uu, gs[m + 2]);
+      }
     }
-    su[ch][lane] = u;
-    sd[ch][lane] = cscale(dv, 0.5 * kap);
+    dv = cscale(dv, 0.5 * kap);
+  }
+  if (ch == 1) {
+    su[lane] = u;
+    sd[lane] = dv;
   }
   __syncthreads();
-  if (w == 0 && lane < rows) {
-    int e = elem_of[db + lane];
-    int f = e / N, l = e - f * N;
-    cd p1 = cadd(cadd(r1[0][lane], r1[1][lane]), cadd(r1[2][lane], r1[3][lane]));
-    cd p2 = cadd(cadd(r2[0][lane], r2[1][lane]), cadd(r2[2][lane], r2[3][lane]));
+  if (ch == 0 && lane < rows) {
+    int pi = psi_idx[db + lane];
     cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
-    cd y1 = cadd(psi[2 * f * N + l], csub(su[0][lane], su[1][lane]));
-    y1 = cadd(y1, p1);
-    cd dn = csub(sd[0][lane], cscale(sd[1][lane], varrho));
-    cd y2 = cfma(c, dn, psi[2 * f * N + N + l]);
-    y2 = cadd(y2, p2);
-    y[2 * f * N + l] = y1;
-    y[2 * f * N + N + l] = y2;
+    y[pi] = cadd(y[pi], csub(u, su[lane]));
+    y[pi + N] = cfma(c, csub(dv, cscale(sd[lane], varrho)), y[pi + N]);
   }
 }
 
@@ -785,54 +870,77 @@ static hipError_t tables_impl(Problem& pb) {
   return hipGetLastError();
 }
 
+// The FMM chain: P2M, M2M (bottom-up), M2L, lattice M2L, L2L (top-down).
 template <int P>
-static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
-  const HostPlan& hp = pb.hp;
-  int n_leaves = (int)hp.leaves.size();
-  int n_joff = (int)hp.joff_xy.size() / 2;
-  if (ev) (void)hipEventRecord(ev[0], pb.stream);
-  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(64), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                     pb.d_eend, pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
-                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole);
-  if (ev) (void)hipEventRecord(ev[1], pb.stream);
-  for (int lv = hp.depth - 1; lv >= 0; --lv) {
-    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
-    if (ce > cb)
-      hipLaunchKernelGGL(k_m2m<P>, dim3(ce - cb, 2), dim3(64), 0, pb.stream, cb, pb.d_first_child,
-                         pb.d_n_child, pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_mpole);
-  }
-  if (ev) (void)hipEventRecord(ev[2], pb.stream);
-  return hipGetLastError();
-}
-
-template <int P>
-static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only) {
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
   int n_off = (int)hp.off_xy.size() / 2;
   int n_joff = (int)hp.joff_xy.size() / 2;
-  hipError_t err = upward_impl<P>(pb, d_psi, ev);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_m2l<P>, dim3(nc, 2), dim3(64), 0, pb.stream, pb.d_m2l_ptr, pb.d_m2l_src,
-                     pb.d_m2l_off, pb.d_m2l_m, pb.d_m2li_ptr, pb.d_m2li_src, pb.d_m2li_off, pb.d_htab,
-                     n_off, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_local);
-  if (ev) (void)hipEventRecord(ev[3], pb.stream);
-  hipLaunchKernelGGL(k_lattice_m2l<P>, dim3(pb.M), dim3(64), 0, pb.stream, pb.M, pb.d_root_of_fibre,
-                     pb.d_root_pair_off, pb.d_lat, pb.d_mpole, pb.d_local);
-  if (ev) (void)hipEventRecord(ev[4], pb.stream);
+  constexpr int NP = 2 * P + 1;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(64), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
+                     pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
+                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  for (int lv = hp.depth - 1; lv >= 0; --lv) {
+    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
+    if (ce > cb)
+      hipLaunchKernelGGL(k_m2m<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, pb.d_first_child, pb.d_n_child,
+                         pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_mpole);
+  }
+  if (ev) (void)hipEventRecord(ev[2], s);
+  if (upward_only) return;
+  hipLaunchKernelGGL(k_m2l<P>, dim3(nc, 2), dim3(64), 0, s, pb.d_m2l_ptr, pb.d_m2l_src, pb.d_m2l_off,
+                     pb.d_m2l_m, pb.d_m2li_ptr, pb.d_m2li_src, pb.d_m2li_off, pb.d_htab, n_off, pb.d_alpha,
+                     hp.m_min, pb.d_mpole, pb.d_local);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  int nchunk = (pb.M + LAT_CHUNK - 1) / LAT_CHUNK;
+  hipLaunchKernelGGL(k_lattice_m2l<P>, dim3(pb.M, nchunk), dim3(64), 0, s, pb.M, pb.d_root_of_fibre,
+                     pb.d_root_pair_off, pb.d_lat, pb.d_mpole, pb.d_latpart);
+  hipLaunchKernelGGL(k_lattice_reduce, dim3(pb.M), dim3(64), 0, s, NP, nchunk, pb.d_root_of_fibre,
+                     pb.d_latpart, pb.d_local);
+  if (ev) (void)hipEventRecord(ev[4], s);
   for (int lv = 1; lv <= hp.depth; ++lv) {
     int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
     if (ce > cb)
-      hipLaunchKernelGGL(k_l2l<P>, dim3(ce - cb, 2), dim3(64), 0, pb.stream, cb, pb.d_parent,
-                         pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_local);
+      hipLaunchKernelGGL(k_l2l<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, pb.d_parent, pb.d_cell_joff,
+                         pb.d_jtab, n_joff, pb.d_local);
   }
-  if (ev) (void)hipEventRecord(ev[5], pb.stream);
-  hipLaunchKernelGGL(k_leaf<P>, dim3(n_leaves), dim3(256), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                     pb.d_eend, pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
-                     pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_near_ptr, pb.d_near_src,
-                     pb.d_near_blk, pb.d_near, hp.n_near_entries, pb.d_local, d_psi, d_y);
+  if (ev) (void)hipEventRecord(ev[5], s);
+}
+
+template <int P>
+static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
+  fmm_chain<P>(pb, d_psi, pb.stream, ev, true);
+  return hipGetLastError();
+}
+
+// y = (I - A) psi.  Without stage events the FMM chain runs on the side
+// stream while the near field streams through HBM on the caller's stream;
+// L2P joins both.  With stage events everything runs in order on the
+// caller's stream so that each stage can be timed alone.
+template <int P>
+static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  const HostPlan& hp = pb.hp;
+  int n_leaves = (int)hp.leaves.size();
+  hipStream_t fs = ev ? pb.stream : pb.side;
+  if (!ev) {
+    (void)hipEventRecord(pb.ev_fork, pb.stream);
+    (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
+  }
+  fmm_chain<P>(pb, d_psi, fs, ev, false);
+  if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
+  hipLaunchKernelGGL(k_p2p, dim3(n_leaves), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_src, pb.d_near_blk,
+                     pb.d_near, hp.n_near_entries, d_psi, d_y);
   if (ev) (void)hipEventRecord(ev[6], pb.stream);
+  if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
+  hipLaunchKernelGGL(k_l2p<P>, dim3(n_leaves), dim3(128), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+                     pb.d_eend, pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx,
+                     pb.d_ty, pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_local, d_y);
+  if (ev) (void)hipEventRecord(ev[7], pb.stream);
   return hipGetLastError();
 }
 

@@ -1,0 +1,163 @@
+"""GPU parity at the benchmark sizes and in the launch configuration that
+bench.py times, on outputs the oracle computes one by one: sampled rows of
+(I - A) applied to a random density, and the lattice sums of every fibre
+offset.  Plus edge cases (smallest element count, one-element leaves, ragged
+leaves), determinism and the error paths of the C ABI.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10863_amd import pfm as m
+    m.lib()
+    return m
+
+
+def _rows_parity(pfm, wl, ka, th, n_rows, seed, **kw):
+    from oracle import system as sy
+    prob = pfm.Problem.from_workload(wl, **kw)
+    prob.set_wave(ka, th)
+    psi = W.random_density(prob.n, seed)
+    y = prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy()
+    pb = sy.problem_from_workload(wl, ka, th)
+    rng = np.random.default_rng(seed)
+    tg = np.sort(rng.choice(pb.bd.E, n_rows, replace=False))
+    R1, R2 = sy.operator_rows(pb, tg)
+    r = np.concatenate([R1 @ psi, R2 @ psi])
+    g = np.concatenate([y[sy.col_phi(pb.bd, tg)], y[sy.col_varphi(pb.bd, tg)]])
+    err = np.max(np.abs(g - r)) / np.sqrt(np.mean(np.abs(r) ** 2))
+    return err, prob
+
+
+# square 8x8 block, 65536 unknowns, p = 24, leaf 64: the benchmark workload
+@pytest.mark.parametrize("ka", [0.5, 3.338709677419355, 6.0])
+def test_square_8x8_rows(pfm, ka):
+    wl = W.square_8x8()
+    _say("square 8x8 rows, ka =", ka)
+    err, prob = _rows_parity(pfm, wl, ka, 0.0, 8, 21, restart=200)
+    _say("  max row error / rms", err)
+    assert err < 1e-8
+
+
+def test_hexagon_16x16_rows(pfm):
+    wl = W.hexagon_16x16()
+    _say("hexagon 16x16 rows")
+    err, prob = _rows_parity(pfm, wl, wl.ka[0], wl.theta[0], 6, 22)
+    _say("  max row error / rms", err, prob.stats()["n_near_entries"])
+    assert err < 1e-8
+
+
+@pytest.mark.parametrize("ka,th", [(0.2, 0.0), (4.0, 3 * math.pi / 16), (8.0, 7 * math.pi / 16)])
+def test_square_4x4_rows(pfm, ka, th):
+    wl = W.square_4x4_sweep()
+    _say("square 4x4 rows", ka, th)
+    err, prob = _rows_parity(pfm, wl, ka, th, 8, 23)
+    _say("  max row error / rms", err)
+    assert err < 1e-8
+
+
+def test_lattice_sums_square_8x8(pfm):
+    from oracle.lattice import lattice_sum_orders
+    wl = W.square_8x8()
+    prob = pfm.Problem.from_workload(wl)
+    for ka in (0.5, 6.0):
+        prob.set_wave(ka, 0.0)
+        S, offs, mr = prob.lattice_sums()
+        _say("lattice 8x8 ka", ka, "offsets", S.shape[0])
+        for o in range(0, S.shape[0], 16):
+            ex = tuple(range(mr[o, 0], mr[o, 1] + 1))
+            ref = lattice_sum_orders(ka, 8.0, 0.0, offs[o, 0], offs[o, 1], 2 * wl.p, exclude=ex)
+            mag = np.abs(ref)
+            scale = np.maximum(mag, np.maximum(np.roll(mag, 1), np.roll(mag, -1)))
+            assert np.max(np.abs(S[o] - ref) / scale) < 1e-10, offs[o]
+
+
+@pytest.mark.parametrize("case", ["n8_leaf1", "ragged_hex", "one_leaf"])
+def test_edge_cases_dense(pfm, case):
+    from oracle import system as sy
+    if case == "n8_leaf1":
+        wl = W.small_square(1, 1, 8, 0.3, 1.5, 0.4, p=8, leaf_max=1)
+        kw = dict(p=16, leaf_max=1)
+    elif case == "ragged_hex":
+        wl = W.small_square(3, 2, 100, 0.3, 2.5, -0.3, lattice=W.HEXAGON,
+                            radii=np.array([0.3, 0.25, 0.28, 0.31, 0.22, 0.3]))
+        kw = dict(p=32, leaf_max=13)
+    else:
+        wl = W.small_square(2, 1, 40, 0.3, 3.0, 0.2)
+        kw = dict(p=32, leaf_max=64)
+    ka, th = wl.ka[0], wl.theta[0]
+    prob = pfm.Problem.from_workload(wl, **kw)
+    prob.set_wave(ka, th)
+    psi = W.random_density(prob.n, 4)
+    y = prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy()
+    pb = sy.problem_from_workload(wl, ka, th)
+    ref = sy.dense_matrix(pb) @ psi
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    _say(case, "rel err", err, prob.stats()["depth"])
+    assert err < 1e-9
+
+
+def test_apply_is_deterministic(pfm):
+    wl = W.square_4x4_sweep()
+    prob = pfm.Problem.from_workload(wl)
+    prob.set_wave(3.0, 0.3)
+    psi = torch.tensor(W.random_density(prob.n, 9), device="cuda")
+    a = prob.matvec(psi).clone()
+    b = prob.matvec(psi).clone()
+    assert torch.equal(a, b)
+
+
+def test_timed_apply_matches_overlapped_apply(pfm):
+    wl = W.square_4x4_sweep()
+    prob = pfm.Problem.from_workload(wl)
+    prob.set_wave(2.0, 0.1)
+    psi = torch.tensor(W.random_density(prob.n, 10), device="cuda")
+    a = prob.matvec(psi).clone()
+    stages, tot, b = prob.matvec_timed(psi, reps=2)
+    assert torch.equal(a, b)
+    assert all(v >= 0 for v in stages.values()) and tot > 0
+
+
+def test_gmres_noconv_and_wood_errors(pfm):
+    wl = W.square_4x4_sweep()
+    prob = pfm.Problem.from_workload(wl, max_iter=2, restart=2)
+    prob.set_wave(3.0, 0.0)
+    x, info = prob.solve()
+    assert info["status"] == 4 and info["iters"] == 2
+    assert np.isfinite(x.cpu().numpy()).all()
+    with pytest.raises(pfm.PfmError) as e:
+        prob.solve(raise_on_noconv=True)
+    assert e.value.code == 4
+    # k H (1 + sin 0) / (2 pi) = 1 exactly: a Wood anomaly of the 4-row block
+    prob2 = pfm.Problem.from_workload(wl, wood_margin=1e-3)
+    with pytest.raises(pfm.PfmError) as e:
+        prob2.set_wave(2 * math.pi / 4, 0.0)
+    assert e.value.code == 5
+    with pytest.raises(ValueError):
+        prob.matvec(torch.zeros(10, dtype=torch.complex128, device="cuda"))
+
+
+def test_warm_start_from_solution_converges_immediately(pfm):
+    wl = W.square_4x4_sweep()
+    prob = pfm.Problem.from_workload(wl, tol=1e-10, restart=100)
+    prob.set_wave(2.5, 0.2)
+    x, info = prob.solve()
+    assert info["status"] == 0
+    x2, info2 = prob.solve(x0=x)
+    assert info2["iters"] == 0 and info2["status"] == 0
