@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy before timing, for HBM counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multi-GPU sharding is not built "
@@ -95,6 +97,14 @@ def main():
     st = prob.stats()
     psi = torch.tensor(W.random_density(prob.n, 5), device="cuda")
     y = prob.empty()
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration * (1 << 20)
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         prob.matvec(psi, y)
     torch.cuda.synchronize()

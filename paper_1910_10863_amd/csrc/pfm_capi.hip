@@ -65,17 +65,19 @@ void dfree(T*& d) {
 void free_all(Problem& pb) {
   dfree(pb.d_centres); dfree(pb.d_radii);
   dfree(pb.d_mx); dfree(pb.d_my); dfree(pb.d_tx); dfree(pb.d_ty); dfree(pb.d_h);
-  dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx); dfree(pb.d_latpart);
+  dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx);
+  dfree(pb.d_e_src); dfree(pb.d_e_off); dfree(pb.d_e_m); dfree(pb.d_chunks); dfree(pb.d_cc_ptr);
+  dfree(pb.d_part);
   dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
   dfree(pb.d_first_child); dfree(pb.d_n_child); dfree(pb.d_cell_joff); dfree(pb.d_parent);
   dfree(pb.d_leaves); dfree(pb.d_root_of_fibre); dfree(pb.d_fibre_of_cell);
   dfree(pb.d_m2l_ptr); dfree(pb.d_m2l_src); dfree(pb.d_m2l_off); dfree(pb.d_m2l_m);
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
-  dfree(pb.d_near_blk);
+  dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi);
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
-  dfree(pb.d_near); dfree(pb.d_htab); dfree(pb.d_jtab); dfree(pb.d_lat); dfree(pb.d_alpha);
+  dfree(pb.d_near); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
   dfree(pb.d_srule);
   dfree(pb.d_mpole); dfree(pb.d_local);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
@@ -254,6 +256,23 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(upload(&pb.d_near_ptr, hp.near_ptr)); CK(upload(&pb.d_near_src, hp.near_src));
   CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
   CK(upload(&pb.d_near_blk, hp.near_blk));
+  {
+    // flattened source columns of every target leaf's near list, in storage order
+    int nl = (int)hp.leaves.size();
+    std::vector<int> cptr(nl + 1, 0), cpsi;
+    for (int li = 0; li < nl; ++li) {
+      for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
+        const Cell& C = hp.cells[hp.near_src[q]];
+        for (int t = C.ebeg; t < C.eend; ++t) {
+          int e = hp.elem_of[t], f = e / pb.N;
+          cpsi.push_back(2 * f * pb.N + (e - f * pb.N));
+        }
+      }
+      cptr[li + 1] = (int)cpsi.size();
+    }
+    CK(upload(&pb.d_cols_ptr, cptr));
+    CK(upload(&pb.d_col_psi, cpsi));
+  }
   CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
   CK(upload(&pb.d_off_xy, hp.off_xy)); CK(upload(&pb.d_joff_xy, hp.joff_xy));
@@ -284,10 +303,53 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   int n_off = std::max<int>(1, (int)hp.off_xy.size() / 2);
   int n_joff = std::max<int>(1, (int)hp.joff_xy.size() / 2);
   int n_roff = std::max<int>(1, (int)hp.root_off_xy.size() / 2);
-  CK(hipMalloc((void**)&pb.d_htab, (size_t)2 * n_off * NT * sizeof(cd)));
+  // translation table rows per channel: explicit M2L offsets, then lattice offsets
+  int n_off_real = (int)hp.off_xy.size() / 2;
+  pb.n_tab = n_off_real + n_roff;
+  CK(hipMalloc((void**)&pb.d_htab, (size_t)2 * pb.n_tab * NT * sizeof(cd)));
+  CK(hipMemset(pb.d_htab, 0, (size_t)2 * pb.n_tab * NT * sizeof(cd)));
+  pb.d_lat = pb.d_htab + (size_t)n_off_real * NT;
   CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_lat, (size_t)n_roff * NT * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_latpart, (size_t)pb.M * ((pb.M + 3) / 4) * NP * sizeof(cd)));
+  (void)n_off;
+  {
+    // M2L work list: per (channel, cell) the entries (source cell, table row, image),
+    // cut into chunks of at most M2L_CHUNK entries
+    const int M2L_CHUNK = 4;
+    std::vector<int> esrc, eoff, em, chunks, ccptr(2 * (size_t)nc + 1, 0);
+    std::vector<int> fibre_of_root(nc, -1);
+    for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;
+    for (int ch = 0; ch < 2; ++ch) {
+      for (int c = 0; c < nc; ++c) {
+        int first = (int)esrc.size();
+        if (ch == 0) {
+          for (int q = hp.m2l_ptr[c]; q < hp.m2l_ptr[c + 1]; ++q) {
+            esrc.push_back(hp.m2l_src[q]); eoff.push_back(hp.m2l_off[q]); em.push_back(hp.m2l_m[q]);
+          }
+          int fi = fibre_of_root[c];
+          if (fi >= 0)
+            for (int j = 0; j < pb.M; ++j) {
+              esrc.push_back(hp.root_of_fibre[j]);
+              eoff.push_back(n_off_real + hp.root_pair_off[(size_t)fi * pb.M + j]);
+              em.push_back(0);
+            }
+        } else {
+          for (int q = hp.m2li_ptr[c]; q < hp.m2li_ptr[c + 1]; ++q) {
+            esrc.push_back(hp.m2li_src[q]); eoff.push_back(hp.m2li_off[q]); em.push_back(0);
+          }
+        }
+        int last = (int)esrc.size();
+        for (int b = first; b < last; b += M2L_CHUNK) {
+          chunks.push_back(c); chunks.push_back(ch); chunks.push_back(b);
+          chunks.push_back(std::min(M2L_CHUNK, last - b));
+        }
+        ccptr[(size_t)ch * nc + c + 1] = (int)(chunks.size() / 4);
+      }
+    }
+    pb.n_chunks = (int)(chunks.size() / 4);
+    CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
+    CK(upload(&pb.d_chunks, chunks)); CK(upload(&pb.d_cc_ptr, ccptr));
+    CK(hipMalloc((void**)&pb.d_part, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd)));
+  }
   CK(hipMalloc((void**)&pb.d_alpha, (size_t)(hp.m_max - hp.m_min + 1) * sizeof(cd)));
   // GMRES workspace
   size_t n = 2 * (size_t)E;
@@ -382,21 +444,21 @@ pfm_status pfm_matvec_timed(pfm_problem* h, const void* d_psi, void* d_y, int re
   if (!h || !d_psi || !d_y || reps < 1) return PFM_EINVAL;
   Problem& pb = h->p;
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0}, tot = 0.0;
+  double acc[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
   for (int r = 0; r < reps; ++r) {
     HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, pb.ev));
-    HIPCHK(pb, hipEventSynchronize(pb.ev[7]));
-    for (int s = 0; s < 7; ++s) {
+    HIPCHK(pb, hipEventSynchronize(pb.ev[6]));
+    for (int s = 0; s < 6; ++s) {
       float ms = 0.f;
       HIPCHK(pb, hipEventElapsedTime(&ms, pb.ev[s], pb.ev[s + 1]));
       acc[s] += ms;
     }
     float all = 0.f;
-    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[7]));
+    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[6]));
     tot += all;
   }
   if (stage_ms)
-    for (int s = 0; s < 7; ++s) stage_ms[s] = acc[s] / reps;
+    for (int s = 0; s < 6; ++s) stage_ms[s] = acc[s] / reps;
   if (total_ms) *total_ms = tot / reps;
   return PFM_OK;
 }

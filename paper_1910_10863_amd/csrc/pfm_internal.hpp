@@ -87,14 +87,23 @@ struct Problem {
   int *d_m2li_ptr = nullptr, *d_m2li_src = nullptr, *d_m2li_off = nullptr;
   int *d_near_ptr = nullptr, *d_near_src = nullptr, *d_near_m = nullptr, *d_near_tgt = nullptr;
   long long *d_near_blk = nullptr;
+  int *d_cols_ptr = nullptr;            // per leaf: range of its flattened near source columns
+  int *d_col_psi = nullptr;             // flattened near source columns: index of phi in Psi
   int *d_root_pair_off = nullptr, *d_root_mrange = nullptr;
   double *d_off_xy = nullptr, *d_joff_xy = nullptr, *d_root_off_xy = nullptr;
   // per-wave data
   cd *d_near = nullptr;                 // 4 planes of n_near_entries
-  cd *d_htab = nullptr;                 // [2 ch][n_off][4p+1]
+  cd *d_htab = nullptr;                 // [2 ch][n_tab][4p+1]
   cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
-  cd *d_lat = nullptr;                  // [n_roff][4p+1]
-  cd *d_latpart = nullptr;              // lattice M2L partial sums [M][chunks][2p+1]
+  cd *d_lat = nullptr;                  // = d_htab + n_off rows: lattice sums [n_roff][4p+1]
+  // M2L work split into chunks of at most M2L_CHUNK entries of one (cell, channel);
+  // exterior entries of a root cell include one lattice entry per source fibre
+  int *d_e_src = nullptr, *d_e_off = nullptr, *d_e_m = nullptr;
+  int *d_chunks = nullptr;              // [n_chunks][4]: cell, channel, first entry, count
+  int *d_cc_ptr = nullptr;              // [2*n_cells+1]: chunks of (channel, cell)
+  cd *d_part = nullptr;                 // [n_chunks][2p+1] partial local expansions
+  int n_chunks = 0;
+  int n_tab = 0;                        // rows per channel of d_htab: M2L offsets, then lattice offsets
   cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights
   int n_srule = 0;

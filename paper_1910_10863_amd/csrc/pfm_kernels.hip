@@ -4,10 +4,11 @@
 // natural order (fibre-major).  Expansion coefficients of cell c, channel
 // ch (0: exterior wavenumber k, 1: interior wavenumber k1), order n in
 // [-p, p] live at [(c * 2 + ch) * (2p+1) + n + p].  Translation tables hold
-// orders nu in [-2p, 2p] at [nu + 2p].  P2P blocks are four planes
-// (B11, B12, B21, B22) of one complex value per (target, source) element
-// pair; inside a leaf pair the pairs are column-major (source column, then
-// target row) so that the lanes of a wavefront, which own target rows, read
+// orders nu in [-2p, 2p] at [nu + 2p].  P2P blocks hold four complex values
+// (B11, B12, B21, B22) per (target, source) element pair, laid out per near
+// leaf pair as [source column][component][target row]; the pairs of one
+// target leaf follow each other, so the near field of a leaf is one
+// contiguous stream and the lanes of a wavefront (target rows) read
 // consecutive addresses.
 #include <hip/hip_runtime.h>
 
@@ -187,11 +188,11 @@ __global__ void __launch_bounds__(256) k_near_blocks(NearArgs A) {
       B21 = cmul(cmul(c, ph), T2);
       B22 = cmul(cmul(cmul(c, mieta), ph), K2);
     }
-    long long idx = blk + (long long)col * rows + row;
+    long long idx = 4 * blk + (long long)col * 4 * rows + row;
     A.out[idx] = B11;
-    A.out[A.n_entries + idx] = B12;
-    A.out[2 * A.n_entries + idx] = B21;
-    A.out[3 * A.n_entries + idx] = B22;
+    A.out[idx + rows] = B12;
+    A.out[idx + 2 * rows] = B21;
+    A.out[idx + 3 * rows] = B22;
   }
 }
 
@@ -225,7 +226,7 @@ hipError_t launch_near_blocks(Problem& pb) {
 // for child-parent offsets, nu = -2p..2p, both wavenumbers.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void k_htab(int n_off, const double* __restrict__ off, double k, double k1, cd* tab) {
+__global__ void k_htab(int n_off, int n_tab, const double* __restrict__ off, double k, double k1, cd* tab) {
   constexpr int NT = 4 * P + 1;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 2 * n_off) return;
@@ -237,7 +238,7 @@ __global__ void k_htab(int n_off, const double* __restrict__ off, double k, doub
   cd e1 = mkc(dx / r, dy / r);             // e^{i theta}
   cd Hm1, Hn;
   hankel01(x, Hm1, Hn);                    // H_0, H_1
-  cd* out = tab + (size_t)i * NT + 2 * P;
+  cd* out = tab + ((size_t)ch * n_tab + o) * NT + 2 * P;
   out[0] = Hm1;
   cd en = e1;                              // e^{i n theta}
   cd Hprev = Hm1;
@@ -473,10 +474,9 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 // S-bar and D-bar combined as in the representation D phi - i eta S varphi):
 //   M_n(C) = (i/4) sum_{e in C} sum_g w_g [ dJm_n/dn_y phi_e - i eta Jm_n varphi_e ],
 //   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2.
-// One wavefront per (leaf, channel); lane = element; per-lane partial moments
-// are summed through LDS (row per lane, one column per order).  Orders are
-// walked by |n| with a window of three Jm values, so that only the scaled
-// Bessel sequence stays in registers.
+// One wavefront per (leaf, channel); each lane takes whole elements, walks
+// the orders by |n| with a window of three Jm values and keeps its partial
+// moments in registers; one LDS transpose sums the lanes at the end.
 template <int P>
 __global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
                                             const int* __restrict__ eend, const int* __restrict__ elem_of,
@@ -493,60 +493,53 @@ __global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, cons
   int ch = blockIdx.y;
   double kap = ch ? k1 : k;
   int lane = threadIdx.x;
-  for (int n = 0; n < NP; ++n) red[lane][n] = mkc(0, 0);
   double ox = cx[cell], oy = cy[cell];
   int b = ebeg[cell], e_ = eend[cell];
+  cd acc[NP];
+#pragma unroll
+  for (int n = 0; n < NP; ++n) acc[n] = mkc(0, 0);
   for (int t = b + lane; t < e_; t += 64) {
     int e = elem_of[t];
     int pi = psi_idx[t];
     cd phi = psi[pi], vphi = psi[pi + N];
     double ex = mx[e], ey = my[e], etx = tx[e], ety = ty[e], hh = h[e];
     cd nu = mkc(ety, -etx);
-    cd a_m = cmul(cscale(cconj(nu), 0.5 * kap), phi);      // multiplies Jm_{n-1}
-    cd a_p = cmul(cscale(nu, -0.5 * kap), phi);            // multiplies Jm_{n+1}
-    cd a_0 = cmul(mkc(0.0, -eta), vphi);                   // multiplies Jm_n
+    cd a_0 = cmul(mkc(0.0, -eta), vphi);                  // multiplies Jm_n
+    cd a_m = cmul(cscale(cconj(nu), 0.5 * kap), phi);     // multiplies Jm_{n-1}
+    cd a_p = cmul(cscale(nu, -0.5 * kap), phi);           // multiplies Jm_{n+1}
     for (int g = 0; g < G; ++g) {
-      double s = 0.5 * hh * gl[g], w = 0.5 * hh * gl[G + g];
+      double s = 0.5 * hh * gl[g], w = 0.25 * 0.5 * hh * gl[G + g];
       double vx = kap * (ex + s * etx - ox), vy = kap * (ey + s * ety - oy);
+      cd w0 = cscale(mkc(-a_0.y, a_0.x), w);              // (i/4) w a
+      cd wm = cscale(mkc(-a_m.y, a_m.x), w);
+      cd wp = cscale(mkc(-a_p.y, a_p.x), w);
       double gs[P + 2];
       scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
-      // Jm_m(v) = (conj(v)/2)^m / m! g_m for m >= 0; Jm_{-m} = (-1)^m conj(Jm_m)
-      cd hv = mkc(0.5 * vx, -0.5 * vy);
-      cd wa_m = cscale(mkc(-a_m.y, a_m.x), 0.25 * w);      // (i/4) w a
-      cd wa_p = cscale(mkc(-a_p.y, a_p.x), 0.25 * w);
-      cd wa_0 = cscale(mkc(-a_0.y, a_0.x), 0.25 * w);
-      cd u = mkc(1.0, 0.0);
-      cd J0 = mkc(gs[0], 0.0);                             // Jm_m at m = 0
-      u = cmul(u, hv);
-      cd J1 = cscale(u, gs[1]);                            // Jm_1
-      cd Jprev = cscale(cconj(J1), -1.0);                  // Jm_{-1}
+      cd hv = mkc(0.5 * vx, -0.5 * vy);                   // conj(v)/2
+      cd uu = hv;
+      cd J0 = mkc(gs[0], 0.0);                            // Jm_0
+      cd J1 = cscale(uu, gs[1]);                          // Jm_1
+      cd Jprev = cscale(cconj(J1), -1.0);                 // Jm_{-1}
 #pragma unroll
       for (int m = 0; m <= P; ++m) {
-        // window: Jprev = Jm_{m-1}, J0 = Jm_m, J1 = Jm_{m+1}
-        cd v = cmul(wa_0, J0);
-        v = cfma(wa_m, Jprev, v);
-        v = cfma(wa_p, J1, v);
-        red[lane][P + m] = cadd(red[lane][P + m], v);
+        acc[P + m] = cfma(wp, J1, cfma(wm, Jprev, cfma(w0, J0, acc[P + m])));
         if (m > 0) {
-          // n = -m: Jm_{-m}, Jm_{-m-1}, Jm_{-m+1}
           double sm = (m & 1) ? -1.0 : 1.0;
-          cd jn = cscale(cconj(J0), sm);
-          cd jnm = cscale(cconj(J1), -sm);
-          cd jnp = cscale(cconj(Jprev), -sm);
-          cd vn = cmul(wa_0, jn);
-          vn = cfma(wa_m, jnm, vn);
-          vn = cfma(wa_p, jnp, vn);
-          red[lane][P - m] = cadd(red[lane][P - m], vn);
+          // n = -m: Jm_{-m} = (-1)^m conj(Jm_m), Jm_{-m-1}, Jm_{-m+1}
+          acc[P - m] = cfma(wp, cscale(cconj(Jprev), -sm),
+                            cfma(wm, cscale(cconj(J1), -sm), cfma(w0, cscale(cconj(J0), sm), acc[P - m])));
         }
         if (m < P) {
-          u = cscale(cmul(u, hv), 1.0 / (double)(m + 2));
+          uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
           Jprev = J0;
           J0 = J1;
-          J1 = cscale(u, gs[m + 2]);
+          J1 = cscale(uu, gs[m + 2]);
         }
       }
     }
   }
+#pragma unroll
+  for (int n = 0; n < NP; ++n) red[lane][n] = acc[n];
   __syncthreads();
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
   for (int n = lane; n < NP; n += 64) {
@@ -557,69 +550,62 @@ __global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, cons
 }
 
 // M2M for the non-leaf cells of one level: M_n(C) = sum_l M_l(CS) Jm_{n-l}(kap (O_CS - O_C)).
+// The (at most four) children and their translation tables are staged at once.
 template <int P>
 __global__ void __launch_bounds__(64) k_m2m(int cbeg, const int* __restrict__ first_child,
                                             const int* __restrict__ n_child, const int* __restrict__ joff,
                                             const cd* __restrict__ jtab, int n_joff, cd* mpole) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
-  __shared__ cd sm[NP], sj[NT];
+  __shared__ cd sm[4][NP], sj[4][NT];
   int cell = cbeg + blockIdx.x;
   int ch = blockIdx.y;
   int nc = n_child[cell];
   if (nc == 0) return;
   int fc = first_child[cell];
-  cd acc[(NP + 63) / 64];
-  for (int i = 0; i < (NP + 63) / 64; ++i) acc[i] = mkc(0, 0);
   for (int c = 0; c < nc; ++c) {
     int child = fc + c;
     const cd* src = mpole + ((size_t)child * 2 + ch) * NP;
     const cd* tj = jtab + ((size_t)ch * n_joff + joff[child]) * NT;
-    for (int i = threadIdx.x; i < NP; i += 64) sm[i] = src[i];
-    for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
-    __syncthreads();
-    for (int i = 0; i < (NP + 63) / 64; ++i) {
-      int n = threadIdx.x + 64 * i - P;
-      if (n > P) break;
-      cd s = acc[i];
-      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[n - l + 2 * P], sm[l + P], s);
-      acc[i] = s;
-    }
-    __syncthreads();
+    for (int i = threadIdx.x; i < NP; i += 64) sm[c][i] = src[i];
+    for (int i = threadIdx.x; i < NT; i += 64) sj[c][i] = tj[i];
   }
+  __syncthreads();
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  for (int i = 0; i < (NP + 63) / 64; ++i) {
-    int n = threadIdx.x + 64 * i;
-    if (n < NP) out[n] = acc[i];
+  for (int i = threadIdx.x; i < NP; i += 64) {
+    int n = i - P;
+    cd s = mkc(0, 0);
+    for (int c = 0; c < nc; ++c)
+#pragma unroll 7
+      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[c][n - l + 2 * P], sm[c][l + P], s);
+    out[i] = s;
   }
 }
 
-// M2L over the explicit lists: L_l(D) = sum_{(C,m)} alpha^m sum_n Hp_{n-l}(kap d) M_n(C)
-// (eq. 13 with the index n - l).  Channel 0: exterior lists with images;
-// channel 1: interior lists.  Assigns L (cells without entries get zero).
+// M2L over chunks of the interaction lists (eq. 13 with the index n - l):
+//   part[c]_l = sum_{(C, t, m) in chunk c} alpha^m sum_n T_t[n - l] M_n(C),
+// where T_t is Hp_nu(kap d) of an explicit pair (channel 0: exterior, with
+// image m; channel 1: interior) or, for the roots, the lattice sum
+// S_nu(c_i - c_j) that carries every far image of fibre j (Sec. 3.3).
+// One wavefront per chunk; the partial sums are reduced in a fixed order by
+// k_down, so the result does not depend on scheduling.
 template <int P>
-__global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ ptr_e, const int* __restrict__ src_e,
-                                            const int* __restrict__ off_e, const int* __restrict__ m_e,
-                                            const int* __restrict__ ptr_i, const int* __restrict__ src_i,
-                                            const int* __restrict__ off_i, const cd* __restrict__ htab,
-                                            int n_off, const cd* __restrict__ alpha, int m_min,
-                                            const cd* __restrict__ mpole, cd* __restrict__ local) {
+__global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, const int* __restrict__ e_src,
+                                            const int* __restrict__ e_off, const int* __restrict__ e_m,
+                                            const cd* __restrict__ htab, int n_tab,
+                                            const cd* __restrict__ alpha, int m_min,
+                                            const cd* __restrict__ mpole, cd* __restrict__ part) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
   __shared__ cd sm[NP], sh[NT];
-  int cell = blockIdx.x;
-  int ch = blockIdx.y;
-  const int* ptr = ch ? ptr_i : ptr_e;
-  const int* src = ch ? src_i : src_e;
-  const int* off = ch ? off_i : off_e;
-  int b = ptr[cell], e = ptr[cell + 1];
+  int c = blockIdx.x;
+  int ch = chunks[4 * c + 1], b = chunks[4 * c + 2], e = b + chunks[4 * c + 3];
   cd acc[(NP + 63) / 64];
   for (int i = 0; i < (NP + 63) / 64; ++i) acc[i] = mkc(0, 0);
   for (int q = b; q < e; ++q) {
-    int C = src[q];
-    const cd* ms = mpole + ((size_t)C * 2 + ch) * NP;
-    const cd* th = htab + ((size_t)ch * n_off + off[q]) * NT;
+    const cd* ms = mpole + ((size_t)e_src[q] * 2 + ch) * NP;
+    const cd* th = htab + ((size_t)ch * n_tab + e_off[q]) * NT;
     for (int i = threadIdx.x; i < NP; i += 64) sm[i] = ms[i];
     for (int i = threadIdx.x; i < NT; i += 64) sh[i] = th[i];
-    cd ph = ch ? mkc(1, 0) : alpha[m_e[q] - m_min];
+    cd ph = alpha[e_m[q] - m_min];
     __syncthreads();
     for (int i = 0; i < (NP + 63) / 64; ++i) {
       int l = threadIdx.x + 64 * i - P;
@@ -630,124 +616,90 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ ptr_e, const
     }
     __syncthreads();
   }
-  cd* out = local + ((size_t)cell * 2 + ch) * NP;
+  cd* out = part + (size_t)c * NP;
   for (int i = 0; i < (NP + 63) / 64; ++i) {
     int l = threadIdx.x + 64 * i;
     if (l < NP) out[l] = acc[i];
   }
 }
 
-// Lattice M2L at the roots, split over chunks of LAT_CHUNK source fibres:
-//   part[i][chunk] = sum_{j in chunk} sum_n S_{n-l}(c_i - c_j) M_n(root_j),
-// then reduced in a fixed order and added to L(root_i).
-constexpr int LAT_CHUNK = 4;
-
+// Downward pass for the cells of one level: the local expansion is the sum of
+// the cell's M2L chunks (fixed order) plus, below the roots, the L2L of the
+// parent's final expansion, L_n(D) += sum_l L_l(DP) Jp_{l-n}(kap (O_D - O_DP)).
 template <int P>
-__global__ void __launch_bounds__(64) k_lattice_m2l(int M, const int* __restrict__ root_of_fibre,
-                                                    const int* __restrict__ pair_off,
-                                                    const cd* __restrict__ lat,
-                                                    const cd* __restrict__ mpole, cd* __restrict__ part) {
-  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
-  __shared__ cd sm[NP], sh[NT];
-  int i = blockIdx.x;
-  int j0 = blockIdx.y * LAT_CHUNK, j1 = min(M, j0 + LAT_CHUNK);
-  cd acc[(NP + 63) / 64];
-  for (int u = 0; u < (NP + 63) / 64; ++u) acc[u] = mkc(0, 0);
-  for (int j = j0; j < j1; ++j) {
-    int C = root_of_fibre[j];
-    const cd* ms = mpole + ((size_t)C * 2) * NP;
-    const cd* th = lat + (size_t)pair_off[(size_t)i * M + j] * NT;
-    for (int t = threadIdx.x; t < NP; t += 64) sm[t] = ms[t];
-    for (int t = threadIdx.x; t < NT; t += 64) sh[t] = th[t];
-    __syncthreads();
-    for (int u = 0; u < (NP + 63) / 64; ++u) {
-      int l = threadIdx.x + 64 * u - P;
-      if (l > P) break;
-      cd s = acc[u];
-      for (int n = -P; n <= P; ++n) s = cfma(sh[n - l + 2 * P], sm[n + P], s);
-      acc[u] = s;
-    }
-    __syncthreads();
-  }
-  cd* out = part + ((size_t)i * gridDim.y + blockIdx.y) * NP;
-  for (int u = 0; u < (NP + 63) / 64; ++u) {
-    int l = threadIdx.x + 64 * u;
-    if (l < NP) out[l] = acc[u];
-  }
-}
-
-__global__ void k_lattice_reduce(int NP, int nchunk, const int* __restrict__ root_of_fibre,
-                                 const cd* __restrict__ part, cd* local) {
-  int i = blockIdx.x;
-  cd* out = local + (size_t)root_of_fibre[i] * 2 * NP;
-  for (int l = threadIdx.x; l < NP; l += blockDim.x) {
-    cd s = out[l];
-    for (int c = 0; c < nchunk; ++c) s = cadd(s, part[((size_t)i * nchunk + c) * NP + l]);
-    out[l] = s;
-  }
-}
-
-// L2L for the cells of one level: L_n(D) += sum_l L_l(DP) Jp_{l-n}(kap (O_D - O_DP)).
-template <int P>
-__global__ void __launch_bounds__(64) k_l2l(int cbeg, const int* __restrict__ parent,
-                                            const int* __restrict__ joff, const cd* __restrict__ jtab,
-                                            int n_joff, cd* local) {
+__global__ void __launch_bounds__(64) k_down(int cbeg, int nc, int with_parent,
+                                             const int* __restrict__ cc_ptr, const cd* __restrict__ part,
+                                             const int* __restrict__ parent, const int* __restrict__ joff,
+                                             const cd* __restrict__ jtab, int n_joff, cd* local) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
   __shared__ cd sl[NP], sj[NT];
   int cell = cbeg + blockIdx.x;
   int ch = blockIdx.y;
-  int par = parent[cell];
-  const cd* lp = local + ((size_t)par * 2 + ch) * NP;
-  const cd* tj = jtab + ((size_t)ch * n_joff + joff[cell]) * NT;
-  for (int i = threadIdx.x; i < NP; i += 64) sl[i] = lp[i];
-  for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
-  __syncthreads();
+  int c0 = cc_ptr[ch * nc + cell], c1 = cc_ptr[ch * nc + cell + 1];
+  if (with_parent) {
+    int par = parent[cell];
+    const cd* lp = local + ((size_t)par * 2 + ch) * NP;
+    const cd* tj = jtab + ((size_t)ch * n_joff + joff[cell]) * NT;
+    for (int i = threadIdx.x; i < NP; i += 64) sl[i] = lp[i];
+    for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
+    __syncthreads();
+  }
   cd* out = local + ((size_t)cell * 2 + ch) * NP;
   for (int i = threadIdx.x; i < NP; i += 64) {
-    int n = i - P;
-    cd s = out[i];
-    for (int l = -P; l <= P; ++l) s = cfma(sl[l + P], sj[l - n + 2 * P], s);
+    cd s = mkc(0, 0);
+    for (int c = c0; c < c1; ++c) s = cadd(s, part[(size_t)c * NP + i]);
+    if (with_parent) {
+      int n = i - P;
+      for (int l = -P; l <= P; ++l) s = cfma(sl[l + P], sj[l - n + 2 * P], s);
+    }
     out[i] = s;
   }
 }
 
 // P2P with the stored near blocks plus the identity of (I - A):
 //   y1 = phi + sum_b (B11 phi_b + B12 varphi_b),  y2 = varphi + sum_b (B21 phi_b + B22 varphi_b).
-// One workgroup (4 wavefronts) per target leaf, lane = target row; the
-// wavefronts take the source columns of the leaf's near blocks in turn and
-// meet in LDS.  Pure streaming of the blocks: the kernel is HBM-bound.
+// One workgroup (4 wavefronts) per target leaf, lane = target row.  The
+// densities of the leaf's source columns are first gathered into LDS (in
+// segments), then the wavefronts take the columns in turn and stream the
+// leaf's contiguous block region; partial rows meet in LDS.  Pure streaming:
+// the kernel is HBM-bound.
 constexpr int P2P_WAVES = 4;
+constexpr int P2P_SEG = 512;
 
 __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
     const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
-    const int* __restrict__ near_src, const long long* __restrict__ near_blk,
-    const cd* __restrict__ blocks, long long n_entries, const cd* __restrict__ psi, cd* __restrict__ y) {
+    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
+    const int* __restrict__ col_psi, const cd* __restrict__ blocks, const cd* __restrict__ psi,
+    cd* __restrict__ y) {
+  __shared__ cd sp[P2P_SEG][2];
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   int li = blockIdx.x;
   int D = leaves[li];
   int db = ebeg[D], rows = eend[D] - db;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   cd a1 = mkc(0, 0), a2 = mkc(0, 0);
-  const cd* B11 = blocks;
-  const cd* B12 = blocks + n_entries;
-  const cd* B21 = blocks + 2 * n_entries;
-  const cd* B22 = blocks + 3 * n_entries;
-  int qb = near_ptr[li], qe = near_ptr[li + 1];
+  int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+  const cd* bl = blocks + 4 * near_blk[near_ptr[li]] + lane;
+  const long long cstride = 4LL * rows;
   bool act = lane < rows;
-  for (int q = qb; q < qe; ++q) {
-    int C = near_src[q];
-    int cb = ebeg[C], cols = eend[C] - cb;
-    long long base = near_blk[q] + lane;
-    int c = w;
-    for (; c + P2P_WAVES < cols; c += 2 * P2P_WAVES) {
-      int pa = psi_idx[cb + c], pb_ = psi_idx[cb + c + P2P_WAVES];
-      cd ph0 = psi[pa], vp0 = psi[pa + N], ph1 = psi[pb_], vp1 = psi[pb_ + N];
+  for (int seg = 0; seg < ncol; seg += P2P_SEG) {
+    int nseg = min(P2P_SEG, ncol - seg);
+    for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
+      int pi = col_psi[k0 + seg + i];
+      sp[i][0] = psi[pi];
+      sp[i][1] = psi[pi + N];
+    }
+    __syncthreads();
+    int k = w;
+    for (; k + P2P_WAVES < nseg; k += 2 * P2P_WAVES) {
       if (act) {
-        long long i0 = base + (long long)c * rows;
-        long long i1 = i0 + (long long)P2P_WAVES * rows;
-        cd b110 = B11[i0], b120 = B12[i0], b210 = B21[i0], b220 = B22[i0];
-        cd b111 = B11[i1], b121 = B12[i1], b211 = B21[i1], b221 = B22[i1];
+        const cd* b0 = bl + (long long)(seg + k) * cstride;
+        const cd* b1 = b0 + P2P_WAVES * cstride;
+        cd b110 = b0[0], b120 = b0[rows], b210 = b0[2 * rows], b220 = b0[3 * rows];
+        cd b111 = b1[0], b121 = b1[rows], b211 = b1[2 * rows], b221 = b1[3 * rows];
+        cd ph0 = sp[k][0], vp0 = sp[k][1];
+        cd ph1 = sp[k + P2P_WAVES][0], vp1 = sp[k + P2P_WAVES][1];
         a1 = cfma(b110, ph0, a1);
         a1 = cfma(b120, vp0, a1);
         a2 = cfma(b210, ph0, a2);
@@ -758,17 +710,17 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p(
         a2 = cfma(b221, vp1, a2);
       }
     }
-    for (; c < cols; c += P2P_WAVES) {
-      int pa = psi_idx[cb + c];
-      cd ph0 = psi[pa], vp0 = psi[pa + N];
+    for (; k < nseg; k += P2P_WAVES) {
       if (act) {
-        long long i0 = base + (long long)c * rows;
-        a1 = cfma(B11[i0], ph0, a1);
-        a1 = cfma(B12[i0], vp0, a1);
-        a2 = cfma(B21[i0], ph0, a2);
-        a2 = cfma(B22[i0], vp0, a2);
+        const cd* b0 = bl + (long long)(seg + k) * cstride;
+        cd ph0 = sp[k][0], vp0 = sp[k][1];
+        a1 = cfma(b0[0], ph0, a1);
+        a1 = cfma(b0[rows], vp0, a1);
+        a2 = cfma(b0[2 * rows], ph0, a2);
+        a2 = cfma(b0[3 * rows], vp0, a2);
       }
     }
+    __syncthreads();
   }
   r1[w][lane] = a1;
   r2[w][lane] = a2;
@@ -862,7 +814,7 @@ static hipError_t tables_impl(Problem& pb) {
   int n_off = (int)hp.off_xy.size() / 2;
   int n_joff = (int)hp.joff_xy.size() / 2;
   if (n_off > 0)
-    hipLaunchKernelGGL(k_htab<P>, dim3((2 * n_off + 63) / 64), dim3(64), 0, pb.stream, n_off,
+    hipLaunchKernelGGL(k_htab<P>, dim3((2 * n_off + 63) / 64), dim3(64), 0, pb.stream, n_off, pb.n_tab,
                        pb.d_off_xy, pb.k, pb.k1, pb.d_htab);
   if (n_joff > 0)
     hipLaunchKernelGGL(k_jtab<P>, dim3((2 * n_joff + 63) / 64), dim3(64), 0, pb.stream, n_joff,
@@ -870,15 +822,13 @@ static hipError_t tables_impl(Problem& pb) {
   return hipGetLastError();
 }
 
-// The FMM chain: P2M, M2M (bottom-up), M2L, lattice M2L, L2L (top-down).
+// The FMM chain: P2M, M2M (bottom-up), M2L with the lattice sums, downward pass.
 template <int P>
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only) {
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
-  int n_off = (int)hp.off_xy.size() / 2;
   int n_joff = (int)hp.joff_xy.size() / 2;
-  constexpr int NP = 2 * P + 1;
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(64), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
                      pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
@@ -892,23 +842,17 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
-  hipLaunchKernelGGL(k_m2l<P>, dim3(nc, 2), dim3(64), 0, s, pb.d_m2l_ptr, pb.d_m2l_src, pb.d_m2l_off,
-                     pb.d_m2l_m, pb.d_m2li_ptr, pb.d_m2li_src, pb.d_m2li_off, pb.d_htab, n_off, pb.d_alpha,
-                     hp.m_min, pb.d_mpole, pb.d_local);
+  if (pb.n_chunks > 0)
+    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_chunks), dim3(64), 0, s, pb.d_chunks, pb.d_e_src, pb.d_e_off,
+                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_part);
   if (ev) (void)hipEventRecord(ev[3], s);
-  int nchunk = (pb.M + LAT_CHUNK - 1) / LAT_CHUNK;
-  hipLaunchKernelGGL(k_lattice_m2l<P>, dim3(pb.M, nchunk), dim3(64), 0, s, pb.M, pb.d_root_of_fibre,
-                     pb.d_root_pair_off, pb.d_lat, pb.d_mpole, pb.d_latpart);
-  hipLaunchKernelGGL(k_lattice_reduce, dim3(pb.M), dim3(64), 0, s, NP, nchunk, pb.d_root_of_fibre,
-                     pb.d_latpart, pb.d_local);
-  if (ev) (void)hipEventRecord(ev[4], s);
-  for (int lv = 1; lv <= hp.depth; ++lv) {
+  for (int lv = 0; lv <= hp.depth; ++lv) {
     int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
     if (ce > cb)
-      hipLaunchKernelGGL(k_l2l<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, pb.d_parent, pb.d_cell_joff,
-                         pb.d_jtab, n_joff, pb.d_local);
+      hipLaunchKernelGGL(k_down<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, nc, lv > 0 ? 1 : 0, pb.d_cc_ptr,
+                         pb.d_part, pb.d_parent, pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_local);
   }
-  if (ev) (void)hipEventRecord(ev[5], s);
+  if (ev) (void)hipEventRecord(ev[4], s);
 }
 
 template <int P>
@@ -933,14 +877,14 @@ static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* 
   fmm_chain<P>(pb, d_psi, fs, ev, false);
   if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
   hipLaunchKernelGGL(k_p2p, dim3(n_leaves), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_src, pb.d_near_blk,
-                     pb.d_near, hp.n_near_entries, d_psi, d_y);
-  if (ev) (void)hipEventRecord(ev[6], pb.stream);
+                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
+                     pb.d_col_psi, pb.d_near, d_psi, d_y);
+  if (ev) (void)hipEventRecord(ev[5], pb.stream);
   if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
   hipLaunchKernelGGL(k_l2p<P>, dim3(n_leaves), dim3(128), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
                      pb.d_eend, pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx,
                      pb.d_ty, pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_local, d_y);
-  if (ev) (void)hipEventRecord(ev[7], pb.stream);
+  if (ev) (void)hipEventRecord(ev[6], pb.stream);
   return hipGetLastError();
 }
 

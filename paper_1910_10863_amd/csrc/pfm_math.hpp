@@ -3,8 +3,9 @@
 // Special functions are written from the series and expansions of the DLMF:
 //   * J0, J1 by Miller's backward recurrence normalised by
 //     J0 + 2 sum_k J_2k = 1 (DLMF 10.12.4 at theta = 0, 3.6),
-//   * Y0, Y1 from the same J values by the Neumann series (DLMF 10.23.E?-type
-//     expansions of Y0 in J_2k; Y1 = -Y0'),
+//   * Y0 from the same J values by Neumann's series
+//     Y0 = (2/pi)(ln(x/2) + gamma) J0 - (4/pi) sum_k (-1)^k J_2k / k
+//     (Abramowitz & Stegun 9.1.88), and Y1 = -Y0' term by term,
 //   * the Hankel asymptotic expansion for large arguments (DLMF 10.17.3),
 //   * scaled J_n sequences g_n(x) = n! (2/x)^n J_n(x) by their power series
 //     (DLMF 10.2.2) at the top order and the scaled backward recurrence
@@ -155,27 +156,37 @@ __host__ __device__ inline void hankel01(double x, cd& H0, cd& H1) {
 }
 
 // Scaled Bessel sequence g_n(x) = n! (2/x)^n J_n(x), n = 0..NT (x >= 0), written to g[].
-// q = x^2/4.  Power series at NT and NT-1, then the scaled backward recurrence.
+// q = x^2/4.  Power series g_n = sum_k (-q)^k n! / (k! (n+k)!) at NT and NT-1,
+// then the scaled backward recurrence g_{n-1} = g_n - q g_{n+1} / (n (n+1)).
+// All divisors are compile-time constants, so no division is executed; for
+// q <= 10 the series is cut at 18 terms (remainder below 1e-17 for NT >= 9),
+// larger arguments sum until the terms are negligible.
 template <int NT>
-__host__ __device__ __forceinline__ void scaled_j(double q, double (&g)[NT + 1]) {
-  // g_n = sum_k (-q)^k n! / (k! (n+k)!)
-  double gt[2];
+__host__ __device__ __forceinline__ double scaled_j_series(double q) {
+  double term = 1.0, sum = 1.0;
+  if (q <= 10.0) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    int n = NT - s;
-    double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 200; ++k) {
-      term *= -q / ((double)k * (double)(n + k));
+    for (int k = 1; k <= 18; ++k) {
+      term *= -q * (1.0 / ((double)k * (double)(NT + k)));
+      sum += term;
+    }
+  } else {
+    for (int k = 1; k < 400; ++k) {
+      term *= -q / ((double)k * (double)(NT + k));
       sum += term;
       if (fabs(term) < 1e-17 * fabs(sum)) break;
     }
-    gt[s] = sum;
   }
-  g[NT] = gt[0];
-  g[NT - 1] = gt[1];
+  return sum;
+}
+
+template <int NT>
+__host__ __device__ __forceinline__ void scaled_j(double q, double (&g)[NT + 1]) {
+  g[NT] = scaled_j_series<NT>(q);
+  g[NT - 1] = scaled_j_series<NT - 1>(q);
 #pragma unroll
   for (int n = NT - 1; n >= 1; --n) {
-    g[n - 1] = g[n] - q * g[n + 1] / ((double)n * (double)(n + 1));
+    g[n - 1] = g[n] - q * g[n + 1] * (1.0 / ((double)n * (double)(n + 1)));
   }
 }
 

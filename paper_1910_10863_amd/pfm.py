@@ -225,11 +225,11 @@ class Problem:
 
     def matvec_timed(self, psi, reps: int = 10):
         y = self.empty()
-        stage = np.zeros(7)
+        stage = np.zeros(6)
         tot = ctypes.c_double()
         self._check(self._L.pfm_matvec_timed(self._h, _ptr(psi), _ptr(y), reps, _dptr(stage),
                                              ctypes.byref(tot)))
-        names = ["p2m", "m2m", "m2l", "lattice_m2l", "l2l", "p2p", "l2p"]
+        names = ["p2m", "m2m", "m2l", "down", "p2p", "l2p"]
         return dict(zip(names, stage.tolist())), tot.value, y
 
     # ---- test hooks ----

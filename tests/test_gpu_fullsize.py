@@ -93,7 +93,7 @@ def test_edge_cases_dense(pfm, case):
     from oracle import system as sy
     if case == "n8_leaf1":
         wl = W.small_square(1, 1, 8, 0.3, 1.5, 0.4, p=8, leaf_max=1)
-        kw = dict(p=16, leaf_max=1)
+        kw = dict(p=32, leaf_max=1, mac=0.4)
     elif case == "ragged_hex":
         wl = W.small_square(3, 2, 100, 0.3, 2.5, -0.3, lattice=W.HEXAGON,
                             radii=np.array([0.3, 0.25, 0.28, 0.31, 0.22, 0.3]))
