@@ -25,6 +25,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "k_p2p_square_8x8_N512.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1910_10863_amd", "csrc", "pfm_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_p2p launch from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(PROFILE).read()
+        vals = dict(line.split(": ", 1) for line in txt.splitlines()
+                    if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if vals.get("kernel_source_sha256", "").strip() != sha:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def p2p_kernel_bytes(st):
@@ -172,7 +190,7 @@ def main():
         "stages_ms": stages,
         "roofline": {"bound": "hbm", "kernel": "k_p2p (near field + identity rows)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": lb, "launch_ms": leaf_ms},
         "sweep": sweep,
         "cpu_baseline": cpu,

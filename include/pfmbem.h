@@ -160,8 +160,8 @@ pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
 /* Apply the operator reps times with every stage in order on the bound
  * stream and return the mean duration (milliseconds, HIP events) of each
  * stage: stage_ms[6] = [P2M, M2M, M2L including the lattice sums, downward
- * pass (M2L reduction and L2L), P2P, L2P], and of the whole apply in
- * *total_ms.  (pfm_matvec overlaps the FMM chain with
+ * pass with L2P, P2P, join of near and far parts], and of the whole apply
+ * in *total_ms.  (pfm_matvec overlaps the FMM chain with
  * P2P on a second stream; this call does not.) */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -68,6 +69,8 @@ void free_all(Problem& pb) {
   dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx);
   dfree(pb.d_e_src); dfree(pb.d_e_off); dfree(pb.d_e_m); dfree(pb.d_chunks); dfree(pb.d_cc_ptr);
   dfree(pb.d_part);
+  dfree(pb.d_up_cells); dfree(pb.d_up_ptr); dfree(pb.d_up_src); dfree(pb.d_up_off);
+  dfree(pb.d_anc_ptr); dfree(pb.d_anc); dfree(pb.d_anc_off); dfree(pb.d_far);
   dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
   dfree(pb.d_first_child); dfree(pb.d_n_child); dfree(pb.d_cell_joff); dfree(pb.d_parent);
   dfree(pb.d_leaves); dfree(pb.d_root_of_fibre); dfree(pb.d_fibre_of_cell);
@@ -167,6 +170,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.N = geo->n_elem;
   pb.E = pb.M * pb.N;
   pb.opt = *opt;
+
   pb.rho_f = mat->rho_fiber;
   pb.c_f = mat->c_fiber;
   pb.rho_m = mat->rho_matrix;
@@ -195,6 +199,14 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.L = pb.lattice == PFM_SQUARE ? pb.ML * pb.a : pb.ML * s3 * pb.a;
   pb.H = pb.MH * pb.a;
 
+  {
+    // P2P runs as a persistent grid of two workgroups per compute unit, which
+    // saturates HBM and leaves room on every CU for the concurrent FMM chain
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      pb.p2p_grid = 2 * ncu;
+  }
   // discretisation on the device
   int E = pb.E;
 #define CK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) { free_all(pb); \
@@ -246,7 +258,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(upload(&pb.d_ebeg, eb)); CK(upload(&pb.d_eend, ee));
   CK(upload(&pb.d_first_child, fc)); CK(upload(&pb.d_n_child, nch));
   CK(upload(&pb.d_parent, par)); CK(upload(&pb.d_fibre_of_cell, fib));
-  CK(upload(&pb.d_cell_joff, hp.cell_joff));
+
   CK(upload(&pb.d_leaves, hp.leaves));
   CK(upload(&pb.d_root_of_fibre, hp.root_of_fibre));
   CK(upload(&pb.d_m2l_ptr, hp.m2l_ptr)); CK(upload(&pb.d_m2l_src, hp.m2l_src));
@@ -314,7 +326,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   {
     // M2L work list: per (channel, cell) the entries (source cell, table row, image),
     // cut into chunks of at most M2L_CHUNK entries
-    const int M2L_CHUNK = 4;
+    const int M2L_CHUNK = 2;
     std::vector<int> esrc, eoff, em, chunks, ccptr(2 * (size_t)nc + 1, 0);
     std::vector<int> fibre_of_root(nc, -1);
     for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;
@@ -349,6 +361,13 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
     CK(upload(&pb.d_chunks, chunks)); CK(upload(&pb.d_cc_ptr, ccptr));
     CK(hipMalloc((void**)&pb.d_part, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd)));
+  }
+  {
+    CK(upload(&pb.d_up_cells, hp.up_cells)); CK(upload(&pb.d_up_ptr, hp.up_ptr));
+    CK(upload(&pb.d_up_src, hp.up_src)); CK(upload(&pb.d_up_off, hp.up_off));
+    pb.n_up = (int)hp.up_cells.size();
+    CK(upload(&pb.d_anc_ptr, hp.anc_ptr)); CK(upload(&pb.d_anc, hp.anc)); CK(upload(&pb.d_anc_off, hp.anc_off));
+    CK(hipMalloc((void**)&pb.d_far, 2 * (size_t)E * sizeof(cd)));
   }
   CK(hipMalloc((void**)&pb.d_alpha, (size_t)(hp.m_max - hp.m_min + 1) * sizeof(cd)));
   // GMRES workspace

@@ -37,8 +37,9 @@ struct HostPlan {
   std::vector<int> m2l_ptr, m2l_src, m2l_off, m2l_m;
   std::vector<int> m2li_ptr, m2li_src, m2li_off;
   std::vector<double> off_xy;           // unique M2L translation vectors [n_off][2]
-  std::vector<double> joff_xy;          // unique child-parent offsets [n_joff][2]
-  std::vector<int> cell_joff;           // per cell: index into joff_xy (-1 for roots)
+  std::vector<double> joff_xy;          // unique leaf-to-ancestor offsets O_L - O_A [n_joff][2]
+  std::vector<int> up_cells, up_ptr, up_src, up_off;   // per non-leaf cell: leaves below it
+  std::vector<int> anc_ptr, anc, anc_off;              // per leaf: its ancestors
   // P2P near lists, CSR by target leaf
   std::vector<int> near_ptr, near_src, near_m, near_tgt;
   std::vector<long long> near_blk;      // block offset (entries) of each near pair
@@ -103,6 +104,13 @@ struct Problem {
   int *d_cc_ptr = nullptr;              // [2*n_cells+1]: chunks of (channel, cell)
   cd *d_part = nullptr;                 // [n_chunks][2p+1] partial local expansions
   int n_chunks = 0;
+  int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per leaf)
+  // upward: per non-leaf cell the leaves below it; downward: per leaf its
+  // ancestors; both with an index into the J translation table
+  int *d_up_cells = nullptr, *d_up_ptr = nullptr, *d_up_src = nullptr, *d_up_off = nullptr;
+  int n_up = 0;
+  int *d_anc_ptr = nullptr, *d_anc = nullptr, *d_anc_off = nullptr;
+  cd *d_far = nullptr;                  // far part of the rows, Psi order
   int n_tab = 0;                        // rows per channel of d_htab: M2L offsets, then lattice offsets
   cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights

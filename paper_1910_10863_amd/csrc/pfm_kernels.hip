@@ -12,6 +12,7 @@
 // consecutive addresses.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 
 #include "pfm_kernels.hpp"
@@ -474,111 +475,163 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 // S-bar and D-bar combined as in the representation D phi - i eta S varphi):
 //   M_n(C) = (i/4) sum_{e in C} sum_g w_g [ dJm_n/dn_y phi_e - i eta Jm_n varphi_e ],
 //   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2.
-// One wavefront per (leaf, channel); each lane takes whole elements, walks
-// the orders by |n| with a window of three Jm values and keeps its partial
-// moments in registers; one LDS transpose sums the lanes at the end.
-template <int P>
-__global__ void __launch_bounds__(64) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
-                                            const int* __restrict__ eend, const int* __restrict__ elem_of,
-                                            const int* __restrict__ psi_idx,
-                                            const double* __restrict__ cx, const double* __restrict__ cy,
-                                            const double* __restrict__ mx, const double* __restrict__ my,
-                                            const double* __restrict__ tx, const double* __restrict__ ty,
-                                            const double* __restrict__ h, const double* __restrict__ gl,
-                                            int G, int N, double k, double k1, double eta,
-                                            const cd* __restrict__ psi, cd* __restrict__ mpole) {
-  constexpr int NP = 2 * P + 1;
-  __shared__ cd red[64][NP];
-  int cell = leaves[blockIdx.x];
-  int ch = blockIdx.y;
-  double kap = ch ? k1 : k;
-  int lane = threadIdx.x;
-  double ox = cx[cell], oy = cy[cell];
-  int b = ebeg[cell], e_ = eend[cell];
-  cd acc[NP];
+// Two wavefronts per (leaf, channel): both walk every Gauss point of the leaf
+// (one point per lane at a time) through the orders |n| = 0..p with a window
+// of three Jm values; wavefront W accumulates the orders M_LO(W) <= |n| <= M_HI(W)
+// in registers.  One LDS transpose per wavefront sums the lanes.
+template <int P, int W>
+struct P2MHalf {
+  static constexpr int HALF = P / 2;
+  static constexpr int LO = W == 0 ? 0 : HALF + 1;
+  static constexpr int HI = W == 0 ? HALF : P;
+  // slots: orders +m at [m - LO], orders -m (m >= max(LO,1)) after them
+  static constexpr int NPOS = HI - LO + 1;
+  static constexpr int NNEG = HI - (LO > 0 ? LO : 1) + 1;
+  static constexpr int NS = NPOS + NNEG;
+};
+
+template <int P, int W, int NA>
+__device__ __forceinline__ void p2m_half(cd (&red)[2][64][NA], int lane, int b, int npts, int G, int N,
+                                         double kap, double eta, double ox, double oy,
+                                         const int* __restrict__ elem_of, const int* __restrict__ psi_idx,
+                                         const double* __restrict__ mx, const double* __restrict__ my,
+                                         const double* __restrict__ tx, const double* __restrict__ ty,
+                                         const double* __restrict__ h, const double* __restrict__ gl,
+                                         const cd* __restrict__ psi) {
+  using H = P2MHalf<P, W>;
+  cd acc[H::NS];
 #pragma unroll
-  for (int n = 0; n < NP; ++n) acc[n] = mkc(0, 0);
-  for (int t = b + lane; t < e_; t += 64) {
+  for (int j = 0; j < H::NS; ++j) acc[j] = mkc(0, 0);
+  for (int pt = lane; pt < npts; pt += 64) {
+    int q = pt / G;
+    int g = pt - q * G;
+    int t = b + q;
     int e = elem_of[t];
     int pi = psi_idx[t];
     cd phi = psi[pi], vphi = psi[pi + N];
-    double ex = mx[e], ey = my[e], etx = tx[e], ety = ty[e], hh = h[e];
-    cd nu = mkc(ety, -etx);
-    cd a_0 = cmul(mkc(0.0, -eta), vphi);                  // multiplies Jm_n
-    cd a_m = cmul(cscale(cconj(nu), 0.5 * kap), phi);     // multiplies Jm_{n-1}
-    cd a_p = cmul(cscale(nu, -0.5 * kap), phi);           // multiplies Jm_{n+1}
-    for (int g = 0; g < G; ++g) {
-      double s = 0.5 * hh * gl[g], w = 0.25 * 0.5 * hh * gl[G + g];
-      double vx = kap * (ex + s * etx - ox), vy = kap * (ey + s * ety - oy);
-      cd w0 = cscale(mkc(-a_0.y, a_0.x), w);              // (i/4) w a
-      cd wm = cscale(mkc(-a_m.y, a_m.x), w);
-      cd wp = cscale(mkc(-a_p.y, a_p.x), w);
-      double gs[P + 2];
-      scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
-      cd hv = mkc(0.5 * vx, -0.5 * vy);                   // conj(v)/2
-      cd uu = hv;
-      cd J0 = mkc(gs[0], 0.0);                            // Jm_0
-      cd J1 = cscale(uu, gs[1]);                          // Jm_1
-      cd Jprev = cscale(cconj(J1), -1.0);                 // Jm_{-1}
+    double etx = tx[e], ety = ty[e], hh = h[e];
+    double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g];       // (1/4) of the weight
+    double vx = kap * (mx[e] + s * etx - ox), vy = kap * (my[e] + s * ety - oy);
+    // (i/4) w [ -i eta varphi | (kap/2) conj(nu) phi | -(kap/2) nu phi ], nu = (ty, -tx)
+    cd w0 = cscale(vphi, eta * w);
+    cd cm = cmul(mkc(ety, etx), phi);
+    cd cp = cmul(mkc(ety, -etx), phi);
+    cd wm = cscale(mkc(-cm.y, cm.x), 0.5 * kap * w);
+    cd wp = cscale(mkc(cp.y, -cp.x), 0.5 * kap * w);
+    double gs[H::HI + 2];
+    scaled_j<H::HI + 1>(0.25 * (vx * vx + vy * vy), gs);
+    cd hv = mkc(0.5 * vx, -0.5 * vy);                              // conj(v)/2
+    cd uu = hv;
+    cd J0 = mkc(gs[0], 0.0);                                       // Jm_0
+    cd J1 = cscale(uu, gs[1]);                                     // Jm_1
+    cd Jprev = cscale(cconj(J1), -1.0);                            // Jm_{-1}
 #pragma unroll
-      for (int m = 0; m <= P; ++m) {
-        acc[P + m] = cfma(wp, J1, cfma(wm, Jprev, cfma(w0, J0, acc[P + m])));
+    for (int m = 0; m <= H::HI; ++m) {
+      if (m >= H::LO) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        int jp = m - H::LO;
+        acc[jp] = cfma(wp, J1, cfma(wm, Jprev, cfma(w0, J0, acc[jp])));
         if (m > 0) {
+          int jn = H::NPOS + m - (H::LO > 0 ? H::LO : 1);
           double sm = (m & 1) ? -1.0 : 1.0;
           // n = -m: Jm_{-m} = (-1)^m conj(Jm_m), Jm_{-m-1}, Jm_{-m+1}
-          acc[P - m] = cfma(wp, cscale(cconj(Jprev), -sm),
-                            cfma(wm, cscale(cconj(J1), -sm), cfma(w0, cscale(cconj(J0), sm), acc[P - m])));
+          acc[jn] = cfma(wp, cscale(cconj(Jprev), -sm),
+                         cfma(wm, cscale(cconj(J1), -sm), cfma(w0, cscale(cconj(J0), sm), acc[jn])));
         }
-        if (m < P) {
-          uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
-          Jprev = J0;
-          J0 = J1;
-          J1 = cscale(uu, gs[m + 2]);
-        }
+      }
+      if (m < H::HI) {
+        uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
+        Jprev = J0;
+        J0 = J1;
+        J1 = cscale(uu, gs[m + 2]);
       }
     }
   }
 #pragma unroll
-  for (int n = 0; n < NP; ++n) red[lane][n] = acc[n];
+  for (int j = 0; j < H::NS; ++j) red[W][lane][j] = acc[j];
+}
+
+template <int P>
+__global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
+                                             const int* __restrict__ eend, const int* __restrict__ elem_of,
+                                             const int* __restrict__ psi_idx,
+                                             const double* __restrict__ cx, const double* __restrict__ cy,
+                                             const double* __restrict__ mx, const double* __restrict__ my,
+                                             const double* __restrict__ tx, const double* __restrict__ ty,
+                                             const double* __restrict__ h, const double* __restrict__ gl,
+                                             int G, int N, double k, double k1, double eta,
+                                             const cd* __restrict__ psi, cd* __restrict__ mpole) {
+  constexpr int NP = 2 * P + 1;
+  constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
+  __shared__ cd red[2][64][NA];
+  int cell = leaves[blockIdx.x];
+  int ch = blockIdx.y;
+  double kap = ch ? k1 : k;
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double ox = cx[cell], oy = cy[cell];
+  int b = ebeg[cell];
+  int npts = (eend[cell] - b) * G;
+  if (wv == 0)
+    p2m_half<P, 0, NA>(red, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
+  else
+    p2m_half<P, 1, NA>(red, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
   __syncthreads();
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  for (int n = lane; n < NP; n += 64) {
-    cd s = mkc(0, 0);
-    for (int r = 0; r < 64; ++r) s = cadd(s, red[r][n]);
-    out[n] = s;
+  // slot -> order, per wavefront
+  int lo = wv == 0 ? 0 : P / 2 + 1, hi = wv == 0 ? P / 2 : P;
+  int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
+  for (int j = lane; j < npos + nneg; j += 64) {
+    cd sres = mkc(0, 0);
+    for (int r = 0; r < 64; ++r) sres = cadd(sres, red[wv][r][j]);
+    int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
+    out[n + P] = sres;
   }
 }
 
-// M2M for the non-leaf cells of one level: M_n(C) = sum_l M_l(CS) Jm_{n-l}(kap (O_CS - O_C)).
-// The (at most four) children and their translation tables are staged at once.
+// M2M, directly from the leaves: every non-leaf cell C gathers the moments of
+// the leaves below it, M_n(C) = sum_L sum_l M_l(L) Jm_{n-l}(kap (O_L - O_C))
+// (Graf's theorem for J, eq. 10, as in the M2M translation of Sec. 3.2,
+// applied across several levels at once), so the whole upward pass above
+// the leaves is a single launch.  One workgroup of four wavefronts per
+// (non-leaf cell, channel); the wavefronts split the leaves and their
+// partial sums meet in LDS in a fixed order.
 template <int P>
-__global__ void __launch_bounds__(64) k_m2m(int cbeg, const int* __restrict__ first_child,
-                                            const int* __restrict__ n_child, const int* __restrict__ joff,
-                                            const cd* __restrict__ jtab, int n_joff, cd* mpole) {
-  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+__global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, const int* __restrict__ ptr,
+                                             const int* __restrict__ src, const int* __restrict__ off,
+                                             const cd* __restrict__ jtab, int n_joff, cd* mpole) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
   __shared__ cd sm[4][NP], sj[4][NT];
-  int cell = cbeg + blockIdx.x;
-  int ch = blockIdx.y;
-  int nc = n_child[cell];
-  if (nc == 0) return;
-  int fc = first_child[cell];
-  for (int c = 0; c < nc; ++c) {
-    int child = fc + c;
-    const cd* src = mpole + ((size_t)child * 2 + ch) * NP;
-    const cd* tj = jtab + ((size_t)ch * n_joff + joff[child]) * NT;
-    for (int i = threadIdx.x; i < NP; i += 64) sm[c][i] = src[i];
-    for (int i = threadIdx.x; i < NT; i += 64) sj[c][i] = tj[i];
+  __shared__ cd sr[4][NP];
+  int ci = blockIdx.x, ch = blockIdx.y;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int cell = cells[ci];
+  cd acc[NU];
+  for (int i = 0; i < NU; ++i) acc[i] = mkc(0, 0);
+  for (int q = ptr[ci] + w; q < ptr[ci + 1]; q += 4) {
+    const cd* ms = mpole + ((size_t)src[q] * 2 + ch) * NP;
+    const cd* tj = jtab + ((size_t)ch * n_joff + off[q]) * NT;
+    for (int i = lane; i < NP; i += 64) sm[w][i] = ms[i];
+    for (int i = lane; i < NT; i += 64) sj[w][i] = tj[i];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    for (int i = 0; i < NU; ++i) {
+      int n = lane + 64 * i - P;
+      if (n > P) break;
+      cd s = acc[i];
+      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[w][n - l + 2 * P], sm[w][l + P], s);
+      acc[i] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int i = 0; i < NU; ++i) {
+    int n = lane + 64 * i;
+    if (n < NP) sr[w][n] = acc[i];
   }
   __syncthreads();
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  for (int i = threadIdx.x; i < NP; i += 64) {
-    int n = i - P;
-    cd s = mkc(0, 0);
-    for (int c = 0; c < nc; ++c)
-#pragma unroll 7
-      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[c][n - l + 2 * P], sm[c][l + P], s);
-    out[i] = s;
-  }
+  for (int n = threadIdx.x; n < NP; n += 256) out[n] = cadd(cadd(sr[0][n], sr[1][n]), cadd(sr[2][n], sr[3][n]));
 }
 
 // M2L over chunks of the interaction lists (eq. 13 with the index n - l):
@@ -623,140 +676,73 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   }
 }
 
-// Downward pass for the cells of one level: the local expansion is the sum of
-// the cell's M2L chunks (fixed order) plus, below the roots, the L2L of the
-// parent's final expansion, L_n(D) += sum_l L_l(DP) Jp_{l-n}(kap (O_D - O_DP)).
+// Downward pass and L2P, one workgroup of two wavefronts (channels) per leaf.
+// The leaf's local expansion is its own M2L sum plus the own M2L sums of all
+// its ancestors translated directly to it (L2L of Sec. 3.2 across several
+// levels, Graf's theorem for J):
+//   L_n(D) = own_n(D) + sum_A sum_l own_l(A) Jp_{l-n}(kap (O_D - O_A)),
+// with own(A) the fixed-order sum of A's M2L chunks.  Then every target of
+// the leaf evaluates (L2P)
+//   u = sum_l L_l Jp_l(kap (x - O)),  dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}),
+// and the far part of the rows of (I - A) (eq. 9) is written:
+//   far1 = u_ext - u_int,  far2 = 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int).
 template <int P>
-__global__ void __launch_bounds__(64) k_down(int cbeg, int nc, int with_parent,
-                                             const int* __restrict__ cc_ptr, const cd* __restrict__ part,
-                                             const int* __restrict__ parent, const int* __restrict__ joff,
-                                             const cd* __restrict__ jtab, int n_joff, cd* local) {
-  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
-  __shared__ cd sl[NP], sj[NT];
-  int cell = cbeg + blockIdx.x;
-  int ch = blockIdx.y;
-  int c0 = cc_ptr[ch * nc + cell], c1 = cc_ptr[ch * nc + cell + 1];
-  if (with_parent) {
-    int par = parent[cell];
-    const cd* lp = local + ((size_t)par * 2 + ch) * NP;
-    const cd* tj = jtab + ((size_t)ch * n_joff + joff[cell]) * NT;
-    for (int i = threadIdx.x; i < NP; i += 64) sl[i] = lp[i];
-    for (int i = threadIdx.x; i < NT; i += 64) sj[i] = tj[i];
-    __syncthreads();
-  }
-  cd* out = local + ((size_t)cell * 2 + ch) * NP;
-  for (int i = threadIdx.x; i < NP; i += 64) {
-    cd s = mkc(0, 0);
-    for (int c = c0; c < c1; ++c) s = cadd(s, part[(size_t)c * NP + i]);
-    if (with_parent) {
-      int n = i - P;
-      for (int l = -P; l <= P; ++l) s = cfma(sl[l + P], sj[l - n + 2 * P], s);
-    }
-    out[i] = s;
-  }
-}
-
-// P2P with the stored near blocks plus the identity of (I - A):
-//   y1 = phi + sum_b (B11 phi_b + B12 varphi_b),  y2 = varphi + sum_b (B21 phi_b + B22 varphi_b).
-// One workgroup (4 wavefronts) per target leaf, lane = target row.  The
-// densities of the leaf's source columns are first gathered into LDS (in
-// segments), then the wavefronts take the columns in turn and stream the
-// leaf's contiguous block region; partial rows meet in LDS.  Pure streaming:
-// the kernel is HBM-bound.
-constexpr int P2P_WAVES = 4;
-constexpr int P2P_SEG = 512;
-
-__global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p(
-    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
-    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
-    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
-    const int* __restrict__ col_psi, const cd* __restrict__ blocks, const cd* __restrict__ psi,
-    cd* __restrict__ y) {
-  __shared__ cd sp[P2P_SEG][2];
-  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
-  int li = blockIdx.x;
-  int D = leaves[li];
-  int db = ebeg[D], rows = eend[D] - db;
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
-  int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
-  const cd* bl = blocks + 4 * near_blk[near_ptr[li]] + lane;
-  const long long cstride = 4LL * rows;
-  bool act = lane < rows;
-  for (int seg = 0; seg < ncol; seg += P2P_SEG) {
-    int nseg = min(P2P_SEG, ncol - seg);
-    for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
-      int pi = col_psi[k0 + seg + i];
-      sp[i][0] = psi[pi];
-      sp[i][1] = psi[pi + N];
-    }
-    __syncthreads();
-    int k = w;
-    for (; k + P2P_WAVES < nseg; k += 2 * P2P_WAVES) {
-      if (act) {
-        const cd* b0 = bl + (long long)(seg + k) * cstride;
-        const cd* b1 = b0 + P2P_WAVES * cstride;
-        cd b110 = b0[0], b120 = b0[rows], b210 = b0[2 * rows], b220 = b0[3 * rows];
-        cd b111 = b1[0], b121 = b1[rows], b211 = b1[2 * rows], b221 = b1[3 * rows];
-        cd ph0 = sp[k][0], vp0 = sp[k][1];
-        cd ph1 = sp[k + P2P_WAVES][0], vp1 = sp[k + P2P_WAVES][1];
-        a1 = cfma(b110, ph0, a1);
-        a1 = cfma(b120, vp0, a1);
-        a2 = cfma(b210, ph0, a2);
-        a2 = cfma(b220, vp0, a2);
-        a1 = cfma(b111, ph1, a1);
-        a1 = cfma(b121, vp1, a1);
-        a2 = cfma(b211, ph1, a2);
-        a2 = cfma(b221, vp1, a2);
-      }
-    }
-    for (; k < nseg; k += P2P_WAVES) {
-      if (act) {
-        const cd* b0 = bl + (long long)(seg + k) * cstride;
-        cd ph0 = sp[k][0], vp0 = sp[k][1];
-        a1 = cfma(b0[0], ph0, a1);
-        a1 = cfma(b0[rows], vp0, a1);
-        a2 = cfma(b0[2 * rows], ph0, a2);
-        a2 = cfma(b0[3 * rows], vp0, a2);
-      }
-    }
-    __syncthreads();
-  }
-  r1[w][lane] = a1;
-  r2[w][lane] = a2;
-  __syncthreads();
-  if (w == 0 && act) {
-    cd s1 = r1[0][lane], s2 = r2[0][lane];
-#pragma unroll
-    for (int v = 1; v < P2P_WAVES; ++v) {
-      s1 = cadd(s1, r1[v][lane]);
-      s2 = cadd(s2, r2[v][lane]);
-    }
-    int pi = psi_idx[db + lane];
-    y[pi] = cadd(psi[pi], s1);
-    y[pi + N] = cadd(psi[pi + N], s2);
-  }
-}
-
-// L2P at both wavenumbers and the far part of the rows of (I - A) (eq. 9):
-//   y1 += u_ext - u_int,  y2 += 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int),
-//   u = sum_l L_l Jp_l(kap (x - O)),  dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}).
-// One workgroup of two wavefronts (channels) per leaf, lane = target row.
-template <int P>
-__global__ void __launch_bounds__(128) k_l2p(
-    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
+__global__ void __launch_bounds__(128) k_down(
+    int nc, const int* __restrict__ leaves, const int* __restrict__ aptr, const int* __restrict__ anc,
+    const int* __restrict__ aoff, const int* __restrict__ cc_ptr, const cd* __restrict__ part,
+    const cd* __restrict__ jtab, int n_joff, const int* __restrict__ ebeg, const int* __restrict__ eend,
     const int* __restrict__ elem_of, const int* __restrict__ psi_idx, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ mx, const double* __restrict__ my,
-    const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1,
-    double eta, double varrho, const cd* __restrict__ local, cd* __restrict__ y) {
-  constexpr int NP = 2 * P + 1;
-  __shared__ cd sL[2][NP];
+    const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1, double eta,
+    double varrho, cd* __restrict__ far) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
+  __shared__ cd sA[2][NP], sJ[2][NT], sL[2][NP];
   __shared__ cd su[64], sd[64];
-  int D = leaves[blockIdx.x];
-  int db = ebeg[D], rows = eend[D] - db;
+  int li = blockIdx.x;
+  int D = leaves[li];
   int ch = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < 2 * NP; i += 128) sL[i / NP][i % NP] = local[(size_t)D * 2 * NP + i];
+  // own chunks of the leaf
+  cd acc[NU];
+  for (int u = 0; u < NU; ++u) {
+    int i = lane + 64 * u;
+    cd sres = mkc(0, 0);
+    if (i < NP) {
+      int c0 = cc_ptr[ch * nc + D], c1 = cc_ptr[ch * nc + D + 1];
+      for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
+    }
+    acc[u] = sres;
+  }
+  // ancestors
+  for (int q = aptr[li]; q < aptr[li + 1]; ++q) {
+    int A = anc[q];
+    int c0 = cc_ptr[ch * nc + A], c1 = cc_ptr[ch * nc + A + 1];
+    if (c1 == c0) continue;                      // wave-uniform
+    for (int i = lane; i < NP; i += 64) {
+      cd sres = mkc(0, 0);
+      for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
+      sA[ch][i] = sres;
+    }
+    const cd* tj = jtab + ((size_t)ch * n_joff + aoff[q]) * NT;
+    for (int i = lane; i < NT; i += 64) sJ[ch][i] = tj[i];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    for (int u = 0; u < NU; ++u) {
+      int n = lane + 64 * u - P;
+      if (n > P) break;
+      cd sres = acc[u];
+      for (int l = -P; l <= P; ++l) sres = cfma(sA[ch][l + P], sJ[ch][l - n + 2 * P], sres);
+      acc[u] = sres;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int u = 0; u < NU; ++u) {
+    int i = lane + 64 * u;
+    if (i < NP) sL[ch][i] = acc[u];
+  }
   __syncthreads();
+  // L2P
+  int db = ebeg[D], rows = eend[D] - db;
   cd u = mkc(0, 0), dv = mkc(0, 0);
   double kap = ch ? k1 : k;
   if (lane < rows) {
@@ -767,7 +753,7 @@ __global__ void __launch_bounds__(128) k_l2p(
     double gs[P + 2];
     scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
     cd hv = mkc(0.5 * vx, 0.5 * vy);
-    cd uu = cmul(mkc(1.0, 0.0), hv);
+    cd uu = hv;
     cd J0 = mkc(gs[0], 0.0);                 // Jp_0
     cd J1 = cscale(uu, gs[1]);               // Jp_1
     cd Jprev = cscale(cconj(J1), -1.0);      // Jp_{-1}
@@ -803,8 +789,81 @@ __global__ void __launch_bounds__(128) k_l2p(
   if (ch == 0 && lane < rows) {
     int pi = psi_idx[db + lane];
     cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
-    y[pi] = cadd(y[pi], csub(u, su[lane]));
-    y[pi + N] = cfma(c, csub(dv, cscale(sd[lane], varrho)), y[pi + N]);
+    far[pi] = csub(u, su[lane]);
+    far[pi + N] = cmul(c, csub(dv, cscale(sd[lane], varrho)));
+  }
+}
+
+// y += far (the join of the near and far parts of the rows)
+__global__ void k_combine(int n, const cd* __restrict__ far, cd* __restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = cadd(y[i], far[i]);
+}
+
+// P2P with the stored near blocks plus the identity of (I - A):
+//   y1 = phi + sum_b (B11 phi_b + B12 varphi_b),  y2 = varphi + sum_b (B21 phi_b + B22 varphi_b).
+// One workgroup (4 wavefronts) per target leaf, lane = target row.  The
+// densities of the leaf's source columns are first gathered into LDS (in
+// segments), then the wavefronts take the columns in turn and stream the
+// leaf's contiguous block region; partial rows meet in LDS.  Pure streaming:
+// the kernel is HBM-bound.
+constexpr int P2P_WAVES = 4;
+constexpr int P2P_SEG = 512;
+
+__global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
+    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
+    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
+    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
+    const int* __restrict__ col_psi, const cd* __restrict__ blocks, const cd* __restrict__ psi,
+    cd* __restrict__ y, int n_leaves) {
+  __shared__ cd sp[P2P_SEG][2];
+  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
+  for (int li = blockIdx.x; li < n_leaves; li += gridDim.x) {
+  int D = leaves[li];
+  int db = ebeg[D], rows = eend[D] - db;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
+  int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+  const cd* bl = blocks + 4 * near_blk[near_ptr[li]];
+  const unsigned cstride = 4u * (unsigned)rows;
+  bool act = lane < rows;
+  for (int seg = 0; seg < ncol; seg += P2P_SEG) {
+    int nseg = min(P2P_SEG, ncol - seg);
+    for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
+      int pi = col_psi[k0 + seg + i];
+      sp[i][0] = psi[pi];
+      sp[i][1] = psi[pi + N];
+    }
+    __syncthreads();
+    const cd* bs = bl + (size_t)seg * cstride + lane;
+    if (act) {
+      for (int k = w; k < nseg; k += P2P_WAVES) {
+        unsigned o = (unsigned)k * cstride;
+        cd b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
+        cd ph = sp[k][0], vp = sp[k][1];
+        a1 = cfma(b11, ph, a1);
+        a1 = cfma(b12, vp, a1);
+        a2 = cfma(b21, ph, a2);
+        a2 = cfma(b22, vp, a2);
+      }
+    }
+    __syncthreads();
+  }
+  r1[w][lane] = a1;
+  r2[w][lane] = a2;
+  __syncthreads();
+  if (w == 0 && act) {
+    cd s1 = r1[0][lane], s2 = r2[0][lane];
+#pragma unroll
+    for (int v = 1; v < P2P_WAVES; ++v) {
+      s1 = cadd(s1, r1[v][lane]);
+      s2 = cadd(s2, r2[v][lane]);
+    }
+    int pi = psi_idx[db + lane];
+    y[pi] = cadd(psi[pi], s1);
+    y[pi + N] = cadd(psi[pi + N], s2);
+  }
+  __syncthreads();
   }
 }
 
@@ -822,7 +881,9 @@ static hipError_t tables_impl(Problem& pb) {
   return hipGetLastError();
 }
 
-// The FMM chain: P2M, M2M (bottom-up), M2L with the lattice sums, downward pass.
+// The FMM chain: P2M, M2M (leaves to every ancestor), M2L with the lattice
+// sums, downward pass (every ancestor to the leaves) with L2P into the
+// far-field buffer.
 template <int P>
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only) {
   const HostPlan& hp = pb.hp;
@@ -830,28 +891,23 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   int n_leaves = (int)hp.leaves.size();
   int n_joff = (int)hp.joff_xy.size() / 2;
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(64), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
+  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(128), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
                      pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
                      pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole);
   if (ev) (void)hipEventRecord(ev[1], s);
-  for (int lv = hp.depth - 1; lv >= 0; --lv) {
-    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
-    if (ce > cb)
-      hipLaunchKernelGGL(k_m2m<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, pb.d_first_child, pb.d_n_child,
-                         pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_mpole);
-  }
+  if (pb.n_up > 0)
+    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2), dim3(256), 0, s, pb.d_up_cells, pb.d_up_ptr, pb.d_up_src,
+                       pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
   if (pb.n_chunks > 0)
     hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_chunks), dim3(64), 0, s, pb.d_chunks, pb.d_e_src, pb.d_e_off,
                        pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_part);
   if (ev) (void)hipEventRecord(ev[3], s);
-  for (int lv = 0; lv <= hp.depth; ++lv) {
-    int cb = hp.level_beg[lv], ce = hp.level_beg[lv + 1];
-    if (ce > cb)
-      hipLaunchKernelGGL(k_down<P>, dim3(ce - cb, 2), dim3(64), 0, s, cb, nc, lv > 0 ? 1 : 0, pb.d_cc_ptr,
-                         pb.d_part, pb.d_parent, pb.d_cell_joff, pb.d_jtab, n_joff, pb.d_local);
-  }
+  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves), dim3(128), 0, s, nc, pb.d_leaves, pb.d_anc_ptr, pb.d_anc,
+                     pb.d_anc_off, pb.d_cc_ptr, pb.d_part, pb.d_jtab, n_joff, pb.d_ebeg, pb.d_eend,
+                     pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.N,
+                     pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 
@@ -863,8 +919,8 @@ static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
 
 // y = (I - A) psi.  Without stage events the FMM chain runs on the side
 // stream while the near field streams through HBM on the caller's stream;
-// L2P joins both.  With stage events everything runs in order on the
-// caller's stream so that each stage can be timed alone.
+// the far part is added after the join.  With stage events everything runs
+// in order on the caller's stream so that each stage can be timed alone.
 template <int P>
 static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
   const HostPlan& hp = pb.hp;
@@ -876,14 +932,14 @@ static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* 
   }
   fmm_chain<P>(pb, d_psi, fs, ev, false);
   if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
-  hipLaunchKernelGGL(k_p2p, dim3(n_leaves), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+  int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, n_leaves) : n_leaves;
+  hipLaunchKernelGGL(k_p2p, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
                      pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                     pb.d_col_psi, pb.d_near, d_psi, d_y);
+                     pb.d_col_psi, pb.d_near, d_psi, d_y, n_leaves);
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
   if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
-  hipLaunchKernelGGL(k_l2p<P>, dim3(n_leaves), dim3(128), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                     pb.d_eend, pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx,
-                     pb.d_ty, pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_local, d_y);
+  int n = 2 * pb.E;
+  hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256), dim3(256), 0, pb.stream, n, pb.d_far, d_y);
   if (ev) (void)hipEventRecord(ev[6], pb.stream);
   return hipGetLastError();
 }

@@ -223,17 +223,41 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
   hp.root_of_fibre.resize(M);
   for (int f = 0; f < M; ++f) hp.root_of_fibre[f] = tc[roots[f]].id;
 
-  // child-parent offsets
+  // leaf-to-ancestor offsets: the upward pass gathers, for every non-leaf
+  // cell, the leaves below it; the downward pass gathers, for every leaf,
+  // its ancestors.  Both use Jp(kap (O_L - O_A)).
   const double scale = std::ldexp(1.0, 36) / pb.a;
   hp.joff_xy.clear();
   KeyHash jh;
   jh.xy = &hp.joff_xy;
-  hp.cell_joff.assign(nc, -1);
-  for (int i = 0; i < nc; ++i) {
-    const Cell& c = hp.cells[i];
-    if (c.parent < 0) continue;
-    const Cell& p = hp.cells[c.parent];
-    hp.cell_joff[i] = jh.get(c.cx - p.cx, c.cy - p.cy, scale);
+  hp.up_cells.clear();
+  hp.up_ptr.assign(1, 0);
+  hp.up_src.clear();
+  hp.up_off.clear();
+  {
+    std::vector<std::vector<std::pair<int, int>>> below(nc);
+    hp.anc_ptr.assign(1, 0);
+    hp.anc.clear();
+    hp.anc_off.clear();
+    for (int l : hp.leaves) {
+      const Cell& L = hp.cells[l];
+      for (int a = L.parent; a >= 0; a = hp.cells[a].parent) {
+        int id = jh.get(L.cx - hp.cells[a].cx, L.cy - hp.cells[a].cy, scale);
+        below[a].push_back({l, id});
+        hp.anc.push_back(a);
+        hp.anc_off.push_back(id);
+      }
+      hp.anc_ptr.push_back((int)hp.anc.size());
+    }
+    for (int c = 0; c < nc; ++c) {
+      if (hp.cells[c].leaf) continue;
+      hp.up_cells.push_back(c);
+      for (auto& pr : below[c]) {
+        hp.up_src.push_back(pr.first);
+        hp.up_off.push_back(pr.second);
+      }
+      hp.up_ptr.push_back((int)hp.up_src.size());
+    }
   }
 
   // fibre-pair offsets and their explicit image ranges

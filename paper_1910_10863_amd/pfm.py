@@ -229,7 +229,7 @@ class Problem:
         tot = ctypes.c_double()
         self._check(self._L.pfm_matvec_timed(self._h, _ptr(psi), _ptr(y), reps, _dptr(stage),
                                              ctypes.byref(tot)))
-        names = ["p2m", "m2m", "m2l", "down", "p2p", "l2p"]
+        names = ["p2m", "m2m", "m2l", "down_l2p", "p2p", "combine"]
         return dict(zip(names, stage.tolist())), tot.value, y
 
     # ---- test hooks ----
