@@ -52,6 +52,64 @@ def p2p_kernel_bytes(st):
     return 64.0 * st["n_near_entries"] + 32.0 * st["n_near_cols"] + 64.0 * st["E"]
 
 
+def time_matvec(apply, psi, y, reps):
+    import torch
+    for _ in range(3):
+        apply(psi, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        apply(psi, y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def mixed_precision_leg(reps):
+    """FP64 GMRES against FP64 iterative refinement around GMRES with the
+    complex64 near field, on the hexagon 16x16 block (131072 unknowns).
+    The refined solution's residual is re-measured with the FP64 apply."""
+    import torch
+
+    import workloads as W
+    from paper_1910_10863_amd import pfm
+    wl = W.hexagon_16x16()
+    ka, th = wl.ka[0], wl.theta[0]
+    out = {"workload": wl.name, "unknowns": None, "ka": ka, "theta": th, "tol": 1e-8}
+    xs = {}
+    for name, prec in (("fp64", pfm.FP64), ("mixed", pfm.MIXED)):
+        prob = pfm.Problem.from_workload(wl, precision=prec, restart=200, max_iter=4000, tol=1e-8)
+        prob.set_wave(ka, th)
+        out["unknowns"] = prob.n
+        psi = torch.tensor(W.random_density(prob.n, 5), device="cuda")
+        y = prob.empty()
+        rec = {"matvec_ms": time_matvec(prob.matvec, psi, y, reps)}
+        if prec == pfm.MIXED:
+            rec["matvec_mixed_ms"] = time_matvec(prob.matvec_mixed, psi, y, reps)
+        prob.solve()                                   # warm the solver path
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = prob.solve()
+        torch.cuda.synchronize()
+        rec.update({"solve_s": time.perf_counter() - t0, "iters": info["iters"],
+                    "matvecs": info["matvecs"], "outer": info["outer"],
+                    "rel_residual": info["rel_residual"], "status": info["status"]})
+        xs[name] = (prob, x)
+        out[name] = rec
+        print(f"mixed-precision leg {name}: {rec}", file=sys.stderr, flush=True)
+    p64, x64 = xs["fp64"]
+    _, xmx = xs["mixed"]
+    b = p64.rhs()
+    r = b - p64.matvec(xmx)
+    out["mixed"]["fp64_checked_residual"] = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+    out["mixed"]["rel_diff_to_fp64_solution"] = (torch.linalg.vector_norm(xmx - x64)
+                                                 / torch.linalg.vector_norm(x64)).item()
+    out["solve_speedup"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    return out
+
+
 def cpu_baseline(wl, ka, theta, n_targets):
     """Dense FP64 oracle: rows of (I - A) assembled and applied for a sample of
     collocation points; scaled to the rate of a full dense apply."""
@@ -88,6 +146,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: the workload's)")
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied by a plain device copy before timing, for HBM counter scaling")
@@ -167,6 +226,10 @@ def main():
                  "max_rel_residual": float(np.max(res)), "tol": 1e-8, "seconds": tsw,
                  "precision": "fp64", "setup_included": True}
 
+    mixed = None
+    if not args.no_mixed and args.sweep > 0:
+        mixed = mixed_precision_leg(max(10, min(args.steps, 50)))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ka_mat, theta, args.cpu_targets)
@@ -193,6 +256,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": lb, "launch_ms": leaf_ms},
         "sweep": sweep,
+        "mixed_precision": mixed,
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_root_offsets", "lattice_q")},

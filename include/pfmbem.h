@@ -56,6 +56,13 @@ typedef enum {
 
 typedef enum { PFM_SQUARE = 0, PFM_HEXAGON = 1 } pfm_lattice;
 
+/* Arithmetic of the operator apply inside the solver.  PFM_FP64: everything in
+ * FP64.  PFM_MIXED: the near field (P2P, the bulk of the bytes) is stored as
+ * complex64 and accumulated in FP32 inside FP64 iterative refinement; the
+ * far-field expansions, lattice sums, self/near element integrals, GMRES
+ * orthogonalisation and the refinement residual stay FP64. */
+typedef enum { PFM_FP64 = 0, PFM_MIXED = 1 } pfm_precision;
+
 /* Fibre lattice (Sec. 2, Fig. 1).  Square: fibre (col i, row j) centred at
  * ((i+1/2)a, (j+1/2)a).  Hexagon: ((i+1/2)(sqrt3/2)a, (j+1/2+(i mod 2)/2)a).
  * Fibre index f = j*M_L + i.  radii: host array of M radii, or NULL to use r0
@@ -85,7 +92,9 @@ typedef struct {
  *  restart    GMRES restart length m (1..200); max_iter total iterations
  *  tol        GMRES stop: true relative residual ||B - (I-A)Psi|| / ||B||
  *  wood_margin  reject (PFM_EWOOD) when the distance of k H (1 +- sin th)/(2 pi)
- *             to an integer is below this; 0 disables the check */
+ *             to an integer is below this; 0 disables the check
+ *  precision  PFM_FP64 or PFM_MIXED (see pfm_precision)
+ *  inner_tol  PFM_MIXED: relative tolerance of each inner solve (<= 0: 1e-5) */
 typedef struct {
   int p;
   int leaf_max;
@@ -95,6 +104,8 @@ typedef struct {
   int max_iter;
   double tol;
   double wood_margin;
+  int precision;
+  double inner_tol;
 } pfm_options;
 
 typedef struct {
@@ -103,6 +114,7 @@ typedef struct {
   int matvecs;             /* total operator applications */
   double rel_residual;     /* true relative residual of the returned Psi */
   double t_solve_s;        /* wall time of the solve */
+  int outer;               /* PFM_MIXED: refinement steps (0 in FP64) */
 } pfm_info;
 
 /* Sizes and counts of the built plan (for reports and tests). */
@@ -137,6 +149,11 @@ pfm_status pfm_set_wave(pfm_problem* pb, double ka, double theta);
 
 /* d_y = (I - A) d_psi, both 2*M*N complex128 on the device.  No allocation. */
 pfm_status pfm_matvec(pfm_problem* pb, const void* d_psi, void* d_y);
+
+/* The same operator with the near field in complex64 (FP32 accumulation) and
+ * the far field in FP64 (the apply used inside PFM_MIXED refinement).
+ * Requires a handle created with precision = PFM_MIXED. */
+pfm_status pfm_matvec_mixed(pfm_problem* pb, const void* d_psi, void* d_y);
 
 /* d_b = B of eq. (9) for the current wave. */
 pfm_status pfm_rhs(pfm_problem* pb, void* d_b);

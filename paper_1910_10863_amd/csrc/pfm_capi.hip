@@ -80,7 +80,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi);
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
-  dfree(pb.d_near); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
+  dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
   dfree(pb.d_srule);
   dfree(pb.d_mpole); dfree(pb.d_local);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
@@ -159,6 +159,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   if (opt->g_far < 1 || opt->g_far > 16) return bail(fail(pb, PFM_EINVAL, "g_far must be 1..16"));
   if (opt->restart < 1 || opt->restart > 200 || opt->max_iter < 1 || !(opt->tol > 0))
     return bail(fail(pb, PFM_EINVAL, "restart 1..200, max_iter >= 1, tol > 0"));
+  if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
+    return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (!(mat->rho_fiber > 0 && mat->c_fiber > 0 && mat->rho_matrix > 0 && mat->c_matrix > 0))
     return bail(fail(pb, PFM_EINVAL, "materials must be positive"));
 
@@ -170,6 +172,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.N = geo->n_elem;
   pb.E = pb.M * pb.N;
   pb.opt = *opt;
+  if (!(pb.opt.inner_tol > 0 && pb.opt.inner_tol < 1)) pb.opt.inner_tol = 1e-5;
 
   pb.rho_f = mat->rho_fiber;
   pb.c_f = mat->c_fiber;
@@ -312,6 +315,11 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMemset(pb.d_local, 0, (size_t)nc * 2 * NP * sizeof(cd)));
   size_t n_ent = std::max<long long>(1, hp.n_near_entries);
   CK(hipMalloc((void**)&pb.d_near, 4 * n_ent * sizeof(cd)));
+  if (pb.opt.precision == PFM_MIXED) {
+    CK(hipMalloc((void**)&pb.d_near32, 4 * n_ent * sizeof(float2)));
+    CK(hipMalloc((void**)&pb.d_ir_r, 2 * (size_t)E * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_ir_d, 2 * (size_t)E * sizeof(cd)));
+  }
   int n_off = std::max<int>(1, (int)hp.off_xy.size() / 2);
   int n_joff = std::max<int>(1, (int)hp.joff_xy.size() / 2);
   int n_roff = std::max<int>(1, (int)hp.root_off_xy.size() / 2);
@@ -377,7 +385,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_r, n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_b, n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_tmp, n * sizeof(cd)));
-  pb.red_blocks = (int)std::min<size_t>(256, (n + 1023) / 1024);
+  pb.red_blocks = (int)std::min<size_t>(512, (n + 511) / 512);
   CK(hipMalloc((void**)&pb.d_red, (size_t)pb.red_blocks * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipHostMalloc((void**)&pb.h_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
@@ -445,6 +453,7 @@ pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
   HIPCHK(pb, launch_tables(pb));
   HIPCHK(pb, launch_lattice_sums(pb));
   HIPCHK(pb, launch_near_blocks(pb));
+  if (pb.opt.precision == PFM_MIXED) HIPCHK(pb, launch_near_to_c64(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   pb.wave_ready = true;
   return PFM_OK;
@@ -455,6 +464,15 @@ pfm_status pfm_matvec(pfm_problem* h, const void* d_psi, void* d_y) {
   Problem& pb = h->p;
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
   HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, nullptr));
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_mixed(pfm_problem* h, const void* d_psi, void* d_y) {
+  if (!h || !d_psi || !d_y) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  if (pb.opt.precision != PFM_MIXED) return fail(pb, PFM_ESTATE, "handle was not created with PFM_MIXED");
+  HIPCHK(pb, apply_operator_mixed(pb, (const cd*)d_psi, (cd*)d_y));
   return PFM_OK;
 }
 
@@ -490,22 +508,29 @@ pfm_status pfm_rhs(pfm_problem* h, void* d_b) {
   return PFM_OK;
 }
 
-pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* info) {
-  if (!h || !d_x_io) return PFM_EINVAL;
-  Problem& pb = h->p;
-  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
-  auto t0 = std::chrono::steady_clock::now();
+}  // extern "C"
+
+namespace {
+
+struct GmresStats {
+  int iters = 0, matvecs = 0;
+  double rel = 1.0;              // true relative residual ||b - A x|| / ||b|| of the returned x
+};
+
+// Restarted GMRES(m) with classical Gram-Schmidt applied twice (CGS2) and a
+// true-residual check at every restart.  apply(in, out) is the operator;
+// b is read only; x holds the start vector when use_x0, the iterate on
+// return.  Workspace: pb.d_V, pb.d_w, pb.d_r, pb.d_hcol, pb.h_hcol.
+template <typename Apply>
+pfm_status gmres(Problem& pb, Apply&& apply, const cd* b, cd* x, bool use_x0, double tol, int max_iter,
+                 GmresStats& gs) {
   const int n = 2 * pb.E;
   const long long ldv = n;
   const int m = pb.opt.restart;
-  cd* x = (cd*)d_x_io;
-  cd* b = pb.d_b;
-  if (d_b_in) HIPCHK(pb, hipMemcpyAsync(b, d_b_in, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-  else HIPCHK(pb, launch_rhs(pb, b));
   cd* V = pb.d_V;
   cd* hc = pb.d_hcol;
   cd* hh = pb.h_hcol;
-  int matvecs = 0, iters = 0;
+  cd* r = pb.d_r;
   auto dot_host = [&](const cd* u, const cd* v, cd* out) -> hipError_t {
     hipError_t e = launch_dots(pb, u, ldv, 1, v, n, hc);
     if (e != hipSuccess) return e;
@@ -519,10 +544,9 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
   HIPCHK(pb, dot_host(b, b, &tmp));
   double bnorm = std::sqrt(std::max(0.0, tmp.x));
   if (!std::isfinite(bnorm)) return fail(pb, PFM_ENUMERIC, "non-finite right-hand side");
-  cd* r = pb.d_r;
   if (use_x0) {
-    HIPCHK(pb, apply_operator(pb, x, pb.d_w, nullptr));
-    ++matvecs;
+    HIPCHK(pb, apply(x, pb.d_w));
+    ++gs.matvecs;
     HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
     HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
   } else {
@@ -531,26 +555,27 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
   }
   HIPCHK(pb, dot_host(r, r, &tmp));
   double beta = std::sqrt(std::max(0.0, tmp.x));
-  pfm_status st = PFM_OK;
-  std::vector<std::complex<double>> Hm((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
   if (bnorm == 0.0) beta = 0.0;
-  double best = bnorm > 0 ? beta / bnorm : 0.0;
+  gs.rel = bnorm > 0 ? beta / bnorm : 0.0;
+  std::vector<std::complex<double>> Hm((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  int iters = 0;
   while (true) {
-    if (!std::isfinite(beta)) { st = PFM_ENUMERIC; break; }
-    if (bnorm == 0.0 || beta / bnorm <= pb.opt.tol) { st = PFM_OK; break; }
-    if (iters >= pb.opt.max_iter) { st = PFM_ENOCONV; break; }
+    if (!std::isfinite(beta)) return fail(pb, PFM_ENUMERIC, "non-finite residual norm");
+    if (bnorm == 0.0 || beta / bnorm <= tol) { gs.iters += iters; return PFM_OK; }
+    if (iters >= max_iter) {
+      gs.iters += iters;
+      return fail(pb, PFM_ENOCONV, "GMRES stopped at relative residual " + std::to_string(gs.rel));
+    }
     HIPCHK(pb, hipMemcpyAsync(V, r, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
     HIPCHK(pb, launch_axpby(pb, V, mkc(0, 0), nullptr, mkc(1.0 / beta, 0), n));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jj = 0;
-    bool bad = false;
     for (int j = 0; j < m; ++j) {
       cd* vj = V + (size_t)j * n;
       cd* w = V + (size_t)(j + 1) * n;
-      HIPCHK(pb, apply_operator(pb, vj, w, nullptr));
-      ++matvecs;
-      // classical Gram-Schmidt, twice
+      HIPCHK(pb, apply(vj, w));
+      ++gs.matvecs;
       HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc));
       HIPCHK(pb, launch_update(pb, w, V, ldv, j + 1, hc, n));
       HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc + (j + 1)));
@@ -562,7 +587,7 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
       for (int i = 0; i <= j; ++i)
         col[i] = std::complex<double>(hh[i].x + hh[j + 1 + i].x, hh[i].y + hh[j + 1 + i].y);
       double hn = std::sqrt(std::max(0.0, hh[2 * (j + 1)].x));
-      if (!std::isfinite(hn)) { bad = true; break; }
+      if (!std::isfinite(hn)) return fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
       col[j + 1] = hn;
       if (hn > 0) HIPCHK(pb, launch_axpby(pb, w, mkc(0, 0), nullptr, mkc(1.0 / hn, 0), n));
       for (int i = 0; i < j; ++i) {
@@ -591,38 +616,107 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
       ++iters;
       jj = j + 1;
       double est = std::abs(g[j + 1]) / bnorm;
-      if (est <= 0.7 * pb.opt.tol || iters >= pb.opt.max_iter || hn == 0.0) break;
+      if (est <= 0.7 * tol || iters >= max_iter || hn == 0.0) break;
     }
-    if (bad) { st = PFM_ENUMERIC; break; }
-    // back substitution and update of x
     for (int i = jj - 1; i >= 0; --i) {
-      std::complex<double> s = g[i];
-      for (int l = i + 1; l < jj; ++l) s -= Hm[(size_t)i * m + l] * y[l];
-      y[i] = s / Hm[(size_t)i * m + i];
+      std::complex<double> sacc = g[i];
+      for (int l = i + 1; l < jj; ++l) sacc -= Hm[(size_t)i * m + l] * y[l];
+      y[i] = sacc / Hm[(size_t)i * m + i];
     }
     for (int i = 0; i < jj; ++i) hh[i] = mkc(y[i].real(), y[i].imag());
     HIPCHK(pb, hipMemcpyAsync(hc, hh, jj * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
     HIPCHK(pb, launch_gemv_acc(pb, x, V, ldv, jj, hc, n));
-    // true residual
-    HIPCHK(pb, apply_operator(pb, x, pb.d_w, nullptr));
-    ++matvecs;
+    HIPCHK(pb, apply(x, pb.d_w));
+    ++gs.matvecs;
     HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
     HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
     HIPCHK(pb, dot_host(r, r, &tmp));
     beta = std::sqrt(std::max(0.0, tmp.x));
-    if (std::isfinite(beta)) best = beta / bnorm;
+    if (std::isfinite(beta)) gs.rel = beta / bnorm;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* info) {
+  if (!h || !d_x_io) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = 2 * pb.E;
+  cd* x = (cd*)d_x_io;
+  cd* b = pb.d_b;
+  if (d_b_in) HIPCHK(pb, hipMemcpyAsync(b, d_b_in, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+  else HIPCHK(pb, launch_rhs(pb, b));
+  auto apply64 = [&](const cd* in, cd* out) { return apply_operator(pb, in, out, nullptr); };
+  GmresStats gs;
+  pfm_status st = PFM_OK;
+  int outer = 0;
+  if (pb.opt.precision == PFM_MIXED) {
+    // FP64 iterative refinement around GMRES with the mixed-precision apply:
+    //   r = b - A x (FP64 apply); solve A d = r to the inner tolerance; x += d.
+    auto apply32 = [&](const cd* in, cd* out) { return apply_operator_mixed(pb, in, out); };
+    cd* rr = pb.d_ir_r;
+    cd* d = pb.d_ir_d;
+    if (use_x0) {
+      HIPCHK(pb, apply64(x, pb.d_w));
+      ++gs.matvecs;
+      HIPCHK(pb, hipMemcpyAsync(rr, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      HIPCHK(pb, launch_axpby(pb, rr, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
+    } else {
+      HIPCHK(pb, hipMemsetAsync(x, 0, n * sizeof(cd), pb.stream));
+      HIPCHK(pb, hipMemcpyAsync(rr, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    }
+    cd* nn = pb.h_hcol;
+    HIPCHK(pb, launch_dots(pb, b, n, 1, b, n, pb.d_hcol));
+    HIPCHK(pb, launch_dots(pb, rr, n, 1, rr, n, pb.d_hcol + 1));
+    HIPCHK(pb, hipMemcpyAsync(nn, pb.d_hcol, 2 * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
+    HIPCHK(pb, hipStreamSynchronize(pb.stream));
+    double bnorm = std::sqrt(std::max(0.0, nn[0].x)), rnorm = std::sqrt(std::max(0.0, nn[1].x));
+    gs.rel = bnorm > 0 ? rnorm / bnorm : 0.0;
+    const int max_outer = 30;
+    while (true) {
+      if (!std::isfinite(rnorm)) { st = fail(pb, PFM_ENUMERIC, "non-finite residual norm"); break; }
+      if (bnorm == 0.0 || rnorm / bnorm <= pb.opt.tol) { st = PFM_OK; break; }
+      if (gs.iters >= pb.opt.max_iter || outer >= max_outer) {
+        st = fail(pb, PFM_ENOCONV, "refinement stopped at relative residual " + std::to_string(gs.rel));
+        break;
+      }
+      // inner solve to the inner tolerance relative to ||r||, but never below
+      // what the outer tolerance needs
+      double tin = std::max(pb.opt.inner_tol, 0.5 * pb.opt.tol * bnorm / rnorm);
+      GmresStats gi;
+      pfm_status si = gmres(pb, apply32, rr, d, false, tin, pb.opt.max_iter - gs.iters, gi);
+      gs.iters += gi.iters;
+      gs.matvecs += gi.matvecs;
+      if (si != PFM_OK && si != PFM_ENOCONV) { st = si; break; }
+      HIPCHK(pb, launch_axpby(pb, x, mkc(1, 0), d, mkc(1, 0), n));
+      HIPCHK(pb, apply64(x, pb.d_w));
+      ++gs.matvecs;
+      HIPCHK(pb, hipMemcpyAsync(rr, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      HIPCHK(pb, launch_axpby(pb, rr, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
+      HIPCHK(pb, launch_dots(pb, rr, n, 1, rr, n, pb.d_hcol));
+      HIPCHK(pb, hipMemcpyAsync(nn, pb.d_hcol, sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
+      HIPCHK(pb, hipStreamSynchronize(pb.stream));
+      rnorm = std::sqrt(std::max(0.0, nn[0].x));
+      if (std::isfinite(rnorm)) gs.rel = rnorm / bnorm;
+      ++outer;
+    }
+  } else {
+    st = gmres(pb, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs);
   }
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   auto t1 = std::chrono::steady_clock::now();
   if (info) {
     info->status = st;
-    info->iters = iters;
-    info->matvecs = matvecs;
-    info->rel_residual = best;
+    info->iters = gs.iters;
+    info->matvecs = gs.matvecs;
+    info->rel_residual = gs.rel;
     info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+    info->outer = outer;
   }
-  if (st == PFM_ENOCONV) return fail(pb, st, "GMRES stopped at relative residual " + std::to_string(best));
-  if (st == PFM_ENUMERIC) return fail(pb, st, "non-finite residual norm");
   return st;
 }
 

@@ -93,7 +93,9 @@ struct Problem {
   int *d_root_pair_off = nullptr, *d_root_mrange = nullptr;
   double *d_off_xy = nullptr, *d_joff_xy = nullptr, *d_root_off_xy = nullptr;
   // per-wave data
-  cd *d_near = nullptr;                 // 4 planes of n_near_entries
+  cd *d_near = nullptr;                 // near blocks, complex128
+  float2 *d_near32 = nullptr;           // near blocks, complex64 (PFM_MIXED)
+  cd *d_ir_r = nullptr, *d_ir_d = nullptr;   // refinement residual and correction
   cd *d_htab = nullptr;                 // [2 ch][n_tab][4p+1]
   cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
   cd *d_lat = nullptr;                  // = d_htab + n_off rows: lattice sums [n_roff][4p+1]

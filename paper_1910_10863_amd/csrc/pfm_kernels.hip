@@ -810,61 +810,93 @@ __global__ void k_combine(int n, const cd* __restrict__ far, cd* __restrict__ y)
 constexpr int P2P_WAVES = 4;
 constexpr int P2P_SEG = 512;
 
+// Complex arithmetic of the P2P stream: FP64 (double2) or FP32 (float2).
+__device__ __forceinline__ double2 p2p_fma(double2 a, double2 b, double2 c) { return cfma(a, b, c); }
+__device__ __forceinline__ float2 p2p_fma(float2 a, float2 b, float2 c) { return cfmaf(a, b, c); }
+template <typename C> __device__ __forceinline__ C p2p_cvt(cd v);
+template <> __device__ __forceinline__ double2 p2p_cvt<double2>(cd v) { return v; }
+template <> __device__ __forceinline__ float2 p2p_cvt<float2>(cd v) {
+  float2 r;
+  r.x = (float)v.x;
+  r.y = (float)v.y;
+  return r;
+}
+template <typename C> __device__ __forceinline__ cd p2p_wide(C v) { return mkc((double)v.x, (double)v.y); }
+
+template <typename C>
 __global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
     const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
     const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
-    const int* __restrict__ col_psi, const cd* __restrict__ blocks, const cd* __restrict__ psi,
+    const int* __restrict__ col_psi, const C* __restrict__ blocks, const cd* __restrict__ psi,
     cd* __restrict__ y, int n_leaves) {
-  __shared__ cd sp[P2P_SEG][2];
-  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
+  __shared__ C sp[P2P_SEG][2];
+  __shared__ C r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   for (int li = blockIdx.x; li < n_leaves; li += gridDim.x) {
-  int D = leaves[li];
-  int db = ebeg[D], rows = eend[D] - db;
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
-  int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
-  const cd* bl = blocks + 4 * near_blk[near_ptr[li]];
-  const unsigned cstride = 4u * (unsigned)rows;
-  bool act = lane < rows;
-  for (int seg = 0; seg < ncol; seg += P2P_SEG) {
-    int nseg = min(P2P_SEG, ncol - seg);
-    for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
-      int pi = col_psi[k0 + seg + i];
-      sp[i][0] = psi[pi];
-      sp[i][1] = psi[pi + N];
-    }
-    __syncthreads();
-    const cd* bs = bl + (size_t)seg * cstride + lane;
-    if (act) {
-      for (int k = w; k < nseg; k += P2P_WAVES) {
-        unsigned o = (unsigned)k * cstride;
-        cd b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
-        cd ph = sp[k][0], vp = sp[k][1];
-        a1 = cfma(b11, ph, a1);
-        a1 = cfma(b12, vp, a1);
-        a2 = cfma(b21, ph, a2);
-        a2 = cfma(b22, vp, a2);
+    int D = leaves[li];
+    int db = ebeg[D], rows = eend[D] - db;
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    C a1 = p2p_cvt<C>(mkc(0, 0)), a2 = a1;
+    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    const C* bl = blocks + 4 * near_blk[near_ptr[li]];
+    const unsigned cstride = 4u * (unsigned)rows;
+    bool act = lane < rows;
+    for (int seg = 0; seg < ncol; seg += P2P_SEG) {
+      int nseg = min(P2P_SEG, ncol - seg);
+      for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
+        int pi = col_psi[k0 + seg + i];
+        sp[i][0] = p2p_cvt<C>(psi[pi]);
+        sp[i][1] = p2p_cvt<C>(psi[pi + N]);
       }
+      __syncthreads();
+      const C* bs = bl + (size_t)seg * cstride + lane;
+      if (act) {
+        for (int k = w; k < nseg; k += P2P_WAVES) {
+          unsigned o = (unsigned)k * cstride;
+          C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
+          C ph = sp[k][0], vp = sp[k][1];
+          a1 = p2p_fma(b11, ph, a1);
+          a1 = p2p_fma(b12, vp, a1);
+          a2 = p2p_fma(b21, ph, a2);
+          a2 = p2p_fma(b22, vp, a2);
+        }
+      }
+      __syncthreads();
+    }
+    r1[w][lane] = a1;
+    r2[w][lane] = a2;
+    __syncthreads();
+    if (w == 0 && act) {
+      cd s1 = p2p_wide(r1[0][lane]), s2 = p2p_wide(r2[0][lane]);
+#pragma unroll
+      for (int v = 1; v < P2P_WAVES; ++v) {
+        s1 = cadd(s1, p2p_wide(r1[v][lane]));
+        s2 = cadd(s2, p2p_wide(r2[v][lane]));
+      }
+      int pi = psi_idx[db + lane];
+      y[pi] = cadd(psi[pi], s1);
+      y[pi + N] = cadd(psi[pi + N], s2);
     }
     __syncthreads();
   }
-  r1[w][lane] = a1;
-  r2[w][lane] = a2;
-  __syncthreads();
-  if (w == 0 && act) {
-    cd s1 = r1[0][lane], s2 = r2[0][lane];
-#pragma unroll
-    for (int v = 1; v < P2P_WAVES; ++v) {
-      s1 = cadd(s1, r1[v][lane]);
-      s2 = cadd(s2, r2[v][lane]);
-    }
-    int pi = psi_idx[db + lane];
-    y[pi] = cadd(psi[pi], s1);
-    y[pi + N] = cadd(psi[pi + N], s2);
+}
+
+__global__ void k_to_c64(long long n, const cd* __restrict__ in, float2* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float2 r;
+    r.x = (float)in[i].x;
+    r.y = (float)in[i].y;
+    out[i] = r;
   }
-  __syncthreads();
-  }
+}
+
+hipError_t launch_near_to_c64(Problem& pb) {
+  long long n = 4 * pb.hp.n_near_entries;
+  if (n == 0 || !pb.d_near32) return hipSuccess;
+  hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_near,
+                     pb.d_near32);
+  return hipGetLastError();
 }
 
 template <int P>
@@ -921,8 +953,8 @@ static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
 // stream while the near field streams through HBM on the caller's stream;
 // the far part is added after the join.  With stage events everything runs
 // in order on the caller's stream so that each stage can be timed alone.
-template <int P>
-static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+template <int P, typename C>
+static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
   const HostPlan& hp = pb.hp;
   int n_leaves = (int)hp.leaves.size();
   hipStream_t fs = ev ? pb.stream : pb.side;
@@ -933,15 +965,24 @@ static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* 
   fmm_chain<P>(pb, d_psi, fs, ev, false);
   if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, n_leaves) : n_leaves;
-  hipLaunchKernelGGL(k_p2p, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+  hipLaunchKernelGGL(k_p2p<C>, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
                      pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                     pb.d_col_psi, pb.d_near, d_psi, d_y, n_leaves);
+                     pb.d_col_psi, blocks, d_psi, d_y, n_leaves);
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
   if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
   int n = 2 * pb.E;
   hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256), dim3(256), 0, pb.stream, n, pb.d_far, d_y);
   if (ev) (void)hipEventRecord(ev[6], pb.stream);
   return hipGetLastError();
+}
+
+template <int P>
+static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  return apply_impl_t<P, double2>(pb, pb.d_near, d_psi, d_y, ev);
+}
+template <int P>
+static hipError_t apply_mixed_impl(Problem& pb, const cd* d_psi, cd* d_y) {
+  return apply_impl_t<P, float2>(pb, pb.d_near32, d_psi, d_y, nullptr);
 }
 
 #define PFM_DISPATCH(fn, ...)                        \
@@ -961,30 +1002,55 @@ hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev)
   PFM_DISPATCH(apply_impl, pb, d_psi, d_y, ev)
 }
 hipError_t apply_upward(Problem& pb, const cd* d_psi) { PFM_DISPATCH(upward_impl, pb, d_psi, nullptr) }
+hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y) {
+  PFM_DISPATCH(apply_mixed_impl, pb, d_psi, d_y)
+}
 
 // ===========================================================================
 // GMRES building blocks
 // ===========================================================================
 constexpr int RED_THREADS = 256;
 
-// partial[i * nblk + blockIdx.x] = sum over this block's share of conj(V_i) w
+constexpr int DOT_PER_LANE = 8;                 // w elements a lane keeps in registers
+constexpr int DOT_CHUNK = 64 * DOT_PER_LANE;      // elements of one block's chunk
+
+__device__ __forceinline__ cd wave_sum(cd v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+// partial[i * gridDim.x + blockIdx.x] = sum over this block's chunk of conj(V_i) w.
+// The block's chunk of w sits in registers (8 values per lane); the four
+// waves take the vectors V_i round robin and reduce with cross-lane sums, so
+// the loop over i has no barrier.
 __global__ void __launch_bounds__(RED_THREADS) k_dots(const cd* __restrict__ V, long long ldv, int cnt,
                                                       const cd* __restrict__ w, int n, cd* partial) {
-  __shared__ cd s[RED_THREADS];
-  int nblk = gridDim.x;
-  for (int i = 0; i < cnt; ++i) {
-    const cd* v = V + (size_t)i * ldv;
-    cd acc = mkc(0, 0);
-    for (int t = blockIdx.x * RED_THREADS + threadIdx.x; t < n; t += nblk * RED_THREADS)
-      acc = cfma_conj(v[t], w[t], acc);
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) s[threadIdx.x] = cadd(s[threadIdx.x], s[threadIdx.x + st]);
-      __syncthreads();
+  const int nblk = gridDim.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c0 = blockIdx.x * DOT_CHUNK; c0 < n; c0 += nblk * DOT_CHUNK) {
+    cd wr[DOT_PER_LANE];
+#pragma unroll
+    for (int s = 0; s < DOT_PER_LANE; ++s) {
+      int t = c0 + lane + 64 * s;
+      wr[s] = t < n ? w[t] : mkc(0, 0);
     }
-    if (threadIdx.x == 0) partial[(size_t)i * nblk + blockIdx.x] = s[0];
-    __syncthreads();
+    const bool first = c0 == blockIdx.x * DOT_CHUNK;
+    for (int i = wv; i < cnt; i += RED_THREADS / 64) {
+      const cd* v = V + (size_t)i * ldv + c0 + lane;
+      cd acc = mkc(0, 0);
+#pragma unroll
+      for (int s = 0; s < DOT_PER_LANE; ++s)
+        if (c0 + lane + 64 * s < n) acc = cfma_conj(v[64 * s], wr[s], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        cd* dst = partial + (size_t)i * nblk + blockIdx.x;
+        *dst = first ? acc : cadd(*dst, acc);
+      }
+    }
   }
 }
 
@@ -1015,6 +1081,7 @@ __global__ void k_update(cd* w, const cd* __restrict__ V, long long ldv, int cnt
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   cd acc = w[t];
+#pragma unroll 8
   for (int i = 0; i < cnt; ++i) {
     cd hv = hcoef[i];
     acc = csub(acc, cmul(hv, V[(size_t)i * ldv + t]));
@@ -1033,6 +1100,7 @@ __global__ void k_gemv_acc(cd* x, const cd* __restrict__ V, long long ldv, int c
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   cd acc = x[t];
+#pragma unroll 8
   for (int i = 0; i < cnt; ++i) acc = cfma(c[i], V[(size_t)i * ldv + t], acc);
   x[t] = acc;
 }

@@ -16,6 +16,10 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 
 // y = (I - A) psi.  When ev != nullptr, events ev[0..6] bracket the stages.
 hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);
+// the same with the near field in complex64 (FP32 accumulation)
+hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y);
+// complex128 near blocks -> complex64 copy
+hipError_t launch_near_to_c64(Problem& pb);
 // upward pass only (P2M and M2M), for tests
 hipError_t apply_upward(Problem& pb, const cd* d_psi);
 

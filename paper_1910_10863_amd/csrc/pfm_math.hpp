@@ -36,6 +36,13 @@ __host__ __device__ __forceinline__ cd cscale(cd a, double s) { return mkc(a.x *
 __host__ __device__ __forceinline__ cd cfma(cd a, cd b, cd c) {
   return mkc(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
+// single-precision complex a*b + c
+__host__ __device__ __forceinline__ float2 cfmaf(float2 a, float2 b, float2 c) {
+  float2 r;
+  r.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x));
+  r.y = fmaf(a.x, b.y, fmaf(a.y, b.x, c.y));
+  return r;
+}
 // conj(a)*b + c
 __host__ __device__ __forceinline__ cd cfma_conj(cd a, cd b, cd c) {
   return mkc(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));

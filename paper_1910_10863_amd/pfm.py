@@ -41,12 +41,14 @@ class Material(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("leaf_max", ctypes.c_int), ("mac", ctypes.c_double),
                 ("g_far", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("tol", ctypes.c_double), ("wood_margin", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("wood_margin", ctypes.c_double),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("matvecs", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("t_solve_s", ctypes.c_double),
+                ("outer", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -61,7 +63,10 @@ class Stats(ctypes.Structure):
                 ("lattice_q", ctypes.c_int)]
 
 
-EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_rhs", "pfm_solve",
+FP64 = 0
+MIXED = 1
+
+EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_matvec_mixed", "pfm_rhs", "pfm_solve",
            "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
 
@@ -81,6 +86,7 @@ def lib():
     L.pfm_set_stream.argtypes = [P, vp]
     L.pfm_set_wave.argtypes = [P, ctypes.c_double, ctypes.c_double]
     L.pfm_matvec.argtypes = [P, vp, vp]
+    L.pfm_matvec_mixed.argtypes = [P, vp, vp]
     L.pfm_rhs.argtypes = [P, vp]
     L.pfm_solve.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
     L.pfm_fields.argtypes = [P, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -128,8 +134,8 @@ class Problem:
     def __init__(self, lattice: int, a: float, M_L: int, M_H: int, n_elem: int, radii,
                  rho_fiber: float, c_fiber: float, rho_matrix: float, c_matrix: float,
                  eta: float = 0.0, p: int = 16, leaf_max: int = 32, mac: float = 0.65,
-                 g_far: int = 4, restart: int = 50, max_iter: int = 3000, tol: float = 1e-8,
-                 wood_margin: float = 0.0):
+                 g_far: int = 4, restart: int = 200, max_iter: int = 4000, tol: float = 1e-8,
+                 wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0):
         import torch
         L = lib()
         self._L = L
@@ -138,7 +144,7 @@ class Problem:
         self._radii = rad
         geo = Geometry(lattice, a, M_L, M_H, n_elem, _dptr(rad), 0.0)
         mat = Material(rho_fiber, c_fiber, rho_matrix, c_matrix, eta)
-        opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin)
+        opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
@@ -192,6 +198,13 @@ class Problem:
         self._check(self._L.pfm_matvec(self._h, _ptr(psi), _ptr(y)))
         return y
 
+    def matvec_mixed(self, psi, out=None):
+        if psi.numel() != self.n:
+            raise ValueError("psi has the wrong length")
+        y = self.empty() if out is None else out
+        self._check(self._L.pfm_matvec_mixed(self._h, _ptr(psi), _ptr(y)))
+        return y
+
     def rhs(self):
         b = self.empty()
         self._check(self._L.pfm_rhs(self._h, _ptr(b)))
@@ -206,7 +219,7 @@ class Problem:
         if code != 0 and (code != 4 or raise_on_noconv):
             self._check(code)
         return x, {"status": info.status, "iters": info.iters, "matvecs": info.matvecs,
-                   "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s}
+                   "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s, "outer": info.outer}
 
     def fields(self, psi, n_orders: int = 10):
         no = 2 * n_orders + 1

@@ -161,3 +161,28 @@ def test_warm_start_from_solution_converges_immediately(pfm):
     assert info["status"] == 0
     x2, info2 = prob.solve(x0=x)
     assert info2["iters"] == 0 and info2["status"] == 0
+
+
+def test_hexagon_16x16_mixed_solve(pfm):
+    """Hexagon 16x16 block (131072 unknowns): the mixed-precision refined
+    solution meets the FP64 residual 1e-8 (checked with the FP64 apply) and
+    agrees with the FP64 GMRES solution to the accuracy the residual allows."""
+    wl = W.hexagon_16x16()
+    ka, th = wl.ka[0], wl.theta[0]
+    _say("hexagon 16x16 mixed solve")
+    p64 = pfm.Problem.from_workload(wl)
+    p64.set_wave(ka, th)
+    x64, i64 = p64.solve()
+    _say("  fp64", i64)
+    pmx = pfm.Problem.from_workload(wl, precision=pfm.MIXED)
+    pmx.set_wave(ka, th)
+    xmx, imx = pmx.solve()
+    _say("  mixed", imx)
+    assert i64["status"] == 0 and imx["status"] == 0
+    b = p64.rhs()
+    r = b - p64.matvec(xmx)
+    res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+    dx = (torch.linalg.vector_norm(xmx - x64) / torch.linalg.vector_norm(x64)).item()
+    _say("  fp64 residual of mixed solution", res, "difference to fp64 solution", dx)
+    assert res < 1e-8
+    assert dx < 1e-6

@@ -162,3 +162,48 @@ def test_fields_vs_oracle(pfm):
     assert np.max(np.abs(T - Tr)) < 1e-10 * np.max(np.abs(Tr))
     assert abs(etc - fl.etc(pb, psi, n_orders=6)) < 1e-12
     assert abs(en - fl.energy_residual(pb, psi, n_orders=6)) < 1e-12
+
+
+# ---- mixed precision: complex64 near field inside FP64 iterative refinement ----
+
+@pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2"])
+def test_mixed_matvec_vs_dense_oracle(pfm, key):
+    """The mixed apply differs from the exact operator by the FP32 rounding of
+    the near blocks and densities: relative error a few times 2^-24."""
+    pb, A, B = _oracle(key)
+    _say("mixed matvec:", key)
+    prob = _gpu_problem(pfm, key, 40, 16 if key != "tiny" else 32, precision=pfm.MIXED)
+    psi = W.random_density(prob.n, 5)
+    t = torch.tensor(psi, device="cuda")
+    y32 = prob.matvec_mixed(t).cpu().numpy()
+    y64 = prob.matvec(t).cpu().numpy()
+    ref = A @ psi
+    e32 = np.linalg.norm(y32 - ref) / np.linalg.norm(ref)
+    e64 = np.linalg.norm(y64 - ref) / np.linalg.norm(ref)
+    _say("  rel err mixed", e32, "fp64", e64)
+    assert e64 < 1e-10
+    assert 1e-9 < e32 < 2e-6
+
+
+@pytest.mark.parametrize("key", ["sq2x2", "hex2x2"])
+def test_mixed_solve_vs_dense_lu(pfm, key):
+    pb, A, B = _oracle(key)
+    ref = np.linalg.solve(A, B)
+    _say("mixed solve:", key)
+    prob = _gpu_problem(pfm, key, 40, 16, tol=1e-12, restart=100, precision=pfm.MIXED)
+    x, info = prob.solve()
+    _say("  ", info)
+    assert info["status"] == 0 and info["outer"] >= 2
+    xs = x.cpu().numpy()
+    # the true residual of the refined solution with the exact dense operator
+    res = np.linalg.norm(B - A @ xs) / np.linalg.norm(B)
+    err = np.linalg.norm(xs - ref) / np.linalg.norm(ref)
+    _say("  dense residual", res, "rel err vs LU", err)
+    assert res < 1e-10
+    assert err < 1e-8
+
+
+def test_mixed_requires_mixed_handle(pfm):
+    prob = _gpu_problem(pfm, "tiny", 16, 32)
+    with pytest.raises(RuntimeError):
+        prob.matvec_mixed(prob.empty())
