@@ -94,7 +94,11 @@ typedef struct {
  *  wood_margin  reject (PFM_EWOOD) when the distance of k H (1 +- sin th)/(2 pi)
  *             to an integer is below this; 0 disables the check
  *  precision  PFM_FP64 or PFM_MIXED (see pfm_precision)
- *  inner_tol  PFM_MIXED: relative tolerance of each inner solve (<= 0: 1e-5) */
+ *  inner_tol  PFM_MIXED: relative tolerance of each inner solve (<= 0: 1e-5)
+ *  max_batch  capacity of the batched calls: angles per frequency (0 -> 1, at
+ *             most PFM_MAX_BATCH); per-member buffers are sized for it
+ *  use_graph  batched solves replay the batched apply from a captured HIP
+ *             graph (1) or launch it kernel by kernel (0) */
 typedef struct {
   int p;
   int leaf_max;
@@ -106,7 +110,11 @@ typedef struct {
   double wood_margin;
   int precision;
   double inner_tol;
+  int max_batch;
+  int use_graph;
 } pfm_options;
+
+#define PFM_MAX_BATCH 16
 
 typedef struct {
   int status;              /* pfm_status of the solve */
@@ -182,6 +190,47 @@ pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
  * P2P on a second stream; this call does not.) */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);
+
+/* ---- batched sweep: B incidence angles at one frequency ------------------
+ * The B members share the tree, the near-field blocks (stored once, without
+ * the quasi-periodic image phase, which each member applies to its source
+ * densities as alpha_b^m), the translation tables at k and k1 and the
+ * orders of the expansions; each member has its own lattice sums (Sec. 3.3,
+ * theta-dependent through alpha), image phases and right-hand side.
+ * Batched vectors are [B][2*M*N] complex128, member after member. */
+
+/* Per-frequency setup for the angles theta[0..B-1], 1 <= B <= max_batch.
+ * Invalidates the single-angle state of pfm_set_wave (and vice versa).
+ * PFM_EWOOD when any angle fails the Wood margin test (nothing is set up). */
+pfm_status pfm_set_batch(pfm_problem* pb, double ka, int B, const double* theta);
+
+/* d_y[b] = (I - A_b) d_psi[b] for every member b.  No allocation. */
+pfm_status pfm_matvec_batch(pfm_problem* pb, const void* d_psi, void* d_y);
+
+/* d_b[b] = B of eq. (9) for member b. */
+pfm_status pfm_rhs_batch(pfm_problem* pb, void* d_b);
+
+/* Restarted GMRES for all members in lockstep: one batched apply per
+ * iteration, Arnoldi (CGS2) per member in FP64.  d_b: [B][2MN] right-hand
+ * sides or NULL (eq. 9); d_x: [B][2MN] start vectors when use_x0 != 0, the
+ * solutions on return; infos: host array of B records.  A member stops
+ * when its true residual meets tol.  Returns PFM_ENOCONV when any member
+ * misses the tolerance within max_iter iterations (its best iterate is
+ * written), PFM_OK otherwise. */
+pfm_status pfm_solve_batch(pfm_problem* pb, const void* d_b, void* d_x, int use_x0, pfm_info* infos);
+
+/* Band sweep: for each ka[i] (i < n_ka), pfm_set_batch(ka[i], B, theta)
+ * and pfm_solve_batch from zero.  d_x: [n_ka][B][2MN] solutions; infos:
+ * host [n_ka][B].  Frequencies that fail the Wood test get status
+ * PFM_EWOOD in their records and zero solutions; the sweep goes on.
+ * Returns the first error that is neither PFM_ENOCONV nor PFM_EWOOD, else
+ * PFM_ENOCONV / PFM_EWOOD if any record has it, else PFM_OK. */
+pfm_status pfm_sweep(pfm_problem* pb, int n_ka, const double* ka, int B, const double* theta, void* d_x,
+                     pfm_info* infos);
+
+/* Batched apply timed like pfm_matvec_timed (stage_ms[6], total_ms). */
+pfm_status pfm_matvec_batch_timed(pfm_problem* pb, const void* d_psi, void* d_y, int reps, double* stage_ms,
+                                  double* total_ms);
 
 const char* pfm_last_error(const pfm_problem* pb);
 void pfm_destroy(pfm_problem* pb);

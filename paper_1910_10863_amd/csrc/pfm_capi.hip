@@ -77,7 +77,12 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2l_ptr); dfree(pb.d_m2l_src); dfree(pb.d_m2l_off); dfree(pb.d_m2l_m);
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
-  dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi);
+  dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
+  dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout);
+  if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
+  pb.graph = nullptr;
+  if (pb.cap) (void)hipStreamDestroy(pb.cap);
+  pb.cap = nullptr;
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
   dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
@@ -161,6 +166,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "restart 1..200, max_iter >= 1, tol > 0"));
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
+  if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
+    return bail(fail(pb, PFM_EINVAL, "max_batch must be 0..16 and use_graph 0 or 1"));
   if (!(mat->rho_fiber > 0 && mat->c_fiber > 0 && mat->rho_matrix > 0 && mat->c_matrix > 0))
     return bail(fail(pb, PFM_EINVAL, "materials must be positive"));
 
@@ -173,6 +180,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.E = pb.M * pb.N;
   pb.opt = *opt;
   if (!(pb.opt.inner_tol > 0 && pb.opt.inner_tol < 1)) pb.opt.inner_tol = 1e-5;
+  pb.max_batch = std::max(1, opt->max_batch);
 
   pb.rho_f = mat->rho_fiber;
   pb.c_f = mat->c_fiber;
@@ -274,19 +282,21 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   {
     // flattened source columns of every target leaf's near list, in storage order
     int nl = (int)hp.leaves.size();
-    std::vector<int> cptr(nl + 1, 0), cpsi;
+    std::vector<int> cptr(nl + 1, 0), cpsi, cm;
     for (int li = 0; li < nl; ++li) {
       for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
         const Cell& C = hp.cells[hp.near_src[q]];
         for (int t = C.ebeg; t < C.eend; ++t) {
           int e = hp.elem_of[t], f = e / pb.N;
           cpsi.push_back(2 * f * pb.N + (e - f * pb.N));
+          cm.push_back(hp.near_m[q]);
         }
       }
       cptr[li + 1] = (int)cpsi.size();
     }
     CK(upload(&pb.d_cols_ptr, cptr));
     CK(upload(&pb.d_col_psi, cpsi));
+    CK(upload(&pb.d_col_m, cm));
   }
   CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
@@ -309,9 +319,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(&pb.d_gl16, u));
   }
   const int NP = 2 * pb.opt.p + 1, NT = 4 * pb.opt.p + 1;
-  CK(hipMalloc((void**)&pb.d_mpole, (size_t)nc * 2 * NP * sizeof(cd)));
+  const size_t MB = (size_t)pb.max_batch;   // per-member buffers: one copy per batch member
+  CK(hipMalloc((void**)&pb.d_mpole, MB * nc * 2 * NP * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_local, (size_t)nc * 2 * NP * sizeof(cd)));
-  CK(hipMemset(pb.d_mpole, 0, (size_t)nc * 2 * NP * sizeof(cd)));
+  CK(hipMemset(pb.d_mpole, 0, MB * nc * 2 * NP * sizeof(cd)));
   CK(hipMemset(pb.d_local, 0, (size_t)nc * 2 * NP * sizeof(cd)));
   size_t n_ent = std::max<long long>(1, hp.n_near_entries);
   CK(hipMalloc((void**)&pb.d_near, 4 * n_ent * sizeof(cd)));
@@ -326,8 +337,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   // translation table rows per channel: explicit M2L offsets, then lattice offsets
   int n_off_real = (int)hp.off_xy.size() / 2;
   pb.n_tab = n_off_real + n_roff;
-  CK(hipMalloc((void**)&pb.d_htab, (size_t)2 * pb.n_tab * NT * sizeof(cd)));
-  CK(hipMemset(pb.d_htab, 0, (size_t)2 * pb.n_tab * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_htab, MB * 2 * pb.n_tab * NT * sizeof(cd)));
+  CK(hipMemset(pb.d_htab, 0, MB * 2 * pb.n_tab * NT * sizeof(cd)));
   pb.d_lat = pb.d_htab + (size_t)n_off_real * NT;
   CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
   (void)n_off;
@@ -368,33 +379,41 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     pb.n_chunks = (int)(chunks.size() / 4);
     CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
     CK(upload(&pb.d_chunks, chunks)); CK(upload(&pb.d_cc_ptr, ccptr));
-    CK(hipMalloc((void**)&pb.d_part, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_part, MB * std::max(1, pb.n_chunks) * NP * sizeof(cd)));
   }
   {
     CK(upload(&pb.d_up_cells, hp.up_cells)); CK(upload(&pb.d_up_ptr, hp.up_ptr));
     CK(upload(&pb.d_up_src, hp.up_src)); CK(upload(&pb.d_up_off, hp.up_off));
     pb.n_up = (int)hp.up_cells.size();
     CK(upload(&pb.d_anc_ptr, hp.anc_ptr)); CK(upload(&pb.d_anc, hp.anc)); CK(upload(&pb.d_anc_off, hp.anc_off));
-    CK(hipMalloc((void**)&pb.d_far, 2 * (size_t)E * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_far, MB * 2 * E * sizeof(cd)));
   }
-  CK(hipMalloc((void**)&pb.d_alpha, (size_t)(hp.m_max - hp.m_min + 1) * sizeof(cd)));
-  // GMRES workspace
+  {
+    size_t na = (size_t)(hp.m_max - hp.m_min + 1);
+    CK(hipMalloc((void**)&pb.d_alpha, MB * na * sizeof(cd)));
+    std::vector<cd> ones(na, mkc(1.0, 0.0));
+    CK(upload(&pb.d_alpha_one, ones));
+  }
+  // GMRES workspace (batched solves use MB members of each vector)
   size_t n = 2 * (size_t)E;
-  CK(hipMalloc((void**)&pb.d_V, (size_t)(pb.opt.restart + 1) * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_w, n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_r, n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_b, n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_tmp, n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_V, (size_t)(pb.opt.restart + 1) * MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_w, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_r, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_b, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_tmp, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_gin, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
   pb.red_blocks = (int)std::min<size_t>(512, (n + 511) / 512);
-  CK(hipMalloc((void**)&pb.d_red, (size_t)pb.red_blocks * (2 * pb.opt.restart + 8) * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
-  CK(hipHostMalloc((void**)&pb.h_hcol, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_red, MB * pb.red_blocks * (2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
+  CK(hipHostMalloc((void**)&pb.h_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_fields, (size_t)2 * 512 * sizeof(cd)));
   for (int i = 0; i < 16; ++i) CK(hipEventCreate(&pb.ev[i]));
   CK(hipEventCreateWithFlags(&pb.ev_fork, hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&pb.ev_join, hipEventDisableTiming));
   pb.events = true;
   CK(hipStreamCreateWithFlags(&pb.side, hipStreamNonBlocking));
+  CK(hipStreamCreateWithFlags(&pb.cap, hipStreamNonBlocking));
 #undef CK
   *out = h;
   return PFM_OK;
@@ -406,27 +425,34 @@ pfm_status pfm_set_stream(pfm_problem* h, void* stream) {
   return PFM_OK;
 }
 
-pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
-  if (!h) return PFM_EINVAL;
-  Problem& pb = h->p;
-  if (!(ka > 0) || !(std::fabs(theta) < 0.5 * PI))
-    return fail(pb, PFM_EINVAL, "need ka > 0 and |theta| < pi/2");
-  pb.wave_ready = false;
+}  // extern "C"
+
+namespace {
+
+void drop_graph(Problem& pb) {
+  if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
+  pb.graph = nullptr;
+}
+
+// Wavenumbers and coupling of a frequency (no device work).
+void set_frequency(Problem& pb, double ka) {
   pb.k = ka / pb.a;
   pb.k1 = pb.k * pb.c_m / pb.c_f;
   pb.varrho = pb.rho_m / pb.rho_f;
   pb.eta = pb.eta_user > 0 ? pb.eta_user : pb.k;
-  pb.theta = theta;
-  pb.beta = pb.k * pb.H * std::sin(theta);
-  double wd = wood_distance(pb.k, pb.H, theta);
-  if (pb.opt.wood_margin > 0 && wd < pb.opt.wood_margin)
-    return fail(pb, PFM_EWOOD, "k H (1 +- sin theta) / (2 pi) is " + std::to_string(wd) +
-                                   " from an integer");
+}
+
+std::vector<cd> image_phases(const Problem& pb, double beta) {
   const HostPlan& hp = pb.hp;
-  // alpha^m for the explicit images
   std::vector<cd> al(hp.m_max - hp.m_min + 1);
-  for (int m = hp.m_min; m <= hp.m_max; ++m) al[m - hp.m_min] = mkc(std::cos(m * pb.beta), std::sin(m * pb.beta));
-  HIPCHK(pb, hipMemcpyAsync(pb.d_alpha, al.data(), al.size() * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+  for (int m = hp.m_min; m <= hp.m_max; ++m) al[m - hp.m_min] = mkc(std::cos(m * beta), std::sin(m * beta));
+  return al;
+}
+
+// Angle-independent per-frequency work: lattice cut-off q and tail rule
+// (they depend on k and the geometry only), translation tables of member 0.
+pfm_status frequency_tables(Problem& pb) {
+  const HostPlan& hp = pb.hp;
   // lattice-sum cut-off q: all excluded images inside |m| <= q, (q+1)H - |Y| >= H/2,
   // and the contour factor exp(k X^2 / (4 ((q+1)H - |Y|))) held below e^2
   double xmax = 0.0, ymax = 0.0;
@@ -451,11 +477,150 @@ pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
   HIPCHK(pb, upload(&pb.d_srule, rule));
   pb.n_srule = (int)rule.size() / 2;
   HIPCHK(pb, launch_tables(pb));
-  HIPCHK(pb, launch_lattice_sums(pb));
-  HIPCHK(pb, launch_near_blocks(pb));
+  return PFM_OK;
+}
+
+pfm_status check_wood(Problem& pb, double theta) {
+  double wd = wood_distance(pb.k, pb.H, theta);
+  if (pb.opt.wood_margin > 0 && wd < pb.opt.wood_margin)
+    return fail(pb, PFM_EWOOD, "k H (1 +- sin theta) / (2 pi) is " + std::to_string(wd) + " from an integer");
+  return PFM_OK;
+}
+
+// Capture the batched apply d_gin -> d_gout of the current batch into a graph.
+pfm_status capture_batch_graph(Problem& pb) {
+  drop_graph(pb);
+  hipStream_t saved = pb.stream;
+  pb.stream = pb.cap;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(pb.cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t ea = apply_operator_batch(pb, pb.d_gin, pb.d_gout, nullptr);
+    e = hipStreamEndCapture(pb.cap, &g);
+    if (ea != hipSuccess) e = ea;
+  }
+  pb.stream = saved;
+  if (e == hipSuccess) e = hipGraphInstantiate(&pb.graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    pb.graph = nullptr;
+    return fail(pb, PFM_EDEVICE, std::string("graph capture of the batched apply: ") + hipGetErrorString(e));
+  }
+  return PFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
+  if (!h) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!(ka > 0) || !(std::fabs(theta) < 0.5 * PI))
+    return fail(pb, PFM_EINVAL, "need ka > 0 and |theta| < pi/2");
+  pb.wave_ready = false;
+  pb.batch_ready = false;
+  drop_graph(pb);
+  set_frequency(pb, ka);
+  pb.theta = theta;
+  pb.beta = pb.k * pb.H * std::sin(theta);
+  pfm_status st = check_wood(pb, theta);
+  if (st != PFM_OK) return st;
+  std::vector<cd> al = image_phases(pb, pb.beta);
+  HIPCHK(pb, hipMemcpyAsync(pb.d_alpha, al.data(), al.size() * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+  st = frequency_tables(pb);
+  if (st != PFM_OK) return st;
+  HIPCHK(pb, launch_lattice_sums(pb, 0, pb.beta));
+  HIPCHK(pb, launch_near_blocks(pb, false));
   if (pb.opt.precision == PFM_MIXED) HIPCHK(pb, launch_near_to_c64(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   pb.wave_ready = true;
+  return PFM_OK;
+}
+
+pfm_status pfm_set_batch(pfm_problem* h, double ka, int B, const double* theta) {
+  if (!h) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!theta || B < 1 || B > pb.max_batch)
+    return fail(pb, PFM_EINVAL, "need 1 <= B <= max_batch and a theta array");
+  if (!(ka > 0)) return fail(pb, PFM_EINVAL, "need ka > 0");
+  for (int b = 0; b < B; ++b)
+    if (!(std::fabs(theta[b]) < 0.5 * PI)) return fail(pb, PFM_EINVAL, "need |theta| < pi/2");
+  pb.wave_ready = false;
+  pb.batch_ready = false;
+  drop_graph(pb);
+  set_frequency(pb, ka);
+  for (int b = 0; b < B; ++b) {
+    pfm_status st = check_wood(pb, theta[b]);
+    if (st != PFM_OK) return st;
+  }
+  pb.B = B;
+  pb.thetas.assign(theta, theta + B);
+  pb.theta = theta[0];
+  pb.beta = pb.k * pb.H * std::sin(theta[0]);
+  const HostPlan& hp = pb.hp;
+  const size_t na = (size_t)(hp.m_max - hp.m_min + 1);
+  std::vector<cd> al(na * B);
+  for (int b = 0; b < B; ++b) {
+    std::vector<cd> ab = image_phases(pb, pb.k * pb.H * std::sin(theta[b]));
+    std::copy(ab.begin(), ab.end(), al.begin() + b * na);
+  }
+  HIPCHK(pb, hipMemcpyAsync(pb.d_alpha, al.data(), al.size() * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+  pfm_status st = frequency_tables(pb);
+  if (st != PFM_OK) return st;
+  // every member starts from member 0's tables; their lattice rows are then replaced
+  const size_t tab = (size_t)2 * pb.n_tab * (4 * pb.opt.p + 1);
+  for (int b = 1; b < B; ++b)
+    HIPCHK(pb, hipMemcpyAsync(pb.d_htab + b * tab, pb.d_htab, tab * sizeof(cd), hipMemcpyDeviceToDevice,
+                              pb.stream));
+  for (int b = 0; b < B; ++b) HIPCHK(pb, launch_lattice_sums(pb, b, pb.k * pb.H * std::sin(theta[b])));
+  HIPCHK(pb, launch_near_blocks(pb, true));
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  if (pb.opt.use_graph) {
+    st = capture_batch_graph(pb);
+    if (st != PFM_OK) return st;
+  }
+  pb.batch_ready = true;
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_batch(pfm_problem* h, const void* d_psi, void* d_y) {
+  if (!h || !d_psi || !d_y) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.batch_ready) return fail(pb, PFM_ESTATE, "pfm_set_batch first");
+  HIPCHK(pb, apply_operator_batch(pb, (const cd*)d_psi, (cd*)d_y, nullptr));
+  return PFM_OK;
+}
+
+pfm_status pfm_rhs_batch(pfm_problem* h, void* d_b) {
+  if (!h || !d_b) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.batch_ready) return fail(pb, PFM_ESTATE, "pfm_set_batch first");
+  for (int b = 0; b < pb.B; ++b) HIPCHK(pb, launch_rhs(pb, pb.thetas[b], (cd*)d_b + (size_t)b * 2 * pb.E));
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_batch_timed(pfm_problem* h, const void* d_psi, void* d_y, int reps, double* stage_ms,
+                                  double* total_ms) {
+  if (!h || !d_psi || !d_y || reps < 1) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.batch_ready) return fail(pb, PFM_ESTATE, "pfm_set_batch first");
+  double acc[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
+  for (int r = 0; r < reps; ++r) {
+    HIPCHK(pb, apply_operator_batch(pb, (const cd*)d_psi, (cd*)d_y, pb.ev));
+    HIPCHK(pb, hipEventSynchronize(pb.ev[6]));
+    for (int s = 0; s < 6; ++s) {
+      float ms = 0.f;
+      HIPCHK(pb, hipEventElapsedTime(&ms, pb.ev[s], pb.ev[s + 1]));
+      acc[s] += ms;
+    }
+    float all = 0.f;
+    HIPCHK(pb, hipEventElapsedTime(&all, pb.ev[0], pb.ev[6]));
+    tot += all;
+  }
+  if (stage_ms)
+    for (int s = 0; s < 6; ++s) stage_ms[s] = acc[s] / reps;
+  if (total_ms) *total_ms = tot / reps;
   return PFM_OK;
 }
 
@@ -504,7 +669,7 @@ pfm_status pfm_rhs(pfm_problem* h, void* d_b) {
   if (!h || !d_b) return PFM_EINVAL;
   Problem& pb = h->p;
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
-  HIPCHK(pb, launch_rhs(pb, (cd*)d_b));
+  HIPCHK(pb, launch_rhs(pb, pb.theta, (cd*)d_b));
   return PFM_OK;
 }
 
@@ -636,6 +801,180 @@ pfm_status gmres(Problem& pb, Apply&& apply, const cd* b, cd* x, bool use_x0, do
   }
 }
 
+// Batched apply of the current batch: from the captured graph (fixed in/out
+// buffers, copies around it) or launched kernel by kernel.
+hipError_t batch_apply(Problem& pb, const cd* in, cd* out) {
+  if (!pb.graph) return apply_operator_batch(pb, in, out, nullptr);
+  const size_t bytes = (size_t)pb.B * 2 * pb.E * sizeof(cd);
+  hipError_t e = hipMemcpyAsync(pb.d_gin, in, bytes, hipMemcpyDeviceToDevice, pb.stream);
+  if (e == hipSuccess) e = hipGraphLaunch(pb.graph, pb.stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, pb.d_gout, bytes, hipMemcpyDeviceToDevice, pb.stream);
+  return e;
+}
+
+// GMRES(m) for the B members of a batch in lockstep.  Every iteration is one
+// batched apply and one batched CGS2 step (per-member dot products, updates
+// and norms in the same launches); the small Hessenberg problems and Givens
+// rotations are per member on the host.  A member that meets the tolerance
+// (estimate inside a cycle, confirmed by its true residual at the cycle end)
+// stops taking part in the host work; its device lanes keep running and
+// are discarded.  Basis layout: V[(j * B + b) * n].
+pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector<GmresStats>& gs,
+                       std::vector<pfm_status>& st) {
+  typedef std::complex<double> C;
+  const int B = pb.B;
+  const int n = 2 * pb.E;
+  const long long nb = (long long)n;
+  const long long ldv = (long long)B * n;
+  const int m = pb.opt.restart;
+  const long long hs = 2 * m + 8;
+  const double tol = pb.opt.tol;
+  cd* V = pb.d_V;
+  cd* W = pb.d_w;
+  cd* R = pb.d_r;
+  cd* hc = pb.d_hcol;
+  cd* hh = pb.h_hcol;
+  gs.assign(B, GmresStats());
+  st.assign(B, PFM_OK);
+  std::vector<double> bnorm(B), beta(B);
+  std::vector<char> done(B, 0), cyc(B, 0);
+  std::vector<int> jj(B, 0);
+  std::vector<C> Hm((size_t)B * (m + 1) * m), g((size_t)B * (m + 1)), cs((size_t)B * m), sn((size_t)B * m);
+  auto fetch = [&](int count) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
+    (void)count;
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(pb.stream);
+  };
+  // norms of the right-hand sides
+  HIPCHK(pb, launch_dots_b(pb, B, b, nb, nb, 1, b, nb, n, hc, hs));
+  HIPCHK(pb, fetch(1));
+  for (int i = 0; i < B; ++i) bnorm[i] = std::sqrt(std::max(0.0, hh[i * hs].x));
+  if (!use_x0) HIPCHK(pb, hipMemsetAsync(x, 0, (size_t)B * n * sizeof(cd), pb.stream));
+  bool first = true;
+  while (true) {
+    // true residuals R = b - A x
+    if (first && !use_x0) {
+      HIPCHK(pb, hipMemcpyAsync(R, b, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    } else {
+      HIPCHK(pb, batch_apply(pb, x, W));
+      for (int i = 0; i < B; ++i)
+        if (!done[i]) ++gs[i].matvecs;
+      HIPCHK(pb, hipMemcpyAsync(R, b, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      HIPCHK(pb, launch_axpby(pb, R, mkc(-1, 0), W, mkc(1, 0), (long long)B * n));
+    }
+    first = false;
+    HIPCHK(pb, launch_dots_b(pb, B, R, nb, nb, 1, R, nb, n, hc, hs));
+    HIPCHK(pb, fetch(1));
+    bool all_done = true;
+    for (int i = 0; i < B; ++i) {
+      if (done[i]) continue;
+      beta[i] = std::sqrt(std::max(0.0, hh[i * hs].x));
+      if (!std::isfinite(beta[i])) {
+        st[i] = fail(pb, PFM_ENUMERIC, "non-finite residual norm");
+        done[i] = 1;
+        continue;
+      }
+      gs[i].rel = bnorm[i] > 0 ? beta[i] / bnorm[i] : 0.0;
+      if (bnorm[i] == 0.0 || beta[i] / bnorm[i] <= tol) {
+        done[i] = 1;
+        continue;
+      }
+      if (gs[i].iters >= pb.opt.max_iter) {
+        st[i] = fail(pb, PFM_ENOCONV, "GMRES stopped at relative residual " + std::to_string(gs[i].rel));
+        done[i] = 1;
+        continue;
+      }
+      all_done = false;
+    }
+    if (all_done) return PFM_OK;
+    // V_0 = R / ||R|| per member
+    HIPCHK(pb, launch_normalize_b(pb, B, V, R, nb, hc, hs, n));
+    for (int i = 0; i < B; ++i) {
+      cyc[i] = !done[i];
+      jj[i] = 0;
+      for (int r = 0; r <= m; ++r) g[(size_t)i * (m + 1) + r] = 0.0;
+      g[(size_t)i * (m + 1)] = beta[i];
+    }
+    for (int j = 0; j < m; ++j) {
+      cd* Vj = V + (size_t)j * ldv;
+      cd* Wj = V + (size_t)(j + 1) * ldv;
+      HIPCHK(pb, batch_apply(pb, Vj, Wj));
+      for (int i = 0; i < B; ++i)
+        if (cyc[i]) ++gs[i].matvecs;
+      HIPCHK(pb, launch_dots_b(pb, B, V, ldv, nb, j + 1, Wj, nb, n, hc, hs));
+      HIPCHK(pb, launch_update_b(pb, B, Wj, nb, V, ldv, nb, j + 1, hc, hs, n));
+      HIPCHK(pb, launch_dots_b(pb, B, V, ldv, nb, j + 1, Wj, nb, n, hc + (j + 1), hs));
+      HIPCHK(pb, launch_update_b(pb, B, Wj, nb, V, ldv, nb, j + 1, hc + (j + 1), hs, n));
+      HIPCHK(pb, launch_dots_b(pb, B, Wj, nb, nb, 1, Wj, nb, n, hc + 2 * (j + 1), hs));
+      HIPCHK(pb, launch_normalize_b(pb, B, Wj, Wj, nb, hc + 2 * (j + 1), hs, n));
+      HIPCHK(pb, fetch(2 * j + 3));
+      bool any = false;
+      for (int i = 0; i < B; ++i) {
+        if (!cyc[i]) continue;
+        const cd* hv = hh + i * hs;
+        std::vector<C> col(j + 2);
+        for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);
+        double hn = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+        if (!std::isfinite(hn)) {
+          st[i] = fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
+          cyc[i] = 0;
+          done[i] = 1;
+          continue;
+        }
+        col[j + 1] = hn;
+        C* csi = &cs[(size_t)i * m];
+        C* sni = &sn[(size_t)i * m];
+        C* gi = &g[(size_t)i * (m + 1)];
+        for (int r = 0; r < j; ++r) {
+          C a = col[r], bb = col[r + 1];
+          col[r] = csi[r] * a + sni[r] * bb;
+          col[r + 1] = -std::conj(sni[r]) * a + csi[r] * bb;
+        }
+        C a = col[j], bb = col[j + 1];
+        double t = std::sqrt(std::norm(a) + std::norm(bb));
+        if (std::abs(a) == 0.0) {
+          csi[j] = 0.0;
+          sni[j] = 1.0;
+          col[j] = bb;
+        } else {
+          C ph = a / std::abs(a);
+          csi[j] = std::abs(a) / t;
+          sni[j] = ph * std::conj(bb) / t;
+          col[j] = ph * t;
+        }
+        gi[j + 1] = -std::conj(sni[j]) * gi[j];
+        gi[j] = csi[j] * gi[j];
+        for (int r = 0; r <= j; ++r) Hm[((size_t)i * (m + 1) + r) * m + j] = col[r];
+        ++gs[i].iters;
+        jj[i] = j + 1;
+        double est = std::abs(gi[j + 1]) / bnorm[i];
+        if (est <= 0.7 * tol || gs[i].iters >= pb.opt.max_iter || hn == 0.0) cyc[i] = 0;
+        any = any || cyc[i];
+      }
+      if (!any) break;
+    }
+    // x_b += V_b y_b, y_b from the triangular systems (zeros past a member's jj)
+    int cnt = 0;
+    for (int i = 0; i < B; ++i) {
+      cd* yv = hh + i * hs;
+      for (int r = 0; r < m; ++r) yv[r] = mkc(0, 0);
+      std::vector<C> y(jj[i]);
+      for (int r = jj[i] - 1; r >= 0; --r) {
+        C acc = g[(size_t)i * (m + 1) + r];
+        for (int l = r + 1; l < jj[i]; ++l) acc -= Hm[((size_t)i * (m + 1) + r) * m + l] * y[l];
+        y[r] = acc / Hm[((size_t)i * (m + 1) + r) * m + r];
+        yv[r] = mkc(y[r].real(), y[r].imag());
+      }
+      cnt = std::max(cnt, jj[i]);
+    }
+    if (cnt > 0) {
+      HIPCHK(pb, hipMemcpyAsync(hc, hh, (size_t)B * hs * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
+      HIPCHK(pb, launch_gemv_acc_b(pb, B, x, nb, V, ldv, nb, cnt, hc, hs, n));
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -649,7 +988,7 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
   cd* x = (cd*)d_x_io;
   cd* b = pb.d_b;
   if (d_b_in) HIPCHK(pb, hipMemcpyAsync(b, d_b_in, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-  else HIPCHK(pb, launch_rhs(pb, b));
+  else HIPCHK(pb, launch_rhs(pb, pb.theta, b));
   auto apply64 = [&](const cd* in, cd* out) { return apply_operator(pb, in, out, nullptr); };
   GmresStats gs;
   pfm_status st = PFM_OK;
@@ -718,6 +1057,66 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
     info->outer = outer;
   }
   return st;
+}
+
+pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* infos) {
+  if (!h || !d_x_io) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.batch_ready) return fail(pb, PFM_ESTATE, "pfm_set_batch first");
+  auto t0 = std::chrono::steady_clock::now();
+  const size_t n = 2 * (size_t)pb.E;
+  cd* b = pb.d_b;
+  if (d_b_in)
+    HIPCHK(pb, hipMemcpyAsync(b, d_b_in, pb.B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+  else
+    for (int i = 0; i < pb.B; ++i) HIPCHK(pb, launch_rhs(pb, pb.thetas[i], b + i * n));
+  std::vector<GmresStats> gs;
+  std::vector<pfm_status> st;
+  pfm_status s = gmres_batch(pb, b, (cd*)d_x_io, use_x0 != 0, gs, st);
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  pfm_status worst = s;
+  for (int i = 0; i < pb.B && i < (int)st.size(); ++i) {
+    if (infos) {
+      infos[i].status = st[i];
+      infos[i].iters = gs[i].iters;
+      infos[i].matvecs = gs[i].matvecs;
+      infos[i].rel_residual = gs[i].rel;
+      infos[i].t_solve_s = dt;
+      infos[i].outer = 0;
+    }
+    if (worst == PFM_OK && st[i] != PFM_OK) worst = st[i];
+  }
+  return worst;
+}
+
+pfm_status pfm_sweep(pfm_problem* h, int n_ka, const double* ka, int B, const double* theta, void* d_x,
+                     pfm_info* infos) {
+  if (!h || !ka || !theta || !d_x || n_ka < 0) return PFM_EINVAL;
+  Problem& pb = h->p;
+  const size_t n = 2 * (size_t)pb.E;
+  pfm_status worst = PFM_OK;
+  for (int i = 0; i < n_ka; ++i) {
+    cd* x = (cd*)d_x + (size_t)i * B * n;
+    pfm_info* inf = infos ? infos + (size_t)i * B : nullptr;
+    pfm_status s = pfm_set_batch(h, ka[i], B, theta);
+    if (s == PFM_EWOOD) {
+      HIPCHK(pb, hipMemsetAsync(x, 0, B * n * sizeof(cd), pb.stream));
+      if (inf)
+        for (int b = 0; b < B; ++b) {
+          inf[b] = pfm_info();
+          inf[b].status = PFM_EWOOD;
+        }
+      if (worst == PFM_OK || worst == PFM_ENOCONV) worst = PFM_EWOOD;
+      continue;
+    }
+    if (s != PFM_OK) return s;
+    s = pfm_solve_batch(h, nullptr, x, 0, inf);
+    if (s != PFM_OK && s != PFM_ENOCONV && s != PFM_ENUMERIC) return s;
+    if (s != PFM_OK && worst == PFM_OK) worst = s;
+  }
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  return worst;
 }
 
 pfm_status pfm_fields(pfm_problem* h, const void* d_psi, int n_orders, double* R, double* T, double* etc,

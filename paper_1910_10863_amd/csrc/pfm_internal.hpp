@@ -61,8 +61,12 @@ struct Problem {
   double L = 1.0, H = 1.0;
   double rho_f = 1, c_f = 1, rho_m = 1, c_m = 1, eta_user = 0;
   pfm_options opt{};
-  // current wave
+  // current wave (one angle) or batch (B angles at one frequency)
   bool wave_ready = false;
+  bool batch_ready = false;
+  int max_batch = 1;                    // capacity of the per-member buffers
+  int B = 0;                            // members of the current batch
+  std::vector<double> thetas;           // their incidence angles
   double k = 0, k1 = 0, eta = 0, varrho = 0, theta = 0, beta = 0;
   int lattice_q = 0;
 
@@ -90,6 +94,7 @@ struct Problem {
   long long *d_near_blk = nullptr;
   int *d_cols_ptr = nullptr;            // per leaf: range of its flattened near source columns
   int *d_col_psi = nullptr;             // flattened near source columns: index of phi in Psi
+  int *d_col_m = nullptr;               // image index m of each flattened near source column
   int *d_root_pair_off = nullptr, *d_root_mrange = nullptr;
   double *d_off_xy = nullptr, *d_joff_xy = nullptr, *d_root_off_xy = nullptr;
   // per-wave data
@@ -114,7 +119,8 @@ struct Problem {
   int *d_anc_ptr = nullptr, *d_anc = nullptr, *d_anc_off = nullptr;
   cd *d_far = nullptr;                  // far part of the rows, Psi order
   int n_tab = 0;                        // rows per channel of d_htab: M2L offsets, then lattice offsets
-  cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max
+  cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max, per batch member
+  cd *d_alpha_one = nullptr;            // ones: phase-free near blocks
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights
   int n_srule = 0;
   // expansions
@@ -133,6 +139,10 @@ struct Problem {
   bool events = false;
   hipStream_t side = nullptr;           // FMM chain runs here, concurrent with P2P
   hipEvent_t ev_fork, ev_join;
+  // batched solves: captured apply of the current batch (fixed in/out buffers)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph = nullptr;
+  cd *d_gin = nullptr, *d_gout = nullptr;
 };
 
 bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);

@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_near_blocks(NearArgs A) {
   }
 }
 
-hipError_t launch_near_blocks(Problem& pb) {
+hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   const HostPlan& hp = pb.hp;
   int npairs = (int)hp.near_src.size();
   if (npairs == 0) return hipSuccess;
@@ -214,7 +214,7 @@ hipError_t launch_near_blocks(Problem& pb) {
   A.elem_of = pb.d_elem_of; A.ebeg = pb.d_ebeg; A.eend = pb.d_eend; A.leaves = pb.d_leaves;
   A.near_tgt = pb.d_near_tgt; A.near_src = pb.d_near_src; A.near_m = pb.d_near_m;
   A.near_blk = pb.d_near_blk;
-  A.alpha = pb.d_alpha;
+  A.alpha = phase_free ? pb.d_alpha_one : pb.d_alpha;
   A.m_min = hp.m_min;
   A.n_entries = hp.n_near_entries;
   A.out = pb.d_near;
@@ -360,11 +360,13 @@ __global__ void k_lattice_sums(int P, int n_roff, const double* __restrict__ rof
   }
 }
 
-hipError_t launch_lattice_sums(Problem& pb) {
+hipError_t launch_lattice_sums(Problem& pb, int member, double beta) {
   int n_roff = (int)pb.hp.root_off_xy.size() / 2;
+  const int NT = 4 * pb.opt.p + 1;
+  cd* out = pb.d_lat + (size_t)member * 2 * pb.n_tab * NT;
   hipLaunchKernelGGL(k_lattice_sums, dim3(n_roff), dim3(128), 0, pb.stream, pb.opt.p, n_roff,
-                     pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, pb.beta, pb.lattice_q,
-                     pb.d_srule, pb.n_srule, pb.d_lat);
+                     pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, beta, pb.lattice_q,
+                     pb.d_srule, pb.n_srule, out);
   return hipGetLastError();
 }
 
@@ -386,9 +388,9 @@ __global__ void k_rhs(int E, int N, const double* mx, const double* my, const do
   b[2 * f * N + N + l] = cscale(cmul_i(du), s);             // 2i/(eta(1+varrho)) du
 }
 
-hipError_t launch_rhs(Problem& pb, cd* d_b) {
+hipError_t launch_rhs(Problem& pb, double theta, cd* d_b) {
   hipLaunchKernelGGL(k_rhs, dim3((pb.E + 255) / 256), dim3(256), 0, pb.stream, pb.E, pb.N, pb.d_mx,
-                     pb.d_my, pb.d_tx, pb.d_ty, pb.k, pb.theta, pb.eta, pb.varrho, d_b);
+                     pb.d_my, pb.d_tx, pb.d_ty, pb.k, theta, pb.eta, pb.varrho, d_b);
   return hipGetLastError();
 }
 
@@ -470,6 +472,19 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 // ===========================================================================
 // The operator apply (hot path)
 // ===========================================================================
+
+// Distances between consecutive members of a batch in the per-member buffers.
+struct BatchStrides { long long vec, mpole, part, tab; int alpha; };
+static BatchStrides batch_strides(const Problem& pb) {
+  const int NP = 2 * pb.opt.p + 1, NT = 4 * pb.opt.p + 1;
+  BatchStrides s;
+  s.vec = 2LL * pb.E;
+  s.mpole = (long long)pb.hp.cells.size() * 2 * NP;
+  s.part = (long long)std::max(1, pb.n_chunks) * NP;
+  s.tab = 2LL * pb.n_tab * NT;
+  s.alpha = pb.hp.m_max - pb.hp.m_min + 1;
+  return s;
+}
 
 // P2M: multipole moments at the leaves, both wavenumbers (Sec. 3.2, MM of
 // S-bar and D-bar combined as in the representation D phi - i eta S varphi):
@@ -561,10 +576,13 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
                                              const double* __restrict__ tx, const double* __restrict__ ty,
                                              const double* __restrict__ h, const double* __restrict__ gl,
                                              int G, int N, double k, double k1, double eta,
-                                             const cd* __restrict__ psi, cd* __restrict__ mpole) {
+                                             const cd* __restrict__ psi, cd* __restrict__ mpole,
+                                             long long psi_stride, long long mp_stride) {
   constexpr int NP = 2 * P + 1;
   constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
   __shared__ cd red[2][64][NA];
+  psi += blockIdx.z * psi_stride;               // batch member
+  mpole += blockIdx.z * mp_stride;
   int cell = leaves[blockIdx.x];
   int ch = blockIdx.y;
   double kap = ch ? k1 : k;
@@ -599,10 +617,12 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
 template <int P>
 __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, const int* __restrict__ ptr,
                                              const int* __restrict__ src, const int* __restrict__ off,
-                                             const cd* __restrict__ jtab, int n_joff, cd* mpole) {
+                                             const cd* __restrict__ jtab, int n_joff, cd* mpole,
+                                             long long mp_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
   __shared__ cd sm[4][NP], sj[4][NT];
   __shared__ cd sr[4][NP];
+  mpole += blockIdx.z * mp_stride;              // batch member
   int ci = blockIdx.x, ch = blockIdx.y;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int cell = cells[ci];
@@ -646,9 +666,16 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
                                             const int* __restrict__ e_off, const int* __restrict__ e_m,
                                             const cd* __restrict__ htab, int n_tab,
                                             const cd* __restrict__ alpha, int m_min,
-                                            const cd* __restrict__ mpole, cd* __restrict__ part) {
+                                            const cd* __restrict__ mpole, cd* __restrict__ part,
+                                            long long mp_stride, long long part_stride, long long tab_stride,
+                                            int alpha_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
   __shared__ cd sm[NP], sh[NT];
+  // batch member: its multipoles, partial sums, lattice rows and image phases
+  mpole += blockIdx.y * mp_stride;
+  part += blockIdx.y * part_stride;
+  htab += blockIdx.y * tab_stride;
+  alpha += blockIdx.y * alpha_stride;
   int c = blockIdx.x;
   int ch = chunks[4 * c + 1], b = chunks[4 * c + 2], e = b + chunks[4 * c + 3];
   cd acc[(NP + 63) / 64];
@@ -694,10 +721,12 @@ __global__ void __launch_bounds__(128) k_down(
     const int* __restrict__ elem_of, const int* __restrict__ psi_idx, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ mx, const double* __restrict__ my,
     const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1, double eta,
-    double varrho, cd* __restrict__ far) {
+    double varrho, cd* __restrict__ far, long long part_stride, long long far_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
   __shared__ cd sA[2][NP], sJ[2][NT], sL[2][NP];
   __shared__ cd su[64], sd[64];
+  part += blockIdx.y * part_stride;             // batch member
+  far += blockIdx.y * far_stride;
   int li = blockIdx.x;
   int D = leaves[li];
   int ch = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -795,8 +824,8 @@ __global__ void __launch_bounds__(128) k_down(
 }
 
 // y += far (the join of the near and far parts of the rows)
-__global__ void k_combine(int n, const cd* __restrict__ far, cd* __restrict__ y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_combine(long long n, const cd* __restrict__ far, cd* __restrict__ y) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = cadd(y[i], far[i]);
 }
 
@@ -881,6 +910,89 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
   }
 }
 
+// Batched P2P: the NB members of a batch share one set of near blocks
+// stored without the quasi-periodic phase; member b sees image m of a source
+// through alpha_b^m, applied to the densities as they are staged in LDS.
+// Each block entry is read from HBM once and used for every member.
+template <int NB> struct P2PBatchSeg { static constexpr int value = 1024 / NB; };
+
+template <typename C, int NB>
+__global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
+    const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
+    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
+    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
+    const int* __restrict__ col_psi, const int* __restrict__ col_m, const cd* __restrict__ alpha,
+    int alpha_stride, int m_min, int B, long long stride, const C* __restrict__ blocks,
+    const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves) {
+  constexpr int SEG = P2PBatchSeg<NB>::value;
+  __shared__ C sp[SEG][NB][2];
+  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
+  for (int li = blockIdx.x; li < n_leaves; li += gridDim.x) {
+    int D = leaves[li];
+    int db = ebeg[D], rows = eend[D] - db;
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    C a1[NB], a2[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) a1[b] = a2[b] = p2p_cvt<C>(mkc(0, 0));
+    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    const C* bl = blocks + 4 * near_blk[near_ptr[li]];
+    const unsigned cstride = 4u * (unsigned)rows;
+    bool act = lane < rows;
+    for (int seg = 0; seg < ncol; seg += SEG) {
+      int nseg = min(SEG, ncol - seg);
+      for (int i = threadIdx.x; i < nseg * NB; i += 64 * P2P_WAVES) {
+        int col = i / NB, b = i - col * NB;
+        cd v0 = mkc(0, 0), v1 = mkc(0, 0);
+        if (b < B) {
+          int pi = col_psi[k0 + seg + col];
+          cd ph = alpha[b * alpha_stride + col_m[k0 + seg + col] - m_min];
+          v0 = cmul(ph, psi[b * stride + pi]);
+          v1 = cmul(ph, psi[b * stride + pi + N]);
+        }
+        sp[col][b][0] = p2p_cvt<C>(v0);
+        sp[col][b][1] = p2p_cvt<C>(v1);
+      }
+      __syncthreads();
+      const C* bs = bl + (size_t)seg * cstride + lane;
+      if (act) {
+        for (int k = w; k < nseg; k += P2P_WAVES) {
+          unsigned o = (unsigned)k * cstride;
+          C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            C ph = sp[k][b][0], vp = sp[k][b][1];
+            a1[b] = p2p_fma(b11, ph, a1[b]);
+            a1[b] = p2p_fma(b12, vp, a1[b]);
+            a2[b] = p2p_fma(b21, ph, a2[b]);
+            a2[b] = p2p_fma(b22, vp, a2[b]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      r1[w][lane] = p2p_wide(a1[b]);
+      r2[w][lane] = p2p_wide(a2[b]);
+      __syncthreads();
+      if (w == 0 && act && b < B) {
+        cd s1 = r1[0][lane], s2 = r2[0][lane];
+#pragma unroll
+        for (int v = 1; v < P2P_WAVES; ++v) {
+          s1 = cadd(s1, r1[v][lane]);
+          s2 = cadd(s2, r2[v][lane]);
+        }
+        int pi = psi_idx[db + lane];
+        const cd* pb_ = psi + b * stride;
+        cd* yb = y + b * stride;
+        yb[pi] = cadd(pb_[pi], s1);
+        yb[pi + N] = cadd(pb_[pi + N], s2);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void k_to_c64(long long n, const cd* __restrict__ in, float2* __restrict__ out) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -917,72 +1029,103 @@ static hipError_t tables_impl(Problem& pb) {
 // sums, downward pass (every ancestor to the leaves) with L2P into the
 // far-field buffer.
 template <int P>
-static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only) {
+static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B) {
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
   int n_joff = (int)hp.joff_xy.size() / 2;
+  const BatchStrides bs = batch_strides(pb);
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2), dim3(128), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
+  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2, B), dim3(128), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
                      pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
-                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole);
+                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec,
+                     bs.mpole);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (pb.n_up > 0)
-    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2), dim3(256), 0, s, pb.d_up_cells, pb.d_up_ptr, pb.d_up_src,
-                       pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole);
+    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2, B), dim3(256), 0, s, pb.d_up_cells, pb.d_up_ptr,
+                       pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
   if (pb.n_chunks > 0)
-    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_chunks), dim3(64), 0, s, pb.d_chunks, pb.d_e_src, pb.d_e_off,
-                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_part);
+    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_chunks, B), dim3(64), 0, s, pb.d_chunks, pb.d_e_src, pb.d_e_off,
+                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_part, bs.mpole,
+                       bs.part, bs.tab, bs.alpha);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves), dim3(128), 0, s, nc, pb.d_leaves, pb.d_anc_ptr, pb.d_anc,
+  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, nc, pb.d_leaves, pb.d_anc_ptr, pb.d_anc,
                      pb.d_anc_off, pb.d_cc_ptr, pb.d_part, pb.d_jtab, n_joff, pb.d_ebeg, pb.d_eend,
                      pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.N,
-                     pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far);
+                     pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far, bs.part, bs.vec);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 
 template <int P>
 static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
-  fmm_chain<P>(pb, d_psi, pb.stream, ev, true);
+  fmm_chain<P>(pb, d_psi, pb.stream, ev, true, 1);
   return hipGetLastError();
+}
+
+template <typename C, int NB>
+static void launch_p2p_batch(Problem& pb, int grid, const C* blocks, const cd* d_psi, cd* d_y, int B) {
+  const BatchStrides bs = batch_strides(pb);
+  hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves,
+                     pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
+                     pb.d_col_psi, pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, d_psi,
+                     d_y, (int)pb.hp.leaves.size());
 }
 
 // y = (I - A) psi.  Without stage events the FMM chain runs on the side
 // stream while the near field streams through HBM on the caller's stream;
 // the far part is added after the join.  With stage events everything runs
 // in order on the caller's stream so that each stage can be timed alone.
+// B = 0: one wave, image phases inside the near blocks; B >= 1: a batch of
+// B members (one per incidence angle) over phase-free near blocks.
 template <int P, typename C>
-static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B) {
   const HostPlan& hp = pb.hp;
   int n_leaves = (int)hp.leaves.size();
+  int nb = B > 0 ? B : 1;
   hipStream_t fs = ev ? pb.stream : pb.side;
   if (!ev) {
     (void)hipEventRecord(pb.ev_fork, pb.stream);
     (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
   }
-  fmm_chain<P>(pb, d_psi, fs, ev, false);
+  fmm_chain<P>(pb, d_psi, fs, ev, false, nb);
   if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, n_leaves) : n_leaves;
-  hipLaunchKernelGGL(k_p2p<C>, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                     pb.d_col_psi, blocks, d_psi, d_y, n_leaves);
+  if (B == 0) {
+    hipLaunchKernelGGL(k_p2p<C>, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
+                       pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
+                       pb.d_col_psi, blocks, d_psi, d_y, n_leaves);
+  } else if (B == 1) {
+    launch_p2p_batch<C, 1>(pb, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B == 2) {
+    launch_p2p_batch<C, 2>(pb, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B <= 4) {
+    launch_p2p_batch<C, 4>(pb, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B <= 8) {
+    launch_p2p_batch<C, 8>(pb, p2p_grid, blocks, d_psi, d_y, B);
+  } else {
+    launch_p2p_batch<C, 16>(pb, p2p_grid, blocks, d_psi, d_y, B);
+  }
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
   if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
-  int n = 2 * pb.E;
-  hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256), dim3(256), 0, pb.stream, n, pb.d_far, d_y);
+  long long n = 2LL * pb.E * nb;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_far, d_y);
   if (ev) (void)hipEventRecord(ev[6], pb.stream);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t apply_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
-  return apply_impl_t<P, double2>(pb, pb.d_near, d_psi, d_y, ev);
+  return apply_impl_t<P, double2>(pb, pb.d_near, d_psi, d_y, ev, 0);
 }
 template <int P>
 static hipError_t apply_mixed_impl(Problem& pb, const cd* d_psi, cd* d_y) {
-  return apply_impl_t<P, float2>(pb, pb.d_near32, d_psi, d_y, nullptr);
+  return apply_impl_t<P, float2>(pb, pb.d_near32, d_psi, d_y, nullptr, 0);
+}
+template <int P>
+static hipError_t apply_batch_impl(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  return apply_impl_t<P, double2>(pb, pb.d_near, d_psi, d_y, ev, pb.B);
 }
 
 #define PFM_DISPATCH(fn, ...)                        \
@@ -1005,6 +1148,9 @@ hipError_t apply_upward(Problem& pb, const cd* d_psi) { PFM_DISPATCH(upward_impl
 hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y) {
   PFM_DISPATCH(apply_mixed_impl, pb, d_psi, d_y)
 }
+hipError_t apply_operator_batch(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev) {
+  PFM_DISPATCH(apply_batch_impl, pb, d_psi, d_y, ev)
+}
 
 // ===========================================================================
 // GMRES building blocks
@@ -1023,14 +1169,26 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
-// partial[i * gridDim.x + blockIdx.x] = sum over this block's chunk of conj(V_i) w.
-// The block's chunk of w sits in registers (8 values per lane); the four
-// waves take the vectors V_i round robin and reduce with cross-lane sums, so
-// the loop over i has no barrier.
-__global__ void __launch_bounds__(RED_THREADS) k_dots(const cd* __restrict__ V, long long ldv, int cnt,
-                                                      const cd* __restrict__ w, int n, cd* partial) {
+constexpr int DOT_VPW = 2;                      // vectors a wave reduces at once
+constexpr int DOT_VPB = DOT_VPW * (RED_THREADS / 64);   // vectors per block
+
+// partial[(z * cnt + i) * gridDim.x + blockIdx.x] = sum over the chunks of
+// blockIdx.x of conj(V_i) w, for the vectors i of blockIdx.y and the batch
+// member z = blockIdx.z (V and w advanced by vsb and wsb per member).  A
+// chunk of w sits in registers (8 values per lane); each wave takes two
+// vectors, keeps their 16 loads per lane in flight together and reduces with
+// cross-lane sums, so there is no barrier.  The vector groups on the y axis
+// keep enough waves resident to cover memory latency.
+__global__ void __launch_bounds__(RED_THREADS) k_dots(const cd* __restrict__ V, long long ldv, long long vsb,
+                                                      int cnt, const cd* __restrict__ w, long long wsb, int n,
+                                                      cd* partial) {
   const int nblk = gridDim.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * DOT_VPB + wv * DOT_VPW;
+  if (i0 >= cnt) return;
+  V += blockIdx.z * vsb;
+  w += blockIdx.z * wsb;
+  partial += (size_t)blockIdx.z * cnt * nblk;
   for (int c0 = blockIdx.x * DOT_CHUNK; c0 < n; c0 += nblk * DOT_CHUNK) {
     cd wr[DOT_PER_LANE];
 #pragma unroll
@@ -1039,24 +1197,33 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(const cd* __restrict__ V, 
       wr[s] = t < n ? w[t] : mkc(0, 0);
     }
     const bool first = c0 == blockIdx.x * DOT_CHUNK;
-    for (int i = wv; i < cnt; i += RED_THREADS / 64) {
+    cd acc[DOT_VPW];
+#pragma unroll
+    for (int u = 0; u < DOT_VPW; ++u) {
+      acc[u] = mkc(0, 0);
+      const int i = min(i0 + u, cnt - 1);
       const cd* v = V + (size_t)i * ldv + c0 + lane;
-      cd acc = mkc(0, 0);
 #pragma unroll
       for (int s = 0; s < DOT_PER_LANE; ++s)
-        if (c0 + lane + 64 * s < n) acc = cfma_conj(v[64 * s], wr[s], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        cd* dst = partial + (size_t)i * nblk + blockIdx.x;
-        *dst = first ? acc : cadd(*dst, acc);
+        if (c0 + lane + 64 * s < n) acc[u] = cfma_conj(v[64 * s], wr[s], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < DOT_VPW; ++u) {
+      cd r = wave_sum(acc[u]);
+      if (lane == 0 && i0 + u < cnt) {
+        cd* dst = partial + (size_t)(i0 + u) * nblk + blockIdx.x;
+        *dst = first ? r : cadd(*dst, r);
       }
     }
   }
 }
 
-__global__ void __launch_bounds__(RED_THREADS) k_dots_final(const cd* partial, int nblk, cd* out) {
+__global__ void __launch_bounds__(RED_THREADS) k_dots_final(const cd* partial, int nblk, int cnt, cd* out,
+                                                            long long osb) {
   __shared__ cd s[RED_THREADS];
   int i = blockIdx.x;
+  partial += (size_t)blockIdx.y * cnt * nblk;
+  out += blockIdx.y * osb;
   cd acc = mkc(0, 0);
   for (int b = threadIdx.x; b < nblk; b += RED_THREADS) acc = cadd(acc, partial[(size_t)i * nblk + b]);
   s[threadIdx.x] = acc;
@@ -1068,18 +1235,28 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots_final(const cd* partial, i
   if (threadIdx.x == 0) out[i] = s[0];
 }
 
-hipError_t launch_dots(Problem& pb, const cd* V, long long ldv, int cnt, const cd* w, int n, cd* d_out) {
+hipError_t launch_dots_b(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int cnt, const cd* w,
+                         long long wsb, int n, cd* d_out, long long osb) {
   int nblk = pb.red_blocks;
-  hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(RED_THREADS), 0, pb.stream, V, ldv, cnt, w, n, pb.d_red);
-  hipLaunchKernelGGL(k_dots_final, dim3(cnt), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, d_out);
+  dim3 grid(nblk, (cnt + DOT_VPB - 1) / DOT_VPB, B);
+  hipLaunchKernelGGL(k_dots, grid, dim3(RED_THREADS), 0, pb.stream, V, ldv, vsb, cnt, w, wsb, n, pb.d_red);
+  hipLaunchKernelGGL(k_dots_final, dim3(cnt, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, cnt, d_out,
+                     osb);
   return hipGetLastError();
 }
 
-// w -= sum_i h_i V_i
-__global__ void k_update(cd* w, const cd* __restrict__ V, long long ldv, int cnt,
-                         const cd* __restrict__ hcoef, int n) {
+hipError_t launch_dots(Problem& pb, const cd* V, long long ldv, int cnt, const cd* w, int n, cd* d_out) {
+  return launch_dots_b(pb, 1, V, ldv, 0, cnt, w, 0, n, d_out, 0);
+}
+
+// w -= sum_i h_i V_i   (member blockIdx.y: w, V, h advanced by their strides)
+__global__ void k_update(cd* w, long long wsb, const cd* __restrict__ V, long long ldv, long long vsb, int cnt,
+                         const cd* __restrict__ hcoef, long long hsb, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
+  w += blockIdx.y * wsb;
+  V += blockIdx.y * vsb;
+  hcoef += blockIdx.y * hsb;
   cd acc = w[t];
 #pragma unroll 8
   for (int i = 0; i < cnt; ++i) {
@@ -1089,36 +1266,69 @@ __global__ void k_update(cd* w, const cd* __restrict__ V, long long ldv, int cnt
   w[t] = acc;
 }
 
-hipError_t launch_update(Problem& pb, cd* w, const cd* V, long long ldv, int cnt, const cd* d_h, int n) {
-  hipLaunchKernelGGL(k_update, dim3((n + 255) / 256), dim3(256), 0, pb.stream, w, V, ldv, cnt, d_h, n);
+hipError_t launch_update_b(Problem& pb, int B, cd* w, long long wsb, const cd* V, long long ldv, long long vsb,
+                           int cnt, const cd* d_h, long long hsb, int n) {
+  hipLaunchKernelGGL(k_update, dim3((n + 255) / 256, B), dim3(256), 0, pb.stream, w, wsb, V, ldv, vsb, cnt, d_h,
+                     hsb, n);
   return hipGetLastError();
 }
 
-// x += sum_i c_i V_i
-__global__ void k_gemv_acc(cd* x, const cd* __restrict__ V, long long ldv, int cnt,
-                           const cd* __restrict__ c, int n) {
+hipError_t launch_update(Problem& pb, cd* w, const cd* V, long long ldv, int cnt, const cd* d_h, int n) {
+  return launch_update_b(pb, 1, w, 0, V, ldv, 0, cnt, d_h, 0, n);
+}
+
+// x += sum_i c_i V_i   (member blockIdx.y)
+__global__ void k_gemv_acc(cd* x, long long xsb, const cd* __restrict__ V, long long ldv, long long vsb, int cnt,
+                           const cd* __restrict__ c, long long csb, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
+  x += blockIdx.y * xsb;
+  V += blockIdx.y * vsb;
+  c += blockIdx.y * csb;
   cd acc = x[t];
 #pragma unroll 8
   for (int i = 0; i < cnt; ++i) acc = cfma(c[i], V[(size_t)i * ldv + t], acc);
   x[t] = acc;
 }
 
-hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n) {
-  hipLaunchKernelGGL(k_gemv_acc, dim3((n + 255) / 256), dim3(256), 0, pb.stream, x, V, ldv, cnt, d_c, n);
+hipError_t launch_gemv_acc_b(Problem& pb, int B, cd* x, long long xsb, const cd* V, long long ldv, long long vsb,
+                             int cnt, const cd* d_c, long long csb, int n) {
+  hipLaunchKernelGGL(k_gemv_acc, dim3((n + 255) / 256, B), dim3(256), 0, pb.stream, x, xsb, V, ldv, vsb, cnt,
+                     d_c, csb, n);
   return hipGetLastError();
 }
 
-__global__ void k_axpby(cd* y, cd a, const cd* __restrict__ x, cd b, int n) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n) {
+  return launch_gemv_acc_b(pb, 1, x, 0, V, ldv, 0, cnt, d_c, 0, n);
+}
+
+__global__ void k_axpby(cd* y, cd a, const cd* __restrict__ x, cd b, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   cd yv = b.x == 0.0 && b.y == 0.0 ? mkc(0, 0) : cmul(b, y[t]);
   y[t] = x ? cfma(a, x[t], yv) : yv;
 }
 
-hipError_t launch_axpby(Problem& pb, cd* y, cd a, const cd* x, cd b, int n) {
-  hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, pb.stream, y, a, x, b, n);
+hipError_t launch_axpby(Problem& pb, cd* y, cd a, const cd* x, cd b, long long n) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, y, a, x, b, n);
+  return hipGetLastError();
+}
+
+// out_b = in_b / sqrt(Re nrm[b * nsb]) for every member whose squared norm is
+// positive; members with a zero norm get a zero vector.
+__global__ void k_normalize_b(cd* out, const cd* __restrict__ in, long long sb, const cd* __restrict__ nrm,
+                              long long nsb, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double q = nrm[blockIdx.y * nsb].x;
+  double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  out[blockIdx.y * sb + t] = cscale(in[blockIdx.y * sb + t], s);
+}
+
+hipError_t launch_normalize_b(Problem& pb, int B, cd* out, const cd* in, long long sb, const cd* d_nrm,
+                              long long nsb, int n) {
+  hipLaunchKernelGGL(k_normalize_b, dim3((n + 255) / 256, B), dim3(256), 0, pb.stream, out, in, sb, d_nrm, nsb,
+                     n);
   return hipGetLastError();
 }
 

@@ -8,9 +8,11 @@ bool supported_p(int p);
 
 hipError_t launch_discretise(Problem& pb, double* d_ends);
 hipError_t launch_tables(Problem& pb);                 // htab, jtab (per k)
-hipError_t launch_lattice_sums(Problem& pb);           // per (k, theta)
-hipError_t launch_near_blocks(Problem& pb);            // per (k, theta)
-hipError_t launch_rhs(Problem& pb, cd* d_b);
+// lattice sums with phase step beta into the table of batch member `member`
+hipError_t launch_lattice_sums(Problem& pb, int member, double beta);
+// near blocks; phase_free: image phases left out (applied per member by the batched P2P)
+hipError_t launch_near_blocks(Problem& pb, bool phase_free);
+hipError_t launch_rhs(Problem& pb, double theta, cd* d_b);
 hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out);
 hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream_t s);
 
@@ -18,6 +20,8 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);
 // the same with the near field in complex64 (FP32 accumulation)
 hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y);
+// B = pb.B members at once over phase-free near blocks; vectors [B][2E]
+hipError_t apply_operator_batch(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);
 // complex128 near blocks -> complex64 copy
 hipError_t launch_near_to_c64(Problem& pb);
 // upward pass only (P2M and M2M), for tests
@@ -26,7 +30,16 @@ hipError_t apply_upward(Problem& pb, const cd* d_psi);
 // GMRES building blocks (deterministic two-stage reductions)
 hipError_t launch_dots(Problem& pb, const cd* V, long long ldv, int cnt, const cd* w, int n, cd* d_out);
 hipError_t launch_update(Problem& pb, cd* w, const cd* V, long long ldv, int cnt, const cd* d_h, int n);
-hipError_t launch_axpby(Problem& pb, cd* y, cd a, const cd* x, cd b, int n);   // y = a x + b y
+hipError_t launch_axpby(Problem& pb, cd* y, cd a, const cd* x, cd b, long long n);   // y = a x + b y
+// batched forms: B members, member z reads its vectors at base + z * (stride)
+hipError_t launch_dots_b(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int cnt, const cd* w,
+                         long long wsb, int n, cd* d_out, long long osb);
+hipError_t launch_update_b(Problem& pb, int B, cd* w, long long wsb, const cd* V, long long ldv, long long vsb,
+                           int cnt, const cd* d_h, long long hsb, int n);
+hipError_t launch_gemv_acc_b(Problem& pb, int B, cd* x, long long xsb, const cd* V, long long ldv, long long vsb,
+                             int cnt, const cd* d_c, long long csb, int n);
+hipError_t launch_normalize_b(Problem& pb, int B, cd* out, const cd* in, long long sb, const cd* d_nrm,
+                              long long nsb, int n);
 hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n);
 
 }  // namespace pfm

@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("leaf_max", ctypes.c_int), ("mac", ctypes.c_double),
                 ("g_far", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("wood_margin", ctypes.c_double),
-                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -66,8 +67,12 @@ class Stats(ctypes.Structure):
 FP64 = 0
 MIXED = 1
 
+MAX_BATCH = 16
+
 EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_matvec_mixed", "pfm_rhs", "pfm_solve",
            "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
+           "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
+           "pfm_matvec_batch_timed",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
 
 
@@ -87,6 +92,13 @@ def lib():
     L.pfm_set_wave.argtypes = [P, ctypes.c_double, ctypes.c_double]
     L.pfm_matvec.argtypes = [P, vp, vp]
     L.pfm_matvec_mixed.argtypes = [P, vp, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.pfm_set_batch.argtypes = [P, ctypes.c_double, ctypes.c_int, dp]
+    L.pfm_matvec_batch.argtypes = [P, vp, vp]
+    L.pfm_rhs_batch.argtypes = [P, vp]
+    L.pfm_solve_batch.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
+    L.pfm_sweep.argtypes = [P, ctypes.c_int, dp, ctypes.c_int, dp, vp, ctypes.POINTER(Info)]
+    L.pfm_matvec_batch_timed.argtypes = [P, vp, vp, ctypes.c_int, dp, dp]
     L.pfm_rhs.argtypes = [P, vp]
     L.pfm_solve.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
     L.pfm_fields.argtypes = [P, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -135,7 +147,8 @@ class Problem:
                  rho_fiber: float, c_fiber: float, rho_matrix: float, c_matrix: float,
                  eta: float = 0.0, p: int = 16, leaf_max: int = 32, mac: float = 0.65,
                  g_far: int = 4, restart: int = 200, max_iter: int = 4000, tol: float = 1e-8,
-                 wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0):
+                 wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
+                 max_batch: int = 1, use_graph: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -144,7 +157,8 @@ class Problem:
         self._radii = rad
         geo = Geometry(lattice, a, M_L, M_H, n_elem, _dptr(rad), 0.0)
         mat = Material(rho_fiber, c_fiber, rho_matrix, c_matrix, eta)
-        opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol)
+        opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
+                      max_batch, 1 if use_graph else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
@@ -154,6 +168,8 @@ class Problem:
             raise PfmError(code, msg)
         self.n = 2 * M_L * M_H * n_elem
         self.p = p
+        self.max_batch = max(1, max_batch)
+        self.B = 0
         self.set_stream(torch.cuda.current_stream())
 
     @classmethod
@@ -242,6 +258,65 @@ class Problem:
         tot = ctypes.c_double()
         self._check(self._L.pfm_matvec_timed(self._h, _ptr(psi), _ptr(y), reps, _dptr(stage),
                                              ctypes.byref(tot)))
+        names = ["p2m", "m2m", "m2l", "down_l2p", "p2p", "combine"]
+        return dict(zip(names, stage.tolist())), tot.value, y
+
+    # ---- batched sweep: B angles at one frequency, vectors [B, n] ----
+    def set_batch(self, ka: float, thetas):
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(-1))
+        self._check(self._L.pfm_set_batch(self._h, float(ka), th.size, _dptr(th)))
+        self.B = th.size
+
+    def empty_batch(self):
+        import torch
+        return torch.empty((self.B, self.n), dtype=torch.complex128, device="cuda")
+
+    def matvec_batch(self, psi, out=None):
+        if psi.numel() != self.B * self.n:
+            raise ValueError("psi must hold B * n values")
+        y = self.empty_batch() if out is None else out
+        self._check(self._L.pfm_matvec_batch(self._h, _ptr(psi), _ptr(y)))
+        return y
+
+    def rhs_batch(self):
+        b = self.empty_batch()
+        self._check(self._L.pfm_rhs_batch(self._h, _ptr(b)))
+        return b
+
+    @staticmethod
+    def _infos(arr):
+        return [{"status": i.status, "iters": i.iters, "matvecs": i.matvecs, "rel_residual": i.rel_residual,
+                 "t_solve_s": i.t_solve_s} for i in arr]
+
+    def solve_batch(self, b=None, x0=None):
+        x = self.empty_batch() if x0 is None else x0.clone()
+        infos = (Info * self.B)()
+        code = self._L.pfm_solve_batch(self._h, _ptr(b) if b is not None else None, _ptr(x),
+                                       1 if x0 is not None else 0, infos)
+        if code not in (0, 4, 6):
+            self._check(code)
+        return x, self._infos(infos)
+
+    def sweep(self, kas, thetas):
+        """Solve every (ka, theta) pair; returns x [n_ka, B, n] and infos [n_ka][B]."""
+        import torch
+        ka = np.ascontiguousarray(np.asarray(kas, dtype=np.float64).reshape(-1))
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(-1))
+        x = torch.empty((ka.size, th.size, self.n), dtype=torch.complex128, device="cuda")
+        infos = (Info * (ka.size * th.size))()
+        code = self._L.pfm_sweep(self._h, ka.size, _dptr(ka), th.size, _dptr(th), _ptr(x), infos)
+        if code not in (0, 4, 5, 6):
+            self._check(code)
+        self.B = th.size
+        flat = self._infos(infos)
+        return x, [flat[i * th.size:(i + 1) * th.size] for i in range(ka.size)]
+
+    def matvec_batch_timed(self, psi, reps: int = 10):
+        y = self.empty_batch()
+        stage = np.zeros(6)
+        tot = ctypes.c_double()
+        self._check(self._L.pfm_matvec_batch_timed(self._h, _ptr(psi), _ptr(y), reps, _dptr(stage),
+                                                   ctypes.byref(tot)))
         names = ["p2m", "m2m", "m2l", "down_l2p", "p2p", "combine"]
         return dict(zip(names, stage.tolist())), tot.value, y
 

@@ -1,0 +1,168 @@
+"""Batched sweep (several incidence angles at one frequency) against the
+single-angle path and the dense oracle, through the C ABI.
+
+The batch shares phase-free near blocks and applies alpha_b^m per member;
+the single-angle path bakes alpha^m into its blocks, so agreement of the two
+checks the phase bookkeeping as well as the batched kernels.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10863_amd import pfm as m
+    m.lib()
+    return m
+
+
+_WL = {
+    "tiny": W.tiny(),
+    "sq2x2": W.small_square(2, 2, 64, 0.3, 2.0, math.pi / 6),
+    "hex2x2": W.small_square(2, 2, 64, 0.3, 3.0, 0.3, lattice=W.HEXAGON),
+}
+_TH = [0.0, 0.3, -0.5, 1.2, 0.7, -1.1, 0.05, 1.45, -0.2, 0.9, 0.4, -0.8, 1.0, -1.3, 0.15, 0.6]
+
+
+@functools.lru_cache(maxsize=16)
+def _dense(key, ka, th):
+    from oracle import system as sy
+    pb = sy.problem_from_workload(_WL[key], ka, th)
+    A = sy.dense_matrix(pb)
+    return A, sy.rhs(pb)
+
+
+@pytest.mark.parametrize("key,ka,B", [("tiny", 2.0, 1), ("tiny", 2.0, 3), ("sq2x2", 2.0, 4),
+                                      ("hex2x2", 3.0, 8), ("sq2x2", 5.0, 16), ("hex2x2", 1.0, 5)])
+def test_batch_matvec_matches_single_angle(pfm, key, ka, B):
+    wl = _WL[key]
+    th = _TH[:B]
+    _say("batch matvec:", key, "ka", ka, "B", B)
+    pb = pfm.Problem.from_workload(wl, p=24, leaf_max=16, max_batch=16)
+    pb.set_batch(ka, th)
+    psi = torch.tensor(np.stack([W.random_density(pb.n, 40 + b) for b in range(B)]), device="cuda")
+    yb = pb.matvec_batch(psi).cpu().numpy()
+    rhs_b = pb.rhs_batch().cpu().numpy()
+    single = pfm.Problem.from_workload(wl, p=24, leaf_max=16)
+    for b in range(B):
+        single.set_wave(ka, th[b])
+        ys = single.matvec(psi[b].contiguous()).cpu().numpy()
+        err = np.linalg.norm(yb[b] - ys) / np.linalg.norm(ys)
+        rerr = np.linalg.norm(rhs_b[b] - single.rhs().cpu().numpy())
+        assert err < 1e-13, (b, th[b], err)
+        assert rerr < 1e-13 * np.linalg.norm(rhs_b[b]), (b, rerr)
+
+
+def test_batch_matvec_vs_dense_oracle(pfm):
+    th = [0.2, -0.6, 1.1]
+    pb = pfm.Problem.from_workload(_WL["sq2x2"], p=40, leaf_max=16, max_batch=4)
+    pb.set_batch(2.0, th)
+    psi = torch.tensor(np.stack([W.random_density(pb.n, 7 + b) for b in range(3)]), device="cuda")
+    y = pb.matvec_batch(psi).cpu().numpy()
+    for b in range(3):
+        A, _ = _dense("sq2x2", 2.0, th[b])
+        ref = A @ psi[b].cpu().numpy()
+        err = np.linalg.norm(y[b] - ref) / np.linalg.norm(ref)
+        _say("  member", b, "rel err vs dense", err)
+        assert err < 1e-10
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_solve_vs_dense_lu(pfm, use_graph):
+    th = [0.1, 0.5, -0.9, 1.3]
+    pb = pfm.Problem.from_workload(_WL["hex2x2"], p=40, leaf_max=16, max_batch=4, tol=1e-12, restart=60,
+                                   use_graph=use_graph)
+    pb.set_batch(3.0, th)
+    x, infos = pb.solve_batch()
+    x = x.cpu().numpy()
+    _say("batch solve (graph=%s):" % use_graph, infos)
+    for b in range(4):
+        A, B_ = _dense("hex2x2", 3.0, th[b])
+        ref = np.linalg.solve(A, B_)
+        err = np.linalg.norm(x[b] - ref) / np.linalg.norm(ref)
+        assert infos[b]["status"] == 0 and infos[b]["rel_residual"] <= 1e-12
+        assert err < 1e-9, (b, err)
+
+
+def test_graph_replay_matches_eager_apply(pfm):
+    """The captured apply is replayed hundreds of times inside GMRES with
+    eager launches in between; the result must equal the kernel-by-kernel run."""
+    th = [0.0, 0.4, 0.8, 1.2, -0.4, -0.8]
+    res = {}
+    for g in (False, True):
+        pb = pfm.Problem.from_workload(_WL["sq2x2"], p=24, leaf_max=16, max_batch=8, use_graph=g, restart=30)
+        pb.set_batch(4.0, th)
+        x, infos = pb.solve_batch()
+        res[g] = (x.cpu().numpy(), [i["iters"] for i in infos])
+        # a second solve from the same handle (graph replays continue)
+        x2, _ = pb.solve_batch()
+        assert np.array_equal(x2.cpu().numpy(), res[g][0])
+    assert res[True][1] == res[False][1]
+    assert np.array_equal(res[True][0], res[False][0])
+
+
+def test_batch_warm_start_from_solution(pfm):
+    th = [0.3, -0.3]
+    pb = pfm.Problem.from_workload(_WL["sq2x2"], p=24, leaf_max=16, max_batch=2)
+    pb.set_batch(2.5, th)
+    x, _ = pb.solve_batch()
+    x2, infos = pb.solve_batch(x0=x)
+    assert all(i["iters"] == 0 and i["status"] == 0 for i in infos)
+
+
+def test_sweep_matches_single_solves(pfm):
+    wl = W.square_4x4_sweep()
+    kas = [0.8, 3.1]
+    th = wl.theta
+    pb = pfm.Problem.from_workload(wl, max_batch=8, use_graph=True)
+    x, infos = pb.sweep(kas, th)
+    single = pfm.Problem.from_workload(wl)
+    for i, ka in enumerate(kas):
+        for b in (0, 3, 7):
+            inf = infos[i][b]
+            assert inf["status"] == 0, inf
+            single.set_wave(ka, th[b])
+            rb = single.rhs()
+            r = rb - single.matvec(x[i, b].contiguous())
+            res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(rb)).item()
+            xs, si = single.solve()
+            dx = (torch.linalg.vector_norm(xs - x[i, b]) / torch.linalg.vector_norm(xs)).item()
+            _say("sweep ka", ka, "theta", th[b], "iters", inf["iters"], "single", si["iters"],
+                 "residual", res, "diff", dx)
+            assert res < 1.5e-8
+            assert dx < 1e-6
+
+
+def test_sweep_reports_wood_anomalies(pfm):
+    wl = _WL["sq2x2"]
+    H = wl.M_H * wl.a
+    ka_wood = 2 * math.pi / H * wl.a          # k H / (2 pi) = 1 at theta = 0
+    pb = pfm.Problem.from_workload(wl, p=16, leaf_max=16, max_batch=2, wood_margin=1e-3)
+    x, infos = pb.sweep([2.0, ka_wood], [0.0, 0.2])
+    assert all(i["status"] == 0 for i in infos[0])
+    assert all(i["status"] == 5 for i in infos[1])
+    assert float(torch.linalg.vector_norm(x[1])) == 0.0
+
+
+def test_batch_state_errors(pfm):
+    pb = pfm.Problem.from_workload(_WL["tiny"], p=16, leaf_max=32, max_batch=2)
+    with pytest.raises(pfm.PfmError):
+        pb.set_batch(2.0, [0.1, 0.2, 0.3])      # more members than max_batch
+    pb.set_wave(2.0, 0.1)
+    pb.B = 1
+    with pytest.raises(pfm.PfmError):
+        pb.matvec_batch(torch.zeros((1, pb.n), dtype=torch.complex128, device="cuda"))
