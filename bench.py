@@ -110,6 +110,62 @@ def mixed_precision_leg(reps):
     return out
 
 
+def batched_sweep_leg(n_single_ka: int, tune: bool):
+    """Band sweep of the square 4x4 block (8192 unknowns per solve): 64 ka x 8
+    theta = 512 solves at residual 1e-8, batched over theta (one frequency per
+    batch), against the plain FP64 path solving one (ka, theta) at a time
+    (timed on every 8th ka, setup included on both sides)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1910_10863_amd import autotune as at
+    from paper_1910_10863_amd import pfm
+    wl = W.square_4x4_sweep()
+    kas, th = list(wl.ka), list(wl.theta)
+    p, leaf, tuned = wl.p, wl.leaf_max, None
+    if tune:
+        t0 = time.perf_counter()
+        ch = at.autotune(at.geometry_of(wl), max(kas), th, target_err=1e-10, reps=10)
+        tuned = {"leaf_max": ch.leaf_max, "p": ch.p, "err": ch.err, "seconds": time.perf_counter() - t0,
+                 "trials": [[t.leaf_max, t.p, t.err, t.cost_ms] for t in ch.trials]}
+        p, leaf = ch.p, ch.leaf_max
+    out = {"workload": wl.name, "unknowns_per_solve": 2 * wl.M * wl.n_elem, "n_ka": len(kas), "n_theta": len(th),
+           "p": p, "leaf_max": leaf, "autotune": tuned, "tol": 1e-8}
+    pb = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, max_batch=len(th), use_graph=False)
+    pb.sweep(kas[:1], th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, infos = pb.sweep(kas, th)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flat = [i for row in infos for i in row]
+    it = [i["iters"] for i in flat]
+    out["batched"] = {"solves_per_s": len(flat) / dt, "seconds": dt, "n_solves": len(flat),
+                      "failed": int(sum(i["status"] != 0 for i in flat)), "mean_iters": float(np.mean(it)),
+                      "max_iters": int(np.max(it)), "max_rel_residual": float(max(i["rel_residual"] for i in flat))}
+    print(f"batched sweep: {out['batched']}", file=sys.stderr, flush=True)
+    single = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf)
+    sub = kas[::max(1, len(kas) // n_single_ka)][:n_single_ka]
+    single.set_wave(sub[0], th[0])
+    single.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for ka in sub:
+        for t in th:
+            single.set_wave(ka, t)
+            _, inf = single.solve()
+            its.append(inf["iters"])
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    out["plain_fp64"] = {"solves_per_s": len(its) / dt1, "n_solves": len(its), "mean_iters": float(np.mean(its)),
+                         "seconds": dt1}
+    out["speedup"] = out["batched"]["solves_per_s"] / out["plain_fp64"]["solves_per_s"]
+    print(f"plain sweep subset: {out['plain_fp64']}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(wl, ka, theta, n_targets):
     """Dense FP64 oracle: rows of (I - A) assembled and applied for a sample of
     collocation points; scaled to the rate of a full dense apply."""
@@ -147,6 +203,8 @@ def main():
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched band-sweep leg")
+    ap.add_argument("--no-tune", action="store_true", help="batched leg without the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied by a plain device copy before timing, for HBM counter scaling")
@@ -229,6 +287,9 @@ def main():
     mixed = None
     if not args.no_mixed and args.sweep > 0:
         mixed = mixed_precision_leg(max(10, min(args.steps, 50)))
+    batched = None
+    if not args.no_batched and args.sweep > 0:
+        batched = batched_sweep_leg(8, not args.no_tune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -257,6 +318,7 @@ def main():
                      "bytes_per_launch": lb, "launch_ms": leaf_ms},
         "sweep": sweep,
         "mixed_precision": mixed,
+        "batched_sweep": batched,
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_root_offsets", "lattice_q")},

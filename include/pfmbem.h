@@ -138,6 +138,7 @@ typedef struct {
   double near_bytes;           /* bytes of the stored P2P blocks */
   double k, k1, eta, varrho, theta;
   int lattice_q;               /* direct images of the lattice sums, |m| <= q */
+  int p2p_split;               /* column splits per target leaf in the P2P launch */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

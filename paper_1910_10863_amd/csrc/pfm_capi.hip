@@ -78,7 +78,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
-  dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout);
+  dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
   pb.graph = nullptr;
   if (pb.cap) (void)hipStreamDestroy(pb.cap);
@@ -86,12 +86,15 @@ void free_all(Problem& pb) {
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
   dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
-  dfree(pb.d_srule);
+  dfree(pb.d_srule); dfree(pb.d_betas); dfree(pb.d_latpart);
   dfree(pb.d_mpole); dfree(pb.d_local);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
   dfree(pb.d_red); dfree(pb.d_hcol); dfree(pb.d_fields);
   if (pb.h_hcol) (void)hipHostFree(pb.h_hcol);
   pb.h_hcol = nullptr;
+  if (pb.h_hall) (void)hipHostFree(pb.h_hall);
+  pb.h_hall = nullptr;
+  dfree(pb.d_npart); dfree(pb.d_hall);
   if (pb.events) {
     for (int i = 0; i < 16; ++i) (void)hipEventDestroy(pb.ev[i]);
     (void)hipEventDestroy(pb.ev_fork);
@@ -115,13 +118,15 @@ double wood_distance(double k, double H, double th) {
 // graded quadratically towards s = 0, where a near-Wood pole of
 // 1/(1 - e^{+-i beta - mu H}) sits, up to s_max where the Gaussian factor
 // exp(-((q+1)H - |Y|) s^2) has removed the integrand.
+constexpr int LAT_RULE_POINTS = 1024;   // points of the lattice tail rule
+
 void tail_rule(double k, double H, double gap, double xmax, int nu_max, std::vector<double>& rule) {
   double smax = 1.0;
   auto logmag = [&](double s) {
     return -gap * s * s + std::sqrt(k) * xmax * s + nu_max * std::log(1.0 + (2.0 * s * s + k) / k);
   };
   while (logmag(smax) > -60.0) smax *= 1.2;
-  const int npan = 64, ng = 16;
+  const int npan = LAT_RULE_POINTS / 16, ng = 16;
   std::vector<double> x, w;
   gauss_legendre(ng, x, w);
   rule.assign(2 * npan * ng, 0.0);
@@ -297,6 +302,14 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(&pb.d_cols_ptr, cptr));
     CK(upload(&pb.d_col_psi, cpsi));
     CK(upload(&pb.d_col_m, cm));
+    // split the columns of each target leaf when there are too few leaves to
+    // fill the P2P grid, keeping at least 32 columns per split on average
+    int S = 1;
+    if (pb.p2p_grid > 0 && nl > 0 && nl < pb.p2p_grid) S = std::min(8, (pb.p2p_grid + nl - 1) / nl);
+    while (S > 1 && (long long)cpsi.size() / ((long long)nl * S) < 32) --S;
+    pb.p2p_split = S;
+    size_t part = S > 1 ? (size_t)S * std::max(1, opt->max_batch) * 2 * (size_t)pb.E : 1;
+    CK(hipMalloc((void**)&pb.d_p2ppart, part * sizeof(cd)));
   }
   CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
@@ -341,6 +354,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMemset(pb.d_htab, 0, MB * 2 * pb.n_tab * NT * sizeof(cd)));
   pb.d_lat = pb.d_htab + (size_t)n_off_real * NT;
   CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_betas, MB * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_latpart, MB * n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd)));
   (void)n_off;
   {
     // M2L work list: per (channel, cell) the entries (source cell, table row, image),
@@ -403,8 +418,12 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_tmp, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gin, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
-  pb.red_blocks = (int)std::min<size_t>(512, (n + 511) / 512);
-  CK(hipMalloc((void**)&pb.d_red, MB * pb.red_blocks * (2 * pb.opt.restart + 8) * sizeof(cd)));
+  pb.red_blocks = (int)std::min<size_t>(256, (n + 511) / 512);
+  CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 255) / 256) * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_hall, (size_t)pb.opt.restart * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
+  CK(hipHostMalloc((void**)&pb.h_hall, (size_t)pb.opt.restart * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
+  // dot partials [member][vector][block], then (long vectors) the reduced [member][vector]
+  CK(hipMalloc((void**)&pb.d_red, MB * (pb.red_blocks + 1) * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipHostMalloc((void**)&pb.h_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_fields, (size_t)2 * 512 * sizeof(cd)));
@@ -530,7 +549,8 @@ pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
   HIPCHK(pb, hipMemcpyAsync(pb.d_alpha, al.data(), al.size() * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
   st = frequency_tables(pb);
   if (st != PFM_OK) return st;
-  HIPCHK(pb, launch_lattice_sums(pb, 0, pb.beta));
+  HIPCHK(pb, hipMemcpyAsync(pb.d_betas, &pb.beta, sizeof(double), hipMemcpyHostToDevice, pb.stream));
+  HIPCHK(pb, launch_lattice_sums(pb, 1));
   HIPCHK(pb, launch_near_blocks(pb, false));
   if (pb.opt.precision == PFM_MIXED) HIPCHK(pb, launch_near_to_c64(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
@@ -573,7 +593,10 @@ pfm_status pfm_set_batch(pfm_problem* h, double ka, int B, const double* theta) 
   for (int b = 1; b < B; ++b)
     HIPCHK(pb, hipMemcpyAsync(pb.d_htab + b * tab, pb.d_htab, tab * sizeof(cd), hipMemcpyDeviceToDevice,
                               pb.stream));
-  for (int b = 0; b < B; ++b) HIPCHK(pb, launch_lattice_sums(pb, b, pb.k * pb.H * std::sin(theta[b])));
+  std::vector<double> betas(B);
+  for (int b = 0; b < B; ++b) betas[b] = pb.k * pb.H * std::sin(theta[b]);
+  HIPCHK(pb, hipMemcpyAsync(pb.d_betas, betas.data(), B * sizeof(double), hipMemcpyHostToDevice, pb.stream));
+  HIPCHK(pb, launch_lattice_sums(pb, B));
   HIPCHK(pb, launch_near_blocks(pb, true));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   if (pb.opt.use_graph) {
@@ -682,125 +705,6 @@ struct GmresStats {
   double rel = 1.0;              // true relative residual ||b - A x|| / ||b|| of the returned x
 };
 
-// Restarted GMRES(m) with classical Gram-Schmidt applied twice (CGS2) and a
-// true-residual check at every restart.  apply(in, out) is the operator;
-// b is read only; x holds the start vector when use_x0, the iterate on
-// return.  Workspace: pb.d_V, pb.d_w, pb.d_r, pb.d_hcol, pb.h_hcol.
-template <typename Apply>
-pfm_status gmres(Problem& pb, Apply&& apply, const cd* b, cd* x, bool use_x0, double tol, int max_iter,
-                 GmresStats& gs) {
-  const int n = 2 * pb.E;
-  const long long ldv = n;
-  const int m = pb.opt.restart;
-  cd* V = pb.d_V;
-  cd* hc = pb.d_hcol;
-  cd* hh = pb.h_hcol;
-  cd* r = pb.d_r;
-  auto dot_host = [&](const cd* u, const cd* v, cd* out) -> hipError_t {
-    hipError_t e = launch_dots(pb, u, ldv, 1, v, n, hc);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(hh, hc, sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(pb.stream);
-    *out = hh[0];
-    return e;
-  };
-  cd tmp;
-  HIPCHK(pb, dot_host(b, b, &tmp));
-  double bnorm = std::sqrt(std::max(0.0, tmp.x));
-  if (!std::isfinite(bnorm)) return fail(pb, PFM_ENUMERIC, "non-finite right-hand side");
-  if (use_x0) {
-    HIPCHK(pb, apply(x, pb.d_w));
-    ++gs.matvecs;
-    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-    HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
-  } else {
-    HIPCHK(pb, hipMemsetAsync(x, 0, n * sizeof(cd), pb.stream));
-    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-  }
-  HIPCHK(pb, dot_host(r, r, &tmp));
-  double beta = std::sqrt(std::max(0.0, tmp.x));
-  if (bnorm == 0.0) beta = 0.0;
-  gs.rel = bnorm > 0 ? beta / bnorm : 0.0;
-  std::vector<std::complex<double>> Hm((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
-  int iters = 0;
-  while (true) {
-    if (!std::isfinite(beta)) return fail(pb, PFM_ENUMERIC, "non-finite residual norm");
-    if (bnorm == 0.0 || beta / bnorm <= tol) { gs.iters += iters; return PFM_OK; }
-    if (iters >= max_iter) {
-      gs.iters += iters;
-      return fail(pb, PFM_ENOCONV, "GMRES stopped at relative residual " + std::to_string(gs.rel));
-    }
-    HIPCHK(pb, hipMemcpyAsync(V, r, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-    HIPCHK(pb, launch_axpby(pb, V, mkc(0, 0), nullptr, mkc(1.0 / beta, 0), n));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jj = 0;
-    for (int j = 0; j < m; ++j) {
-      cd* vj = V + (size_t)j * n;
-      cd* w = V + (size_t)(j + 1) * n;
-      HIPCHK(pb, apply(vj, w));
-      ++gs.matvecs;
-      HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc));
-      HIPCHK(pb, launch_update(pb, w, V, ldv, j + 1, hc, n));
-      HIPCHK(pb, launch_dots(pb, V, ldv, j + 1, w, n, hc + (j + 1)));
-      HIPCHK(pb, launch_update(pb, w, V, ldv, j + 1, hc + (j + 1), n));
-      HIPCHK(pb, launch_dots(pb, w, ldv, 1, w, n, hc + 2 * (j + 1)));
-      HIPCHK(pb, hipMemcpyAsync(hh, hc, (2 * (j + 1) + 1) * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
-      HIPCHK(pb, hipStreamSynchronize(pb.stream));
-      std::vector<std::complex<double>> col(j + 2);
-      for (int i = 0; i <= j; ++i)
-        col[i] = std::complex<double>(hh[i].x + hh[j + 1 + i].x, hh[i].y + hh[j + 1 + i].y);
-      double hn = std::sqrt(std::max(0.0, hh[2 * (j + 1)].x));
-      if (!std::isfinite(hn)) return fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
-      col[j + 1] = hn;
-      if (hn > 0) HIPCHK(pb, launch_axpby(pb, w, mkc(0, 0), nullptr, mkc(1.0 / hn, 0), n));
-      for (int i = 0; i < j; ++i) {
-        std::complex<double> a = col[i], bb = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * bb;
-        col[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
-      }
-      {
-        std::complex<double> a = col[j], bb = col[j + 1];
-        double t = std::sqrt(std::norm(a) + std::norm(bb));
-        if (std::abs(a) == 0.0) {
-          cs[j] = 0.0;
-          sn[j] = 1.0;
-          col[j] = bb;
-        } else {
-          std::complex<double> ph = a / std::abs(a);
-          cs[j] = std::abs(a) / t;
-          sn[j] = ph * std::conj(bb) / t;
-          col[j] = ph * t;
-        }
-        col[j + 1] = 0.0;
-        g[j + 1] = -std::conj(sn[j]) * g[j];
-        g[j] = cs[j] * g[j];
-      }
-      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = col[i];
-      ++iters;
-      jj = j + 1;
-      double est = std::abs(g[j + 1]) / bnorm;
-      if (est <= 0.7 * tol || iters >= max_iter || hn == 0.0) break;
-    }
-    for (int i = jj - 1; i >= 0; --i) {
-      std::complex<double> sacc = g[i];
-      for (int l = i + 1; l < jj; ++l) sacc -= Hm[(size_t)i * m + l] * y[l];
-      y[i] = sacc / Hm[(size_t)i * m + i];
-    }
-    for (int i = 0; i < jj; ++i) hh[i] = mkc(y[i].real(), y[i].imag());
-    HIPCHK(pb, hipMemcpyAsync(hc, hh, jj * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
-    HIPCHK(pb, launch_gemv_acc(pb, x, V, ldv, jj, hc, n));
-    HIPCHK(pb, apply(x, pb.d_w));
-    ++gs.matvecs;
-    HIPCHK(pb, hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-    HIPCHK(pb, launch_axpby(pb, r, mkc(-1, 0), pb.d_w, mkc(1, 0), n));
-    HIPCHK(pb, dot_host(r, r, &tmp));
-    beta = std::sqrt(std::max(0.0, tmp.x));
-    if (std::isfinite(beta)) gs.rel = beta / bnorm;
-  }
-}
-
 // Batched apply of the current batch: from the captured graph (fixed in/out
 // buffers, copies around it) or launched kernel by kernel.
 hipError_t batch_apply(Problem& pb, const cd* in, cd* out) {
@@ -812,23 +716,28 @@ hipError_t batch_apply(Problem& pb, const cd* in, cd* out) {
   return e;
 }
 
-// GMRES(m) for the B members of a batch in lockstep.  Every iteration is one
-// batched apply and one batched CGS2 step (per-member dot products, updates
-// and norms in the same launches); the small Hessenberg problems and Givens
-// rotations are per member on the host.  A member that meets the tolerance
-// (estimate inside a cycle, confirmed by its true residual at the cycle end)
-// stops taking part in the host work; its device lanes keep running and
-// are discarded.  Basis layout: V[(j * B + b) * n].
-pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector<GmresStats>& gs,
-                       std::vector<pfm_status>& st) {
+// Restarted GMRES(m) for B systems in lockstep (B = 1: a single system).
+// apply(in, out) applies the B operators to B stacked vectors.  Every
+// iteration is one apply and one fused CGS2 Arnoldi step for all members;
+// the Hessenberg columns stay on the device and are read back two
+// iterations at a time while the next two are already queued, so the host
+// never waits on a single iteration.  The small least-squares problems
+// (Givens rotations) are per member on the host.  A member stops taking part
+// when its estimate meets the tolerance; the cycle ends when no member is
+// left (a member may have up to three extra queued iterations, which are
+// discarded).  Every cycle starts with the true residual b - A x, which also
+// decides convergence.  Basis layout: V[(j * B + b) * n].
+template <typename Apply>
+pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x, bool use_x0, double tol,
+                          int max_iter, std::vector<GmresStats>& gs, std::vector<pfm_status>& st) {
   typedef std::complex<double> C;
-  const int B = pb.B;
   const int n = 2 * pb.E;
   const long long nb = (long long)n;
   const long long ldv = (long long)B * n;
   const int m = pb.opt.restart;
-  const long long hs = 2 * m + 8;
-  const double tol = pb.opt.tol;
+  const long long hs = 2 * m + 8;           // d_hcol stride per member
+  const long long hs2 = 2 * m + 4;          // column stride per member in d_hall
+  const int LOOK = 2;                        // iterations per read-back group
   cd* V = pb.d_V;
   cd* W = pb.d_w;
   cd* R = pb.d_r;
@@ -840,16 +749,14 @@ pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector
   std::vector<char> done(B, 0), cyc(B, 0);
   std::vector<int> jj(B, 0);
   std::vector<C> Hm((size_t)B * (m + 1) * m), g((size_t)B * (m + 1)), cs((size_t)B * m), sn((size_t)B * m);
-  auto fetch = [&](int count) -> hipError_t {
-    hipError_t e = hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
-    (void)count;
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(pb.stream);
+  auto sync_norms = [&](const cd* vec, std::vector<double>& out) -> hipError_t {
+    hipError_t e = launch_dots_b(pb, B, vec, nb, nb, 1, vec, nb, n, hc, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pb.stream);
+    for (int i = 0; i < B; ++i) out[i] = std::sqrt(std::max(0.0, hh[i * hs].x));
+    return e;
   };
-  // norms of the right-hand sides
-  HIPCHK(pb, launch_dots_b(pb, B, b, nb, nb, 1, b, nb, n, hc, hs));
-  HIPCHK(pb, fetch(1));
-  for (int i = 0; i < B; ++i) bnorm[i] = std::sqrt(std::max(0.0, hh[i * hs].x));
+  HIPCHK(pb, sync_norms(b, bnorm));
   if (!use_x0) HIPCHK(pb, hipMemsetAsync(x, 0, (size_t)B * n * sizeof(cd), pb.stream));
   bool first = true;
   while (true) {
@@ -857,19 +764,17 @@ pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector
     if (first && !use_x0) {
       HIPCHK(pb, hipMemcpyAsync(R, b, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
     } else {
-      HIPCHK(pb, batch_apply(pb, x, W));
+      HIPCHK(pb, apply(x, W));
       for (int i = 0; i < B; ++i)
         if (!done[i]) ++gs[i].matvecs;
       HIPCHK(pb, hipMemcpyAsync(R, b, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
       HIPCHK(pb, launch_axpby(pb, R, mkc(-1, 0), W, mkc(1, 0), (long long)B * n));
     }
     first = false;
-    HIPCHK(pb, launch_dots_b(pb, B, R, nb, nb, 1, R, nb, n, hc, hs));
-    HIPCHK(pb, fetch(1));
+    HIPCHK(pb, sync_norms(R, beta));
     bool all_done = true;
     for (int i = 0; i < B; ++i) {
       if (done[i]) continue;
-      beta[i] = std::sqrt(std::max(0.0, hh[i * hs].x));
       if (!std::isfinite(beta[i])) {
         st[i] = fail(pb, PFM_ENUMERIC, "non-finite residual norm");
         done[i] = 1;
@@ -880,7 +785,7 @@ pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector
         done[i] = 1;
         continue;
       }
-      if (gs[i].iters >= pb.opt.max_iter) {
+      if (gs[i].iters >= max_iter) {
         st[i] = fail(pb, PFM_ENOCONV, "GMRES stopped at relative residual " + std::to_string(gs[i].rel));
         done[i] = 1;
         continue;
@@ -888,72 +793,102 @@ pfm_status gmres_batch(Problem& pb, const cd* b, cd* x, bool use_x0, std::vector
       all_done = false;
     }
     if (all_done) return PFM_OK;
-    // V_0 = R / ||R|| per member
+    // V_0 = R / ||R|| per member (the squared norms are still in d_hcol)
     HIPCHK(pb, launch_normalize_b(pb, B, V, R, nb, hc, hs, n));
+    int budget = 0;      // iterations any member may still take
     for (int i = 0; i < B; ++i) {
       cyc[i] = !done[i];
       jj[i] = 0;
       for (int r = 0; r <= m; ++r) g[(size_t)i * (m + 1) + r] = 0.0;
       g[(size_t)i * (m + 1)] = beta[i];
+      if (cyc[i]) budget = std::max(budget, max_iter - gs[i].iters);
     }
-    for (int j = 0; j < m; ++j) {
+    const int jmax = std::min(m, budget);
+    auto enqueue = [&](int j) -> hipError_t {
       cd* Vj = V + (size_t)j * ldv;
       cd* Wj = V + (size_t)(j + 1) * ldv;
-      HIPCHK(pb, batch_apply(pb, Vj, Wj));
-      for (int i = 0; i < B; ++i)
-        if (cyc[i]) ++gs[i].matvecs;
-      HIPCHK(pb, launch_dots_b(pb, B, V, ldv, nb, j + 1, Wj, nb, n, hc, hs));
-      HIPCHK(pb, launch_update_b(pb, B, Wj, nb, V, ldv, nb, j + 1, hc, hs, n));
-      HIPCHK(pb, launch_dots_b(pb, B, V, ldv, nb, j + 1, Wj, nb, n, hc + (j + 1), hs));
-      HIPCHK(pb, launch_update_b(pb, B, Wj, nb, V, ldv, nb, j + 1, hc + (j + 1), hs, n));
-      HIPCHK(pb, launch_dots_b(pb, B, Wj, nb, nb, 1, Wj, nb, n, hc + 2 * (j + 1), hs));
-      HIPCHK(pb, launch_normalize_b(pb, B, Wj, Wj, nb, hc + 2 * (j + 1), hs, n));
-      HIPCHK(pb, fetch(2 * j + 3));
-      bool any = false;
-      for (int i = 0; i < B; ++i) {
-        if (!cyc[i]) continue;
-        const cd* hv = hh + i * hs;
-        std::vector<C> col(j + 2);
-        for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);
-        double hn = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
-        if (!std::isfinite(hn)) {
-          st[i] = fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
-          cyc[i] = 0;
-          done[i] = 1;
-          continue;
-        }
-        col[j + 1] = hn;
-        C* csi = &cs[(size_t)i * m];
-        C* sni = &sn[(size_t)i * m];
-        C* gi = &g[(size_t)i * (m + 1)];
-        for (int r = 0; r < j; ++r) {
-          C a = col[r], bb = col[r + 1];
-          col[r] = csi[r] * a + sni[r] * bb;
-          col[r + 1] = -std::conj(sni[r]) * a + csi[r] * bb;
-        }
-        C a = col[j], bb = col[j + 1];
-        double t = std::sqrt(std::norm(a) + std::norm(bb));
-        if (std::abs(a) == 0.0) {
-          csi[j] = 0.0;
-          sni[j] = 1.0;
-          col[j] = bb;
-        } else {
-          C ph = a / std::abs(a);
-          csi[j] = std::abs(a) / t;
-          sni[j] = ph * std::conj(bb) / t;
-          col[j] = ph * t;
-        }
-        gi[j + 1] = -std::conj(sni[j]) * gi[j];
-        gi[j] = csi[j] * gi[j];
-        for (int r = 0; r <= j; ++r) Hm[((size_t)i * (m + 1) + r) * m + j] = col[r];
-        ++gs[i].iters;
-        jj[i] = j + 1;
-        double est = std::abs(gi[j + 1]) / bnorm[i];
-        if (est <= 0.7 * tol || gs[i].iters >= pb.opt.max_iter || hn == 0.0) cyc[i] = 0;
-        any = any || cyc[i];
+      hipError_t e = apply(Vj, Wj);
+      if (e != hipSuccess) return e;
+      return launch_arnoldi_step(pb, B, V, ldv, nb, j, Wj, nb, n, pb.d_hall + (size_t)j * B * hs2, hs2);
+    };
+    auto readback = [&](int j0, int j1) -> hipError_t {
+      return hipMemcpyAsync(pb.h_hall + (size_t)j0 * B * hs2, pb.d_hall + (size_t)j0 * B * hs2,
+                            (size_t)(j1 - j0) * B * hs2 * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
+    };
+    int j_enq = 0, j_proc = 0;
+    int grp = 0;
+    hipEvent_t gev[2] = {pb.ev[14], pb.ev[15]};
+    int gbeg[2] = {0, 0}, gend[2] = {0, 0};
+    // queue the first group
+    for (; j_enq < std::min(jmax, LOOK); ++j_enq) HIPCHK(pb, enqueue(j_enq));
+    HIPCHK(pb, readback(0, j_enq));
+    HIPCHK(pb, hipEventRecord(gev[0], pb.stream));
+    gbeg[0] = 0;
+    gend[0] = j_enq;
+    bool any = true;
+    while (j_proc < jmax && any) {
+      // queue the next group before waiting for the current one
+      int nxt = grp ^ 1;
+      gbeg[nxt] = gend[nxt] = j_enq;
+      if (j_enq < jmax) {
+        int stop = std::min(jmax, j_enq + LOOK);
+        for (; j_enq < stop; ++j_enq) HIPCHK(pb, enqueue(j_enq));
+        HIPCHK(pb, readback(gbeg[nxt], j_enq));
+        HIPCHK(pb, hipEventRecord(gev[nxt], pb.stream));
+        gend[nxt] = j_enq;
       }
-      if (!any) break;
+      HIPCHK(pb, hipEventSynchronize(gev[grp]));
+      for (int j = gbeg[grp]; j < gend[grp] && any; ++j) {
+        any = false;
+        for (int i = 0; i < B; ++i) {
+          if (!cyc[i]) continue;
+          const cd* hv = pb.h_hall + ((size_t)j * B + i) * hs2;
+          std::vector<C> col(j + 2);
+          for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);
+          double hn = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+          if (!std::isfinite(hn)) {
+            st[i] = fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
+            cyc[i] = 0;
+            done[i] = 1;
+            continue;
+          }
+          col[j + 1] = hn;
+          C* csi = &cs[(size_t)i * m];
+          C* sni = &sn[(size_t)i * m];
+          C* gi = &g[(size_t)i * (m + 1)];
+          for (int r = 0; r < j; ++r) {
+            C a = col[r], bb = col[r + 1];
+            col[r] = csi[r] * a + sni[r] * bb;
+            col[r + 1] = -std::conj(sni[r]) * a + csi[r] * bb;
+          }
+          C a = col[j], bb = col[j + 1];
+          double t = std::sqrt(std::norm(a) + std::norm(bb));
+          if (std::abs(a) == 0.0) {
+            csi[j] = 0.0;
+            sni[j] = 1.0;
+            col[j] = bb;
+          } else {
+            C ph = a / std::abs(a);
+            csi[j] = std::abs(a) / t;
+            sni[j] = ph * std::conj(bb) / t;
+            col[j] = ph * t;
+          }
+          gi[j + 1] = -std::conj(sni[j]) * gi[j];
+          gi[j] = csi[j] * gi[j];
+          for (int r = 0; r <= j; ++r) Hm[((size_t)i * (m + 1) + r) * m + j] = col[r];
+          ++gs[i].iters;
+          ++gs[i].matvecs;
+          jj[i] = j + 1;
+          double est = std::abs(gi[j + 1]) / bnorm[i];
+          if (est <= 0.7 * tol || gs[i].iters >= max_iter || hn == 0.0) cyc[i] = 0;
+          any = any || cyc[i];
+        }
+        j_proc = j + 1;
+      }
+      grp ^= 1;
     }
+    // drain what is still queued before the basis is used
+    HIPCHK(pb, hipStreamSynchronize(pb.stream));
     // x_b += V_b y_b, y_b from the triangular systems (zeros past a member's jj)
     int cnt = 0;
     for (int i = 0; i < B; ++i) {
@@ -1026,11 +961,13 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
       // inner solve to the inner tolerance relative to ||r||, but never below
       // what the outer tolerance needs
       double tin = std::max(pb.opt.inner_tol, 0.5 * pb.opt.tol * bnorm / rnorm);
-      GmresStats gi;
-      pfm_status si = gmres(pb, apply32, rr, d, false, tin, pb.opt.max_iter - gs.iters, gi);
-      gs.iters += gi.iters;
-      gs.matvecs += gi.matvecs;
-      if (si != PFM_OK && si != PFM_ENOCONV) { st = si; break; }
+      std::vector<GmresStats> gi;
+      std::vector<pfm_status> sti;
+      pfm_status si = gmres_lockstep(pb, 1, apply32, rr, d, false, tin, pb.opt.max_iter - gs.iters, gi, sti);
+      gs.iters += gi[0].iters;
+      gs.matvecs += gi[0].matvecs;
+      if (si != PFM_OK) { st = si; break; }
+      if (sti[0] != PFM_OK && sti[0] != PFM_ENOCONV) { st = sti[0]; break; }
       HIPCHK(pb, launch_axpby(pb, x, mkc(1, 0), d, mkc(1, 0), n));
       HIPCHK(pb, apply64(x, pb.d_w));
       ++gs.matvecs;
@@ -1044,7 +981,11 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
       ++outer;
     }
   } else {
-    st = gmres(pb, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs);
+    std::vector<GmresStats> g1;
+    std::vector<pfm_status> s1;
+    st = gmres_lockstep(pb, 1, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1);
+    gs = g1[0];
+    if (st == PFM_OK) st = s1[0];
   }
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   auto t1 = std::chrono::steady_clock::now();
@@ -1072,7 +1013,8 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
     for (int i = 0; i < pb.B; ++i) HIPCHK(pb, launch_rhs(pb, pb.thetas[i], b + i * n));
   std::vector<GmresStats> gs;
   std::vector<pfm_status> st;
-  pfm_status s = gmres_batch(pb, b, (cd*)d_x_io, use_x0 != 0, gs, st);
+  auto apply = [&](const cd* in, cd* out) { return batch_apply(pb, in, out); };
+  pfm_status s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st);
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   pfm_status worst = s;
@@ -1190,6 +1132,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->varrho = pb.varrho;
   st->theta = pb.theta;
   st->lattice_q = pb.lattice_q;
+  st->p2p_split = pb.p2p_split;
   return PFM_OK;
 }
 

@@ -111,7 +111,9 @@ struct Problem {
   int *d_cc_ptr = nullptr;              // [2*n_cells+1]: chunks of (channel, cell)
   cd *d_part = nullptr;                 // [n_chunks][2p+1] partial local expansions
   int n_chunks = 0;
-  int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per leaf)
+  int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
+  int p2p_split = 1;                    // column splits per target leaf
+  cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table
   int *d_up_cells = nullptr, *d_up_ptr = nullptr, *d_up_src = nullptr, *d_up_off = nullptr;
@@ -123,6 +125,8 @@ struct Problem {
   cd *d_alpha_one = nullptr;            // ones: phase-free near blocks
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights
   int n_srule = 0;
+  double *d_betas = nullptr;            // k H sin(theta) per batch member
+  cd *d_latpart = nullptr;              // tail partial sums [member][offset][rule block][4p+1]
   // expansions
   cd *d_mpole = nullptr;                // [n_cells][2][2p+1]
   cd *d_local = nullptr;                // [n_cells][2][2p+1]
@@ -130,6 +134,8 @@ struct Problem {
   cd *d_V = nullptr;                    // [restart+1][n]
   cd *d_w = nullptr, *d_r = nullptr, *d_b = nullptr, *d_tmp = nullptr;
   cd *d_red = nullptr;                  // reduction partials
+  double *d_npart = nullptr;            // per-block squared norms [member][block]
+  cd *d_hall = nullptr, *h_hall = nullptr;   // Arnoldi columns [restart][member][2 restart + 4]
   cd *d_hcol = nullptr;                 // column of dots
   cd *h_hcol = nullptr;                 // pinned host copy
   int red_blocks = 0;

@@ -142,7 +142,7 @@ __device__ inline void far_rule(double kap, double x, double y, double nux, doub
   }
 }
 
-__global__ void __launch_bounds__(256) k_near_blocks(NearArgs A) {
+__global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
   int q = blockIdx.x;
   int D = A.leaves[A.near_tgt[q]];
   int C = A.near_src[q];
@@ -153,7 +153,8 @@ __global__ void __launch_bounds__(256) k_near_blocks(NearArgs A) {
   cd ph = A.alpha[m - A.m_min];
   cd c = mkc(0.0, -2.0 / (A.eta * (1.0 + A.varrho)));     // 2 / (i eta (1 + varrho))
   cd mieta = mkc(0.0, -A.eta);                              // -i eta
-  for (int rc = threadIdx.x; rc < rows * cols; rc += blockDim.x) {
+  // the pair's entries are spread over the y axis of the grid, one per thread
+  for (int rc = blockIdx.y * blockDim.x + threadIdx.x; rc < rows * cols; rc += gridDim.y * blockDim.x) {
     int col = rc / rows, row = rc - col * rows;
     int ea = A.elem_of[db + row], eb = A.elem_of[cb + col];
     double x = A.mx[ea], y = A.my[ea];
@@ -218,7 +219,8 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   A.m_min = hp.m_min;
   A.n_entries = hp.n_near_entries;
   A.out = pb.d_near;
-  hipLaunchKernelGGL(k_near_blocks, dim3(npairs), dim3(256), 0, pb.stream, A);
+  int lm = pb.opt.leaf_max;
+  hipLaunchKernelGGL(k_near_blocks, dim3(npairs, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
   return hipGetLastError();
 }
 
@@ -281,14 +283,109 @@ __global__ void k_jtab(int n_off, const double* __restrict__ off, double k, doub
 // (t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik, dt/mu = 2 ds / sqrt(s^2 - 2ik)),
 // one workgroup per fibre offset, one thread per order nu.
 // ---------------------------------------------------------------------------
-__global__ void k_lattice_sums(int P, int n_roff, const double* __restrict__ roff,
-                               const int* __restrict__ mrange, double k, double H,
-                               double beta, int q, const double* __restrict__ rule,
-                               int n_rule, cd* out) {
-  int o = blockIdx.x;
+// Tails of the lattice sums (both sides |m| > q), from the corrected contour
+// integrals: for the rule point s with t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik,
+//   up:   exp(i X t + mu Y + (q+1)(i beta - mu H)) / (1 - e^{i beta - mu H}),
+//   down: exp(i X t - mu Y - (q+1)(i beta + mu H)) / (1 - e^{-i beta - mu H}),
+// times 2 w / sqrt(s^2 - 2ik) and the order factors (-i(t +- mu)/k)^nu
+// (nu >= 0) or (i(t -+ mu)/k)^|nu| (nu < 0).  One thread per rule point
+// carries all orders by running products; each order is summed over the
+// wavefront by cross-lane sums and over the block in LDS.  Partial sums per
+// (member, offset, rule block) are added by k_lattice_direct.
+// sum of a complex value over the 64 lanes of a wavefront (every lane gets it)
+__device__ __forceinline__ cd wave_sum(cd v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+constexpr int LAT_MAX_NT = 4 * 40 + 1;
+
+__global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const double* __restrict__ roff,
+                                                       double k, double H, const double* __restrict__ betas,
+                                                       int q, const double* __restrict__ rule, int n_rule,
+                                                       cd* __restrict__ partial) {
+  __shared__ cd sred[4][LAT_MAX_NT];
+  const int NT = 4 * P + 1;
+  const int o = blockIdx.x, rb = blockIdx.y, mb = blockIdx.z;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double beta = betas[mb];
+  const double ox = roff[2 * o], oy = roff[2 * o + 1];
+  const double invk = 1.0 / k;
+  const int i = rb * 256 + threadIdx.x;
+  // running products per branch: up/down x positive/negative orders
+  cd aup[2], adn[2], bup[2], bdn[2];      // a*: orders >= 0, b*: orders < 0
+  cd zup[2], zdn[2], yup[2], ydn[2];
+  for (int br = 0; br < 2; ++br) {
+    aup[br] = adn[br] = bup[br] = bdn[br] = mkc(0, 0);
+    zup[br] = zdn[br] = yup[br] = ydn[br] = mkc(0, 0);
+  }
+  if (i < n_rule) {
+    double s = rule[i], wgt = rule[n_rule + i];
+    cd root = csqrt(mkc(s * s, -2.0 * k));
+    cd mu = mkc(s * s, -k);
+    cd jac = cdiv(mkc(2.0 * wgt, 0.0), root);
+    cd emh = cexp(mkc(-mu.x * H, -mu.y * H));                  // e^{-mu H}
+    cd eib = mkc(cos(beta), sin(beta));
+    cd den_up = csub(mkc(1, 0), cmul(eib, emh));
+    cd den_dn = csub(mkc(1, 0), cmul(cconj(eib), emh));
+    for (int br = 0; br < 2; ++br) {
+      cd tt = cscale(root, br ? -s : s);
+      cd itx = cmul_i(cscale(tt, ox));
+      cd ex_up = cadd(itx, cadd(cscale(mu, oy), cscale(csub(mkc(0, beta), cscale(mu, H)), q + 1.0)));
+      cd ex_dn = cadd(itx, csub(cscale(mu, -oy), cscale(cadd(mkc(0, beta), cscale(mu, H)), q + 1.0)));
+      cd fu = cmul(jac, cdiv(cexp(ex_up), den_up));
+      cd fd = cmul(jac, cdiv(cexp(ex_dn), den_dn));
+      cd tpm = cadd(tt, mu), tmm = csub(tt, mu);
+      aup[br] = bup[br] = fu;
+      adn[br] = bdn[br] = fd;
+      zup[br] = cscale(mkc(tpm.y, -tpm.x), invk);     // -i (t + mu) / k
+      zdn[br] = cscale(mkc(tmm.y, -tmm.x), invk);     // -i (t - mu) / k
+      yup[br] = cscale(mkc(-tmm.y, tmm.x), invk);     //  i (t - mu) / k
+      ydn[br] = cscale(mkc(-tpm.y, tpm.x), invk);     //  i (t + mu) / k
+    }
+  }
+  for (int nu = 0; nu <= 2 * P; ++nu) {
+    cd vp = cadd(cadd(aup[0], adn[0]), cadd(aup[1], adn[1]));
+    vp = wave_sum(vp);
+    if (lane == 0) sred[w][2 * P + nu] = vp;
+    if (nu > 0) {
+      cd vn = cadd(cadd(bup[0], bdn[0]), cadd(bup[1], bdn[1]));
+      vn = wave_sum(vn);
+      if (lane == 0) sred[w][2 * P - nu] = vn;
+    }
+    for (int br = 0; br < 2; ++br) {
+      aup[br] = cmul(aup[br], zup[br]);
+      adn[br] = cmul(adn[br], zdn[br]);
+      bup[br] = cmul(bup[br], yup[br]);
+      bdn[br] = cmul(bdn[br], ydn[br]);
+    }
+  }
+  __syncthreads();
+  cd* out = partial + (((size_t)mb * n_roff + o) * gridDim.y + rb) * NT;
+  for (int t = threadIdx.x; t < NT; t += 256)
+    out[t] = cadd(cadd(sred[0][t], sred[1][t]), cadd(sred[2][t], sred[3][t]));
+}
+
+// Direct part of the lattice sums, the images |m| <= q outside the explicit
+// range [m_lo, m_hi] of the offset:
+//   S_nu(o) = sum_m alpha^m Hp_nu(k (o - m H e_y)),  Hp_nu(v) = H_|nu|(|v|) e^{i nu arg v}
+//             (times (-1)^nu for nu < 0),
+// plus the tails of k_lattice_tails times 1/(i pi).  One workgroup per
+// (offset, member), one thread per order.
+__global__ void k_lattice_direct(int P, int n_roff, const double* __restrict__ roff,
+                                 const int* __restrict__ mrange, double k, double H,
+                                 const double* __restrict__ betas, int q, int n_rblk,
+                                 const cd* __restrict__ partial, cd* out, long long out_stride) {
+  int o = blockIdx.x, mb = blockIdx.y;
   int NT = 4 * P + 1;
+  double beta = betas[mb];
   double ox = roff[2 * o], oy = roff[2 * o + 1];
   int mlo = mrange[2 * o], mhi = mrange[2 * o + 1];
+  const cd* part = partial + ((size_t)mb * n_roff + o) * n_rblk * NT;
   for (int t = threadIdx.x; t < NT; t += blockDim.x) {
     int nu = t - 2 * P;
     int an = nu < 0 ? -nu : nu;
@@ -319,54 +416,25 @@ __global__ void k_lattice_sums(int P, int n_roff, const double* __restrict__ rof
       sincos(m * beta, &sb, &cb);
       acc = cfma(mkc(cb, sb), v, acc);
     }
-    // tails
     cd tail = mkc(0, 0);
-    cd eib = mkc(cos(beta), sin(beta));
-    cd emib = cconj(eib);
-    double invk = 1.0 / k;
-    for (int i = 0; i < n_rule; ++i) {
-      double s = rule[i], w = rule[n_rule + i];
-      cd root = csqrt(mkc(s * s, -2.0 * k));
-      cd mu = mkc(s * s, -k);
-      cd jac = cdiv(mkc(2.0 * w, 0.0), root);
-      cd emh = cexp(mkc(-mu.x * H, -mu.y * H));          // e^{-mu H}
-      cd den_up = csub(mkc(1, 0), cmul(eib, emh));
-      cd den_dn = csub(mkc(1, 0), cmul(emib, emh));
-      for (int br = 0; br < 2; ++br) {
-        cd tt = cmul(root, mkc(br ? -s : s, 0.0));
-        cd itx = cmul_i(cscale(tt, ox));                  // i X t
-        // up tail: exp(i X t + mu Y + (q+1)(i beta - mu H)) / den_up
-        cd ex_up = cadd(itx, cadd(cscale(mu, oy), cscale(csub(mkc(0, beta), cscale(mu, H)), q + 1.0)));
-        cd ex_dn = cadd(itx, csub(cscale(mu, -oy), cscale(cadd(mkc(0, beta), cscale(mu, H)), q + 1.0)));
-        cd fu = cdiv(cexp(ex_up), den_up);
-        cd fd = cdiv(cexp(ex_dn), den_dn);
-        cd tpm = cadd(tt, mu), tmm = csub(tt, mu);
-        cd fac_up, fac_dn;
-        if (nu >= 0) {
-          // (-i (t +- mu) / k)^nu
-          fac_up = cpowi(cscale(mkc(tpm.y, -tpm.x), invk), an);
-          fac_dn = cpowi(cscale(mkc(tmm.y, -tmm.x), invk), an);
-        } else {
-          // (i (t -+ mu) / k)^|nu|
-          fac_up = cpowi(cscale(mkc(-tmm.y, tmm.x), invk), an);
-          fac_dn = cpowi(cscale(mkc(-tpm.y, tpm.x), invk), an);
-        }
-        tail = cadd(tail, cmul(jac, cadd(cmul(fu, fac_up), cmul(fd, fac_dn))));
-      }
-    }
+    for (int rb = 0; rb < n_rblk; ++rb) tail = cadd(tail, part[(size_t)rb * NT + t]);
     // 1/(i pi) * tail
     tail = mkc(tail.y / PI, -tail.x / PI);
-    out[(size_t)o * NT + t] = cadd(acc, tail);
+    out[mb * out_stride + (size_t)o * NT + t] = cadd(acc, tail);
   }
 }
 
-hipError_t launch_lattice_sums(Problem& pb, int member, double beta) {
+hipError_t launch_lattice_sums(Problem& pb, int B) {
   int n_roff = (int)pb.hp.root_off_xy.size() / 2;
+  if (n_roff == 0) return hipSuccess;
   const int NT = 4 * pb.opt.p + 1;
-  cd* out = pb.d_lat + (size_t)member * 2 * pb.n_tab * NT;
-  hipLaunchKernelGGL(k_lattice_sums, dim3(n_roff), dim3(128), 0, pb.stream, pb.opt.p, n_roff,
-                     pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, beta, pb.lattice_q,
-                     pb.d_srule, pb.n_srule, out);
+  int n_rblk = (pb.n_srule + 255) / 256;
+  hipLaunchKernelGGL(k_lattice_tails, dim3(n_roff, n_rblk, B), dim3(256), 0, pb.stream, pb.opt.p, n_roff,
+                     pb.d_root_off_xy, pb.k, pb.H, pb.d_betas, pb.lattice_q, pb.d_srule, pb.n_srule,
+                     pb.d_latpart);
+  hipLaunchKernelGGL(k_lattice_direct, dim3(n_roff, B), dim3(128), 0, pb.stream, pb.opt.p, n_roff,
+                     pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, pb.d_betas, pb.lattice_q, n_rblk,
+                     pb.d_latpart, pb.d_lat, 2LL * pb.n_tab * NT);
   return hipGetLastError();
 }
 
@@ -823,10 +891,20 @@ __global__ void __launch_bounds__(128) k_down(
   }
 }
 
-// y += far (the join of the near and far parts of the rows)
-__global__ void k_combine(long long n, const cd* __restrict__ far, cd* __restrict__ y) {
+// The join of the near and far parts of the rows: y += far when the P2P
+// wrote y = psi + near itself (S = 1), else y = psi + far + sum of the S
+// partial near parts, added in split order.
+__global__ void k_combine(long long n, const cd* __restrict__ far, const cd* __restrict__ psi,
+                          const cd* __restrict__ part, int S, cd* __restrict__ y) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = cadd(y[i], far[i]);
+  if (i >= n) return;
+  if (S == 1) {
+    y[i] = cadd(y[i], far[i]);
+    return;
+  }
+  cd acc = part[i];
+  for (int s = 1; s < S; ++s) acc = cadd(acc, part[s * n + i]);
+  y[i] = cadd(cadd(psi[i], acc), far[i]);
 }
 
 // P2P with the stored near blocks plus the identity of (I - A):
@@ -858,20 +936,25 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
     const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
     const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
     const int* __restrict__ col_psi, const C* __restrict__ blocks, const cd* __restrict__ psi,
-    cd* __restrict__ y, int n_leaves) {
+    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part, long long vec) {
   __shared__ C sp[P2P_SEG][2];
   __shared__ C r1[P2P_WAVES][64], r2[P2P_WAVES][64];
-  for (int li = blockIdx.x; li < n_leaves; li += gridDim.x) {
+  // work item = (target leaf, column split); with S > 1 the splits write
+  // partial rows that k_combine adds in a fixed order
+  for (int item = blockIdx.x; item < n_leaves * S; item += gridDim.x) {
+    int li = item / S, sp_i = item - li * S;
     int D = leaves[li];
     int db = ebeg[D], rows = eend[D] - db;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     C a1 = p2p_cvt<C>(mkc(0, 0)), a2 = a1;
     int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    int chunk = (ncol + S - 1) / S;
+    int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
     const C* bl = blocks + 4 * near_blk[near_ptr[li]];
     const unsigned cstride = 4u * (unsigned)rows;
     bool act = lane < rows;
-    for (int seg = 0; seg < ncol; seg += P2P_SEG) {
-      int nseg = min(P2P_SEG, ncol - seg);
+    for (int seg = c_lo; seg < c_hi; seg += P2P_SEG) {
+      int nseg = min(P2P_SEG, c_hi - seg);
       for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
         int pi = col_psi[k0 + seg + i];
         sp[i][0] = p2p_cvt<C>(psi[pi]);
@@ -903,8 +986,14 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
         s2 = cadd(s2, p2p_wide(r2[v][lane]));
       }
       int pi = psi_idx[db + lane];
-      y[pi] = cadd(psi[pi], s1);
-      y[pi + N] = cadd(psi[pi + N], s2);
+      if (S == 1) {
+        y[pi] = cadd(psi[pi], s1);
+        y[pi + N] = cadd(psi[pi + N], s2);
+      } else {
+        cd* pp = part + (size_t)sp_i * vec;
+        pp[pi] = s1;
+        pp[pi + N] = s2;
+      }
     }
     __syncthreads();
   }
@@ -923,11 +1012,14 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
     const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
     const int* __restrict__ col_psi, const int* __restrict__ col_m, const cd* __restrict__ alpha,
     int alpha_stride, int m_min, int B, long long stride, const C* __restrict__ blocks,
-    const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves) {
+    const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part) {
   constexpr int SEG = P2PBatchSeg<NB>::value;
   __shared__ C sp[SEG][NB][2];
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
-  for (int li = blockIdx.x; li < n_leaves; li += gridDim.x) {
+  // work item = (target leaf, column split); with S > 1 the splits write
+  // partial rows [split][member][vector] that k_combine adds in a fixed order
+  for (int item = blockIdx.x; item < n_leaves * S; item += gridDim.x) {
+    int li = item / S, sp_i = item - li * S;
     int D = leaves[li];
     int db = ebeg[D], rows = eend[D] - db;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -935,11 +1027,13 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
 #pragma unroll
     for (int b = 0; b < NB; ++b) a1[b] = a2[b] = p2p_cvt<C>(mkc(0, 0));
     int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    int chunk = (ncol + S - 1) / S;
+    int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
     const C* bl = blocks + 4 * near_blk[near_ptr[li]];
     const unsigned cstride = 4u * (unsigned)rows;
     bool act = lane < rows;
-    for (int seg = 0; seg < ncol; seg += SEG) {
-      int nseg = min(SEG, ncol - seg);
+    for (int seg = c_lo; seg < c_hi; seg += SEG) {
+      int nseg = min(SEG, c_hi - seg);
       for (int i = threadIdx.x; i < nseg * NB; i += 64 * P2P_WAVES) {
         int col = i / NB, b = i - col * NB;
         cd v0 = mkc(0, 0), v1 = mkc(0, 0);
@@ -983,10 +1077,16 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
           s2 = cadd(s2, r2[v][lane]);
         }
         int pi = psi_idx[db + lane];
-        const cd* pb_ = psi + b * stride;
-        cd* yb = y + b * stride;
-        yb[pi] = cadd(pb_[pi], s1);
-        yb[pi + N] = cadd(pb_[pi + N], s2);
+        if (S == 1) {
+          const cd* pb_ = psi + b * stride;
+          cd* yb = y + b * stride;
+          yb[pi] = cadd(pb_[pi], s1);
+          yb[pi + N] = cadd(pb_[pi + N], s2);
+        } else {
+          cd* pp = part + ((size_t)sp_i * B + b) * stride;
+          pp[pi] = s1;
+          pp[pi + N] = s2;
+        }
       }
       __syncthreads();
     }
@@ -1070,7 +1170,7 @@ static void launch_p2p_batch(Problem& pb, int grid, const C* blocks, const cd* d
   hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves,
                      pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
                      pb.d_col_psi, pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, d_psi,
-                     d_y, (int)pb.hp.leaves.size());
+                     d_y, (int)pb.hp.leaves.size(), pb.p2p_split, pb.d_p2ppart);
 }
 
 // y = (I - A) psi.  Without stage events the FMM chain runs on the side
@@ -1089,13 +1189,14 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
     (void)hipEventRecord(pb.ev_fork, pb.stream);
     (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
   }
-  fmm_chain<P>(pb, d_psi, fs, ev, false, nb);
-  if (!ev) (void)hipEventRecord(pb.ev_join, pb.side);
-  int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, n_leaves) : n_leaves;
+  if (ev) fmm_chain<P>(pb, d_psi, fs, ev, false, nb);
+  // the P2P stream is queued first so that it starts while the chain is being queued
+  int items = n_leaves * pb.p2p_split;
+  int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
   if (B == 0) {
     hipLaunchKernelGGL(k_p2p<C>, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
                        pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                       pb.d_col_psi, blocks, d_psi, d_y, n_leaves);
+                       pb.d_col_psi, blocks, d_psi, d_y, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E);
   } else if (B == 1) {
     launch_p2p_batch<C, 1>(pb, p2p_grid, blocks, d_psi, d_y, B);
   } else if (B == 2) {
@@ -1108,9 +1209,14 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
     launch_p2p_batch<C, 16>(pb, p2p_grid, blocks, d_psi, d_y, B);
   }
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
-  if (!ev) (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
+  if (!ev) {
+    fmm_chain<P>(pb, d_psi, fs, nullptr, false, nb);
+    (void)hipEventRecord(pb.ev_join, pb.side);
+    (void)hipStreamWaitEvent(pb.stream, pb.ev_join, 0);
+  }
   long long n = 2LL * pb.E * nb;
-  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_far, d_y);
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_far, d_psi,
+                     pb.d_p2ppart, pb.p2p_split, d_y);
   if (ev) (void)hipEventRecord(ev[6], pb.stream);
   return hipGetLastError();
 }
@@ -1159,15 +1265,6 @@ constexpr int RED_THREADS = 256;
 
 constexpr int DOT_PER_LANE = 8;                 // w elements a lane keeps in registers
 constexpr int DOT_CHUNK = 64 * DOT_PER_LANE;      // elements of one block's chunk
-
-__device__ __forceinline__ cd wave_sum(cd v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
-  return v;
-}
 
 constexpr int DOT_VPW = 2;                      // vectors a wave reduces at once
 constexpr int DOT_VPB = DOT_VPW * (RED_THREADS / 64);   // vectors per block
@@ -1328,6 +1425,105 @@ __global__ void k_normalize_b(cd* out, const cd* __restrict__ in, long long sb, 
 hipError_t launch_normalize_b(Problem& pb, int B, cd* out, const cd* in, long long sb, const cd* d_nrm,
                               long long nsb, int n) {
   hipLaunchKernelGGL(k_normalize_b, dim3((n + 255) / 256, B), dim3(256), 0, pb.stream, out, in, sb, d_nrm, nsb,
+                     n);
+  return hipGetLastError();
+}
+
+// ---- fused Arnoldi steps (the coefficient reductions are redone per block) ----
+
+// w_b -= V_b h_b with h_b[i] = sum over the nblk dot partials of member b
+// (partial[(b * cnt + i) * nblk + blk]); block 0 of each member stores h_b at
+// hout + b * hsb.  With npart != nullptr every block also writes the squared
+// norm of its updated chunk to npart[b * gridDim.x + blockIdx.x].
+__global__ void __launch_bounds__(256) k_update_fused(cd* w, long long wsb, const cd* __restrict__ V, long long ldv,
+                                                      long long vsb, int cnt, const cd* __restrict__ partial,
+                                                      int nblk, cd* hout, long long hsb, int n, double* npart) {
+  __shared__ cd sh[256];
+  __shared__ double sn[256];
+  const int b = blockIdx.y;
+  const cd* pb_ = partial + (size_t)b * cnt * nblk;
+  w += b * wsb;
+  V += b * vsb;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  cd acc = t < n ? w[t] : mkc(0, 0);
+  for (int i0 = 0; i0 < cnt; i0 += 256) {
+    int c = min(256, cnt - i0);
+    if ((int)threadIdx.x < c) {
+      int i = i0 + threadIdx.x;
+      cd hv = mkc(0, 0);
+      for (int k = 0; k < nblk; ++k) hv = cadd(hv, pb_[(size_t)i * nblk + k]);
+      sh[threadIdx.x] = hv;
+      if (blockIdx.x == 0) hout[b * hsb + i] = hv;
+    }
+    __syncthreads();
+    if (t < n) {
+#pragma unroll 8
+      for (int i = 0; i < c; ++i) acc = csub(acc, cmul(sh[i], V[(size_t)(i0 + i) * ldv + t]));
+    }
+    __syncthreads();
+  }
+  if (t < n) w[t] = acc;
+  if (npart) {
+    sn[threadIdx.x] = t < n ? cabs2(acc) : 0.0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sn[threadIdx.x] += sn[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) npart[(size_t)b * gridDim.x + blockIdx.x] = sn[0];
+  }
+}
+
+// out_b = w_b / ||w_b|| with ||w_b||^2 the fixed-order sum of the np block
+// partials of member b (npart[b * np + k]); block 0 stores ||w_b||^2 at
+// nout + b * nsb (as a complex number with zero imaginary part).
+__global__ void __launch_bounds__(256) k_normalize_fused(cd* w, long long wsb, const double* __restrict__ npart,
+                                                         int np, cd* nout, long long nsb, int n) {
+  __shared__ double sn[256];
+  const int b = blockIdx.y;
+  double q = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) q += npart[(size_t)b * np + k];
+  sn[threadIdx.x] = q;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sn[threadIdx.x] += sn[threadIdx.x + st];
+    __syncthreads();
+  }
+  q = sn[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) nout[b * nsb] = mkc(q, 0.0);
+  double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) w[b * wsb + t] = cscale(w[b * wsb + t], s);
+}
+
+// One CGS2 Arnoldi step for B members after W_b = A V_{j,b}:
+// h1 = V^H W; W -= V h1; h2 = V^H W; W -= V h2; W /= ||W||.
+// Column j of every member is stored at hcol + b * hsb: h1 in [0, j],
+// h2 in [j+1, 2j+1], ||W||^2 in [2j+2].
+hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int j, cd* W,
+                               long long wsb, int n, cd* hcol, long long hsb) {
+  const int cnt = j + 1;
+  const int nblk = pb.red_blocks;
+  const int nu = (n + 255) / 256;
+  dim3 gd(nblk, (cnt + DOT_VPB - 1) / DOT_VPB, B), gu(nu, B);
+  // Few dot partials per coefficient (short vectors): every update block sums
+  // them itself.  Many (long vectors): one extra launch reduces them first.
+  const bool fused = nblk <= 32;
+  cd* fin = pb.d_red + (size_t)B * cnt * nblk;     // [B][cnt] reduced coefficients
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_dots, gd, dim3(RED_THREADS), 0, pb.stream, V, ldv, vsb, cnt, W, wsb, n, pb.d_red);
+    const cd* part = pb.d_red;
+    int np = nblk;
+    if (!fused) {
+      hipLaunchKernelGGL(k_dots_final, dim3(cnt, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, cnt, fin,
+                         (long long)cnt);
+      part = fin;
+      np = 1;
+    }
+    hipLaunchKernelGGL(k_update_fused, gu, dim3(256), 0, pb.stream, W, wsb, V, ldv, vsb, cnt, part, np,
+                       hcol + pass * cnt, hsb, n, pass ? pb.d_npart : (double*)nullptr);
+  }
+  hipLaunchKernelGGL(k_normalize_fused, gu, dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nu, hcol + 2 * cnt, hsb,
                      n);
   return hipGetLastError();
 }

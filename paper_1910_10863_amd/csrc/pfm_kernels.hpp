@@ -8,8 +8,8 @@ bool supported_p(int p);
 
 hipError_t launch_discretise(Problem& pb, double* d_ends);
 hipError_t launch_tables(Problem& pb);                 // htab, jtab (per k)
-// lattice sums with phase step beta into the table of batch member `member`
-hipError_t launch_lattice_sums(Problem& pb, int member, double beta);
+// lattice sums of members 0..B-1 (phase steps pb.d_betas) into their tables
+hipError_t launch_lattice_sums(Problem& pb, int B);
 // near blocks; phase_free: image phases left out (applied per member by the batched P2P)
 hipError_t launch_near_blocks(Problem& pb, bool phase_free);
 hipError_t launch_rhs(Problem& pb, double theta, cd* d_b);
@@ -38,6 +38,9 @@ hipError_t launch_update_b(Problem& pb, int B, cd* w, long long wsb, const cd* V
                            int cnt, const cd* d_h, long long hsb, int n);
 hipError_t launch_gemv_acc_b(Problem& pb, int B, cd* x, long long xsb, const cd* V, long long ldv, long long vsb,
                              int cnt, const cd* d_c, long long csb, int n);
+// one CGS2 Arnoldi step of B members (fused: five launches)
+hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int j, cd* W,
+                               long long wsb, int n, cd* hcol, long long hsb);
 hipError_t launch_normalize_b(Problem& pb, int B, cd* out, const cd* in, long long sb, const cd* d_nrm,
                               long long nsb, int n);
 hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n);

@@ -166,3 +166,22 @@ def test_batch_state_errors(pfm):
     pb.B = 1
     with pytest.raises(pfm.PfmError):
         pb.matvec_batch(torch.zeros((1, pb.n), dtype=torch.complex128, device="cuda"))
+
+
+def test_autotuner_choice_meets_target(pfm):
+    from paper_1910_10863_amd import autotune as at
+    wl = _WL["sq2x2"]
+    th = [0.0, 0.5, 1.0]
+    ch = at.autotune(at.geometry_of(wl), 5.0, th, target_err=1e-10, leaves=(16, 32), ps=(12, 16, 20, 24, 32),
+                     reps=5)
+    _say("autotune:", ch.leaf_max, ch.p, ch.err, [(t.leaf_max, t.p, t.err, t.cost_ms) for t in ch.trials])
+    assert ch.err <= 1e-10
+    # the chosen configuration against the dense oracle at every angle
+    pb = pfm.Problem(**at.geometry_of(wl), p=ch.p, leaf_max=ch.leaf_max, max_batch=3)
+    pb.set_batch(5.0, th)
+    psi = torch.tensor(np.stack([W.random_density(pb.n, 60 + b) for b in range(3)]), device="cuda")
+    y = pb.matvec_batch(psi).cpu().numpy()
+    for b in range(3):
+        A, _ = _dense("sq2x2", 5.0, th[b])
+        ref = A @ psi[b].cpu().numpy()
+        assert np.linalg.norm(y[b] - ref) / np.linalg.norm(ref) < 1e-9
