@@ -18,4 +18,6 @@ Modules:
   system    dense (I - A), right-hand side B, LU solve
   fields    Bragg amplitudes, energy transmission coefficient (Sec. 4)
   fmmdefs   FMM stage definitions by direct summation (Sec. 3.2)
+  warmstart learned warm start: features, MLP with MSE gradients, Adam,
+            per-fibre modal transform of the densities (not from the paper)
 """

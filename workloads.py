@@ -124,3 +124,25 @@ def warm_start_draws(n: int, seed: int) -> np.ndarray:
     lo = np.array([0.2, 0.0, 0.15, 0.5, 0.5])
     hi = np.array([8.0, math.pi / 2, 0.4, 20.0, 2.0])
     return lo + (hi - lo) * rng.random((n, 5))
+
+
+def warm_start_groups(n_groups: int, per_group: int, seed: int):
+    """Draws of the warm-start study grouped by geometry and frequency:
+    [n_groups, 4] of (ka, r/a, rho_fiber/rho_matrix, c_fiber/c_matrix) uniform
+    over the ranges of warm_start_draws, and [n_groups, per_group] angles
+    uniform in [0, pi/2); group g with angle j is the draw
+    (ka_g, theta_gj, r_g, rho_g, c_g).  The block is a square 4 x 4 of equal
+    fibres with 256 elements each, matrix water."""
+    rng = np.random.default_rng(seed)
+    lo = np.array([0.2, 0.15, 0.5, 0.5])
+    hi = np.array([8.0, 0.4, 20.0, 2.0])
+    g = lo + (hi - lo) * rng.random((n_groups, 4))
+    th = (math.pi / 2) * rng.random((n_groups, per_group))
+    return g, th
+
+
+def warm_start_block(r: float, rho_ratio: float, c_ratio: float) -> Workload:
+    """The square 4 x 4 block of the warm-start study for one draw."""
+    return Workload("square_4x4_N256_warm", SQUARE, 1.0, 4, 4, 256, _full(16, r),
+                    rho_ratio * WATER["rho"], c_ratio * WATER["c"], WATER["rho"], WATER["c"],
+                    [], [], 24, 32)
