@@ -166,6 +166,29 @@ def batched_sweep_leg(n_single_ka: int, tune: bool):
     return out
 
 
+def warm_start_leg(n_train_groups: int, n_eval_groups: int, epochs: int):
+    """Learned warm start on the square 4x4 block (8192 unknowns): solves of
+    n_train_groups x 8 draws (ka, theta, r, rho ratio, c ratio uniform over
+    their ranges) train the 5-256-256-256-2048 network in FP32 with the
+    library's own kernels; on n_eval_groups x 8 held-out draws the BF16
+    prediction is compared with the cold start at residuals 1e-8 and 1e-4."""
+    import workloads as W
+    from paper_1910_10863_amd import warm
+    g, th = W.warm_start_groups(n_train_groups, 8, 5)
+    data = warm.generate(g, th)
+    print(f"warm start: generated {data.x.shape[0]} solves in {data.seconds:.1f} s", file=sys.stderr, flush=True)
+    net = warm.train(data, epochs=epochs, batch=256, lr=1e-3, seed=2)
+    print(f"warm start: trained in {net.train_seconds:.1f} s, loss {net.losses[0]:.3e} -> {net.losses[-1]:.3e}",
+          file=sys.stderr, flush=True)
+    ge, te = W.warm_start_groups(n_eval_groups, 8, 77)
+    ev = warm.evaluate(net, ge, te, tols=(1e-8, 1e-4))
+    print(f"warm start: {ev}", file=sys.stderr, flush=True)
+    return {"workload": "square_4x4_N256_warm", "network": list(warm.SIZES), "train_solves": int(data.x.shape[0]),
+            "generate_seconds": data.seconds, "train_seconds": net.train_seconds, "epochs": epochs,
+            "final_loss_standardised": net.losses[-1], "validation_rel_err": getattr(net, "val_rel_err", None),
+            "evaluation": ev}
+
+
 def cpu_baseline(wl, ka, theta, n_targets):
     """Dense FP64 oracle: rows of (I - A) assembled and applied for a sample of
     collocation points; scaled to the rate of a full dense apply."""
@@ -205,6 +228,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched band-sweep leg")
     ap.add_argument("--no-tune", action="store_true", help="batched leg without the autotuner")
+    ap.add_argument("--warm-train-groups", type=int, default=2500,
+                    help="groups of 8 training solves of the warm-start leg (0: skip the leg)")
+    ap.add_argument("--warm-eval-groups", type=int, default=128)
+    ap.add_argument("--warm-epochs", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied by a plain device copy before timing, for HBM counter scaling")
@@ -290,6 +317,9 @@ def main():
     batched = None
     if not args.no_batched and args.sweep > 0:
         batched = batched_sweep_leg(8, not args.no_tune)
+    warm_leg = None
+    if args.warm_train_groups > 0 and args.sweep > 0:
+        warm_leg = warm_start_leg(args.warm_train_groups, args.warm_eval_groups, args.warm_epochs)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -319,6 +349,7 @@ def main():
         "sweep": sweep,
         "mixed_precision": mixed,
         "batched_sweep": batched,
+        "warm_start": warm_leg,
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_root_offsets", "lattice_q")},

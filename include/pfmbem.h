@@ -123,6 +123,7 @@ typedef struct {
   double rel_residual;     /* true relative residual of the returned Psi */
   double t_solve_s;        /* wall time of the solve */
   int outer;               /* PFM_MIXED: refinement steps (0 in FP64) */
+  int fallback;            /* use_x0 = 2: the start vector was replaced by zero */
 } pfm_info;
 
 /* Sizes and counts of the built plan (for reports and tests). */
@@ -169,7 +170,12 @@ pfm_status pfm_rhs(pfm_problem* pb, void* d_b);
 
 /* Restarted GMRES for (I - A) Psi = B with the FMM apply.  d_b: right-hand
  * side (NULL: B of eq. 9).  d_x: on entry the start vector when use_x0 != 0
- * (else zero is used), on return the solution.  Returns PFM_ENOCONV when the
+ * (else zero is used), on return the solution.  use_x0 = 2: a start vector
+ * whose true residual is not below ||B|| is replaced by zero (the cold start
+ * is the fallback; info->fallback = 1).  use_x0 = 3: d_x holds a guess u that
+ * augments the first cycle, which minimises the residual over
+ * span{u} + K_j((I - A), B) starting from zero, so it never needs more
+ * iterations than the cold start (FP64 precision only).  Returns PFM_ENOCONV when the
  * tolerance is not met in max_iter iterations (d_x holds the best iterate). */
 pfm_status pfm_solve(pfm_problem* pb, const void* d_b, void* d_x, int use_x0,
                      pfm_info* info);
@@ -214,7 +220,8 @@ pfm_status pfm_rhs_batch(pfm_problem* pb, void* d_b);
 /* Restarted GMRES for all members in lockstep: one batched apply per
  * iteration, Arnoldi (CGS2) per member in FP64.  d_b: [B][2MN] right-hand
  * sides or NULL (eq. 9); d_x: [B][2MN] start vectors when use_x0 != 0, the
- * solutions on return; infos: host array of B records.  A member stops
+ * solutions on return (use_x0 = 2: per-member fallback to zero, 3:
+ * per-member augmentation, as in pfm_solve); infos: host array of B records.  A member stops
  * when its true residual meets tol.  Returns PFM_ENOCONV when any member
  * misses the tolerance within max_iter iterations (its best iterate is
  * written), PFM_OK otherwise. */

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpfmbem.so")
-SOURCES = ["pfm_kernels.hip", "pfm_capi.hip", "pfm_plan.cpp"]
+SOURCES = ["pfm_kernels.hip", "pfm_capi.hip", "pfm_warm.hip", "pfm_plan.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -15,9 +15,6 @@
 
 using namespace pfm;
 
-struct pfm_problem {
-  Problem p;
-};
 
 namespace {
 
@@ -85,8 +82,8 @@ void free_all(Problem& pb) {
   pb.cap = nullptr;
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
-  dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
-  dfree(pb.d_srule); dfree(pb.d_betas); dfree(pb.d_latpart);
+  dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_ir_aug); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
+  dfree(pb.d_srule); dfree(pb.d_betas); dfree(pb.d_thetas); dfree(pb.d_latpart);
   dfree(pb.d_mpole); dfree(pb.d_local);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
   dfree(pb.d_red); dfree(pb.d_hcol); dfree(pb.d_fields);
@@ -355,6 +352,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.d_lat = pb.d_htab + (size_t)n_off_real * NT;
   CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_betas, MB * sizeof(double)));
+  CK(hipMalloc((void**)&pb.d_thetas, MB * sizeof(double)));
   CK(hipMalloc((void**)&pb.d_latpart, MB * n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd)));
   (void)n_off;
   {
@@ -417,6 +415,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_b, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_tmp, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gin, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_ir_aug, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
   pb.red_blocks = (int)std::min<size_t>(256, (n + 511) / 512);
   CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 255) / 256) * sizeof(double)));
@@ -729,7 +728,8 @@ hipError_t batch_apply(Problem& pb, const cd* in, cd* out) {
 // decides convergence.  Basis layout: V[(j * B + b) * n].
 template <typename Apply>
 pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x, bool use_x0, double tol,
-                          int max_iter, std::vector<GmresStats>& gs, std::vector<pfm_status>& st) {
+                          int max_iter, std::vector<GmresStats>& gs, std::vector<pfm_status>& st,
+                          std::vector<int>* fallback = nullptr, const cd* aug = nullptr) {
   typedef std::complex<double> C;
   const int n = 2 * pb.E;
   const long long nb = (long long)n;
@@ -758,6 +758,23 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
   };
   HIPCHK(pb, sync_norms(b, bnorm));
   if (!use_x0) HIPCHK(pb, hipMemsetAsync(x, 0, (size_t)B * n * sizeof(cd), pb.stream));
+  // Augmented first cycle (aug != nullptr): minimise the residual over
+  // span{u} + K_j(A, b) with u = aug.  With c = A u split as c = V g + c_perp
+  // against the Arnoldi basis, the least-squares problem in (y, alpha) reduces,
+  // after the Givens rotations of the Hessenberg matrix (also applied to g,
+  // giving s), to the scalar alpha = conj(s_j1) t_j1 / (|s_j1|^2 + |c_perp|^2)
+  // and the residual |t_j1| |c_perp| / sqrt(|s_j1|^2 + |c_perp|^2), never more
+  // than the plain GMRES estimate |t_j1|.
+  cd* Cv = pb.d_tmp;                             // c = A u
+  std::vector<double> cc(B, 0.0), gsum(B, 0.0);
+  std::vector<C> sv((size_t)B * (m + 1)), alpha(B, 0.0);
+  bool augmenting = aug != nullptr;
+  if (augmenting) {
+    HIPCHK(pb, apply(aug, Cv));
+    std::vector<double> cn(B);
+    HIPCHK(pb, sync_norms(Cv, cn));
+    for (int i = 0; i < B; ++i) cc[i] = cn[i] * cn[i];
+  }
   bool first = true;
   while (true) {
     // true residuals R = b - A x
@@ -770,8 +787,20 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       HIPCHK(pb, hipMemcpyAsync(R, b, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
       HIPCHK(pb, launch_axpby(pb, R, mkc(-1, 0), W, mkc(1, 0), (long long)B * n));
     }
-    first = false;
     HIPCHK(pb, sync_norms(R, beta));
+    if (first && use_x0 && fallback) {
+      // a start vector that does not beat zero is replaced by zero
+      for (int i = 0; i < B; ++i) {
+        if (std::isfinite(beta[i]) && beta[i] < bnorm[i]) continue;
+        (*fallback)[i] = 1;
+        HIPCHK(pb, hipMemsetAsync(x + (size_t)i * n, 0, n * sizeof(cd), pb.stream));
+        HIPCHK(pb, hipMemcpyAsync(R + (size_t)i * n, b + (size_t)i * n, n * sizeof(cd), hipMemcpyDeviceToDevice,
+                                  pb.stream));
+        beta[i] = bnorm[i];
+      }
+      HIPCHK(pb, launch_dots_b(pb, B, R, nb, nb, 1, R, nb, n, hc, hs));   // squared norms for V_0
+    }
+    first = false;
     bool all_done = true;
     for (int i = 0; i < B; ++i) {
       if (done[i]) continue;
@@ -795,6 +824,16 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
     if (all_done) return PFM_OK;
     // V_0 = R / ||R|| per member (the squared norms are still in d_hcol)
     HIPCHK(pb, launch_normalize_b(pb, B, V, R, nb, hc, hs, n));
+    if (augmenting) {
+      // g_0 = v_0^H c
+      HIPCHK(pb, launch_dots_b(pb, B, V, nb, nb, 1, Cv, nb, n, hc, hs));
+      HIPCHK(pb, hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
+      HIPCHK(pb, hipStreamSynchronize(pb.stream));
+      for (int i = 0; i < B; ++i) {
+        sv[(size_t)i * (m + 1)] = C(hh[i * hs].x, hh[i * hs].y);
+        gsum[i] = std::norm(sv[(size_t)i * (m + 1)]);
+      }
+    }
     int budget = 0;      // iterations any member may still take
     for (int i = 0; i < B; ++i) {
       cyc[i] = !done[i];
@@ -809,7 +848,11 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       cd* Wj = V + (size_t)(j + 1) * ldv;
       hipError_t e = apply(Vj, Wj);
       if (e != hipSuccess) return e;
-      return launch_arnoldi_step(pb, B, V, ldv, nb, j, Wj, nb, n, pb.d_hall + (size_t)j * B * hs2, hs2);
+      cd* hcol = pb.d_hall + (size_t)j * B * hs2;
+      e = launch_arnoldi_step(pb, B, V, ldv, nb, j, Wj, nb, n, hcol, hs2);
+      if (e != hipSuccess || !augmenting) return e;
+      // g_{j+1} = v_{j+1}^H c into slot 2j+3 of the column
+      return launch_dots_b(pb, B, Wj, nb, nb, 1, Cv, nb, n, hcol + 2 * (j + 1) + 1, hs2);
     };
     auto readback = [&](int j0, int j1) -> hipError_t {
       return hipMemcpyAsync(pb.h_hall + (size_t)j0 * B * hs2, pb.d_hall + (size_t)j0 * B * hs2,
@@ -880,6 +923,19 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
           ++gs[i].matvecs;
           jj[i] = j + 1;
           double est = std::abs(gi[j + 1]) / bnorm[i];
+          if (augmenting) {
+            C* s_ = &sv[(size_t)i * (m + 1)];
+            C gnew(hv[2 * (j + 1) + 1].x, hv[2 * (j + 1) + 1].y);
+            gsum[i] += std::norm(gnew);
+            C a2 = s_[j];
+            s_[j] = csi[j] * a2 + sni[j] * gnew;
+            s_[j + 1] = -std::conj(sni[j]) * a2 + csi[j] * gnew;
+            double cp2 = std::max(0.0, cc[i] - gsum[i]);
+            double den = std::norm(s_[j + 1]) + cp2;
+            alpha[i] = den > 0 ? std::conj(s_[j + 1]) * gi[j + 1] / den : C(0.0);
+            double r2 = den > 0 ? std::norm(gi[j + 1]) * cp2 / den : 0.0;
+            est = std::sqrt(r2) / bnorm[i];
+          }
           if (est <= 0.7 * tol || gs[i].iters >= max_iter || hn == 0.0) cyc[i] = 0;
           any = any || cyc[i];
         }
@@ -897,6 +953,7 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       std::vector<C> y(jj[i]);
       for (int r = jj[i] - 1; r >= 0; --r) {
         C acc = g[(size_t)i * (m + 1) + r];
+        if (augmenting) acc -= alpha[i] * sv[(size_t)i * (m + 1) + r];
         for (int l = r + 1; l < jj[i]; ++l) acc -= Hm[((size_t)i * (m + 1) + r) * m + l] * y[l];
         y[r] = acc / Hm[((size_t)i * (m + 1) + r) * m + r];
         yv[r] = mkc(y[r].real(), y[r].imag());
@@ -907,6 +964,14 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       HIPCHK(pb, hipMemcpyAsync(hc, hh, (size_t)B * hs * sizeof(cd), hipMemcpyHostToDevice, pb.stream));
       HIPCHK(pb, launch_gemv_acc_b(pb, B, x, nb, V, ldv, nb, cnt, hc, hs, n));
     }
+    if (augmenting) {
+      // x_b += alpha_b u_b, then plain restarts
+      for (int i = 0; i < B; ++i) {
+        C a = jj[i] > 0 ? alpha[i] : C(0.0);
+        HIPCHK(pb, launch_axpby(pb, x + (size_t)i * n, mkc(a.real(), a.imag()), aug + (size_t)i * n, mkc(1, 0), n));
+      }
+      augmenting = false;
+    }
   }
 }
 
@@ -915,8 +980,10 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
 extern "C" {
 
 pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* info) {
-  if (!h || !d_x_io) return PFM_EINVAL;
+  if (!h || !d_x_io || use_x0 < 0 || use_x0 > 3) return PFM_EINVAL;
   Problem& pb = h->p;
+  if (use_x0 == 3 && pb.opt.precision == PFM_MIXED)
+    return fail(pb, PFM_EINVAL, "augmentation (use_x0 = 3) needs precision PFM_FP64");
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
   auto t0 = std::chrono::steady_clock::now();
   const int n = 2 * pb.E;
@@ -928,6 +995,7 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
   GmresStats gs;
   pfm_status st = PFM_OK;
   int outer = 0;
+  int fell_back = 0;
   if (pb.opt.precision == PFM_MIXED) {
     // FP64 iterative refinement around GMRES with the mixed-precision apply:
     //   r = b - A x (FP64 apply); solve A d = r to the inner tolerance; x += d.
@@ -983,9 +1051,17 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
   } else {
     std::vector<GmresStats> g1;
     std::vector<pfm_status> s1;
-    st = gmres_lockstep(pb, 1, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1);
+    std::vector<int> fb(1, 0);
+    if (use_x0 == 3) {
+      HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, x, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      st = gmres_lockstep(pb, 1, apply64, b, x, false, pb.opt.tol, pb.opt.max_iter, g1, s1, nullptr, pb.d_ir_aug);
+    } else {
+      st = gmres_lockstep(pb, 1, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
+                          use_x0 == 2 ? &fb : nullptr);
+    }
     gs = g1[0];
     if (st == PFM_OK) st = s1[0];
+    fell_back = fb[0];
   }
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   auto t1 = std::chrono::steady_clock::now();
@@ -996,12 +1072,13 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
     info->rel_residual = gs.rel;
     info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
     info->outer = outer;
+    info->fallback = fell_back;
   }
   return st;
 }
 
 pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* infos) {
-  if (!h || !d_x_io) return PFM_EINVAL;
+  if (!h || !d_x_io || use_x0 < 0 || use_x0 > 3) return PFM_EINVAL;
   Problem& pb = h->p;
   if (!pb.batch_ready) return fail(pb, PFM_ESTATE, "pfm_set_batch first");
   auto t0 = std::chrono::steady_clock::now();
@@ -1014,7 +1091,16 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
   std::vector<GmresStats> gs;
   std::vector<pfm_status> st;
   auto apply = [&](const cd* in, cd* out) { return batch_apply(pb, in, out); };
-  pfm_status s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st);
+  std::vector<int> fb(pb.B, 0);
+  pfm_status s;
+  if (use_x0 == 3) {
+    HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, d_x_io, pb.B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, false, pb.opt.tol, pb.opt.max_iter, gs, st, nullptr,
+                       pb.d_ir_aug);
+  } else {
+    s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
+                       use_x0 == 2 ? &fb : nullptr);
+  }
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   pfm_status worst = s;
@@ -1026,6 +1112,7 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
       infos[i].rel_residual = gs[i].rel;
       infos[i].t_solve_s = dt;
       infos[i].outer = 0;
+      infos[i].fallback = fb[i];
     }
     if (worst == PFM_OK && st[i] != PFM_OK) worst = st[i];
   }

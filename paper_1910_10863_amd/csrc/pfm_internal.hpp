@@ -101,6 +101,7 @@ struct Problem {
   cd *d_near = nullptr;                 // near blocks, complex128
   float2 *d_near32 = nullptr;           // near blocks, complex64 (PFM_MIXED)
   cd *d_ir_r = nullptr, *d_ir_d = nullptr;   // refinement residual and correction
+  cd *d_ir_aug = nullptr;               // augmentation vectors of the first GMRES cycle [member][2E]
   cd *d_htab = nullptr;                 // [2 ch][n_tab][4p+1]
   cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
   cd *d_lat = nullptr;                  // = d_htab + n_off rows: lattice sums [n_roff][4p+1]
@@ -126,6 +127,7 @@ struct Problem {
   double *d_srule = nullptr;            // lattice tail rule: nodes, weights
   int n_srule = 0;
   double *d_betas = nullptr;            // k H sin(theta) per batch member
+  double *d_thetas = nullptr;           // incidence angles per batch member (modal transforms)
   cd *d_latpart = nullptr;              // tail partial sums [member][offset][rule block][4p+1]
   // expansions
   cd *d_mpole = nullptr;                // [n_cells][2][2p+1]
@@ -155,3 +157,8 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
 }  // namespace pfm
+
+// the opaque handle of the C interface
+struct pfm_problem {
+  pfm::Problem p;
+};

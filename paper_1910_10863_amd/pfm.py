@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("matvecs", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("outer", ctypes.c_int)]
+                ("outer", ctypes.c_int), ("fallback", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -167,6 +167,8 @@ class Problem:
             self._h = None
             raise PfmError(code, msg)
         self.n = 2 * M_L * M_H * n_elem
+        self.M = M_L * M_H
+        self.N = n_elem
         self.p = p
         self.max_batch = max(1, max_batch)
         self.B = 0
@@ -226,16 +228,25 @@ class Problem:
         self._check(self._L.pfm_rhs(self._h, _ptr(b)))
         return b
 
-    def solve(self, b=None, x0=None, raise_on_noconv: bool = False):
+    @staticmethod
+    def _mode(x0, fallback, augment):
+        if x0 is None:
+            return 0
+        return 3 if augment else (2 if fallback else 1)
+
+    def solve(self, b=None, x0=None, raise_on_noconv: bool = False, fallback: bool = False, augment: bool = False):
+        """x0: start vector (fallback: replaced by zero when it does not beat
+        zero) or, with augment, a guess that augments the first GMRES cycle."""
         import torch
         x = self.empty() if x0 is None else x0.clone()
         info = Info()
         code = self._L.pfm_solve(self._h, _ptr(b) if b is not None else None, _ptr(x),
-                                 1 if x0 is not None else 0, ctypes.byref(info))
+                                 self._mode(x0, fallback, augment), ctypes.byref(info))
         if code != 0 and (code != 4 or raise_on_noconv):
             self._check(code)
         return x, {"status": info.status, "iters": info.iters, "matvecs": info.matvecs,
-                   "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s, "outer": info.outer}
+                   "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s, "outer": info.outer,
+                   "fallback": info.fallback}
 
     def fields(self, psi, n_orders: int = 10):
         no = 2 * n_orders + 1
@@ -286,13 +297,13 @@ class Problem:
     @staticmethod
     def _infos(arr):
         return [{"status": i.status, "iters": i.iters, "matvecs": i.matvecs, "rel_residual": i.rel_residual,
-                 "t_solve_s": i.t_solve_s} for i in arr]
+                 "t_solve_s": i.t_solve_s, "fallback": i.fallback} for i in arr]
 
-    def solve_batch(self, b=None, x0=None):
+    def solve_batch(self, b=None, x0=None, fallback: bool = False, augment: bool = False):
         x = self.empty_batch() if x0 is None else x0.clone()
         infos = (Info * self.B)()
         code = self._L.pfm_solve_batch(self._h, _ptr(b) if b is not None else None, _ptr(x),
-                                       1 if x0 is not None else 0, infos)
+                                       self._mode(x0, fallback, augment), infos)
         if code not in (0, 4, 6):
             self._check(code)
         return x, self._infos(infos)

@@ -1,20 +1,23 @@
-"""The C-ABI library loads and exports every symbol that include/pfmbem.h declares.
+"""The C-ABI library loads and exports every symbol that include/*.h declares.
 No compute call is made here (no GPU needed)."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HDR = os.path.join(ROOT, "include", "pfmbem.h")
+HDRS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_1910_10863_amd", "libpfmbem.so")
 
 
 def declared():
-    txt = open(HDR).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(pfm_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    for h in HDRS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(pfm_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_declares_entry_points():
@@ -32,5 +35,5 @@ def test_library_exports_all_declared_symbols():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_binding_lists_match_header():
-    from paper_1910_10863_amd import pfm
-    assert sorted(pfm.EXPORTS) == declared()
+    from paper_1910_10863_amd import pfm, warm
+    assert sorted(pfm.EXPORTS + warm.EXPORTS) == declared()
