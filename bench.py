@@ -225,8 +225,10 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: the workload's)")
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched band-sweep leg")
+    ap.add_argument("--legs", default="sweep,mixed,batched,warm",
+                    help="comma list of the legs besides the timed apply: sweep (square 8x8 ka sweep), "
+                         "mixed (hexagon 16x16 mixed precision), batched (square 4x4 band sweep), "
+                         "warm (learned warm start); empty: none")
     ap.add_argument("--no-tune", action="store_true", help="batched leg without the autotuner")
     ap.add_argument("--warm-train-groups", type=int, default=2500,
                     help="groups of 8 training solves of the warm-start leg (0: skip the leg)")
@@ -290,7 +292,8 @@ def main():
     achieved = lb / (leaf_ms * 1e-3) / 1e9
 
     sweep = None
-    if args.sweep > 0:
+    legs = set(x for x in args.legs.split(",") if x)
+    if "sweep" in legs and args.sweep > 0:
         kas = wl.ka[:args.sweep] if args.sweep >= len(wl.ka) else \
             [wl.ka[int(i)] for i in np.linspace(0, len(wl.ka) - 1, args.sweep)]
         iters, res, fails = [], [], 0
@@ -312,13 +315,13 @@ def main():
                  "precision": "fp64", "setup_included": True}
 
     mixed = None
-    if not args.no_mixed and args.sweep > 0:
+    if "mixed" in legs:
         mixed = mixed_precision_leg(max(10, min(args.steps, 50)))
     batched = None
-    if not args.no_batched and args.sweep > 0:
+    if "batched" in legs:
         batched = batched_sweep_leg(8, not args.no_tune)
     warm_leg = None
-    if args.warm_train_groups > 0 and args.sweep > 0:
+    if "warm" in legs and args.warm_train_groups > 0:
         warm_leg = warm_start_leg(args.warm_train_groups, args.warm_eval_groups, args.warm_epochs)
 
     cpu = None

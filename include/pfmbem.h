@@ -98,7 +98,11 @@ typedef struct {
  *  max_batch  capacity of the batched calls: angles per frequency (0 -> 1, at
  *             most PFM_MAX_BATCH); per-member buffers are sized for it
  *  use_graph  batched solves replay the batched apply from a captured HIP
- *             graph (1) or launch it kernel by kernel (0) */
+ *             graph (1) or launch it kernel by kernel (0)
+ *  p2p_blocks_per_cu  workgroups per compute unit of the persistent P2P
+ *             launch (0: 2; at most 8)
+ *  p2p_unroll  source columns whose block entries a P2P wavefront keeps in
+ *             flight at once: 1, 2 or 4 (0: 1) */
 typedef struct {
   int p;
   int leaf_max;
@@ -112,6 +116,8 @@ typedef struct {
   double inner_tol;
   int max_batch;
   int use_graph;
+  int p2p_blocks_per_cu;
+  int p2p_unroll;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16

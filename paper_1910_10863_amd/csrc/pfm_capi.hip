@@ -170,6 +170,9 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
     return bail(fail(pb, PFM_EINVAL, "max_batch must be 0..16 and use_graph 0 or 1"));
+  if (opt->p2p_blocks_per_cu < 0 || opt->p2p_blocks_per_cu > 8 ||
+      !(opt->p2p_unroll == 0 || opt->p2p_unroll == 1 || opt->p2p_unroll == 2 || opt->p2p_unroll == 4))
+    return bail(fail(pb, PFM_EINVAL, "p2p_blocks_per_cu must be 0..8 and p2p_unroll 0, 1, 2 or 4"));
   if (!(mat->rho_fiber > 0 && mat->c_fiber > 0 && mat->rho_matrix > 0 && mat->c_matrix > 0))
     return bail(fail(pb, PFM_EINVAL, "materials must be positive"));
 
@@ -218,7 +221,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
-      pb.p2p_grid = 2 * ncu;
+      pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : 2) * ncu;
+    pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : 1;
   }
   // discretisation on the device
   int E = pb.E;

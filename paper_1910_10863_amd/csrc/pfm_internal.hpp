@@ -114,6 +114,7 @@ struct Problem {
   int n_chunks = 0;
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
+  int p2p_unroll = 1;                   // source columns in flight per P2P wavefront
   cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table

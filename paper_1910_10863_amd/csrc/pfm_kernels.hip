@@ -574,7 +574,7 @@ struct P2MHalf {
 };
 
 template <int P, int W, int NA>
-__device__ __forceinline__ void p2m_half(cd (&red)[2][64][NA], int lane, int b, int npts, int G, int N,
+__device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npts, int G, int N,
                                          double kap, double eta, double ox, double oy,
                                          const int* __restrict__ elem_of, const int* __restrict__ psi_idx,
                                          const double* __restrict__ mx, const double* __restrict__ my,
@@ -632,7 +632,7 @@ __device__ __forceinline__ void p2m_half(cd (&red)[2][64][NA], int lane, int b, 
     }
   }
 #pragma unroll
-  for (int j = 0; j < H::NS; ++j) red[W][lane][j] = acc[j];
+  for (int j = 0; j < H::NS; ++j) out[j] = acc[j];
 }
 
 template <int P>
@@ -648,7 +648,9 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
                                              long long psi_stride, long long mp_stride) {
   constexpr int NP = 2 * P + 1;
   constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
-  __shared__ cd red[2][64][NA];
+  // one transpose buffer, used by the two wavefronts in turn (keeps the LDS
+  // footprint small so that P2M co-resides with the concurrent P2P)
+  __shared__ cd red[64][NA];
   psi += blockIdx.z * psi_stride;               // batch member
   mpole += blockIdx.z * mp_stride;
   int cell = leaves[blockIdx.x];
@@ -658,20 +660,30 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
   double ox = cx[cell], oy = cy[cell];
   int b = ebeg[cell];
   int npts = (eend[cell] - b) * G;
+  cd acc[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = mkc(0, 0);
   if (wv == 0)
-    p2m_half<P, 0, NA>(red, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
+    p2m_half<P, 0, NA>(acc, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
   else
-    p2m_half<P, 1, NA>(red, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
-  __syncthreads();
+    p2m_half<P, 1, NA>(acc, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  // slot -> order, per wavefront
-  int lo = wv == 0 ? 0 : P / 2 + 1, hi = wv == 0 ? P / 2 : P;
-  int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
-  for (int j = lane; j < npos + nneg; j += 64) {
-    cd sres = mkc(0, 0);
-    for (int r = 0; r < 64; ++r) sres = cadd(sres, red[wv][r][j]);
-    int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
-    out[n + P] = sres;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (wv == pass) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) red[lane][j] = acc[j];
+    }
+    __syncthreads();
+    // slot -> order of the wavefront of this pass
+    int lo = pass == 0 ? 0 : P / 2 + 1, hi = pass == 0 ? P / 2 : P;
+    int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
+    for (int j = threadIdx.x; j < npos + nneg; j += 128) {
+      cd sres = mkc(0, 0);
+      for (int r = 0; r < 64; ++r) sres = cadd(sres, red[r][j]);
+      int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
+      out[n + P] = sres;
+    }
+    __syncthreads();
   }
 }
 
@@ -915,7 +927,7 @@ __global__ void k_combine(long long n, const cd* __restrict__ far, const cd* __r
 // leaf's contiguous block region; partial rows meet in LDS.  Pure streaming:
 // the kernel is HBM-bound.
 constexpr int P2P_WAVES = 4;
-constexpr int P2P_SEG = 512;
+constexpr int P2P_SEG = 256;
 
 // Complex arithmetic of the P2P stream: FP64 (double2) or FP32 (float2).
 __device__ __forceinline__ double2 p2p_fma(double2 a, double2 b, double2 c) { return cfma(a, b, c); }
@@ -930,8 +942,8 @@ template <> __device__ __forceinline__ float2 p2p_cvt<float2>(cd v) {
 }
 template <typename C> __device__ __forceinline__ cd p2p_wide(C v) { return mkc((double)v.x, (double)v.y); }
 
-template <typename C>
-__global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
+template <typename C, int U>
+__global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
     const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
     const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
@@ -963,7 +975,28 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 8) k_p2p(
       __syncthreads();
       const C* bs = bl + (size_t)seg * cstride + lane;
       if (act) {
-        for (int k = w; k < nseg; k += P2P_WAVES) {
+        // U columns per step: their 4U block loads are issued before the FMAs
+        int k = w;
+        for (; k + (U - 1) * P2P_WAVES < nseg; k += U * P2P_WAVES) {
+          C bb[U][4];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            unsigned o = (unsigned)(k + u * P2P_WAVES) * cstride;
+            bb[u][0] = bs[o];
+            bb[u][1] = bs[o + rows];
+            bb[u][2] = bs[o + 2 * rows];
+            bb[u][3] = bs[o + 3 * rows];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            C ph = sp[k + u * P2P_WAVES][0], vp = sp[k + u * P2P_WAVES][1];
+            a1 = p2p_fma(bb[u][0], ph, a1);
+            a1 = p2p_fma(bb[u][1], vp, a1);
+            a2 = p2p_fma(bb[u][2], ph, a2);
+            a2 = p2p_fma(bb[u][3], vp, a2);
+          }
+        }
+        for (; k < nseg; k += P2P_WAVES) {
           unsigned o = (unsigned)k * cstride;
           C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
           C ph = sp[k][0], vp = sp[k][1];
@@ -1194,9 +1227,14 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
   int items = n_leaves * pb.p2p_split;
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
   if (B == 0) {
-    hipLaunchKernelGGL(k_p2p<C>, dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg,
-                       pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                       pb.d_col_psi, blocks, d_psi, d_y, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E);
+#define PFM_P2P(U)                                                                                             \
+  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg, \
+                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr, pb.d_col_psi,  \
+                     blocks, d_psi, d_y, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
+    if (pb.p2p_unroll == 4) PFM_P2P(4);
+    else if (pb.p2p_unroll == 2) PFM_P2P(2);
+    else PFM_P2P(1);
+#undef PFM_P2P
   } else if (B == 1) {
     launch_p2p_batch<C, 1>(pb, p2p_grid, blocks, d_psi, d_y, B);
   } else if (B == 2) {
