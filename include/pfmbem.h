@@ -146,6 +146,7 @@ typedef struct {
   double k, k1, eta, varrho, theta;
   int lattice_q;               /* direct images of the lattice sums, |m| <= q */
   int p2p_split;               /* column splits per target leaf in the P2P launch */
+  int n_near_computed;         /* near pairs whose blocks are computed (equal fibres share blocks) */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

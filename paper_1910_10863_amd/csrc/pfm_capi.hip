@@ -10,6 +10,8 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <map>
+#include <array>
 
 #include "pfm_kernels.hpp"
 
@@ -75,6 +77,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
+  dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
   pb.graph = nullptr;
@@ -82,7 +85,7 @@ void free_all(Problem& pb) {
   pb.cap = nullptr;
   dfree(pb.d_root_pair_off); dfree(pb.d_root_mrange);
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
-  dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_ir_aug); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
+  dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_ir_aug); dfree(pb.d_cperp); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
   dfree(pb.d_srule); dfree(pb.d_betas); dfree(pb.d_thetas); dfree(pb.d_latpart);
   dfree(pb.d_mpole); dfree(pb.d_local);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
@@ -286,6 +289,69 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
   CK(upload(&pb.d_near_blk, hp.near_blk));
   {
+    // Equal fibres (same radius, so the same chords and the same tree about
+    // each centre): a near block depends only on the two leaves' places in
+    // their fibres' trees and on the offset between the fibres (image
+    // included).  Such blocks are computed once and copied.
+    const int npairs = (int)hp.near_src.size();
+    bool equal = pb.M > 1 && npairs > 0;
+    for (int f = 1; f < pb.M && equal; ++f) equal = pb.radii[f] == pb.radii[0];
+    std::vector<std::vector<int>> leaves_of(pb.M);
+    std::vector<int> local(hp.cells.size(), -1);
+    if (equal) {
+      for (int li = 0; li < (int)hp.leaves.size(); ++li) {
+        const Cell& c = hp.cells[hp.leaves[li]];
+        local[hp.leaves[li]] = (int)leaves_of[c.fiber].size();
+        leaves_of[c.fiber].push_back(hp.leaves[li]);
+      }
+      for (int f = 1; f < pb.M && equal; ++f) {
+        if (leaves_of[f].size() != leaves_of[0].size()) { equal = false; break; }
+        for (size_t j = 0; j < leaves_of[f].size() && equal; ++j) {
+          const Cell& a = hp.cells[leaves_of[0][j]];
+          const Cell& b = hp.cells[leaves_of[f][j]];
+          if (std::fabs((a.cx - pb.centres[0]) - (b.cx - pb.centres[2 * f])) > 1e-12 ||
+              std::fabs((a.cy - pb.centres[1]) - (b.cy - pb.centres[2 * f + 1])) > 1e-12 ||
+              a.eend - a.ebeg != b.eend - b.ebeg) {
+            equal = false;
+            break;
+          }
+          for (int t = 0; t < a.eend - a.ebeg; ++t)
+            if (hp.elem_of[a.ebeg + t] != hp.elem_of[b.ebeg + t] - f * pb.N) { equal = false; break; }
+        }
+      }
+    }
+    std::vector<int> uniq, cp_len;
+    std::vector<long long> cp_src, cp_dst;
+    if (equal) {
+      std::map<std::array<long long, 4>, int> first;
+      for (int q = 0; q < npairs; ++q) {
+        const Cell& D = hp.cells[hp.leaves[hp.near_tgt[q]]];
+        const Cell& C = hp.cells[hp.near_src[q]];
+        double ox = pb.centres[2 * C.fiber] - pb.centres[2 * D.fiber];
+        double oy = pb.centres[2 * C.fiber + 1] - pb.centres[2 * D.fiber + 1] + hp.near_m[q] * pb.H;
+        std::array<long long, 4> key = {local[hp.leaves[hp.near_tgt[q]]], local[hp.near_src[q]],
+                                        std::llround(ox * 1e9), std::llround(oy * 1e9)};
+        auto it = first.find(key);
+        if (it == first.end()) {
+          first.emplace(key, q);
+          uniq.push_back(q);
+        } else {
+          int r = it->second;
+          cp_src.push_back(hp.near_blk[r]);
+          cp_dst.push_back(hp.near_blk[q]);
+          cp_len.push_back(4 * (D.eend - D.ebeg) * (C.eend - C.ebeg));
+        }
+      }
+    }
+    pb.n_near_uniq = equal ? (int)uniq.size() : npairs;
+    pb.n_near_copies = (int)cp_src.size();
+    if (equal) {
+      CK(upload(&pb.d_near_uniq, uniq));
+      CK(upload(&pb.d_near_cp_src, cp_src)); CK(upload(&pb.d_near_cp_dst, cp_dst));
+      CK(upload(&pb.d_near_cp_len, cp_len));
+    }
+  }
+  {
     // flattened source columns of every target leaf's near list, in storage order
     int nl = (int)hp.leaves.size();
     std::vector<int> cptr(nl + 1, 0), cpsi, cm;
@@ -420,6 +486,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_tmp, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gin, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_ir_aug, MB * n * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_cperp, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
   pb.red_blocks = (int)std::min<size_t>(256, (n + 511) / 512);
   CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 255) / 256) * sizeof(double)));
@@ -768,17 +835,15 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
   // after the Givens rotations of the Hessenberg matrix (also applied to g,
   // giving s), to the scalar alpha = conj(s_j1) t_j1 / (|s_j1|^2 + |c_perp|^2)
   // and the residual |t_j1| |c_perp| / sqrt(|s_j1|^2 + |c_perp|^2), never more
-  // than the plain GMRES estimate |t_j1|.
+  // than the plain GMRES estimate |t_j1|.  c_perp is kept as a vector (each
+  // new basis vector projected out, modified Gram-Schmidt) so that its norm
+  // does not suffer the cancellation of ||c||^2 - ||g||^2.
   cd* Cv = pb.d_tmp;                             // c = A u
-  std::vector<double> cc(B, 0.0), gsum(B, 0.0);
+  cd* Cp = pb.d_cperp;                           // c_perp
+  std::vector<double> cp2(B, 0.0);
   std::vector<C> sv((size_t)B * (m + 1)), alpha(B, 0.0);
   bool augmenting = aug != nullptr;
-  if (augmenting) {
-    HIPCHK(pb, apply(aug, Cv));
-    std::vector<double> cn(B);
-    HIPCHK(pb, sync_norms(Cv, cn));
-    for (int i = 0; i < B; ++i) cc[i] = cn[i] * cn[i];
-  }
+  if (augmenting) HIPCHK(pb, apply(aug, Cv));
   bool first = true;
   while (true) {
     // true residuals R = b - A x
@@ -829,13 +894,14 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
     // V_0 = R / ||R|| per member (the squared norms are still in d_hcol)
     HIPCHK(pb, launch_normalize_b(pb, B, V, R, nb, hc, hs, n));
     if (augmenting) {
-      // g_0 = v_0^H c
-      HIPCHK(pb, launch_dots_b(pb, B, V, nb, nb, 1, Cv, nb, n, hc, hs));
+      // g_0 = v_0^H c, c_perp = c - g_0 v_0
+      HIPCHK(pb, hipMemcpyAsync(Cp, Cv, (size_t)B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      HIPCHK(pb, launch_project_out(pb, B, V, Cp, nb, n, hc, hc + 1, hs));
       HIPCHK(pb, hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream));
       HIPCHK(pb, hipStreamSynchronize(pb.stream));
       for (int i = 0; i < B; ++i) {
         sv[(size_t)i * (m + 1)] = C(hh[i * hs].x, hh[i * hs].y);
-        gsum[i] = std::norm(sv[(size_t)i * (m + 1)]);
+        cp2[i] = std::max(0.0, hh[i * hs + 1].x);
       }
     }
     int budget = 0;      // iterations any member may still take
@@ -855,8 +921,9 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       cd* hcol = pb.d_hall + (size_t)j * B * hs2;
       e = launch_arnoldi_step(pb, B, V, ldv, nb, j, Wj, nb, n, hcol, hs2);
       if (e != hipSuccess || !augmenting) return e;
-      // g_{j+1} = v_{j+1}^H c into slot 2j+3 of the column
-      return launch_dots_b(pb, B, Wj, nb, nb, 1, Cv, nb, n, hcol + 2 * (j + 1) + 1, hs2);
+      // g_{j+1} = v_{j+1}^H c_perp into slot 2j+3, c_perp -= g_{j+1} v_{j+1},
+      // ||c_perp||^2 into slot 2j+4
+      return launch_project_out(pb, B, Wj, Cp, nb, n, hcol + 2 * (j + 1) + 1, hcol + 2 * (j + 1) + 2, hs2);
     };
     auto readback = [&](int j0, int j1) -> hipError_t {
       return hipMemcpyAsync(pb.h_hall + (size_t)j0 * B * hs2, pb.d_hall + (size_t)j0 * B * hs2,
@@ -930,14 +997,13 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
           if (augmenting) {
             C* s_ = &sv[(size_t)i * (m + 1)];
             C gnew(hv[2 * (j + 1) + 1].x, hv[2 * (j + 1) + 1].y);
-            gsum[i] += std::norm(gnew);
+            cp2[i] = std::max(0.0, hv[2 * (j + 1) + 2].x);
             C a2 = s_[j];
             s_[j] = csi[j] * a2 + sni[j] * gnew;
             s_[j + 1] = -std::conj(sni[j]) * a2 + csi[j] * gnew;
-            double cp2 = std::max(0.0, cc[i] - gsum[i]);
-            double den = std::norm(s_[j + 1]) + cp2;
+            double den = std::norm(s_[j + 1]) + cp2[i];
             alpha[i] = den > 0 ? std::conj(s_[j + 1]) * gi[j + 1] / den : C(0.0);
-            double r2 = den > 0 ? std::norm(gi[j + 1]) * cp2 / den : 0.0;
+            double r2 = den > 0 ? std::norm(gi[j + 1]) * cp2[i] / den : 0.0;
             est = std::sqrt(r2) / bnorm[i];
           }
           if (est <= 0.7 * tol || gs[i].iters >= max_iter || hn == 0.0) cyc[i] = 0;
@@ -1224,6 +1290,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->theta = pb.theta;
   st->lattice_q = pb.lattice_q;
   st->p2p_split = pb.p2p_split;
+  st->n_near_computed = pb.d_near_uniq ? pb.n_near_uniq : (int)hp.near_src.size();
   return PFM_OK;
 }
 

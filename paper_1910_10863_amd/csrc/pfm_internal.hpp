@@ -92,6 +92,11 @@ struct Problem {
   int *d_m2li_ptr = nullptr, *d_m2li_src = nullptr, *d_m2li_off = nullptr;
   int *d_near_ptr = nullptr, *d_near_src = nullptr, *d_near_m = nullptr, *d_near_tgt = nullptr;
   long long *d_near_blk = nullptr;
+  // equal fibres: near pairs whose blocks are computed, and copies of them
+  int *d_near_uniq = nullptr;           // pair ids to compute (nullptr: all pairs)
+  long long *d_near_cp_src = nullptr, *d_near_cp_dst = nullptr;   // block offsets (entries)
+  int *d_near_cp_len = nullptr;         // complex values per copied block
+  int n_near_uniq = 0, n_near_copies = 0;
   int *d_cols_ptr = nullptr;            // per leaf: range of its flattened near source columns
   int *d_col_psi = nullptr;             // flattened near source columns: index of phi in Psi
   int *d_col_m = nullptr;               // image index m of each flattened near source column
@@ -102,6 +107,7 @@ struct Problem {
   float2 *d_near32 = nullptr;           // near blocks, complex64 (PFM_MIXED)
   cd *d_ir_r = nullptr, *d_ir_d = nullptr;   // refinement residual and correction
   cd *d_ir_aug = nullptr;               // augmentation vectors of the first GMRES cycle [member][2E]
+  cd *d_cperp = nullptr;                // their images A u with the Krylov basis projected out
   cd *d_htab = nullptr;                 // [2 ch][n_tab][4p+1]
   cd *d_jtab = nullptr;                 // [2 ch][n_joff][4p+1]
   cd *d_lat = nullptr;                  // = d_htab + n_off rows: lattice sums [n_roff][4p+1]

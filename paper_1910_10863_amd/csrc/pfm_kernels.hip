@@ -123,6 +123,7 @@ struct NearArgs {
   int m_min;
   long long n_entries;
   cd* out;
+  const int* pair_ids;     // pair of each workgroup row (nullptr: blockIdx.x)
 };
 
 __device__ inline void far_rule(double kap, double x, double y, double nux, double nuy,
@@ -143,7 +144,7 @@ __device__ inline void far_rule(double kap, double x, double y, double nux, doub
 }
 
 __global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
-  int q = blockIdx.x;
+  int q = A.pair_ids ? A.pair_ids[blockIdx.x] : blockIdx.x;
   int D = A.leaves[A.near_tgt[q]];
   int C = A.near_src[q];
   int m = A.near_m[q];
@@ -198,6 +199,15 @@ __global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
   }
 }
 
+// copy of computed near blocks into the slots of the pairs that share them
+__global__ void k_copy_blocks(const long long* __restrict__ src, const long long* __restrict__ dst,
+                              const int* __restrict__ len, cd* blocks) {
+  int c = blockIdx.x;
+  const cd* s = blocks + 4 * src[c];
+  cd* d = blocks + 4 * dst[c];
+  for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < len[c]; i += gridDim.y * blockDim.x) d[i] = s[i];
+}
+
 hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   const HostPlan& hp = pb.hp;
   int npairs = (int)hp.near_src.size();
@@ -220,7 +230,12 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   A.n_entries = hp.n_near_entries;
   A.out = pb.d_near;
   int lm = pb.opt.leaf_max;
-  hipLaunchKernelGGL(k_near_blocks, dim3(npairs, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
+  A.pair_ids = pb.d_near_uniq;
+  int nrows = pb.d_near_uniq ? pb.n_near_uniq : npairs;
+  hipLaunchKernelGGL(k_near_blocks, dim3(nrows, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
+  if (pb.n_near_copies > 0)
+    hipLaunchKernelGGL(k_copy_blocks, dim3(pb.n_near_copies, (4 * lm * lm + 255) / 256), dim3(256), 0, pb.stream,
+                       pb.d_near_cp_src, pb.d_near_cp_dst, pb.d_near_cp_len, pb.d_near);
   return hipGetLastError();
 }
 
@@ -1563,6 +1578,43 @@ hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, l
   }
   hipLaunchKernelGGL(k_normalize_fused, gu, dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nu, hcol + 2 * cnt, hsb,
                      n);
+  return hipGetLastError();
+}
+
+// out[b * osb] = (sum of the np partials of member b, 0)
+__global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ npart, int np, cd* out, long long osb) {
+  __shared__ double sn[256];
+  const int b = blockIdx.x;
+  double q = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) q += npart[(size_t)b * np + k];
+  sn[threadIdx.x] = q;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sn[threadIdx.x] += sn[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b * osb] = mkc(sn[0], 0.0);
+}
+
+// For B members: g = v^H c; c -= g v; g stored at gout + b*hsb and ||c||^2
+// at nout + b*hsb (v, c: member stride wsb).
+hipError_t launch_project_out(Problem& pb, int B, const cd* v, cd* c, long long wsb, int n, cd* gout, cd* nout,
+                              long long hsb) {
+  const int nblk = pb.red_blocks;
+  const int nu = (n + 255) / 256;
+  dim3 gd(nblk, 1, B), gu(nu, B);
+  hipLaunchKernelGGL(k_dots, gd, dim3(RED_THREADS), 0, pb.stream, v, wsb, wsb, 1, c, wsb, n, pb.d_red);
+  const cd* part = pb.d_red;
+  int np = nblk;
+  if (nblk > 32) {
+    cd* fin = pb.d_red + (size_t)B * nblk;
+    hipLaunchKernelGGL(k_dots_final, dim3(1, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, 1, fin, 1LL);
+    part = fin;
+    np = 1;
+  }
+  hipLaunchKernelGGL(k_update_fused, gu, dim3(256), 0, pb.stream, c, wsb, v, wsb, wsb, 1, part, np, gout, hsb, n,
+                     pb.d_npart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(256), 0, pb.stream, pb.d_npart, nu, nout, hsb);
   return hipGetLastError();
 }
 

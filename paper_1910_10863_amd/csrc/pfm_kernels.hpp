@@ -41,6 +41,9 @@ hipError_t launch_gemv_acc_b(Problem& pb, int B, cd* x, long long xsb, const cd*
 // one CGS2 Arnoldi step of B members (fused: five launches)
 hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int j, cd* W,
                                long long wsb, int n, cd* hcol, long long hsb);
+// B members: g = v^H c, c -= g v, store g and ||c||^2 (augmented GMRES)
+hipError_t launch_project_out(Problem& pb, int B, const cd* v, cd* c, long long wsb, int n, cd* gout, cd* nout,
+                              long long hsb);
 hipError_t launch_normalize_b(Problem& pb, int B, cd* out, const cd* in, long long sb, const cd* d_nrm,
                               long long nsb, int n);
 hipError_t launch_gemv_acc(Problem& pb, cd* x, const cd* V, long long ldv, int cnt, const cd* d_c, int n);

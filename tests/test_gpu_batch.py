@@ -185,3 +185,28 @@ def test_autotuner_choice_meets_target(pfm):
         A, _ = _dense("sq2x2", 5.0, th[b])
         ref = A @ psi[b].cpu().numpy()
         assert np.linalg.norm(y[b] - ref) / np.linalg.norm(ref) < 1e-9
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_equal_fibres_share_near_blocks(pfm, batch):
+    """Equal radii: near blocks that differ by a translation are computed once
+    and copied.  A block whose last radius is one ulp larger computes every
+    block; the two operators agree to rounding."""
+    radii = np.full(4, 0.3)
+    bumped = radii.copy()
+    bumped[-1] = np.nextafter(0.3, 1.0)
+    ys, counts = [], []
+    for r in (radii, bumped):
+        wl = W.small_square(2, 2, 64, 0.3, 2.0, 0.3, radii=r)
+        pb = pfm.Problem.from_workload(wl, p=24, leaf_max=16, max_batch=2)
+        psi = torch.tensor(np.stack([W.random_density(pb.n, 70 + b) for b in range(2)]), device="cuda")
+        if batch:
+            pb.set_batch(2.0, [0.3, -0.7])
+            ys.append(pb.matvec_batch(psi).cpu().numpy())
+        else:
+            pb.set_wave(2.0, 0.3)
+            ys.append(pb.matvec(psi[0].contiguous()).cpu().numpy())
+        counts.append((pb.stats()["n_near_computed"], pb.stats()["n_near_pairs"]))
+    _say("near pairs computed / total:", counts)
+    assert counts[0][0] < counts[0][1] and counts[1][0] == counts[1][1]
+    assert np.max(np.abs(ys[0] - ys[1])) < 1e-12 * np.max(np.abs(ys[1]))
