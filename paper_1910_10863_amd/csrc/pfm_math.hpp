@@ -1,6 +1,7 @@
 // Complex arithmetic and FP64 cylinder functions for the FMM (host + device).
 //
 // Special functions are written from the series and expansions of the DLMF:
+//   * J0, J1, Y0, Y1 by their ascending series for x <= 2,
 //   * J0, J1 by Miller's backward recurrence normalised by
 //     J0 + 2 sum_k J_2k = 1 (DLMF 10.12.4 at theta = 0, 3.6),
 //   * Y0 from the same J values by Neumann's series
@@ -80,8 +81,45 @@ __host__ __device__ __forceinline__ cd cpowi(cd a, int n) {
 constexpr double PI = 3.14159265358979323846;
 constexpr double EULER_GAMMA = 0.57721566490153286061;
 
+// J0, J1, Y0, Y1 for 0 < x <= 2 by their ascending series (DLMF 10.2.2, 10.8.1;
+// Abramowitz & Stegun 9.1.10-9.1.11), q = x^2/4:
+//   J0 = sum_k (-q)^k / (k!)^2,  J1 = (x/2) sum_k (-q)^k / (k! (k+1)!),
+//   Y0 = (2/pi) (ln(x/2) + gamma) J0 + (2/pi) sum_{k>=1} (-1)^{k+1} H_k q^k / (k!)^2,
+//   Y1 = -2/(pi x) + (2/pi) ln(x/2) J1 - (x/(2 pi)) sum_k (psi(k+1) + psi(k+2)) (-q)^k / (k! (k+1)!),
+// with H_k the harmonic numbers and psi(k+1) = H_k - gamma.  For q <= 1 the
+// terms fall below 1e-18 of the sum after 14 of them; the fixed count keeps
+// the lanes of a wavefront together.
+__host__ __device__ inline void bessel_jy01_series(double x, double& J0, double& J1, double& Y0, double& Y1) {
+  const double q = 0.25 * x * x;
+  double t0 = 1.0, t1 = 1.0;          // (-q)^k/(k!)^2 and (-q)^k/(k!(k+1)!)
+  double sj0 = 1.0, sj1 = 1.0;
+  double sy0 = 0.0;                   // sum (-1)^{k+1} H_k q^k/(k!)^2 = -sum H_k t0
+  double sy1 = 1.0 - 2.0 * EULER_GAMMA; // k = 0 term: psi(1) + psi(2) = 1 - 2 gamma
+  double hk = 0.0;
+#pragma unroll
+  for (int k = 1; k <= 14; ++k) {
+    t0 *= -q * (1.0 / ((double)k * (double)k));
+    t1 *= -q * (1.0 / ((double)k * (double)(k + 1)));
+    hk += 1.0 / (double)k;
+    sj0 += t0;
+    sj1 += t1;
+    sy0 -= hk * t0;
+    // psi(k+1) + psi(k+2) = 2 H_k + 1/(k+1) - 2 gamma
+    sy1 += (2.0 * hk + 1.0 / (double)(k + 1) - 2.0 * EULER_GAMMA) * t1;
+  }
+  const double lg = log(0.5 * x);
+  J0 = sj0;
+  J1 = 0.5 * x * sj1;
+  Y0 = (2.0 / PI) * ((lg + EULER_GAMMA) * J0 + sy0);
+  Y1 = -2.0 / (PI * x) + (2.0 / PI) * lg * J1 - (0.5 * x / PI) * sy1;
+}
+
 // J0, J1, Y0, Y1 for x > 0.
 __host__ __device__ inline void bessel_jy01(double x, double& J0, double& J1, double& Y0, double& Y1) {
+  if (x <= 2.0) {
+    bessel_jy01_series(x, J0, J1, Y0, Y1);
+    return;
+  }
   if (x > 25.0) {
     // Hankel's expansion H_nu(x) ~ sqrt(2/(pi x)) e^{i w} sum_k i^k a_k(nu) / x^k,
     // a_k(nu) = prod_{j=1..k} (4 nu^2 - (2j-1)^2) / (k! 8^k),  w = x - nu pi/2 - pi/4.
