@@ -702,6 +702,16 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
   }
 }
 
+// The value of lane `lane` (wave-uniform) of a complex register, through the
+// scalar unit (four 32-bit lane reads); every lane receives it without LDS.
+__device__ __forceinline__ cd lane_cd(cd v, int lane) {
+  long long xr = __double_as_longlong(v.x), yr = __double_as_longlong(v.y);
+  int xl = __builtin_amdgcn_readlane((int)xr, lane), xh = __builtin_amdgcn_readlane((int)(xr >> 32), lane);
+  int yl = __builtin_amdgcn_readlane((int)yr, lane), yh = __builtin_amdgcn_readlane((int)(yr >> 32), lane);
+  return mkc(__longlong_as_double(((long long)xh << 32) | (unsigned int)xl),
+             __longlong_as_double(((long long)yh << 32) | (unsigned int)yl));
+}
+
 // M2M, directly from the leaves: every non-leaf cell C gathers the moments of
 // the leaves below it, M_n(C) = sum_L sum_l M_l(L) Jm_{n-l}(kap (O_L - O_C))
 // (Graf's theorem for J, eq. 10, as in the M2M translation of Sec. 3.2,
@@ -715,7 +725,7 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
                                              const cd* __restrict__ jtab, int n_joff, cd* mpole,
                                              long long mp_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
-  __shared__ cd sm[4][NP], sj[4][NT];
+  __shared__ cd sj[4][NT];
   __shared__ cd sr[4][NP];
   mpole += blockIdx.z * mp_stride;              // batch member
   int ci = blockIdx.x, ch = blockIdx.y;
@@ -726,16 +736,24 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
   for (int q = ptr[ci] + w; q < ptr[ci + 1]; q += 4) {
     const cd* ms = mpole + ((size_t)src[q] * 2 + ch) * NP;
     const cd* tj = jtab + ((size_t)ch * n_joff + off[q]) * NT;
-    for (int i = lane; i < NP; i += 64) sm[w][i] = ms[i];
+    // the leaf's moments stay in registers and reach the lanes by lane reads
+    cd mreg[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) mreg[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
     for (int i = lane; i < NT; i += 64) sj[w][i] = tj[i];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
+#pragma unroll
     for (int i = 0; i < NU; ++i) {
-      int n = lane + 64 * i - P;
-      if (n > P) break;
+      int n = min(lane + 64 * i - P, P);      // lanes past the last order repeat it
       cd s = acc[i];
-      for (int l = -P; l <= P; ++l) s = cfma_conj(sj[w][n - l + 2 * P], sm[w][l + P], s);
+#pragma unroll
+      for (int sl = 0; sl < NU; ++sl) {
+        const int hi = NP < 64 * sl + 64 ? NP : 64 * sl + 64;
+        for (int idx = 64 * sl; idx < hi; ++idx)
+          s = cfma_conj(sj[w][n - idx + 3 * P], lane_cd(mreg[sl], idx - 64 * sl), s);
+      }
       acc[i] = s;
     }
     __builtin_amdgcn_wave_barrier();
@@ -765,7 +783,7 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
                                             long long mp_stride, long long part_stride, long long tab_stride,
                                             int alpha_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
-  __shared__ cd sm[NP], sh[NT];
+  __shared__ cd sh[NT];
   // batch member: its multipoles, partial sums, lattice rows and image phases
   mpole += blockIdx.y * mp_stride;
   part += blockIdx.y * part_stride;
@@ -773,27 +791,39 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   alpha += blockIdx.y * alpha_stride;
   int c = blockIdx.x;
   int ch = chunks[4 * c + 1], b = chunks[4 * c + 2], e = b + chunks[4 * c + 3];
-  cd acc[(NP + 63) / 64];
-  for (int i = 0; i < (NP + 63) / 64; ++i) acc[i] = mkc(0, 0);
+  constexpr int NU = (NP + 63) / 64;
+  const int lane = threadIdx.x;
+  cd acc[NU];
+  for (int i = 0; i < NU; ++i) acc[i] = mkc(0, 0);
   for (int q = b; q < e; ++q) {
     const cd* ms = mpole + ((size_t)e_src[q] * 2 + ch) * NP;
     const cd* th = htab + ((size_t)ch * n_tab + e_off[q]) * NT;
-    for (int i = threadIdx.x; i < NP; i += 64) sm[i] = ms[i];
-    for (int i = threadIdx.x; i < NT; i += 64) sh[i] = th[i];
+    // the source moments stay in registers (order n in lane n % 64 of slot
+    // n / 64) and reach every lane through lane reads; only the translation
+    // row goes through LDS
+    cd mreg[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) mreg[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
+    for (int i = lane; i < NT; i += 64) sh[i] = th[i];
     cd ph = alpha[e_m[q] - m_min];
     __syncthreads();
-    for (int i = 0; i < (NP + 63) / 64; ++i) {
-      int l = threadIdx.x + 64 * i - P;
-      if (l > P) break;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      int l = min(lane + 64 * i - P, P);      // lanes past the last order repeat it
       cd s = mkc(0, 0);
-      for (int n = -P; n <= P; ++n) s = cfma(sh[n - l + 2 * P], sm[n + P], s);
+#pragma unroll
+      for (int sl = 0; sl < NU; ++sl) {
+        const int hi = NP < 64 * sl + 64 ? NP : 64 * sl + 64;
+        for (int idx = 64 * sl; idx < hi; ++idx)
+          s = cfma(sh[idx - P - l + 2 * P], lane_cd(mreg[sl], idx - 64 * sl), s);
+      }
       acc[i] = cfma(ph, s, acc[i]);
     }
     __syncthreads();
   }
   cd* out = part + (size_t)c * NP;
-  for (int i = 0; i < (NP + 63) / 64; ++i) {
-    int l = threadIdx.x + 64 * i;
+  for (int i = 0; i < NU; ++i) {
+    int l = lane + 64 * i;
     if (l < NP) out[l] = acc[i];
   }
 }
@@ -818,7 +848,7 @@ __global__ void __launch_bounds__(128) k_down(
     const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1, double eta,
     double varrho, cd* __restrict__ far, long long part_stride, long long far_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
-  __shared__ cd sA[2][NP], sJ[2][NT], sL[2][NP];
+  __shared__ cd sJ[2][NT], sL[2][NP];
   __shared__ cd su[64], sd[64];
   part += blockIdx.y * part_stride;             // batch member
   far += blockIdx.y * far_stride;
@@ -841,21 +871,31 @@ __global__ void __launch_bounds__(128) k_down(
     int A = anc[q];
     int c0 = cc_ptr[ch * nc + A], c1 = cc_ptr[ch * nc + A + 1];
     if (c1 == c0) continue;                      // wave-uniform
-    for (int i = lane; i < NP; i += 64) {
+    // the ancestor's own sum, order l in lane l % 64 of slot l / 64
+    cd areg[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      int i = lane + 64 * u;
       cd sres = mkc(0, 0);
-      for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
-      sA[ch][i] = sres;
+      if (i < NP)
+        for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
+      areg[u] = sres;
     }
     const cd* tj = jtab + ((size_t)ch * n_joff + aoff[q]) * NT;
     for (int i = lane; i < NT; i += 64) sJ[ch][i] = tj[i];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
+#pragma unroll
     for (int u = 0; u < NU; ++u) {
-      int n = lane + 64 * u - P;
-      if (n > P) break;
+      int n = min(lane + 64 * u - P, P);      // lanes past the last order repeat it
       cd sres = acc[u];
-      for (int l = -P; l <= P; ++l) sres = cfma(sA[ch][l + P], sJ[ch][l - n + 2 * P], sres);
+#pragma unroll
+      for (int sl = 0; sl < NU; ++sl) {
+        const int hi = NP < 64 * sl + 64 ? NP : 64 * sl + 64;
+        for (int idx = 64 * sl; idx < hi; ++idx)
+          sres = cfma(lane_cd(areg[sl], idx - 64 * sl), sJ[ch][idx - n + P], sres);
+      }
       acc[u] = sres;
     }
     __builtin_amdgcn_wave_barrier();
