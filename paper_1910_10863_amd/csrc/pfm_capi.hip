@@ -67,7 +67,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_mx); dfree(pb.d_my); dfree(pb.d_tx); dfree(pb.d_ty); dfree(pb.d_h);
   dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx);
   dfree(pb.d_e_src); dfree(pb.d_e_off); dfree(pb.d_e_m); dfree(pb.d_chunks); dfree(pb.d_cc_ptr);
-  dfree(pb.d_part);
+  dfree(pb.d_part); dfree(pb.d_epart); dfree(pb.d_mchunks);
   dfree(pb.d_up_cells); dfree(pb.d_up_ptr); dfree(pb.d_up_src); dfree(pb.d_up_off);
   dfree(pb.d_anc_ptr); dfree(pb.d_anc); dfree(pb.d_anc_off); dfree(pb.d_far);
   dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
@@ -426,10 +426,11 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_latpart, MB * n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd)));
   (void)n_off;
   {
-    // M2L work list: per (channel, cell) the entries (source cell, table row, image),
-    // cut into chunks of at most M2L_CHUNK entries
-    const int M2L_CHUNK = 2;
-    std::vector<int> esrc, eoff, em, chunks, ccptr(2 * (size_t)nc + 1, 0);
+    // M2L work: per (channel, cell) the entries (source cell, table row, image),
+    // contiguous, cut into chunks of at most M2L_CHUNK entries (one wavefront
+    // each); one sum per (channel, cell) with entries adds its chunks' partial
+    // expansions in order, so the downward pass reads one sum per cell.
+    std::vector<int> esrc, eoff, em, mchunks, sums, ccptr(2 * (size_t)nc + 1, 0);
     std::vector<int> fibre_of_root(nc, -1);
     for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;
     for (int ch = 0; ch < 2; ++ch) {
@@ -452,17 +453,24 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
           }
         }
         int last = (int)esrc.size();
+        int chunk0 = (int)(mchunks.size() / 4);
         for (int b = first; b < last; b += M2L_CHUNK) {
-          chunks.push_back(c); chunks.push_back(ch); chunks.push_back(b);
-          chunks.push_back(std::min(M2L_CHUNK, last - b));
+          mchunks.push_back(c); mchunks.push_back(ch); mchunks.push_back(b);
+          mchunks.push_back(std::min(M2L_CHUNK, last - b));
         }
-        ccptr[(size_t)ch * nc + c + 1] = (int)(chunks.size() / 4);
+        int chunk1 = (int)(mchunks.size() / 4);
+        if (chunk1 > chunk0) {
+          sums.push_back(c); sums.push_back(ch); sums.push_back(chunk0); sums.push_back(chunk1 - chunk0);
+        }
+        ccptr[(size_t)ch * nc + c + 1] = (int)(sums.size() / 4);
       }
     }
-    pb.n_chunks = (int)(chunks.size() / 4);
+    pb.n_chunks = (int)(sums.size() / 4);
+    pb.n_mchunks = (int)(mchunks.size() / 4);
     CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
-    CK(upload(&pb.d_chunks, chunks)); CK(upload(&pb.d_cc_ptr, ccptr));
+    CK(upload(&pb.d_mchunks, mchunks)); CK(upload(&pb.d_chunks, sums)); CK(upload(&pb.d_cc_ptr, ccptr));
     CK(hipMalloc((void**)&pb.d_part, MB * std::max(1, pb.n_chunks) * NP * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_epart, MB * std::max(1, pb.n_mchunks) * NP * sizeof(cd)));
   }
   {
     CK(upload(&pb.d_up_cells, hp.up_cells)); CK(upload(&pb.d_up_ptr, hp.up_ptr));

@@ -25,6 +25,9 @@ struct Cell {
 };
 
 struct M2LEntry { int tgt, src, off, m; };
+
+// M2L entries are processed in chunks of at most this many entries of one (channel, cell)
+constexpr int M2L_CHUNK = 2;
 struct NearEntry { int tgt_leaf, src, m; };
 
 struct HostPlan {
@@ -114,10 +117,13 @@ struct Problem {
   // M2L work split into chunks of at most M2L_CHUNK entries of one (cell, channel);
   // exterior entries of a root cell include one lattice entry per source fibre
   int *d_e_src = nullptr, *d_e_off = nullptr, *d_e_m = nullptr;
-  int *d_chunks = nullptr;              // [n_chunks][4]: cell, channel, first entry, count
+  int *d_chunks = nullptr;              // [n_chunks][4]: cell, channel, first entry chunk, chunk count (one per (ch, cell) with entries)
   int *d_cc_ptr = nullptr;              // [2*n_cells+1]: chunks of (channel, cell)
-  cd *d_part = nullptr;                 // [n_chunks][2p+1] partial local expansions
+  cd *d_part = nullptr;                 // [n_chunks][2p+1] M2L sums of each (channel, cell)
   int n_chunks = 0;
+  int *d_mchunks = nullptr;             // [n_mchunks][4]: cell, channel, first entry, count (<= 2 entries)
+  int n_mchunks = 0;
+  cd *d_epart = nullptr;                // [n_mchunks][2p+1] M2L result of each entry chunk
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
   int p2p_unroll = 1;                   // source columns in flight per P2P wavefront

@@ -557,13 +557,14 @@ hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream
 // ===========================================================================
 
 // Distances between consecutive members of a batch in the per-member buffers.
-struct BatchStrides { long long vec, mpole, part, tab; int alpha; };
+struct BatchStrides { long long vec, mpole, part, epart, tab; int alpha; };
 static BatchStrides batch_strides(const Problem& pb) {
   const int NP = 2 * pb.opt.p + 1, NT = 4 * pb.opt.p + 1;
   BatchStrides s;
   s.vec = 2LL * pb.E;
   s.mpole = (long long)pb.hp.cells.size() * 2 * NP;
   s.part = (long long)std::max(1, pb.n_chunks) * NP;
+  s.epart = (long long)std::max(1, pb.n_mchunks) * NP;
   s.tab = 2LL * pb.n_tab * NT;
   s.alpha = pb.hp.m_max - pb.hp.m_min + 1;
   return s;
@@ -772,8 +773,8 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
 // where T_t is Hp_nu(kap d) of an explicit pair (channel 0: exterior, with
 // image m; channel 1: interior) or, for the roots, the lattice sum
 // S_nu(c_i - c_j) that carries every far image of fibre j (Sec. 3.3).
-// One wavefront per chunk; the partial sums are reduced in a fixed order by
-// k_down, so the result does not depend on scheduling.
+// One wavefront per chunk; k_m2l_sum adds the chunks of each (channel, cell)
+// in a fixed order, so the result does not depend on scheduling.
 template <int P>
 __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, const int* __restrict__ e_src,
                                             const int* __restrict__ e_off, const int* __restrict__ e_m,
@@ -826,6 +827,31 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
     int l = lane + 64 * i;
     if (l < NP) out[l] = acc[i];
   }
+}
+
+// The M2L sum of each (channel, cell) with entries: the partial expansions
+// of its chunks, their range cut into four consecutive quarters (one per
+// wavefront, added in order with eight loads in flight), the quarters then
+// added in order.  The downward pass then reads one sum per cell.
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l_sum(const int* __restrict__ sums, const cd* __restrict__ epart,
+                                                 cd* __restrict__ part, long long ep_stride, long long part_stride) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd sq[4][NP];
+  epart += blockIdx.y * ep_stride;
+  part += blockIdx.y * part_stride;
+  const int c = blockIdx.x, first = sums[4 * c + 2], cnt = sums[4 * c + 3];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q0 = first + (cnt * w) / 4, q1 = first + (cnt * (w + 1)) / 4;
+  for (int l = lane; l < NP; l += 64) {
+    cd s = mkc(0, 0);
+#pragma unroll 8
+    for (int e = q0; e < q1; ++e) s = cadd(s, epart[(size_t)e * NP + l]);
+    sq[w][l] = s;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < NP; l += 256)
+    part[(size_t)c * NP + l] = cadd(cadd(sq[0][l], sq[1][l]), cadd(sq[2][l], sq[3][l]));
 }
 
 // Downward pass and L2P, one workgroup of two wavefronts (channels) per leaf.
@@ -1234,10 +1260,13 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                        pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
-  if (pb.n_chunks > 0)
-    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_chunks, B), dim3(64), 0, s, pb.d_chunks, pb.d_e_src, pb.d_e_off,
-                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_part, bs.mpole,
-                       bs.part, bs.tab, bs.alpha);
+  if (pb.n_mchunks > 0) {
+    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_mchunks, B), dim3(64), 0, s, pb.d_mchunks, pb.d_e_src, pb.d_e_off,
+                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
+                       bs.epart, bs.tab, bs.alpha);
+    hipLaunchKernelGGL(k_m2l_sum<P>, dim3(pb.n_chunks, B), dim3(256), 0, s, pb.d_chunks, pb.d_epart, pb.d_part,
+                       bs.epart, bs.part);
+  }
   if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, nc, pb.d_leaves, pb.d_anc_ptr, pb.d_anc,
                      pb.d_anc_off, pb.d_cc_ptr, pb.d_part, pb.d_jtab, n_joff, pb.d_ebeg, pb.d_eend,
