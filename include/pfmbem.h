@@ -142,11 +142,14 @@ typedef struct {
   long long n_near_cols;       /* sum over near leaf pairs of source elements */
   int n_root_offsets;          /* distinct fibre offsets of the lattice M2L */
   int n_m2l_offsets;           /* distinct M2L translation vectors */
-  double near_bytes;           /* bytes of the stored P2P blocks */
+  double near_bytes;           /* bytes of the stored P2P blocks (n_near_stored x 64) */
   double k, k1, eta, varrho, theta;
   int lattice_q;               /* direct images of the lattice sums, |m| <= q */
   int p2p_split;               /* column splits per target leaf in the P2P launch */
   int n_near_computed;         /* near pairs whose blocks are computed (equal fibres share blocks) */
+  long long n_near_stored;     /* element pairs stored: with equal fibres, target leaves with the
+                                  same near region (the same sources at the same offsets and
+                                  images) read one stored copy of it */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

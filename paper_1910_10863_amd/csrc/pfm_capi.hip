@@ -287,19 +287,21 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(upload(&pb.d_m2li_off, hp.m2li_off));
   CK(upload(&pb.d_near_ptr, hp.near_ptr)); CK(upload(&pb.d_near_src, hp.near_src));
   CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
-  CK(upload(&pb.d_near_blk, hp.near_blk));
+  // near-block storage: with equal fibres, a region (the blocks of one target
+  // leaf's near list) is stored once for every leaf that has the same region
   {
     // Equal fibres (same radius, so the same chords and the same tree about
     // each centre): a near block depends only on the two leaves' places in
-    // their fibres' trees and on the offset between the fibres (image
-    // included).  Such blocks are computed once and copied.
+    // their fibres' trees, on the offset between the fibres and, through the
+    // quasi-periodic phase alpha^m, on the image m.
     const int npairs = (int)hp.near_src.size();
+    const int nl = (int)hp.leaves.size();
     bool equal = pb.M > 1 && npairs > 0;
     for (int f = 1; f < pb.M && equal; ++f) equal = pb.radii[f] == pb.radii[0];
     std::vector<std::vector<int>> leaves_of(pb.M);
     std::vector<int> local(hp.cells.size(), -1);
     if (equal) {
-      for (int li = 0; li < (int)hp.leaves.size(); ++li) {
+      for (int li = 0; li < nl; ++li) {
         const Cell& c = hp.cells[hp.leaves[li]];
         local[hp.leaves[li]] = (int)leaves_of[c.fiber].size();
         leaves_of[c.fiber].push_back(hp.leaves[li]);
@@ -320,31 +322,62 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         }
       }
     }
+    std::vector<long long> blk(npairs);
     std::vector<int> uniq, cp_len;
     std::vector<long long> cp_src, cp_dst;
+    long long stored = 0;
     if (equal) {
-      std::map<std::array<long long, 4>, int> first;
-      for (int q = 0; q < npairs; ++q) {
+      // key of a pair: (target's place, source's place, offset, image)
+      auto pair_key = [&](int q) {
         const Cell& D = hp.cells[hp.leaves[hp.near_tgt[q]]];
         const Cell& C = hp.cells[hp.near_src[q]];
         double ox = pb.centres[2 * C.fiber] - pb.centres[2 * D.fiber];
         double oy = pb.centres[2 * C.fiber + 1] - pb.centres[2 * D.fiber + 1] + hp.near_m[q] * pb.H;
-        std::array<long long, 4> key = {local[hp.leaves[hp.near_tgt[q]]], local[hp.near_src[q]],
-                                        std::llround(ox * 1e9), std::llround(oy * 1e9)};
-        auto it = first.find(key);
-        if (it == first.end()) {
-          first.emplace(key, q);
-          uniq.push_back(q);
-        } else {
-          int r = it->second;
-          cp_src.push_back(hp.near_blk[r]);
-          cp_dst.push_back(hp.near_blk[q]);
-          cp_len.push_back(4 * (D.eend - D.ebeg) * (C.eend - C.ebeg));
+        return std::array<long long, 5>{local[hp.leaves[hp.near_tgt[q]]], local[hp.near_src[q]],
+                                        std::llround(ox * 1e9), std::llround(oy * 1e9), (long long)hp.near_m[q]};
+      };
+      std::map<std::vector<long long>, int> region_first;
+      std::map<std::array<long long, 5>, long long> pair_first;
+      for (int li = 0; li < nl; ++li) {
+        std::vector<long long> rkey = {local[hp.leaves[li]]};
+        for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
+          auto k = pair_key(q);
+          rkey.insert(rkey.end(), k.begin() + 1, k.end());
+        }
+        auto it = region_first.find(rkey);
+        if (it != region_first.end()) {
+          const int lf = it->second;
+          for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q)
+            blk[q] = blk[hp.near_ptr[lf] + (q - hp.near_ptr[li])];
+          continue;
+        }
+        region_first.emplace(rkey, li);
+        const Cell& D = hp.cells[hp.leaves[li]];
+        for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
+          const Cell& C = hp.cells[hp.near_src[q]];
+          const long long len = (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
+          blk[q] = stored;
+          stored += len;
+          auto k = pair_key(q);
+          auto pf = pair_first.find(k);
+          if (pf == pair_first.end()) {
+            pair_first.emplace(k, blk[q]);
+            uniq.push_back(q);
+          } else {
+            cp_src.push_back(pf->second);
+            cp_dst.push_back(blk[q]);
+            cp_len.push_back((int)(4 * len));
+          }
         }
       }
+    } else {
+      blk = hp.near_blk;
+      stored = hp.n_near_entries;
     }
+    pb.n_near_stored = stored;
     pb.n_near_uniq = equal ? (int)uniq.size() : npairs;
     pb.n_near_copies = (int)cp_src.size();
+    CK(upload(&pb.d_near_blk, blk));
     if (equal) {
       CK(upload(&pb.d_near_uniq, uniq));
       CK(upload(&pb.d_near_cp_src, cp_src)); CK(upload(&pb.d_near_cp_dst, cp_dst));
@@ -404,7 +437,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_local, (size_t)nc * 2 * NP * sizeof(cd)));
   CK(hipMemset(pb.d_mpole, 0, MB * nc * 2 * NP * sizeof(cd)));
   CK(hipMemset(pb.d_local, 0, (size_t)nc * 2 * NP * sizeof(cd)));
-  size_t n_ent = std::max<long long>(1, hp.n_near_entries);
+  size_t n_ent = std::max<long long>(1, pb.n_near_stored);
   CK(hipMalloc((void**)&pb.d_near, 4 * n_ent * sizeof(cd)));
   if (pb.opt.precision == PFM_MIXED) {
     CK(hipMalloc((void**)&pb.d_near32, 4 * n_ent * sizeof(float2)));
@@ -1290,7 +1323,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
     st->n_near_cols += hp.cells[hp.near_src[q]].eend - hp.cells[hp.near_src[q]].ebeg;
   st->n_root_offsets = (int)hp.root_off_xy.size() / 2;
   st->n_m2l_offsets = (int)hp.off_xy.size() / 2;
-  st->near_bytes = 4.0 * 16.0 * (double)hp.n_near_entries;
+  st->near_bytes = 4.0 * 16.0 * (double)pb.n_near_stored;
   st->k = pb.k;
   st->k1 = pb.k1;
   st->eta = pb.eta;
@@ -1299,6 +1332,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->lattice_q = pb.lattice_q;
   st->p2p_split = pb.p2p_split;
   st->n_near_computed = pb.d_near_uniq ? pb.n_near_uniq : (int)hp.near_src.size();
+  st->n_near_stored = pb.n_near_stored;
   return PFM_OK;
 }
 

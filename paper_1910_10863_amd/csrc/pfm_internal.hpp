@@ -94,8 +94,12 @@ struct Problem {
   int *d_m2l_ptr = nullptr, *d_m2l_src = nullptr, *d_m2l_off = nullptr, *d_m2l_m = nullptr;
   int *d_m2li_ptr = nullptr, *d_m2li_src = nullptr, *d_m2li_off = nullptr;
   int *d_near_ptr = nullptr, *d_near_src = nullptr, *d_near_m = nullptr, *d_near_tgt = nullptr;
-  long long *d_near_blk = nullptr;
-  // equal fibres: near pairs whose blocks are computed, and copies of them
+  long long *d_near_blk = nullptr;      // block offset (entries) of each near pair in d_near
+  long long n_near_stored = 0;          // element pairs stored in d_near
+  // equal fibres: target leaves with the same near region (same place in
+  // their fibres, same sources at the same offsets and images) read one
+  // stored region; inside a stored region, pairs equal to an earlier pair are
+  // computed once and copied
   int *d_near_uniq = nullptr;           // pair ids to compute (nullptr: all pairs)
   long long *d_near_cp_src = nullptr, *d_near_cp_dst = nullptr;   // block offsets (entries)
   int *d_near_cp_len = nullptr;         // complex values per copied block
@@ -121,7 +125,7 @@ struct Problem {
   int *d_cc_ptr = nullptr;              // [2*n_cells+1]: chunks of (channel, cell)
   cd *d_part = nullptr;                 // [n_chunks][2p+1] M2L sums of each (channel, cell)
   int n_chunks = 0;
-  int *d_mchunks = nullptr;             // [n_mchunks][4]: cell, channel, first entry, count (<= 2 entries)
+  int *d_mchunks = nullptr;             // [n_mchunks][4]: cell, channel, first entry, count (<= M2L_CHUNK entries)
   int n_mchunks = 0;
   cd *d_epart = nullptr;                // [n_mchunks][2p+1] M2L result of each entry chunk
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)

@@ -227,7 +227,7 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   A.near_blk = pb.d_near_blk;
   A.alpha = phase_free ? pb.d_alpha_one : pb.d_alpha;
   A.m_min = hp.m_min;
-  A.n_entries = hp.n_near_entries;
+  A.n_entries = pb.n_near_stored;
   A.out = pb.d_near;
   int lm = pb.opt.leaf_max;
   A.pair_ids = pb.d_near_uniq;
@@ -573,11 +573,20 @@ static BatchStrides batch_strides(const Problem& pb) {
 // P2M: multipole moments at the leaves, both wavenumbers (Sec. 3.2, MM of
 // S-bar and D-bar combined as in the representation D phi - i eta S varphi):
 //   M_n(C) = (i/4) sum_{e in C} sum_g w_g [ dJm_n/dn_y phi_e - i eta Jm_n varphi_e ],
-//   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2.
+//   dJm_n/dn_y = (kap/2) (conj(nu) Jm_{n-1} - nu Jm_{n+1}),  nu = n1 + i n2,
+// i.e. per Gauss point M_n += w0 Jm_n + wm Jm_{n-1} + wp Jm_{n+1}.
 // Two wavefronts per (leaf, channel): both walk every Gauss point of the leaf
 // (one point per lane at a time) through the orders |n| = 0..p with a window
 // of three Jm values; wavefront W accumulates the orders M_LO(W) <= |n| <= M_HI(W)
-// in registers.  One LDS transpose per wavefront sums the lanes.
+// in registers.  Orders m and -m share their products through
+// Jm_{-j} = (-1)^j conj(Jm_j): with s = (-1)^m, K = Jm_{m-1} - conj(Jm_{m+1})
+// and K' = Jm_{m-1} + conj(Jm_{m+1}) the lane keeps
+//   Pm = (M_m + s M_{-m}) / 2 = sum w0 Re(Jm_m) + (wm K - wp conj(K)) / 2,
+//   Qm = (M_m - s M_{-m}) / 2 = sum i w0 Im(Jm_m) + (wm K' + wp conj(K')) / 2,
+// whose real and imaginary parts take 12 FMA with the point weights
+// (wm + wp)/2 and (wm - wp)/2 (against 24 for M_m and M_{-m} apart), and
+// turns them into M_m = Pm + Qm, M_{-m} = s (Pm - Qm) once at the end.  One
+// LDS transpose per wavefront sums the lanes.
 template <int P, int W>
 struct P2MHalf {
   static constexpr int HALF = P / 2;
@@ -598,6 +607,8 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
                                          const double* __restrict__ h, const double* __restrict__ gl,
                                          const cd* __restrict__ psi) {
   using H = P2MHalf<P, W>;
+  constexpr int M1 = H::LO > 0 ? H::LO : 1;   // first order with a +- pair
+  // slot of order +m: m - LO (Pm for m >= 1); slot of order -m: NPOS + m - M1 (Qm)
   cd acc[H::NS];
 #pragma unroll
   for (int j = 0; j < H::NS; ++j) acc[j] = mkc(0, 0);
@@ -611,12 +622,12 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
     double etx = tx[e], ety = ty[e], hh = h[e];
     double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g];       // (1/4) of the weight
     double vx = kap * (mx[e] + s * etx - ox), vy = kap * (my[e] + s * ety - oy);
-    // (i/4) w [ -i eta varphi | (kap/2) conj(nu) phi | -(kap/2) nu phi ], nu = (ty, -tx)
+    // (i/4) w [ -i eta varphi | (kap/2) conj(nu) phi | -(kap/2) nu phi ], nu = (ty, -tx):
+    // w0 = eta w varphi, wm = i (ty + i tx) phi sk, wp = -i (ty - i tx) phi sk, sk = kap w / 2
+    const double sk = 0.5 * kap * w;
     cd w0 = cscale(vphi, eta * w);
-    cd cm = cmul(mkc(ety, etx), phi);
-    cd cp = cmul(mkc(ety, -etx), phi);
-    cd wm = cscale(mkc(-cm.y, cm.x), 0.5 * kap * w);
-    cd wp = cscale(mkc(cp.y, -cp.x), 0.5 * kap * w);
+    cd ah = cscale(phi, -sk * etx);                                // (wm + wp) / 2
+    cd bh = mkc(-sk * ety * phi.y, sk * ety * phi.x);               // (wm - wp) / 2
     double gs[H::HI + 2];
     scaled_j<H::HI + 1>(0.25 * (vx * vx + vy * vy), gs);
     cd hv = mkc(0.5 * vx, -0.5 * vy);                              // conj(v)/2
@@ -627,16 +638,17 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
 #pragma unroll
     for (int m = 0; m <= H::HI; ++m) {
       if (m >= H::LO) {
-        constexpr int dummy = 0;
-        (void)dummy;
-        int jp = m - H::LO;
-        acc[jp] = cfma(wp, J1, cfma(wm, Jprev, cfma(w0, J0, acc[jp])));
-        if (m > 0) {
-          int jn = H::NPOS + m - (H::LO > 0 ? H::LO : 1);
-          double sm = (m & 1) ? -1.0 : 1.0;
-          // n = -m: Jm_{-m} = (-1)^m conj(Jm_m), Jm_{-m-1}, Jm_{-m+1}
-          acc[jn] = cfma(wp, cscale(cconj(Jprev), -sm),
-                         cfma(wm, cscale(cconj(J1), -sm), cfma(w0, cscale(cconj(J0), sm), acc[jn])));
+        if (m == 0) {
+          cd wm = cadd(ah, bh), wp = csub(ah, bh);
+          acc[0] = cfma(wp, J1, cfma(wm, Jprev, cfma(w0, J0, acc[0])));
+        } else {
+          const int jp = m - H::LO, jn = H::NPOS + m - M1;
+          const double kx = Jprev.x - J1.x, ky = Jprev.y + J1.y;     // K
+          const double kpx = Jprev.x + J1.x, kpy = Jprev.y - J1.y;   // K'
+          acc[jp].x = fma(w0.x, J0.x, fma(bh.x, kx, fma(-ah.y, ky, acc[jp].x)));
+          acc[jp].y = fma(w0.y, J0.x, fma(ah.x, ky, fma(bh.y, kx, acc[jp].y)));
+          acc[jn].x = fma(-w0.y, J0.y, fma(ah.x, kpx, fma(-bh.y, kpy, acc[jn].x)));
+          acc[jn].y = fma(w0.x, J0.y, fma(bh.x, kpy, fma(ah.y, kpx, acc[jn].y)));
         }
       }
       if (m < H::HI) {
@@ -646,6 +658,13 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
         J1 = cscale(uu, gs[m + 2]);
       }
     }
+  }
+#pragma unroll
+  for (int m = M1; m <= H::HI; ++m) {
+    const int jp = m - H::LO, jn = H::NPOS + m - M1;
+    const cd pm = acc[jp], qm = acc[jn];
+    acc[jp] = cadd(pm, qm);
+    acc[jn] = cscale(csub(pm, qm), (m & 1) ? -1.0 : 1.0);
   }
 #pragma unroll
   for (int j = 0; j < H::NS; ++j) out[j] = acc[j];
@@ -1218,7 +1237,7 @@ __global__ void k_to_c64(long long n, const cd* __restrict__ in, float2* __restr
 }
 
 hipError_t launch_near_to_c64(Problem& pb) {
-  long long n = 4 * pb.hp.n_near_entries;
+  long long n = 4 * pb.n_near_stored;
   if (n == 0 || !pb.d_near32) return hipSuccess;
   hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_near,
                      pb.d_near32);

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("n_root_offsets", ctypes.c_int), ("n_m2l_offsets", ctypes.c_int),
                 ("near_bytes", ctypes.c_double), ("k", ctypes.c_double), ("k1", ctypes.c_double),
                 ("eta", ctypes.c_double), ("varrho", ctypes.c_double), ("theta", ctypes.c_double),
-                ("lattice_q", ctypes.c_int), ("p2p_split", ctypes.c_int), ("n_near_computed", ctypes.c_int)]
+                ("lattice_q", ctypes.c_int), ("p2p_split", ctypes.c_int), ("n_near_computed", ctypes.c_int),
+                ("n_near_stored", ctypes.c_longlong)]
 
 
 FP64 = 0

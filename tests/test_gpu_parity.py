@@ -48,6 +48,11 @@ _WL = {
     "sq2x2": (W.small_square(2, 2, 64, 0.3, 2.0, math.pi / 6), 2.0, math.pi / 6),
     "hex2x2": (W.small_square(2, 2, 64, 0.3, 3.0, 0.3, lattice=W.HEXAGON), 3.0, 0.3),
     "sq3x1": (W.small_square(3, 1, 96, 0.25, 5.0, 0.2, radii=np.array([0.2, 0.3, 0.25])), 5.0, 0.2),
+    # close equal fibres: near pairs between neighbours, also across the
+    # periodic boundary (image m = +-1), share stored near regions
+    "sq2x2close": (W.small_square(2, 2, 64, 0.45, 2.0, 0.4), 2.0, 0.4),
+    # four columns: the two inner columns' leaves read shared near regions
+    "sq4x2close": (W.small_square(4, 2, 64, 0.45, 2.0, 0.3), 2.0, 0.3),
 }
 
 
@@ -120,6 +125,8 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     ("sq2x2", 40, 16, 1e-10),
     ("hex2x2", 40, 16, 1e-10),
     ("sq3x1", 40, 16, 1e-10),
+    ("sq2x2close", 40, 16, 1e-10),
+    ("sq4x2close", 40, 16, 1e-10),
 ])
 def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol):
     _say("matvec:", key, "p =", p, "leaf =", leaf)
@@ -166,7 +173,7 @@ def test_fields_vs_oracle(pfm):
 
 # ---- mixed precision: complex64 near field inside FP64 iterative refinement ----
 
-@pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2"])
+@pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2", "sq2x2close"])
 def test_mixed_matvec_vs_dense_oracle(pfm, key):
     """The mixed apply differs from the exact operator by the FP32 rounding of
     the near blocks and densities: relative error a few times 2^-24."""
