@@ -94,7 +94,7 @@ def mixed_precision_leg(reps):
         x, info = prob.solve()
         torch.cuda.synchronize()
         rec.update({"solve_s": time.perf_counter() - t0, "iters": info["iters"],
-                    "matvecs": info["matvecs"], "outer": info["outer"],
+                    "matvecs": info["matvecs"], "matvecs_mixed": info["matvecs_mixed"], "outer": info["outer"],
                     "rel_residual": info["rel_residual"], "status": info["status"]})
         xs[name] = (prob, x)
         out[name] = rec

@@ -58,9 +58,12 @@ typedef enum { PFM_SQUARE = 0, PFM_HEXAGON = 1 } pfm_lattice;
 
 /* Arithmetic of the operator apply inside the solver.  PFM_FP64: everything in
  * FP64.  PFM_MIXED: the near field (P2P, the bulk of the bytes) is stored as
- * complex64 and accumulated in FP32 inside FP64 iterative refinement; the
+ * complex64 (densities and sums FP64) inside FP64 iterative refinement; the
  * far-field expansions, lattice sums, self/near element integrals, GMRES
- * orthogonalisation and the refinement residual stay FP64. */
+ * orthogonalisation and the refinement residual stay FP64.  The inner GMRES
+ * applies the FP64 operator while its residual estimate (relative to ||B||)
+ * is above the relaxation point inner_tol and the complex64 near field below
+ * it (an inexact Krylov method: late applies may be less accurate). */
 typedef enum { PFM_FP64 = 0, PFM_MIXED = 1 } pfm_precision;
 
 /* Fibre lattice (Sec. 2, Fig. 1).  Square: fibre (col i, row j) centred at
@@ -94,7 +97,10 @@ typedef struct {
  *  wood_margin  reject (PFM_EWOOD) when the distance of k H (1 +- sin th)/(2 pi)
  *             to an integer is below this; 0 disables the check
  *  precision  PFM_FP64 or PFM_MIXED (see pfm_precision)
- *  inner_tol  PFM_MIXED: relative tolerance of each inner solve (<= 0: 1e-5)
+ *  inner_tol  PFM_MIXED: relaxation point, the relative residual below which the
+ *             inner GMRES applies the complex64 near field (<= 0 or >= 1:
+ *             min(0.1, 1e4 tol), where the measured GMRES iterations stay
+ *             those of the FP64 solve)
  *  max_batch  capacity of the batched calls: angles per frequency (0 -> 1, at
  *             most PFM_MAX_BATCH); per-member buffers are sized for it
  *  use_graph  batched solves replay the batched apply from a captured HIP
@@ -130,6 +136,7 @@ typedef struct {
   double t_solve_s;        /* wall time of the solve */
   int outer;               /* PFM_MIXED: refinement steps (0 in FP64) */
   int fallback;            /* use_x0 = 2: the start vector was replaced by zero */
+  int matvecs_mixed;       /* PFM_MIXED: applies with the complex64 near field (0 in FP64) */
 } pfm_info;
 
 /* Sizes and counts of the built plan (for reports and tests). */

@@ -1029,7 +1029,7 @@ __global__ void k_combine(long long n, const cd* __restrict__ far, const cd* __r
 constexpr int P2P_WAVES = 4;
 constexpr int P2P_SEG = 256;
 
-// Complex arithmetic of the P2P stream: FP64 (double2) or FP32 (float2).
+// Complex arithmetic of the batched P2P stream: FP64 (double2) or FP32 (float2).
 __device__ __forceinline__ double2 p2p_fma(double2 a, double2 b, double2 c) { return cfma(a, b, c); }
 __device__ __forceinline__ float2 p2p_fma(float2 a, float2 b, float2 c) { return cfmaf(a, b, c); }
 template <typename C> __device__ __forceinline__ C p2p_cvt(cd v);
@@ -1049,8 +1049,11 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
     const int* __restrict__ col_psi, const C* __restrict__ blocks, const cd* __restrict__ psi,
     cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part, long long vec) {
-  __shared__ C sp[P2P_SEG][2];
-  __shared__ C r1[P2P_WAVES][64], r2[P2P_WAVES][64];
+  // the blocks are stored as C (complex128, or complex64 for PFM_MIXED); the
+  // densities and the sums stay FP64, so the complex64 form only rounds the
+  // stored blocks (the stream is bandwidth-bound either way)
+  __shared__ cd sp[P2P_SEG][2];
+  __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   // work item = (target leaf, column split); with S > 1 the splits write
   // partial rows that k_combine adds in a fixed order
   for (int item = blockIdx.x; item < n_leaves * S; item += gridDim.x) {
@@ -1058,7 +1061,7 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     int D = leaves[li];
     int db = ebeg[D], rows = eend[D] - db;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    C a1 = p2p_cvt<C>(mkc(0, 0)), a2 = a1;
+    cd a1 = mkc(0, 0), a2 = a1;
     int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
     int chunk = (ncol + S - 1) / S;
     int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
@@ -1069,8 +1072,8 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
       int nseg = min(P2P_SEG, c_hi - seg);
       for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
         int pi = col_psi[k0 + seg + i];
-        sp[i][0] = p2p_cvt<C>(psi[pi]);
-        sp[i][1] = p2p_cvt<C>(psi[pi + N]);
+        sp[i][0] = psi[pi];
+        sp[i][1] = psi[pi + N];
       }
       __syncthreads();
       const C* bs = bl + (size_t)seg * cstride + lane;
@@ -1089,21 +1092,21 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            C ph = sp[k + u * P2P_WAVES][0], vp = sp[k + u * P2P_WAVES][1];
-            a1 = p2p_fma(bb[u][0], ph, a1);
-            a1 = p2p_fma(bb[u][1], vp, a1);
-            a2 = p2p_fma(bb[u][2], ph, a2);
-            a2 = p2p_fma(bb[u][3], vp, a2);
+            cd ph = sp[k + u * P2P_WAVES][0], vp = sp[k + u * P2P_WAVES][1];
+            a1 = cfma(p2p_wide(bb[u][0]), ph, a1);
+            a1 = cfma(p2p_wide(bb[u][1]), vp, a1);
+            a2 = cfma(p2p_wide(bb[u][2]), ph, a2);
+            a2 = cfma(p2p_wide(bb[u][3]), vp, a2);
           }
         }
         for (; k < nseg; k += P2P_WAVES) {
           unsigned o = (unsigned)k * cstride;
           C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
-          C ph = sp[k][0], vp = sp[k][1];
-          a1 = p2p_fma(b11, ph, a1);
-          a1 = p2p_fma(b12, vp, a1);
-          a2 = p2p_fma(b21, ph, a2);
-          a2 = p2p_fma(b22, vp, a2);
+          cd ph = sp[k][0], vp = sp[k][1];
+          a1 = cfma(p2p_wide(b11), ph, a1);
+          a1 = cfma(p2p_wide(b12), vp, a1);
+          a2 = cfma(p2p_wide(b21), ph, a2);
+          a2 = cfma(p2p_wide(b22), vp, a2);
         }
       }
       __syncthreads();
@@ -1112,11 +1115,11 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     r2[w][lane] = a2;
     __syncthreads();
     if (w == 0 && act) {
-      cd s1 = p2p_wide(r1[0][lane]), s2 = p2p_wide(r2[0][lane]);
+      cd s1 = r1[0][lane], s2 = r2[0][lane];
 #pragma unroll
       for (int v = 1; v < P2P_WAVES; ++v) {
-        s1 = cadd(s1, p2p_wide(r1[v][lane]));
-        s2 = cadd(s2, p2p_wide(r2[v][lane]));
+        s1 = cadd(s1, r1[v][lane]);
+        s2 = cadd(s2, r2[v][lane]);
       }
       int pi = psi_idx[db + lane];
       if (S == 1) {

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("matvecs", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("outer", ctypes.c_int), ("fallback", ctypes.c_int)]
+                ("outer", ctypes.c_int), ("fallback", ctypes.c_int), ("matvecs_mixed", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -248,7 +248,7 @@ class Problem:
             self._check(code)
         return x, {"status": info.status, "iters": info.iters, "matvecs": info.matvecs,
                    "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s, "outer": info.outer,
-                   "fallback": info.fallback}
+                   "fallback": info.fallback, "matvecs_mixed": info.matvecs_mixed}
 
     def fields(self, psi, n_orders: int = 10):
         no = 2 * n_orders + 1

@@ -179,6 +179,7 @@ def test_hexagon_16x16_mixed_solve(pfm):
     xmx, imx = pmx.solve()
     _say("  mixed", imx)
     assert i64["status"] == 0 and imx["status"] == 0
+    assert imx["matvecs_mixed"] > 0
     b = p64.rhs()
     r = b - p64.matvec(xmx)
     res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()

@@ -200,7 +200,9 @@ def test_mixed_solve_vs_dense_lu(pfm, key):
     prob = _gpu_problem(pfm, key, 40, 16, tol=1e-12, restart=100, precision=pfm.MIXED)
     x, info = prob.solve()
     _say("  ", info)
-    assert info["status"] == 0 and info["outer"] >= 2
+    # relaxed inner applies: FP64 first, complex64 once the residual is small
+    assert info["status"] == 0 and info["outer"] >= 1
+    assert 0 < info["matvecs_mixed"] < info["matvecs"]
     xs = x.cpu().numpy()
     # the true residual of the refined solution with the exact dense operator
     res = np.linalg.norm(B - A @ xs) / np.linalg.norm(B)
