@@ -1042,6 +1042,24 @@ template <> __device__ __forceinline__ float2 p2p_cvt<float2>(cd v) {
 }
 template <typename C> __device__ __forceinline__ cd p2p_wide(C v) { return mkc((double)v.x, (double)v.y); }
 
+// Loads of the near-block stream.  The blocks are read once per apply and
+// are far larger than the L2, so they are loaded non-temporally and do not
+// evict the densities the P2P gathers or the expansions and tables of the
+// concurrent FMM chain.
+template <typename C> __device__ __forceinline__ C nt_load(const C* p);
+template <> __device__ __forceinline__ double2 nt_load<double2>(const double2* p) {
+  double2 r;
+  r.x = __builtin_nontemporal_load(&p->x);
+  r.y = __builtin_nontemporal_load(&p->y);
+  return r;
+}
+template <> __device__ __forceinline__ float2 nt_load<float2>(const float2* p) {
+  float2 r;
+  r.x = __builtin_nontemporal_load(&p->x);
+  r.y = __builtin_nontemporal_load(&p->y);
+  return r;
+}
+
 template <typename C, int U>
 __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
@@ -1085,10 +1103,10 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             unsigned o = (unsigned)(k + u * P2P_WAVES) * cstride;
-            bb[u][0] = bs[o];
-            bb[u][1] = bs[o + rows];
-            bb[u][2] = bs[o + 2 * rows];
-            bb[u][3] = bs[o + 3 * rows];
+            bb[u][0] = nt_load(bs + o);
+            bb[u][1] = nt_load(bs + o + rows);
+            bb[u][2] = nt_load(bs + o + 2 * rows);
+            bb[u][3] = nt_load(bs + o + 3 * rows);
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
@@ -1101,7 +1119,8 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
         }
         for (; k < nseg; k += P2P_WAVES) {
           unsigned o = (unsigned)k * cstride;
-          C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
+          C b11 = nt_load(bs + o), b12 = nt_load(bs + o + rows);
+          C b21 = nt_load(bs + o + 2 * rows), b22 = nt_load(bs + o + 3 * rows);
           cd ph = sp[k][0], vp = sp[k][1];
           a1 = cfma(p2p_wide(b11), ph, a1);
           a1 = cfma(p2p_wide(b12), vp, a1);
@@ -1187,7 +1206,8 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
       if (act) {
         for (int k = w; k < nseg; k += P2P_WAVES) {
           unsigned o = (unsigned)k * cstride;
-          C b11 = bs[o], b12 = bs[o + rows], b21 = bs[o + 2 * rows], b22 = bs[o + 3 * rows];
+          C b11 = nt_load(bs + o), b12 = nt_load(bs + o + rows);
+          C b21 = nt_load(bs + o + 2 * rows), b22 = nt_load(bs + o + 3 * rows);
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             C ph = sp[k][b][0], vp = sp[k][b][1];
