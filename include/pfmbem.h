@@ -108,7 +108,11 @@ typedef struct {
  *  p2p_blocks_per_cu  workgroups per compute unit of the persistent P2P
  *             launch (0: 2; at most 8)
  *  p2p_unroll  source columns whose block entries a P2P wavefront keeps in
- *             flight at once: 1, 2 or 4 (0: 1) */
+ *             flight at once: 1, 2 or 4 (0: 1)
+ *  store_self_blocks  0: near pairs of a fibre with itself (image 0) use one
+ *             circulant row per fibre (the N chords of a circle are rotations
+ *             of each other, so their 2x2 block depends only on the index
+ *             difference mod N); 1: every near pair is a stored block */
 typedef struct {
   int p;
   int leaf_max;
@@ -124,6 +128,7 @@ typedef struct {
   int use_graph;
   int p2p_blocks_per_cu;
   int p2p_unroll;
+  int store_self_blocks;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -153,10 +158,11 @@ typedef struct {
   double k, k1, eta, varrho, theta;
   int lattice_q;               /* direct images of the lattice sums, |m| <= q */
   int p2p_split;               /* column splits per target leaf in the P2P launch */
-  int n_near_computed;         /* near pairs whose blocks are computed (equal fibres share blocks) */
+  int n_near_computed;         /* stored near pairs whose blocks are computed (equal fibres share blocks) */
   long long n_near_stored;     /* element pairs stored: with equal fibres, target leaves with the
                                   same near region (the same sources at the same offsets and
                                   images) read one stored copy of it */
+  long long n_near_circulant;  /* element pairs taken from the circulant rows of their fibre */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

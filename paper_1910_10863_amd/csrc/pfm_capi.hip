@@ -76,7 +76,8 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2l_ptr); dfree(pb.d_m2l_src); dfree(pb.d_m2l_off); dfree(pb.d_m2l_m);
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
-  dfree(pb.d_near_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
+  dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
+  dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_circ);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
@@ -169,6 +170,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   if (opt->g_far < 1 || opt->g_far > 16) return bail(fail(pb, PFM_EINVAL, "g_far must be 1..16"));
   if (opt->restart < 1 || opt->restart > 200 || opt->max_iter < 1 || !(opt->tol > 0))
     return bail(fail(pb, PFM_EINVAL, "restart 1..200, max_iter >= 1, tol > 0"));
+  if (opt->store_self_blocks != 0 && opt->store_self_blocks != 1)
+    return bail(fail(pb, PFM_EINVAL, "store_self_blocks must be 0 or 1"));
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -287,14 +290,31 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(upload(&pb.d_m2li_off, hp.m2li_off));
   CK(upload(&pb.d_near_ptr, hp.near_ptr)); CK(upload(&pb.d_near_src, hp.near_src));
   CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
-  // near-block storage: with equal fibres, a region (the blocks of one target
-  // leaf's near list) is stored once for every leaf that has the same region
+  // Near pairs of one fibre with itself (m = 0) are circulant: the chords of
+  // a circle are rotations of each other, so the 2x2 block of target element
+  // a and source element b depends only on (b - a) mod N, and one row per
+  // fibre (pfm_set_wave fills it) stands for all of them.  The other pairs
+  // (another fibre, or an image) keep stored blocks; store_self_blocks = 1
+  // stores every pair.
+  const int npairs_all = (int)hp.near_src.size();
+  std::vector<char> circ(npairs_all, 0);
+  long long n_circ_entries = 0;
+  for (int q = 0; q < npairs_all; ++q) {
+    const Cell& D = hp.cells[hp.leaves[hp.near_tgt[q]]];
+    const Cell& C = hp.cells[hp.near_src[q]];
+    circ[q] = !pb.opt.store_self_blocks && C.fiber == D.fiber && hp.near_m[q] == 0;
+    if (circ[q]) n_circ_entries += (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
+  }
+  pb.n_near_circ = n_circ_entries;
+  // near-block storage of the other pairs: per target leaf its stored pairs
+  // one after the other; with equal fibres, a region (the stored blocks of one
+  // target leaf) is stored once for every leaf that has the same region
   {
     // Equal fibres (same radius, so the same chords and the same tree about
     // each centre): a near block depends only on the two leaves' places in
     // their fibres' trees, on the offset between the fibres and, through the
     // quasi-periodic phase alpha^m, on the image m.
-    const int npairs = (int)hp.near_src.size();
+    const int npairs = npairs_all;
     const int nl = (int)hp.leaves.size();
     bool equal = pb.M > 1 && npairs > 0;
     for (int f = 1; f < pb.M && equal; ++f) equal = pb.radii[f] == pb.radii[0];
@@ -322,10 +342,15 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         }
       }
     }
-    std::vector<long long> blk(npairs);
+    std::vector<long long> blk(npairs, 0), leaf_blk(nl, 0);
     std::vector<int> uniq, cp_len;
     std::vector<long long> cp_src, cp_dst;
     long long stored = 0;
+    auto pair_len = [&](int q) {
+      const Cell& D = hp.cells[hp.leaves[hp.near_tgt[q]]];
+      const Cell& C = hp.cells[hp.near_src[q]];
+      return (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
+    };
     if (equal) {
       // key of a pair: (target's place, source's place, offset, image)
       auto pair_key = [&](int q) {
@@ -341,21 +366,26 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       for (int li = 0; li < nl; ++li) {
         std::vector<long long> rkey = {local[hp.leaves[li]]};
         for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
+          if (circ[q]) continue;
           auto k = pair_key(q);
           rkey.insert(rkey.end(), k.begin() + 1, k.end());
         }
         auto it = region_first.find(rkey);
         if (it != region_first.end()) {
           const int lf = it->second;
-          for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q)
-            blk[q] = blk[hp.near_ptr[lf] + (q - hp.near_ptr[li])];
+          leaf_blk[li] = leaf_blk[lf];
+          for (int q = hp.near_ptr[li], r = hp.near_ptr[lf]; q < hp.near_ptr[li + 1]; ++q) {
+            if (circ[q]) continue;
+            while (circ[r]) ++r;
+            blk[q] = blk[r++];
+          }
           continue;
         }
         region_first.emplace(rkey, li);
-        const Cell& D = hp.cells[hp.leaves[li]];
+        leaf_blk[li] = stored;
         for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
-          const Cell& C = hp.cells[hp.near_src[q]];
-          const long long len = (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
+          if (circ[q]) continue;
+          const long long len = pair_len(q);
           blk[q] = stored;
           stored += len;
           auto k = pair_key(q);
@@ -371,45 +401,67 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         }
       }
     } else {
-      blk = hp.near_blk;
-      stored = hp.n_near_entries;
+      for (int li = 0; li < nl; ++li) {
+        leaf_blk[li] = stored;
+        for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
+          if (circ[q]) continue;
+          blk[q] = stored;
+          stored += pair_len(q);
+          uniq.push_back(q);
+        }
+      }
     }
     pb.n_near_stored = stored;
-    pb.n_near_uniq = equal ? (int)uniq.size() : npairs;
+    pb.n_near_uniq = (int)uniq.size();
     pb.n_near_copies = (int)cp_src.size();
     CK(upload(&pb.d_near_blk, blk));
-    if (equal) {
-      CK(upload(&pb.d_near_uniq, uniq));
+    CK(upload(&pb.d_leaf_blk, leaf_blk));
+    CK(upload(&pb.d_near_uniq, uniq));
+    if (!cp_src.empty()) {
       CK(upload(&pb.d_near_cp_src, cp_src)); CK(upload(&pb.d_near_cp_dst, cp_dst));
       CK(upload(&pb.d_near_cp_len, cp_len));
     }
   }
   {
-    // flattened source columns of every target leaf's near list, in storage order
+    // flattened source columns of every target leaf: the stored pairs' columns
+    // in storage order, and the circulant pairs' columns with the source's
+    // place on its circle
     int nl = (int)hp.leaves.size();
-    std::vector<int> cptr(nl + 1, 0), cpsi, cm;
+    std::vector<int> cptr(nl + 1, 0), cpsi, cm, qptr(nl + 1, 0), qpsi, qloc;
     for (int li = 0; li < nl; ++li) {
       for (int q = hp.near_ptr[li]; q < hp.near_ptr[li + 1]; ++q) {
         const Cell& C = hp.cells[hp.near_src[q]];
         for (int t = C.ebeg; t < C.eend; ++t) {
           int e = hp.elem_of[t], f = e / pb.N;
-          cpsi.push_back(2 * f * pb.N + (e - f * pb.N));
-          cm.push_back(hp.near_m[q]);
+          if (circ[q]) {
+            qpsi.push_back(2 * f * pb.N + (e - f * pb.N));
+            qloc.push_back(e - f * pb.N);
+          } else {
+            cpsi.push_back(2 * f * pb.N + (e - f * pb.N));
+            cm.push_back(hp.near_m[q]);
+          }
         }
       }
       cptr[li + 1] = (int)cpsi.size();
+      qptr[li + 1] = (int)qpsi.size();
     }
     CK(upload(&pb.d_cols_ptr, cptr));
     CK(upload(&pb.d_col_psi, cpsi));
     CK(upload(&pb.d_col_m, cm));
+    CK(upload(&pb.d_ccols_ptr, qptr));
+    CK(upload(&pb.d_ccol_psi, qpsi));
+    CK(upload(&pb.d_ccol_loc, qloc));
     // split the columns of each target leaf when there are too few leaves to
     // fill the P2P grid, keeping at least 32 columns per split on average
+    const long long ncols = (long long)cpsi.size() + (long long)qpsi.size();
     int S = 1;
     if (pb.p2p_grid > 0 && nl > 0 && nl < pb.p2p_grid) S = std::min(8, (pb.p2p_grid + nl - 1) / nl);
-    while (S > 1 && (long long)cpsi.size() / ((long long)nl * S) < 32) --S;
+    while (S > 1 && ncols / ((long long)nl * S) < 32) --S;
     pb.p2p_split = S;
     size_t part = S > 1 ? (size_t)S * std::max(1, opt->max_batch) * 2 * (size_t)pb.E : 1;
     CK(hipMalloc((void**)&pb.d_p2ppart, part * sizeof(cd)));
+    // circulant rows [fibre][component][2N] (the second copy spares the wrap)
+    CK(hipMalloc((void**)&pb.d_circ, (size_t)std::max(1, pb.M) * 8 * pb.N * sizeof(cd)));
   }
   CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
@@ -1360,8 +1412,9 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->theta = pb.theta;
   st->lattice_q = pb.lattice_q;
   st->p2p_split = pb.p2p_split;
-  st->n_near_computed = pb.d_near_uniq ? pb.n_near_uniq : (int)hp.near_src.size();
+  st->n_near_computed = pb.n_near_uniq;
   st->n_near_stored = pb.n_near_stored;
+  st->n_near_circulant = pb.n_near_circ;
   return PFM_OK;
 }
 

@@ -94,13 +94,19 @@ struct Problem {
   int *d_m2l_ptr = nullptr, *d_m2l_src = nullptr, *d_m2l_off = nullptr, *d_m2l_m = nullptr;
   int *d_m2li_ptr = nullptr, *d_m2li_src = nullptr, *d_m2li_off = nullptr;
   int *d_near_ptr = nullptr, *d_near_src = nullptr, *d_near_m = nullptr, *d_near_tgt = nullptr;
-  long long *d_near_blk = nullptr;      // block offset (entries) of each near pair in d_near
+  long long *d_near_blk = nullptr;      // block offset (entries) of each stored near pair in d_near
+  long long *d_leaf_blk = nullptr;      // per leaf: offset of its stored region
   long long n_near_stored = 0;          // element pairs stored in d_near
+  long long n_near_circ = 0;            // element pairs taken from the circulant rows
+  int *d_ccols_ptr = nullptr;           // per leaf: range of its circulant source columns
+  int *d_ccol_psi = nullptr;            // circulant source columns: index of phi in Psi
+  int *d_ccol_loc = nullptr;            // circulant source columns: element index on its circle
+  cd *d_circ = nullptr;                 // [fibre][B11, B12, B21, B22][2N] circulant near rows
   // equal fibres: target leaves with the same near region (same place in
   // their fibres, same sources at the same offsets and images) read one
   // stored region; inside a stored region, pairs equal to an earlier pair are
   // computed once and copied
-  int *d_near_uniq = nullptr;           // pair ids to compute (nullptr: all pairs)
+  int *d_near_uniq = nullptr;           // stored pair ids whose blocks are computed
   long long *d_near_cp_src = nullptr, *d_near_cp_dst = nullptr;   // block offsets (entries)
   int *d_near_cp_len = nullptr;         // complex values per copied block
   int n_near_uniq = 0, n_near_copies = 0;

@@ -123,7 +123,7 @@ struct NearArgs {
   int m_min;
   long long n_entries;
   cd* out;
-  const int* pair_ids;     // pair of each workgroup row (nullptr: blockIdx.x)
+  const int* pair_ids;     // stored pair computed by each workgroup row
 };
 
 __device__ inline void far_rule(double kap, double x, double y, double nux, double nuy,
@@ -143,8 +143,48 @@ __device__ inline void far_rule(double kap, double x, double y, double nux, doub
   }
 }
 
+// The 2x2 block of (I - A) for target element ea and source element eb
+// (natural ids), source shifted by image m with phase ph.
+__device__ inline void near_entry(const NearArgs& A, int ea, int eb, int m, cd ph, cd& B11, cd& B12, cd& B21,
+                                  cd& B22) {
+  cd c = mkc(0.0, -2.0 / (A.eta * (1.0 + A.varrho)));     // 2 / (i eta (1 + varrho))
+  cd mieta = mkc(0.0, -A.eta);                              // -i eta
+  double x = A.mx[ea], y = A.my[ea];
+  double nux = A.ty[ea], nuy = -A.tx[ea];
+  double sx = A.mx[eb], sy = A.my[eb] + m * A.H;
+  double tx = A.tx[eb], ty = A.ty[eb], hh = A.h[eb];
+  int fa = ea / A.N, fb = eb / A.N;
+  if (fa == fb && m == 0) {
+    int dl = abs((ea - fa * A.N) - (eb - fb * A.N));
+    dl = min(dl, A.N - dl);
+    cd S2, D2, K2, T2, S1, D1, K1, T1;
+    if (dl == 0) {
+      self_terms(A.k, hh, S2, T2);
+      self_terms(A.k1, hh, S1, T1);
+      D2 = K2 = D1 = K1 = mkc(0, 0);
+    } else if (dl <= 2) {
+      far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S2, D2, K2, T2);
+      far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S1, D1, K1, T1);
+    } else {
+      far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
+      far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S1, D1, K1, T1);
+    }
+    B11 = csub(D2, D1);
+    B12 = cmul(mieta, csub(S2, S1));
+    B21 = cmul(c, csub(T2, cscale(T1, A.varrho)));
+    B22 = cmul(cmul(c, mieta), csub(K2, cscale(K1, A.varrho)));
+  } else {
+    cd S2, D2, K2, T2;
+    far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
+    B11 = cmul(ph, D2);
+    B12 = cmul(cmul(mieta, ph), S2);
+    B21 = cmul(cmul(c, ph), T2);
+    B22 = cmul(cmul(cmul(c, mieta), ph), K2);
+  }
+}
+
 __global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
-  int q = A.pair_ids ? A.pair_ids[blockIdx.x] : blockIdx.x;
+  int q = A.pair_ids[blockIdx.x];
   int D = A.leaves[A.near_tgt[q]];
   int C = A.near_src[q];
   int m = A.near_m[q];
@@ -152,51 +192,34 @@ __global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
   int cb = A.ebeg[C], cols = A.eend[C] - cb;
   long long blk = A.near_blk[q];
   cd ph = A.alpha[m - A.m_min];
-  cd c = mkc(0.0, -2.0 / (A.eta * (1.0 + A.varrho)));     // 2 / (i eta (1 + varrho))
-  cd mieta = mkc(0.0, -A.eta);                              // -i eta
   // the pair's entries are spread over the y axis of the grid, one per thread
   for (int rc = blockIdx.y * blockDim.x + threadIdx.x; rc < rows * cols; rc += gridDim.y * blockDim.x) {
     int col = rc / rows, row = rc - col * rows;
-    int ea = A.elem_of[db + row], eb = A.elem_of[cb + col];
-    double x = A.mx[ea], y = A.my[ea];
-    double nux = A.ty[ea], nuy = -A.tx[ea];
-    double sx = A.mx[eb], sy = A.my[eb] + m * A.H;
-    double tx = A.tx[eb], ty = A.ty[eb], hh = A.h[eb];
-    int fa = ea / A.N, fb = eb / A.N;
     cd B11, B12, B21, B22;
-    if (fa == fb && m == 0) {
-      int dl = abs((ea - fa * A.N) - (eb - fb * A.N));
-      dl = min(dl, A.N - dl);
-      cd S2, D2, K2, T2, S1, D1, K1, T1;
-      if (dl == 0) {
-        self_terms(A.k, hh, S2, T2);
-        self_terms(A.k1, hh, S1, T1);
-        D2 = K2 = D1 = K1 = mkc(0, 0);
-      } else if (dl <= 2) {
-        far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S2, D2, K2, T2);
-        far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl16, 16, S1, D1, K1, T1);
-      } else {
-        far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
-        far_rule(A.k1, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S1, D1, K1, T1);
-      }
-      B11 = csub(D2, D1);
-      B12 = cmul(mieta, csub(S2, S1));
-      B21 = cmul(c, csub(T2, cscale(T1, A.varrho)));
-      B22 = cmul(cmul(c, mieta), csub(K2, cscale(K1, A.varrho)));
-    } else {
-      cd S2, D2, K2, T2;
-      far_rule(A.k, x, y, nux, nuy, sx, sy, tx, ty, hh, A.gl, A.g_far, S2, D2, K2, T2);
-      B11 = cmul(ph, D2);
-      B12 = cmul(cmul(mieta, ph), S2);
-      B21 = cmul(cmul(c, ph), T2);
-      B22 = cmul(cmul(cmul(c, mieta), ph), K2);
-    }
+    near_entry(A, A.elem_of[db + row], A.elem_of[cb + col], m, ph, B11, B12, B21, B22);
     long long idx = 4 * blk + (long long)col * 4 * rows + row;
     A.out[idx] = B11;
     A.out[idx + rows] = B12;
     A.out[idx + 2 * rows] = B21;
     A.out[idx + 3 * rows] = B22;
   }
+}
+
+// Circulant near rows: for fibre f the block of its element 0 with its
+// element d (image 0) for d = 0..N-1, which is the block of any element a
+// with element (a + d) mod N.  Layout [f][B11, B12, B21, B22][2N], entry d
+// stored at d and at d + N so that the index (b - a) + N needs no wrap.
+__global__ void __launch_bounds__(128) k_circ_rows(NearArgs A, cd* __restrict__ circ) {
+  const int f = blockIdx.y, N = A.N;
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= N) return;
+  cd B11, B12, B21, B22;
+  near_entry(A, f * N, f * N + d, 0, mkc(1, 0), B11, B12, B21, B22);
+  cd* row = circ + (size_t)f * 8 * N;
+  row[d] = row[d + N] = B11;
+  row[2 * N + d] = row[3 * N + d] = B12;
+  row[4 * N + d] = row[5 * N + d] = B21;
+  row[6 * N + d] = row[7 * N + d] = B22;
 }
 
 // copy of computed near blocks into the slots of the pairs that share them
@@ -231,11 +254,13 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   A.out = pb.d_near;
   int lm = pb.opt.leaf_max;
   A.pair_ids = pb.d_near_uniq;
-  int nrows = pb.d_near_uniq ? pb.n_near_uniq : npairs;
-  hipLaunchKernelGGL(k_near_blocks, dim3(nrows, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
+  if (pb.n_near_uniq > 0)
+    hipLaunchKernelGGL(k_near_blocks, dim3(pb.n_near_uniq, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
   if (pb.n_near_copies > 0)
     hipLaunchKernelGGL(k_copy_blocks, dim3(pb.n_near_copies, (4 * lm * lm + 255) / 256), dim3(256), 0, pb.stream,
                        pb.d_near_cp_src, pb.d_near_cp_dst, pb.d_near_cp_len, pb.d_near);
+  if (pb.n_near_circ > 0)
+    hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + 127) / 128, pb.M), dim3(128), 0, pb.stream, A, pb.d_circ);
   return hipGetLastError();
 }
 
@@ -1063,14 +1088,16 @@ template <> __device__ __forceinline__ float2 nt_load<float2>(const float2* p) {
 template <typename C, int U>
 __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
-    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
-    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
-    const int* __restrict__ col_psi, const C* __restrict__ blocks, const cd* __restrict__ psi,
-    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part, long long vec) {
+    const int* __restrict__ psi_idx, int N, const long long* __restrict__ leaf_blk,
+    const int* __restrict__ cols_ptr, const int* __restrict__ col_psi, const C* __restrict__ blocks,
+    const int* __restrict__ ccols_ptr, const int* __restrict__ ccol_psi, const int* __restrict__ ccol_loc,
+    const cd* __restrict__ circ, const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves, int S,
+    cd* __restrict__ part, long long vec) {
   // the blocks are stored as C (complex128, or complex64 for PFM_MIXED); the
   // densities and the sums stay FP64, so the complex64 form only rounds the
   // stored blocks (the stream is bandwidth-bound either way)
   __shared__ cd sp[P2P_SEG][2];
+  __shared__ int sl[P2P_SEG];
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   // work item = (target leaf, column split); with S > 1 the splits write
   // partial rows that k_combine adds in a fixed order
@@ -1083,9 +1110,10 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
     int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
     int chunk = (ncol + S - 1) / S;
     int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
-    const C* bl = blocks + 4 * near_blk[near_ptr[li]];
+    const C* bl = blocks + 4 * leaf_blk[li];
     const unsigned cstride = 4u * (unsigned)rows;
     bool act = lane < rows;
+    // stored columns: stream the leaf's block region
     for (int seg = c_lo; seg < c_hi; seg += P2P_SEG) {
       int nseg = min(P2P_SEG, c_hi - seg);
       for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
@@ -1130,6 +1158,37 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
       }
       __syncthreads();
     }
+    // circulant columns (same fibre, image 0): the block of target element a
+    // and source element b is entry (b - a) mod N of the fibre's row
+    {
+      const int q0 = ccols_ptr[li], nq = ccols_ptr[li + 1] - q0;
+      const int qchunk = (nq + S - 1) / S;
+      const int q_lo = min(nq, sp_i * qchunk), q_hi = min(nq, q_lo + qchunk);
+      const int pr = psi_idx[db + min(lane, rows - 1)];
+      const int fD = pr / (2 * N), aloc = pr - 2 * fD * N;
+      const cd* crow = circ + (size_t)fD * 8 * N + (N - aloc);   // + b: entry (b - a) + N
+      for (int seg = q_lo; seg < q_hi; seg += P2P_SEG) {
+        int nseg = min(P2P_SEG, q_hi - seg);
+        for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
+          int pi = ccol_psi[q0 + seg + i];
+          sp[i][0] = psi[pi];
+          sp[i][1] = psi[pi + N];
+          sl[i] = ccol_loc[q0 + seg + i];
+        }
+        __syncthreads();
+        if (act) {
+          for (int k = w; k < nseg; k += P2P_WAVES) {
+            const cd* cr = crow + sl[k];
+            cd ph = sp[k][0], vp = sp[k][1];
+            a1 = cfma(cr[0], ph, a1);
+            a1 = cfma(cr[2 * N], vp, a1);
+            a2 = cfma(cr[4 * N], ph, a2);
+            a2 = cfma(cr[6 * N], vp, a2);
+          }
+        }
+        __syncthreads();
+      }
+    }
     r1[w][lane] = a1;
     r2[w][lane] = a2;
     __syncthreads();
@@ -1163,13 +1222,15 @@ template <int NB> struct P2PBatchSeg { static constexpr int value = 1024 / NB; }
 template <typename C, int NB>
 __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
-    const int* __restrict__ psi_idx, int N, const int* __restrict__ near_ptr,
-    const long long* __restrict__ near_blk, const int* __restrict__ cols_ptr,
-    const int* __restrict__ col_psi, const int* __restrict__ col_m, const cd* __restrict__ alpha,
-    int alpha_stride, int m_min, int B, long long stride, const C* __restrict__ blocks,
-    const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part) {
+    const int* __restrict__ psi_idx, int N, const long long* __restrict__ leaf_blk,
+    const int* __restrict__ cols_ptr, const int* __restrict__ col_psi, const int* __restrict__ col_m,
+    const cd* __restrict__ alpha, int alpha_stride, int m_min, int B, long long stride,
+    const C* __restrict__ blocks, const int* __restrict__ ccols_ptr, const int* __restrict__ ccol_psi,
+    const int* __restrict__ ccol_loc, const cd* __restrict__ circ, const cd* __restrict__ psi,
+    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part) {
   constexpr int SEG = P2PBatchSeg<NB>::value;
   __shared__ C sp[SEG][NB][2];
+  __shared__ int sl[SEG];
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   // work item = (target leaf, column split); with S > 1 the splits write
   // partial rows [split][member][vector] that k_combine adds in a fixed order
@@ -1184,7 +1245,7 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
     int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
     int chunk = (ncol + S - 1) / S;
     int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
-    const C* bl = blocks + 4 * near_blk[near_ptr[li]];
+    const C* bl = blocks + 4 * leaf_blk[li];
     const unsigned cstride = 4u * (unsigned)rows;
     bool act = lane < rows;
     for (int seg = c_lo; seg < c_hi; seg += SEG) {
@@ -1219,6 +1280,47 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
         }
       }
       __syncthreads();
+    }
+    // circulant columns (same fibre, image 0, so no image phase), as in k_p2p
+    {
+      const int q0 = ccols_ptr[li], nq = ccols_ptr[li + 1] - q0;
+      const int qchunk = (nq + S - 1) / S;
+      const int q_lo = min(nq, sp_i * qchunk), q_hi = min(nq, q_lo + qchunk);
+      const int pr = psi_idx[db + min(lane, rows - 1)];
+      const int fD = pr / (2 * N), aloc = pr - 2 * fD * N;
+      const cd* crow = circ + (size_t)fD * 8 * N + (N - aloc);
+      for (int seg = q_lo; seg < q_hi; seg += SEG) {
+        int nseg = min(SEG, q_hi - seg);
+        for (int i = threadIdx.x; i < nseg * NB; i += 64 * P2P_WAVES) {
+          int col = i / NB, b = i - col * NB;
+          cd v0 = mkc(0, 0), v1 = mkc(0, 0);
+          if (b < B) {
+            int pi = ccol_psi[q0 + seg + col];
+            v0 = psi[b * stride + pi];
+            v1 = psi[b * stride + pi + N];
+          }
+          sp[col][b][0] = p2p_cvt<C>(v0);
+          sp[col][b][1] = p2p_cvt<C>(v1);
+          if (b == 0) sl[col] = ccol_loc[q0 + seg + col];
+        }
+        __syncthreads();
+        if (act) {
+          for (int k = w; k < nseg; k += P2P_WAVES) {
+            const cd* cr = crow + sl[k];
+            const C b11 = p2p_cvt<C>(cr[0]), b12 = p2p_cvt<C>(cr[2 * N]);
+            const C b21 = p2p_cvt<C>(cr[4 * N]), b22 = p2p_cvt<C>(cr[6 * N]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              C ph = sp[k][b][0], vp = sp[k][b][1];
+              a1[b] = p2p_fma(b11, ph, a1[b]);
+              a1[b] = p2p_fma(b12, vp, a1[b]);
+              a2[b] = p2p_fma(b21, ph, a2[b]);
+              a2[b] = p2p_fma(b22, vp, a2[b]);
+            }
+          }
+        }
+        __syncthreads();
+      }
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -1327,9 +1429,10 @@ template <typename C, int NB>
 static void launch_p2p_batch(Problem& pb, int grid, const C* blocks, const cd* d_psi, cd* d_y, int B) {
   const BatchStrides bs = batch_strides(pb);
   hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves,
-                     pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr,
-                     pb.d_col_psi, pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, d_psi,
-                     d_y, (int)pb.hp.leaves.size(), pb.p2p_split, pb.d_p2ppart);
+                     pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi,
+                     pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, pb.d_ccols_ptr,
+                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, (int)pb.hp.leaves.size(), pb.p2p_split,
+                     pb.d_p2ppart);
 }
 
 // y = (I - A) psi.  Without stage events the FMM chain runs on the side
@@ -1355,8 +1458,9 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
   if (B == 0) {
 #define PFM_P2P(U)                                                                                             \
   hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg, \
-                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_near_ptr, pb.d_near_blk, pb.d_cols_ptr, pb.d_col_psi,  \
-                     blocks, d_psi, d_y, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
+                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks,     \
+                     pb.d_ccols_ptr, pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, n_leaves,             \
+                     pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
     if (pb.p2p_unroll == 4) PFM_P2P(4);
     else if (pb.p2p_unroll == 2) PFM_P2P(2);
     else PFM_P2P(1);

@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("wood_margin", ctypes.c_double),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int)]
+                ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
+                ("store_self_blocks", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -63,7 +64,7 @@ class Stats(ctypes.Structure):
                 ("near_bytes", ctypes.c_double), ("k", ctypes.c_double), ("k1", ctypes.c_double),
                 ("eta", ctypes.c_double), ("varrho", ctypes.c_double), ("theta", ctypes.c_double),
                 ("lattice_q", ctypes.c_int), ("p2p_split", ctypes.c_int), ("n_near_computed", ctypes.c_int),
-                ("n_near_stored", ctypes.c_longlong)]
+                ("n_near_stored", ctypes.c_longlong), ("n_near_circulant", ctypes.c_longlong)]
 
 
 FP64 = 0
@@ -150,7 +151,8 @@ class Problem:
                  eta: float = 0.0, p: int = 16, leaf_max: int = 32, mac: float = 0.65,
                  g_far: int = 4, restart: int = 200, max_iter: int = 4000, tol: float = 1e-8,
                  wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
-                 max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0):
+                 max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
+                 store_self_blocks: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -160,7 +162,8 @@ class Problem:
         geo = Geometry(lattice, a, M_L, M_H, n_elem, _dptr(rad), 0.0)
         mat = Material(rho_fiber, c_fiber, rho_matrix, c_matrix, eta)
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
-                      max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll)
+                      max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
+                      1 if store_self_blocks else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"

@@ -208,7 +208,8 @@ def test_equal_fibres_share_near_blocks(pfm, batch, r0):
     ys, counts = [], []
     for r in (radii, bumped):
         wl = W.small_square(ml, 2, 64, r0, 2.0, 0.3, radii=r)
-        pb = pfm.Problem.from_workload(wl, p=24, leaf_max=16, max_batch=2)
+        # every near pair stored as a block (the sharing concerns stored blocks)
+        pb = pfm.Problem.from_workload(wl, p=24, leaf_max=16, max_batch=2, store_self_blocks=True)
         psi = torch.tensor(np.stack([W.random_density(pb.n, 70 + b) for b in range(2)]), device="cuda")
         if batch:
             pb.set_batch(2.0, [0.3, -0.7])

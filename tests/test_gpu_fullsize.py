@@ -174,7 +174,8 @@ def test_hexagon_16x16_mixed_solve(pfm):
     p64.set_wave(ka, th)
     x64, i64 = p64.solve()
     _say("  fp64", i64)
-    pmx = pfm.Problem.from_workload(wl, precision=pfm.MIXED)
+    # complex64 stored blocks (self pairs stored too); p64 keeps the circulant rows
+    pmx = pfm.Problem.from_workload(wl, precision=pfm.MIXED, store_self_blocks=True)
     pmx.set_wave(ka, th)
     xmx, imx = pmx.solve()
     _say("  mixed", imx)

@@ -135,6 +135,27 @@ def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("key", ["sq3x1", "sq2x2close", "hex2x2"])
+def test_circulant_self_rows_equal_stored_blocks(pfm, key):
+    """The near pairs of a fibre with itself from one circulant row per fibre
+    equal their stored blocks (the chords of a circle are rotations of each
+    other); pairs with other fibres or images stay stored either way."""
+    wl, ka, th = _WL[key]
+    psi = W.random_density(2 * wl.M * wl.n_elem, 21)
+    ys, st = [], []
+    for store in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=16, store_self_blocks=store)
+        prob.set_wave(ka, th)
+        ys.append(prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy())
+        st.append(prob.stats())
+    _say("circulant vs stored:", key, [(s["n_near_circulant"], s["n_near_stored"], s["n_near_entries"]) for s in st])
+    assert st[0]["n_near_circulant"] > 0 and st[1]["n_near_circulant"] == 0
+    assert st[0]["n_near_circulant"] + st[0]["n_near_stored"] <= st[0]["n_near_entries"]
+    # stored: every pair has a block (equal fibres may share regions)
+    assert 0 < st[1]["n_near_stored"] <= st[1]["n_near_entries"]
+    assert np.max(np.abs(ys[0] - ys[1])) < 1e-12 * np.max(np.abs(ys[1]))
+
+
 def test_matvec_error_decreases_with_p(pfm):
     errs = [(_matvec_err(pfm, "sq2x2", p, 16)[0]) for p in (8, 16, 24, 32)]
     _say("matvec error vs p:", errs)
@@ -179,7 +200,8 @@ def test_mixed_matvec_vs_dense_oracle(pfm, key):
     the near blocks and densities: relative error a few times 2^-24."""
     pb, A, B = _oracle(key)
     _say("mixed matvec:", key)
-    prob = _gpu_problem(pfm, key, 40, 16 if key != "tiny" else 32, precision=pfm.MIXED)
+    # complex64 concerns stored blocks: store the self pairs too
+    prob = _gpu_problem(pfm, key, 40, 16 if key != "tiny" else 32, precision=pfm.MIXED, store_self_blocks=True)
     psi = W.random_density(prob.n, 5)
     t = torch.tensor(psi, device="cuda")
     y32 = prob.matvec_mixed(t).cpu().numpy()
@@ -197,7 +219,7 @@ def test_mixed_solve_vs_dense_lu(pfm, key):
     pb, A, B = _oracle(key)
     ref = np.linalg.solve(A, B)
     _say("mixed solve:", key)
-    prob = _gpu_problem(pfm, key, 40, 16, tol=1e-12, restart=100, precision=pfm.MIXED)
+    prob = _gpu_problem(pfm, key, 40, 16, tol=1e-12, restart=100, precision=pfm.MIXED, store_self_blocks=True)
     x, info = prob.solve()
     _say("  ", info)
     # relaxed inner applies: FP64 first, complex64 once the residual is small
