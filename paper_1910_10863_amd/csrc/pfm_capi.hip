@@ -306,6 +306,17 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     if (circ[q]) n_circ_entries += (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
   }
   pb.n_near_circ = n_circ_entries;
+  // with mostly circulant pairs P2P is the short branch of the overlapped apply
+  {
+    long long stored_entries = 0;
+    for (int q = 0; q < npairs_all; ++q)
+      if (!circ[q]) {
+        const Cell& D = hp.cells[hp.leaves[hp.near_tgt[q]]];
+        const Cell& C = hp.cells[hp.near_src[q]];
+        stored_entries += (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
+      }
+    pb.p2p_on_side = n_circ_entries > stored_entries;
+  }
   // near-block storage of the other pairs: per target leaf its stored pairs
   // one after the other; with equal fibres, a region (the stored blocks of one
   // target leaf) is stored once for every leaf that has the same region

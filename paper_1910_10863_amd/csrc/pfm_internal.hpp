@@ -98,6 +98,7 @@ struct Problem {
   long long *d_leaf_blk = nullptr;      // per leaf: offset of its stored region
   long long n_near_stored = 0;          // element pairs stored in d_near
   long long n_near_circ = 0;            // element pairs taken from the circulant rows
+  bool p2p_on_side = false;             // overlapped apply: P2P on the side stream, the chain on the caller's
   int *d_ccols_ptr = nullptr;           // per leaf: range of its circulant source columns
   int *d_ccol_psi = nullptr;            // circulant source columns: index of phi in Psi
   int *d_ccol_loc = nullptr;            // circulant source columns: element index on its circle

@@ -1426,9 +1426,10 @@ static hipError_t upward_impl(Problem& pb, const cd* d_psi, hipEvent_t* ev) {
 }
 
 template <typename C, int NB>
-static void launch_p2p_batch(Problem& pb, int grid, const C* blocks, const cd* d_psi, cd* d_y, int B) {
+static void launch_p2p_batch(Problem& pb, hipStream_t st, int grid, const C* blocks, const cd* d_psi, cd* d_y,
+                             int B) {
   const BatchStrides bs = batch_strides(pb);
-  hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves,
+  hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, st, pb.d_leaves,
                      pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi,
                      pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, pb.d_ccols_ptr,
                      pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, (int)pb.hp.leaves.size(), pb.p2p_split,
@@ -1446,18 +1447,26 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
   const HostPlan& hp = pb.hp;
   int n_leaves = (int)hp.leaves.size();
   int nb = B > 0 ? B : 1;
-  hipStream_t fs = ev ? pb.stream : pb.side;
+  // Overlapped: the longer branch runs on the caller's stream and the shorter
+  // on the side stream, so that the join event has fired by the time the
+  // caller's stream reaches it (crossing between hardware queues costs
+  // microseconds at the fork and at the join).  P2P is the shorter branch
+  // when most near pairs come from the circulant rows.
+  const bool p2p_side = !ev && pb.p2p_on_side;
+  hipStream_t ps = p2p_side ? pb.side : pb.stream;
+  hipStream_t fs = (ev || p2p_side) ? pb.stream : pb.side;
   if (!ev) {
     (void)hipEventRecord(pb.ev_fork, pb.stream);
     (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
   }
   if (ev) fmm_chain<P>(pb, d_psi, fs, ev, false, nb);
-  // the P2P stream is queued first so that it starts while the chain is being queued
+  // P2P is queued first: on the side stream it starts while the chain is
+  // queued; on the caller's stream the chain's side-stream launches follow
   int items = n_leaves * pb.p2p_split;
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
   if (B == 0) {
 #define PFM_P2P(U)                                                                                             \
-  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, pb.stream, pb.d_leaves, pb.d_ebeg, \
+  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, ps, pb.d_leaves, pb.d_ebeg,       \
                      pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks,     \
                      pb.d_ccols_ptr, pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, n_leaves,             \
                      pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
@@ -1466,15 +1475,15 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
     else PFM_P2P(1);
 #undef PFM_P2P
   } else if (B == 1) {
-    launch_p2p_batch<C, 1>(pb, p2p_grid, blocks, d_psi, d_y, B);
+    launch_p2p_batch<C, 1>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   } else if (B == 2) {
-    launch_p2p_batch<C, 2>(pb, p2p_grid, blocks, d_psi, d_y, B);
+    launch_p2p_batch<C, 2>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   } else if (B <= 4) {
-    launch_p2p_batch<C, 4>(pb, p2p_grid, blocks, d_psi, d_y, B);
+    launch_p2p_batch<C, 4>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   } else if (B <= 8) {
-    launch_p2p_batch<C, 8>(pb, p2p_grid, blocks, d_psi, d_y, B);
+    launch_p2p_batch<C, 8>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   } else {
-    launch_p2p_batch<C, 16>(pb, p2p_grid, blocks, d_psi, d_y, B);
+    launch_p2p_batch<C, 16>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   }
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
   if (!ev) {
