@@ -95,7 +95,7 @@ void free_all(Problem& pb) {
   pb.h_hcol = nullptr;
   if (pb.h_hall) (void)hipHostFree(pb.h_hall);
   pb.h_hall = nullptr;
-  dfree(pb.d_npart); dfree(pb.d_hall);
+  dfree(pb.d_npart); dfree(pb.d_dcoef); dfree(pb.d_hall);
   if (pb.events) {
     for (int i = 0; i < 16; ++i) (void)hipEventDestroy(pb.ev[i]);
     (void)hipEventDestroy(pb.ev_fork);
@@ -594,8 +594,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
   pb.red_blocks = (int)std::min<size_t>(256, (n + 511) / 512);
   CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 255) / 256) * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_hall, (size_t)pb.opt.restart * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
-  CK(hipHostMalloc((void**)&pb.h_hall, (size_t)pb.opt.restart * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
+  CK(hipMalloc((void**)&pb.d_dcoef, MB * (2 * (size_t)pb.opt.restart + 4) * sizeof(cd)));
+  // restart + 1 columns: DCGS2 leaves the last reorthogonalisation of a cycle in column restart
+  CK(hipMalloc((void**)&pb.d_hall, ((size_t)pb.opt.restart + 1) * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
+  CK(hipHostMalloc((void**)&pb.h_hall, ((size_t)pb.opt.restart + 1) * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
   // dot partials [member][vector][block], then (long vectors) the reduced [member][vector]
   CK(hipMalloc((void**)&pb.d_red, MB * (pb.red_blocks + 1) * (2 * pb.opt.restart + 8) * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
@@ -925,6 +927,7 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
   std::vector<char> done(B, 0), cyc(B, 0);
   std::vector<int> jj(B, 0);
   std::vector<C> Hm((size_t)B * (m + 1) * m), g((size_t)B * (m + 1)), cs((size_t)B * m), sn((size_t)B * m);
+  std::vector<C> Hraw((size_t)B * (m + 1) * m);   // DCGS2: the Hessenberg matrix before the rotations
   auto sync_norms = [&](const cd* vec, std::vector<double>& out) -> hipError_t {
     hipError_t e = launch_dots_b(pb, B, vec, nb, nb, 1, vec, nb, n, hc, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(hh, hc, (size_t)B * hs * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
@@ -1019,11 +1022,16 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       if (cyc[i]) budget = std::max(budget, max_iter - gs[i].iters);
     }
     const int jmax = std::min(m, budget);
+    // plain cycles orthogonalise with delayed reorthogonalisation (DCGS2: two
+    // passes over the basis per step, column j final after step j + 1); the
+    // augmented first cycle keeps CGS2 (four passes, column j final at once)
+    const bool dcgs = !augmenting;
     auto enqueue = [&](int j) -> hipError_t {
       cd* Vj = V + (size_t)j * ldv;
       cd* Wj = V + (size_t)(j + 1) * ldv;
       hipError_t e = apply(Vj, Wj);
       if (e != hipSuccess) return e;
+      if (dcgs) return launch_dcgs_step(pb, B, V, ldv, nb, j, Wj, nb, n, hs2);
       cd* hcol = pb.d_hall + (size_t)j * B * hs2;
       e = launch_arnoldi_step(pb, B, V, ldv, nb, j, Wj, nb, n, hcol, hs2);
       if (e != hipSuccess || !augmenting) return e;
@@ -1035,28 +1043,40 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
       return hipMemcpyAsync(pb.h_hall + (size_t)j0 * B * hs2, pb.d_hall + (size_t)j0 * B * hs2,
                             (size_t)(j1 - j0) * B * hs2 * sizeof(cd), hipMemcpyDeviceToHost, pb.stream);
     };
-    int j_enq = 0, j_proc = 0;
+    int j_enq = 0, j_proc = 0, c_sched = 0;
     int grp = 0;
     hipEvent_t gev[2] = {pb.ev[14], pb.ev[15]};
     int gbeg[2] = {0, 0}, gend[2] = {0, 0};
-    // queue the first group
-    for (; j_enq < std::min(jmax, LOOK); ++j_enq) HIPCHK(pb, enqueue(j_enq));
-    HIPCHK(pb, readback(0, j_enq));
-    HIPCHK(pb, hipEventRecord(gev[0], pb.stream));
-    gbeg[0] = 0;
-    gend[0] = j_enq;
+    // Queue up to LOOK more steps and the read-back of the columns they make
+    // final (DCGS2: one behind, all at the end of the cycle), as group `slot`.
+    auto queue_group = [&](int slot) -> hipError_t {
+      int stop = std::min(jmax, j_enq + LOOK);
+      for (; j_enq < stop; ++j_enq) {
+        hipError_t e = enqueue(j_enq);
+        if (e != hipSuccess) return e;
+      }
+      if (dcgs && j_enq == jmax && jmax > 0) {
+        hipError_t e = launch_dcgs_finish(pb, B, V, ldv, nb, jmax - 1, n, hs2);
+        if (e != hipSuccess) return e;
+      }
+      const int c1 = std::max(c_sched, dcgs && j_enq < jmax ? j_enq - 1 : j_enq);
+      gbeg[slot] = c_sched;
+      gend[slot] = c1;
+      if (c1 > c_sched) {
+        // DCGS2 also needs the raw column c1 (the next step's a and gamma)
+        hipError_t e = readback(c_sched, dcgs ? c1 + 1 : c1);
+        if (e != hipSuccess) return e;
+      }
+      c_sched = c1;
+      return hipEventRecord(gev[slot], pb.stream);
+    };
+    HIPCHK(pb, queue_group(0));
     bool any = true;
     while (j_proc < jmax && any) {
       // queue the next group before waiting for the current one
       int nxt = grp ^ 1;
-      gbeg[nxt] = gend[nxt] = j_enq;
-      if (j_enq < jmax) {
-        int stop = std::min(jmax, j_enq + LOOK);
-        for (; j_enq < stop; ++j_enq) HIPCHK(pb, enqueue(j_enq));
-        HIPCHK(pb, readback(gbeg[nxt], j_enq));
-        HIPCHK(pb, hipEventRecord(gev[nxt], pb.stream));
-        gend[nxt] = j_enq;
-      }
+      gbeg[nxt] = gend[nxt] = c_sched;
+      if (j_enq < jmax) HIPCHK(pb, queue_group(nxt));
       HIPCHK(pb, hipEventSynchronize(gev[grp]));
       for (int j = gbeg[grp]; j < gend[grp] && any; ++j) {
         any = false;
@@ -1064,8 +1084,29 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
           if (!cyc[i]) continue;
           const cd* hv = pb.h_hall + ((size_t)j * B + i) * hs2;
           std::vector<C> col(j + 2);
-          for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);
-          double hn = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+          double hn;
+          if (dcgs) {
+            // raw step data of j and j + 1 -> column j of H (see launch_dcgs_step):
+            // h = ((b, s) - H[0..j][0..j-1] a) / gamma, plus beta a' of step j + 1,
+            // subdiagonal beta gamma'
+            const cd* rn = pb.h_hall + ((size_t)(j + 1) * B + i) * hs2;
+            const double gam = hv[2 * j + 1].x, beta = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+            const double gam1 = rn[2 * (j + 1) + 1].x;
+            C* Hr = &Hraw[(size_t)i * (m + 1) * m];
+            for (int r = 0; r <= j; ++r) {
+              C gr = 0.0;
+              for (int c = std::max(r - 1, 0); c < j; ++c) gr += Hr[(size_t)r * m + c] * C(hv[c].x, hv[c].y);
+              const C br = r < j ? C(hv[j + r].x, hv[j + r].y) : C(hv[2 * j].x, hv[2 * j].y);
+              const C hrj = (br - gr) / gam + beta * C(rn[r].x, rn[r].y);
+              Hr[(size_t)r * m + j] = hrj;
+              col[r] = hrj;
+            }
+            hn = beta * gam1;
+            Hr[(size_t)(j + 1) * m + j] = hn;
+          } else {
+            for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);
+            hn = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+          }
           if (!std::isfinite(hn)) {
             st[i] = fail(pb, PFM_ENUMERIC, "non-finite Arnoldi norm");
             cyc[i] = 0;

@@ -161,6 +161,7 @@ struct Problem {
   cd *d_w = nullptr, *d_r = nullptr, *d_b = nullptr, *d_tmp = nullptr;
   cd *d_red = nullptr;                  // reduction partials
   double *d_npart = nullptr;            // per-block squared norms [member][block]
+  cd *d_dcoef = nullptr;                // DCGS2 update coefficients [member][2 restart + 4]
   cd *d_hall = nullptr, *h_hall = nullptr;   // Arnoldi columns [restart][member][2 restart + 4]
   cd *d_hcol = nullptr;                 // column of dots
   cd *h_hcol = nullptr;                 // pinned host copy

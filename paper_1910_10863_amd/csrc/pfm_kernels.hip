@@ -1777,6 +1777,207 @@ __global__ void __launch_bounds__(256) k_normalize_fused(cd* w, long long wsb, c
 // h1 = V^H W; W -= V h1; h2 = V^H W; W -= V h2; W /= ||W||.
 // Column j of every member is stored at hcol + b * hsb: h1 in [0, j],
 // h2 in [j+1, 2j+1], ||W||^2 in [2j+2].
+// ---- Arnoldi with delayed reorthogonalisation (DCGS2: Bielich, Langou,
+// Thomas, Swirydowicz, Yamazaki & Boman 2022) ----
+// Step j holds v_0..v_{j-1} final and u_j (slot j) orthogonalised once and
+// normalised; w = Op u_j is in slot j+1.  One reduction gives
+// a = V_{j-1}^H u_j, d = u_j^H u_j, b = V_{j-1}^H w, c = u_j^H w.  Then
+//   gamma = sqrt(d - |a|^2),  v_j = (u_j - V_{j-1} a) / gamma      (second pass of step j-1)
+//   s = v_j^H w = (c - a^H b) / gamma
+//   w1 = (w - V_{j-1} b - s v_j) / gamma,  u_{j+1} = w1 / ||w1||
+// so every step reads the basis twice (one reduction, one update) instead of
+// four times.  The Hessenberg column needs g = H[0..j][0..j-1] a (the
+// Arnoldi relation applied to V_{j-1} a): h = ((b, s) - g) / gamma, and
+// column j-1 gains beta a and the subdiagonal beta gamma.  That small dense
+// algebra is left to the host, which reads per step j the raw column
+// [a (j) | b (j) | s | gamma | ||w1||^2] from d_hall (slot 2(j+1) is the
+// squared norm, as for CGS2).
+
+// partial[member][v * cnt + i][block] = V_i^H x_v over the block's chunks, x_0 = V_{cnt-1}
+// (u_j), x_1 = w (NV = 2) or only x_0 (NV = 1)
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS) k_dots2(const cd* __restrict__ V, long long ldv, long long vsb,
+                                                       int cnt, const cd* __restrict__ w, long long wsb, int n,
+                                                       cd* partial) {
+  const int nblk = gridDim.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * DOT_VPB + wv * DOT_VPW;
+  if (i0 >= cnt) return;
+  V += blockIdx.z * vsb;
+  w += blockIdx.z * wsb;
+  partial += (size_t)blockIdx.z * NV * cnt * nblk;
+  const cd* u = V + (size_t)(cnt - 1) * ldv;
+  for (int c0 = blockIdx.x * DOT_CHUNK; c0 < n; c0 += nblk * DOT_CHUNK) {
+    cd xr[NV][DOT_PER_LANE];
+#pragma unroll
+    for (int s = 0; s < DOT_PER_LANE; ++s) {
+      int t = c0 + lane + 64 * s;
+      xr[0][s] = t < n ? u[t] : mkc(0, 0);
+      if (NV == 2) xr[NV - 1][s] = t < n ? w[t] : mkc(0, 0);
+    }
+    const bool first = c0 == blockIdx.x * DOT_CHUNK;
+    cd acc[DOT_VPW][NV];
+#pragma unroll
+    for (int q = 0; q < DOT_VPW; ++q) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[q][v] = mkc(0, 0);
+      const int i = min(i0 + q, cnt - 1);
+      const cd* vi = V + (size_t)i * ldv + c0 + lane;
+#pragma unroll
+      for (int s = 0; s < DOT_PER_LANE; ++s)
+        if (c0 + lane + 64 * s < n) {
+          const cd a = vi[64 * s];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[q][v] = cfma_conj(a, xr[v][s], acc[q][v]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < DOT_VPW; ++q)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cd r = wave_sum(acc[q][v]);
+        if (lane == 0 && i0 + q < cnt) {
+          cd* dst = partial + ((size_t)v * cnt + i0 + q) * nblk + blockIdx.x;
+          *dst = first ? r : cadd(*dst, r);
+        }
+      }
+  }
+}
+
+// One block per member, from the reduced dots fin[member][NV cnt]: gamma, s,
+// the update coefficients (coef: [0, j) a/gamma, [j, 2j) b/gamma, 2j s/gamma,
+// 2j+1 1/gamma) and the raw column j of d_hall (slots [0, j) a, [j, 2j) b,
+// 2j s, 2j+1 gamma).  NV = 1 (end of a cycle, x_0 = u_j): a and gamma only.
+__global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, int j, int NV, cd* hcol,
+                                                    long long hsb, cd* coef, long long csb) {
+  __shared__ double s_a2[256];
+  __shared__ cd s_ab[256];
+  const int b = blockIdx.x, cnt = j + 1;
+  fin += (size_t)b * NV * cnt;
+  hcol += b * hsb;
+  coef += b * csb;
+  double q2 = 0.0;
+  cd ab = mkc(0, 0);
+  for (int i = threadIdx.x; i < j; i += 256) {
+    q2 += cabs2(fin[i]);
+    if (NV == 2) ab = cfma_conj(fin[i], fin[cnt + i], ab);
+  }
+  s_a2[threadIdx.x] = q2;
+  s_ab[threadIdx.x] = ab;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s_a2[threadIdx.x] += s_a2[threadIdx.x + st];
+      s_ab[threadIdx.x] = cadd(s_ab[threadIdx.x], s_ab[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  const double g2 = fin[j].x - s_a2[0];
+  const double gamma = sqrt(g2 > 1e-300 ? g2 : 1e-300);
+  const double ig = 1.0 / gamma;
+  for (int i = threadIdx.x; i < j; i += 256) {
+    hcol[i] = fin[i];
+    coef[i] = cscale(fin[i], ig);
+    if (NV == 2) {
+      hcol[j + i] = fin[cnt + i];
+      coef[j + i] = cscale(fin[cnt + i], ig);
+    }
+  }
+  if (threadIdx.x == 0) {
+    hcol[2 * j + 1] = mkc(gamma, 0.0);
+    if (NV == 2) {
+      const cd sv = cscale(csub(fin[cnt + j], s_ab[0]), ig);
+      hcol[2 * j] = sv;
+      coef[2 * j] = cscale(sv, ig);
+      coef[2 * j + 1] = mkc(ig, 0.0);
+    }
+  }
+}
+
+// v_j = u_j / gamma - V_{j-1} (a / gamma) into slot j; w = w / gamma - V_{j-1} (b / gamma)
+// - (s / gamma) v_j, and the partial squared norms of w.
+__global__ void __launch_bounds__(256) k_dcgs_update(cd* V, long long ldv, long long vsb, int j, cd* w,
+                                                     long long wsb, const cd* __restrict__ coef, long long csb,
+                                                     int n, double* npart) {
+  __shared__ cd sv[256], sw[256];
+  __shared__ double sn[256];
+  const int b = blockIdx.y;
+  V += b * vsb;
+  w += b * wsb;
+  coef += b * csb;
+  const double ig = coef[2 * j + 1].x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  cd vj = t < n ? cscale(V[(size_t)j * ldv + t], ig) : mkc(0, 0);
+  cd wa = t < n ? cscale(w[t], ig) : mkc(0, 0);
+  for (int i0 = 0; i0 < j; i0 += 256) {
+    const int c = min(256, j - i0);
+    if ((int)threadIdx.x < c) {
+      sv[threadIdx.x] = coef[i0 + threadIdx.x];
+      sw[threadIdx.x] = coef[j + i0 + threadIdx.x];
+    }
+    __syncthreads();
+    if (t < n) {
+#pragma unroll 8
+      for (int i = 0; i < c; ++i) {
+        const cd vi = V[(size_t)(i0 + i) * ldv + t];
+        vj = csub(vj, cmul(sv[i], vi));
+        wa = csub(wa, cmul(sw[i], vi));
+      }
+    }
+    __syncthreads();
+  }
+  wa = csub(wa, cmul(coef[2 * j], vj));
+  if (t < n) {
+    V[(size_t)j * ldv + t] = vj;
+    w[t] = wa;
+  }
+  sn[threadIdx.x] = t < n ? cabs2(wa) : 0.0;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sn[threadIdx.x] += sn[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) npart[(size_t)b * gridDim.x + blockIdx.x] = sn[0];
+}
+
+hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long vsb, int j, cd* W, long long wsb,
+                            int n, long long hsb) {
+  const int cnt = j + 1;
+  const int nblk = pb.red_blocks;
+  const int nu = (n + 255) / 256;
+  const long long hcs = (long long)B * hsb;                 // column stride in d_hall
+  const long long csb = 2LL * pb.opt.restart + 4;
+  cd* fin = pb.d_red + (size_t)B * 2 * cnt * nblk;          // [B][2 cnt] reduced dots
+  hipLaunchKernelGGL(k_dots2<2>, dim3(nblk, (cnt + DOT_VPB - 1) / DOT_VPB, B), dim3(RED_THREADS), 0, pb.stream,
+                     V, ldv, vsb, cnt, W, wsb, n, pb.d_red);
+  hipLaunchKernelGGL(k_dots_final, dim3(2 * cnt, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, 2 * cnt, fin,
+                     2LL * cnt);
+  hipLaunchKernelGGL(k_dcgs_coeff, dim3(B), dim3(256), 0, pb.stream, fin, j, 2, pb.d_hall + (size_t)j * hcs, hsb,
+                     pb.d_dcoef, csb);
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nu, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, pb.d_dcoef, csb, n,
+                     pb.d_npart);
+  hipLaunchKernelGGL(k_normalize_fused, dim3(nu, B), dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nu,
+                     pb.d_hall + (size_t)j * hcs + 2 * cnt, hsb, n);
+  return hipGetLastError();
+}
+
+// End of a cycle after step jl: the reorthogonalisation coefficients a and
+// gamma of u_{jl+1} (slot jl + 1) into raw column jl + 1 of d_hall.
+hipError_t launch_dcgs_finish(Problem& pb, int B, cd* V, long long ldv, long long vsb, int jl, int n,
+                              long long hsb) {
+  const int j = jl + 1, cnt = j + 1;
+  const int nblk = pb.red_blocks;
+  const long long hcs = (long long)B * hsb;
+  cd* fin = pb.d_red + (size_t)B * cnt * nblk;
+  hipLaunchKernelGGL(k_dots2<1>, dim3(nblk, (cnt + DOT_VPB - 1) / DOT_VPB, B), dim3(RED_THREADS), 0, pb.stream,
+                     V, ldv, vsb, cnt, (const cd*)V, vsb, n, pb.d_red);
+  hipLaunchKernelGGL(k_dots_final, dim3(cnt, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, cnt, fin,
+                     (long long)cnt);
+  hipLaunchKernelGGL(k_dcgs_coeff, dim3(B), dim3(256), 0, pb.stream, fin, j, 1, pb.d_hall + (size_t)j * hcs, hsb,
+                     pb.d_dcoef, 2LL * pb.opt.restart + 4);
+  return hipGetLastError();
+}
+
 hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int j, cd* W,
                                long long wsb, int n, cd* hcol, long long hsb) {
   const int cnt = j + 1;

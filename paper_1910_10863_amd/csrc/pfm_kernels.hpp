@@ -39,6 +39,10 @@ hipError_t launch_update_b(Problem& pb, int B, cd* w, long long wsb, const cd* V
 hipError_t launch_gemv_acc_b(Problem& pb, int B, cd* x, long long xsb, const cd* V, long long ldv, long long vsb,
                              int cnt, const cd* d_c, long long csb, int n);
 // one CGS2 Arnoldi step of B members (fused: five launches)
+hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long vsb, int j, cd* W, long long wsb,
+                            int n, long long hsb);
+hipError_t launch_dcgs_finish(Problem& pb, int B, cd* V, long long ldv, long long vsb, int jl, int n,
+                              long long hsb);
 hipError_t launch_arnoldi_step(Problem& pb, int B, const cd* V, long long ldv, long long vsb, int j, cd* W,
                                long long wsb, int n, cd* hcol, long long hsb);
 // B members: g = v^H c, c -= g v, store g and ||c||^2 (augmented GMRES)
