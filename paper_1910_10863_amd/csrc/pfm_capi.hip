@@ -222,12 +222,13 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.H = pb.MH * pb.a;
 
   {
-    // P2P runs as a persistent grid of two workgroups per compute unit, which
-    // saturates HBM and leaves room on every CU for the concurrent FMM chain
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
-      pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : 2) * ncu;
+    // P2P runs as a persistent grid of a few workgroups per compute unit (set
+    // once the near pairs are classified), leaving room on every CU for the
+    // concurrent FMM chain
+    int dev = 0;
+    if (!(hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&pb.n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess))
+      pb.n_cu = 0;
     pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : 1;
   }
   // discretisation on the device
@@ -316,6 +317,11 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         stored_entries += (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
       }
     pb.p2p_on_side = n_circ_entries > stored_entries;
+    // default grid: two workgroups per CU stream stored blocks at full HBM
+    // rate without starving the chain; the light circulant P2P on the side
+    // stream takes four (measured fastest for the overlapped apply)
+    if (pb.n_cu > 0)
+      pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : (pb.p2p_on_side ? 4 : 2)) * pb.n_cu;
   }
   // near-block storage of the other pairs: per target leaf its stored pairs
   // one after the other; with equal fibres, a region (the stored blocks of one

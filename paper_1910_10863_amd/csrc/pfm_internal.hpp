@@ -135,6 +135,7 @@ struct Problem {
   int *d_mchunks = nullptr;             // [n_mchunks][4]: cell, channel, first entry, count (<= M2L_CHUNK entries)
   int n_mchunks = 0;
   cd *d_epart = nullptr;                // [n_mchunks][2p+1] M2L result of each entry chunk
+  int n_cu = 0;                         // compute units of the device
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
   int p2p_unroll = 1;                   // source columns in flight per P2P wavefront

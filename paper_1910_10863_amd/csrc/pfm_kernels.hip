@@ -1086,7 +1086,9 @@ template <> __device__ __forceinline__ float2 nt_load<float2>(const float2* p) {
 }
 
 template <typename C, int U>
-__global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
+// the persistent grid holds few workgroups per CU (p2p_blocks_per_cu), so the
+// register budget is not cut for occupancy
+__global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
     const int* __restrict__ leaves, const int* __restrict__ ebeg, const int* __restrict__ eend,
     const int* __restrict__ psi_idx, int N, const long long* __restrict__ leaf_blk,
     const int* __restrict__ cols_ptr, const int* __restrict__ col_psi, const C* __restrict__ blocks,
@@ -1177,7 +1179,29 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, U >= 4 ? 4 : 8) k_p2p(
         }
         __syncthreads();
         if (act) {
-          for (int k = w; k < nseg; k += P2P_WAVES) {
+          // four columns' row entries in flight per wavefront (cached loads)
+          constexpr int CU = 4;
+          int k = w;
+          for (; k + (CU - 1) * P2P_WAVES < nseg; k += CU * P2P_WAVES) {
+            cd cc[CU][4];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+              const cd* cr = crow + sl[k + u * P2P_WAVES];
+              cc[u][0] = cr[0];
+              cc[u][1] = cr[2 * N];
+              cc[u][2] = cr[4 * N];
+              cc[u][3] = cr[6 * N];
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+              cd ph = sp[k + u * P2P_WAVES][0], vp = sp[k + u * P2P_WAVES][1];
+              a1 = cfma(cc[u][0], ph, a1);
+              a1 = cfma(cc[u][1], vp, a1);
+              a2 = cfma(cc[u][2], ph, a2);
+              a2 = cfma(cc[u][3], vp, a2);
+            }
+          }
+          for (; k < nseg; k += P2P_WAVES) {
             const cd* cr = crow + sl[k];
             cd ph = sp[k][0], vp = sp[k][1];
             a1 = cfma(cr[0], ph, a1);
