@@ -778,17 +778,33 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
   int cell = cells[ci];
   cd acc[NU];
   for (int i = 0; i < NU; ++i) acc[i] = mkc(0, 0);
-  for (int q = ptr[ci] + w; q < ptr[ci + 1]; q += 4) {
-    const cd* ms = mpole + ((size_t)src[q] * 2 + ch) * NP;
-    const cd* tj = jtab + ((size_t)ch * n_joff + off[q]) * NT;
+  constexpr int NTU = (NT + 63) / 64;
+  // the next leaf's moments and translation row are loaded into registers
+  // while the current leaf is translated (double buffering of the loads)
+  const int qend = ptr[ci + 1];
+  int q = ptr[ci] + w;
+  cd mnext[NU], tnext[NTU];
+  auto fetch = [&](int qq) {
+    const cd* ms = mpole + ((size_t)src[qq] * 2 + ch) * NP;
+    const cd* tj = jtab + ((size_t)ch * n_joff + off[qq]) * NT;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) mnext[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
+#pragma unroll
+    for (int u = 0; u < NTU; ++u) tnext[u] = lane + 64 * u < NT ? tj[lane + 64 * u] : mkc(0, 0);
+  };
+  if (q < qend) fetch(q);
+  for (; q < qend; q += 4) {
     // the leaf's moments stay in registers and reach the lanes by lane reads
     cd mreg[NU];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) mreg[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
-    for (int i = lane; i < NT; i += 64) sj[w][i] = tj[i];
+    for (int u = 0; u < NU; ++u) mreg[u] = mnext[u];
+#pragma unroll
+    for (int u = 0; u < NTU; ++u)
+      if (lane + 64 * u < NT) sj[w][lane + 64 * u] = tnext[u];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
+    if (q + 4 < qend) fetch(q + 4);
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
       int n = min(lane + 64 * i - P, P);      // lanes past the last order repeat it
@@ -840,18 +856,33 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   const int lane = threadIdx.x;
   cd acc[NU];
   for (int i = 0; i < NU; ++i) acc[i] = mkc(0, 0);
+  constexpr int NTU = (NT + 63) / 64;
+  // the next entry's moments, row and phase are loaded into registers while
+  // the current entry is translated (double buffering of the loads)
+  cd mnext[NU], tnext[NTU], pnext;
+  auto fetch = [&](int qq) {
+    const cd* ms = mpole + ((size_t)e_src[qq] * 2 + ch) * NP;
+    const cd* th = htab + ((size_t)ch * n_tab + e_off[qq]) * NT;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) mnext[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
+#pragma unroll
+    for (int u = 0; u < NTU; ++u) tnext[u] = lane + 64 * u < NT ? th[lane + 64 * u] : mkc(0, 0);
+    pnext = alpha[e_m[qq] - m_min];
+  };
+  if (b < e) fetch(b);
   for (int q = b; q < e; ++q) {
-    const cd* ms = mpole + ((size_t)e_src[q] * 2 + ch) * NP;
-    const cd* th = htab + ((size_t)ch * n_tab + e_off[q]) * NT;
     // the source moments stay in registers (order n in lane n % 64 of slot
     // n / 64) and reach every lane through lane reads; only the translation
     // row goes through LDS
     cd mreg[NU];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) mreg[u] = lane + 64 * u < NP ? ms[lane + 64 * u] : mkc(0, 0);
-    for (int i = lane; i < NT; i += 64) sh[i] = th[i];
-    cd ph = alpha[e_m[q] - m_min];
+    for (int u = 0; u < NU; ++u) mreg[u] = mnext[u];
+#pragma unroll
+    for (int u = 0; u < NTU; ++u)
+      if (lane + 64 * u < NT) sh[lane + 64 * u] = tnext[u];
+    cd ph = pnext;
     __syncthreads();
+    if (q + 1 < e) fetch(q + 1);
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
       int l = min(lane + 64 * i - P, P);      // lanes past the last order repeat it
