@@ -155,3 +155,30 @@ def test_energy_balance_converges():
         res.append(abs(fl.energy_residual(pb, psi)))
     assert res[1] < 3e-3
     assert 1.7 < res[0] / res[1] < 2.3
+
+
+def test_free_space_self_blocks_are_circulant():
+    """A fibre is a circle cut into N equal chords; rotating by one chord maps
+    element a to a + 1 together with its normal, quadrature points and self
+    term, so without images every 2x2 block of a fibre's elements a, b
+    depends only on (b - a) mod N (the symmetry behind the circulant self
+    rows of the near field).  Two fibres of different radii in free space."""
+    wl = W.small_square(2, 1, 32, radii=np.array([0.3, 0.22]))
+    pb = sy.problem_from_workload(wl, 2.5, 0.4, periodic=False)
+    A = sy.dense_matrix(pb)
+    bd = pb.bd
+    N = bd.N
+    for f in range(bd.M):
+        e = f * N + np.arange(N)
+        rot = f * N + (np.arange(N) + 1) % N
+        for rows in (sy.col_phi, sy.col_varphi):
+            for cols in (sy.col_phi, sy.col_varphi):
+                blk = A[np.ix_(rows(bd, e), cols(bd, e))]
+                shifted = A[np.ix_(rows(bd, rot), cols(bd, rot))]
+                assert np.max(np.abs(shifted - blk)) < 1e-11 * np.max(np.abs(blk))
+    # with the images the diagonal blocks lose the symmetry: the periodic
+    # system differs from the free-space one there
+    Ap = sy.dense_matrix(sy.problem_from_workload(wl, 2.5, 0.4, periodic=True))
+    e0 = np.arange(N)
+    d = Ap[np.ix_(sy.col_phi(bd, e0), sy.col_phi(bd, e0))] - A[np.ix_(sy.col_phi(bd, e0), sy.col_phi(bd, e0))]
+    assert np.max(np.abs(d[1:, 1:] - d[:-1, :-1])) > 1e-6
