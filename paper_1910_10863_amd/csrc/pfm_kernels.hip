@@ -939,53 +939,64 @@ __global__ void __launch_bounds__(256) k_m2l_sum(const int* __restrict__ sums, c
 //   u = sum_l L_l Jp_l(kap (x - O)),  dn = (kap/2) sum_l L_l (nu Jp_{l-1} - conj(nu) Jp_{l+1}),
 // and the far part of the rows of (I - A) (eq. 9) is written:
 //   far1 = u_ext - u_int,  far2 = 2/(i eta (1 + varrho)) (dn_ext - varrho dn_int).
+// The kernel is bound by load latency, not arithmetic: the leaf descriptor
+// names the sum rows and the target geometry directly, so the loads form two
+// dependent steps, and each ancestor's sum and translation row are loaded
+// while the previous ancestor is translated.
 template <int P>
-__global__ void __launch_bounds__(128) k_down(
-    int nc, const int* __restrict__ leaves, const int* __restrict__ aptr, const int* __restrict__ anc,
-    const int* __restrict__ aoff, const int* __restrict__ cc_ptr, const cd* __restrict__ part,
-    const cd* __restrict__ jtab, int n_joff, const int* __restrict__ ebeg, const int* __restrict__ eend,
-    const int* __restrict__ elem_of, const int* __restrict__ psi_idx, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ mx, const double* __restrict__ my,
-    const double* __restrict__ tx, const double* __restrict__ ty, int N, double k, double k1, double eta,
-    double varrho, cd* __restrict__ far, long long part_stride, long long far_stride) {
-  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
+__global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, const int2* __restrict__ lanc,
+                                              const double4* __restrict__ tgeo, const int* __restrict__ psi_idx,
+                                              const cd* __restrict__ part, const cd* __restrict__ jtab, int n_joff,
+                                              int N, double k, double k1, double eta, double varrho,
+                                              cd* __restrict__ far, long long part_stride, long long far_stride) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64;
   __shared__ cd sJ[2][NT], sL[2][NP];
   __shared__ cd su[64], sd[64];
   part += blockIdx.y * part_stride;             // batch member
   far += blockIdx.y * far_stride;
-  int li = blockIdx.x;
-  int D = leaves[li];
-  int ch = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // own chunks of the leaf
+  const int* dsc = ldesc + 8 * blockIdx.x;
+  const int ch = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = dsc[0], rows = dsc[1], own = dsc[2 + ch];
+  const int q0 = dsc[4 + 2 * ch], na = dsc[5 + 2 * ch] - q0;
+  // independent loads first: target geometry, the leaf's own sum (order l in
+  // lane l % 64 of slot l / 64) and the ancestors' (sum row, offset), one per lane
+  double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+  int pi = 0;
+  if (lane < rows) {
+    g = tgeo[rb + lane];
+    pi = psi_idx[rb + lane];
+  }
   cd acc[NU];
+#pragma unroll
   for (int u = 0; u < NU; ++u) {
     int i = lane + 64 * u;
-    cd sres = mkc(0, 0);
-    if (i < NP) {
-      int c0 = cc_ptr[ch * nc + D], c1 = cc_ptr[ch * nc + D + 1];
-      for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
-    }
-    acc[u] = sres;
+    acc[u] = (own >= 0 && i < NP) ? part[(size_t)own * NP + i] : mkc(0, 0);
   }
-  // ancestors
-  for (int q = aptr[li]; q < aptr[li + 1]; ++q) {
-    int A = anc[q];
-    int c0 = cc_ptr[ch * nc + A], c1 = cc_ptr[ch * nc + A + 1];
-    if (c1 == c0) continue;                      // wave-uniform
-    // the ancestor's own sum, order l in lane l % 64 of slot l / 64
+  int2 an = make_int2(0, 0);
+  if (lane < na) an = lanc[q0 + lane];
+  cd anext[NU], tnext[NTU];
+  auto fetch = [&](int q) {
+    const int r = __builtin_amdgcn_readlane(an.x, q), o = __builtin_amdgcn_readlane(an.y, q);
+    const cd* ps = part + (size_t)r * NP;
+    const cd* tj = jtab + ((size_t)ch * n_joff + o) * NT;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) anext[u] = lane + 64 * u < NP ? ps[lane + 64 * u] : mkc(0, 0);
+#pragma unroll
+    for (int u = 0; u < NTU; ++u) tnext[u] = lane + 64 * u < NT ? tj[lane + 64 * u] : mkc(0, 0);
+  };
+  if (na > 0) fetch(0);
+  for (int q = 0; q < na; ++q) {                // wave-uniform trip count
     cd areg[NU];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      int i = lane + 64 * u;
-      cd sres = mkc(0, 0);
-      if (i < NP)
-        for (int c = c0; c < c1; ++c) sres = cadd(sres, part[(size_t)c * NP + i]);
-      areg[u] = sres;
-    }
-    const cd* tj = jtab + ((size_t)ch * n_joff + aoff[q]) * NT;
-    for (int i = lane; i < NT; i += 64) sJ[ch][i] = tj[i];
+    for (int u = 0; u < NU; ++u) areg[u] = anext[u];
+#pragma unroll
+    for (int u = 0; u < NTU; ++u)
+      if (lane + 64 * u < NT) sJ[ch][lane + 64 * u] = tnext[u];
+    if (q + 1 < na) fetch(q + 1);
+    // the row is read only by this wavefront: its LDS stores must be done
+    // (lgkmcnt 0), the loads of the next ancestor stay in flight
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -1007,13 +1018,11 @@ __global__ void __launch_bounds__(128) k_down(
   }
   __syncthreads();
   // L2P
-  int db = ebeg[D], rows = eend[D] - db;
   cd u = mkc(0, 0), dv = mkc(0, 0);
   double kap = ch ? k1 : k;
   if (lane < rows) {
-    int e = elem_of[db + lane];
-    double vx = kap * (mx[e] - cx[D]), vy = kap * (my[e] - cy[D]);
-    cd nu = mkc(ty[e], -tx[e]);
+    double vx = kap * g.x, vy = kap * g.y;
+    cd nu = mkc(g.w, -g.z);
     cd nub = cconj(nu);
     double gs[P + 2];
     scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
@@ -1052,7 +1061,6 @@ __global__ void __launch_bounds__(128) k_down(
   }
   __syncthreads();
   if (ch == 0 && lane < rows) {
-    int pi = psi_idx[db + lane];
     cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
     far[pi] = csub(u, su[lane]);
     far[pi + N] = cmul(c, csub(dv, cscale(sd[lane], varrho)));
@@ -1467,10 +1475,10 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                        bs.epart, bs.part);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, nc, pb.d_leaves, pb.d_anc_ptr, pb.d_anc,
-                     pb.d_anc_off, pb.d_cc_ptr, pb.d_part, pb.d_jtab, n_joff, pb.d_ebeg, pb.d_eend,
-                     pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.N,
-                     pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far, bs.part, bs.vec);
+  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, pb.d_ldesc,
+                     reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
+                     pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far,
+                     bs.part, bs.vec);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 

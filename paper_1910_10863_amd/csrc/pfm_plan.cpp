@@ -213,6 +213,9 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
     if (c.leaf) {
       c.leaf_index = (int)hp.leaves.size();
       hp.leaves.push_back(i);
+      // a leaf's rows are the lanes of one wavefront in P2P and L2P;
+      // only the level cap can leave more than leaf_max elements in a leaf
+      if (c.eend - c.ebeg > 64) return false;
     }
   }
   for (int i = 0; i < nc; ++i) {
