@@ -950,7 +950,7 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
                                               int N, double k, double k1, double eta, double varrho,
                                               cd* __restrict__ far, long long part_stride, long long far_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64;
-  __shared__ cd sJ[2][NT], sL[2][NP];
+  __shared__ cd sJ[2][NT], sL[2][NP], sS[2][3][P + 2], sT[2][3][P + 2];
   __shared__ cd su[64], sd[64];
   part += blockIdx.y * part_stride;             // batch member
   far += blockIdx.y * far_stride;
@@ -1017,43 +1017,54 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
     if (i < NP) sL[ch][i] = acc[u];
   }
   __syncthreads();
-  // L2P
+  // L2P.  The three sums u = sum_n L_n Jp_n, A = sum_n L_{n+1} Jp_n and
+  // B = sum_n L_{n-1} Jp_n (|n| <= P + 1; dn = (kap/2)(nu A - conj(nu) B))
+  // fold order -n onto order n through Jp_{-n} = (-1)^n conj(Jp_n): with
+  // Jp_n = x_n + i y_n and coefficients c_n,
+  //   c_n Jp_n + c_{-n} Jp_{-n} = s_n x_n + t_n y_n,
+  //   s_n = c_n + (-1)^n c_{-n},  t_n = i (c_n - (-1)^n c_{-n}),
+  // so each target needs 4 real FMA per sum and order n >= 0.
+  constexpr int K = P + 1;
+  if (lane <= K) {
+    const int n = lane;
+    const double sg = (n & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int sh = j == 0 ? 0 : (j == 1 ? 1 : -1);
+      const int lp = n + sh, lm = -n + sh;
+      cd c = (lp >= -P && lp <= P) ? sL[ch][P + lp] : mkc(0, 0);
+      cd e = (lm >= -P && lm <= P) ? cscale(sL[ch][P + lm], sg) : mkc(0, 0);
+      cd d = csub(c, e);
+      sS[ch][j][n] = n ? cadd(c, e) : c;
+      sT[ch][j][n] = n ? mkc(-d.y, d.x) : mkc(0, 0);
+    }
+  }
+  __syncthreads();
   cd u = mkc(0, 0), dv = mkc(0, 0);
   double kap = ch ? k1 : k;
   if (lane < rows) {
     double vx = kap * g.x, vy = kap * g.y;
-    cd nu = mkc(g.w, -g.z);
-    cd nub = cconj(nu);
-    double gs[P + 2];
-    scaled_j<P + 1>(0.25 * (vx * vx + vy * vy), gs);
+    double gs[K + 1];
+    scaled_j<K>(0.25 * (vx * vx + vy * vy), gs);
     cd hv = mkc(0.5 * vx, 0.5 * vy);
-    cd uu = hv;
-    cd J0 = mkc(gs[0], 0.0);                 // Jp_0
-    cd J1 = cscale(uu, gs[1]);               // Jp_1
-    cd Jprev = cscale(cconj(J1), -1.0);      // Jp_{-1}
+    cd uu = mkc(1.0, 0.0);                   // (v/2)^n / n!
+    cd sa = mkc(0, 0), sb = mkc(0, 0);
 #pragma unroll
-    for (int m = 0; m <= P; ++m) {
-      cd Lp = sL[ch][P + m];
-      u = cfma(Lp, J0, u);
-      dv = cfma(Lp, csub(cmul(nu, Jprev), cmul(nub, J1)), dv);
-      if (m > 0) {
-        // l = -m: Jp_{-m} = (-1)^m conj(Jp_m), Jp_{-m-1}, Jp_{-m+1}
-        double sm = (m & 1) ? -1.0 : 1.0;
-        cd jn = cscale(cconj(J0), sm);
-        cd jnm = cscale(cconj(J1), -sm);
-        cd jnp = cscale(cconj(Jprev), -sm);
-        cd Lm = sL[ch][P - m];
-        u = cfma(Lm, jn, u);
-        dv = cfma(Lm, csub(cmul(nu, jnm), cmul(nub, jnp)), dv);
-      }
-      if (m < P) {
-        uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
-        Jprev = J0;
-        J0 = J1;
-        J1 = cscale(uu, gs[m + 2]);
-      }
+    for (int n = 0; n <= K; ++n) {
+      const double x = uu.x * gs[n], y = uu.y * gs[n];   // Jp_n
+      cd s0 = sS[ch][0][n], t0 = sT[ch][0][n];
+      cd s1 = sS[ch][1][n], t1 = sT[ch][1][n];
+      cd s2 = sS[ch][2][n], t2 = sT[ch][2][n];
+      u.x = fma(s0.x, x, fma(t0.x, y, u.x));
+      u.y = fma(s0.y, x, fma(t0.y, y, u.y));
+      sa.x = fma(s1.x, x, fma(t1.x, y, sa.x));
+      sa.y = fma(s1.y, x, fma(t1.y, y, sa.y));
+      sb.x = fma(s2.x, x, fma(t2.x, y, sb.x));
+      sb.y = fma(s2.y, x, fma(t2.y, y, sb.y));
+      if (n < K) uu = cscale(cmul(uu, hv), 1.0 / (double)(n + 1));
     }
-    dv = cscale(dv, 0.5 * kap);
+    cd nu = mkc(g.w, -g.z);
+    dv = cscale(csub(cmul(nu, sa), cmul(cconj(nu), sb)), 0.5 * kap);
   }
   if (ch == 1) {
     su[lane] = u;
