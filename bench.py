@@ -379,7 +379,7 @@ def main():
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_near_stored", "n_near_circulant",
-                                    "n_root_offsets", "lattice_q")},
+                                    "p2p_window_leaves", "p2p_window_max", "n_root_offsets", "lattice_q")},
         "wall_s": wall,
     }
     print(json.dumps(out), flush=True)

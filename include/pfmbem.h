@@ -113,7 +113,11 @@ typedef struct {
  *  store_self_blocks  0: near pairs of a fibre with itself (image 0) use one
  *             circulant row per fibre (the N chords of a circle are rotations
  *             of each other, so their 2x2 block depends only on the index
- *             difference mod N); 1: every near pair is a stored block */
+ *             difference mod N); 1: every near pair is a stored block
+ *  p2p_cached_rows  0: for each target leaf, P2P copies the window of its
+ *             fibre's circulant rows that the leaf reads (at most 320 entries)
+ *             into LDS once; 1: every row entry is read through the caches.
+ *             Both give the same sums in the same order. */
 typedef struct {
   int p;
   int leaf_max;
@@ -130,6 +134,7 @@ typedef struct {
   int p2p_blocks_per_cu;
   int p2p_unroll;
   int store_self_blocks;
+  int p2p_cached_rows;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -164,6 +169,9 @@ typedef struct {
                                   same near region (the same sources at the same offsets and
                                   images) read one stored copy of it */
   long long n_near_circulant;  /* element pairs taken from the circulant rows of their fibre */
+  int p2p_window_leaves;       /* target leaves whose circulant row entries P2P stages in LDS
+                                  (one window of consecutive entries per leaf) */
+  int p2p_window_max;          /* entries of the largest such window (at most 320) */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

@@ -77,7 +77,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
-  dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_circ);
+  dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
@@ -172,6 +172,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "restart 1..200, max_iter >= 1, tol > 0"));
   if (opt->store_self_blocks != 0 && opt->store_self_blocks != 1)
     return bail(fail(pb, PFM_EINVAL, "store_self_blocks must be 0 or 1"));
+  if (opt->p2p_cached_rows != 0 && opt->p2p_cached_rows != 1)
+    return bail(fail(pb, PFM_EINVAL, "p2p_cached_rows must be 0 or 1"));
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -468,6 +470,52 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(&pb.d_ccols_ptr, qptr));
     CK(upload(&pb.d_ccol_psi, qpsi));
     CK(upload(&pb.d_ccol_loc, qloc));
+    // LDS windows of the circulant rows.  Target leaf li reads the entries
+    // (b - a) + N of its fibre's rows for its rows a and circulant columns b;
+    // counted from the start of the arc that holds them (after the largest
+    // gap on the circle), a' = a - rot and b' = b - rot (mod N) keep b - a
+    // mod N, and the entries N - a' + b' form one range of
+    // (a'_max - a'_min) + (b'_max - b'_min) + 1 entries.  Leaves whose range
+    // exceeds P2P_WCAP read the entries through the caches.
+    std::vector<int> cwin(3 * (size_t)std::max(1, nl), 0);
+    pb.p2p_wmax = 0;
+    pb.n_win_leaves = 0;
+    for (int li = 0; li < nl; ++li) {
+      if (qptr[li + 1] == qptr[li]) continue;
+      const Cell& L = hp.cells[hp.leaves[li]];
+      std::vector<int> u;
+      for (int t = L.ebeg; t < L.eend; ++t) u.push_back(hp.elem_of[t] % pb.N);
+      for (int q = qptr[li]; q < qptr[li + 1]; ++q) u.push_back(qloc[q]);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      int rot = u[0], gap = u[0] + pb.N - u.back();
+      for (size_t i = 1; i < u.size(); ++i)
+        if (u[i] - u[i - 1] > gap) {
+          gap = u[i] - u[i - 1];
+          rot = u[i];
+        }
+      auto place = [&](int x) { return x >= rot ? x - rot : x - rot + pb.N; };
+      int amin = pb.N, amax = -1, bmin = pb.N, bmax = -1;
+      for (int t = L.ebeg; t < L.eend; ++t) {
+        int a = place(hp.elem_of[t] % pb.N);
+        amin = std::min(amin, a);
+        amax = std::max(amax, a);
+      }
+      for (int q = qptr[li]; q < qptr[li + 1]; ++q) {
+        int b = place(qloc[q]);
+        bmin = std::min(bmin, b);
+        bmax = std::max(bmax, b);
+      }
+      const int elo = pb.N - amax + bmin, wl = (bmax - bmin) + (amax - amin) + 1;
+      cwin[3 * (size_t)li] = rot;
+      cwin[3 * (size_t)li + 1] = elo;
+      if (!pb.opt.p2p_cached_rows && wl <= P2P_WCAP) {
+        cwin[3 * (size_t)li + 2] = wl;
+        pb.p2p_wmax = std::max(pb.p2p_wmax, wl);
+        pb.n_win_leaves++;
+      }
+    }
+    CK(upload(&pb.d_cwin, cwin));
     // split the columns of each target leaf when there are too few leaves to
     // fill the P2P grid, keeping at least 32 columns per split on average
     const long long ncols = (long long)cpsi.size() + (long long)qpsi.size();
@@ -1509,6 +1557,8 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->n_near_computed = pb.n_near_uniq;
   st->n_near_stored = pb.n_near_stored;
   st->n_near_circulant = pb.n_near_circ;
+  st->p2p_window_leaves = pb.n_win_leaves;
+  st->p2p_window_max = pb.p2p_wmax;
   return PFM_OK;
 }
 

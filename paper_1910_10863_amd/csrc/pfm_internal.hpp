@@ -28,6 +28,10 @@ struct M2LEntry { int tgt, src, off, m; };
 
 // M2L entries are processed in chunks of at most this many entries of one (channel, cell)
 constexpr int M2L_CHUNK = 2;
+// largest LDS window of a fibre's circulant rows that P2P stages per target
+// leaf (entries; 4 components x 16 B each: 20 KB, so that four P2P
+// workgroups still fit on a CU)
+constexpr int P2P_WCAP = 320;
 struct NearEntry { int tgt_leaf, src, m; };
 
 struct HostPlan {
@@ -102,6 +106,8 @@ struct Problem {
   int *d_ccols_ptr = nullptr;           // per leaf: range of its circulant source columns
   int *d_ccol_psi = nullptr;            // circulant source columns: index of phi in Psi
   int *d_ccol_loc = nullptr;            // circulant source columns: element index on its circle
+  int *d_cwin = nullptr;                // per leaf: [rotation, first row entry, entries] of its LDS window
+  int p2p_wmax = 0, n_win_leaves = 0;   // largest window; leaves with a window
   cd *d_circ = nullptr;                 // [fibre][B11, B12, B21, B22][2N] circulant near rows
   // equal fibres: target leaves with the same near region (same place in
   // their fibres, same sources at the same offsets and images) read one

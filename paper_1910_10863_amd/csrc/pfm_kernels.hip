@@ -948,7 +948,8 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
                                               const double4* __restrict__ tgeo, const int* __restrict__ psi_idx,
                                               const cd* __restrict__ part, const cd* __restrict__ jtab, int n_joff,
                                               int N, double k, double k1, double eta, double varrho,
-                                              cd* __restrict__ far, long long part_stride, long long far_stride) {
+                                              cd* __restrict__ far, long long part_stride, long long far_stride,
+                                              int add_into) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64;
   __shared__ cd sJ[2][NT], sL[2][NP], sS[2][3][P + 2], sT[2][3][P + 2];
   __shared__ cd su[64], sd[64];
@@ -1073,8 +1074,15 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
   __syncthreads();
   if (ch == 0 && lane < rows) {
     cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
-    far[pi] = csub(u, su[lane]);
-    far[pi + N] = cmul(c, csub(dv, cscale(sd[lane], varrho)));
+    const cd f1 = csub(u, su[lane]), f2 = cmul(c, csub(dv, cscale(sd[lane], varrho)));
+    if (add_into) {
+      // far is the output y, which already holds psi + near (the join)
+      far[pi] = cadd(far[pi], f1);
+      far[pi + N] = cadd(far[pi + N], f2);
+    } else {
+      far[pi] = f1;
+      far[pi + N] = f2;
+    }
   }
 }
 
@@ -1143,11 +1151,13 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
     const int* __restrict__ psi_idx, int N, const long long* __restrict__ leaf_blk,
     const int* __restrict__ cols_ptr, const int* __restrict__ col_psi, const C* __restrict__ blocks,
     const int* __restrict__ ccols_ptr, const int* __restrict__ ccol_psi, const int* __restrict__ ccol_loc,
-    const cd* __restrict__ circ, const cd* __restrict__ psi, cd* __restrict__ y, int n_leaves, int S,
-    cd* __restrict__ part, long long vec) {
+    const cd* __restrict__ circ, const int* __restrict__ cwin, const cd* __restrict__ psi,
+    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part, long long vec) {
   // the blocks are stored as C (complex128, or complex64 for PFM_MIXED); the
   // densities and the sums stay FP64, so the complex64 form only rounds the
   // stored blocks (the stream is bandwidth-bound either way)
+  extern __shared__ cd swin[];                  // [B11, B12, B21, B22][P2P_WCAP] row window
+  constexpr int WS = P2P_WCAP;
   __shared__ cd sp[P2P_SEG][2];
   __shared__ int sl[P2P_SEG];
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
@@ -1211,24 +1221,73 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
       __syncthreads();
     }
     // circulant columns (same fibre, image 0): the block of target element a
-    // and source element b is entry (b - a) mod N of the fibre's row
+    // and source element b is entry (b - a) mod N of the fibre's row.  Places
+    // on the circle are counted from the leaf's rotation rot (a' = a - rot,
+    // b' = b - rot mod N), so that the entries N - a' + b' the leaf reads form
+    // one window [elo, elo + wl) of the doubled row; with wl > 0 it is staged
+    // in LDS once per leaf (a Toeplitz block needs rows + columns - 1 entries,
+    // not rows x columns loads), else the entries are read through the caches.
+    // Both read the same entries and sum in the same order.
     {
       const int q0 = ccols_ptr[li], nq = ccols_ptr[li + 1] - q0;
       const int qchunk = (nq + S - 1) / S;
       const int q_lo = min(nq, sp_i * qchunk), q_hi = min(nq, q_lo + qchunk);
+      const int rot = cwin[3 * li], elo = cwin[3 * li + 1], wl = cwin[3 * li + 2];
       const int pr = psi_idx[db + min(lane, rows - 1)];
       const int fD = pr / (2 * N), aloc = pr - 2 * fD * N;
-      const cd* crow = circ + (size_t)fD * 8 * N + (N - aloc);   // + b: entry (b - a) + N
+      const int ar = aloc >= rot ? aloc - rot : aloc - rot + N;
+      const cd* frow = circ + (size_t)fD * 8 * N;
+      const cd* crow = frow + (N - ar);                 // + b': entry (b' - a') + N
+      const int woff = N - ar - elo;                    // window slot of column b': woff + b'
+      if (wl > 0 && q_lo < q_hi) {
+        // visible after the barrier that follows the first column staging
+        for (int i = threadIdx.x; i < 4 * wl; i += 64 * P2P_WAVES) {
+          const int c = i / wl, j = i - c * wl;
+          swin[c * WS + j] = frow[(size_t)c * 2 * N + elo + j];
+        }
+      }
       for (int seg = q_lo; seg < q_hi; seg += P2P_SEG) {
         int nseg = min(P2P_SEG, q_hi - seg);
         for (int i = threadIdx.x; i < nseg; i += 64 * P2P_WAVES) {
           int pi = ccol_psi[q0 + seg + i];
           sp[i][0] = psi[pi];
           sp[i][1] = psi[pi + N];
-          sl[i] = ccol_loc[q0 + seg + i];
+          const int bl = ccol_loc[q0 + seg + i];
+          sl[i] = bl >= rot ? bl - rot : bl - rot + N;
         }
         __syncthreads();
-        if (act) {
+        if (act && wl > 0) {
+          // four columns per step, their row entries read from LDS
+          constexpr int CU = 4;
+          int k = w;
+          for (; k + (CU - 1) * P2P_WAVES < nseg; k += CU * P2P_WAVES) {
+            cd cc[CU][4];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+              const cd* x = swin + woff + sl[k + u * P2P_WAVES];
+              cc[u][0] = x[0];
+              cc[u][1] = x[WS];
+              cc[u][2] = x[2 * WS];
+              cc[u][3] = x[3 * WS];
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+              cd ph = sp[k + u * P2P_WAVES][0], vp = sp[k + u * P2P_WAVES][1];
+              a1 = cfma(cc[u][0], ph, a1);
+              a1 = cfma(cc[u][1], vp, a1);
+              a2 = cfma(cc[u][2], ph, a2);
+              a2 = cfma(cc[u][3], vp, a2);
+            }
+          }
+          for (; k < nseg; k += P2P_WAVES) {
+            const cd* x = swin + woff + sl[k];
+            cd ph = sp[k][0], vp = sp[k][1];
+            a1 = cfma(x[0], ph, a1);
+            a1 = cfma(x[WS], vp, a1);
+            a2 = cfma(x[2 * WS], ph, a2);
+            a2 = cfma(x[3 * WS], vp, a2);
+          }
+        } else if (act) {
           // four columns' row entries in flight per wavefront (cached loads)
           constexpr int CU = 4;
           int k = w;
@@ -1461,7 +1520,10 @@ static hipError_t tables_impl(Problem& pb) {
 // sums, downward pass (every ancestor to the leaves) with L2P into the
 // far-field buffer.
 template <int P>
-static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B) {
+// join != nullptr: the stream waits for it before the downward pass, which
+// then adds the far part into y_join (holding psi + near) instead of d_far.
+static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B,
+                      hipEvent_t join = nullptr, cd* y_join = nullptr) {
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
@@ -1486,10 +1548,11 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                        bs.epart, bs.part);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
+  if (join) (void)hipStreamWaitEvent(s, join, 0);
   hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, pb.d_ldesc,
                      reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
-                     pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_far,
-                     bs.part, bs.vec);
+                     pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
+                     join ? y_join : pb.d_far, bs.part, bs.vec, join ? 1 : 0);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 
@@ -1540,10 +1603,11 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
   if (B == 0) {
 #define PFM_P2P(U)                                                                                             \
-  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES), 0, ps, pb.d_leaves, pb.d_ebeg,       \
-                     pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks,     \
-                     pb.d_ccols_ptr, pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, n_leaves,             \
-                     pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
+  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES),                                      \
+                     pb.p2p_wmax ? 4 * P2P_WCAP * sizeof(cd) : 0, ps, pb.d_leaves, pb.d_ebeg, pb.d_eend,       \
+                     pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks, pb.d_ccols_ptr,    \
+                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, pb.d_cwin, d_psi, d_y, n_leaves, pb.p2p_split,   \
+                     pb.d_p2ppart, 2LL * pb.E)
     if (pb.p2p_unroll == 4) PFM_P2P(4);
     else if (pb.p2p_unroll == 2) PFM_P2P(2);
     else PFM_P2P(1);
@@ -1560,6 +1624,14 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
     launch_p2p_batch<C, 16>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
   }
   if (ev) (void)hipEventRecord(ev[5], pb.stream);
+  if (!ev && p2p_side && B == 0 && pb.p2p_split == 1) {
+    // P2P wrote y = psi + near on the side stream: the chain waits for it
+    // just before the downward pass, which adds the far part into y (P2P
+    // has long finished by then, and no join kernel follows)
+    (void)hipEventRecord(pb.ev_join, pb.side);
+    fmm_chain<P>(pb, d_psi, fs, nullptr, false, nb, pb.ev_join, d_y);
+    return hipGetLastError();
+  }
   if (!ev) {
     fmm_chain<P>(pb, d_psi, fs, nullptr, false, nb);
     (void)hipEventRecord(pb.ev_join, pb.side);

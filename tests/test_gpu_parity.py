@@ -156,6 +156,26 @@ def test_circulant_self_rows_equal_stored_blocks(pfm, key):
     assert np.max(np.abs(ys[0] - ys[1])) < 1e-12 * np.max(np.abs(ys[1]))
 
 
+@pytest.mark.parametrize("key,leaf", [("sq3x1", 16), ("sq2x2close", 16), ("hex2x2", 16), ("tiny", 32), ("tiny", 64)])
+def test_p2p_row_windows_equal_cached_rows(pfm, key, leaf):
+    """P2P reading each target leaf's window of the circulant rows from LDS
+    gives exactly the sums of reading every entry through the caches (the
+    same entries, FMAs and order); leaves whose window would exceed the LDS
+    cap take the cached path within the same launch."""
+    wl, ka, th = _WL[key]
+    psi = W.random_density(2 * wl.M * wl.n_elem, 23)
+    ys, st = [], []
+    for cached in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=leaf, p2p_cached_rows=cached)
+        prob.set_wave(ka, th)
+        ys.append(prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy())
+        st.append(prob.stats())
+    _say("row windows:", key, leaf, st[0]["n_leaves"], st[0]["p2p_window_leaves"], st[0]["p2p_window_max"])
+    assert st[0]["p2p_window_leaves"] > 0 and 0 < st[0]["p2p_window_max"] <= 320
+    assert st[1]["p2p_window_leaves"] == 0 and st[1]["p2p_window_max"] == 0
+    assert np.array_equal(ys[0], ys[1])
+
+
 def test_matvec_error_decreases_with_p(pfm):
     errs = [(_matvec_err(pfm, "sq2x2", p, 16)[0]) for p in (8, 16, 24, 32)]
     _say("matvec error vs p:", errs)
