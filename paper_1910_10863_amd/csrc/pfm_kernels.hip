@@ -951,7 +951,7 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
                                               cd* __restrict__ far, long long part_stride, long long far_stride,
                                               int add_into) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64;
-  __shared__ cd sJ[2][NT], sL[2][NP], sS[2][3][P + 2], sT[2][3][P + 2];
+  __shared__ cd sJ[2][NT], sA[2][NP], sL[2][NP], sS[2][3][P + 2], sT[2][3][P + 2];
   __shared__ cd su[64], sd[64];
   part += blockIdx.y * part_stride;             // batch member
   far += blockIdx.y * far_stride;
@@ -987,9 +987,9 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
   };
   if (na > 0) fetch(0);
   for (int q = 0; q < na; ++q) {                // wave-uniform trip count
-    cd areg[NU];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) areg[u] = anext[u];
+    for (int u = 0; u < NU; ++u)
+      if (lane + 64 * u < NP) sA[ch][lane + 64 * u] = anext[u];
 #pragma unroll
     for (int u = 0; u < NTU; ++u)
       if (lane + 64 * u < NT) sJ[ch][lane + 64 * u] = tnext[u];
@@ -1003,12 +1003,7 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
     for (int u = 0; u < NU; ++u) {
       int n = min(lane + 64 * u - P, P);      // lanes past the last order repeat it
       cd sres = acc[u];
-#pragma unroll
-      for (int sl = 0; sl < NU; ++sl) {
-        const int hi = NP < 64 * sl + 64 ? NP : 64 * sl + 64;
-        for (int idx = 64 * sl; idx < hi; ++idx)
-          sres = cfma(lane_cd(areg[sl], idx - 64 * sl), sJ[ch][idx - n + P], sres);
-      }
+      for (int idx = 0; idx < NP; ++idx) sres = cfma(sA[ch][idx], sJ[ch][idx - n + P], sres);
       acc[u] = sres;
     }
     __builtin_amdgcn_wave_barrier();
