@@ -123,15 +123,44 @@ def test_apply_is_deterministic(pfm):
     assert torch.equal(a, b)
 
 
-def test_timed_apply_matches_overlapped_apply(pfm):
-    wl = W.square_4x4_sweep()
-    prob = pfm.Problem.from_workload(wl)
+@pytest.mark.parametrize("key,bpc", [("square_4x4", 0), ("square_8x8", 0), ("square_8x8", 3), ("hexagon_16x16", 0)])
+def test_timed_apply_matches_overlapped_apply(pfm, key, bpc):
+    """The overlapped apply (P2P on the side stream; with one column split
+    per leaf the downward pass adds the far part into y after waiting for
+    P2P, else a join kernel adds it) equals the in-order timed apply bit
+    for bit."""
+    wl = {"square_4x4": W.square_4x4_sweep, "square_8x8": W.square_8x8, "hexagon_16x16": W.hexagon_16x16}[key]()
+    prob = pfm.Problem.from_workload(wl, p2p_blocks_per_cu=bpc)
     prob.set_wave(2.0, 0.1)
+    st = prob.stats()
+    _say("overlapped vs in-order:", key, bpc, "split", st["p2p_split"], "circulant", st["n_near_circulant"],
+         "stored", st["n_near_stored"])
+    if key == "hexagon_16x16" or bpc == 3:
+        # one split per leaf and mostly circulant pairs: the fused join runs
+        assert st["p2p_split"] == 1 and st["n_near_circulant"] > st["n_near_stored"]
     psi = torch.tensor(W.random_density(prob.n, 10), device="cuda")
     a = prob.matvec(psi).clone()
     stages, tot, b = prob.matvec_timed(psi, reps=2)
-    assert torch.equal(a, b)
+    c = prob.matvec(psi).clone()
+    assert torch.equal(a, b) and torch.equal(a, c)
     assert all(v >= 0 for v in stages.values()) and tot > 0
+
+
+def test_row_windows_equal_cached_rows_square_8x8(pfm):
+    """At the benchmark configuration the P2P row windows in LDS give the
+    cache path's sums bit for bit."""
+    wl = W.square_8x8()
+    psi = torch.tensor(W.random_density(2 * wl.M * wl.n_elem, 12), device="cuda")
+    ys, st = [], []
+    for cached in (False, True):
+        prob = pfm.Problem.from_workload(wl, p2p_cached_rows=cached)
+        prob.set_wave(3.338709677419355, 0.0)
+        ys.append(prob.matvec(psi).clone())
+        st.append(prob.stats())
+        prob.close()
+    _say("square 8x8 windows:", st[0]["p2p_window_leaves"], "of", st[0]["n_leaves"], "max", st[0]["p2p_window_max"])
+    assert st[0]["p2p_window_leaves"] > st[0]["n_leaves"] // 2 and st[1]["p2p_window_leaves"] == 0
+    assert torch.equal(ys[0], ys[1])
 
 
 def test_gmres_noconv_and_wood_errors(pfm):
