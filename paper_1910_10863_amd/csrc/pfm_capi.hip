@@ -579,18 +579,22 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     // M2L work: per (channel, cell) the entries (source cell, table row, image),
     // contiguous, cut into chunks of at most M2L_CHUNK entries (one wavefront
     // each); one sum per (channel, cell) with entries adds its chunks' partial
-    // expansions in order, so the downward pass reads one sum per cell.
+    // expansions in order, so the downward pass reads one sum per cell.  A
+    // root's M lattice entries go in chunks of M2L_LAT_CHUNK once M >= 128,
+    // where 2-entry chunks would write M / 2 partial expansions per root.
     std::vector<int> esrc, eoff, em, mchunks, sums, ccptr(2 * (size_t)nc + 1, 0);
     std::vector<int> fibre_of_root(nc, -1);
     for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;
     for (int ch = 0; ch < 2; ++ch) {
       for (int c = 0; c < nc; ++c) {
         int first = (int)esrc.size();
+        bool lattice_root = false;
         if (ch == 0) {
           for (int q = hp.m2l_ptr[c]; q < hp.m2l_ptr[c + 1]; ++q) {
             esrc.push_back(hp.m2l_src[q]); eoff.push_back(hp.m2l_off[q]); em.push_back(hp.m2l_m[q]);
           }
           int fi = fibre_of_root[c];
+          lattice_root = fi >= 0;
           if (fi >= 0)
             for (int j = 0; j < pb.M; ++j) {
               esrc.push_back(hp.root_of_fibre[j]);
@@ -604,9 +608,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         }
         int last = (int)esrc.size();
         int chunk0 = (int)(mchunks.size() / 4);
-        for (int b = first; b < last; b += M2L_CHUNK) {
+        const int csz = lattice_root && pb.M >= 128 ? M2L_LAT_CHUNK : M2L_CHUNK;
+        for (int b = first; b < last; b += csz) {
           mchunks.push_back(c); mchunks.push_back(ch); mchunks.push_back(b);
-          mchunks.push_back(std::min(M2L_CHUNK, last - b));
+          mchunks.push_back(std::min(csz, last - b));
         }
         int chunk1 = (int)(mchunks.size() / 4);
         if (chunk1 > chunk0) {

@@ -28,6 +28,7 @@ struct M2LEntry { int tgt, src, off, m; };
 
 // M2L entries are processed in chunks of at most this many entries of one (channel, cell)
 constexpr int M2L_CHUNK = 2;
+constexpr int M2L_LAT_CHUNK = 8;     // lattice entries of a root, for M >= 128 fibres
 // largest LDS window of a fibre's circulant rows that P2P stages per target
 // leaf (entries; 4 components x 16 B each: 20 KB, so that four P2P
 // workgroups still fit on a CU)
