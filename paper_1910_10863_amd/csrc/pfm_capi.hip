@@ -687,8 +687,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMalloc((void**)&pb.d_ir_aug, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_cperp, MB * n * sizeof(cd)));
   CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
-  pb.red_blocks = (int)std::min<size_t>(256, (n + 511) / 512);
-  CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 255) / 256) * sizeof(double)));
+  pb.red_blocks = (int)std::min<size_t>(512, (n + 255) / 256);
+  CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 63) / 64) * sizeof(double)));
   CK(hipMalloc((void**)&pb.d_dcoef, MB * (2 * (size_t)pb.opt.restart + 4) * sizeof(cd)));
   // restart + 1 columns: DCGS2 leaves the last reorthogonalisation of a cycle in column restart
   CK(hipMalloc((void**)&pb.d_hall, ((size_t)pb.opt.restart + 1) * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));

@@ -342,6 +342,12 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 constexpr int LAT_MAX_NT = 4 * 40 + 1;
 
 __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const double* __restrict__ roff,
@@ -1681,7 +1687,7 @@ hipError_t apply_operator_batch(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_
 // ===========================================================================
 constexpr int RED_THREADS = 256;
 
-constexpr int DOT_PER_LANE = 8;                 // w elements a lane keeps in registers
+constexpr int DOT_PER_LANE = 4;                 // w elements a lane keeps in registers
 constexpr int DOT_CHUNK = 64 * DOT_PER_LANE;      // elements of one block's chunk
 
 constexpr int DOT_VPW = 2;                      // vectors a wave reduces at once
@@ -2036,49 +2042,49 @@ __global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, 
 }
 
 // v_j = u_j / gamma - V_{j-1} (a / gamma) into slot j; w = w / gamma - V_{j-1} (b / gamma)
-// - (s / gamma) v_j, and the partial squared norms of w.
+// - (s / gamma) v_j, and the partial squared norms of w.  A workgroup covers
+// 64 elements; its four wavefronts take the basis vectors i = wv, wv + 4, ...
+// (four times the loads in flight of one wavefront per element block), and
+// their partial sums are added in wavefront order.
+constexpr int UPD_ELEMS = 64;
 __global__ void __launch_bounds__(256) k_dcgs_update(cd* V, long long ldv, long long vsb, int j, cd* w,
                                                      long long wsb, const cd* __restrict__ coef, long long csb,
                                                      int n, double* npart) {
-  __shared__ cd sv[256], sw[256];
-  __shared__ double sn[256];
+  __shared__ cd pv[4][UPD_ELEMS], pw[4][UPD_ELEMS];
   const int b = blockIdx.y;
   V += b * vsb;
   w += b * wsb;
   coef += b * csb;
-  const double ig = coef[2 * j + 1].x;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  cd vj = t < n ? cscale(V[(size_t)j * ldv + t], ig) : mkc(0, 0);
-  cd wa = t < n ? cscale(w[t], ig) : mkc(0, 0);
-  for (int i0 = 0; i0 < j; i0 += 256) {
-    const int c = min(256, j - i0);
-    if ((int)threadIdx.x < c) {
-      sv[threadIdx.x] = coef[i0 + threadIdx.x];
-      sw[threadIdx.x] = coef[j + i0 + threadIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = blockIdx.x * UPD_ELEMS + lane;
+  const bool in = t < n;
+  cd dv = mkc(0, 0), dw = mkc(0, 0);
+  if (in) {
+    const cd* vp = V + t;
+#pragma unroll 4
+    for (int i = wv; i < j; i += 4) {
+      const cd vi = vp[(size_t)i * ldv];
+      dv = cfma(coef[i], vi, dv);
+      dw = cfma(coef[j + i], vi, dw);
     }
-    __syncthreads();
-    if (t < n) {
-#pragma unroll 8
-      for (int i = 0; i < c; ++i) {
-        const cd vi = V[(size_t)(i0 + i) * ldv + t];
-        vj = csub(vj, cmul(sv[i], vi));
-        wa = csub(wa, cmul(sw[i], vi));
-      }
-    }
-    __syncthreads();
   }
-  wa = csub(wa, cmul(coef[2 * j], vj));
-  if (t < n) {
+  pv[wv][lane] = dv;
+  pw[wv][lane] = dw;
+  __syncthreads();
+  if (wv != 0) return;
+  const double ig = coef[2 * j + 1].x;
+  const cd sv = cadd(cadd(pv[0][lane], pv[1][lane]), cadd(pv[2][lane], pv[3][lane]));
+  const cd sw = cadd(cadd(pw[0][lane], pw[1][lane]), cadd(pw[2][lane], pw[3][lane]));
+  double q = 0.0;
+  if (in) {
+    const cd vj = csub(cscale(V[(size_t)j * ldv + t], ig), sv);
+    const cd wa = csub(csub(cscale(w[t], ig), sw), cmul(coef[2 * j], vj));
     V[(size_t)j * ldv + t] = vj;
     w[t] = wa;
+    q = cabs2(wa);
   }
-  sn[threadIdx.x] = t < n ? cabs2(wa) : 0.0;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) sn[threadIdx.x] += sn[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) npart[(size_t)b * gridDim.x + blockIdx.x] = sn[0];
+  q = wave_sum_d(q);
+  if (lane == 0) npart[(size_t)b * gridDim.x + blockIdx.x] = q;
 }
 
 hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long vsb, int j, cd* W, long long wsb,
@@ -2095,9 +2101,10 @@ hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long 
                      2LL * cnt);
   hipLaunchKernelGGL(k_dcgs_coeff, dim3(B), dim3(256), 0, pb.stream, fin, j, 2, pb.d_hall + (size_t)j * hcs, hsb,
                      pb.d_dcoef, csb);
-  hipLaunchKernelGGL(k_dcgs_update, dim3(nu, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, pb.d_dcoef, csb, n,
-                     pb.d_npart);
-  hipLaunchKernelGGL(k_normalize_fused, dim3(nu, B), dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nu,
+  const int nup = (n + UPD_ELEMS - 1) / UPD_ELEMS;
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nup, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, pb.d_dcoef, csb,
+                     n, pb.d_npart);
+  hipLaunchKernelGGL(k_normalize_fused, dim3(nu, B), dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nup,
                      pb.d_hall + (size_t)j * hcs + 2 * cnt, hsb, n);
   return hipGetLastError();
 }
