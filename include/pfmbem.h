@@ -117,7 +117,13 @@ typedef struct {
  *  p2p_cached_rows  0: for each target leaf, P2P copies the window of its
  *             fibre's circulant rows that the leaf reads (at most 320 entries)
  *             into LDS once; 1: every row entry is read through the caches.
- *             Both give the same sums in the same order. */
+ *             Both give the same sums in the same order.
+ *  direct_lattice_m2l  0: from 128 fibres up, the root lattice M2L (Sec. 3.3)
+ *             runs as a convolution over the fibre grid (a root pair's lattice
+ *             sum depends only on the grid displacement and, on the hexagonal
+ *             lattice, on the parities of the two columns), by zero-padded 2D
+ *             DFTs: (2 M_L)(2 M_H) Toeplitz products per sublattice pair
+ *             instead of M^2; 1: every root pair is an M2L entry. */
 typedef struct {
   int p;
   int leaf_max;
@@ -135,6 +141,7 @@ typedef struct {
   int p2p_unroll;
   int store_self_blocks;
   int p2p_cached_rows;
+  int direct_lattice_m2l;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -172,6 +179,7 @@ typedef struct {
   int p2p_window_leaves;       /* target leaves whose circulant row entries P2P stages in LDS
                                   (one window of consecutive entries per leaf) */
   int p2p_window_max;          /* entries of the largest such window (at most 320) */
+  int lattice_m2l_grid;        /* 1: the root lattice M2L runs as a convolution over the fibre grid */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction

@@ -78,6 +78,8 @@ void free_all(Problem& pb) {
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
   dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
+  dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
+  dfree(pb.d_lat_lhat);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
@@ -174,6 +176,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "store_self_blocks must be 0 or 1"));
   if (opt->p2p_cached_rows != 0 && opt->p2p_cached_rows != 1)
     return bail(fail(pb, PFM_EINVAL, "p2p_cached_rows must be 0 or 1"));
+  if (opt->direct_lattice_m2l != 0 && opt->direct_lattice_m2l != 1)
+    return bail(fail(pb, PFM_EINVAL, "direct_lattice_m2l must be 0 or 1"));
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -585,6 +589,29 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     std::vector<int> esrc, eoff, em, mchunks, sums, ccptr(2 * (size_t)nc + 1, 0);
     std::vector<int> fibre_of_root(nc, -1);
     for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;
+    // Fibre grid of the lattice M2L convolution.  Fibre f = j M_L + i sits in
+    // column i, row j; on the hexagonal lattice odd columns are half a
+    // spacing higher, so the column parity is a sublattice and gx = i / 2.
+    // Every root pair's lattice row must depend only on (sublattices, grid
+    // displacement); that is checked here, else the pairs stay M2L entries.
+    const bool hexl = pb.lattice == PFM_HEXAGON;
+    const int lns = hexl ? 2 : 1, lgx = hexl ? (pb.ML + 1) / 2 : pb.ML, lgy = pb.MH;
+    const int lpx = 2 * lgx, lpy = 2 * lgy;
+    auto lsub = [&](int f) { return hexl ? (f % pb.ML) & 1 : 0; };
+    auto lgxf = [&](int f) { return hexl ? (f % pb.ML) >> 1 : f % pb.ML; };
+    auto lgyf = [&](int f) { return f / pb.ML; };
+    std::vector<int> lkey((size_t)lns * lns * (2 * lgy - 1) * (2 * lgx - 1), -1);
+    pb.lat_fft = pb.M >= 128 && !pb.opt.direct_lattice_m2l && lpx <= 64 && lpy <= 64 && lpx * lpy <= LAT_PXY_MAX;
+    for (int i = 0; pb.lat_fft && i < pb.M; ++i)
+      for (int j = 0; j < pb.M; ++j) {
+        const size_t kk = (((size_t)lsub(i) * lns + lsub(j)) * (2 * lgy - 1) + (lgyf(i) - lgyf(j) + lgy - 1)) *
+                              (2 * lgx - 1) + (lgxf(i) - lgxf(j) + lgx - 1);
+        const int id = hp.root_pair_off[(size_t)i * pb.M + j];
+        if (lkey[kk] < 0) lkey[kk] = id;
+        else if (lkey[kk] != id) pb.lat_fft = false;
+      }
+    std::vector<int> lcell((size_t)lns * lgy * lgx, -1), lslot((size_t)lns * lgy * lgx, -1);
+    for (int f = 0; f < pb.M; ++f) lcell[((size_t)lsub(f) * lgy + lgyf(f)) * lgx + lgxf(f)] = hp.root_of_fibre[f];
     for (int ch = 0; ch < 2; ++ch) {
       for (int c = 0; c < nc; ++c) {
         int first = (int)esrc.size();
@@ -595,7 +622,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
           }
           int fi = fibre_of_root[c];
           lattice_root = fi >= 0;
-          if (fi >= 0)
+          if (fi >= 0 && !pb.lat_fft)
             for (int j = 0; j < pb.M; ++j) {
               esrc.push_back(hp.root_of_fibre[j]);
               eoff.push_back(n_off_real + hp.root_pair_off[(size_t)fi * pb.M + j]);
@@ -612,6 +639,14 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         for (int b = first; b < last; b += csz) {
           mchunks.push_back(c); mchunks.push_back(ch); mchunks.push_back(b);
           mchunks.push_back(std::min(csz, last - b));
+        }
+        if (ch == 0 && lattice_root && pb.lat_fft) {
+          // the root's lattice M2L arrives from the grid convolution as one more
+          // partial expansion, after its explicit entries (an empty chunk that
+          // k_m2l leaves alone)
+          const int f = fibre_of_root[c];
+          lslot[((size_t)lsub(f) * lgy + lgyf(f)) * lgx + lgxf(f)] = (int)(mchunks.size() / 4);
+          mchunks.push_back(c); mchunks.push_back(ch); mchunks.push_back(last); mchunks.push_back(0);
         }
         int chunk1 = (int)(mchunks.size() / 4);
         if (chunk1 > chunk0) {
@@ -663,6 +698,14 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(&pb.d_ldesc, ldesc)); CK(upload(&pb.d_lanc, lanc)); CK(upload(&pb.d_tgeo, tgeo));
     CK(hipMalloc((void**)&pb.d_part, MB * std::max(1, pb.n_chunks) * NP * sizeof(cd)));
     CK(hipMalloc((void**)&pb.d_epart, MB * std::max(1, pb.n_mchunks) * NP * sizeof(cd)));
+    if (pb.lat_fft) {
+      pb.lat_ns = lns; pb.lat_gx = lgx; pb.lat_gy = lgy; pb.lat_px = lpx; pb.lat_py = lpy;
+      const size_t pxy = (size_t)lpx * lpy;
+      CK(upload(&pb.d_lat_cell, lcell)); CK(upload(&pb.d_lat_slot, lslot)); CK(upload(&pb.d_lat_key, lkey));
+      CK(hipMalloc((void**)&pb.d_lat_shat, MB * lns * lns * pxy * NT * sizeof(cd)));
+      CK(hipMalloc((void**)&pb.d_lat_xhat, MB * lns * pxy * NP * sizeof(cd)));
+      CK(hipMalloc((void**)&pb.d_lat_lhat, MB * lns * pxy * NP * sizeof(cd)));
+    }
   }
   {
     CK(upload(&pb.d_up_cells, hp.up_cells)); CK(upload(&pb.d_up_ptr, hp.up_ptr));
@@ -1564,6 +1607,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->n_near_circulant = pb.n_near_circ;
   st->p2p_window_leaves = pb.n_win_leaves;
   st->p2p_window_max = pb.p2p_wmax;
+  st->lattice_m2l_grid = pb.lat_fft ? 1 : 0;
   return PFM_OK;
 }
 

@@ -29,6 +29,9 @@ struct M2LEntry { int tgt, src, off, m; };
 // M2L entries are processed in chunks of at most this many entries of one (channel, cell)
 constexpr int M2L_CHUNK = 2;
 constexpr int M2L_LAT_CHUNK = 8;     // lattice entries of a root, for M >= 128 fibres
+// largest padded fibre grid of the lattice M2L convolution (LDS per DFT;
+// each axis at most 64 points)
+constexpr int LAT_PXY_MAX = 1024;
 // largest LDS window of a fibre's circulant rows that P2P stages per target
 // leaf (entries; 4 components x 16 B each: 20 KB, so that four P2P
 // workgroups still fit on a CU)
@@ -108,6 +111,18 @@ struct Problem {
   int *d_ccol_psi = nullptr;            // circulant source columns: index of phi in Psi
   int *d_ccol_loc = nullptr;            // circulant source columns: element index on its circle
   int *d_cwin = nullptr;                // per leaf: [rotation, first row entry, entries] of its LDS window
+  // root lattice M2L as a convolution over the fibre grid: fibre f sits at
+  // (sublattice, gx, gy); a root pair's lattice row depends only on the two
+  // sublattices and the grid displacement; DFTs over the zero-padded
+  // lat_px x lat_py grid
+  bool lat_fft = false;
+  int lat_ns = 1, lat_gx = 1, lat_gy = 1, lat_px = 2, lat_py = 2;
+  int* d_lat_cell = nullptr;            // [ns][gy][gx]: root cell at the grid point (-1: none)
+  int* d_lat_slot = nullptr;            // [ns][gy][gx]: M2L partial slot of that root (-1: none)
+  int* d_lat_key = nullptr;             // [ns][ns][2gy-1][2gx-1]: lattice row of the displacement (-1: none)
+  cd* d_lat_shat = nullptr;             // [member][ns][ns][px py][4p+1]: DFT of the rows over the grid
+  cd* d_lat_xhat = nullptr;             // [member][ns][px py][2p+1]: DFT of the root multipoles
+  cd* d_lat_lhat = nullptr;             // [member][ns][px py][2p+1]: their product, before the inverse DFT
   int p2p_wmax = 0, n_win_leaves = 0;   // largest window; leaves with a window
   cd *d_circ = nullptr;                 // [fibre][B11, B12, B21, B22][2N] circulant near rows
   // equal fibres: target leaves with the same near region (same place in

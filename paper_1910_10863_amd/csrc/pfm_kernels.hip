@@ -470,6 +470,152 @@ __global__ void k_lattice_direct(int P, int n_roff, const double* __restrict__ r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Root lattice M2L (Sec. 3.3) as a convolution over the fibre grid.  With
+// fibre f at (sublattice s, gx, gy) and the lattice row of a root pair
+// depending only on (s_t, s_s, dgx, dgy), the M2L of every root,
+//   L_l(t) = sum_s sum_n S_{n-l}(o_ts) M_n(s),
+// is for each (l, n) a 2D linear convolution over the grid, done as a product
+// of zero-padded DFTs on the px x py grid (px = 2 gx, py = 2 gy):
+//   Shat_nu(xi) = DFT of S_nu over the displacements (once per frequency),
+//   Xhat_n(xi) = DFT of M_n over the grid, Lhat_l(xi) = sum_n Shat_{n-l} Xhat_n,
+// and L_l = inverse DFT of Lhat_l at the grid points.  The DFTs are direct sums
+// over each grid axis (at most 64 points) with tabulated roots of unity.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cd unit_root(int k, int n, double sign) {
+  double s, c;
+  sincospi(sign * 2.0 * (double)k / (double)n, &s, &c);
+  return mkc(c, s);
+}
+
+// One block per (order nu, sublattice pair, member): the rows over the
+// padded grid (K[y][x] at x = dgx mod px, y = dgy mod py), then DFT along x
+// and along y into shat[member][pair][xi][nu].
+__global__ void __launch_bounds__(256) k_lat_shat(const cd* __restrict__ lat, long long lat_stride,
+                                                  const int* __restrict__ key, int ns, int gx, int gy, int px,
+                                                  int py, int NT, cd* __restrict__ shat) {
+  __shared__ cd sk[LAT_PXY_MAX], tmp[LAT_PXY_MAX], wx[64], wy[64];
+  const int nu = blockIdx.x, pair = blockIdx.y, st = pair / ns, ss = pair - st * ns;
+  const int pxy = px * py;
+  lat += blockIdx.z * lat_stride;
+  shat += ((size_t)blockIdx.z * ns * ns + pair) * pxy * NT;
+  for (int i = threadIdx.x; i < px; i += 256) wx[i] = unit_root(i, px, -1.0);
+  for (int i = threadIdx.x; i < py; i += 256) wy[i] = unit_root(i, py, -1.0);
+  for (int idx = threadIdx.x; idx < pxy; idx += 256) {
+    const int x = idx % px, y = idx / px;
+    const int dx = x < gx ? x : x - px, dy = y < gy ? y : y - py;
+    cd v = mkc(0, 0);
+    if (dx > -gx && dy > -gy) {
+      const int r = key[(((size_t)st * ns + ss) * (2 * gy - 1) + dy + gy - 1) * (2 * gx - 1) + dx + gx - 1];
+      if (r >= 0) v = lat[(size_t)r * NT + nu];
+    }
+    sk[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < pxy; idx += 256) {
+    const int fx = idx % px, y = idx / px;
+    cd s = mkc(0, 0);
+    for (int x = 0; x < px; ++x) s = cfma(sk[y * px + x], wx[(fx * x) % px], s);
+    tmp[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < pxy; idx += 256) {
+    const int fx = idx % px, fy = idx / px;
+    cd s = mkc(0, 0);
+    for (int y = 0; y < py; ++y) s = cfma(tmp[y * px + fx], wy[(fy * y) % py], s);
+    shat[(size_t)idx * NT + nu] = s;
+  }
+}
+
+// One block per (order n, sublattice, member): the roots' exterior multipoles
+// on the grid, DFT along x and y into xhat[member][s][xi][n].
+template <int P>
+__global__ void __launch_bounds__(256) k_lat_fwd(const cd* __restrict__ mpole, long long mp_stride,
+                                                 const int* __restrict__ cell, int ns, int gx, int gy, int px,
+                                                 int py, cd* __restrict__ xhat) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd sk[LAT_PXY_MAX], tmp[LAT_PXY_MAX], wx[64], wy[64];
+  const int n = blockIdx.x, s = blockIdx.y, pxy = px * py;
+  mpole += blockIdx.z * mp_stride;
+  xhat += ((size_t)blockIdx.z * ns + s) * pxy * NP;
+  for (int i = threadIdx.x; i < px; i += 256) wx[i] = unit_root(i, px, -1.0);
+  for (int i = threadIdx.x; i < py; i += 256) wy[i] = unit_root(i, py, -1.0);
+  for (int idx = threadIdx.x; idx < gx * gy; idx += 256) {
+    const int c = cell[(size_t)s * gx * gy + idx];
+    sk[idx] = c >= 0 ? mpole[((size_t)c * 2) * NP + n] : mkc(0, 0);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < gy * px; idx += 256) {
+    const int fx = idx % px, y = idx / px;
+    cd a = mkc(0, 0);
+    for (int x = 0; x < gx; ++x) a = cfma(sk[y * gx + x], wx[(fx * x) % px], a);
+    tmp[idx] = a;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < pxy; idx += 256) {
+    const int fx = idx % px, fy = idx / px;
+    cd a = mkc(0, 0);
+    for (int y = 0; y < gy; ++y) a = cfma(tmp[y * px + fx], wy[(fy * y) % py], a);
+    xhat[(size_t)idx * NP + n] = a;
+  }
+}
+
+// One wavefront per (grid frequency, target sublattice, member), lane = order
+// l: Lhat_l = sum over source sublattices and n of Shat_{n-l} Xhat_n.
+template <int P>
+__global__ void __launch_bounds__(64) k_lat_mul(const cd* __restrict__ shat, const cd* __restrict__ xhat, int ns,
+                                                int pxy, cd* __restrict__ lhat) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
+  __shared__ cd sS[2][NT], sX[2][NP];
+  const int xi = blockIdx.x, st = blockIdx.y, b = blockIdx.z, lane = threadIdx.x;
+  for (int ss = 0; ss < ns; ++ss) {
+    const cd* sr = shat + ((((size_t)b * ns + st) * ns + ss) * pxy + xi) * NT;
+    const cd* xr = xhat + (((size_t)b * ns + ss) * pxy + xi) * NP;
+    for (int i = lane; i < NT; i += 64) sS[ss][i] = sr[i];
+    for (int i = lane; i < NP; i += 64) sX[ss][i] = xr[i];
+  }
+  __syncthreads();
+  cd* out = lhat + (((size_t)b * ns + st) * pxy + xi) * NP;
+  for (int l = lane; l < NP; l += 64) {
+    cd a = mkc(0, 0);
+    for (int ss = 0; ss < ns; ++ss)
+      for (int n = 0; n < NP; ++n) a = cfma(sS[ss][n - l + 2 * P], sX[ss][n], a);
+    out[l] = a;
+  }
+}
+
+// One block per (order l, sublattice, member): inverse DFT along y and x at
+// the grid points, scaled by 1 / (px py), into the roots' M2L partial slots.
+template <int P>
+__global__ void __launch_bounds__(256) k_lat_inv(const cd* __restrict__ lhat, const int* __restrict__ slot, int ns,
+                                                 int gx, int gy, int px, int py, cd* __restrict__ epart,
+                                                 long long ep_stride) {
+  constexpr int NP = 2 * P + 1;
+  __shared__ cd sk[LAT_PXY_MAX], tmp[LAT_PXY_MAX], wx[64], wy[64];
+  const int l = blockIdx.x, s = blockIdx.y, pxy = px * py;
+  lhat += ((size_t)blockIdx.z * ns + s) * pxy * NP;
+  epart += blockIdx.z * ep_stride;
+  for (int i = threadIdx.x; i < px; i += 256) wx[i] = unit_root(i, px, 1.0);
+  for (int i = threadIdx.x; i < py; i += 256) wy[i] = unit_root(i, py, 1.0);
+  for (int idx = threadIdx.x; idx < pxy; idx += 256) sk[idx] = lhat[(size_t)idx * NP + l];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < gy * px; idx += 256) {
+    const int fx = idx % px, y = idx / px;
+    cd a = mkc(0, 0);
+    for (int fy = 0; fy < py; ++fy) a = cfma(sk[fy * px + fx], wy[(fy * y) % py], a);
+    tmp[idx] = a;
+  }
+  __syncthreads();
+  const double sc = 1.0 / (double)pxy;
+  for (int idx = threadIdx.x; idx < gx * gy; idx += 256) {
+    const int x = idx % gx, y = idx / gx;
+    cd a = mkc(0, 0);
+    for (int fx = 0; fx < px; ++fx) a = cfma(tmp[y * px + fx], wx[(fx * x) % px], a);
+    const int sl = slot[(size_t)s * gx * gy + idx];
+    if (sl >= 0) epart[(size_t)sl * NP + l] = cscale(a, sc);
+  }
+}
+
 hipError_t launch_lattice_sums(Problem& pb, int B) {
   int n_roff = (int)pb.hp.root_off_xy.size() / 2;
   if (n_roff == 0) return hipSuccess;
@@ -481,6 +627,10 @@ hipError_t launch_lattice_sums(Problem& pb, int B) {
   hipLaunchKernelGGL(k_lattice_direct, dim3(n_roff, B), dim3(128), 0, pb.stream, pb.opt.p, n_roff,
                      pb.d_root_off_xy, pb.d_root_mrange, pb.k, pb.H, pb.d_betas, pb.lattice_q, n_rblk,
                      pb.d_latpart, pb.d_lat, 2LL * pb.n_tab * NT);
+  if (pb.lat_fft)
+    hipLaunchKernelGGL(k_lat_shat, dim3(NT, pb.lat_ns * pb.lat_ns, B), dim3(256), 0, pb.stream, pb.d_lat,
+                       2LL * pb.n_tab * NT, pb.d_lat_key, pb.lat_ns, pb.lat_gx, pb.lat_gy, pb.lat_px, pb.lat_py, NT,
+                       pb.d_lat_shat);
   return hipGetLastError();
 }
 
@@ -858,6 +1008,7 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   alpha += blockIdx.y * alpha_stride;
   int c = blockIdx.x;
   int ch = chunks[4 * c + 1], b = chunks[4 * c + 2], e = b + chunks[4 * c + 3];
+  if (e == b) return;                           // a root's slot for the lattice convolution
   constexpr int NU = (NP + 63) / 64;
   const int lane = threadIdx.x;
   cd acc[NU];
@@ -1545,6 +1696,16 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
     hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_mchunks, B), dim3(64), 0, s, pb.d_mchunks, pb.d_e_src, pb.d_e_off,
                        pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
                        bs.epart, bs.tab, bs.alpha);
+    if (pb.lat_fft) {
+      const int ns = pb.lat_ns, pxy = pb.lat_px * pb.lat_py;
+      constexpr int NP = 2 * P + 1;
+      hipLaunchKernelGGL(k_lat_fwd<P>, dim3(NP, ns, B), dim3(256), 0, s, pb.d_mpole, bs.mpole, pb.d_lat_cell, ns,
+                         pb.lat_gx, pb.lat_gy, pb.lat_px, pb.lat_py, pb.d_lat_xhat);
+      hipLaunchKernelGGL(k_lat_mul<P>, dim3(pxy, ns, B), dim3(64), 0, s, pb.d_lat_shat, pb.d_lat_xhat, ns, pxy,
+                         pb.d_lat_lhat);
+      hipLaunchKernelGGL(k_lat_inv<P>, dim3(NP, ns, B), dim3(256), 0, s, pb.d_lat_lhat, pb.d_lat_slot, ns,
+                         pb.lat_gx, pb.lat_gy, pb.lat_px, pb.lat_py, pb.d_epart, bs.epart);
+    }
     hipLaunchKernelGGL(k_m2l_sum<P>, dim3(pb.n_chunks, B), dim3(256), 0, s, pb.d_chunks, pb.d_epart, pb.d_part,
                        bs.epart, bs.part);
   }

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
-                ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int)]
+                ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
+                ("direct_lattice_m2l", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -65,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("eta", ctypes.c_double), ("varrho", ctypes.c_double), ("theta", ctypes.c_double),
                 ("lattice_q", ctypes.c_int), ("p2p_split", ctypes.c_int), ("n_near_computed", ctypes.c_int),
                 ("n_near_stored", ctypes.c_longlong), ("n_near_circulant", ctypes.c_longlong),
-                ("p2p_window_leaves", ctypes.c_int), ("p2p_window_max", ctypes.c_int)]
+                ("p2p_window_leaves", ctypes.c_int), ("p2p_window_max", ctypes.c_int),
+                ("lattice_m2l_grid", ctypes.c_int)]
 
 
 FP64 = 0
@@ -153,7 +155,8 @@ class Problem:
                  g_far: int = 4, restart: int = 200, max_iter: int = 4000, tol: float = 1e-8,
                  wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
-                 store_self_blocks: bool = False, p2p_cached_rows: bool = False):
+                 store_self_blocks: bool = False, p2p_cached_rows: bool = False,
+                 direct_lattice_m2l: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -164,7 +167,8 @@ class Problem:
         mat = Material(rho_fiber, c_fiber, rho_matrix, c_matrix, eta)
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
                       max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
-                      1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0)
+                      1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
+                      1 if direct_lattice_m2l else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"

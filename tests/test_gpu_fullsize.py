@@ -217,3 +217,28 @@ def test_hexagon_16x16_mixed_solve(pfm):
     _say("  fp64 residual of mixed solution", res, "difference to fp64 solution", dx)
     assert res < 1e-8
     assert dx < 1e-6
+
+
+@pytest.mark.parametrize("key", ["hexagon_16x16", "square_12x12", "hexagon_13x11"])
+def test_lattice_grid_m2l_equals_direct(pfm, key):
+    """From 128 fibres up the root lattice M2L runs as a convolution over the
+    fibre grid (zero-padded 2D DFTs); it equals the direct sum over every root
+    pair to rounding.  Square and hexagonal grids, and an odd column count
+    (the two hexagonal sublattices of different widths)."""
+    wl = {"hexagon_16x16": W.hexagon_16x16(),
+          "square_12x12": W.small_square(12, 12, 32, 0.3, 2.5, 0.3, lattice=W.SQUARE),
+          "hexagon_13x11": W.small_square(13, 11, 32, 0.25, 2.0, 0.5, lattice=W.HEXAGON)}[key]
+    ka, th = (2.0, math.pi / 6) if key == "hexagon_16x16" else (wl.ka[0], wl.theta[0])
+    psi = torch.tensor(W.random_density(2 * wl.M * wl.n_elem, 14), device="cuda")
+    ys, st = [], []
+    for direct in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=16 if key != "hexagon_16x16" else 64,
+                                         direct_lattice_m2l=direct)
+        prob.set_wave(ka, th)
+        ys.append(prob.matvec(psi).clone())
+        st.append(prob.stats())
+        prob.close()
+    d = float(torch.max(torch.abs(ys[0] - ys[1])) / torch.max(torch.abs(ys[1])))
+    _say("lattice grid vs direct:", key, st[0]["lattice_m2l_grid"], st[1]["lattice_m2l_grid"], d)
+    assert st[0]["lattice_m2l_grid"] == 1 and st[1]["lattice_m2l_grid"] == 0
+    assert d < 1e-12
