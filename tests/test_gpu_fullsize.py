@@ -242,3 +242,23 @@ def test_lattice_grid_m2l_equals_direct(pfm, key):
     _say("lattice grid vs direct:", key, st[0]["lattice_m2l_grid"], st[1]["lattice_m2l_grid"], d)
     assert st[0]["lattice_m2l_grid"] == 1 and st[1]["lattice_m2l_grid"] == 0
     assert d < 1e-12
+
+
+def test_batched_apply_with_lattice_grid_m2l(pfm):
+    """A batch of angles on a 144-fibre block (lattice M2L as a grid
+    convolution, one set of transformed lattice rows per member) against the
+    single-angle apply of each member and the direct lattice M2L."""
+    wl = W.small_square(12, 12, 32, 0.3, 2.5, 0.3, lattice=W.SQUARE)
+    th = [0.0, 0.4, 1.1]
+    pb = pfm.Problem.from_workload(wl, p=24, leaf_max=16, max_batch=4)
+    assert pb.stats()["lattice_m2l_grid"] == 1
+    pb.set_batch(2.5, th)
+    psi = torch.tensor(np.stack([W.random_density(pb.n, 60 + b) for b in range(3)]), device="cuda")
+    yb = pb.matvec_batch(psi).cpu().numpy()
+    single = pfm.Problem.from_workload(wl, p=24, leaf_max=16, direct_lattice_m2l=True)
+    for b in range(3):
+        single.set_wave(2.5, th[b])
+        ys = single.matvec(psi[b].contiguous()).cpu().numpy()
+        err = np.linalg.norm(yb[b] - ys) / np.linalg.norm(ys)
+        _say("batched grid lattice vs single direct:", b, err)
+        assert err < 1e-13
