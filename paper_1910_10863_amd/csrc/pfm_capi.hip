@@ -1225,21 +1225,21 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
           double hn;
           if (dcgs) {
             // raw step data of j and j + 1 -> column j of H (see launch_dcgs_step):
-            // h = ((b, s) - H[0..j][0..j-1] a) / gamma, plus beta a' of step j + 1,
-            // subdiagonal beta gamma'
+            // h = ((b, s) - H[0..j][0..j-1] a) / gamma, plus a' of step j + 1,
+            // subdiagonal gamma' (u_{j+1} = w1 is not normalised)
             const cd* rn = pb.h_hall + ((size_t)(j + 1) * B + i) * hs2;
-            const double gam = hv[2 * j + 1].x, beta = std::sqrt(std::max(0.0, hv[2 * (j + 1)].x));
+            const double gam = hv[2 * j + 1].x;
             const double gam1 = rn[2 * (j + 1) + 1].x;
             C* Hr = &Hraw[(size_t)i * (m + 1) * m];
             for (int r = 0; r <= j; ++r) {
               C gr = 0.0;
               for (int c = std::max(r - 1, 0); c < j; ++c) gr += Hr[(size_t)r * m + c] * C(hv[c].x, hv[c].y);
               const C br = r < j ? C(hv[j + r].x, hv[j + r].y) : C(hv[2 * j].x, hv[2 * j].y);
-              const C hrj = (br - gr) / gam + beta * C(rn[r].x, rn[r].y);
+              const C hrj = (br - gr) / gam + C(rn[r].x, rn[r].y);
               Hr[(size_t)r * m + j] = hrj;
               col[r] = hrj;
             }
-            hn = beta * gam1;
+            hn = gam1;
             Hr[(size_t)(j + 1) * m + j] = hn;
           } else {
             for (int r = 0; r <= j; ++r) col[r] = C(hv[r].x + hv[j + 1 + r].x, hv[r].y + hv[j + 1 + r].y);

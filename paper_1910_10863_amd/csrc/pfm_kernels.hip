@@ -2087,19 +2087,20 @@ __global__ void __launch_bounds__(256) k_normalize_fused(cd* w, long long wsb, c
 // h2 in [j+1, 2j+1], ||W||^2 in [2j+2].
 // ---- Arnoldi with delayed reorthogonalisation (DCGS2: Bielich, Langou,
 // Thomas, Swirydowicz, Yamazaki & Boman 2022) ----
-// Step j holds v_0..v_{j-1} final and u_j (slot j) orthogonalised once and
-// normalised; w = Op u_j is in slot j+1.  One reduction gives
+// Step j holds v_0..v_{j-1} final and u_j (slot j) orthogonalised once (not
+// normalised); w = Op u_j is in slot j+1.  One reduction gives
 // a = V_{j-1}^H u_j, d = u_j^H u_j, b = V_{j-1}^H w, c = u_j^H w.  Then
 //   gamma = sqrt(d - |a|^2),  v_j = (u_j - V_{j-1} a) / gamma      (second pass of step j-1)
 //   s = v_j^H w = (c - a^H b) / gamma
-//   w1 = (w - V_{j-1} b - s v_j) / gamma,  u_{j+1} = w1 / ||w1||
+//   w1 = (w - V_{j-1} b - s v_j) / gamma,  u_{j+1} = w1
 // so every step reads the basis twice (one reduction, one update) instead of
-// four times.  The Hessenberg column needs g = H[0..j][0..j-1] a (the
-// Arnoldi relation applied to V_{j-1} a): h = ((b, s) - g) / gamma, and
-// column j-1 gains beta a and the subdiagonal beta gamma.  That small dense
-// algebra is left to the host, which reads per step j the raw column
-// [a (j) | b (j) | s | gamma | ||w1||^2] from d_hall (slot 2(j+1) is the
-// squared norm, as for CGS2).
+// four times.  u_{j+1} is left unnormalised: the next step's gamma divides
+// its norm out (scaling u_j by nu scales a, b, s, gamma and w by nu, and v_j
+// and w1 not at all).  The Hessenberg column needs g = H[0..j][0..j-1] a (the
+// Arnoldi relation applied to V_{j-1} a): h = ((b, s) - g) / gamma plus the
+// next step's a, and the subdiagonal is the next step's gamma (w1 =
+// gamma' v_{j+1} + V_j a').  That small dense algebra is left to the host,
+// which reads per step j the raw column [a (j) | b (j) | s | gamma] from d_hall.
 
 // partial[member][v * cnt + i][block] = V_i^H x_v over the block's chunks, x_0 = V_{cnt-1}
 // (u_j), x_1 = w (NV = 2) or only x_0 (NV = 1)
@@ -2203,14 +2204,14 @@ __global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, 
 }
 
 // v_j = u_j / gamma - V_{j-1} (a / gamma) into slot j; w = w / gamma - V_{j-1} (b / gamma)
-// - (s / gamma) v_j, and the partial squared norms of w.  A workgroup covers
+// - (s / gamma) v_j.  A workgroup covers
 // 64 elements; its four wavefronts take the basis vectors i = wv, wv + 4, ...
 // (four times the loads in flight of one wavefront per element block), and
 // their partial sums are added in wavefront order.
 constexpr int UPD_ELEMS = 64;
 __global__ void __launch_bounds__(256) k_dcgs_update(cd* V, long long ldv, long long vsb, int j, cd* w,
                                                      long long wsb, const cd* __restrict__ coef, long long csb,
-                                                     int n, double* npart) {
+                                                     int n) {
   __shared__ cd pv[4][UPD_ELEMS], pw[4][UPD_ELEMS];
   const int b = blockIdx.y;
   V += b * vsb;
@@ -2236,23 +2237,18 @@ __global__ void __launch_bounds__(256) k_dcgs_update(cd* V, long long ldv, long 
   const double ig = coef[2 * j + 1].x;
   const cd sv = cadd(cadd(pv[0][lane], pv[1][lane]), cadd(pv[2][lane], pv[3][lane]));
   const cd sw = cadd(cadd(pw[0][lane], pw[1][lane]), cadd(pw[2][lane], pw[3][lane]));
-  double q = 0.0;
   if (in) {
     const cd vj = csub(cscale(V[(size_t)j * ldv + t], ig), sv);
     const cd wa = csub(csub(cscale(w[t], ig), sw), cmul(coef[2 * j], vj));
     V[(size_t)j * ldv + t] = vj;
     w[t] = wa;
-    q = cabs2(wa);
   }
-  q = wave_sum_d(q);
-  if (lane == 0) npart[(size_t)b * gridDim.x + blockIdx.x] = q;
 }
 
 hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long vsb, int j, cd* W, long long wsb,
                             int n, long long hsb) {
   const int cnt = j + 1;
   const int nblk = pb.red_blocks;
-  const int nu = (n + 255) / 256;
   const long long hcs = (long long)B * hsb;                 // column stride in d_hall
   const long long csb = 2LL * pb.opt.restart + 4;
   cd* fin = pb.d_red + (size_t)B * 2 * cnt * nblk;          // [B][2 cnt] reduced dots
@@ -2264,9 +2260,7 @@ hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long 
                      pb.d_dcoef, csb);
   const int nup = (n + UPD_ELEMS - 1) / UPD_ELEMS;
   hipLaunchKernelGGL(k_dcgs_update, dim3(nup, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, pb.d_dcoef, csb,
-                     n, pb.d_npart);
-  hipLaunchKernelGGL(k_normalize_fused, dim3(nu, B), dim3(256), 0, pb.stream, W, wsb, pb.d_npart, nup,
-                     pb.d_hall + (size_t)j * hcs + 2 * cnt, hsb, n);
+                     n);
   return hipGetLastError();
 }
 
