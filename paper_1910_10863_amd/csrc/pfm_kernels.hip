@@ -342,12 +342,6 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 constexpr int LAT_MAX_NT = 4 * 40 + 1;
 
 __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const double* __restrict__ roff,
