@@ -262,3 +262,27 @@ def test_batched_apply_with_lattice_grid_m2l(pfm):
         err = np.linalg.norm(yb[b] - ys) / np.linalg.norm(ys)
         _say("batched grid lattice vs single direct:", b, err)
         assert err < 1e-13
+
+
+def test_mixed_apply_with_circulant_rows_hexagon(pfm):
+    """The complex64 apply with the default near field (circulant self rows
+    in FP64, only cross-fibre pairs stored and rounded to complex64; one
+    column split per leaf, so the downward pass adds the far part after the
+    P2P of the complex64 kernel) stays within the rounding of the stored
+    blocks of the FP64 apply; on this block every near pair is a same-fibre
+    pair, so the two applies agree exactly."""
+    wl = W.hexagon_16x16()
+    prob = pfm.Problem.from_workload(wl, precision=pfm.MIXED)
+    prob.set_wave(wl.ka[0], wl.theta[0])
+    st = prob.stats()
+    assert st["p2p_split"] == 1 and st["n_near_circulant"] > st["n_near_stored"]
+    psi = torch.tensor(W.random_density(prob.n, 15), device="cuda")
+    y64 = prob.matvec(psi).clone()
+    y32 = prob.matvec_mixed(psi).clone()
+    y32b = prob.matvec_mixed(psi).clone()
+    d = float(torch.max(torch.abs(y32 - y64)) / torch.max(torch.abs(y64)))
+    _say("hexagon mixed vs fp64 apply (circulant rows):", st["n_near_stored"], d)
+    assert torch.equal(y32, y32b)
+    assert d < 2e-6
+    if st["n_near_stored"] == 0:
+        assert d == 0.0
