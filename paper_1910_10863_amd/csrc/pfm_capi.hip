@@ -585,7 +585,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     // each); one sum per (channel, cell) with entries adds its chunks' partial
     // expansions in order, so the downward pass reads one sum per cell.  A
     // root's M lattice entries go in chunks of M2L_LAT_CHUNK once M >= 128,
-    // where 2-entry chunks would write M / 2 partial expansions per root.
+    // where one-entry chunks would write M partial expansions per root.
     std::vector<int> esrc, eoff, em, mchunks, sums, ccptr(2 * (size_t)nc + 1, 0);
     std::vector<int> fibre_of_root(nc, -1);
     for (int f = 0; f < pb.M; ++f) fibre_of_root[hp.root_of_fibre[f]] = f;

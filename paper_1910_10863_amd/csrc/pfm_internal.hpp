@@ -27,7 +27,7 @@ struct Cell {
 struct M2LEntry { int tgt, src, off, m; };
 
 // M2L entries are processed in chunks of at most this many entries of one (channel, cell)
-constexpr int M2L_CHUNK = 2;
+constexpr int M2L_CHUNK = 1;
 constexpr int M2L_LAT_CHUNK = 8;     // lattice entries of a root, for M >= 128 fibres
 // largest padded fibre grid of the lattice M2L convolution (LDS per DFT;
 // each axis at most 64 points)
