@@ -911,17 +911,18 @@ __device__ __forceinline__ cd lane_cd(cd v, int lane) {
 // the leaves below it, M_n(C) = sum_L sum_l M_l(L) Jm_{n-l}(kap (O_L - O_C))
 // (Graf's theorem for J, eq. 10, as in the M2M translation of Sec. 3.2,
 // applied across several levels at once), so the whole upward pass above
-// the leaves is a single launch.  One workgroup of four wavefronts per
+// the leaves is a single launch.  One workgroup of eight wavefronts per
 // (non-leaf cell, channel); the wavefronts split the leaves and their
 // partial sums meet in LDS in a fixed order.
+constexpr int M2M_WAVES = 8;
 template <int P>
-__global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, const int* __restrict__ ptr,
+__global__ void __launch_bounds__(64 * M2M_WAVES) k_m2m(const int* __restrict__ cells, const int* __restrict__ ptr,
                                              const int* __restrict__ src, const int* __restrict__ off,
                                              const cd* __restrict__ jtab, int n_joff, cd* mpole,
                                              long long mp_stride) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64;
-  __shared__ cd sj[4][NT];
-  __shared__ cd sr[4][NP];
+  __shared__ cd sj[M2M_WAVES][NT];
+  __shared__ cd sr[M2M_WAVES][NP];
   mpole += blockIdx.z * mp_stride;              // batch member
   int ci = blockIdx.x, ch = blockIdx.y;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -943,7 +944,7 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
     for (int u = 0; u < NTU; ++u) tnext[u] = lane + 64 * u < NT ? tj[lane + 64 * u] : mkc(0, 0);
   };
   if (q < qend) fetch(q);
-  for (; q < qend; q += 4) {
+  for (; q < qend; q += M2M_WAVES) {
     // the leaf's moments stay in registers and reach the lanes by lane reads
     cd mreg[NU];
 #pragma unroll
@@ -954,7 +955,7 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    if (q + 4 < qend) fetch(q + 4);
+    if (q + M2M_WAVES < qend) fetch(q + M2M_WAVES);
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
       int n = min(lane + 64 * i - P, P);      // lanes past the last order repeat it
@@ -975,7 +976,11 @@ __global__ void __launch_bounds__(256) k_m2m(const int* __restrict__ cells, cons
   }
   __syncthreads();
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  for (int n = threadIdx.x; n < NP; n += 256) out[n] = cadd(cadd(sr[0][n], sr[1][n]), cadd(sr[2][n], sr[3][n]));
+  for (int n = threadIdx.x; n < NP; n += 64 * M2M_WAVES) {
+    cd a = sr[0][n];
+    for (int v = 1; v < M2M_WAVES; ++v) a = cadd(a, sr[v][n]);
+    out[n] = a;
+  }
 }
 
 // M2L over chunks of the interaction lists (eq. 13 with the index n - l):
@@ -1682,7 +1687,7 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                      bs.mpole);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (pb.n_up > 0)
-    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2, B), dim3(256), 0, s, pb.d_up_cells, pb.d_up_ptr,
+    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
                        pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
