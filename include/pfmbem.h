@@ -106,7 +106,7 @@ typedef struct {
  *  use_graph  batched solves replay the batched apply from a captured HIP
  *             graph (1) or launch it kernel by kernel (0)
  *  p2p_blocks_per_cu  workgroups per compute unit of the persistent P2P
- *             launch (0: 4 when most near pairs use circulant rows, else 2;
+ *             launch (0: 3 when most near pairs use circulant rows, else 2;
  *             at most 8)
  *  p2p_unroll  source columns whose block entries a P2P wavefront keeps in
  *             flight at once: 1, 2 or 4 (0: 1)

@@ -327,7 +327,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     // rate without starving the chain; the light circulant P2P on the side
     // stream takes four (measured fastest for the overlapped apply)
     if (pb.n_cu > 0)
-      pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : (pb.p2p_on_side ? 4 : 2)) * pb.n_cu;
+      pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : (pb.p2p_on_side ? 3 : 2)) * pb.n_cu;
   }
   // near-block storage of the other pairs: per target leaf its stored pairs
   // one after the other; with equal fibres, a region (the stored blocks of one

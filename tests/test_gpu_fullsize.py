@@ -123,7 +123,7 @@ def test_apply_is_deterministic(pfm):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("key,bpc", [("square_4x4", 0), ("square_8x8", 0), ("square_8x8", 3), ("hexagon_16x16", 0)])
+@pytest.mark.parametrize("key,bpc", [("square_4x4", 0), ("square_8x8", 0), ("square_8x8", 4), ("hexagon_16x16", 0)])
 def test_timed_apply_matches_overlapped_apply(pfm, key, bpc):
     """The overlapped apply (P2P on the side stream; with one column split
     per leaf the downward pass adds the far part into y after waiting for
@@ -135,9 +135,12 @@ def test_timed_apply_matches_overlapped_apply(pfm, key, bpc):
     st = prob.stats()
     _say("overlapped vs in-order:", key, bpc, "split", st["p2p_split"], "circulant", st["n_near_circulant"],
          "stored", st["n_near_stored"])
-    if key == "hexagon_16x16" or bpc == 3:
+    if key == "hexagon_16x16" or (key == "square_8x8" and bpc == 0):
         # one split per leaf and mostly circulant pairs: the fused join runs
         assert st["p2p_split"] == 1 and st["n_near_circulant"] > st["n_near_stored"]
+    if key == "square_8x8" and bpc == 4:
+        # 1024 workgroups for 848 leaves: two column splits, the join kernel
+        assert st["p2p_split"] == 2
     psi = torch.tensor(W.random_density(prob.n, 10), device="cuda")
     a = prob.matvec(psi).clone()
     stages, tot, b = prob.matvec_timed(psi, reps=2)
