@@ -803,10 +803,10 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
     cd w0 = cscale(vphi, eta * w);
     cd ah = cscale(phi, -sk * etx);                                // (wm + wp) / 2
     cd bh = mkc(-sk * ety * phi.y, sk * ety * phi.x);               // (wm - wp) / 2
-    double gs[H::HI + 2];
-    scaled_j<H::HI + 1>(0.25 * (vx * vx + vy * vy), gs);
+    double gs[H::HI + 2];                                          // h_n = g_n / n!
+    scaled_h<H::HI + 1>(0.25 * (vx * vx + vy * vy), gs);
     cd hv = mkc(0.5 * vx, -0.5 * vy);                              // conj(v)/2
-    cd uu = hv;
+    cd uu = hv;                                                    // (conj(v)/2)^n
     cd J0 = mkc(gs[0], 0.0);                                       // Jm_0
     cd J1 = cscale(uu, gs[1]);                                     // Jm_1
     cd Jprev = cscale(cconj(J1), -1.0);                            // Jm_{-1}
@@ -827,7 +827,7 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
         }
       }
       if (m < H::HI) {
-        uu = cscale(cmul(uu, hv), 1.0 / (double)(m + 2));
+        uu = cmul(uu, hv);
         Jprev = J0;
         J0 = J1;
         J1 = cscale(uu, gs[m + 2]);
@@ -1196,10 +1196,10 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
   double kap = ch ? k1 : k;
   if (lane < rows) {
     double vx = kap * g.x, vy = kap * g.y;
-    double gs[K + 1];
-    scaled_j<K>(0.25 * (vx * vx + vy * vy), gs);
+    double gs[K + 1];                        // h_n = g_n / n!
+    scaled_h<K>(0.25 * (vx * vx + vy * vy), gs);
     cd hv = mkc(0.5 * vx, 0.5 * vy);
-    cd uu = mkc(1.0, 0.0);                   // (v/2)^n / n!
+    cd uu = mkc(1.0, 0.0);                   // (v/2)^n
     cd sa = mkc(0, 0), sb = mkc(0, 0);
 #pragma unroll
     for (int n = 0; n <= K; ++n) {
@@ -1213,7 +1213,7 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
       sa.y = fma(s1.y, x, fma(t1.y, y, sa.y));
       sb.x = fma(s2.x, x, fma(t2.x, y, sb.x));
       sb.y = fma(s2.y, x, fma(t2.y, y, sb.y));
-      if (n < K) uu = cscale(cmul(uu, hv), 1.0 / (double)(n + 1));
+      if (n < K) uu = cmul(uu, hv);
     }
     cd nu = mkc(g.w, -g.z);
     dv = cscale(csub(cmul(nu, sa), cmul(cconj(nu), sb)), 0.5 * kap);

@@ -235,6 +235,48 @@ __host__ __device__ __forceinline__ void scaled_j(double q, double (&g)[NT + 1])
   }
 }
 
+// The same sequence divided by n!: h_n(x) = (2/x)^n J_n(x) = g_n / n!, so that
+// Jp_n(v) = (v/2)^n h_n(|v|) needs no factorial in the power sequence.  Power
+// series at NT and NT-1 (h_n = sum_k (-q)^k / (k! (n+k)!)); for q <= 1/4 eight
+// terms leave a remainder below 1e-19 relative for n >= 4, else as scaled_j.
+// Backward recurrence h_{n-1} = n h_n - q h_{n+1} (that of g_n times 1/(n-1)!).
+__host__ __device__ constexpr double inv_factorial(int n) { return n <= 1 ? 1.0 : inv_factorial(n - 1) / n; }
+
+template <int NT>
+__host__ __device__ __forceinline__ double scaled_h_series(double q) {
+  constexpr double f = inv_factorial(NT);
+  double term = f, sum = f;
+  if (q <= 0.25) {
+#pragma unroll
+    for (int k = 1; k <= 8; ++k) {
+      term *= -q * (1.0 / ((double)k * (double)(NT + k)));
+      sum += term;
+    }
+  } else if (q <= 10.0) {
+#pragma unroll
+    for (int k = 1; k <= 18; ++k) {
+      term *= -q * (1.0 / ((double)k * (double)(NT + k)));
+      sum += term;
+    }
+  } else {
+    for (int k = 1; k < 400; ++k) {
+      term *= -q / ((double)k * (double)(NT + k));
+      sum += term;
+      if (fabs(term) < 1e-17 * fabs(sum)) break;
+    }
+  }
+  return sum;
+}
+
+template <int NT>
+__host__ __device__ __forceinline__ void scaled_h(double q, double (&h)[NT + 1]) {
+  static_assert(NT >= 5, "the eight-term series needs n >= 4");
+  h[NT] = scaled_h_series<NT>(q);
+  h[NT - 1] = scaled_h_series<NT - 1>(q);
+#pragma unroll
+  for (int n = NT - 1; n >= 1; --n) h[n - 1] = (double)n * h[n] - q * h[n + 1];
+}
+
 // Jp_n(v) for n = 0..NT at the complex point v (v = vx + i vy), into jp[].
 template <int NT>
 __host__ __device__ __forceinline__ void jplus_seq(double vx, double vy, cd (&jp)[NT + 1]) {
