@@ -69,7 +69,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_e_src); dfree(pb.d_e_off); dfree(pb.d_e_m); dfree(pb.d_chunks); dfree(pb.d_cc_ptr);
   dfree(pb.d_part); dfree(pb.d_epart); dfree(pb.d_mchunks);
   dfree(pb.d_up_cells); dfree(pb.d_up_ptr); dfree(pb.d_up_src); dfree(pb.d_up_off);
-  dfree(pb.d_ldesc); dfree(pb.d_lanc); dfree(pb.d_tgeo); dfree(pb.d_far);
+  dfree(pb.d_ldesc); dfree(pb.d_lanc); dfree(pb.d_tgeo); dfree(pb.d_trh); dfree(pb.d_far);
   dfree(pb.d_cx); dfree(pb.d_cy); dfree(pb.d_ebeg); dfree(pb.d_eend);
   dfree(pb.d_first_child); dfree(pb.d_n_child); dfree(pb.d_cell_joff); dfree(pb.d_parent);
   dfree(pb.d_leaves); dfree(pb.d_root_of_fibre); dfree(pb.d_fibre_of_cell);
@@ -659,13 +659,15 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     pb.n_mchunks = (int)(mchunks.size() / 4);
     CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
     CK(upload(&pb.d_mchunks, mchunks)); CK(upload(&pb.d_chunks, sums)); CK(upload(&pb.d_cc_ptr, ccptr));
-    // downward pass descriptors: everything a leaf's workgroup reads is one
-    // load away from its index (no chain leaf -> cell -> sum row)
+    // leaf descriptors of P2M and the downward pass: everything a leaf's
+    // workgroup reads is one load away from its index (no chain leaf -> cell
+    // -> element -> geometry, or cell -> sum row)
     const int nl = (int)hp.leaves.size();
     std::vector<int> ldesc(8 * (size_t)nl), lanc;
-    std::vector<double> tgeo(4 * (size_t)E), tx(E), ty(E);
+    std::vector<double> tgeo(4 * (size_t)E), trh(E), tx(E), ty(E), hh(E);
     CK(hipMemcpy(tx.data(), pb.d_tx, E * sizeof(double), hipMemcpyDeviceToHost));
     CK(hipMemcpy(ty.data(), pb.d_ty, E * sizeof(double), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(hh.data(), pb.d_h, E * sizeof(double), hipMemcpyDeviceToHost));
     auto sum_row = [&](int ch, int c) {
       size_t i = (size_t)ch * nc + c;
       return ccptr[i + 1] > ccptr[i] ? ccptr[i] : -1;
@@ -692,10 +694,11 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         tgeo[4 * (size_t)t + 1] = my[e] - L.cy;
         tgeo[4 * (size_t)t + 2] = tx[e];
         tgeo[4 * (size_t)t + 3] = ty[e];
+        trh[t] = hh[e];
       }
     }
     if (lanc.empty()) lanc.assign(2, 0);
-    CK(upload(&pb.d_ldesc, ldesc)); CK(upload(&pb.d_lanc, lanc)); CK(upload(&pb.d_tgeo, tgeo));
+    CK(upload(&pb.d_ldesc, ldesc)); CK(upload(&pb.d_lanc, lanc)); CK(upload(&pb.d_tgeo, tgeo)); CK(upload(&pb.d_trh, trh));
     CK(hipMalloc((void**)&pb.d_part, MB * std::max(1, pb.n_chunks) * NP * sizeof(cd)));
     CK(hipMalloc((void**)&pb.d_epart, MB * std::max(1, pb.n_mchunks) * NP * sizeof(cd)));
     if (pb.lat_fft) {

@@ -166,11 +166,11 @@ struct Problem {
   // ancestors; both with an index into the J translation table
   int *d_up_cells = nullptr, *d_up_ptr = nullptr, *d_up_src = nullptr, *d_up_off = nullptr;
   int n_up = 0;
-  // downward pass, per leaf: [row begin, rows, own M2L sum row per channel,
+  // P2M and downward pass, per leaf: [row begin, rows, own M2L sum row per channel,
   // ancestor range per channel] (8 ints), the ancestors' (M2L sum row, leaf
   // offset) pairs, and the targets' (x - O, y - O, tx, ty) in row order
   int *d_ldesc = nullptr, *d_lanc = nullptr;
-  double* d_tgeo = nullptr;
+  double *d_tgeo = nullptr, *d_trh = nullptr;   // [E][4] target geometry, [E] chord length, row order
   cd *d_far = nullptr;                  // far part of the rows, Psi order
   int n_tab = 0;                        // rows per channel of d_htab: M2L offsets, then lattice offsets
   cd *d_alpha = nullptr;                // alpha^m, m = m_min..m_max, per batch member

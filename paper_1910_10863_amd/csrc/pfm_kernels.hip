@@ -773,14 +773,17 @@ struct P2MHalf {
   static constexpr int NS = NPOS + NNEG;
 };
 
+// A leaf's rows staged in LDS: element midpoint relative to the leaf centre,
+// unit tangent, chord length and the two densities, plus the Gauss rule.
+struct P2MRows {
+  double x[64], y[64], tx[64], ty[64], h[64];
+  cd phi[64], vphi[64];
+  double gl[32];
+};
+
 template <int P, int W, int NA>
-__device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npts, int G, int N,
-                                         double kap, double eta, double ox, double oy,
-                                         const int* __restrict__ elem_of, const int* __restrict__ psi_idx,
-                                         const double* __restrict__ mx, const double* __restrict__ my,
-                                         const double* __restrict__ tx, const double* __restrict__ ty,
-                                         const double* __restrict__ h, const double* __restrict__ gl,
-                                         const cd* __restrict__ psi) {
+__device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int npts, int G, double kap, double eta,
+                                         const P2MRows& rw) {
   using H = P2MHalf<P, W>;
   constexpr int M1 = H::LO > 0 ? H::LO : 1;   // first order with a +- pair
   // slot of order +m: m - LO (Pm for m >= 1); slot of order -m: NPOS + m - M1 (Qm)
@@ -790,13 +793,10 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
   for (int pt = lane; pt < npts; pt += 64) {
     int q = pt / G;
     int g = pt - q * G;
-    int t = b + q;
-    int e = elem_of[t];
-    int pi = psi_idx[t];
-    cd phi = psi[pi], vphi = psi[pi + N];
-    double etx = tx[e], ety = ty[e], hh = h[e];
-    double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g];       // (1/4) of the weight
-    double vx = kap * (mx[e] + s * etx - ox), vy = kap * (my[e] + s * ety - oy);
+    cd phi = rw.phi[q], vphi = rw.vphi[q];
+    double etx = rw.tx[q], ety = rw.ty[q], hh = rw.h[q];
+    double s = 0.5 * hh * rw.gl[g], w = 0.125 * hh * rw.gl[G + g];
+    double vx = kap * (rw.x[q] + s * etx), vy = kap * (rw.y[q] + s * ety);
     // (i/4) w [ -i eta varphi | (kap/2) conj(nu) phi | -(kap/2) nu phi ], nu = (ty, -tx):
     // w0 = eta w varphi, wm = i (ty + i tx) phi sk, wp = -i (ty - i tx) phi sk, sk = kap w / 2
     const double sk = 0.5 * kap * w;
@@ -846,13 +846,9 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int b, int npt
 }
 
 template <int P>
-__global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ebeg,
-                                             const int* __restrict__ eend, const int* __restrict__ elem_of,
-                                             const int* __restrict__ psi_idx,
-                                             const double* __restrict__ cx, const double* __restrict__ cy,
-                                             const double* __restrict__ mx, const double* __restrict__ my,
-                                             const double* __restrict__ tx, const double* __restrict__ ty,
-                                             const double* __restrict__ h, const double* __restrict__ gl,
+__global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
+                                             const double4* __restrict__ tgeo, const double* __restrict__ trh,
+                                             const int* __restrict__ psi_idx, const double* __restrict__ gl,
                                              int G, int N, double k, double k1, double eta,
                                              const cd* __restrict__ psi, cd* __restrict__ mpole,
                                              long long psi_stride, long long mp_stride) {
@@ -861,22 +857,37 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
   // one transpose buffer, used by the two wavefronts in turn (keeps the LDS
   // footprint small so that P2M co-resides with the concurrent P2P)
   __shared__ cd red[64][NA];
-  psi += blockIdx.z * psi_stride;               // batch member
+  // the leaf's rows (from its descriptor and the row-ordered geometry) are
+  // loaded once by the first wavefront; the point loop then reads only LDS
+  __shared__ P2MRows rw;
+  psi += blockIdx.z * psi_stride;
   mpole += blockIdx.z * mp_stride;
-  int cell = leaves[blockIdx.x];
+  const int cell = leaves[blockIdx.x];
+  const int rb = ldesc[8 * blockIdx.x], rows = ldesc[8 * blockIdx.x + 1];
   int ch = blockIdx.y;
   double kap = ch ? k1 : k;
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double ox = cx[cell], oy = cy[cell];
-  int b = ebeg[cell];
-  int npts = (eend[cell] - b) * G;
+  if (wv == 0) {
+    if (lane < rows) {
+      const double4 g = tgeo[rb + lane];
+      const int pi = psi_idx[rb + lane];
+      rw.x[lane] = g.x; rw.y[lane] = g.y; rw.tx[lane] = g.z; rw.ty[lane] = g.w;
+      rw.h[lane] = trh[rb + lane];
+      rw.phi[lane] = psi[pi];
+      rw.vphi[lane] = psi[pi + N];
+    }
+  } else if (lane < 2 * G) {
+    rw.gl[lane] = gl[lane];
+  }
+  __syncthreads();
+  const int npts = rows * G;
   cd acc[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = mkc(0, 0);
   if (wv == 0)
-    p2m_half<P, 0, NA>(acc, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
+    p2m_half<P, 0, NA>(acc, lane, npts, G, kap, eta, rw);
   else
-    p2m_half<P, 1, NA>(acc, lane, b, npts, G, N, kap, eta, ox, oy, elem_of, psi_idx, mx, my, tx, ty, h, gl, psi);
+    p2m_half<P, 1, NA>(acc, lane, npts, G, kap, eta, rw);
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
   for (int pass = 0; pass < 2; ++pass) {
     if (wv == pass) {
@@ -1681,10 +1692,9 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   int n_joff = (int)hp.joff_xy.size() / 2;
   const BatchStrides bs = batch_strides(pb);
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2, B), dim3(128), 0, s, pb.d_leaves, pb.d_ebeg, pb.d_eend,
-                     pb.d_elem_of, pb.d_psi_idx, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty,
-                     pb.d_h, pb.d_gl, pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec,
-                     bs.mpole);
+  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
+                     reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl, pb.opt.g_far,
+                     pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (pb.n_up > 0)
     hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
