@@ -338,6 +338,29 @@ def main():
                  "mean_iters": float(np.mean(iters)), "max_iters": int(np.max(iters)),
                  "max_rel_residual": float(np.max(res)), "tol": 1e-8, "seconds": tsw,
                  "precision": "fp64", "setup_included": True}
+        # the same sweep with GMRES right-preconditioned by the fibres'
+        # free-space self blocks (power-of-two N only)
+        if wl.n_elem & (wl.n_elem - 1) == 0 and 8 <= wl.n_elem <= 512:
+            pcp = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, restart=200, max_iter=4000, tol=1e-8,
+                                            precond=True)
+            pits, pres, pfails = [], [], 0
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for ka in kas:
+                pcp.set_wave(ka, theta)
+                x, info = pcp.solve()
+                pits.append(info["iters"])
+                pres.append(info["rel_residual"])
+                pfails += info["status"] != 0
+                print(f"sweep precond ka={ka:.4f} iters={info['iters']} res={info['rel_residual']:.2e} "
+                      f"t={info['t_solve_s']:.3f}s", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            tpc = time.perf_counter() - ts
+            pcp.close()
+            sweep["precond"] = {"solves_per_s": len(kas) / tpc, "failed": pfails,
+                                "mean_iters": float(np.mean(pits)), "max_iters": int(np.max(pits)),
+                                "max_rel_residual": float(np.max(pres)), "seconds": tpc,
+                                "speedup": tsw / tpc}
 
     mixed = None
     if "mixed" in legs:

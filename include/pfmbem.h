@@ -123,7 +123,16 @@ typedef struct {
  *             sum depends only on the grid displacement and, on the hexagonal
  *             lattice, on the parities of the two columns), by zero-padded 2D
  *             DFTs: (2 M_L)(2 M_H) Toeplitz products per sublattice pair
- *             instead of M^2; 1: every root pair is an M2L entry. */
+ *             instead of M^2; 1: every root pair is an M2L entry.
+ *  precond    0: plain GMRES; 1: pfm_solve (precision PFM_FP64) runs GMRES
+ *             right-preconditioned by the fibres' free-space self blocks of
+ *             (I - A) (the block-Jacobi preconditioner of the paper's
+ *             "preconditioned GMRES", Sec. 4): each is block circulant, so it
+ *             is inverted per Fourier mode of the element index (one 2x2
+ *             solve per mode, FFTs of length N per fibre).  The residual and
+ *             the stop test are those of the unpreconditioned system.  Needs
+ *             N a power of two, 8 <= N <= 512.  Batched solves and the
+ *             augmented start (use_x0 = 3) do not use it. */
 typedef struct {
   int p;
   int leaf_max;
@@ -142,6 +151,7 @@ typedef struct {
   int store_self_blocks;
   int p2p_cached_rows;
   int direct_lattice_m2l;
+  int precond;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -219,6 +229,16 @@ pfm_status pfm_rhs(pfm_problem* pb, void* d_b);
  * tolerance is not met in max_iter iterations (d_x holds the best iterate). */
 pfm_status pfm_solve(pfm_problem* pb, const void* d_b, void* d_x, int use_x0,
                      pfm_info* info);
+
+/* Block-Jacobi preconditioner of the current wave (options.precond = 1):
+ * d_out = P^{-1} d_in (inverse = 1) or d_out = P d_in (inverse = 0), where P
+ * is block diagonal with, for each fibre, its free-space self block of
+ * (I - A): the 2N x 2N block of its own elements at image 0, near and far
+ * pairs alike (Sec. 2, the operators of eq. 6 with the row scaling of eq. 9).
+ * d_in, d_out: device vectors of 2 M N complex128 in the layout of Psi;
+ * they may be the same buffer.  Enqueued on the bound stream.  PFM_ESTATE
+ * without pfm_set_wave or when the handle was created with precond = 0. */
+pfm_status pfm_precond_apply(pfm_problem* pb, const void* d_in, void* d_out, int inverse);
 
 /* Reflected and transmitted Bragg amplitudes for orders -n_orders..n_orders
  * (host arrays of 2*(2*n_orders+1) doubles, interleaved complex), the energy

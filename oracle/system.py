@@ -18,7 +18,8 @@ Readings: eta = k unless given (the paper only says 'a real constant');
 element integrals as in elements.py; the exterior kernel is the full image
 sum: the m = 0 term by the far/near/self rules, every m != 0 by the far rule
 with the image sums of lattice.py.  `periodic=False` drops all images
-(one fibre in free space), used only to pin the oracle against the Mie series.
+(fibres in free space), used to pin the oracle against the Mie series and
+to define the fibres' free-space self blocks (the GMRES preconditioner).
 """
 from __future__ import annotations
 
@@ -163,6 +164,38 @@ def dense_matrix(pb: Problem, chunk: int = 0) -> np.ndarray:
     A[col_phi(bd, tg)] = R1
     A[col_varphi(bd, tg)] = R2
     return A
+
+
+def fibre_self_blocks(pb: Problem) -> np.ndarray:
+    """Blocks of the block-Jacobi preconditioner of GMRES (Sec. 4 names the
+    solver a preconditioned GMRES): for each fibre f, its free-space self
+    block of (I - A), the rows and columns of its own densities with every
+    periodic image left out (and so independent of theta).  Returns
+    [M, 2N, 2N], rows and columns in the order (phi_f, varphi_f) of Psi."""
+    free = dataclasses.replace(pb, periodic=False)
+    bd = pb.bd
+    N = bd.N
+    out = np.zeros((bd.M, 2 * N, 2 * N), dtype=np.complex128)
+    for f in range(bd.M):
+        e = f * N + np.arange(N)
+        R1, R2 = operator_rows(free, e)
+        cols = np.concatenate([col_phi(bd, e), col_varphi(bd, e)])
+        out[f, :N] = R1[:, cols]
+        out[f, N:] = R2[:, cols]
+    return out
+
+
+def precond_apply(pb: Problem, x, inverse: bool = True, blocks=None) -> np.ndarray:
+    """P^{-1} x (inverse) or P x for the block-diagonal P of fibre_self_blocks."""
+    if blocks is None:
+        blocks = fibre_self_blocks(pb)
+    N = pb.bd.N
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    for f in range(pb.bd.M):
+        seg = slice(2 * f * N, 2 * f * N + 2 * N)
+        y[seg] = np.linalg.solve(blocks[f], x[seg]) if inverse else blocks[f] @ x[seg]
+    return y
 
 
 def rhs(pb: Problem) -> np.ndarray:

@@ -78,6 +78,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
   dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
+  dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x);
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
@@ -180,6 +181,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "direct_lattice_m2l must be 0 or 1"));
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
+  if (opt->precond != 0 && opt->precond != 1) return bail(fail(pb, PFM_EINVAL, "precond must be 0 or 1"));
+  if (opt->precond == 1 &&
+      (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0 || opt->precision != PFM_FP64))
+    return bail(fail(pb, PFM_EINVAL, "precond = 1 needs n_elem a power of two in 8..512 and precision PFM_FP64"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
     return bail(fail(pb, PFM_EINVAL, "max_batch must be 0..16 and use_graph 0 or 1"));
   if (opt->p2p_blocks_per_cu < 0 || opt->p2p_blocks_per_cu > 8 ||
@@ -532,6 +537,21 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     // circulant rows [fibre][component][2N] (the second copy spares the wrap)
     CK(hipMalloc((void**)&pb.d_circ, (size_t)std::max(1, pb.M) * 8 * pb.N * sizeof(cd)));
   }
+  if (pb.opt.precond) {
+    // preconditioner blocks per (fibre, mode), twiddles exp(2 pi i j / N), and
+    // the vector P^{-1} v of the preconditioned apply
+    CK(hipMalloc((void**)&pb.d_pc_fwd, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_pc_inv, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_pc_x, (size_t)2 * pb.E * sizeof(cd)));
+    std::vector<cd> tw(pb.N);
+    for (int j = 0; j < pb.N; ++j) {
+      const double t = 2.0 * M_PI * j / pb.N;
+      tw[j] = mkc(std::cos(t), std::sin(t));
+    }
+    CK(upload(&pb.d_pc_tw, tw));
+    pb.pc_logN = 0;
+    while ((1 << pb.pc_logN) < pb.N) ++pb.pc_logN;
+  }
   CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
   CK(upload(&pb.d_off_xy, hp.off_xy)); CK(upload(&pb.d_joff_xy, hp.joff_xy));
@@ -870,6 +890,7 @@ pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
   HIPCHK(pb, launch_lattice_sums(pb, 1));
   HIPCHK(pb, launch_near_blocks(pb, false));
   if (pb.opt.precision == PFM_MIXED) HIPCHK(pb, launch_near_to_c64(pb));
+  if (pb.opt.precond) HIPCHK(pb, launch_precond_setup(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   pb.wave_ready = true;
   return PFM_OK;
@@ -1438,6 +1459,19 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
     if (use_x0 == 3) {
       HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, x, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
       st = gmres_lockstep(pb, 1, apply64, b, x, false, pb.opt.tol, pb.opt.max_iter, g1, s1, nullptr, pb.d_ir_aug);
+    } else if (pb.opt.precond) {
+      // right preconditioning: GMRES for (I - A) P^{-1} z = B, then Psi = P^{-1} z;
+      // the residual B - (I - A) P^{-1} z is that of Psi, so the stop test and
+      // the reported residual are those of the unpreconditioned system
+      auto apply_pc = [&](const cd* in, cd* out) -> hipError_t {
+        hipError_t e = launch_precond(pb, in, pb.d_pc_x, true);
+        if (e == hipSuccess) e = apply_operator(pb, pb.d_pc_x, out, nullptr);
+        return e;
+      };
+      if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false));     // z0 = P Psi0
+      st = gmres_lockstep(pb, 1, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
+                          use_x0 == 2 ? &fb : nullptr);
+      HIPCHK(pb, launch_precond(pb, x, x, true));
     } else {
       st = gmres_lockstep(pb, 1, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
                           use_x0 == 2 ? &fb : nullptr);
@@ -1459,6 +1493,15 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
     info->matvecs_mixed = matvecs_low;
   }
   return st;
+}
+
+pfm_status pfm_precond_apply(pfm_problem* h, const void* d_in, void* d_out, int inverse) {
+  if (!h || !d_in || !d_out || (inverse != 0 && inverse != 1)) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.opt.precond) return fail(pb, PFM_ESTATE, "the handle was created with precond = 0");
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  HIPCHK(pb, launch_precond(pb, (const cd*)d_in, (cd*)d_out, inverse != 0));
+  return PFM_OK;
 }
 
 pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x0, pfm_info* infos) {

@@ -125,6 +125,12 @@ struct Problem {
   cd* d_lat_lhat = nullptr;             // [member][ns][px py][2p+1]: their product, before the inverse DFT
   int p2p_wmax = 0, n_win_leaves = 0;   // largest window; leaves with a window
   cd *d_circ = nullptr;                 // [fibre][B11, B12, B21, B22][2N] circulant near rows
+  // block-Jacobi preconditioner (options.precond): for each fibre and Fourier
+  // mode kappa of the element index, the 2x2 block of P and of P^{-1}
+  cd *d_pc_fwd = nullptr, *d_pc_inv = nullptr;   // [fibre][kappa][4]
+  cd *d_pc_tw = nullptr;                // [N]: exp(2 pi i j / N)
+  cd *d_pc_x = nullptr;                 // [2 M N]: P^{-1} v inside the preconditioned apply
+  int pc_logN = 0;
   // equal fibres: target leaves with the same near region (same place in
   // their fibres, same sources at the same offsets and images) read one
   // stored region; inside a stored region, pairs equal to an earlier pair are

@@ -259,8 +259,129 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   if (pb.n_near_copies > 0)
     hipLaunchKernelGGL(k_copy_blocks, dim3(pb.n_near_copies, (4 * lm * lm + 255) / 256), dim3(256), 0, pb.stream,
                        pb.d_near_cp_src, pb.d_near_cp_dst, pb.d_near_cp_len, pb.d_near);
-  if (pb.n_near_circ > 0)
+  if (pb.n_near_circ > 0 || pb.opt.precond)
     hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + 127) / 128, pb.M), dim3(128), 0, pb.stream, A, pb.d_circ);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block-Jacobi preconditioner (the "preconditioned GMRES" of Sec. 4), one
+// block per fibre: its free-space self block of (I - A), whose 2x2 block for
+// elements a, b is I delta_ab + R((b - a) mod N) with R the circulant row
+// (the row holds no identity).  The vectors e_kappa(a) = w^{kappa a},
+// w = exp(2 pi i / N), diagonalise it: mode kappa sees the 2x2 matrix
+// I + L(kappa), L(kappa) = sum_d R(d) w^{kappa d}.  With the forward DFT
+// xhat(kappa) = sum_b x_b w^{-kappa b}, P x is the inverse DFT of
+// (I + L(kappa)) xhat(kappa) and P^{-1} x that of (I + L(kappa))^{-1} xhat.
+// The DFTs are radix-2 Stockham transforms in LDS (natural order in and
+// out, so no bit reversal), one workgroup per fibre.
+// ---------------------------------------------------------------------------
+constexpr int PC_THREADS = 256;
+
+// nv vectors of length N = 2^logN at X + v N, transformed with Y (same size)
+// as the other buffer of each stage; fwd: exponent -i (unscaled either way).
+// Stage st splits each remaining sub-sequence of length N / 2^st into its
+// sum and twiddled difference halves.  Returns the buffer with the result.
+__device__ cd* pc_fft(cd* X, cd* Y, int nv, int N, int logN, const cd* __restrict__ tw, bool fwd) {
+  const int half = N >> 1;
+  for (int st = 0; st < logN; ++st) {
+    const int s = 1 << st, m = half >> st;
+    for (int i = threadIdx.x; i < nv * half; i += blockDim.x) {
+      const int v = i >> (logN - 1), r = i & (half - 1);
+      const int p = r >> st, q = r & (s - 1);
+      cd w = tw[p * s];
+      if (fwd) w.y = -w.y;
+      const cd* x = X + v * N;
+      cd* y = Y + v * N;
+      const cd a = x[q + s * p], b = x[q + s * (p + m)];
+      y[q + 2 * s * p] = cadd(a, b);
+      y[q + 2 * s * p + s] = cmul(csub(a, b), w);
+    }
+    __syncthreads();
+    cd* t = X;
+    X = Y;
+    Y = t;
+  }
+  return X;
+}
+
+// L(kappa) of fibre blockIdx.x for the two row components 2 blockIdx.y and
+// 2 blockIdx.y + 1, written with the identity added as the blocks of P:
+// pfwd[fibre][kappa][B11, B12, B21, B22].
+__global__ void __launch_bounds__(PC_THREADS) k_pc_lambda(const cd* __restrict__ circ, const cd* __restrict__ tw,
+                                                           int N, int logN, cd* __restrict__ pfwd) {
+  extern __shared__ cd pcs[];
+  const int f = blockIdx.x, h = blockIdx.y;
+  cd* X = pcs;
+  cd* Y = pcs + 2 * N;
+  const cd* row = circ + (size_t)f * 8 * N;
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+    const int j = i >> logN, d = i & (N - 1);
+    X[i] = row[(2 * h + j) * 2 * N + d];
+  }
+  __syncthreads();
+  const cd* L = pc_fft(X, Y, 2, N, logN, tw, false);
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+    const int j = i >> logN, kk = i & (N - 1);
+    cd v = L[i];
+    if (j == h) v.x += 1.0;            // components B11 (h = 0, j = 0) and B22 (h = 1, j = 1)
+    pfwd[((size_t)f * N + kk) * 4 + 2 * h + j] = v;
+  }
+}
+
+// per (fibre, mode): P^{-1} block = adj(P block) / det
+__global__ void k_pc_invert(const cd* __restrict__ pfwd, cd* __restrict__ pinv, long long n_modes) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_modes) return;
+  const cd a = pfwd[4 * i], b = pfwd[4 * i + 1], c = pfwd[4 * i + 2], d = pfwd[4 * i + 3];
+  const cd idet = cdiv(mkc(1.0, 0.0), csub(cmul(a, d), cmul(b, c)));
+  pinv[4 * i] = cmul(d, idet);
+  pinv[4 * i + 1] = cmul(cscale(b, -1.0), idet);
+  pinv[4 * i + 2] = cmul(cscale(c, -1.0), idet);
+  pinv[4 * i + 3] = cmul(a, idet);
+}
+
+// out = blockdiag(P_f) in or blockdiag(P_f^{-1}) in, one workgroup per fibre;
+// in and out may alias (a workgroup reads its fibre whole before writing).
+__global__ void __launch_bounds__(PC_THREADS) k_pc_apply(const cd* in, cd* out, const cd* __restrict__ coef,
+                                                          const cd* __restrict__ tw, int N, int logN) {
+  extern __shared__ cd pcs[];
+  const int f = blockIdx.x;
+  cd* X = pcs;
+  cd* Y = pcs + 2 * N;
+  const cd* src = in + (size_t)f * 2 * N;        // phi_f then varphi_f
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  __syncthreads();
+  cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
+  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    const cd u = H[kk], v = H[N + kk];
+    H[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
+    H[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+  }
+  __syncthreads();
+  const cd* Z = pc_fft(H, H == X ? Y : X, 2, N, logN, tw, false);
+  const double sc = 1.0 / N;
+  cd* dst = out + (size_t)f * 2 * N;
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) dst[i] = cscale(Z[i], sc);
+}
+
+hipError_t launch_precond_setup(Problem& pb) {
+  const int N = pb.N;
+  const size_t lds = 4 * (size_t)N * sizeof(cd);
+  hipLaunchKernelGGL(k_pc_lambda, dim3(pb.M, 2), dim3(PC_THREADS), lds, pb.stream, pb.d_circ, pb.d_pc_tw, N,
+                     pb.pc_logN, pb.d_pc_fwd);
+  const long long nm = (long long)pb.M * N;
+  hipLaunchKernelGGL(k_pc_invert, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, pb.stream, pb.d_pc_fwd,
+                     pb.d_pc_inv, nm);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse) {
+  const int N = pb.N;
+  const size_t lds = 4 * (size_t)N * sizeof(cd);
+  hipLaunchKernelGGL(k_pc_apply, dim3(pb.M), dim3(PC_THREADS), lds, pb.stream, in, out,
+                     inverse ? pb.d_pc_inv : pb.d_pc_fwd, pb.d_pc_tw, N, pb.pc_logN);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
                 ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
-                ("direct_lattice_m2l", ctypes.c_int)]
+                ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -76,7 +76,7 @@ MIXED = 1
 MAX_BATCH = 16
 
 EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_matvec_mixed", "pfm_rhs", "pfm_solve",
-           "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
+           "pfm_precond_apply", "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
            "pfm_matvec_batch_timed",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
@@ -107,6 +107,7 @@ def lib():
     L.pfm_matvec_batch_timed.argtypes = [P, vp, vp, ctypes.c_int, dp, dp]
     L.pfm_rhs.argtypes = [P, vp]
     L.pfm_solve.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
+    L.pfm_precond_apply.argtypes = [P, vp, vp, ctypes.c_int]
     L.pfm_fields.argtypes = [P, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double)]
@@ -156,7 +157,7 @@ class Problem:
                  wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
-                 direct_lattice_m2l: bool = False):
+                 direct_lattice_m2l: bool = False, precond: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -168,7 +169,7 @@ class Problem:
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
                       max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
-                      1 if direct_lattice_m2l else 0)
+                      1 if direct_lattice_m2l else 0, 1 if precond else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
@@ -257,6 +258,14 @@ class Problem:
         return x, {"status": info.status, "iters": info.iters, "matvecs": info.matvecs,
                    "rel_residual": info.rel_residual, "t_solve_s": info.t_solve_s, "outer": info.outer,
                    "fallback": info.fallback, "matvecs_mixed": info.matvecs_mixed}
+
+    def precond_apply(self, x, inverse: bool = True, out=None):
+        """P^{-1} x (inverse) or P x, P the fibres' free-space self blocks."""
+        if x.numel() != self.n:
+            raise ValueError("x has the wrong length")
+        y = self.empty() if out is None else out
+        self._check(self._L.pfm_precond_apply(self._h, _ptr(x), _ptr(y), 1 if inverse else 0))
+        return y
 
     def fields(self, psi, n_orders: int = 10):
         no = 2 * n_orders + 1

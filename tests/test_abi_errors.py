@@ -18,7 +18,7 @@ def _create(**over):
     m = dict(rho_fiber=13500.0, c_fiber=1450.0, rho_matrix=1000.0, c_matrix=1490.0, eta=0.0)
     o = dict(p=16, leaf_max=32, mac=0.65, g_far=4, restart=50, max_iter=100, tol=1e-8, wood_margin=0.0,
              precision=0, inner_tol=0.0, max_batch=0, use_graph=0, p2p_blocks_per_cu=0, p2p_unroll=0,
-             store_self_blocks=0, p2p_cached_rows=0, direct_lattice_m2l=0)
+             store_self_blocks=0, p2p_cached_rows=0, direct_lattice_m2l=0, precond=0)
     for k, v in over.items():
         for d in (g, m, o):
             if k in d:
@@ -39,6 +39,7 @@ def _create(**over):
     dict(n_elem=4), dict(M_L=0), dict(r0=0.5), dict(r0=-0.1), dict(lattice=2), dict(a=0.0),
     dict(g_far=0), dict(restart=0), dict(tol=0.0), dict(rho_fiber=-1.0), dict(precision=2), dict(max_batch=17), dict(use_graph=2),
     dict(p2p_blocks_per_cu=9), dict(p2p_unroll=3), dict(store_self_blocks=2), dict(p2p_cached_rows=2), dict(direct_lattice_m2l=2),
+    dict(precond=2), dict(precond=1, n_elem=48), dict(precond=1, n_elem=1024), dict(precond=1, precision=1),
 ])
 def test_create_rejects_invalid_arguments(bad):
     code, msg = _create(**bad)
@@ -58,3 +59,4 @@ def test_null_arguments():
     assert L.pfm_rhs_batch(None, None) == 1
     assert L.pfm_solve_batch(None, None, None, 0, None) == 1
     assert L.pfm_sweep(None, 0, None, 1, None, None, None) == 1
+    assert L.pfm_precond_apply(None, None, None, 1) == 1

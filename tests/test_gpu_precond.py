@@ -1,0 +1,154 @@
+"""GPU parity of the block-Jacobi preconditioner (options.precond = 1).
+
+Each fibre's block is its free-space self block of (I - A) (the solver of
+Sec. 4 is a preconditioned GMRES).  The GPU inverts it per Fourier mode of the
+element index from the circulant rows; the oracle builds the dense blocks and
+solves with them.  Checked: P x and P^{-1} x against the oracle, the solve
+against the dense LU solution, start vectors, and at full size the solution
+and iteration count against the unpreconditioned solve.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10863_amd import pfm as m
+    m.lib()
+    return m
+
+
+_WL = {
+    "tiny": (W.tiny(), 2.0, math.pi / 4),
+    "sq2x2": (W.small_square(2, 2, 64, 0.3, 2.0, math.pi / 6), 2.0, math.pi / 6),
+    "hex2x2": (W.small_square(2, 2, 64, 0.3, 3.0, 0.3, lattice=W.HEXAGON), 3.0, 0.3),
+    "sq2x2close": (W.small_square(2, 2, 64, 0.45, 2.0, 0.4), 2.0, 0.4),
+    "sq2x1n8": (W.small_square(2, 1, 8, 0.3, 1.5, 0.4, p=8, leaf_max=4), 1.5, 0.4),
+}
+
+
+@functools.lru_cache(maxsize=8)
+def _oracle(key):
+    from oracle import system as sy
+    wl, ka, th = _WL[key]
+    pb = sy.problem_from_workload(wl, ka, th)
+    return pb, sy.fibre_self_blocks(pb)
+
+
+def _gpu(pfm, key, p=24, leaf=16, **kw):
+    wl, ka, th = _WL[key]
+    prob = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, precond=True, **kw)
+    prob.set_wave(ka, th)
+    return prob
+
+
+@pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2", "sq2x2close", "sq2x1n8"])
+def test_precond_apply_vs_oracle(pfm, key):
+    from oracle import system as sy
+    pb, blk = _oracle(key)
+    _say("precond apply:", key, "N =", pb.bd.N, "M =", pb.bd.M)
+    prob = _gpu(pfm, key, leaf=16 if key != "sq2x1n8" else 4)
+    x = W.random_density(pb.n, 31)
+    xd = torch.tensor(x, device="cuda")
+    yf = prob.precond_apply(xd, inverse=False).cpu().numpy()
+    yi = prob.precond_apply(xd, inverse=True).cpu().numpy()
+    rf = sy.precond_apply(pb, x, inverse=False, blocks=blk)
+    ri = sy.precond_apply(pb, x, inverse=True, blocks=blk)
+    ef = np.linalg.norm(yf - rf) / np.linalg.norm(rf)
+    ei = np.linalg.norm(yi - ri) / np.linalg.norm(ri)
+    _say("  rel err P x", ef, "P^-1 x", ei)
+    assert ef < 1e-10
+    assert ei < 1e-9
+    # in place, and the round trip
+    zd = xd.clone()
+    prob.precond_apply(zd, inverse=True, out=zd)
+    assert torch.equal(zd, torch.tensor(yi, device="cuda"))
+    back = prob.precond_apply(zd, inverse=False).cpu().numpy()
+    assert np.linalg.norm(back - x) < 1e-11 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("key", ["sq2x2", "hex2x2"])
+def test_precond_solve_vs_dense_lu(pfm, key):
+    from oracle import system as sy
+    wl, ka, th = _WL[key]
+    pb = sy.problem_from_workload(wl, ka, th)
+    A = sy.dense_matrix(pb)
+    ref = np.linalg.solve(A, sy.rhs(pb))
+    iters = {}
+    for pc in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=40, leaf_max=16, tol=1e-12, restart=100, precond=pc)
+        prob.set_wave(ka, th)
+        x, info = prob.solve()
+        err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+        _say("solve:", key, "precond", pc, info, "rel err vs LU", err)
+        assert info["status"] == 0
+        assert info["rel_residual"] <= 1e-12
+        assert err < 1e-8
+        iters[pc] = info["iters"]
+    assert iters[True] <= iters[False]
+
+
+def test_precond_start_vectors(pfm):
+    prob = _gpu(pfm, "sq2x2", p=40, tol=1e-10)
+    x, info = prob.solve()
+    assert info["status"] == 0
+    for mode in ("x0", "fallback"):
+        x2, info2 = prob.solve(x0=x, fallback=(mode == "fallback"))
+        _say("start vector", mode, info2)
+        assert info2["status"] == 0 and info2["iters"] <= 1 and info2["fallback"] == 0
+        assert torch.allclose(x2, x, rtol=0, atol=1e-8 * float(x.abs().max()))
+
+
+def test_precond_state_errors(pfm):
+    wl, ka, th = _WL["sq2x2"]
+    plain = pfm.Problem.from_workload(wl, p=16, leaf_max=16)
+    plain.set_wave(ka, th)
+    v = plain.empty()
+    with pytest.raises(pfm.PfmError):
+        plain.precond_apply(v)
+    prob = pfm.Problem.from_workload(wl, p=16, leaf_max=16, precond=True)
+    with pytest.raises(pfm.PfmError):
+        prob.precond_apply(v)                # no wave yet
+
+
+def test_precond_square_8x8_full_size(pfm):
+    """The 8x8 block (N = 512) at a mid-band frequency: the preconditioned
+    solve meets the tolerance on the true residual of the unpreconditioned
+    operator, agrees with the plain solve, and takes fewer iterations."""
+    wl = W.square_8x8()
+    ka = wl.ka[len(wl.ka) // 2]
+    res, probs = {}, {}
+    for pc in (False, True):
+        prob = pfm.Problem.from_workload(wl, precond=pc)
+        prob.set_wave(ka, 0.0)
+        x, info = prob.solve()
+        _say("8x8 ka", ka, "precond", pc, info)
+        assert info["status"] == 0 and info["rel_residual"] <= wl.tol
+        res[pc] = (x, info["iters"])
+        probs[pc] = prob
+    plain = probs[False]
+    b = plain.rhs()
+    r = b - plain.matvec(res[True][0])
+    rel = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+    d = float(torch.linalg.vector_norm(res[True][0] - res[False][0]) / torch.linalg.vector_norm(res[False][0]))
+    _say("  true residual of the preconditioned solution", rel, "difference to the plain solution", d)
+    assert rel <= 1.05 * wl.tol
+    assert d < 1e-5
+    assert res[True][1] < res[False][1]

@@ -182,3 +182,51 @@ def test_free_space_self_blocks_are_circulant():
     e0 = np.arange(N)
     d = Ap[np.ix_(sy.col_phi(bd, e0), sy.col_phi(bd, e0))] - A[np.ix_(sy.col_phi(bd, e0), sy.col_phi(bd, e0))]
     assert np.max(np.abs(d[1:, 1:] - d[:-1, :-1])) > 1e-6
+
+
+def test_fibre_self_blocks_are_the_free_space_diagonal():
+    """The preconditioner blocks are the diagonal fibre blocks of the
+    free-space system: for one fibre the whole free-space matrix, for two
+    fibres the diagonal blocks of theirs (the cross-fibre blocks left out),
+    the same at every angle, and different from the periodic system's
+    diagonal blocks, which carry the images."""
+    wl1 = W.small_square(1, 1, 32, r=0.3)
+    pb1 = sy.problem_from_workload(wl1, 2.5, 0.4, periodic=False)
+    blk1 = sy.fibre_self_blocks(sy.problem_from_workload(wl1, 2.5, 0.4))
+    assert np.max(np.abs(blk1[0] - sy.dense_matrix(pb1))) == 0.0
+    wl = W.small_square(2, 1, 32, radii=np.array([0.3, 0.22]))
+    pb = sy.problem_from_workload(wl, 2.5, 0.4)
+    blk = sy.fibre_self_blocks(pb)
+    Af = sy.dense_matrix(sy.problem_from_workload(wl, 2.5, 0.4, periodic=False))
+    Ap = sy.dense_matrix(pb)
+    N = wl.n_elem
+    for f in range(2):
+        seg = slice(2 * f * N, 2 * f * N + 2 * N)
+        assert np.max(np.abs(blk[f] - Af[seg, seg])) == 0.0
+        assert np.max(np.abs(blk[f] - Ap[seg, seg])) > 1e-6
+    assert np.max(np.abs(Af[0:2 * N, 2 * N:4 * N])) > 1e-3      # the left-out coupling is real
+    blk_th = sy.fibre_self_blocks(sy.problem_from_workload(wl, 2.5, 1.1))
+    assert np.max(np.abs(blk_th - blk)) == 0.0
+    x = W.random_density(4 * N, 5)
+    y = sy.precond_apply(pb, x, inverse=True, blocks=blk)
+    assert np.linalg.norm(sy.precond_apply(pb, y, inverse=False, blocks=blk) - x) < 1e-12 * np.linalg.norm(x)
+
+
+def test_fibre_self_block_is_diagonalised_by_the_dft():
+    """Block-circulant structure, checked with numpy's FFT: with R(d) the 2x2
+    block of element 0 with element d (identity removed) and
+    L(kappa) = sum_d R(d) w^{kappa d}, w = exp(2 pi i / N), the block maps x
+    to the inverse DFT of (I + L(kappa)) xhat(kappa)."""
+    wl = W.small_square(1, 1, 32, r=0.35)
+    pb = sy.problem_from_workload(wl, 3.0, 0.2)
+    P = sy.fibre_self_blocks(pb)[0]
+    N = wl.n_elem
+    R = np.stack([[P[0, :N], P[0, N:]], [P[N, :N], P[N, N:]]])      # [2, 2, N] over source offset d
+    R[0, 0, 0] -= 1.0
+    R[1, 1, 0] -= 1.0
+    L = np.fft.ifft(R, axis=-1) * N                                   # sum_d R(d) w^{+kappa d}
+    x = W.random_density(2 * N, 9)
+    xh = np.stack([np.fft.fft(x[:N]), np.fft.fft(x[N:])])
+    yh = xh + np.einsum("ijk,jk->ik", L, xh)
+    y = np.concatenate([np.fft.ifft(yh[0]), np.fft.ifft(yh[1])])
+    assert np.linalg.norm(y - P @ x) < 1e-12 * np.linalg.norm(P @ x)
