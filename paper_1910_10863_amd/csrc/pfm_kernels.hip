@@ -276,7 +276,7 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
 // The DFTs are radix-2 Stockham transforms in LDS (natural order in and
 // out, so no bit reversal), one workgroup per fibre.
 // ---------------------------------------------------------------------------
-constexpr int PC_THREADS = 256;
+constexpr int PC_THREADS = 512;
 
 // nv vectors of length N = 2^logN at X + v N, transformed with Y (same size)
 // as the other buffer of each stage; fwd: exponent -i (unscaled either way).
