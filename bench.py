@@ -158,6 +158,26 @@ def batched_sweep_leg(n_single_ka: int, tune: bool):
                       "failed": int(sum(i["status"] != 0 for i in flat)), "mean_iters": float(np.mean(it)),
                       "max_iters": int(np.max(it)), "max_rel_residual": float(max(i["rel_residual"] for i in flat))}
     print(f"batched sweep: {out['batched']}", file=sys.stderr, flush=True)
+    pb.close()
+    # the same batched sweep right-preconditioned by the fibres' free-space
+    # self blocks (shared by the angles of a frequency)
+    if wl.n_elem & (wl.n_elem - 1) == 0 and 8 <= wl.n_elem <= 512:
+        pbp = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, max_batch=len(th), use_graph=False, precond=True)
+        pbp.sweep(kas[:1], th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xp, infp = pbp.sweep(kas, th)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        flp = [i for row in infp for i in row]
+        itp = [i["iters"] for i in flp]
+        out["batched_precond"] = {"solves_per_s": len(flp) / dtp, "seconds": dtp, "n_solves": len(flp),
+                                  "failed": int(sum(i["status"] != 0 for i in flp)),
+                                  "mean_iters": float(np.mean(itp)), "max_iters": int(np.max(itp)),
+                                  "max_rel_residual": float(max(i["rel_residual"] for i in flp)),
+                                  "speedup_vs_batched": dt / dtp}
+        print(f"batched sweep, preconditioned: {out['batched_precond']}", file=sys.stderr, flush=True)
+        pbp.close()
     single = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf)
     sub = kas[::max(1, len(kas) // n_single_ka)][:n_single_ka]
     single.set_wave(sub[0], th[0])

@@ -131,8 +131,9 @@ typedef struct {
  *             is inverted per Fourier mode of the element index (one 2x2
  *             solve per mode, FFTs of length N per fibre).  The residual and
  *             the stop test are those of the unpreconditioned system.  Needs
- *             N a power of two, 8 <= N <= 512.  Batched solves and the
- *             augmented start (use_x0 = 3) do not use it. */
+ *             N a power of two, 8 <= N <= 512.  pfm_solve_batch and
+ *             pfm_sweep use it too (the blocks do not depend on theta, so a
+ *             batch shares them); the augmented start (use_x0 = 3) does not. */
 typedef struct {
   int p;
   int leaf_max;

@@ -542,7 +542,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     // the vector P^{-1} v of the preconditioned apply
     CK(hipMalloc((void**)&pb.d_pc_fwd, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
     CK(hipMalloc((void**)&pb.d_pc_inv, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
-    CK(hipMalloc((void**)&pb.d_pc_x, (size_t)2 * pb.E * sizeof(cd)));
+    CK(hipMalloc((void**)&pb.d_pc_x, (size_t)pb.max_batch * 2 * pb.E * sizeof(cd)));
     std::vector<cd> tw(pb.N);
     for (int j = 0; j < pb.N; ++j) {
       const double t = 2.0 * M_PI * j / pb.N;
@@ -936,6 +936,7 @@ pfm_status pfm_set_batch(pfm_problem* h, double ka, int B, const double* theta) 
   HIPCHK(pb, hipMemcpyAsync(pb.d_betas, betas.data(), B * sizeof(double), hipMemcpyHostToDevice, pb.stream));
   HIPCHK(pb, launch_lattice_sums(pb, B));
   HIPCHK(pb, launch_near_blocks(pb, true));
+  if (pb.opt.precond) HIPCHK(pb, launch_precond_setup(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   if (pb.opt.use_graph) {
     st = capture_batch_graph(pb);
@@ -1524,6 +1525,20 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
     HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, d_x_io, pb.B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
     s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, false, pb.opt.tol, pb.opt.max_iter, gs, st, nullptr,
                        pb.d_ir_aug);
+  } else if (pb.opt.precond) {
+    // right preconditioning as in pfm_solve; the members share P (it does not
+    // depend on the angle), and the preconditioner runs ahead of the
+    // (possibly graph-replayed) batched apply
+    cd* x = (cd*)d_x_io;
+    auto apply_pc = [&](const cd* in, cd* out) -> hipError_t {
+      hipError_t e = launch_precond(pb, in, pb.d_pc_x, true, pb.B);
+      if (e == hipSuccess) e = batch_apply(pb, pb.d_pc_x, out);
+      return e;
+    };
+    if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false, pb.B));
+    s = gmres_lockstep(pb, pb.B, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
+                       use_x0 == 2 ? &fb : nullptr);
+    HIPCHK(pb, launch_precond(pb, x, x, true, pb.B));
   } else {
     s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
                        use_x0 == 2 ? &fb : nullptr);

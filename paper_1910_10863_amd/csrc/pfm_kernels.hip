@@ -341,15 +341,18 @@ __global__ void k_pc_invert(const cd* __restrict__ pfwd, cd* __restrict__ pinv, 
   pinv[4 * i + 3] = cmul(a, idet);
 }
 
-// out = blockdiag(P_f) in or blockdiag(P_f^{-1}) in, one workgroup per fibre;
-// in and out may alias (a workgroup reads its fibre whole before writing).
+// out = blockdiag(P_f) in or blockdiag(P_f^{-1}) in, one workgroup per
+// (fibre, batch member): the blocks do not depend on the angle, so the
+// members of a batch share them; in and out may alias (a workgroup reads its
+// fibre whole before writing).
 __global__ void __launch_bounds__(PC_THREADS) k_pc_apply(const cd* in, cd* out, const cd* __restrict__ coef,
                                                           const cd* __restrict__ tw, int N, int logN) {
   extern __shared__ cd pcs[];
   const int f = blockIdx.x;
+  const size_t mem = (size_t)blockIdx.y * gridDim.x * 2 * N;   // member offset: 2 M N
   cd* X = pcs;
   cd* Y = pcs + 2 * N;
-  const cd* src = in + (size_t)f * 2 * N;        // phi_f then varphi_f
+  const cd* src = in + mem + (size_t)f * 2 * N;  // phi_f then varphi_f
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
   __syncthreads();
   cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
@@ -362,7 +365,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_pc_apply(const cd* in, cd* out, 
   __syncthreads();
   const cd* Z = pc_fft(H, H == X ? Y : X, 2, N, logN, tw, false);
   const double sc = 1.0 / N;
-  cd* dst = out + (size_t)f * 2 * N;
+  cd* dst = out + mem + (size_t)f * 2 * N;
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) dst[i] = cscale(Z[i], sc);
 }
 
@@ -377,10 +380,10 @@ hipError_t launch_precond_setup(Problem& pb) {
   return hipGetLastError();
 }
 
-hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse) {
+hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B) {
   const int N = pb.N;
   const size_t lds = 4 * (size_t)N * sizeof(cd);
-  hipLaunchKernelGGL(k_pc_apply, dim3(pb.M), dim3(PC_THREADS), lds, pb.stream, in, out,
+  hipLaunchKernelGGL(k_pc_apply, dim3(pb.M, std::max(1, B)), dim3(PC_THREADS), lds, pb.stream, in, out,
                      inverse ? pb.d_pc_inv : pb.d_pc_fwd, pb.d_pc_tw, N, pb.pc_logN);
   return hipGetLastError();
 }

@@ -13,9 +13,9 @@ hipError_t launch_lattice_sums(Problem& pb, int B);
 // near blocks; phase_free: image phases left out (applied per member by the batched P2P)
 hipError_t launch_near_blocks(Problem& pb, bool phase_free);
 // per-fibre block preconditioner: coefficients from the circulant rows, and
-// out = P^{-1} in (inverse) or P in
+// out = P^{-1} in (inverse) or P in, for B stacked vectors of 2 M N
 hipError_t launch_precond_setup(Problem& pb);
-hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse);
+hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B = 1);
 hipError_t launch_rhs(Problem& pb, double theta, cd* d_b);
 hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out);
 hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream_t s);

@@ -152,3 +152,42 @@ def test_precond_square_8x8_full_size(pfm):
     assert rel <= 1.05 * wl.tol
     assert d < 1e-5
     assert res[True][1] < res[False][1]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_precond_batch_solve_vs_dense_lu(pfm, use_graph):
+    """Batched solves share P across the angles of a frequency (the blocks
+    have no image and so no theta); each member against dense LU, in no more
+    iterations than the plain batched solve."""
+    from oracle import system as sy
+    wl, ka, _ = _WL["sq2x2"]
+    thetas = [0.1, 0.5, 0.9]
+    res = {}
+    for pc in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=40, leaf_max=16, tol=1e-12, restart=100, max_batch=4,
+                                         use_graph=use_graph, precond=pc)
+        prob.set_batch(ka, thetas)
+        res[pc] = prob.solve_batch()
+        _say("batch solve graph", use_graph, "precond", pc, [i["iters"] for i in res[pc][1]])
+    x = res[True][0].cpu().numpy()
+    for i, th in enumerate(thetas):
+        pb = sy.problem_from_workload(wl, ka, th)
+        ref = np.linalg.solve(sy.dense_matrix(pb), sy.rhs(pb))
+        err = np.linalg.norm(x[i] - ref) / np.linalg.norm(ref)
+        _say("  member", i, "rel err vs LU", err)
+        assert res[True][1][i]["status"] == 0 and res[True][1][i]["rel_residual"] <= 1e-12
+        assert err < 1e-8
+        assert res[True][1][i]["iters"] <= res[False][1][i]["iters"]
+
+
+def test_precond_sweep_equals_batch_solves(pfm):
+    wl, _, _ = _WL["sq2x2"]
+    kas, thetas = [1.5, 2.5], [0.2, 0.7]
+    prob = pfm.Problem.from_workload(wl, p=24, leaf_max=16, tol=1e-10, max_batch=2, precond=True)
+    xs, infos = prob.sweep(kas, thetas)
+    for i, ka in enumerate(kas):
+        prob.set_batch(ka, thetas)
+        x, inf = prob.solve_batch()
+        _say("sweep ka", ka, [d["iters"] for d in infos[i]], [d["iters"] for d in inf])
+        assert all(d["status"] == 0 for d in infos[i])
+        assert torch.equal(xs[i], x)
