@@ -124,7 +124,8 @@ typedef struct {
  *             lattice, on the parities of the two columns), by zero-padded 2D
  *             DFTs: (2 M_L)(2 M_H) Toeplitz products per sublattice pair
  *             instead of M^2; 1: every root pair is an M2L entry.
- *  precond    0: plain GMRES; 1: pfm_solve (precision PFM_FP64) runs GMRES
+ *  precond    0: plain GMRES; 1: pfm_solve runs GMRES (with PFM_MIXED the
+ *             inner GMRES of the refinement)
  *             right-preconditioned by the fibres' free-space self blocks of
  *             (I - A) (the block-Jacobi preconditioner of the paper's
  *             "preconditioned GMRES", Sec. 4): each is block circulant, so it

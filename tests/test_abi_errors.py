@@ -39,7 +39,7 @@ def _create(**over):
     dict(n_elem=4), dict(M_L=0), dict(r0=0.5), dict(r0=-0.1), dict(lattice=2), dict(a=0.0),
     dict(g_far=0), dict(restart=0), dict(tol=0.0), dict(rho_fiber=-1.0), dict(precision=2), dict(max_batch=17), dict(use_graph=2),
     dict(p2p_blocks_per_cu=9), dict(p2p_unroll=3), dict(store_self_blocks=2), dict(p2p_cached_rows=2), dict(direct_lattice_m2l=2),
-    dict(precond=2), dict(precond=1, n_elem=48), dict(precond=1, n_elem=1024), dict(precond=1, precision=1),
+    dict(precond=2), dict(precond=1, n_elem=48), dict(precond=1, n_elem=1024),
 ])
 def test_create_rejects_invalid_arguments(bad):
     code, msg = _create(**bad)

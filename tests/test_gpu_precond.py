@@ -191,3 +191,32 @@ def test_precond_sweep_equals_batch_solves(pfm):
         _say("sweep ka", ka, [d["iters"] for d in infos[i]], [d["iters"] for d in inf])
         assert all(d["status"] == 0 for d in infos[i])
         assert torch.equal(xs[i], x)
+
+
+@pytest.mark.parametrize("key", ["sq2x2", "hex2x2"])
+def test_precond_mixed_solve_vs_dense_lu(pfm, key):
+    """Mixed precision: the inner GMRES of the FP64 refinement runs
+    right-preconditioned; the refined solution against the dense operator and
+    dense LU, with complex64 applies used and no more iterations than the
+    unpreconditioned mixed solve."""
+    from oracle import system as sy
+    wl, ka, th = _WL[key]
+    pb = sy.problem_from_workload(wl, ka, th)
+    A, B = sy.dense_matrix(pb), sy.rhs(pb)
+    ref = np.linalg.solve(A, B)
+    iters = {}
+    for pc in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=40, leaf_max=16, tol=1e-12, restart=100, precision=pfm.MIXED,
+                                         store_self_blocks=True, precond=pc)
+        prob.set_wave(ka, th)
+        x, info = prob.solve()
+        xs = x.cpu().numpy()
+        res = np.linalg.norm(B - A @ xs) / np.linalg.norm(B)
+        err = np.linalg.norm(xs - ref) / np.linalg.norm(ref)
+        _say("mixed solve:", key, "precond", pc, info, "dense residual", res, "rel err vs LU", err)
+        assert info["status"] == 0 and info["outer"] >= 1
+        assert 0 < info["matvecs_mixed"] < info["matvecs"]
+        assert res < 1e-10
+        assert err < 1e-8
+        iters[pc] = info["iters"]
+    assert iters[True] <= iters[False]
