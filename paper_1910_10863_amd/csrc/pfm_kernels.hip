@@ -273,29 +273,56 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
 // I + L(kappa), L(kappa) = sum_d R(d) w^{kappa d}.  With the forward DFT
 // xhat(kappa) = sum_b x_b w^{-kappa b}, P x is the inverse DFT of
 // (I + L(kappa)) xhat(kappa) and P^{-1} x that of (I + L(kappa))^{-1} xhat.
-// The DFTs are radix-2 Stockham transforms in LDS (natural order in and
-// out, so no bit reversal), one workgroup per fibre.
+// The DFTs are Stockham transforms in LDS (radix 4, plus one radix-2 stage
+// when log2 N is odd; natural order in and out, so no bit reversal), one
+// workgroup per fibre.
 // ---------------------------------------------------------------------------
 constexpr int PC_THREADS = 512;
 
 // nv vectors of length N = 2^logN at X + v N, transformed with Y (same size)
 // as the other buffer of each stage; fwd: exponent -i (unscaled either way).
-// Stage st splits each remaining sub-sequence of length N / 2^st into its
-// sum and twiddled difference halves.  Returns the buffer with the result.
+// Radix-4 stages: each splits every remaining sub-sequence of length n into
+// four interleaved quarters (a 4-point DFT and the twiddles w^{j p s},
+// j = 1..3), then one radix-2 stage when log2 N is odd.  Returns the buffer
+// with the result.
 __device__ cd* pc_fft(cd* X, cd* Y, int nv, int N, int logN, const cd* __restrict__ tw, bool fwd) {
-  const int half = N >> 1;
-  for (int st = 0; st < logN; ++st) {
-    const int s = 1 << st, m = half >> st;
-    for (int i = threadIdx.x; i < nv * half; i += blockDim.x) {
-      const int v = i >> (logN - 1), r = i & (half - 1);
-      const int p = r >> st, q = r & (s - 1);
-      cd w = tw[p * s];
-      if (fwd) w.y = -w.y;
+  const int quarter = N >> 2;
+  int lg = 0;
+  for (; lg + 2 <= logN; lg += 2) {
+    const int s = 1 << lg, m = quarter >> lg;
+    for (int i = threadIdx.x; i < nv * quarter; i += blockDim.x) {
+      const int v = i >> (logN - 2), r = i & (quarter - 1);
+      const int p = r >> lg, q = r & (s - 1);
+      cd w1 = tw[p * s], w2 = tw[2 * p * s], w3 = tw[3 * p * s];
+      if (fwd) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+        w3.y = -w3.y;
+      }
       const cd* x = X + v * N;
       cd* y = Y + v * N;
-      const cd a = x[q + s * p], b = x[q + s * (p + m)];
-      y[q + 2 * s * p] = cadd(a, b);
-      y[q + 2 * s * p + s] = cmul(csub(a, b), w);
+      const cd a0 = x[q + s * p], a1 = x[q + s * (p + m)], a2 = x[q + s * (p + 2 * m)], a3 = x[q + s * (p + 3 * m)];
+      const cd b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3), d = csub(a1, a3);
+      const cd b3 = fwd ? mkc(d.y, -d.x) : mkc(-d.y, d.x);     // -i d (forward) or +i d
+      y[q + 4 * s * p] = cadd(b0, b2);
+      y[q + 4 * s * p + s] = cmul(cadd(b1, b3), w1);
+      y[q + 4 * s * p + 2 * s] = cmul(csub(b0, b2), w2);
+      y[q + 4 * s * p + 3 * s] = cmul(csub(b1, b3), w3);
+    }
+    __syncthreads();
+    cd* t = X;
+    X = Y;
+    Y = t;
+  }
+  if (lg < logN) {                     // the last radix-2 stage (stride N / 2, no twiddle)
+    const int half = N >> 1;
+    for (int i = threadIdx.x; i < nv * half; i += blockDim.x) {
+      const int v = i >> (logN - 1), q = i & (half - 1);
+      const cd* x = X + v * N;
+      cd* y = Y + v * N;
+      const cd a = x[q], b = x[q + half];
+      y[q] = cadd(a, b);
+      y[q + half] = csub(a, b);
     }
     __syncthreads();
     cd* t = X;
