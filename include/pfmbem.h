@@ -134,7 +134,8 @@ typedef struct {
  *             the stop test are those of the unpreconditioned system.  Needs
  *             N a power of two, 8 <= N <= 512.  pfm_solve_batch and
  *             pfm_sweep use it too (the blocks do not depend on theta, so a
- *             batch shares them); the augmented start (use_x0 = 3) does not. */
+ *             batch shares them), as do start vectors and the augmented
+ *             start (use_x0 = 3), whose guess u enters as P u. */
 typedef struct {
   int p;
   int leaf_max;

@@ -1466,22 +1466,30 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
     std::vector<GmresStats> g1;
     std::vector<pfm_status> s1;
     std::vector<int> fb(1, 0);
-    if (use_x0 == 3) {
-      HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, x, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-      st = gmres_lockstep(pb, 1, apply64, b, x, false, pb.opt.tol, pb.opt.max_iter, g1, s1, nullptr, pb.d_ir_aug);
-    } else if (pb.opt.precond) {
+    if (pb.opt.precond) {
       // right preconditioning: GMRES for (I - A) P^{-1} z = B, then Psi = P^{-1} z;
       // the residual B - (I - A) P^{-1} z is that of Psi, so the stop test and
-      // the reported residual are those of the unpreconditioned system
+      // the reported residual are those of the unpreconditioned system.  A
+      // start vector or an augmenting guess u enters as P u, since
+      // (I - A) P^{-1} (P u) = (I - A) u.
       auto apply_pc = [&](const cd* in, cd* out) -> hipError_t {
         hipError_t e = launch_precond(pb, in, pb.d_pc_x, true);
         if (e == hipSuccess) e = apply_operator(pb, pb.d_pc_x, out, nullptr);
         return e;
       };
-      if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false));     // z0 = P Psi0
-      st = gmres_lockstep(pb, 1, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
-                          use_x0 == 2 ? &fb : nullptr);
+      if (use_x0 == 3) {
+        HIPCHK(pb, launch_precond(pb, x, pb.d_ir_aug, false));
+        st = gmres_lockstep(pb, 1, apply_pc, b, x, false, pb.opt.tol, pb.opt.max_iter, g1, s1, nullptr,
+                            pb.d_ir_aug);
+      } else {
+        if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false));     // z0 = P Psi0
+        st = gmres_lockstep(pb, 1, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
+                            use_x0 == 2 ? &fb : nullptr);
+      }
       HIPCHK(pb, launch_precond(pb, x, x, true));
+    } else if (use_x0 == 3) {
+      HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, x, n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+      st = gmres_lockstep(pb, 1, apply64, b, x, false, pb.opt.tol, pb.opt.max_iter, g1, s1, nullptr, pb.d_ir_aug);
     } else {
       st = gmres_lockstep(pb, 1, apply64, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, g1, s1,
                           use_x0 == 2 ? &fb : nullptr);
@@ -1530,11 +1538,7 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
   auto apply = [&](const cd* in, cd* out) { return batch_apply(pb, in, out); };
   std::vector<int> fb(pb.B, 0);
   pfm_status s;
-  if (use_x0 == 3) {
-    HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, d_x_io, pb.B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
-    s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, false, pb.opt.tol, pb.opt.max_iter, gs, st, nullptr,
-                       pb.d_ir_aug);
-  } else if (pb.opt.precond) {
+  if (pb.opt.precond) {
     // right preconditioning as in pfm_solve; the members share P (it does not
     // depend on the angle), and the preconditioner runs ahead of the
     // (possibly graph-replayed) batched apply
@@ -1544,10 +1548,20 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
       if (e == hipSuccess) e = batch_apply(pb, pb.d_pc_x, out);
       return e;
     };
-    if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false, pb.B));
-    s = gmres_lockstep(pb, pb.B, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
-                       use_x0 == 2 ? &fb : nullptr);
+    if (use_x0 == 3) {
+      HIPCHK(pb, launch_precond(pb, x, pb.d_ir_aug, false, pb.B));
+      s = gmres_lockstep(pb, pb.B, apply_pc, b, x, false, pb.opt.tol, pb.opt.max_iter, gs, st, nullptr,
+                         pb.d_ir_aug);
+    } else {
+      if (use_x0) HIPCHK(pb, launch_precond(pb, x, x, false, pb.B));
+      s = gmres_lockstep(pb, pb.B, apply_pc, b, x, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
+                         use_x0 == 2 ? &fb : nullptr);
+    }
     HIPCHK(pb, launch_precond(pb, x, x, true, pb.B));
+  } else if (use_x0 == 3) {
+    HIPCHK(pb, hipMemcpyAsync(pb.d_ir_aug, d_x_io, pb.B * n * sizeof(cd), hipMemcpyDeviceToDevice, pb.stream));
+    s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, false, pb.opt.tol, pb.opt.max_iter, gs, st, nullptr,
+                       pb.d_ir_aug);
   } else {
     s = gmres_lockstep(pb, pb.B, apply, b, (cd*)d_x_io, use_x0 != 0, pb.opt.tol, pb.opt.max_iter, gs, st,
                        use_x0 == 2 ? &fb : nullptr);
