@@ -222,11 +222,13 @@ def warm_start_leg(n_train_groups: int, n_eval_groups: int, epochs: int):
           file=sys.stderr, flush=True)
     ge, te = W.warm_start_groups(n_eval_groups, 8, 77)
     ev = warm.evaluate(net, ge, te, tols=(1e-8, 1e-4))
+    # the same draws at 1e-8 with the block-Jacobi preconditioner in all three
+    ev_pc = warm.evaluate(net, ge, te, tols=(1e-8,), precond=True)
     print(f"warm start: {ev}", file=sys.stderr, flush=True)
     return {"workload": "square_4x4_N256_warm", "network": list(warm.SIZES), "train_solves": int(data.x.shape[0]),
             "generate_seconds": data.seconds, "train_seconds": net.train_seconds, "epochs": epochs,
             "final_loss_standardised": net.losses[-1], "validation_rel_err": getattr(net, "val_rel_err", None),
-            "evaluation": ev}
+            "evaluation": ev, "evaluation_precond": ev_pc}
 
 
 def cpu_baseline(wl, ka, theta, n_targets):

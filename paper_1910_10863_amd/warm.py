@@ -288,12 +288,13 @@ def train(data: Dataset, epochs: int = 100, batch: int = 256, lr: float = 1e-3, 
 
 
 def evaluate(net: "MLP", groups: np.ndarray, thetas: np.ndarray, K: int = N_MODES, tols=(1e-8,),
-             log=None) -> Dict:
+             log=None, precond: bool = False) -> Dict:
     """Cold start against the BF16 prediction used two ways on the same draws:
     as the start vector (with fallback to zero) and as the augmentation of
-    the first GMRES cycle, at each GMRES tolerance in `tols`.  Returns, per
-    tolerance, iteration counts and times (inference included), and the
-    start residuals of the predictions."""
+    the first GMRES cycle, at each GMRES tolerance in `tols`, all three with
+    plain GMRES or (precond) GMRES right-preconditioned by the fibres'
+    free-space self blocks.  Returns, per tolerance, iteration counts and
+    times (inference included), and the start residuals of the predictions."""
     import torch
     out = {"tolerances": {}}
     r0 = []
@@ -304,7 +305,7 @@ def evaluate(net: "MLP", groups: np.ndarray, thetas: np.ndarray, K: int = N_MODE
         for g in range(groups.shape[0]):
             ka, r, rr, cr = (float(v) for v in groups[g])
             th = thetas[g]
-            prob = block_problem(r, rr, cr, th.size, tol=tol)
+            prob = block_problem(r, rr, cr, th.size, tol=tol, precond=precond)
             try:
                 prob.set_batch(ka, th)
             except pfm.PfmError as e:
