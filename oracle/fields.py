@@ -57,11 +57,20 @@ def energy_residual(pb: Problem, psi, n_orders: int = 20):
     return flux / (pb.k * math.cos(pb.theta)) - 1.0
 
 
+def etc_from_modes(k: float, H: float, L: float, n, kap, gam, T, n_pts: int = 512):
+    """ETC of Sec. 4 from the transmitted Bragg amplitudes T_n (orders n,
+    wavenumbers kap, gam): right of the block the total field is
+    sum_n (delta_n0 + T_n) e^{i(gam_n x1 + kap_n x2)}, so
+    du/dx1 (L, x2) = sum_n i gam_n (delta_n0 + T_n) e^{i(gam_n L + kap_n x2)};
+    its modulus is averaged over one period in x2 by the trapezoid rule
+    (spectrally accurate for the periodic integrand) and divided by k."""
+    x2 = np.arange(n_pts) * H / n_pts
+    t0 = np.asarray(T) + (np.asarray(n) == 0)
+    du = (1j * gam[:, None] * t0[:, None]
+          * np.exp(1j * (gam[:, None] * L + kap[:, None] * x2[None, :]))).sum(0)
+    return float(np.mean(np.abs(du)) * H / (k * H))
+
+
 def etc(pb: Problem, psi, n_orders: int = 30, n_pts: int = 512):
     n, kap, gam, R, T = bragg(pb, psi, n_orders)
-    bd = pb.bd
-    x2 = np.arange(n_pts) * bd.H / n_pts
-    t0 = T + (n == 0)
-    du = (1j * gam[:, None] * t0[:, None]
-          * np.exp(1j * (gam[:, None] * bd.L + kap[:, None] * x2[None, :]))).sum(0)
-    return float(np.mean(np.abs(du)) * bd.H / (pb.k * bd.H))
+    return etc_from_modes(pb.k, pb.bd.H, pb.bd.L, n, kap, gam, T, n_pts)
