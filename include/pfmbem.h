@@ -24,9 +24,10 @@
  *
  * Conventions: every pointer argument named d_* is DEVICE memory owned by
  * the caller (for example a torch tensor's data_ptr()); host arrays are
- * owned by the caller as well.  The library owns only what it allocates in
- * pfm_create / pfm_set_wave and frees it in pfm_destroy; pfm_matvec and
- * pfm_solve allocate nothing.  All work is queued on the stream given to
+ * owned by the caller as well.  The library allocates device memory only in
+ * pfm_create (plan metadata and, until the caller binds a block of its own
+ * with pfm_bind, the workspace) and frees it in pfm_destroy; no other call
+ * allocates.  All work is queued on the stream given to
  * pfm_set_stream (default: the null stream); calls that return host values
  * synchronise that stream.  Functions return PFM_OK or an error code; the
  * message of the last error of a handle is returned by pfm_last_error.
@@ -68,8 +69,19 @@ typedef enum { PFM_FP64 = 0, PFM_MIXED = 1 } pfm_precision;
 
 /* Fibre lattice (Sec. 2, Fig. 1).  Square: fibre (col i, row j) centred at
  * ((i+1/2)a, (j+1/2)a).  Hexagon: ((i+1/2)(sqrt3/2)a, (j+1/2+(i mod 2)/2)a).
- * Fibre index f = j*M_L + i.  radii: host array of M radii, or NULL to use r0
- * for every fibre.  Boundary nodes c_f + r_f (cos t_e, sin t_e), t_e = 2 pi e/N. */
+ * Fibre index f = j*M_L + i.  radii: host array of M size parameters r_f, or
+ * NULL to use r0 for every fibre.  Boundary nodes c_f + gamma(r_f, t_e),
+ * t_e = 2 pi e/N, counter-clockwise, with the curve gamma of `shape`:
+ *   PFM_CIRCLE        r (cos t, sin t)
+ *   PFM_ROUND_SQUARE  r ((3 + 2 sin^2 t) cos t, (3 + 2 cos^2 t) sin t), the
+ *                     round-square scatterer of Sec. 4 (area 23 pi r^2 / 2,
+ *                     farthest point 4 r from the centre, on the diagonals).
+ * Fibres may not touch: twice the farthest distance of the curve from its
+ * centre must stay below a.  Non-circular fibres keep every near pair as a
+ * stored block (their chords are not rotations of each other), so the
+ * circulant self rows, self_mode 0 and precond = 1 need PFM_CIRCLE. */
+typedef enum { PFM_CIRCLE = 0, PFM_ROUND_SQUARE = 1 } pfm_shape;
+
 typedef struct {
   int lattice;
   double a;
@@ -77,6 +89,7 @@ typedef struct {
   int n_elem;              /* N, elements per fibre, >= 8 */
   const double* radii;     /* host, M entries, or NULL */
   double r0;
+  int shape;               /* pfm_shape */
 } pfm_geometry;
 
 /* Materials: fibre (rho_1, c_1), matrix (rho_2, c_2).  eta is the real
@@ -124,6 +137,18 @@ typedef struct {
  *             lattice, on the parities of the two columns), by zero-padded 2D
  *             DFTs: (2 M_L)(2 M_H) Toeplitz products per sublattice pair
  *             instead of M^2; 1: every root pair is an M2L entry.
+ *  self_mode  how the pairs of a fibre with itself at image 0 (both
+ *             wavenumbers) are applied.  0 (auto): when every fibre is a circle
+ *             cut into N equal chords with N a power of two, 8 <= N <= 512, and
+ *             store_self_blocks = 0, that 2N x 2N block of each fibre is block
+ *             circulant (rotation by one chord maps element a to a + 1), so it
+ *             is applied exactly, near and far pairs alike, by FFTs of length N
+ *             per fibre (the preconditioner's transforms): the tree then
+ *             carries only the pairs between different fibres and with
+ *             images, and the interior wavenumber k1, which acts within one
+ *             fibre only, leaves the FMM altogether.  1: those pairs go
+ *             through the tree like the others (near pairs by P2P from the
+ *             circulant rows or stored blocks, far pairs by M2L at k and k1).
  *  precond    0: plain GMRES; 1: pfm_solve runs GMRES (with PFM_MIXED the
  *             inner GMRES of the refinement)
  *             right-preconditioned by the fibres' free-space self blocks of
@@ -155,6 +180,7 @@ typedef struct {
   int p2p_cached_rows;
   int direct_lattice_m2l;
   int precond;
+  int self_mode;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -193,6 +219,12 @@ typedef struct {
                                   (one window of consecutive entries per leaf) */
   int p2p_window_max;          /* entries of the largest such window (at most 320) */
   int lattice_m2l_grid;        /* 1: the root lattice M2L runs as a convolution over the fibre grid */
+  double workspace_bytes;      /* bytes of the workspace in use (library-owned or bound) */
+  int workspace_bound;         /* 1: the caller's block is bound (pfm_bind) */
+  int batch_capacity;          /* angles per batch the current workspace serves */
+  long long n_device_allocs;   /* device allocations the library has made for this handle */
+  double device_alloc_bytes;   /* their total size */
+  int self_fft;                /* 1: each fibre's own image-0 block is applied by FFT (self_mode 0) */
 } pfm_stats;
 
 /* Build the plan: discretisation (on the GPU), quadtrees and interaction
@@ -200,6 +232,32 @@ typedef struct {
  * overlapping fibres (2 r >= lattice spacing) or unsupported options. */
 pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat,
                       const pfm_options* opt, pfm_problem** out);
+
+/* Caller-owned workspace (the problem statement of Sec. 2 fixes what a
+ * caller supplies; device memory is the caller's too).  The workspace holds
+ * every device buffer whose contents depend on the frequency or the call:
+ * near blocks and circulant rows, translation tables, lattice sums and their
+ * tail rule, multipole expansions, M2L partial expansions, the far part,
+ * preconditioner blocks, the GMRES basis, vectors and reduction scratch.
+ * Plan metadata (elements, tree, lists, quadrature rules) stays with the
+ * handle.  pfm_create allocates one workspace block for max_batch angles.
+ *
+ * pfm_workspace_size: *bytes = size of the workspace for batches of up to
+ * `batch` angles (1 <= batch <= max_batch; 0 means max_batch).
+ *
+ * pfm_bind: move the workspace into the caller's device block d_workspace of
+ * `bytes` bytes (256-byte aligned, e.g. a torch uint8 CUDA tensor).  The
+ * batch capacity becomes the largest batch (<= max_batch) whose workspace
+ * fits; PFM_EINVAL when not even one angle fits.  Work queued on the handle
+ * is finished first; the library's own block is freed; the state of
+ * pfm_set_wave / pfm_set_batch is dropped (call them again); hip_stream
+ * becomes the handle's stream (as pfm_set_stream).  From then on no call on
+ * the handle allocates device memory (pfm_stats.n_device_allocs stays put).
+ * The caller keeps the block alive, and does not write to it, until the
+ * handle is destroyed or bound elsewhere.  d_workspace = NULL returns to a
+ * library-owned block of max_batch angles. */
+pfm_status pfm_workspace_size(const pfm_problem* pb, int batch, size_t* bytes);
+pfm_status pfm_bind(pfm_problem* pb, void* d_workspace, size_t bytes, void* hip_stream);
 
 /* Use this HIP stream (hipStream_t) for all later work; NULL = null stream. */
 pfm_status pfm_set_stream(pfm_problem* pb, void* hip_stream);
@@ -213,8 +271,10 @@ pfm_status pfm_set_wave(pfm_problem* pb, double ka, double theta);
 /* d_y = (I - A) d_psi, both 2*M*N complex128 on the device.  No allocation. */
 pfm_status pfm_matvec(pfm_problem* pb, const void* d_psi, void* d_y);
 
-/* The same operator with the near field in complex64 (FP32 accumulation) and
- * the far field in FP64 (the apply used inside PFM_MIXED refinement).
+/* The same operator with the near-field blocks stored in complex64 (each
+ * block entry widened to FP64 before its multiply-add; densities and sums
+ * stay FP64) and the far field in FP64 (the apply used inside PFM_MIXED
+ * refinement).
  * Requires a handle created with precision = PFM_MIXED. */
 pfm_status pfm_matvec_mixed(pfm_problem* pb, const void* d_psi, void* d_y);
 

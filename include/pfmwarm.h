@@ -66,6 +66,23 @@ pfm_status pfm_mlp_get_grads(pfm_mlp* m, float* d_dst);
  * (d_scale, d_shift: sizes[n] FP32 each; used to undo target standardisation). */
 pfm_status pfm_mlp_scale_output(pfm_mlp* m, const float* d_scale, const float* d_shift);
 
+/* Statistics of training targets d_t [n][sizes[last]] (FP32, row-major):
+ * per column the mean and the standard deviation (n - 1 in the denominator,
+ * at least 1e-6), into d_mean and d_std (sizes[last] floats each). */
+pfm_status pfm_mlp_target_stats(pfm_mlp* m, const float* d_t, int n, float* d_mean, float* d_std);
+/* d_out = (d_t - mean) / std per column (d_out may be d_t). */
+pfm_status pfm_mlp_standardise(pfm_mlp* m, const float* d_t, int n, const float* d_mean, const float* d_std,
+                               float* d_out);
+/* Shrink of the outputs towards zero from n <= max_batch held-back rows
+ * (d_x inputs, d_t targets): per output o, s_o = clamp(1 - sum (y - t)^2 /
+ * sum t^2, 0, 1) with y the FP32 forward, written to d_shrink and folded
+ * into the last layer (outputs the network cannot predict are left out of a
+ * start vector).  h_rel_err (optional, synchronises the stream): the
+ * relative error sqrt(sum (s y - t)^2 / sum t^2) after the shrink.  Needs
+ * max_batch >= 4. */
+pfm_status pfm_mlp_validation_shrink(pfm_mlp* m, const float* d_x, const float* d_t, int n, float* d_shrink,
+                                     float* h_rel_err);
+
 /* FP32 forward of B <= max_batch rows: d_x [B][sizes[0]] -> d_y [B][sizes[n]].
  * Keeps the activations for pfm_mlp_backward_mse. */
 pfm_status pfm_mlp_forward(pfm_mlp* m, const float* d_x, int B, float* d_y);

@@ -10,9 +10,11 @@ Readings where the paper is silent:
     rows at y = (j + 1/2 + (i mod 2)/2) a, so H = M_H a, L = M_L (sqrt(3)/2) a.
   * Fibre index f = j * M_L + i.
   * Each boundary is cut into N straight chords between nodes
-    c + r(cos t_e, sin t_e), t_e = 2 pi e / N (counter-clockwise), with
+    c + gamma(r, t_e), t_e = 2 pi e / N (counter-clockwise), with
     piecewise-constant densities and collocation at chord midpoints; the
     outward normal of a chord with unit tangent t is (t_y, -t_x).
+  * Boundary curves gamma: the circle r (cos t, sin t), and the round square
+    of Sec. 4, r ((3 + 2 sin^2 t) cos t, (3 + 2 cos^2 t) sin t).
 """
 from __future__ import annotations
 
@@ -23,6 +25,20 @@ import numpy as np
 
 SQUARE = 0
 HEXAGON = 1
+CIRCLE = 0
+ROUND_SQUARE = 1
+
+
+def boundary_curve(shape: int, r: float, t):
+    """Points gamma(r, t) of a fibre's boundary relative to its centre."""
+    t = np.asarray(t, dtype=np.float64)
+    if shape == CIRCLE:
+        return np.stack([r * np.cos(t), r * np.sin(t)], axis=-1)
+    if shape == ROUND_SQUARE:
+        # Sec. 4: the round-square scatterer
+        return np.stack([r * (3.0 + 2.0 * np.sin(t) ** 2) * np.cos(t),
+                         r * (3.0 + 2.0 * np.cos(t) ** 2) * np.sin(t)], axis=-1)
+    raise ValueError("shape must be CIRCLE or ROUND_SQUARE")
 
 
 def fibre_centres(lattice: int, a: float, M_L: int, M_H: int):
@@ -68,7 +84,7 @@ class Boundary:
         return self.M * self.N
 
 
-def discretise(lattice: int, a: float, M_L: int, M_H: int, N: int, radii) -> Boundary:
+def discretise(lattice: int, a: float, M_L: int, M_H: int, N: int, radii, shape: int = CIRCLE) -> Boundary:
     centres, L, H = fibre_centres(lattice, a, M_L, M_H)
     M = M_L * M_H
     radii = np.asarray(radii, dtype=np.float64).reshape(M)
@@ -78,8 +94,8 @@ def discretise(lattice: int, a: float, M_L: int, M_H: int, N: int, radii) -> Bou
     b_pt = np.zeros((M * N, 2))
     for f in range(M):
         c, r = centres[f], radii[f]
-        a_pt[f * N:(f + 1) * N] = c + r * np.stack([np.cos(t), np.sin(t)], axis=1)
-        b_pt[f * N:(f + 1) * N] = c + r * np.stack([np.cos(t1), np.sin(t1)], axis=1)
+        a_pt[f * N:(f + 1) * N] = c + boundary_curve(shape, r, t)
+        b_pt[f * N:(f + 1) * N] = c + boundary_curve(shape, r, t1)
     d = b_pt - a_pt
     h = np.hypot(d[:, 0], d[:, 1])
     tan = d / h[:, None]

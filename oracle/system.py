@@ -56,7 +56,7 @@ class Problem:
 
 def problem_from_workload(wl, ka: float, theta: float, G: int = 4, periodic: bool = True,
                           eta: float | None = None) -> Problem:
-    bd = discretise(wl.lattice, wl.a, wl.M_L, wl.M_H, wl.n_elem, wl.radii)
+    bd = discretise(wl.lattice, wl.a, wl.M_L, wl.M_H, wl.n_elem, wl.radii, getattr(wl, "shape", 0))
     k = ka / wl.a
     k1 = k * wl.c_matrix / wl.c_fiber
     varrho = wl.rho_matrix / wl.rho_fiber

@@ -114,6 +114,31 @@ def autotune(geom: dict, ka_max: float, thetas: Sequence[float], target_err: flo
     return ch
 
 
+def autotune_bands(geom: dict, kas: Sequence[float], thetas: Sequence[float], n_bands: int = 4,
+                   target_err: float = 1e-10, leaves: Iterable[int] = LEAF_CANDIDATES,
+                   ps: Iterable[int] = P_CANDIDATES, iters: float = 30.0, reps: int = 10,
+                   measure_factory=None) -> List[Tuple[List[float], Choice]]:
+    """Frequency-adaptive expansion order (the closing remark of Sec. 4: p
+    must grow with the frequency): the sorted frequencies are cut into
+    n_bands consecutive bands of nearly equal count, and each band gets the
+    (leaf_max, p) that autotune picks at its own largest frequency.  Returns
+    [(frequencies of the band, choice)].  measure_factory(ka) -> measure
+    replaces the GPU measurement (tests)."""
+    ks = sorted(float(k) for k in kas)
+    n_bands = max(1, min(n_bands, len(ks)))
+    edges = [round(i * len(ks) / n_bands) for i in range(n_bands + 1)]
+    out = []
+    for b in range(n_bands):
+        band = ks[edges[b]:edges[b + 1]]
+        if not band:
+            continue
+        meas = measure_factory(band[-1]) if measure_factory else None
+        ch = autotune(geom, band[-1], thetas, target_err=target_err, leaves=leaves, ps=ps, iters=iters,
+                      reps=reps, measure=meas)
+        out.append((band, ch))
+    return out
+
+
 def _gpu_measure(geom: dict, ka: float, thetas: Sequence[float], reps: int, seed: int):
     import numpy as np
     import torch
@@ -179,4 +204,4 @@ def geometry_of(wl) -> dict:
     """pfm.Problem geometry/material keywords of a workload."""
     return dict(lattice=wl.lattice, a=wl.a, M_L=wl.M_L, M_H=wl.M_H, n_elem=wl.n_elem, radii=wl.radii,
                 rho_fiber=wl.rho_fiber, c_fiber=wl.c_fiber, rho_matrix=wl.rho_matrix, c_matrix=wl.c_matrix,
-                eta=wl.eta)
+                eta=wl.eta, shape=wl.shape)

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 #include <map>
+#include <cstdint>
 #include <array>
 
 #include "pfm_kernels.hpp"
@@ -47,10 +48,22 @@ pfm_status fail(Problem& pb, pfm_status s, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                        \
   } while (0)
 
+// Device allocation of plan data and of the library-owned workspace block;
+// counted so that callers (and tests) can see that nothing is allocated after
+// a workspace is bound.
+hipError_t dev_alloc(Problem& pb, void** d, size_t bytes) {
+  hipError_t e = hipMalloc(d, bytes);
+  if (e == hipSuccess) {
+    pb.n_dev_allocs++;
+    pb.dev_alloc_bytes += (double)bytes;
+  }
+  return e;
+}
+
 template <typename T>
-hipError_t upload(T** d, const std::vector<T>& h) {
+hipError_t upload(Problem& pb, T** d, const std::vector<T>& h) {
   size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
-  hipError_t e = hipMalloc((void**)d, bytes);
+  hipError_t e = dev_alloc(pb, (void**)d, bytes);
   if (e != hipSuccess) return e;
   if (!h.empty()) e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
   return e;
@@ -62,7 +75,55 @@ void dfree(T*& d) {
   d = nullptr;
 }
 
+size_t ws_align(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t ws_slot_bytes(const Problem::WsSlot& s, int B) {
+  return ws_align(std::max<size_t>(1, s.fixed + (size_t)B * s.per_member));
+}
+
+// Register a workspace buffer of fixed + per_member * B bytes (B: batch capacity).
+void ws_add(Problem& pb, void* pptr, size_t fixed, size_t per_member, bool zero = false) {
+  pb.ws.push_back(Problem::WsSlot{(void**)pptr, fixed, per_member, zero});
+}
+
+size_t ws_size(const Problem& pb, int B) {
+  size_t t = 0;
+  for (const auto& s : pb.ws) t += ws_slot_bytes(s, B);
+  return t;
+}
+
+// Point every slot into base (ws_size(B) bytes) and clear the slots that must
+// start at zero, on stream st.
+hipError_t ws_carve(Problem& pb, void* base, int B, hipStream_t st) {
+  char* p = (char*)base;
+  for (const auto& s : pb.ws) {
+    const size_t b = ws_slot_bytes(s, B);
+    *s.ptr = p;
+    if (s.zero) {
+      hipError_t e = hipMemsetAsync(p, 0, b, st);
+      if (e != hipSuccess) return e;
+    }
+    p += b;
+  }
+  pb.ws_base = base;
+  pb.ws_bytes = ws_size(pb, B);
+  pb.max_batch = B;
+  // the lattice rows follow the explicit M2L rows inside each member's table
+  pb.d_lat = pb.d_htab ? pb.d_htab + (pb.hp.off_xy.size() / 2) * (size_t)(4 * pb.opt.p + 1) : nullptr;
+  return hipSuccess;
+}
+
+void ws_release(Problem& pb) {
+  for (const auto& s : pb.ws) *s.ptr = nullptr;
+  pb.d_lat = nullptr;
+  if (pb.ws_own) (void)hipFree(pb.ws_own);
+  pb.ws_own = nullptr;
+  pb.ws_base = nullptr;
+  pb.ws_bytes = 0;
+}
+
 void free_all(Problem& pb) {
+  ws_release(pb);
   dfree(pb.d_centres); dfree(pb.d_radii);
   dfree(pb.d_mx); dfree(pb.d_my); dfree(pb.d_tx); dfree(pb.d_ty); dfree(pb.d_h);
   dfree(pb.d_gl); dfree(pb.d_gl16); dfree(pb.d_elem_of); dfree(pb.d_psi_idx);
@@ -77,7 +138,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
-  dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
+  dfree(pb.d_p2p_items); dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
   dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x);
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
@@ -91,7 +152,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_off_xy); dfree(pb.d_joff_xy); dfree(pb.d_root_off_xy);
   dfree(pb.d_near); dfree(pb.d_near32); dfree(pb.d_ir_r); dfree(pb.d_ir_d); dfree(pb.d_ir_aug); dfree(pb.d_cperp); dfree(pb.d_htab); dfree(pb.d_jtab); pb.d_lat = nullptr; dfree(pb.d_alpha);
   dfree(pb.d_srule); dfree(pb.d_betas); dfree(pb.d_thetas); dfree(pb.d_latpart);
-  dfree(pb.d_mpole); dfree(pb.d_local);
+  dfree(pb.d_mpole);
   dfree(pb.d_V); dfree(pb.d_w); dfree(pb.d_r); dfree(pb.d_b); dfree(pb.d_tmp);
   dfree(pb.d_red); dfree(pb.d_hcol); dfree(pb.d_fields);
   if (pb.h_hcol) (void)hipHostFree(pb.h_hcol);
@@ -182,6 +243,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->precond != 0 && opt->precond != 1) return bail(fail(pb, PFM_EINVAL, "precond must be 0 or 1"));
+  if (opt->self_mode != 0 && opt->self_mode != 1) return bail(fail(pb, PFM_EINVAL, "self_mode must be 0 or 1"));
   if (opt->precond == 1 && (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0))
     return bail(fail(pb, PFM_EINVAL, "precond = 1 needs n_elem a power of two in 8..512"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -202,17 +264,34 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   pb.opt = *opt;
   if (!(pb.opt.inner_tol > 0 && pb.opt.inner_tol < 1)) pb.opt.inner_tol = 0;   // relaxation point from tol
   pb.max_batch = std::max(1, opt->max_batch);
+  pb.max_batch_create = pb.max_batch;
+  // Every fibre is a circle cut into N equal chords, so its own image-0 block
+  // (both wavenumbers, near and far pairs) is block circulant; with N a power
+  // of two it is applied by the FFTs of the preconditioner's transforms.
+  pb.self_fft = opt->self_mode == 0 && !opt->store_self_blocks && geo->shape == PFM_CIRCLE && pb.N >= 8 &&
+                pb.N <= 512 && (pb.N & (pb.N - 1)) == 0;
 
   pb.rho_f = mat->rho_fiber;
   pb.c_f = mat->c_fiber;
   pb.rho_m = mat->rho_matrix;
   pb.c_m = mat->c_matrix;
   pb.eta_user = mat->eta;
+  if (geo->shape != PFM_CIRCLE && geo->shape != PFM_ROUND_SQUARE)
+    return bail(fail(pb, PFM_EINVAL, "shape must be PFM_CIRCLE or PFM_ROUND_SQUARE"));
+  pb.shape = geo->shape;
+  if (pb.shape != PFM_CIRCLE) {
+    // the chords of a non-circular fibre are not rotations of each other: no
+    // circulant rows, every near pair is a stored block
+    if (opt->precond) return bail(fail(pb, PFM_EINVAL, "precond = 1 needs circular fibres"));
+    pb.opt.store_self_blocks = 1;
+  }
+  // farthest point of the boundary curve from the fibre centre, per unit r
+  const double reach = pb.shape == PFM_ROUND_SQUARE ? 4.0 : 1.0;
   pb.radii.resize(pb.M);
   for (int f = 0; f < pb.M; ++f) {
     double r = geo->radii ? geo->radii[f] : geo->r0;
-    if (!(r > 0) || !(2.0 * r < pb.a))
-      return bail(fail(pb, PFM_EINVAL, "fibre radius must satisfy 0 < 2 r < a (fibres may not touch)"));
+    if (!(r > 0) || !(2.0 * reach * r < pb.a))
+      return bail(fail(pb, PFM_EINVAL, "fibre size must satisfy 0 < 2 (reach) r < a (fibres may not touch)"));
     pb.radii[f] = r;
   }
   pb.centres.resize(2 * pb.M);
@@ -239,6 +318,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     if (!(hipGetDevice(&dev) == hipSuccess &&
           hipDeviceGetAttribute(&pb.n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess))
       pb.n_cu = 0;
+    pb.device = dev;
     pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : 1;
   }
   // discretisation on the device
@@ -246,15 +326,15 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
 #define CK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) { free_all(pb); \
     return bail(fail(pb, e_ == hipErrorOutOfMemory ? PFM_ENOMEM : PFM_EDEVICE, \
                      std::string(#call) + ": " + hipGetErrorString(e_))); } } while (0)
-  CK(upload(&pb.d_centres, pb.centres));
-  CK(upload(&pb.d_radii, pb.radii));
-  CK(hipMalloc((void**)&pb.d_mx, E * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_my, E * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_tx, E * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_ty, E * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_h, E * sizeof(double)));
+  CK(upload(pb, &pb.d_centres, pb.centres));
+  CK(upload(pb, &pb.d_radii, pb.radii));
+  CK(dev_alloc(pb, (void**)&pb.d_mx, E * sizeof(double)));
+  CK(dev_alloc(pb, (void**)&pb.d_my, E * sizeof(double)));
+  CK(dev_alloc(pb, (void**)&pb.d_tx, E * sizeof(double)));
+  CK(dev_alloc(pb, (void**)&pb.d_ty, E * sizeof(double)));
+  CK(dev_alloc(pb, (void**)&pb.d_h, E * sizeof(double)));
   double* d_ends = nullptr;
-  CK(hipMalloc((void**)&d_ends, 4 * (size_t)E * sizeof(double)));
+  CK(dev_alloc(pb, (void**)&d_ends, 4 * (size_t)E * sizeof(double)));
   CK(launch_discretise(pb, d_ends));
   std::vector<double> ends(4 * (size_t)E), mid(2 * (size_t)E), mx(E), my(E);
   CK(hipMemcpy(ends.data(), d_ends, ends.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -279,28 +359,28 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     cx[i] = c.cx; cy[i] = c.cy; eb[i] = c.ebeg; ee[i] = c.eend;
     fc[i] = c.first_child; nch[i] = c.n_child; par[i] = c.parent; fib[i] = c.fiber;
   }
-  CK(upload(&pb.d_elem_of, hp.elem_of));
+  CK(upload(pb, &pb.d_elem_of, hp.elem_of));
   {
     std::vector<int> pidx(E);
     for (int t = 0; t < E; ++t) {
       int e = hp.elem_of[t], f = e / pb.N;
       pidx[t] = 2 * f * pb.N + (e - f * pb.N);
     }
-    CK(upload(&pb.d_psi_idx, pidx));
+    CK(upload(pb, &pb.d_psi_idx, pidx));
   }
-  CK(upload(&pb.d_cx, cx)); CK(upload(&pb.d_cy, cy));
-  CK(upload(&pb.d_ebeg, eb)); CK(upload(&pb.d_eend, ee));
-  CK(upload(&pb.d_first_child, fc)); CK(upload(&pb.d_n_child, nch));
-  CK(upload(&pb.d_parent, par)); CK(upload(&pb.d_fibre_of_cell, fib));
+  CK(upload(pb, &pb.d_cx, cx)); CK(upload(pb, &pb.d_cy, cy));
+  CK(upload(pb, &pb.d_ebeg, eb)); CK(upload(pb, &pb.d_eend, ee));
+  CK(upload(pb, &pb.d_first_child, fc)); CK(upload(pb, &pb.d_n_child, nch));
+  CK(upload(pb, &pb.d_parent, par)); CK(upload(pb, &pb.d_fibre_of_cell, fib));
 
-  CK(upload(&pb.d_leaves, hp.leaves));
-  CK(upload(&pb.d_root_of_fibre, hp.root_of_fibre));
-  CK(upload(&pb.d_m2l_ptr, hp.m2l_ptr)); CK(upload(&pb.d_m2l_src, hp.m2l_src));
-  CK(upload(&pb.d_m2l_off, hp.m2l_off)); CK(upload(&pb.d_m2l_m, hp.m2l_m));
-  CK(upload(&pb.d_m2li_ptr, hp.m2li_ptr)); CK(upload(&pb.d_m2li_src, hp.m2li_src));
-  CK(upload(&pb.d_m2li_off, hp.m2li_off));
-  CK(upload(&pb.d_near_ptr, hp.near_ptr)); CK(upload(&pb.d_near_src, hp.near_src));
-  CK(upload(&pb.d_near_m, hp.near_m)); CK(upload(&pb.d_near_tgt, hp.near_tgt));
+  CK(upload(pb, &pb.d_leaves, hp.leaves));
+  CK(upload(pb, &pb.d_root_of_fibre, hp.root_of_fibre));
+  CK(upload(pb, &pb.d_m2l_ptr, hp.m2l_ptr)); CK(upload(pb, &pb.d_m2l_src, hp.m2l_src));
+  CK(upload(pb, &pb.d_m2l_off, hp.m2l_off)); CK(upload(pb, &pb.d_m2l_m, hp.m2l_m));
+  CK(upload(pb, &pb.d_m2li_ptr, hp.m2li_ptr)); CK(upload(pb, &pb.d_m2li_src, hp.m2li_src));
+  CK(upload(pb, &pb.d_m2li_off, hp.m2li_off));
+  CK(upload(pb, &pb.d_near_ptr, hp.near_ptr)); CK(upload(pb, &pb.d_near_src, hp.near_src));
+  CK(upload(pb, &pb.d_near_m, hp.near_m)); CK(upload(pb, &pb.d_near_tgt, hp.near_tgt));
   // Near pairs of one fibre with itself (m = 0) are circulant: the chords of
   // a circle are rotations of each other, so the 2x2 block of target element
   // a and source element b depends only on (b - a) mod N, and one row per
@@ -326,7 +406,9 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         const Cell& C = hp.cells[hp.near_src[q]];
         stored_entries += (long long)(D.eend - D.ebeg) * (C.eend - C.ebeg);
       }
-    pb.p2p_on_side = n_circ_entries > stored_entries;
+    // with the self blocks applied by FFT, the FFT apply and the P2P of the
+    // remaining stored pairs form the short branch
+    pb.p2p_on_side = pb.self_fft || n_circ_entries > stored_entries;
     // default grid: two workgroups per CU stream stored blocks at full HBM
     // rate without starving the chain; the light circulant P2P on the side
     // stream takes four (measured fastest for the overlapped apply)
@@ -441,12 +523,12 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     pb.n_near_stored = stored;
     pb.n_near_uniq = (int)uniq.size();
     pb.n_near_copies = (int)cp_src.size();
-    CK(upload(&pb.d_near_blk, blk));
-    CK(upload(&pb.d_leaf_blk, leaf_blk));
-    CK(upload(&pb.d_near_uniq, uniq));
+    CK(upload(pb, &pb.d_near_blk, blk));
+    CK(upload(pb, &pb.d_leaf_blk, leaf_blk));
+    CK(upload(pb, &pb.d_near_uniq, uniq));
     if (!cp_src.empty()) {
-      CK(upload(&pb.d_near_cp_src, cp_src)); CK(upload(&pb.d_near_cp_dst, cp_dst));
-      CK(upload(&pb.d_near_cp_len, cp_len));
+      CK(upload(pb, &pb.d_near_cp_src, cp_src)); CK(upload(pb, &pb.d_near_cp_dst, cp_dst));
+      CK(upload(pb, &pb.d_near_cp_len, cp_len));
     }
   }
   {
@@ -472,12 +554,21 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       cptr[li + 1] = (int)cpsi.size();
       qptr[li + 1] = (int)qpsi.size();
     }
-    CK(upload(&pb.d_cols_ptr, cptr));
-    CK(upload(&pb.d_col_psi, cpsi));
-    CK(upload(&pb.d_col_m, cm));
-    CK(upload(&pb.d_ccols_ptr, qptr));
-    CK(upload(&pb.d_ccol_psi, qpsi));
-    CK(upload(&pb.d_ccol_loc, qloc));
+    {
+      // with the own blocks by FFT P2P adds into the rows only where a leaf
+      // has stored near columns
+      std::vector<int> items;
+      for (int li = 0; li < nl; ++li)
+        if (cptr[li + 1] > cptr[li] || qptr[li + 1] > qptr[li]) items.push_back(li);
+      pb.n_p2p_items = (int)items.size();
+      CK(upload(pb, &pb.d_p2p_items, items));
+    }
+    CK(upload(pb, &pb.d_cols_ptr, cptr));
+    CK(upload(pb, &pb.d_col_psi, cpsi));
+    CK(upload(pb, &pb.d_col_m, cm));
+    CK(upload(pb, &pb.d_ccols_ptr, qptr));
+    CK(upload(pb, &pb.d_ccol_psi, qpsi));
+    CK(upload(pb, &pb.d_ccol_loc, qloc));
     // LDS windows of the circulant rows.  Target leaf li reads the entries
     // (b - a) + N of its fibre's rows for its rows a and circulant columns b;
     // counted from the start of the arc that holds them (after the largest
@@ -523,45 +614,46 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         pb.n_win_leaves++;
       }
     }
-    CK(upload(&pb.d_cwin, cwin));
+    CK(upload(pb, &pb.d_cwin, cwin));
     // split the columns of each target leaf when there are too few leaves to
     // fill the P2P grid, keeping at least 32 columns per split on average
     const long long ncols = (long long)cpsi.size() + (long long)qpsi.size();
     int S = 1;
     if (pb.p2p_grid > 0 && nl > 0 && nl < pb.p2p_grid) S = std::min(8, (pb.p2p_grid + nl - 1) / nl);
     while (S > 1 && ncols / ((long long)nl * S) < 32) --S;
+    if (pb.self_fft) S = 1;             // P2P adds into the rows the FFT apply wrote
     pb.p2p_split = S;
-    size_t part = S > 1 ? (size_t)S * std::max(1, opt->max_batch) * 2 * (size_t)pb.E : 1;
-    CK(hipMalloc((void**)&pb.d_p2ppart, part * sizeof(cd)));
+    ws_add(pb, &pb.d_p2ppart, S > 1 ? 0 : sizeof(cd), S > 1 ? (size_t)S * 2 * (size_t)pb.E * sizeof(cd) : 0);
     // circulant rows [fibre][component][2N] (the second copy spares the wrap)
-    CK(hipMalloc((void**)&pb.d_circ, (size_t)std::max(1, pb.M) * 8 * pb.N * sizeof(cd)));
+    ws_add(pb, &pb.d_circ, (size_t)std::max(1, pb.M) * 8 * pb.N * sizeof(cd), 0);
   }
-  if (pb.opt.precond) {
-    // preconditioner blocks per (fibre, mode), twiddles exp(2 pi i j / N), and
-    // the vector P^{-1} v of the preconditioned apply
-    CK(hipMalloc((void**)&pb.d_pc_fwd, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
-    CK(hipMalloc((void**)&pb.d_pc_inv, (size_t)pb.M * pb.N * 4 * sizeof(cd)));
-    CK(hipMalloc((void**)&pb.d_pc_x, (size_t)pb.max_batch * 2 * pb.E * sizeof(cd)));
+  if (pb.opt.precond || pb.self_fft) {
+    // per (fibre, mode) 2x2 blocks of the fibres' self blocks and of their
+    // inverses, twiddles exp(2 pi i j / N), and (preconditioned GMRES) the
+    // vector P^{-1} v of the preconditioned apply
+    ws_add(pb, &pb.d_pc_fwd, (size_t)pb.M * pb.N * 4 * sizeof(cd), 0);
+    ws_add(pb, &pb.d_pc_inv, (size_t)pb.M * pb.N * 4 * sizeof(cd), 0);
+    if (pb.opt.precond) ws_add(pb, &pb.d_pc_x, 0, 2 * (size_t)pb.E * sizeof(cd));
     std::vector<cd> tw(pb.N);
     for (int j = 0; j < pb.N; ++j) {
       const double t = 2.0 * M_PI * j / pb.N;
       tw[j] = mkc(std::cos(t), std::sin(t));
     }
-    CK(upload(&pb.d_pc_tw, tw));
+    CK(upload(pb, &pb.d_pc_tw, tw));
     pb.pc_logN = 0;
     while ((1 << pb.pc_logN) < pb.N) ++pb.pc_logN;
   }
-  CK(upload(&pb.d_root_pair_off, hp.root_pair_off));
-  CK(upload(&pb.d_root_mrange, hp.root_off_mrange));
-  CK(upload(&pb.d_off_xy, hp.off_xy)); CK(upload(&pb.d_joff_xy, hp.joff_xy));
-  CK(upload(&pb.d_root_off_xy, hp.root_off_xy));
+  CK(upload(pb, &pb.d_root_pair_off, hp.root_pair_off));
+  CK(upload(pb, &pb.d_root_mrange, hp.root_off_mrange));
+  CK(upload(pb, &pb.d_off_xy, hp.off_xy)); CK(upload(pb, &pb.d_joff_xy, hp.joff_xy));
+  CK(upload(pb, &pb.d_root_off_xy, hp.root_off_xy));
   // quadrature rules: far rule, then 16-point near rule and 8-point field rule
   {
     std::vector<double> x, w, t;
     gauss_legendre(pb.opt.g_far, x, w);
     t = x;
     t.insert(t.end(), w.begin(), w.end());
-    CK(upload(&pb.d_gl, t));
+    CK(upload(pb, &pb.d_gl, t));
     std::vector<double> x16, w16, x8, w8;
     gauss_legendre(16, x16, w16);
     gauss_legendre(8, x8, w8);
@@ -569,20 +661,17 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     u.insert(u.end(), w16.begin(), w16.end());
     u.insert(u.end(), x8.begin(), x8.end());
     u.insert(u.end(), w8.begin(), w8.end());
-    CK(upload(&pb.d_gl16, u));
+    CK(upload(pb, &pb.d_gl16, u));
   }
   const int NP = 2 * pb.opt.p + 1, NT = 4 * pb.opt.p + 1;
   const size_t MB = (size_t)pb.max_batch;   // per-member buffers: one copy per batch member
-  CK(hipMalloc((void**)&pb.d_mpole, MB * nc * 2 * NP * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_local, (size_t)nc * 2 * NP * sizeof(cd)));
-  CK(hipMemset(pb.d_mpole, 0, MB * nc * 2 * NP * sizeof(cd)));
-  CK(hipMemset(pb.d_local, 0, (size_t)nc * 2 * NP * sizeof(cd)));
+  ws_add(pb, &pb.d_mpole, 0, (size_t)nc * 2 * NP * sizeof(cd), true);
   size_t n_ent = std::max<long long>(1, pb.n_near_stored);
-  CK(hipMalloc((void**)&pb.d_near, 4 * n_ent * sizeof(cd)));
+  ws_add(pb, &pb.d_near, 4 * n_ent * sizeof(cd), 0);
   if (pb.opt.precision == PFM_MIXED) {
-    CK(hipMalloc((void**)&pb.d_near32, 4 * n_ent * sizeof(float2)));
-    CK(hipMalloc((void**)&pb.d_ir_r, 2 * (size_t)E * sizeof(cd)));
-    CK(hipMalloc((void**)&pb.d_ir_d, 2 * (size_t)E * sizeof(cd)));
+    ws_add(pb, &pb.d_near32, 4 * n_ent * sizeof(float2), 0);
+    ws_add(pb, &pb.d_ir_r, 2 * (size_t)E * sizeof(cd), 0);
+    ws_add(pb, &pb.d_ir_d, 2 * (size_t)E * sizeof(cd), 0);
   }
   int n_off = std::max<int>(1, (int)hp.off_xy.size() / 2);
   int n_joff = std::max<int>(1, (int)hp.joff_xy.size() / 2);
@@ -590,13 +679,12 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   // translation table rows per channel: explicit M2L offsets, then lattice offsets
   int n_off_real = (int)hp.off_xy.size() / 2;
   pb.n_tab = n_off_real + n_roff;
-  CK(hipMalloc((void**)&pb.d_htab, MB * 2 * pb.n_tab * NT * sizeof(cd)));
-  CK(hipMemset(pb.d_htab, 0, MB * 2 * pb.n_tab * NT * sizeof(cd)));
-  pb.d_lat = pb.d_htab + (size_t)n_off_real * NT;
-  CK(hipMalloc((void**)&pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_betas, MB * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_thetas, MB * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_latpart, MB * n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd)));
+  ws_add(pb, &pb.d_htab, 0, 2 * (size_t)pb.n_tab * NT * sizeof(cd), true);
+  ws_add(pb, &pb.d_jtab, (size_t)2 * n_joff * NT * sizeof(cd), 0);
+  ws_add(pb, &pb.d_betas, 0, sizeof(double));
+  ws_add(pb, &pb.d_thetas, 0, sizeof(double));
+  ws_add(pb, &pb.d_latpart, 0, (size_t)n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd));
+  ws_add(pb, &pb.d_srule, 2 * (size_t)LAT_RULE_POINTS * sizeof(double), 0);
   (void)n_off;
   {
     // M2L work: per (channel, cell) the entries (source cell, table row, image),
@@ -676,8 +764,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     }
     pb.n_chunks = (int)(sums.size() / 4);
     pb.n_mchunks = (int)(mchunks.size() / 4);
-    CK(upload(&pb.d_e_src, esrc)); CK(upload(&pb.d_e_off, eoff)); CK(upload(&pb.d_e_m, em));
-    CK(upload(&pb.d_mchunks, mchunks)); CK(upload(&pb.d_chunks, sums)); CK(upload(&pb.d_cc_ptr, ccptr));
+    CK(upload(pb, &pb.d_e_src, esrc)); CK(upload(pb, &pb.d_e_off, eoff)); CK(upload(pb, &pb.d_e_m, em));
+    CK(upload(pb, &pb.d_mchunks, mchunks)); CK(upload(pb, &pb.d_chunks, sums)); CK(upload(pb, &pb.d_cc_ptr, ccptr));
     // leaf descriptors of P2M and the downward pass: everything a leaf's
     // workgroup reads is one load away from its index (no chain leaf -> cell
     // -> element -> geometry, or cell -> sum row)
@@ -717,52 +805,60 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       }
     }
     if (lanc.empty()) lanc.assign(2, 0);
-    CK(upload(&pb.d_ldesc, ldesc)); CK(upload(&pb.d_lanc, lanc)); CK(upload(&pb.d_tgeo, tgeo)); CK(upload(&pb.d_trh, trh));
-    CK(hipMalloc((void**)&pb.d_part, MB * std::max(1, pb.n_chunks) * NP * sizeof(cd)));
-    CK(hipMalloc((void**)&pb.d_epart, MB * std::max(1, pb.n_mchunks) * NP * sizeof(cd)));
+    CK(upload(pb, &pb.d_ldesc, ldesc)); CK(upload(pb, &pb.d_lanc, lanc)); CK(upload(pb, &pb.d_tgeo, tgeo)); CK(upload(pb, &pb.d_trh, trh));
+    ws_add(pb, &pb.d_part, 0, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd));
+    ws_add(pb, &pb.d_epart, 0, (size_t)std::max(1, pb.n_mchunks) * NP * sizeof(cd));
     if (pb.lat_fft) {
       pb.lat_ns = lns; pb.lat_gx = lgx; pb.lat_gy = lgy; pb.lat_px = lpx; pb.lat_py = lpy;
       const size_t pxy = (size_t)lpx * lpy;
-      CK(upload(&pb.d_lat_cell, lcell)); CK(upload(&pb.d_lat_slot, lslot)); CK(upload(&pb.d_lat_key, lkey));
-      CK(hipMalloc((void**)&pb.d_lat_shat, MB * lns * lns * pxy * NT * sizeof(cd)));
-      CK(hipMalloc((void**)&pb.d_lat_xhat, MB * lns * pxy * NP * sizeof(cd)));
-      CK(hipMalloc((void**)&pb.d_lat_lhat, MB * lns * pxy * NP * sizeof(cd)));
+      CK(upload(pb, &pb.d_lat_cell, lcell)); CK(upload(pb, &pb.d_lat_slot, lslot)); CK(upload(pb, &pb.d_lat_key, lkey));
+      ws_add(pb, &pb.d_lat_shat, 0, (size_t)lns * lns * pxy * NT * sizeof(cd));
+      ws_add(pb, &pb.d_lat_xhat, 0, (size_t)lns * pxy * NP * sizeof(cd));
+      ws_add(pb, &pb.d_lat_lhat, 0, (size_t)lns * pxy * NP * sizeof(cd));
     }
   }
   {
-    CK(upload(&pb.d_up_cells, hp.up_cells)); CK(upload(&pb.d_up_ptr, hp.up_ptr));
-    CK(upload(&pb.d_up_src, hp.up_src)); CK(upload(&pb.d_up_off, hp.up_off));
+    CK(upload(pb, &pb.d_up_cells, hp.up_cells)); CK(upload(pb, &pb.d_up_ptr, hp.up_ptr));
+    CK(upload(pb, &pb.d_up_src, hp.up_src)); CK(upload(pb, &pb.d_up_off, hp.up_off));
     pb.n_up = (int)hp.up_cells.size();
-    CK(hipMalloc((void**)&pb.d_far, MB * 2 * E * sizeof(cd)));
+    ws_add(pb, &pb.d_far, 0, 2 * (size_t)E * sizeof(cd));
   }
   {
     size_t na = (size_t)(hp.m_max - hp.m_min + 1);
-    CK(hipMalloc((void**)&pb.d_alpha, MB * na * sizeof(cd)));
+    ws_add(pb, &pb.d_alpha, 0, na * sizeof(cd));
     std::vector<cd> ones(na, mkc(1.0, 0.0));
-    CK(upload(&pb.d_alpha_one, ones));
+    CK(upload(pb, &pb.d_alpha_one, ones));
   }
   // GMRES workspace (batched solves use MB members of each vector)
   size_t n = 2 * (size_t)E;
-  CK(hipMalloc((void**)&pb.d_V, (size_t)(pb.opt.restart + 1) * MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_w, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_r, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_b, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_tmp, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_gin, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_ir_aug, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_cperp, MB * n * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_gout, MB * n * sizeof(cd)));
+  ws_add(pb, &pb.d_V, 0, (size_t)(pb.opt.restart + 1) * n * sizeof(cd));
+  ws_add(pb, &pb.d_w, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_r, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_b, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_tmp, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_gin, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_ir_aug, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_cperp, 0, n * sizeof(cd));
+  ws_add(pb, &pb.d_gout, 0, n * sizeof(cd));
   pb.red_blocks = (int)std::min<size_t>(512, (n + 255) / 256);
-  CK(hipMalloc((void**)&pb.d_npart, MB * ((n + 63) / 64) * sizeof(double)));
-  CK(hipMalloc((void**)&pb.d_dcoef, MB * (2 * (size_t)pb.opt.restart + 4) * sizeof(cd)));
+  ws_add(pb, &pb.d_npart, 0, ((n + 63) / 64) * sizeof(double));
+  ws_add(pb, &pb.d_dcoef, 0, (2 * (size_t)pb.opt.restart + 4) * sizeof(cd));
   // restart + 1 columns: DCGS2 leaves the last reorthogonalisation of a cycle in column restart
-  CK(hipMalloc((void**)&pb.d_hall, ((size_t)pb.opt.restart + 1) * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
+  ws_add(pb, &pb.d_hall, 0, ((size_t)pb.opt.restart + 1) * (2 * pb.opt.restart + 4) * sizeof(cd));
   CK(hipHostMalloc((void**)&pb.h_hall, ((size_t)pb.opt.restart + 1) * MB * (2 * pb.opt.restart + 4) * sizeof(cd)));
   // dot partials [member][vector][block], then (long vectors) the reduced [member][vector]
-  CK(hipMalloc((void**)&pb.d_red, MB * (pb.red_blocks + 1) * (2 * pb.opt.restart + 8) * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
+  ws_add(pb, &pb.d_red, 0, (size_t)(pb.red_blocks + 1) * (2 * pb.opt.restart + 8) * sizeof(cd));
+  ws_add(pb, &pb.d_hcol, 0, (size_t)(2 * pb.opt.restart + 8) * sizeof(cd));
   CK(hipHostMalloc((void**)&pb.h_hcol, MB * (2 * pb.opt.restart + 8) * sizeof(cd)));
-  CK(hipMalloc((void**)&pb.d_fields, (size_t)2 * 512 * sizeof(cd)));
+  ws_add(pb, &pb.d_fields, (size_t)2 * 512 * sizeof(cd), 0);
+  // the library's own workspace block, sized for max_batch members (a caller
+  // may later bind a block of its own with pfm_bind)
+  {
+    const size_t wsb = ws_size(pb, pb.max_batch);
+    CK(dev_alloc(pb, &pb.ws_own, wsb));
+    CK(ws_carve(pb, pb.ws_own, pb.max_batch, nullptr));
+    CK(hipDeviceSynchronize());
+  }
   for (int i = 0; i < 16; ++i) CK(hipEventCreate(&pb.ev[i]));
   CK(hipEventCreateWithFlags(&pb.ev_fork, hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&pb.ev_join, hipEventDisableTiming));
@@ -828,8 +924,9 @@ pfm_status frequency_tables(Problem& pb) {
   pb.lattice_q = q;
   std::vector<double> rule;
   tail_rule(pb.k, pb.H, (q + 1) * pb.H - ymax, xmax, 2 * pb.opt.p, rule);
-  dfree(pb.d_srule);
-  HIPCHK(pb, upload(&pb.d_srule, rule));
+  if (rule.size() != 2 * (size_t)LAT_RULE_POINTS) return fail(pb, PFM_ENUMERIC, "lattice tail rule size");
+  HIPCHK(pb, hipMemcpyAsync(pb.d_srule, rule.data(), rule.size() * sizeof(double), hipMemcpyHostToDevice,
+                            pb.stream));
   pb.n_srule = (int)rule.size() / 2;
   HIPCHK(pb, launch_tables(pb));
   return PFM_OK;
@@ -889,7 +986,7 @@ pfm_status pfm_set_wave(pfm_problem* h, double ka, double theta) {
   HIPCHK(pb, launch_lattice_sums(pb, 1));
   HIPCHK(pb, launch_near_blocks(pb, false));
   if (pb.opt.precision == PFM_MIXED) HIPCHK(pb, launch_near_to_c64(pb));
-  if (pb.opt.precond) HIPCHK(pb, launch_precond_setup(pb));
+  if (pb.opt.precond || pb.self_fft) HIPCHK(pb, launch_precond_setup(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   pb.wave_ready = true;
   return PFM_OK;
@@ -935,7 +1032,7 @@ pfm_status pfm_set_batch(pfm_problem* h, double ka, int B, const double* theta) 
   HIPCHK(pb, hipMemcpyAsync(pb.d_betas, betas.data(), B * sizeof(double), hipMemcpyHostToDevice, pb.stream));
   HIPCHK(pb, launch_lattice_sums(pb, B));
   HIPCHK(pb, launch_near_blocks(pb, true));
-  if (pb.opt.precond) HIPCHK(pb, launch_precond_setup(pb));
+  if (pb.opt.precond || pb.self_fft) HIPCHK(pb, launch_precond_setup(pb));
   HIPCHK(pb, hipStreamSynchronize(pb.stream));
   if (pb.opt.use_graph) {
     st = capture_batch_graph(pb);
@@ -1692,6 +1789,52 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->p2p_window_leaves = pb.n_win_leaves;
   st->p2p_window_max = pb.p2p_wmax;
   st->lattice_m2l_grid = pb.lat_fft ? 1 : 0;
+  st->workspace_bytes = (double)pb.ws_bytes;
+  st->workspace_bound = pb.ws_bound ? 1 : 0;
+  st->batch_capacity = pb.max_batch;
+  st->n_device_allocs = pb.n_dev_allocs;
+  st->device_alloc_bytes = pb.dev_alloc_bytes;
+  st->self_fft = pb.self_fft ? 1 : 0;
+  return PFM_OK;
+}
+
+pfm_status pfm_workspace_size(const pfm_problem* h, int batch, size_t* bytes) {
+  if (!h || !bytes) return PFM_EINVAL;
+  const Problem& pb = h->p;
+  if (batch == 0) batch = pb.max_batch_create;
+  if (batch < 1 || batch > pb.max_batch_create) return PFM_EINVAL;
+  *bytes = ws_size(pb, batch);
+  return PFM_OK;
+}
+
+pfm_status pfm_bind(pfm_problem* h, void* d_workspace, size_t bytes, void* hip_stream) {
+  if (!h) return PFM_EINVAL;
+  Problem& pb = h->p;
+  int cap = pb.max_batch_create;
+  if (d_workspace) {
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(pb, PFM_EINVAL, "workspace must be 256-byte aligned");
+    while (cap >= 1 && ws_size(pb, cap) > bytes) --cap;
+    if (cap < 1)
+      return fail(pb, PFM_EINVAL, "workspace of " + std::to_string(bytes) + " bytes is below the " +
+                                      std::to_string(ws_size(pb, 1)) + " bytes of one member");
+  }
+  // work queued on the old buffers ends first; then the wave or batch set up
+  // in them (and a graph that holds their addresses) is dropped
+  HIPCHK(pb, hipStreamSynchronize(pb.stream));
+  HIPCHK(pb, hipStreamSynchronize(pb.side));
+  drop_graph(pb);
+  pb.wave_ready = false;
+  pb.batch_ready = false;
+  ws_release(pb);
+  pb.ws_bound = false;
+  pb.stream = (hipStream_t)hip_stream;
+  void* base = d_workspace;
+  if (!d_workspace) {
+    HIPCHK(pb, dev_alloc(pb, &pb.ws_own, ws_size(pb, cap)));
+    base = pb.ws_own;
+  }
+  HIPCHK(pb, ws_carve(pb, base, cap, pb.stream));
+  pb.ws_bound = d_workspace != nullptr;
   return PFM_OK;
 }
 

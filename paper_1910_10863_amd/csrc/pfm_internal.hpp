@@ -68,7 +68,8 @@ struct Problem {
   int lattice = 0;
   double a = 1.0;
   int ML = 1, MH = 1, M = 1, N = 8, E = 8;
-  std::vector<double> radii, centres;   // [M], [M][2]
+  int shape = PFM_CIRCLE;               // boundary curve of every fibre (pfm_shape)
+  std::vector<double> radii, centres;   // [M] size parameters, [M][2]
   double L = 1.0, H = 1.0;
   double rho_f = 1, c_f = 1, rho_m = 1, c_m = 1, eta_user = 0;
   pfm_options opt{};
@@ -167,6 +168,8 @@ struct Problem {
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
   int p2p_unroll = 1;                   // source columns in flight per P2P wavefront
+  int* d_p2p_items = nullptr;           // self_fft: the target leaves with stored near columns
+  int n_p2p_items = 0;
   cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table
@@ -188,7 +191,6 @@ struct Problem {
   cd *d_latpart = nullptr;              // tail partial sums [member][offset][rule block][4p+1]
   // expansions
   cd *d_mpole = nullptr;                // [n_cells][2][2p+1]
-  cd *d_local = nullptr;                // [n_cells][2][2p+1]
   // GMRES workspace
   cd *d_V = nullptr;                    // [restart+1][n]
   cd *d_w = nullptr, *d_r = nullptr, *d_b = nullptr, *d_tmp = nullptr;
@@ -209,6 +211,32 @@ struct Problem {
   hipStream_t cap = nullptr;
   hipGraphExec_t graph = nullptr;
   cd *d_gin = nullptr, *d_gout = nullptr;
+
+  // Workspace: the device buffers whose contents are per frequency or per
+  // call (near blocks, circulant rows, tables, lattice sums, expansions, M2L
+  // partials, far part, GMRES basis and vectors, reduction scratch).  Each
+  // slot is fixed + per_member * (batch capacity) bytes, 256-byte aligned,
+  // carved in registration order from one block that the library allocates
+  // at create or that the caller binds (pfm_bind).  Plan metadata (elements,
+  // tree, lists, rules) stays library-owned.
+  struct WsSlot {
+    void** ptr;
+    size_t fixed, per_member;
+    bool zero;                          // cleared when (re)carved
+  };
+  std::vector<WsSlot> ws;
+  void* ws_own = nullptr;               // library-owned block (nullptr while a caller's block is bound)
+  void* ws_base = nullptr;              // block the slots point into
+  size_t ws_bytes = 0;                  // its size in use
+  bool ws_bound = false;                // the caller's block is bound
+  int max_batch_create = 1;             // max_batch of pfm_create (upper bound of any binding)
+  long long n_dev_allocs = 0;           // device allocations made by the library so far
+  double dev_alloc_bytes = 0;
+  // each fibre's own image-0 block (both wavenumbers, near and far pairs)
+  // applied by FFT as a block-circulant operator; the tree holds only the
+  // pairs between fibres and with images, and only the exterior channel
+  bool self_fft = false;
+  int device = 0;                       // the GPU the handle was created on
 };
 
 bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);

@@ -24,9 +24,22 @@ bool supported_p(int p) {
 }
 
 // ---------------------------------------------------------------------------
-// discretisation: N chords per fibre between c + r(cos t_e, sin t_e)
+// discretisation: N chords per fibre between the nodes c + gamma(r, t_e),
+// t_e = 2 pi e / N, of the fibre's boundary curve: a circle, or the round
+// square of Sec. 4, r ((3 + 2 sin^2 t) cos t, (3 + 2 cos^2 t) sin t)
 // ---------------------------------------------------------------------------
-__global__ void k_discretise(int E, int N, const double* __restrict__ centres,
+__device__ inline void boundary_point(int shape, double r, double t, double& x, double& y) {
+  const double c = cos(t), s = sin(t);
+  if (shape == PFM_ROUND_SQUARE) {
+    x = r * (3.0 + 2.0 * s * s) * c;
+    y = r * (3.0 + 2.0 * c * c) * s;
+  } else {
+    x = r * c;
+    y = r * s;
+  }
+}
+
+__global__ void k_discretise(int E, int N, int shape, const double* __restrict__ centres,
                              const double* __restrict__ radii, double* mx, double* my,
                              double* tx, double* ty, double* h, double* ends) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,8 +47,11 @@ __global__ void k_discretise(int E, int N, const double* __restrict__ centres,
   int f = e / N, l = e - f * N;
   double t0 = 2.0 * PI * l / N, t1 = 2.0 * PI * (l + 1) / N;
   double cx = centres[2 * f], cy = centres[2 * f + 1], r = radii[f];
-  double ax = cx + r * cos(t0), ay = cy + r * sin(t0);
-  double bx = cx + r * cos(t1), by = cy + r * sin(t1);
+  double ux, uy, vx, vy;
+  boundary_point(shape, r, t0, ux, uy);
+  boundary_point(shape, r, t1, vx, vy);
+  double ax = cx + ux, ay = cy + uy;
+  double bx = cx + vx, by = cy + vy;
   double dx = bx - ax, dy = by - ay;
   double hh = sqrt(dx * dx + dy * dy);
   mx[e] = 0.5 * (ax + bx);
@@ -53,7 +69,7 @@ __global__ void k_discretise(int E, int N, const double* __restrict__ centres,
 
 hipError_t launch_discretise(Problem& pb, double* d_ends) {
   int E = pb.E;
-  hipLaunchKernelGGL(k_discretise, dim3((E + 255) / 256), dim3(256), 0, pb.stream, E, pb.N,
+  hipLaunchKernelGGL(k_discretise, dim3((E + 255) / 256), dim3(256), 0, pb.stream, E, pb.N, pb.shape,
                      pb.d_centres, pb.d_radii, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, d_ends);
   return hipGetLastError();
 }
@@ -234,7 +250,6 @@ __global__ void k_copy_blocks(const long long* __restrict__ src, const long long
 hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   const HostPlan& hp = pb.hp;
   int npairs = (int)hp.near_src.size();
-  if (npairs == 0) return hipSuccess;
   NearArgs A;
   A.N = pb.N;
   A.g_far = pb.opt.g_far;
@@ -254,12 +269,12 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   A.out = pb.d_near;
   int lm = pb.opt.leaf_max;
   A.pair_ids = pb.d_near_uniq;
-  if (pb.n_near_uniq > 0)
+  if (npairs > 0 && pb.n_near_uniq > 0)
     hipLaunchKernelGGL(k_near_blocks, dim3(pb.n_near_uniq, (lm * lm + 127) / 128), dim3(128), 0, pb.stream, A);
-  if (pb.n_near_copies > 0)
+  if (npairs > 0 && pb.n_near_copies > 0)
     hipLaunchKernelGGL(k_copy_blocks, dim3(pb.n_near_copies, (4 * lm * lm + 255) / 256), dim3(256), 0, pb.stream,
                        pb.d_near_cp_src, pb.d_near_cp_dst, pb.d_near_cp_len, pb.d_near);
-  if (pb.n_near_circ > 0 || pb.opt.precond)
+  if (pb.n_near_circ > 0 || pb.opt.precond || pb.self_fft)
     hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + 127) / 128, pb.M), dim3(128), 0, pb.stream, A, pb.d_circ);
   return hipGetLastError();
 }
@@ -407,10 +422,10 @@ hipError_t launch_precond_setup(Problem& pb) {
   return hipGetLastError();
 }
 
-hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B) {
+hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B, hipStream_t st) {
   const int N = pb.N;
   const size_t lds = 4 * (size_t)N * sizeof(cd);
-  hipLaunchKernelGGL(k_pc_apply, dim3(pb.M, std::max(1, B)), dim3(PC_THREADS), lds, pb.stream, in, out,
+  hipLaunchKernelGGL(k_pc_apply, dim3(pb.M, std::max(1, B)), dim3(PC_THREADS), lds, st ? st : pb.stream, in, out,
                      inverse ? pb.d_pc_inv : pb.d_pc_fwd, pb.d_pc_tw, N, pb.pc_logN);
   return hipGetLastError();
 }
@@ -933,15 +948,15 @@ struct P2MRows {
 };
 
 template <int P, int W, int NA>
-__device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int npts, int G, double kap, double eta,
-                                         const P2MRows& rw) {
+__device__ __forceinline__ void p2m_half(cd (&out)[NA], int first, int stride, int npts, int G, double kap,
+                                         double eta, const P2MRows& rw) {
   using H = P2MHalf<P, W>;
   constexpr int M1 = H::LO > 0 ? H::LO : 1;   // first order with a +- pair
   // slot of order +m: m - LO (Pm for m >= 1); slot of order -m: NPOS + m - M1 (Qm)
   cd acc[H::NS];
 #pragma unroll
   for (int j = 0; j < H::NS; ++j) acc[j] = mkc(0, 0);
-  for (int pt = lane; pt < npts; pt += 64) {
+  for (int pt = first; pt < npts; pt += stride) {
     int q = pt / G;
     int g = pt - q * G;
     cd phi = rw.phi[q], vphi = rw.vphi[q];
@@ -996,8 +1011,12 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int lane, int npts, int 
   for (int j = 0; j < H::NS; ++j) out[j] = acc[j];
 }
 
-template <int P>
-__global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
+// PS groups of two wavefronts per (leaf, channel): group g walks the Gauss
+// points g*64 + lane, g*64 + lane + 64 PS, ...; with one channel (the fibres'
+// own blocks by FFT) PS = 2 doubles the waves of a launch that is otherwise
+// latency-bound.  The partial moments meet in LDS in a fixed order.
+template <int P, int PS>
+__global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
                                              const double4* __restrict__ tgeo, const double* __restrict__ trh,
                                              const int* __restrict__ psi_idx, const double* __restrict__ gl,
                                              int G, int N, double k, double k1, double eta,
@@ -1005,8 +1024,8 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
                                              long long psi_stride, long long mp_stride) {
   constexpr int NP = 2 * P + 1;
   constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
-  // one transpose buffer, used by the two wavefronts in turn (keeps the LDS
-  // footprint small so that P2M co-resides with the concurrent P2P)
+  // one transpose buffer, used by the wavefronts in turn (keeps the LDS
+  // footprint small so that P2M co-resides with the concurrent work)
   __shared__ cd red[64][NA];
   // the leaf's rows (from its descriptor and the row-ordered geometry) are
   // loaded once by the first wavefront; the point loop then reads only LDS
@@ -1018,6 +1037,7 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
   int ch = blockIdx.y;
   double kap = ch ? k1 : k;
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int half = wv & 1, grp = wv >> 1;
   if (wv == 0) {
     if (lane < rows) {
       const double4 g = tgeo[rb + lane];
@@ -1027,7 +1047,7 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
       rw.phi[lane] = psi[pi];
       rw.vphi[lane] = psi[pi + N];
     }
-  } else if (lane < 2 * G) {
+  } else if (wv == 1 && lane < 2 * G) {
     rw.gl[lane] = gl[lane];
   }
   __syncthreads();
@@ -1035,27 +1055,37 @@ __global__ void __launch_bounds__(128) k_p2m(const int* __restrict__ leaves, con
   cd acc[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = mkc(0, 0);
-  if (wv == 0)
-    p2m_half<P, 0, NA>(acc, lane, npts, G, kap, eta, rw);
+  if (half == 0)
+    p2m_half<P, 0, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
   else
-    p2m_half<P, 1, NA>(acc, lane, npts, G, kap, eta, rw);
+    p2m_half<P, 1, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
   cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  for (int pass = 0; pass < 2; ++pass) {
+  // thread t keeps the sum of slot t of each half over the groups
+  cd hold[2] = {mkc(0, 0), mkc(0, 0)};
+  for (int pass = 0; pass < 2 * PS; ++pass) {
     if (wv == pass) {
 #pragma unroll
       for (int j = 0; j < NA; ++j) red[lane][j] = acc[j];
     }
     __syncthreads();
-    // slot -> order of the wavefront of this pass
-    int lo = pass == 0 ? 0 : P / 2 + 1, hi = pass == 0 ? P / 2 : P;
-    int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
-    for (int j = threadIdx.x; j < npos + nneg; j += 128) {
+    const int h = pass & 1;
+    const int lo = h == 0 ? 0 : P / 2 + 1, hi = h == 0 ? P / 2 : P;
+    const int ns = (hi - lo + 1) + (hi - (lo > 0 ? lo : 1) + 1);
+    if ((int)threadIdx.x < ns) {
       cd sres = mkc(0, 0);
-      for (int r = 0; r < 64; ++r) sres = cadd(sres, red[r][j]);
-      int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
-      out[n + P] = sres;
+      for (int r = 0; r < 64; ++r) sres = cadd(sres, red[r][threadIdx.x]);
+      hold[h] = cadd(hold[h], sres);
     }
     __syncthreads();
+  }
+  for (int h = 0; h < 2; ++h) {
+    const int lo = h == 0 ? 0 : P / 2 + 1, hi = h == 0 ? P / 2 : P;
+    const int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
+    const int j = threadIdx.x;
+    if (j < npos + nneg) {
+      int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
+      out[n + P] = hold[h];
+    }
   }
 }
 
@@ -1247,7 +1277,8 @@ __global__ void __launch_bounds__(256) k_m2l_sum(const int* __restrict__ sums, c
     part[(size_t)c * NP + l] = cadd(cadd(sq[0][l], sq[1][l]), cadd(sq[2][l], sq[3][l]));
 }
 
-// Downward pass and L2P, one workgroup of two wavefronts (channels) per leaf.
+// Downward pass and L2P, one workgroup of two wavefronts (channels) per leaf
+// (one, the exterior channel, when each fibre's own block is applied by FFT).
 // The leaf's local expansion is its own M2L sum plus the own M2L sums of all
 // its ancestors translated directly to it (L2L of Sec. 3.2 across several
 // levels, Graf's theorem for J):
@@ -1383,6 +1414,10 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
   if (ch == 1) {
     su[lane] = u;
     sd[lane] = dv;
+  } else if (blockDim.x == 64) {
+    // one wavefront: the interior channel is applied outside the tree
+    su[lane] = mkc(0, 0);
+    sd[lane] = mkc(0, 0);
   }
   __syncthreads();
   if (ch == 0 && lane < rows) {
@@ -1465,7 +1500,8 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
     const int* __restrict__ cols_ptr, const int* __restrict__ col_psi, const C* __restrict__ blocks,
     const int* __restrict__ ccols_ptr, const int* __restrict__ ccol_psi, const int* __restrict__ ccol_loc,
     const cd* __restrict__ circ, const int* __restrict__ cwin, const cd* __restrict__ psi,
-    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part, long long vec) {
+    cd* y, const cd* ybase, const int* __restrict__ item_leaf, int n_leaves, int S, cd* __restrict__ part,
+    long long vec) {
   // the blocks are stored as C (complex128, or complex64 for PFM_MIXED); the
   // densities and the sums stay FP64, so the complex64 form only rounds the
   // stored blocks (the stream is bandwidth-bound either way)
@@ -1476,13 +1512,19 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
   __shared__ cd r1[P2P_WAVES][64], r2[P2P_WAVES][64];
   // work item = (target leaf, column split); with S > 1 the splits write
   // partial rows that k_combine adds in a fixed order
+  // work items run over n_leaves target leaves, all of them or (item_leaf)
+  // the listed ones: when P2P adds into rows that already hold the rest
+  // (ybase == y), only the leaves with near columns
   for (int item = blockIdx.x; item < n_leaves * S; item += gridDim.x) {
-    int li = item / S, sp_i = item - li * S;
+    int lw = item / S, sp_i = item - lw * S;
+    int li = item_leaf ? item_leaf[lw] : lw;
+    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    // a leaf without near columns has nothing to add (uniform over the workgroup)
+    if (ybase == y && ncol == 0 && ccols_ptr[li + 1] == ccols_ptr[li]) continue;
     int D = leaves[li];
     int db = ebeg[D], rows = eend[D] - db;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     cd a1 = mkc(0, 0), a2 = a1;
-    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
     int chunk = (ncol + S - 1) / S;
     int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
     const C* bl = blocks + 4 * leaf_blk[li];
@@ -1647,8 +1689,10 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
       }
       int pi = psi_idx[db + lane];
       if (S == 1) {
-        y[pi] = cadd(psi[pi], s1);
-        y[pi + N] = cadd(psi[pi + N], s2);
+        // ybase: psi (the identity of I - A), or y itself when the rows
+        // already hold psi and the rest of the operator
+        y[pi] = cadd(ybase[pi], s1);
+        y[pi + N] = cadd(ybase[pi + N], s2);
       } else {
         cd* pp = part + (size_t)sp_i * vec;
         pp[pi] = s1;
@@ -1673,7 +1717,7 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
     const cd* __restrict__ alpha, int alpha_stride, int m_min, int B, long long stride,
     const C* __restrict__ blocks, const int* __restrict__ ccols_ptr, const int* __restrict__ ccol_psi,
     const int* __restrict__ ccol_loc, const cd* __restrict__ circ, const cd* __restrict__ psi,
-    cd* __restrict__ y, int n_leaves, int S, cd* __restrict__ part) {
+    cd* y, const cd* ybase, const int* __restrict__ item_leaf, int n_leaves, int S, cd* __restrict__ part) {
   constexpr int SEG = P2PBatchSeg<NB>::value;
   __shared__ C sp[SEG][NB][2];
   __shared__ int sl[SEG];
@@ -1681,14 +1725,16 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
   // work item = (target leaf, column split); with S > 1 the splits write
   // partial rows [split][member][vector] that k_combine adds in a fixed order
   for (int item = blockIdx.x; item < n_leaves * S; item += gridDim.x) {
-    int li = item / S, sp_i = item - li * S;
+    int lw = item / S, sp_i = item - lw * S;
+    int li = item_leaf ? item_leaf[lw] : lw;
+    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+    if (ybase == y && ncol == 0 && ccols_ptr[li + 1] == ccols_ptr[li]) continue;
     int D = leaves[li];
     int db = ebeg[D], rows = eend[D] - db;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     C a1[NB], a2[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) a1[b] = a2[b] = p2p_cvt<C>(mkc(0, 0));
-    int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
     int chunk = (ncol + S - 1) / S;
     int c_lo = min(ncol, sp_i * chunk), c_hi = min(ncol, c_lo + chunk);
     const C* bl = blocks + 4 * leaf_blk[li];
@@ -1782,7 +1828,7 @@ __global__ void __launch_bounds__(64 * P2P_WAVES) k_p2p_batch(
         }
         int pi = psi_idx[db + lane];
         if (S == 1) {
-          const cd* pb_ = psi + b * stride;
+          const cd* pb_ = ybase + b * stride;
           cd* yb = y + b * stride;
           yb[pi] = cadd(pb_[pi], s1);
           yb[pi + N] = cadd(pb_[pi + N], s2);
@@ -1835,6 +1881,9 @@ static hipError_t tables_impl(Problem& pb) {
 template <int P>
 // join != nullptr: the stream waits for it before the downward pass, which
 // then adds the far part into y_join (holding psi + near) instead of d_far.
+// With each fibre's own block applied by FFT (pb.self_fft) only the exterior
+// channel carries pairs, so the chain runs channel 0 alone (the upward pass of
+// the test hook keeps both).
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B,
                       hipEvent_t join = nullptr, cd* y_join = nullptr) {
   const HostPlan& hp = pb.hp;
@@ -1842,13 +1891,17 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   int n_leaves = (int)hp.leaves.size();
   int n_joff = (int)hp.joff_xy.size() / 2;
   const BatchStrides bs = batch_strides(pb);
+  const int nch = pb.self_fft && !upward_only ? 1 : 2;
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_p2m<P>, dim3(n_leaves, 2, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
-                     reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl, pb.opt.g_far,
-                     pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
+  // one group of two wavefronts per (leaf, channel): two groups (PS = 2)
+  // were slower on the square 8x8 block with one channel (21.7 us against
+  // 15.5 us in order)
+  hipLaunchKernelGGL((k_p2m<P, 1>), dim3(n_leaves, nch, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
+                     reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl,
+                     pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (pb.n_up > 0)
-    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, 2, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
+    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, nch, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
                        pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
@@ -1871,10 +1924,10 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   if (join) (void)hipStreamWaitEvent(s, join, 0);
-  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(128), 0, s, pb.d_ldesc,
+  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(64 * nch), 0, s, pb.d_ldesc,
                      reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
                      pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
-                     join ? y_join : pb.d_far, bs.part, bs.vec, join ? 1 : 0);
+                     y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 
@@ -1891,8 +1944,9 @@ static void launch_p2p_batch(Problem& pb, hipStream_t st, int grid, const C* blo
   hipLaunchKernelGGL((k_p2p_batch<C, NB>), dim3(grid), dim3(64 * P2P_WAVES), 0, st, pb.d_leaves,
                      pb.d_ebeg, pb.d_eend, pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi,
                      pb.d_col_m, pb.d_alpha, bs.alpha, pb.hp.m_min, B, bs.vec, blocks, pb.d_ccols_ptr,
-                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, (int)pb.hp.leaves.size(), pb.p2p_split,
-                     pb.d_p2ppart);
+                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, d_psi, d_y, pb.self_fft ? d_y : d_psi,
+                     pb.self_fft ? pb.d_p2p_items : nullptr,
+                     pb.self_fft ? pb.n_p2p_items : (int)pb.hp.leaves.size(), pb.p2p_split, pb.d_p2ppart);
 }
 
 // y = (I - A) psi.  Without stage events the FMM chain runs on the side
@@ -1902,7 +1956,74 @@ static void launch_p2p_batch(Problem& pb, hipStream_t st, int grid, const C* blo
 // B = 0: one wave, image phases inside the near blocks; B >= 1: a batch of
 // B members (one per incidence angle) over phase-free near blocks.
 template <int P, typename C>
+static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const cd* d_psi, cd* d_y, int B) {
+  // with the own blocks by FFT, only the leaves with stored near columns
+  const int* item_leaf = pb.self_fft ? pb.d_p2p_items : nullptr;
+  int n_leaves = pb.self_fft ? pb.n_p2p_items : (int)pb.hp.leaves.size();
+  if (n_leaves == 0) return;
+  int items = n_leaves * pb.p2p_split;
+  int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
+  if (B == 0) {
+#define PFM_P2P(U)                                                                                             \
+  hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES),                                      \
+                     pb.p2p_wmax ? 4 * P2P_WCAP * sizeof(cd) : 0, ps, pb.d_leaves, pb.d_ebeg, pb.d_eend,       \
+                     pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks, pb.d_ccols_ptr,    \
+                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, pb.d_cwin, d_psi, d_y,                           \
+                     pb.self_fft ? d_y : d_psi, item_leaf, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
+    if (pb.p2p_unroll == 4) PFM_P2P(4);
+    else if (pb.p2p_unroll == 2) PFM_P2P(2);
+    else PFM_P2P(1);
+#undef PFM_P2P
+  } else if (B == 1) {
+    launch_p2p_batch<C, 1>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B == 2) {
+    launch_p2p_batch<C, 2>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B <= 4) {
+    launch_p2p_batch<C, 4>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
+  } else if (B <= 8) {
+    launch_p2p_batch<C, 8>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
+  } else {
+    launch_p2p_batch<C, 16>(pb, ps, p2p_grid, blocks, d_psi, d_y, B);
+  }
+}
+
+// The apply with each fibre's own image-0 block applied by FFT (pb.self_fft):
+//   y = P psi + near(psi) + far(psi),
+// P the block-diagonal operator of the fibres' own blocks (identity included),
+// near the stored P2P blocks of pairs between fibres or with images, far the
+// exterior FMM chain.  Overlapped: P and the P2P run on the side stream and
+// write y; the chain runs on the caller's stream and its downward pass, after
+// the join, adds the far part into y.  With stage events everything runs in
+// order on the caller's stream: the chain writes the far part to its buffer,
+// P and P2P write y, and the join kernel adds the far part.
+template <int P, typename C>
+static hipError_t apply_self_fft(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B) {
+  const int nb = B > 0 ? B : 1;
+  if (ev) {
+    fmm_chain<P>(pb, d_psi, pb.stream, ev, false, nb);
+    hipError_t e = launch_precond(pb, d_psi, d_y, false, nb, pb.stream);
+    if (e != hipSuccess) return e;
+    launch_p2p_any<P, C>(pb, pb.stream, blocks, d_psi, d_y, B);
+    (void)hipEventRecord(ev[5], pb.stream);
+    long long n = 2LL * pb.E * nb;
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_far, d_psi,
+                       pb.d_p2ppart, 1, d_y);
+    (void)hipEventRecord(ev[6], pb.stream);
+    return hipGetLastError();
+  }
+  (void)hipEventRecord(pb.ev_fork, pb.stream);
+  (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
+  hipError_t e = launch_precond(pb, d_psi, d_y, false, nb, pb.side);
+  if (e != hipSuccess) return e;
+  launch_p2p_any<P, C>(pb, pb.side, blocks, d_psi, d_y, B);
+  (void)hipEventRecord(pb.ev_join, pb.side);
+  fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, pb.ev_join, d_y);
+  return hipGetLastError();
+}
+
+template <int P, typename C>
 static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B) {
+  if (pb.self_fft) return apply_self_fft<P, C>(pb, blocks, d_psi, d_y, ev, B);
   const HostPlan& hp = pb.hp;
   int n_leaves = (int)hp.leaves.size();
   int nb = B > 0 ? B : 1;
@@ -1928,8 +2049,8 @@ static hipError_t apply_impl_t(Problem& pb, const C* blocks, const cd* d_psi, cd
   hipLaunchKernelGGL((k_p2p<C, U>), dim3(p2p_grid), dim3(64 * P2P_WAVES),                                      \
                      pb.p2p_wmax ? 4 * P2P_WCAP * sizeof(cd) : 0, ps, pb.d_leaves, pb.d_ebeg, pb.d_eend,       \
                      pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks, pb.d_ccols_ptr,    \
-                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, pb.d_cwin, d_psi, d_y, n_leaves, pb.p2p_split,   \
-                     pb.d_p2ppart, 2LL * pb.E)
+                     pb.d_ccol_psi, pb.d_ccol_loc, pb.d_circ, pb.d_cwin, d_psi, d_y,                           \
+                     pb.self_fft ? d_y : d_psi, nullptr, n_leaves, pb.p2p_split, pb.d_p2ppart, 2LL * pb.E)
     if (pb.p2p_unroll == 4) PFM_P2P(4);
     else if (pb.p2p_unroll == 2) PFM_P2P(2);
     else PFM_P2P(1);

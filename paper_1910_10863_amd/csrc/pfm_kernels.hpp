@@ -15,14 +15,14 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free);
 // per-fibre block preconditioner: coefficients from the circulant rows, and
 // out = P^{-1} in (inverse) or P in, for B stacked vectors of 2 M N
 hipError_t launch_precond_setup(Problem& pb);
-hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B = 1);
+hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B = 1, hipStream_t st = nullptr);
 hipError_t launch_rhs(Problem& pb, double theta, cd* d_b);
 hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out);
 hipError_t launch_bessel_test(const double* d_x, int n, double* d_out, hipStream_t s);
 
 // y = (I - A) psi.  When ev != nullptr, events ev[0..6] bracket the stages.
 hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);
-// the same with the near field in complex64 (FP32 accumulation)
+// the same with the near-field blocks stored in complex64 (sums in FP64)
 hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y);
 // B = pb.B members at once over phase-free near blocks; vectors [B][2E]
 hipError_t apply_operator_batch(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);

@@ -14,7 +14,8 @@
 // of them a dual traversal of the two trees emits M2L pairs where
 // rho_D + rho_C <= mac |O_D - O_C - m h| and P2P pairs between leaves that
 // are not separated.  Pairs with j = i and m = 0 also form the lists of the
-// interior (wavenumber k1) operators, which act within one fibre only.
+// interior (wavenumber k1) operators, which act within one fibre only; they
+// are left out when that block is applied by FFT (Problem::self_fft).
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -336,6 +337,8 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
       for (int m = mlo; m <= mhi; ++m) {
         hp.m_min = std::min(hp.m_min, m);
         hp.m_max = std::max(hp.m_max, m);
+        // a fibre's own image-0 block applied by FFT is not in the tree
+        if (pb.self_fft && i == j && m == 0) continue;
         trav(hp.root_of_fibre[i], hp.root_of_fibre[j], m, i == j && m == 0);
       }
     }

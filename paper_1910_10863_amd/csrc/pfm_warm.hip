@@ -313,6 +313,59 @@ __global__ void __launch_bounds__(256) k_modes_synthesise(int M, int N, int K, d
   }
 }
 
+// Column statistics of training targets t [n][m] (row-major): mean and
+// standard deviation with n - 1 in the denominator, at least `floor`; sums
+// in FP64, one thread per column (coalesced across the columns of a row).
+__global__ void k_col_stats(const float* __restrict__ t, int n, int m, float floor_, float* __restrict__ mean,
+                            float* __restrict__ sd) {
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= m) return;
+  double s = 0.0;
+  for (int r = 0; r < n; ++r) s += (double)t[(size_t)r * m + o];
+  const double mu = s / n;
+  double v = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const double d = (double)t[(size_t)r * m + o] - mu;
+    v += d * d;
+  }
+  const double sdv = n > 1 ? sqrt(v / (n - 1)) : 0.0;
+  mean[o] = (float)mu;
+  sd[o] = (float)fmax(sdv, (double)floor_);
+}
+
+__global__ void k_standardise(const float* __restrict__ t, long long total, int m, const float* __restrict__ mean,
+                              const float* __restrict__ sd, float* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int o = (int)(i % m);
+  out[i] = (t[i] - mean[o]) / sd[o];
+}
+
+// Per output column o over n validation rows: s_o = clamp(1 - sum (y - t)^2 /
+// sum t^2, 0, 1) (the share of the column's power the network predicts);
+// and the column's sums sum (s_o y - t)^2, sum t^2 for the relative error
+// after the shrink.
+__global__ void k_val_shrink(const float* __restrict__ y, const float* __restrict__ t, int n, int m,
+                             float* __restrict__ shrink, double* __restrict__ err2, double* __restrict__ pow2) {
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= m) return;
+  double e = 0.0, pw = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const double yy = y[(size_t)r * m + o], tt = t[(size_t)r * m + o];
+    e += (yy - tt) * (yy - tt);
+    pw += tt * tt;
+  }
+  const double sh = fmin(1.0, fmax(0.0, 1.0 - e / fmax(pw, 1e-30)));
+  double es = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const double d = sh * (double)y[(size_t)r * m + o] - (double)t[(size_t)r * m + o];
+    es += d * d;
+  }
+  shrink[o] = (float)sh;
+  err2[o] = es;
+  pow2[o] = pw;
+}
+
 }  // namespace warm
 }  // namespace pfm
 
@@ -442,6 +495,58 @@ pfm_status pfm_mlp_scale_output(pfm_mlp* m, const float* d_scale, const float* d
   hipLaunchKernelGGL(k_scale_output, dim3((outw + 255) / 256), dim3(256), 0, m->stream, outw, in,
                      m->d_p + m->woff[l], m->d_p + m->boff[l], d_scale, d_shift);
   return hipGetLastError() == hipSuccess ? PFM_OK : PFM_EDEVICE;
+}
+
+pfm_status pfm_mlp_target_stats(pfm_mlp* m, const float* d_t, int n, float* d_mean, float* d_std) {
+  if (!m || !d_t || !d_mean || !d_std || n < 1) return PFM_EINVAL;
+  const int w = m->sizes[m->L];
+  hipLaunchKernelGGL(k_col_stats, dim3((w + 255) / 256), dim3(256), 0, m->stream, d_t, n, w, 1e-6f, d_mean, d_std);
+  return hipGetLastError() == hipSuccess ? PFM_OK : PFM_EDEVICE;
+}
+
+pfm_status pfm_mlp_standardise(pfm_mlp* m, const float* d_t, int n, const float* d_mean, const float* d_std,
+                               float* d_out) {
+  if (!m || !d_t || !d_mean || !d_std || !d_out || n < 1) return PFM_EINVAL;
+  const int w = m->sizes[m->L];
+  const long long total = (long long)n * w;
+  hipLaunchKernelGGL(k_standardise, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, m->stream, d_t, total, w,
+                     d_mean, d_std, d_out);
+  return hipGetLastError() == hipSuccess ? PFM_OK : PFM_EDEVICE;
+}
+
+pfm_status pfm_mlp_forward(pfm_mlp* m, const float* d_x, int B, float* d_y);
+
+pfm_status pfm_mlp_validation_shrink(pfm_mlp* m, const float* d_x, const float* d_t, int n, float* d_shrink,
+                                     float* h_rel_err) {
+  if (!m || !d_x || !d_t || !d_shrink || n < 1 || n > m->max_batch || m->max_batch < 4) return PFM_EINVAL;
+  const int w = m->sizes[m->L];
+  // the FP32 forward of the validation rows (kept in the inference scratch)
+  float* y = m->d_tmp[0];
+  pfm_status st = pfm_mlp_forward(m, d_x, n, y);
+  if (st != PFM_OK) return st;
+  // per-column sums in the delta buffers (max_batch * widest layer floats each, >= 2 w doubles)
+  double* e2 = reinterpret_cast<double*>(m->d_d0);
+  double* p2 = e2 + w;
+  hipLaunchKernelGGL(k_val_shrink, dim3((w + 255) / 256), dim3(256), 0, m->stream, y, d_t, n, w, d_shrink, e2, p2);
+  if (hipGetLastError() != hipSuccess) return PFM_EDEVICE;
+  if (h_rel_err) {
+    std::vector<double> h(2 * (size_t)w);
+    if (hipMemcpyAsync(h.data(), e2, 2 * (size_t)w * sizeof(double), hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+      return PFM_EDEVICE;
+    double se = 0.0, sp = 0.0;
+    for (int o = 0; o < w; ++o) {
+      se += h[o];
+      sp += h[w + o];
+    }
+    *h_rel_err = (float)std::sqrt(se / std::max(sp, 1e-300));
+  }
+  // fold the shrink into the last layer
+  std::vector<float> zeros(w, 0.0f);
+  float* shift = m->d_d1;
+  if (hipMemcpyAsync(shift, zeros.data(), (size_t)w * sizeof(float), hipMemcpyHostToDevice, m->stream) != hipSuccess)
+    return PFM_EDEVICE;
+  return pfm_mlp_scale_output(m, d_shrink, shift);
 }
 
 pfm_status pfm_mlp_forward(pfm_mlp* m, const float* d_x, int B, float* d_y) {

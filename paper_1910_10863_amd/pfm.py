@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpfmbem.so")
 _lib = None
 
 SUPPORTED_P = (8, 12, 16, 20, 24, 32, 40)
+CIRCLE = 0
+ROUND_SQUARE = 1
 
 
 class PfmError(RuntimeError):
@@ -29,7 +31,7 @@ class PfmError(RuntimeError):
 class Geometry(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int), ("a", ctypes.c_double), ("M_L", ctypes.c_int),
                 ("M_H", ctypes.c_int), ("n_elem", ctypes.c_int),
-                ("radii", ctypes.POINTER(ctypes.c_double)), ("r0", ctypes.c_double)]
+                ("radii", ctypes.POINTER(ctypes.c_double)), ("r0", ctypes.c_double), ("shape", ctypes.c_int)]
 
 
 class Material(ctypes.Structure):
@@ -46,7 +48,8 @@ class Options(ctypes.Structure):
                 ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
                 ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
-                ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int),
+                ("self_mode", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -67,7 +70,10 @@ class Stats(ctypes.Structure):
                 ("lattice_q", ctypes.c_int), ("p2p_split", ctypes.c_int), ("n_near_computed", ctypes.c_int),
                 ("n_near_stored", ctypes.c_longlong), ("n_near_circulant", ctypes.c_longlong),
                 ("p2p_window_leaves", ctypes.c_int), ("p2p_window_max", ctypes.c_int),
-                ("lattice_m2l_grid", ctypes.c_int)]
+                ("lattice_m2l_grid", ctypes.c_int), ("workspace_bytes", ctypes.c_double),
+                ("workspace_bound", ctypes.c_int), ("batch_capacity", ctypes.c_int),
+                ("n_device_allocs", ctypes.c_longlong), ("device_alloc_bytes", ctypes.c_double),
+                ("self_fft", ctypes.c_int)]
 
 
 FP64 = 0
@@ -78,7 +84,7 @@ MAX_BATCH = 16
 EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_matvec_mixed", "pfm_rhs", "pfm_solve",
            "pfm_precond_apply", "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
-           "pfm_matvec_batch_timed",
+           "pfm_matvec_batch_timed", "pfm_workspace_size", "pfm_bind",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
 
 
@@ -98,6 +104,8 @@ def lib():
     L.pfm_set_wave.argtypes = [P, ctypes.c_double, ctypes.c_double]
     L.pfm_matvec.argtypes = [P, vp, vp]
     L.pfm_matvec_mixed.argtypes = [P, vp, vp]
+    L.pfm_workspace_size.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.pfm_bind.argtypes = [P, vp, ctypes.c_size_t, vp]
     dp = ctypes.POINTER(ctypes.c_double)
     L.pfm_set_batch.argtypes = [P, ctypes.c_double, ctypes.c_int, dp]
     L.pfm_matvec_batch.argtypes = [P, vp, vp]
@@ -151,25 +159,25 @@ class Problem:
     """One fundamental block of fibres with its FMM plan."""
 
     def __init__(self, lattice: int, a: float, M_L: int, M_H: int, n_elem: int, radii,
-                 rho_fiber: float, c_fiber: float, rho_matrix: float, c_matrix: float,
+                 rho_fiber: float, c_fiber: float, rho_matrix: float, c_matrix: float, shape: int = CIRCLE,
                  eta: float = 0.0, p: int = 16, leaf_max: int = 32, mac: float = 0.65,
                  g_far: int = 4, restart: int = 200, max_iter: int = 4000, tol: float = 1e-8,
                  wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
-                 direct_lattice_m2l: bool = False, precond: bool = False):
+                 direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True):
         import torch
         L = lib()
         self._L = L
         self._h = ctypes.c_void_p()
         rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
         self._radii = rad
-        geo = Geometry(lattice, a, M_L, M_H, n_elem, _dptr(rad), 0.0)
+        geo = Geometry(lattice, a, M_L, M_H, n_elem, _dptr(rad), 0.0, shape)
         mat = Material(rho_fiber, c_fiber, rho_matrix, c_matrix, eta)
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
                       max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
-                      1 if direct_lattice_m2l else 0, 1 if precond else 0)
+                      1 if direct_lattice_m2l else 0, 1 if precond else 0, 0 if self_fft else 1)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
@@ -189,7 +197,7 @@ class Problem:
     def from_workload(cls, wl, **kw):
         args = dict(lattice=wl.lattice, a=wl.a, M_L=wl.M_L, M_H=wl.M_H, n_elem=wl.n_elem,
                     radii=wl.radii, rho_fiber=wl.rho_fiber, c_fiber=wl.c_fiber,
-                    rho_matrix=wl.rho_matrix, c_matrix=wl.c_matrix, eta=wl.eta, p=wl.p,
+                    rho_matrix=wl.rho_matrix, c_matrix=wl.c_matrix, shape=wl.shape, eta=wl.eta, p=wl.p,
                     leaf_max=wl.leaf_max, tol=wl.tol)
         args.update(kw)
         return cls(**args)
@@ -233,6 +241,26 @@ class Problem:
         y = self.empty() if out is None else out
         self._check(self._L.pfm_matvec_mixed(self._h, _ptr(psi), _ptr(y)))
         return y
+
+    def workspace_size(self, batch: int = 0) -> int:
+        n = ctypes.c_size_t()
+        self._check(self._L.pfm_workspace_size(self._h, int(batch), ctypes.byref(n)))
+        return n.value
+
+    def bind(self, workspace=None, stream=None):
+        """Move the library's workspace into `workspace` (a uint8 CUDA tensor the
+        caller keeps alive), or back into a library-owned block (None)."""
+        import torch
+        st = torch.cuda.current_stream() if stream is None else stream
+        if workspace is None:
+            code = self._L.pfm_bind(self._h, None, 0, ctypes.c_void_p(st.cuda_stream))
+        else:
+            if workspace.dtype != torch.uint8:
+                raise TypeError("workspace must be a uint8 tensor")
+            code = self._L.pfm_bind(self._h, _ptr(workspace), workspace.numel(), ctypes.c_void_p(st.cuda_stream))
+        self._check(code)
+        self._stream = st
+        self._workspace = workspace
 
     def rhs(self):
         b = self.empty()

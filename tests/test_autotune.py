@@ -51,3 +51,21 @@ def test_cache_round_trip(tmp_path):
 def test_tie_prefers_larger_p():
     ts = [at.Trial(32, 16, 1e-11, 1.0, 0.1, 4.0, True), at.Trial(32, 20, 1e-13, 1.0, 0.1, 4.0, True)]
     assert at.select(ts).p == 20
+
+
+def test_frequency_bands_get_their_own_order():
+    """The truncation error grows with k (Theorems 1-2; Sec. 4 closes with p
+    growing with frequency): with an error model err = (k/32)^p each band is
+    tuned at its largest frequency and the higher bands get larger p."""
+    def factory(ka):
+        def measure(leaf, p):
+            return ((ka / 32.0) ** p, 1.0, 0.1 + 0.001 * p + 0.01 * leaf / 16)
+        return measure
+    kas = [0.2 + 0.25 * i for i in range(32)]
+    bands = at.autotune_bands({"g": 4}, kas, [0.0], n_bands=4, target_err=1e-10, measure_factory=factory)
+    assert [len(b) for b, _ in bands] == [8, 8, 8, 8]
+    assert sorted(sum((b for b, _ in bands), [])) == sorted(kas)
+    ps = [ch.p for _, ch in bands]
+    assert ps == sorted(ps) and ps[0] < ps[-1]
+    for band, ch in bands:
+        assert (max(band) / 32.0) ** ch.p <= 1e-10

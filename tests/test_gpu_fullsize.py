@@ -130,7 +130,7 @@ def test_timed_apply_matches_overlapped_apply(pfm, key, bpc):
     P2P, else a join kernel adds it) equals the in-order timed apply bit
     for bit."""
     wl = {"square_4x4": W.square_4x4_sweep, "square_8x8": W.square_8x8, "hexagon_16x16": W.hexagon_16x16}[key]()
-    prob = pfm.Problem.from_workload(wl, p2p_blocks_per_cu=bpc)
+    prob = pfm.Problem.from_workload(wl, p2p_blocks_per_cu=bpc, self_fft=False)
     prob.set_wave(2.0, 0.1)
     st = prob.stats()
     _say("overlapped vs in-order:", key, bpc, "split", st["p2p_split"], "circulant", st["n_near_circulant"],
@@ -149,6 +149,31 @@ def test_timed_apply_matches_overlapped_apply(pfm, key, bpc):
     assert all(v >= 0 for v in stages.values()) and tot > 0
 
 
+@pytest.mark.parametrize("key", ["square_4x4", "square_8x8", "hexagon_16x16"])
+def test_self_fft_apply_timed_overlapped_and_tree(pfm, key):
+    """With the fibres' own blocks applied by FFT (the default): the overlapped
+    apply (FFT apply and P2P on the side stream, the downward pass adding the
+    far part after the join) equals the in-order timed apply bit for bit, and
+    differs from the apply with every pair in the tree by no more than the
+    FMM truncation of the in-fibre far pairs (p = 24)."""
+    wl = {"square_4x4": W.square_4x4_sweep, "square_8x8": W.square_8x8, "hexagon_16x16": W.hexagon_16x16}[key]()
+    prob = pfm.Problem.from_workload(wl)
+    prob.set_wave(2.0, 0.1)
+    st = prob.stats()
+    assert st["self_fft"] == 1 and st["n_m2l_int"] == 0 and st["p2p_split"] == 1
+    psi = torch.tensor(W.random_density(prob.n, 10), device="cuda")
+    a = prob.matvec(psi).clone()
+    stages, tot, b = prob.matvec_timed(psi, reps=2)
+    c = prob.matvec(psi).clone()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    tree = pfm.Problem.from_workload(wl, self_fft=False)
+    tree.set_wave(2.0, 0.1)
+    t = tree.matvec(psi)
+    d = float(torch.max(torch.abs(a - t)) / torch.max(torch.abs(t)))
+    _say("own blocks by FFT vs tree:", key, d, "stages", stages)
+    assert d < 1e-9
+
+
 def test_row_windows_equal_cached_rows_square_8x8(pfm):
     """At the benchmark configuration the P2P row windows in LDS give the
     cache path's sums bit for bit."""
@@ -156,7 +181,7 @@ def test_row_windows_equal_cached_rows_square_8x8(pfm):
     psi = torch.tensor(W.random_density(2 * wl.M * wl.n_elem, 12), device="cuda")
     ys, st = [], []
     for cached in (False, True):
-        prob = pfm.Problem.from_workload(wl, p2p_cached_rows=cached)
+        prob = pfm.Problem.from_workload(wl, p2p_cached_rows=cached, self_fft=False)
         prob.set_wave(3.338709677419355, 0.0)
         ys.append(prob.matvec(psi).clone())
         st.append(prob.stats())
@@ -275,7 +300,7 @@ def test_mixed_apply_with_circulant_rows_hexagon(pfm):
     blocks of the FP64 apply; on this block every near pair is a same-fibre
     pair, so the two applies agree exactly."""
     wl = W.hexagon_16x16()
-    prob = pfm.Problem.from_workload(wl, precision=pfm.MIXED)
+    prob = pfm.Problem.from_workload(wl, precision=pfm.MIXED, self_fft=False)
     prob.set_wave(wl.ka[0], wl.theta[0])
     st = prob.stats()
     assert st["p2p_split"] == 1 and st["n_near_circulant"] > st["n_near_stored"]

@@ -119,6 +119,7 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     return np.linalg.norm(y - ref) / np.linalg.norm(ref), prob
 
 
+@pytest.mark.parametrize("self_fft", [True, False])
 @pytest.mark.parametrize("key,p,leaf,tol", [
     ("tiny", 40, 32, 1e-10),
     ("tiny", 16, 32, 1e-5),
@@ -128,10 +129,20 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     ("sq2x2close", 40, 16, 1e-10),
     ("sq4x2close", 40, 16, 1e-10),
 ])
-def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol):
-    _say("matvec:", key, "p =", p, "leaf =", leaf)
-    err, prob = _matvec_err(pfm, key, p, leaf)
-    _say("  rel err", err, prob.stats())
+def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, self_fft):
+    """Both forms of a fibre's own image-0 block: applied by FFT (self_fft,
+    the default; only pairs between fibres and with images in the tree) and
+    through the tree like every other pair."""
+    _say("matvec:", key, "p =", p, "leaf =", leaf, "self_fft =", self_fft)
+    err, prob = _matvec_err(pfm, key, p, leaf, self_fft=self_fft)
+    st = prob.stats()
+    _say("  rel err", err, st)
+    # the FFT form needs a power of two elements per fibre (sq3x1 has 96)
+    n = _WL[key][0].n_elem
+    eligible = self_fft and 8 <= n <= 512 and n & (n - 1) == 0
+    assert st["self_fft"] == (1 if eligible else 0)
+    if eligible:
+        assert st["n_m2l_int"] == 0 and st["n_near_circulant"] == 0
     assert err < tol
 
 
@@ -144,7 +155,7 @@ def test_circulant_self_rows_equal_stored_blocks(pfm, key):
     psi = W.random_density(2 * wl.M * wl.n_elem, 21)
     ys, st = [], []
     for store in (False, True):
-        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=16, store_self_blocks=store)
+        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=16, store_self_blocks=store, self_fft=False)
         prob.set_wave(ka, th)
         ys.append(prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy())
         st.append(prob.stats())
@@ -166,7 +177,7 @@ def test_p2p_row_windows_equal_cached_rows(pfm, key, leaf):
     psi = W.random_density(2 * wl.M * wl.n_elem, 23)
     ys, st = [], []
     for cached in (False, True):
-        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=leaf, p2p_cached_rows=cached)
+        prob = pfm.Problem.from_workload(wl, p=24, leaf_max=leaf, p2p_cached_rows=cached, self_fft=False)
         prob.set_wave(ka, th)
         ys.append(prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy())
         st.append(prob.stats())
@@ -177,10 +188,16 @@ def test_p2p_row_windows_equal_cached_rows(pfm, key, leaf):
 
 
 def test_matvec_error_decreases_with_p(pfm):
-    errs = [(_matvec_err(pfm, "sq2x2", p, 16)[0]) for p in (8, 16, 24, 32)]
-    _say("matvec error vs p:", errs)
+    """Through the tree the truncation error of eq. 10 falls with p (Theorems
+    1-2); with the own blocks applied by FFT only the pairs between fibres
+    and with images carry it, so the error there is never larger."""
+    errs = [(_matvec_err(pfm, "sq2x2", p, 16, self_fft=False)[0]) for p in (8, 16, 24, 32)]
+    errs_fft = [(_matvec_err(pfm, "sq2x2", p, 16)[0]) for p in (8, 16, 24, 32)]
+    _say("matvec error vs p:", errs, "own blocks by FFT:", errs_fft)
     for a, b in zip(errs, errs[1:]):
         assert b < a
+    for a, b in zip(errs_fft, errs):
+        assert a <= 1.5 * b
 
 
 @pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2"])

@@ -25,6 +25,38 @@ def warm():
     return w
 
 
+warm_train = pytest.importorskip("paper_1910_10863_amd.warm_train")
+
+
+def test_target_stats_standardise_and_shrink(warm):
+    """The library's statistics of training targets (mean, standard deviation
+    with n - 1) and the validation shrink s_o = clamp(1 - sum (y - t)^2 /
+    sum t^2, 0, 1), folded into the last layer, against numpy in FP64."""
+    rng = np.random.default_rng(8)
+    sizes = (5, 32, 48)
+    n = 40
+    net = warm.MLP(sizes, max_batch=n, seed=5)
+    t = (rng.standard_normal((n, 48)) * rng.uniform(0.1, 3.0, 48) + rng.uniform(-1, 1, 48)).astype(np.float32)
+    tt = torch.tensor(t, device="cuda")
+    mean, std = net.target_stats(tt)
+    assert np.allclose(mean.cpu().numpy(), t.astype(np.float64).mean(0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(std.cpu().numpy(), t.astype(np.float64).std(0, ddof=1), rtol=1e-6)
+    z = net.standardise(tt, mean, std).cpu().numpy()
+    ref = (t - mean.cpu().numpy()) / std.cpu().numpy()
+    assert np.max(np.abs(z - ref)) < 1e-5
+    x = rng.uniform(-1, 1, (n, 5)).astype(np.float32)
+    xt = torch.tensor(x, device="cuda")
+    y = net.forward(xt).cpu().numpy().astype(np.float64)
+    shrink, err = net.validation_shrink(xt, tt)
+    tv = t.astype(np.float64)
+    s_ref = np.clip(1 - ((y - tv) ** 2).sum(0) / np.maximum((tv ** 2).sum(0), 1e-30), 0, 1)
+    assert np.allclose(shrink.cpu().numpy(), s_ref, rtol=1e-5, atol=1e-6)
+    e_ref = np.sqrt(((s_ref * y - tv) ** 2).sum() / (tv ** 2).sum())
+    assert abs(err - e_ref) < 1e-5 * e_ref
+    y2 = net.forward(xt).cpu().numpy()
+    assert np.allclose(y2, s_ref * y, rtol=1e-4, atol=1e-5)
+
+
 def _flat(params):
     return np.concatenate([np.concatenate([Wm.ravel(), b]) for Wm, b in params])
 
@@ -153,7 +185,7 @@ def test_modes_vs_oracle(warm):
 
 
 def test_bad_start_falls_back_to_cold(warm):
-    prob = warm.block_problem(0.3, 10.0, 1.1, 2)
+    prob = warm_train.block_problem(0.3, 10.0, 1.1, 2)
     prob.set_batch(2.5, [0.2, 0.9])
     xc, ic = prob.solve_batch()
     x0 = xc.clone()
@@ -167,7 +199,7 @@ def test_bad_start_falls_back_to_cold(warm):
 def test_augmented_cycle_never_loses_to_cold(warm):
     """Augmentation with the exact solution converges at once; with a
     random vector it takes no more iterations than the cold start."""
-    prob = warm.block_problem(0.3, 10.0, 1.1, 3)
+    prob = warm_train.block_problem(0.3, 10.0, 1.1, 3)
     prob.set_batch(2.5, [0.2, 0.9, 1.3])
     xc, ic = prob.solve_batch()
     xa, ia = prob.solve_batch(x0=xc, augment=True)
@@ -197,13 +229,13 @@ def test_trained_network_gain(warm):
         return g, th
 
     g_tr, t_tr = groups(60, 1)
-    data = warm.generate(g_tr, t_tr)
+    data = warm_train.generate(g_tr, t_tr)
     _say("generated", data.x.shape[0], "solves in", data.seconds, "s; mean cold iters", data.iters.mean())
-    net = warm.train(data, epochs=300, batch=64, lr=2e-3, seed=2)
+    net = warm_train.train(data, epochs=300, batch=64, lr=2e-3, seed=2)
     _say("loss", net.losses[0], "->", net.losses[-1], "in", net.train_seconds, "s")
     assert net.losses[-1] < 0.1 * net.losses[0]
     g_te, t_te = groups(4, 99)
-    res = warm.evaluate(net, g_te, t_te, tols=(1e-4, 1e-8))
+    res = warm_train.evaluate(net, g_te, t_te, tols=(1e-4, 1e-8))
     _say("evaluation", res)
     assert res["median_start_residual"] < 0.1
     loose, tight = res["tolerances"]["1e-04"], res["tolerances"]["1e-08"]

@@ -20,6 +20,8 @@ import numpy as np
 
 SQUARE = 0
 HEXAGON = 1
+CIRCLE = 0
+ROUND_SQUARE = 1
 
 # Mercury fibres in water, the contrast used by the benchmark workloads.
 MERCURY = dict(rho=13500.0, c=1450.0)
@@ -45,6 +47,7 @@ class Workload:
     leaf_max: int           # max elements per quadtree leaf
     tol: float = 1e-8       # GMRES relative residual
     eta: float = 0.0        # coupling constant; <= 0 means eta = k
+    shape: int = 0          # CIRCLE, or ROUND_SQUARE (radii are then the curve's size parameter r)
 
     @property
     def M(self) -> int:
@@ -146,3 +149,39 @@ def warm_start_block(r: float, rho_ratio: float, c_ratio: float) -> Workload:
     return Workload("square_4x4_N256_warm", SQUARE, 1.0, 4, 4, 256, _full(16, r),
                     rho_ratio * WATER["rho"], c_ratio * WATER["c"], WATER["rho"], WATER["c"],
                     [], [], 24, 32)
+
+
+# The liquid phononic crystals of the band-gap experiments (Sec. 4): water
+# fibres (rho 1000, c 1500) in a mercury matrix (rho 13600, c 1450), lattice
+# constant a = 0.5, M_H = 6 rows by M_L = 4 columns, 256 points per fibre,
+# incidence along +x (theta = 0), filling fractions 35 % and 50 %.
+WATER_SEC4 = dict(rho=1000.0, c=1500.0)
+MERCURY_SEC4 = dict(rho=13600.0, c=1450.0)
+BANDGAP_CASES = ("circle_square", "circle_triangle", "round_square_square")
+
+
+def bandgap_block(case: str, filling: float, n_elem: int = 256, M_L: int = 4, M_H: int = 6,
+                  p: int = 24, leaf_max: int = 64) -> Workload:
+    """Block of one band-gap case.  The size parameter follows from the
+    filling fraction: the fibre area (pi r^2 for a circle, 23 pi r^2 / 2 for
+    the round square) over the lattice cell area (a^2 square, sqrt(3)/2 a^2
+    for the hexagonal, i.e. triangular, lattice)."""
+    a = 0.5
+    if case == "circle_square":
+        lattice, shape, r = SQUARE, CIRCLE, a * math.sqrt(filling / math.pi)
+    elif case == "circle_triangle":
+        lattice, shape, r = HEXAGON, CIRCLE, a * math.sqrt(filling * math.sqrt(3.0) / (2.0 * math.pi))
+    elif case == "round_square_square":
+        lattice, shape, r = SQUARE, ROUND_SQUARE, a * math.sqrt(2.0 * filling / (23.0 * math.pi))
+    else:
+        raise ValueError(case)
+    return Workload(f"bandgap_{case}_ff{int(round(100 * filling))}", lattice, a, M_L, M_H, n_elem,
+                    _full(M_L * M_H, r), WATER_SEC4["rho"], WATER_SEC4["c"], MERCURY_SEC4["rho"],
+                    MERCURY_SEC4["c"], [], [0.0], p, leaf_max, shape=shape)
+
+
+def bandgap_frequencies(n: int = 150, f_max: float = 1.5) -> np.ndarray:
+    """Normalised frequencies ka / (2 pi) of the ETC sweep, cell-centred on
+    (0, f_max] so that none falls on a Wood anomaly of the 6-row block at
+    theta = 0 (ka / (2 pi) = j / 6)."""
+    return (np.arange(n) + 0.5) * f_max / n
