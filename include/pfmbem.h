@@ -271,6 +271,21 @@ pfm_status pfm_set_wave(pfm_problem* pb, double ka, double theta);
 /* d_y = (I - A) d_psi, both 2*M*N complex128 on the device.  No allocation. */
 pfm_status pfm_matvec(pfm_problem* pb, const void* d_psi, void* d_y);
 
+/* For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * d_y = (I - A) d_psi exactly as pfm_matvec, with the apply's scratch
+ * (multipole moments, M2L partial expansions and their sums, the lattice
+ * convolution's spectra, the far part, split P2P partial rows) taken from a
+ * fixed device array of PFM_STATIC_SCRATCH_BYTES that the library holds on
+ * each GPU until the process ends, instead of from the handle's workspace.
+ * Allocates nothing.  The handle's GPU must be the current device.
+ * PFM_EINVAL when the apply needs more scratch than the array holds (the
+ * message gives the size).  Every call on one GPU shares its array, and the
+ * array keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other handles) race. */
+#define PFM_STATIC_SCRATCH_BYTES (64u << 20)
+pfm_status pfm_matvec_static(pfm_problem* pb, const void* d_psi, void* d_y);
+
 /* The same operator with the near-field blocks stored in complex64 (each
  * block entry widened to FP64 before its multiply-add; densities and sums
  * stay FP64) and the far field in FP64 (the apply used inside PFM_MIXED

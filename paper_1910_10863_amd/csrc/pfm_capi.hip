@@ -19,7 +19,31 @@
 using namespace pfm;
 
 
+// The fixed device array behind pfm_matvec_static: its per-apply scratch
+// (multipole moments, M2L partial expansions and their sums, the lattice
+// convolution's spectra, the far part, split P2P partial rows).  Each GPU the
+// library runs on holds one copy until the process ends.  In host code the
+// name stands for a host-side shadow, never for device memory: the device
+// address comes from hipGetSymbolAddress, once per device, at pfm_create.
+static __device__ __align__(256) unsigned char scratch[PFM_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t static_scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 const char* status_name(pfm_status s) {
   switch (s) {
@@ -320,6 +344,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       pb.n_cu = 0;
     pb.device = dev;
     pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : 1;
+    // this device's address of the fixed scratch array of pfm_matvec_static
+    hipError_t e = static_scratch_address(dev, &pb.static_scratch);
+    if (e != hipSuccess)
+      return bail(fail(pb, PFM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)));
   }
   // discretisation on the device
   int E = pb.E;
@@ -1087,6 +1115,52 @@ pfm_status pfm_matvec(pfm_problem* h, const void* d_psi, void* d_y) {
   Problem& pb = h->p;
   if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
   HIPCHK(pb, apply_operator(pb, (const cd*)d_psi, (cd*)d_y, nullptr));
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_static(pfm_problem* h, const void* d_psi, void* d_y) {
+  if (!h || !d_psi || !d_y) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  if (!pb.static_scratch) return fail(pb, PFM_EDEVICE, "no address of the static scratch array");
+  int dev = -1;
+  HIPCHK(pb, hipGetDevice(&dev));
+  if (dev != pb.device) return fail(pb, PFM_EINVAL, "the handle's GPU is not the current device");
+  const size_t NP = 2 * (size_t)pb.opt.p + 1;
+  const size_t nc = pb.hp.cells.size();
+  const size_t pxy = (size_t)pb.lat_px * pb.lat_py;
+  struct Use {
+    cd** ptr;
+    size_t bytes;
+  } use[] = {
+      {&pb.d_mpole, nc * 2 * NP * sizeof(cd)},
+      {&pb.d_epart, (size_t)std::max(1, pb.n_mchunks) * NP * sizeof(cd)},
+      {&pb.d_part, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd)},
+      {&pb.d_far, 2 * (size_t)pb.E * sizeof(cd)},
+      {&pb.d_p2ppart, pb.p2p_split > 1 ? (size_t)pb.p2p_split * 2 * pb.E * sizeof(cd) : sizeof(cd)},
+      {&pb.d_lat_xhat, pb.lat_fft ? (size_t)pb.lat_ns * pxy * NP * sizeof(cd) : 0},
+      {&pb.d_lat_lhat, pb.lat_fft ? (size_t)pb.lat_ns * pxy * NP * sizeof(cd) : 0},
+  };
+  size_t total = 0;
+  for (const Use& u : use) total += ws_align(u.bytes);
+  if (total > (size_t)PFM_STATIC_SCRATCH_BYTES)
+    return fail(pb, PFM_EINVAL, "the apply needs " + std::to_string(total) + " bytes of scratch, above the " +
+                                    std::to_string((size_t)PFM_STATIC_SCRATCH_BYTES) + " of the static array");
+  // point the apply's scratch buffers into the array for this call only (the
+  // kernels take the addresses as arguments when they are queued)
+  cd* saved[sizeof(use) / sizeof(use[0])];
+  char* at = (char*)pb.static_scratch;
+  for (size_t i = 0; i < sizeof(use) / sizeof(use[0]); ++i) {
+    saved[i] = *use[i].ptr;
+    if (use[i].bytes) *use[i].ptr = (cd*)at;
+    at += ws_align(use[i].bytes);
+  }
+  // the moments start from zero as in a fresh workspace (the array keeps the
+  // last call's contents)
+  hipError_t e = launch_fill_zero(pb.d_mpole, use[0].bytes, pb.stream);
+  if (e == hipSuccess) e = apply_operator(pb, (const cd*)d_psi, (cd*)d_y, nullptr);
+  for (size_t i = 0; i < sizeof(use) / sizeof(use[0]); ++i) *use[i].ptr = saved[i];
+  HIPCHK(pb, e);
   return PFM_OK;
 }
 

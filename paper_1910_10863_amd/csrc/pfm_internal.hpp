@@ -237,6 +237,7 @@ struct Problem {
   // pairs between fibres and with images, and only the exterior channel
   bool self_fft = false;
   int device = 0;                       // the GPU the handle was created on
+  void* static_scratch = nullptr;       // that GPU's address of the fixed scratch array (pfm_matvec_static)
 };
 
 bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);

@@ -1853,6 +1853,20 @@ __global__ void k_to_c64(long long n, const cd* __restrict__ in, float2* __restr
   }
 }
 
+// Clear a buffer of n16 16-byte words with vector stores (a kernel rather
+// than a memset node, so that the clear may sit inside a captured graph).
+__global__ void k_fill_zero(double2* __restrict__ p, long long n16) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) p[i] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n16 = (long long)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s, (double2*)p, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_near_to_c64(Problem& pb) {
   long long n = 4 * pb.n_near_stored;
   if (n == 0 || !pb.d_near32) return hipSuccess;

@@ -26,6 +26,8 @@ hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev)
 hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y);
 // B = pb.B members at once over phase-free near blocks; vectors [B][2E]
 hipError_t apply_operator_batch(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev);
+// zero bytes (a multiple of 16) at p on stream s
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // complex128 near blocks -> complex64 copy
 hipError_t launch_near_to_c64(Problem& pb);
 // upward pass only (P2M and M2M), for tests

@@ -84,7 +84,7 @@ MAX_BATCH = 16
 EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_matvec_mixed", "pfm_rhs", "pfm_solve",
            "pfm_precond_apply", "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
-           "pfm_matvec_batch_timed", "pfm_workspace_size", "pfm_bind",
+           "pfm_matvec_batch_timed", "pfm_workspace_size", "pfm_bind", "pfm_matvec_static",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
 
 
@@ -104,6 +104,7 @@ def lib():
     L.pfm_set_wave.argtypes = [P, ctypes.c_double, ctypes.c_double]
     L.pfm_matvec.argtypes = [P, vp, vp]
     L.pfm_matvec_mixed.argtypes = [P, vp, vp]
+    L.pfm_matvec_static.argtypes = [P, vp, vp]
     L.pfm_workspace_size.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.pfm_bind.argtypes = [P, vp, ctypes.c_size_t, vp]
     dp = ctypes.POINTER(ctypes.c_double)
@@ -240,6 +241,14 @@ class Problem:
             raise ValueError("psi has the wrong length")
         y = self.empty() if out is None else out
         self._check(self._L.pfm_matvec_mixed(self._h, _ptr(psi), _ptr(y)))
+        return y
+
+    def matvec_static(self, psi, out=None):
+        """The apply with its scratch in the library's fixed device array."""
+        if psi.numel() != self.n:
+            raise ValueError("psi has the wrong length")
+        y = self.empty() if out is None else out
+        self._check(self._L.pfm_matvec_static(self._h, _ptr(psi), _ptr(y)))
         return y
 
     def workspace_size(self, batch: int = 0) -> int:
