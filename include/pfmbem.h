@@ -122,7 +122,7 @@ typedef struct {
  *             launch (0: 3 when most near pairs use circulant rows, else 2;
  *             at most 8)
  *  p2p_unroll  source columns whose block entries a P2P wavefront keeps in
- *             flight at once: 1, 2 or 4 (0: 1)
+ *             flight at once: 1, 2 or 4 (0: 4 with self_mode 0 in effect, else 1)
  *  store_self_blocks  0: near pairs of a fibre with itself (image 0) use one
  *             circulant row per fibre (the N chords of a circle are rotations
  *             of each other, so their 2x2 block depends only on the index

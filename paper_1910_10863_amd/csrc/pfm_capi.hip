@@ -162,7 +162,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
-  dfree(pb.d_p2p_items); dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
+  dfree(pb.d_p2p_items); dfree(pb.d_p2p_rowtasks); dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
   dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x);
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
@@ -343,7 +343,9 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
           hipDeviceGetAttribute(&pb.n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess))
       pb.n_cu = 0;
     pb.device = dev;
-    pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : 1;
+    // with the own blocks by FFT the P2P stream is a few leaves of stored
+    // blocks, bound by load latency: four columns' loads in flight per wave
+    pb.p2p_unroll = opt->p2p_unroll > 0 ? opt->p2p_unroll : (pb.self_fft ? 4 : 1);
     // this device's address of the fixed scratch array of pfm_matvec_static
     hipError_t e = static_scratch_address(dev, &pb.static_scratch);
     if (e != hipSuccess)
@@ -585,11 +587,20 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     {
       // with the own blocks by FFT P2P adds into the rows only where a leaf
       // has stored near columns
-      std::vector<int> items;
+      std::vector<int> items, rowtasks;
       for (int li = 0; li < nl; ++li)
-        if (cptr[li + 1] > cptr[li] || qptr[li + 1] > qptr[li]) items.push_back(li);
+        if (cptr[li + 1] > cptr[li] || qptr[li + 1] > qptr[li]) {
+          items.push_back(li);
+          const Cell& L = hp.cells[hp.leaves[li]];
+          for (int r = 0; r < L.eend - L.ebeg; ++r) {
+            rowtasks.push_back(li);
+            rowtasks.push_back(r);
+          }
+        }
       pb.n_p2p_items = (int)items.size();
+      pb.n_p2p_rowtasks = (int)(rowtasks.size() / 2);
       CK(upload(pb, &pb.d_p2p_items, items));
+      CK(upload(pb, &pb.d_p2p_rowtasks, rowtasks));
     }
     CK(upload(pb, &pb.d_cols_ptr, cptr));
     CK(upload(pb, &pb.d_col_psi, cpsi));

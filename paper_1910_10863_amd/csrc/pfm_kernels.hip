@@ -1011,10 +1011,47 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int first, int stride, i
   for (int j = 0; j < H::NS; ++j) out[j] = acc[j];
 }
 
+// Sum over the 64 lanes of a wavefront of NA complex slots held by every
+// lane, by recursive halving: at each step a lane keeps half of its live
+// slots (the upper half when its lane bit m is set), sends the other half to
+// lane ^ m and adds what that lane sends for the half it keeps.  With
+// V = 32 live slots at the start (NA <= 32) five steps leave lanes 2s and
+// 2s + 1 with halves of slot s, and one more exchange completes both; with
+// V = 64 six steps leave lane s with slot s.  Slots past NA are zero.
+// Returns the total of slot lane >> 1 (V = 32) or slot lane (V = 64).
+template <int NA>
+__device__ __forceinline__ cd wave_sum_slots(cd (&a)[NA], int lane) {
+  constexpr int V = NA <= 32 ? 32 : 64;
+  static_assert(NA <= 64, "at most 64 slots");
+  constexpr int STEPS = V == 32 ? 5 : 6;
+#pragma unroll
+  for (int step = 0; step < STEPS; ++step) {
+    const int h = (V >> step) >> 1, m = 32 >> step;
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      if (i >= h) break;
+      const cd lo = i < NA ? a[i] : mkc(0, 0);
+      const cd hi = i + h < NA ? a[i + h] : mkc(0, 0);
+      const cd keep = up ? hi : lo, send = up ? lo : hi;
+      cd got;
+      got.x = __shfl_xor(send.x, m, 64);
+      got.y = __shfl_xor(send.y, m, 64);
+      if (i < NA) a[i] = cadd(keep, got);
+    }
+  }
+  cd r = a[0];
+  if (V == 32) {
+    r.x += __shfl_xor(r.x, 1, 64);
+    r.y += __shfl_xor(r.y, 1, 64);
+  }
+  return r;
+}
+
 // PS groups of two wavefronts per (leaf, channel): group g walks the Gauss
-// points g*64 + lane, g*64 + lane + 64 PS, ...; with one channel (the fibres'
-// own blocks by FFT) PS = 2 doubles the waves of a launch that is otherwise
-// latency-bound.  The partial moments meet in LDS in a fixed order.
+// points g*64 + lane, g*64 + lane + 64 PS, ...  Each wavefront sums its
+// lanes' partial moments by a butterfly across the lanes (no LDS round
+// trips); with PS > 1 the groups' sums meet in LDS in a fixed order.
 template <int P, int PS>
 __global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
                                              const double4* __restrict__ tgeo, const double* __restrict__ trh,
@@ -1024,12 +1061,11 @@ __global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves
                                              long long psi_stride, long long mp_stride) {
   constexpr int NP = 2 * P + 1;
   constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
-  // one transpose buffer, used by the wavefronts in turn (keeps the LDS
-  // footprint small so that P2M co-resides with the concurrent work)
-  __shared__ cd red[64][NA];
+  constexpr int SPL = NA <= 32 ? 2 : 1;         // lanes per slot after the butterfly
   // the leaf's rows (from its descriptor and the row-ordered geometry) are
   // loaded once by the first wavefront; the point loop then reads only LDS
   __shared__ P2MRows rw;
+  __shared__ cd grp_sum[PS > 1 ? PS - 1 : 1][2][64];
   psi += blockIdx.z * psi_stride;
   mpole += blockIdx.z * mp_stride;
   const int cell = leaves[blockIdx.x];
@@ -1059,33 +1095,22 @@ __global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves
     p2m_half<P, 0, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
   else
     p2m_half<P, 1, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
-  cd* out = mpole + ((size_t)cell * 2 + ch) * NP;
-  // thread t keeps the sum of slot t of each half over the groups
-  cd hold[2] = {mkc(0, 0), mkc(0, 0)};
-  for (int pass = 0; pass < 2 * PS; ++pass) {
-    if (wv == pass) {
-#pragma unroll
-      for (int j = 0; j < NA; ++j) red[lane][j] = acc[j];
-    }
+  cd tot = wave_sum_slots<NA>(acc, lane);
+  const int slot = SPL == 2 ? lane >> 1 : lane;
+  const bool writer = SPL == 2 ? (lane & 1) == 0 : true;
+  if (PS > 1) {
+    if (grp > 0 && writer && slot < NA) grp_sum[grp - 1][half][slot] = tot;
     __syncthreads();
-    const int h = pass & 1;
-    const int lo = h == 0 ? 0 : P / 2 + 1, hi = h == 0 ? P / 2 : P;
-    const int ns = (hi - lo + 1) + (hi - (lo > 0 ? lo : 1) + 1);
-    if ((int)threadIdx.x < ns) {
-      cd sres = mkc(0, 0);
-      for (int r = 0; r < 64; ++r) sres = cadd(sres, red[r][threadIdx.x]);
-      hold[h] = cadd(hold[h], sres);
-    }
-    __syncthreads();
+    if (grp == 0)
+      for (int g2 = 1; g2 < PS; ++g2)
+        if (writer && slot < NA) tot = cadd(tot, grp_sum[g2 - 1][half][slot]);
   }
-  for (int h = 0; h < 2; ++h) {
-    const int lo = h == 0 ? 0 : P / 2 + 1, hi = h == 0 ? P / 2 : P;
-    const int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
-    const int j = threadIdx.x;
-    if (j < npos + nneg) {
-      int n = j < npos ? lo + j : -((lo > 0 ? lo : 1) + (j - npos));
-      out[n + P] = hold[h];
-    }
+  // slot -> order of this wavefront's half: orders +m at [m - LO], then -m
+  const int lo = half == 0 ? 0 : P / 2 + 1, hi = half == 0 ? P / 2 : P;
+  const int npos = hi - lo + 1, nneg = hi - (lo > 0 ? lo : 1) + 1;
+  if (grp == 0 && writer && slot < npos + nneg) {
+    const int n = slot < npos ? lo + slot : -((lo > 0 ? lo : 1) + (slot - npos));
+    mpole[((size_t)cell * 2 + ch) * NP + n + P] = tot;
   }
 }
 
@@ -1703,6 +1728,51 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
   }
 }
 
+// P2P of the stored near blocks by target row, for one wave when each
+// fibre's own block is applied by FFT and only pairs between fibres or with
+// images are stored (a few leaves): one wavefront per row of a leaf with
+// stored columns, the lanes over the leaf's stored columns, the lanes' sums
+// added by a butterfly and into y, which already holds the rest of the row.
+// Many short waves instead of a few long, latency-bound ones.
+template <typename C>
+__global__ void __launch_bounds__(64) k_p2p_rows(const int2* __restrict__ tasks, const int* __restrict__ leaves,
+                                                 const int* __restrict__ ebeg, const int* __restrict__ eend,
+                                                 const int* __restrict__ psi_idx, int N,
+                                                 const long long* __restrict__ leaf_blk,
+                                                 const int* __restrict__ cols_ptr, const int* __restrict__ col_psi,
+                                                 const C* __restrict__ blocks, const cd* __restrict__ psi, cd* y) {
+  const int2 t = tasks[blockIdx.x];
+  const int li = t.x, r = t.y, lane = threadIdx.x;
+  const int D = leaves[li];
+  const int db = ebeg[D], rows = eend[D] - db;
+  const int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
+  // entry (column k, component c, row r) of the leaf's stored region
+  const C* bl = blocks + 4 * leaf_blk[li] + r;
+  const size_t cs = 4 * (size_t)rows;
+  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
+  for (int k = lane; k < ncol; k += 64) {
+    const C* b = bl + (size_t)k * cs;
+    const int pi = col_psi[k0 + k];
+    const cd ph = psi[pi], vp = psi[pi + N];
+    a1 = cfma(p2p_wide(b[0]), ph, a1);
+    a1 = cfma(p2p_wide(b[rows]), vp, a1);
+    a2 = cfma(p2p_wide(b[2 * rows]), ph, a2);
+    a2 = cfma(p2p_wide(b[3 * rows]), vp, a2);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a1.x += __shfl_xor(a1.x, m, 64);
+    a1.y += __shfl_xor(a1.y, m, 64);
+    a2.x += __shfl_xor(a2.x, m, 64);
+    a2.y += __shfl_xor(a2.y, m, 64);
+  }
+  if (lane == 0) {
+    const int pr = psi_idx[db + r];
+    y[pr] = cadd(y[pr], a1);
+    y[pr + N] = cadd(y[pr + N], a2);
+  }
+}
+
 // Batched P2P: the NB members of a batch share one set of near blocks
 // stored without the quasi-periodic phase; member b sees image m of a source
 // through alpha_b^m, applied to the densities as they are staged in LDS.
@@ -1975,6 +2045,13 @@ static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const c
   const int* item_leaf = pb.self_fft ? pb.d_p2p_items : nullptr;
   int n_leaves = pb.self_fft ? pb.n_p2p_items : (int)pb.hp.leaves.size();
   if (n_leaves == 0) return;
+  if (pb.self_fft && B == 0) {
+    // one wavefront per target row of those leaves
+    hipLaunchKernelGGL((k_p2p_rows<C>), dim3(pb.n_p2p_rowtasks), dim3(64), 0, ps,
+                       reinterpret_cast<const int2*>(pb.d_p2p_rowtasks), pb.d_leaves, pb.d_ebeg, pb.d_eend,
+                       pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks, d_psi, d_y);
+    return;
+  }
   int items = n_leaves * pb.p2p_split;
   int p2p_grid = pb.p2p_grid > 0 ? std::min(pb.p2p_grid, items) : items;
   if (B == 0) {
@@ -2005,11 +2082,12 @@ static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const c
 //   y = P psi + near(psi) + far(psi),
 // P the block-diagonal operator of the fibres' own blocks (identity included),
 // near the stored P2P blocks of pairs between fibres or with images, far the
-// exterior FMM chain.  Overlapped: P and the P2P run on the side stream and
-// write y; the chain runs on the caller's stream and its downward pass, after
-// the join, adds the far part into y.  With stage events everything runs in
-// order on the caller's stream: the chain writes the far part to its buffer,
-// P and P2P write y, and the join kernel adds the far part.
+// exterior FMM chain.  Everything runs in order on the caller's stream: P
+// writes y, P2P adds the near part, and the chain's downward pass adds the far
+// part (a second stream for P and P2P was 4.5 us slower on the square 8x8
+// block: the crossings between hardware queues cost more than the overlap
+// gains).  With stage events the chain comes first and writes the far part to
+// its buffer, P and P2P write y, and the join kernel adds the far part.
 template <int P, typename C>
 static hipError_t apply_self_fft(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B) {
   const int nb = B > 0 ? B : 1;
@@ -2025,13 +2103,10 @@ static hipError_t apply_self_fft(Problem& pb, const C* blocks, const cd* d_psi, 
     (void)hipEventRecord(ev[6], pb.stream);
     return hipGetLastError();
   }
-  (void)hipEventRecord(pb.ev_fork, pb.stream);
-  (void)hipStreamWaitEvent(pb.side, pb.ev_fork, 0);
-  hipError_t e = launch_precond(pb, d_psi, d_y, false, nb, pb.side);
+  hipError_t e = launch_precond(pb, d_psi, d_y, false, nb, pb.stream);
   if (e != hipSuccess) return e;
-  launch_p2p_any<P, C>(pb, pb.side, blocks, d_psi, d_y, B);
-  (void)hipEventRecord(pb.ev_join, pb.side);
-  fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, pb.ev_join, d_y);
+  launch_p2p_any<P, C>(pb, pb.stream, blocks, d_psi, d_y, B);
+  fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, d_y);
   return hipGetLastError();
 }
 
