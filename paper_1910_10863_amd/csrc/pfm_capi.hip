@@ -162,7 +162,8 @@ void free_all(Problem& pb) {
   dfree(pb.d_m2li_ptr); dfree(pb.d_m2li_src); dfree(pb.d_m2li_off);
   dfree(pb.d_near_ptr); dfree(pb.d_near_src); dfree(pb.d_near_m); dfree(pb.d_near_tgt);
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
-  dfree(pb.d_p2p_items); dfree(pb.d_p2p_rowtasks); dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
+  dfree(pb.d_p2p_items); dfree(pb.d_p2p_rowtasks); dfree(pb.d_p2p_rowoff); dfree(pb.d_leaf_near_t0);
+  dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
   dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x);
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
@@ -445,6 +446,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     if (pb.n_cu > 0)
       pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : (pb.p2p_on_side ? 3 : 2)) * pb.n_cu;
   }
+  std::vector<long long> leaf_blk_host;   // per leaf: start of its stored region (entries)
   // near-block storage of the other pairs: per target leaf its stored pairs
   // one after the other; with equal fibres, a region (the stored blocks of one
   // target leaf) is stored once for every leaf that has the same region
@@ -555,6 +557,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     pb.n_near_copies = (int)cp_src.size();
     CK(upload(pb, &pb.d_near_blk, blk));
     CK(upload(pb, &pb.d_leaf_blk, leaf_blk));
+    leaf_blk_host = leaf_blk;
     CK(upload(pb, &pb.d_near_uniq, uniq));
     if (!cp_src.empty()) {
       CK(upload(pb, &pb.d_near_cp_src, cp_src)); CK(upload(pb, &pb.d_near_cp_dst, cp_dst));
@@ -587,20 +590,30 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     {
       // with the own blocks by FFT P2P adds into the rows only where a leaf
       // has stored near columns
-      std::vector<int> items, rowtasks;
+      std::vector<int> items, rowtasks, near_t0(std::max(1, nl), -1);
+      std::vector<long long> rowoff;
       for (int li = 0; li < nl; ++li)
         if (cptr[li + 1] > cptr[li] || qptr[li + 1] > qptr[li]) {
           items.push_back(li);
           const Cell& L = hp.cells[hp.leaves[li]];
-          for (int r = 0; r < L.eend - L.ebeg; ++r) {
-            rowtasks.push_back(li);
-            rowtasks.push_back(r);
+          const int rows = L.eend - L.ebeg;
+          near_t0[li] = (int)(rowtasks.size() / 4);
+          for (int r = 0; r < rows; ++r) {
+            const int e = hp.elem_of[L.ebeg + r], f = e / pb.N;
+            rowtasks.push_back(2 * f * pb.N + (e - f * pb.N));
+            rowtasks.push_back(cptr[li]);
+            rowtasks.push_back(cptr[li + 1] - cptr[li]);
+            rowtasks.push_back(rows);
+            rowoff.push_back(4 * leaf_blk_host[li] + r);
           }
         }
       pb.n_p2p_items = (int)items.size();
-      pb.n_p2p_rowtasks = (int)(rowtasks.size() / 2);
+      pb.n_p2p_rowtasks = (int)(rowtasks.size() / 4);
       CK(upload(pb, &pb.d_p2p_items, items));
       CK(upload(pb, &pb.d_p2p_rowtasks, rowtasks));
+      CK(upload(pb, &pb.d_p2p_rowoff, rowoff));
+      CK(upload(pb, &pb.d_leaf_near_t0, near_t0));
+      if (pb.self_fft) ws_add(pb, &pb.d_near_rows, 2 * (size_t)std::max(1, pb.n_p2p_rowtasks) * sizeof(cd), 0);
     }
     CK(upload(pb, &pb.d_cols_ptr, cptr));
     CK(upload(pb, &pb.d_col_psi, cpsi));

@@ -170,8 +170,12 @@ struct Problem {
   int p2p_unroll = 1;                   // source columns in flight per P2P wavefront
   int* d_p2p_items = nullptr;           // self_fft: the target leaves with stored near columns
   int n_p2p_items = 0;
-  int* d_p2p_rowtasks = nullptr;        // self_fft: (leaf, row) of every row of those leaves
+  int* d_p2p_rowtasks = nullptr;        // self_fft: per row of those leaves (phi index, first column,
+                                        // columns, rows of the leaf)
+  long long* d_p2p_rowoff = nullptr;    // and the entry offset of the row in the leaf's block region
   int n_p2p_rowtasks = 0;
+  int* d_leaf_near_t0 = nullptr;        // per leaf: its first row task (-1: none)
+  cd* d_near_rows = nullptr;            // [task][2] the row tasks' sums (one wave)
   cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table

@@ -1323,7 +1323,8 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
                                               const cd* __restrict__ part, const cd* __restrict__ jtab, int n_joff,
                                               int N, double k, double k1, double eta, double varrho,
                                               cd* __restrict__ far, long long part_stride, long long far_stride,
-                                              int add_into) {
+                                              int add_into, const int* __restrict__ leaf_near_t0,
+                                              const cd* __restrict__ near_buf) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64;
   __shared__ cd sJ[2][NT], sA[2][NP], sL[2][NP], sS[2][3][P + 2], sT[2][3][P + 2];
   __shared__ cd su[64], sd[64];
@@ -1449,9 +1450,16 @@ __global__ void __launch_bounds__(128) k_down(const int* __restrict__ ldesc, con
     cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
     const cd f1 = csub(u, su[lane]), f2 = cmul(c, csub(dv, cscale(sd[lane], varrho)));
     if (add_into) {
-      // far is the output y, which already holds psi + near (the join)
-      far[pi] = cadd(far[pi], f1);
-      far[pi + N] = cadd(far[pi + N], f2);
+      // far is the output y, which already holds psi + near (the join), or
+      // P psi, with the near sums of this leaf's rows in near_buf
+      cd y1 = far[pi], y2 = far[pi + N];
+      const int t0 = leaf_near_t0 ? leaf_near_t0[blockIdx.x] : -1;
+      if (t0 >= 0) {
+        y1 = cadd(y1, near_buf[2 * (t0 + lane)]);
+        y2 = cadd(y2, near_buf[2 * (t0 + lane) + 1]);
+      }
+      far[pi] = cadd(y1, f1);
+      far[pi + N] = cadd(y2, f2);
     } else {
       far[pi] = f1;
       far[pi + N] = f2;
@@ -1728,28 +1736,23 @@ __global__ void __launch_bounds__(64 * P2P_WAVES, 2) k_p2p(
   }
 }
 
-// P2P of the stored near blocks by target row, for one wave when each
-// fibre's own block is applied by FFT and only pairs between fibres or with
-// images are stored (a few leaves): one wavefront per row of a leaf with
-// stored columns, the lanes over the leaf's stored columns, the lanes' sums
-// added by a butterfly and into y, which already holds the rest of the row.
-// Many short waves instead of a few long, latency-bound ones.
+// P2P of the stored near blocks by target row, when each fibre's own block
+// is applied by FFT and only pairs between fibres or with images are stored
+// (a few leaves): one wavefront per row of a leaf with stored columns, the
+// lanes over the leaf's stored columns, the lanes' sums added by a butterfly.
+// A row task is described by (index of phi of the row in Psi, first stored
+// column of the leaf, stored columns, rows of the leaf) and the offset of its
+// row in the leaf's block region (entries), so that the sums start two loads
+// away from the task index.
 template <typename C>
-__global__ void __launch_bounds__(64) k_p2p_rows(const int2* __restrict__ tasks, const int* __restrict__ leaves,
-                                                 const int* __restrict__ ebeg, const int* __restrict__ eend,
-                                                 const int* __restrict__ psi_idx, int N,
-                                                 const long long* __restrict__ leaf_blk,
-                                                 const int* __restrict__ cols_ptr, const int* __restrict__ col_psi,
-                                                 const C* __restrict__ blocks, const cd* __restrict__ psi, cd* y) {
-  const int2 t = tasks[blockIdx.x];
-  const int li = t.x, r = t.y, lane = threadIdx.x;
-  const int D = leaves[li];
-  const int db = ebeg[D], rows = eend[D] - db;
-  const int k0 = cols_ptr[li], ncol = cols_ptr[li + 1] - k0;
-  // entry (column k, component c, row r) of the leaf's stored region
-  const C* bl = blocks + 4 * leaf_blk[li] + r;
+__device__ __forceinline__ void p2p_row_sums(const int4 d, const long long off, const int* __restrict__ col_psi,
+                                             const C* __restrict__ blocks, const cd* __restrict__ psi, int N,
+                                             int lane, cd& a1, cd& a2) {
+  const int k0 = d.y, ncol = d.z, rows = d.w;
+  const C* bl = blocks + off;
   const size_t cs = 4 * (size_t)rows;
-  cd a1 = mkc(0, 0), a2 = mkc(0, 0);
+  a1 = mkc(0, 0);
+  a2 = mkc(0, 0);
   for (int k = lane; k < ncol; k += 64) {
     const C* b = bl + (size_t)k * cs;
     const int pi = col_psi[k0 + k];
@@ -1766,11 +1769,64 @@ __global__ void __launch_bounds__(64) k_p2p_rows(const int2* __restrict__ tasks,
     a2.x += __shfl_xor(a2.x, m, 64);
     a2.y += __shfl_xor(a2.y, m, 64);
   }
-  if (lane == 0) {
-    const int pr = psi_idx[db + r];
-    y[pr] = cadd(y[pr], a1);
-    y[pr + N] = cadd(y[pr + N], a2);
+}
+
+// The row tasks added into y (which already holds the rest of the rows).
+template <typename C>
+__global__ void __launch_bounds__(64) k_p2p_rows(const int4* __restrict__ tasks, const long long* __restrict__ toff,
+                                                 const int* __restrict__ col_psi, const C* __restrict__ blocks,
+                                                 const cd* __restrict__ psi, int N, cd* y) {
+  const int4 d = tasks[blockIdx.x];
+  cd a1, a2;
+  p2p_row_sums<C>(d, toff[blockIdx.x], col_psi, blocks, psi, N, threadIdx.x, a1, a2);
+  if (threadIdx.x == 0) {
+    y[d.x] = cadd(y[d.x], a1);
+    y[d.x + N] = cadd(y[d.x + N], a2);
   }
+}
+
+// The first launch of the apply with each fibre's own block by FFT (one
+// wave): workgroups f < M apply fibre f's block to its rows, y = P psi (as
+// k_pc_apply); the workgroups after them take the row tasks of the stored
+// near pairs, eight per workgroup (one per wavefront), and leave each row's
+// sums in near_buf for the downward pass to add.
+template <typename C>
+__global__ void __launch_bounds__(PC_THREADS) k_self_apply(const cd* in, cd* out, const cd* __restrict__ coef,
+                                                           const cd* __restrict__ tw, int N, int logN, int M,
+                                                           const int4* __restrict__ tasks,
+                                                           const long long* __restrict__ toff, int ntasks,
+                                                           const int* __restrict__ col_psi,
+                                                           const C* __restrict__ blocks, cd* __restrict__ near_buf) {
+  extern __shared__ cd pcs[];
+  if ((int)blockIdx.x >= M) {
+    const int t = ((int)blockIdx.x - M) * (PC_THREADS / 64) + (threadIdx.x >> 6);
+    if (t >= ntasks) return;
+    cd a1, a2;
+    p2p_row_sums<C>(tasks[t], toff[t], col_psi, blocks, in, N, threadIdx.x & 63, a1, a2);
+    if ((threadIdx.x & 63) == 0) {
+      near_buf[2 * t] = a1;
+      near_buf[2 * t + 1] = a2;
+    }
+    return;
+  }
+  const int f = blockIdx.x;
+  cd* X = pcs;
+  cd* Y = pcs + 2 * N;
+  const cd* src = in + (size_t)f * 2 * N;  // phi_f then varphi_f
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  __syncthreads();
+  cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
+  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    const cd u = H[kk], v = H[N + kk];
+    H[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
+    H[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+  }
+  __syncthreads();
+  const cd* Z = pc_fft(H, H == X ? Y : X, 2, N, logN, tw, false);
+  const double sc = 1.0 / N;
+  cd* dst = out + (size_t)f * 2 * N;
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) dst[i] = cscale(Z[i], sc);
 }
 
 // Batched P2P: the NB members of a batch share one set of near blocks
@@ -1969,7 +2025,7 @@ template <int P>
 // channel carries pairs, so the chain runs channel 0 alone (the upward pass of
 // the test hook keeps both).
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B,
-                      hipEvent_t join = nullptr, cd* y_join = nullptr) {
+                      hipEvent_t join = nullptr, cd* y_join = nullptr, bool near_in_down = false) {
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
@@ -2011,7 +2067,8 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(64 * nch), 0, s, pb.d_ldesc,
                      reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
                      pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
-                     y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0);
+                     y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0,
+                     near_in_down ? pb.d_leaf_near_t0 : nullptr, pb.d_near_rows);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
 
@@ -2048,8 +2105,8 @@ static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const c
   if (pb.self_fft && B == 0) {
     // one wavefront per target row of those leaves
     hipLaunchKernelGGL((k_p2p_rows<C>), dim3(pb.n_p2p_rowtasks), dim3(64), 0, ps,
-                       reinterpret_cast<const int2*>(pb.d_p2p_rowtasks), pb.d_leaves, pb.d_ebeg, pb.d_eend,
-                       pb.d_psi_idx, pb.N, pb.d_leaf_blk, pb.d_cols_ptr, pb.d_col_psi, blocks, d_psi, d_y);
+                       reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, pb.d_col_psi, blocks,
+                       d_psi, pb.N, d_y);
     return;
   }
   int items = n_leaves * pb.p2p_split;
@@ -2101,6 +2158,19 @@ static hipError_t apply_self_fft(Problem& pb, const C* blocks, const cd* d_psi, 
     hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb.stream, n, pb.d_far, d_psi,
                        pb.d_p2ppart, 1, d_y);
     (void)hipEventRecord(ev[6], pb.stream);
+    return hipGetLastError();
+  }
+  if (B == 0) {
+    // one launch for P psi and the stored pairs' row sums, which the
+    // downward pass adds with the far part
+    const int ntask = pb.n_p2p_rowtasks, tpb = PC_THREADS / 64;
+    const int extra = (ntask + tpb - 1) / tpb;
+    const size_t lds = 4 * (size_t)pb.N * sizeof(cd);
+    hipLaunchKernelGGL((k_self_apply<C>), dim3(pb.M + extra), dim3(PC_THREADS), lds, pb.stream, d_psi, d_y,
+                       pb.d_pc_fwd, pb.d_pc_tw, pb.N, pb.pc_logN, pb.M,
+                       reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, ntask, pb.d_col_psi,
+                       blocks, pb.d_near_rows);
+    fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, d_y, ntask > 0);
     return hipGetLastError();
   }
   hipError_t e = launch_precond(pb, d_psi, d_y, false, nb, pb.stream);
