@@ -218,6 +218,24 @@ def batched_sweep_leg(n_single_ka: int, tune: bool):
     out["batched"]["rel_err_vs_dense_lu"] = golden_members(x, kas, th)
     print(f"batched sweep: {out['batched']}", file=sys.stderr, flush=True)
     pb.close()
+    # the same sweep with the batched apply replayed from a captured HIP graph
+    # (one graph per frequency, captured when the frequency is set)
+    pbg = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, max_batch=len(th), use_graph=True)
+    pbg.sweep(kas[:1], th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg, infg = pbg.sweep(kas, th)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
+    flg = [i for row in infg for i in row]
+    out["batched_graph"] = {"solves_per_s": len(flg) / dtg, "seconds": dtg, "n_solves": len(flg),
+                            "failed": int(sum(i["status"] != 0 for i in flg)),
+                            "mean_iters": float(np.mean([i["iters"] for i in flg])),
+                            "max_rel_residual": float(max(i["rel_residual"] for i in flg)),
+                            "speed_vs_launched": dt / dtg,
+                            "max_rel_diff_vs_launched": float(((xg - x).norm(dim=2) / x.norm(dim=2)).max())}
+    print(f"batched sweep, graph-captured apply: {out['batched_graph']}", file=sys.stderr, flush=True)
+    pbg.close()
     # the same batched sweep right-preconditioned by the fibres' free-space
     # self blocks (shared by the angles of a frequency)
     if wl.n_elem & (wl.n_elem - 1) == 0 and 8 <= wl.n_elem <= 512:

@@ -160,7 +160,15 @@ typedef struct {
  *             N a power of two, 8 <= N <= 512.  pfm_solve_batch and
  *             pfm_sweep use it too (the blocks do not depend on theta, so a
  *             batch shares them), as do start vectors and the augmented
- *             start (use_x0 = 3), whose guess u enters as P u. */
+ *             start (use_x0 = 3), whose guess u enters as P u.
+ *  tree_on_host  0: the quadtrees and interaction lists (Sec. 3.1) are built
+ *             by GPU kernels (element keys sorted per fibre, cells level by
+ *             level, one dual traversal per fibre pair and image), which
+ *             give the host construction's plan bit for bit; where they do not
+ *             apply (more than 4096 elements per fibre, or a level of one
+ *             fibre's tree with more than 512 cells) the host builds it
+ *             (pfm_stats.tree_on_device tells which ran).  1: the host
+ *             construction (the reference the GPU build is tested against). */
 typedef struct {
   int p;
   int leaf_max;
@@ -181,6 +189,7 @@ typedef struct {
   int direct_lattice_m2l;
   int precond;
   int self_mode;
+  int tree_on_host;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -225,10 +234,11 @@ typedef struct {
   long long n_device_allocs;   /* device allocations the library has made for this handle */
   double device_alloc_bytes;   /* their total size */
   int self_fft;                /* 1: each fibre's own image-0 block is applied by FFT (self_mode 0) */
+  int tree_on_device;          /* 1: the plan's tree and lists were built by the GPU kernels */
 } pfm_stats;
 
-/* Build the plan: discretisation (on the GPU), quadtrees and interaction
- * lists (host).  Fills *out on success.  Errors: PFM_EINVAL for bad sizes,
+/* Build the plan: discretisation, quadtrees and interaction lists (on the
+ * GPU unless tree_on_host = 1).  Fills *out on success.  Errors: PFM_EINVAL for bad sizes,
  * overlapping fibres (2 r >= lattice spacing) or unsupported options. */
 pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat,
                       const pfm_options* opt, pfm_problem** out);
@@ -400,6 +410,15 @@ pfm_status pfm_test_lattice(pfm_problem* pb, double* sums, double* offsets, int*
  * Any output pointer may be NULL. */
 pfm_status pfm_test_moments(pfm_problem* pb, const void* d_psi, double* moments,
                             double* centres, int* cellinfo, int* elem_order);
+
+/* Digests of the built plan (Sec. 3.1), for comparing the GPU tree build
+ * with the host construction: out[0..7] = 64-bit FNV-1a hashes of, in order,
+ * the cells (every field), the level ranges with the element order, leaves
+ * and fibre roots, the leaf-to-ancestor lists with their offsets, the upward
+ * lists, the fibre offsets with their image ranges and pair table, the M2L
+ * lists with their translation vectors, the interior M2L lists, and the near
+ * lists with their block offsets and the image range. */
+pfm_status pfm_test_plan_digest(const pfm_problem* pb, unsigned long long* out);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpfmbem.so")
-SOURCES = ["pfm_kernels.hip", "pfm_capi.hip", "pfm_warm.hip", "pfm_plan.cpp"]
+SOURCES = ["pfm_kernels.hip", "pfm_capi.hip", "pfm_warm.hip", "pfm_tree.hip", "pfm_plan.cpp"]
+# the GPU tree build reproduces the host plan's distances bit for bit: no
+# contraction of multiplies and adds into FMAs in that file
+EXTRA = {"pfm_tree.hip": ["-ffp-contract=off"]}
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
@@ -23,7 +26,7 @@ def build(verbose: bool = False) -> str:
         src = os.path.join(SRC, s)
         obj = os.path.join(bdir, s + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmd = [hipcc] + FLAGS + lang + ["-c", src, "-o", obj]
+        cmd = [hipcc] + FLAGS + EXTRA.get(s, []) + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

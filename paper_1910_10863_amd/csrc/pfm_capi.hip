@@ -232,6 +232,26 @@ void tail_rule(double k, double H, double gap, double xmax, int nu_max, std::vec
 
 }  // namespace
 
+namespace {
+// 64-bit FNV-1a over the bytes of values
+struct Fnv {
+  unsigned long long h = 1469598103934665603ULL;
+  template <typename T>
+  void add(const T& v) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+    for (size_t i = 0; i < sizeof(T); ++i) {
+      h ^= b[i];
+      h *= 1099511628211ULL;
+    }
+  }
+  template <typename T>
+  void vec(const std::vector<T>& v) {
+    add(v.size());
+    for (const T& x : v) add(x);
+  }
+};
+}  // namespace
+
 extern "C" {
 
 pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pfm_options* opt,
@@ -269,6 +289,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->precond != 0 && opt->precond != 1) return bail(fail(pb, PFM_EINVAL, "precond must be 0 or 1"));
   if (opt->self_mode != 0 && opt->self_mode != 1) return bail(fail(pb, PFM_EINVAL, "self_mode must be 0 or 1"));
+  if (opt->tree_on_host != 0 && opt->tree_on_host != 1)
+    return bail(fail(pb, PFM_EINVAL, "tree_on_host must be 0 or 1"));
   if (opt->precond == 1 && (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0))
     return bail(fail(pb, PFM_EINVAL, "precond = 1 needs n_elem a power of two in 8..512"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -367,20 +389,42 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   double* d_ends = nullptr;
   CK(dev_alloc(pb, (void**)&d_ends, 4 * (size_t)E * sizeof(double)));
   CK(launch_discretise(pb, d_ends));
-  std::vector<double> ends(4 * (size_t)E), mid(2 * (size_t)E), mx(E), my(E);
-  CK(hipMemcpy(ends.data(), d_ends, ends.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // quadtrees and interaction lists: GPU kernels, or the host construction
+  // (asked for, or where the GPU build does not apply)
+  std::vector<double> mx(E), my(E);
   CK(hipMemcpy(mx.data(), pb.d_mx, E * sizeof(double), hipMemcpyDeviceToHost));
   CK(hipMemcpy(my.data(), pb.d_my, E * sizeof(double), hipMemcpyDeviceToHost));
+  bool planned = false;
+  pb.tree_on_device = false;
+  if (!opt->tree_on_host) {
+    std::string why;
+    planned = build_device_plan(pb, pb.d_mx, pb.d_my, d_ends, why);
+    pb.tree_on_device = planned;
+    if (!planned && why.find("leaf holds more than 64") != std::string::npos) {
+      (void)hipFree(d_ends);
+      free_all(pb);
+      return bail(fail(pb, PFM_EINVAL, "tree construction failed"));
+    }
+    if (!planned && why.rfind("more than", 0) != 0 && why.rfind("a level", 0) != 0) {
+      (void)hipFree(d_ends);
+      free_all(pb);
+      return bail(fail(pb, PFM_EDEVICE, "GPU tree build: " + why));
+    }
+  }
+  if (!planned) {
+    std::vector<double> ends(4 * (size_t)E), mid(2 * (size_t)E);
+    CK(hipMemcpy(ends.data(), d_ends, ends.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int e = 0; e < E; ++e) {
+      mid[2 * e] = mx[e];
+      mid[2 * e + 1] = my[e];
+    }
+    if (!build_host_plan(pb, mid, ends)) {
+      (void)hipFree(d_ends);
+      free_all(pb);
+      return bail(fail(pb, PFM_EINVAL, "tree construction failed"));
+    }
+  }
   (void)hipFree(d_ends);
-  for (int e = 0; e < E; ++e) {
-    mid[2 * e] = mx[e];
-    mid[2 * e + 1] = my[e];
-  }
-
-  if (!build_host_plan(pb, mid, ends)) {
-    free_all(pb);
-    return bail(fail(pb, PFM_EINVAL, "tree construction failed"));
-  }
   const HostPlan& hp = pb.hp;
   int nc = (int)hp.cells.size();
   std::vector<double> cx(nc), cy(nc);
@@ -1893,6 +1937,30 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->n_device_allocs = pb.n_dev_allocs;
   st->device_alloc_bytes = pb.dev_alloc_bytes;
   st->self_fft = pb.self_fft ? 1 : 0;
+  st->tree_on_device = pb.tree_on_device ? 1 : 0;
+  return PFM_OK;
+}
+
+
+pfm_status pfm_test_plan_digest(const pfm_problem* h, unsigned long long* out) {
+  if (!h || !out) return PFM_EINVAL;
+  const HostPlan& hp = h->p.hp;
+  Fnv d[8];
+  for (const Cell& c : hp.cells) {
+    d[0].add(c.cx); d[0].add(c.cy); d[0].add(c.half); d[0].add(c.rho);
+    d[0].add(c.level); d[0].add(c.fiber); d[0].add(c.parent); d[0].add(c.first_child);
+    d[0].add(c.n_child); d[0].add(c.ebeg); d[0].add(c.eend); d[0].add(c.leaf); d[0].add(c.leaf_index);
+  }
+  d[1].vec(hp.level_beg); d[1].vec(hp.elem_of); d[1].vec(hp.leaves); d[1].vec(hp.root_of_fibre);
+  d[1].add(hp.depth);
+  d[2].vec(hp.joff_xy); d[2].vec(hp.anc_ptr); d[2].vec(hp.anc); d[2].vec(hp.anc_off);
+  d[3].vec(hp.up_cells); d[3].vec(hp.up_ptr); d[3].vec(hp.up_src); d[3].vec(hp.up_off);
+  d[4].vec(hp.root_off_xy); d[4].vec(hp.root_off_mrange); d[4].vec(hp.root_pair_off);
+  d[5].vec(hp.m2l_ptr); d[5].vec(hp.m2l_src); d[5].vec(hp.m2l_off); d[5].vec(hp.m2l_m); d[5].vec(hp.off_xy);
+  d[6].vec(hp.m2li_ptr); d[6].vec(hp.m2li_src); d[6].vec(hp.m2li_off);
+  d[7].vec(hp.near_ptr); d[7].vec(hp.near_src); d[7].vec(hp.near_m); d[7].vec(hp.near_tgt);
+  d[7].vec(hp.near_blk); d[7].add(hp.n_near_entries); d[7].add(hp.m_min); d[7].add(hp.m_max);
+  for (int i = 0; i < 8; ++i) out[i] = d[i].h;
   return PFM_OK;
 }
 

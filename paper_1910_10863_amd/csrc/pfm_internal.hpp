@@ -242,11 +242,17 @@ struct Problem {
   // applied by FFT as a block-circulant operator; the tree holds only the
   // pairs between fibres and with images, and only the exterior channel
   bool self_fft = false;
+  bool tree_on_device = false;          // the plan was built by the GPU kernels
   int device = 0;                       // the GPU the handle was created on
   void* static_scratch = nullptr;       // that GPU's address of the fixed scratch array (pfm_matvec_static)
 };
 
 bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vector<double>& ends);
+// The same plan built by GPU kernels from the device copies of the element
+// midpoints (natural order) and chord end points [E][4]; false with the
+// reason when the build does not apply (more than 4096 elements per fibre, a
+// level of one fibre's tree with more than 512 cells) or fails.
+bool build_device_plan(Problem& pb, const double* d_mx, const double* d_my, const double* d_ends, std::string& why);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
 }  // namespace pfm

@@ -286,7 +286,8 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
         int mc = (int)std::floor(oy / pb.H);
         int span = (int)std::ceil(R / pb.H) + 2;
         for (int m = mc - span; m <= mc + span; ++m) {
-          double d = std::hypot(ox, oy - m * pb.H);
+          const double t = oy - m * pb.H;
+          double d = std::sqrt(ox * ox + t * t);
           if (!(2.0 * rho_max <= mac * d)) {
             if (mlo > mhi) { mlo = m; mhi = m; }
             mlo = std::min(mlo, m);

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
                 ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
                 ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int),
-                ("self_mode", ctypes.c_int)]
+                ("self_mode", ctypes.c_int), ("tree_on_host", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
                 ("lattice_m2l_grid", ctypes.c_int), ("workspace_bytes", ctypes.c_double),
                 ("workspace_bound", ctypes.c_int), ("batch_capacity", ctypes.c_int),
                 ("n_device_allocs", ctypes.c_longlong), ("device_alloc_bytes", ctypes.c_double),
-                ("self_fft", ctypes.c_int)]
+                ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int)]
 
 
 FP64 = 0
@@ -85,7 +85,7 @@ EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_ma
            "pfm_precond_apply", "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
            "pfm_matvec_batch_timed", "pfm_workspace_size", "pfm_bind", "pfm_matvec_static",
-           "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments"]
+           "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments", "pfm_test_plan_digest"]
 
 
 def lib():
@@ -132,6 +132,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int)]
     L.pfm_test_moments.argtypes = [P, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.pfm_test_plan_digest.argtypes = [P, ctypes.POINTER(ctypes.c_ulonglong)]
     for name in EXPORTS:
         if name not in ("pfm_last_error", "pfm_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -166,7 +167,8 @@ class Problem:
                  wood_margin: float = 0.0, precision: int = FP64, inner_tol: float = 0.0,
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
-                 direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True):
+                 direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True,
+                 tree_on_host: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -178,7 +180,8 @@ class Problem:
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
                       max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
-                      1 if direct_lattice_m2l else 0, 1 if precond else 0, 0 if self_fft else 1)
+                      1 if direct_lattice_m2l else 0, 1 if precond else 0, 0 if self_fft else 1,
+                      1 if tree_on_host else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
@@ -318,6 +321,12 @@ class Problem:
         st = Stats()
         self._check(self._L.pfm_get_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def plan_digest(self) -> list:
+        """Eight 64-bit digests of the plan's tree and lists (pfm_test_plan_digest)."""
+        out = (ctypes.c_ulonglong * 8)()
+        self._check(self._L.pfm_test_plan_digest(self._h, out))
+        return list(out)
 
     def matvec_timed(self, psi, reps: int = 10):
         y = self.empty()
