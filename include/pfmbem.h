@@ -149,6 +149,16 @@ typedef struct {
  *             fibre only, leaves the FMM altogether.  1: those pairs go
  *             through the tree like the others (near pairs by P2P from the
  *             circulant rows or stored blocks, far pairs by M2L at k and k1).
+ *             With 0, when moreover no pair between fibres or with images
+ *             needs P2P and every M2L entry joins two fibre roots (fibres
+ *             farther apart than the admissibility ratio allows for their
+ *             radii), the roots' multipole moments come from each fibre's
+ *             discrete Fourier modes (element e is element 0 turned by
+ *             2 pi e / N, so the moment of order n is A_n phihat(n) +
+ *             B_n varphihat(n)) and the roots' local expansions are
+ *             evaluated at the midpoints by a synthesis over the orders:
+ *             no P2M at leaves, M2M, L2L or L2P per leaf
+ *             (pfm_stats.spectral_roots).  2: as 0 without this.
  *  precond    0: plain GMRES; 1: pfm_solve runs GMRES (with PFM_MIXED the
  *             inner GMRES of the refinement)
  *             right-preconditioned by the fibres' free-space self blocks of
@@ -235,6 +245,7 @@ typedef struct {
   double device_alloc_bytes;   /* their total size */
   int self_fft;                /* 1: each fibre's own image-0 block is applied by FFT (self_mode 0) */
   int tree_on_device;          /* 1: the plan's tree and lists were built by the GPU kernels */
+  int spectral_roots;          /* 1: fibre roots' moments and locals by Fourier modes (self_mode 0) */
 } pfm_stats;
 
 /* Build the plan: discretisation, quadtrees and interaction lists (on the
@@ -340,9 +351,10 @@ pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
 /* Apply the operator reps times with every stage in order on the bound
  * stream and return the mean duration (milliseconds, HIP events) of each
  * stage: stage_ms[6] = [P2M, M2M, M2L including the lattice sums, downward
- * pass with L2P, P2P, join of near and far parts], and of the whole apply
- * in *total_ms.  (pfm_matvec overlaps the FMM chain with
- * P2P on a second stream; this call does not.) */
+ * pass with L2P, near part (each fibre's own block by FFT and P2P of the
+ * stored pairs), join of near and far parts], and of the whole apply in
+ * *total_ms.  The stages write the far part to a buffer of their own and a
+ * join kernel adds it (pfm_matvec fuses the join into the downward pass). */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);
 
@@ -383,6 +395,14 @@ pfm_status pfm_solve_batch(pfm_problem* pb, const void* d_b, void* d_x, int use_
  * PFM_ENOCONV / PFM_EWOOD if any record has it, else PFM_OK. */
 pfm_status pfm_sweep(pfm_problem* pb, int n_ka, const double* ka, int B, const double* theta, void* d_x,
                      pfm_info* infos);
+
+/* One stage of the FMM chain of the current wave (0 P2M, 1 M2M, 2 M2L
+ * with the lattice sums, 3 downward pass with L2P) launched reps times back
+ * to back on the bound stream after one whole chain for d_psi, which leaves
+ * every stage's inputs in place; *ms_per_launch = the mean duration of one
+ * launch (HIP events around the reps launches).  For measuring a kernel
+ * in steady state; PFM_EINVAL for a bad stage or reps < 1. */
+pfm_status pfm_matvec_stage_timed(pfm_problem* pb, const void* d_psi, int stage, int reps, double* ms_per_launch);
 
 /* Batched apply timed like pfm_matvec_timed (stage_ms[6], total_ms). */
 pfm_status pfm_matvec_batch_timed(pfm_problem* pb, const void* d_psi, void* d_y, int reps, double* stage_ms,

@@ -288,7 +288,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   if (opt->precision != PFM_FP64 && opt->precision != PFM_MIXED)
     return bail(fail(pb, PFM_EINVAL, "precision must be PFM_FP64 or PFM_MIXED"));
   if (opt->precond != 0 && opt->precond != 1) return bail(fail(pb, PFM_EINVAL, "precond must be 0 or 1"));
-  if (opt->self_mode != 0 && opt->self_mode != 1) return bail(fail(pb, PFM_EINVAL, "self_mode must be 0 or 1"));
+  if (opt->self_mode < 0 || opt->self_mode > 2) return bail(fail(pb, PFM_EINVAL, "self_mode must be 0, 1 or 2"));
   if (opt->tree_on_host != 0 && opt->tree_on_host != 1)
     return bail(fail(pb, PFM_EINVAL, "tree_on_host must be 0 or 1"));
   if (opt->precond == 1 && (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0))
@@ -315,7 +315,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   // Every fibre is a circle cut into N equal chords, so its own image-0 block
   // (both wavenumbers, near and far pairs) is block circulant; with N a power
   // of two it is applied by the FFTs of the preconditioner's transforms.
-  pb.self_fft = opt->self_mode == 0 && !opt->store_self_blocks && geo->shape == PFM_CIRCLE && pb.N >= 8 &&
+  pb.self_fft = opt->self_mode != 1 && !opt->store_self_blocks && geo->shape == PFM_CIRCLE && pb.N >= 8 &&
                 pb.N <= 512 && (pb.N & (pb.N - 1)) == 0;
 
   pb.rho_f = mat->rho_fiber;
@@ -782,6 +782,13 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   ws_add(pb, &pb.d_latpart, 0, (size_t)n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd));
   ws_add(pb, &pb.d_srule, 2 * (size_t)LAT_RULE_POINTS * sizeof(double), 0);
   (void)n_off;
+  // fibre roots by their Fourier modes: with the own blocks by FFT, when no
+  // pair needs P2P and every M2L entry joins two roots
+  pb.spec_root = pb.self_fft && opt->self_mode == 0 && hp.near_src.empty() && hp.m2li_src.empty();
+  for (int c = 0; c < nc && pb.spec_root; ++c)
+    for (int q = hp.m2l_ptr[c]; q < hp.m2l_ptr[c + 1]; ++q)
+      if (hp.cells[c].level != 0 || hp.cells[hp.m2l_src[q]].level != 0) pb.spec_root = false;
+  if (pb.spec_root) ws_add(pb, &pb.d_spec_tab, (size_t)pb.M * 4 * NP * sizeof(cd), 0);
   {
     // M2L work: per (channel, cell) the entries (source cell, table row, image),
     // contiguous, cut into chunks of at most M2L_CHUNK entries (one wavefront
@@ -875,6 +882,11 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       size_t i = (size_t)ch * nc + c;
       return ccptr[i + 1] > ccptr[i] ? ccptr[i] : -1;
     };
+    if (pb.spec_root) {
+      std::vector<int> rows(pb.M);
+      for (int f = 0; f < pb.M; ++f) rows[f] = sum_row(0, hp.root_of_fibre[f]);
+      CK(upload(pb, &pb.d_spec_row, rows));
+    }
     for (int li = 0; li < nl; ++li) {
       const Cell& L = hp.cells[hp.leaves[li]];
       int* d = &ldesc[8 * (size_t)li];
@@ -1262,6 +1274,18 @@ pfm_status pfm_matvec_timed(pfm_problem* h, const void* d_psi, void* d_y, int re
   if (stage_ms)
     for (int s = 0; s < 6; ++s) stage_ms[s] = acc[s] / reps;
   if (total_ms) *total_ms = tot / reps;
+  return PFM_OK;
+}
+
+pfm_status pfm_matvec_stage_timed(pfm_problem* h, const void* d_psi, int stage, int reps, double* ms_per_launch) {
+  if (!h || !d_psi || !ms_per_launch || stage < 0 || stage > 3 || reps < 1) return PFM_EINVAL;
+  Problem& pb = h->p;
+  if (!pb.wave_ready) return fail(pb, PFM_ESTATE, "pfm_set_wave first");
+  HIPCHK(pb, time_chain_stage(pb, (const cd*)d_psi, stage, reps, pb.ev[0], pb.ev[1]));
+  HIPCHK(pb, hipEventSynchronize(pb.ev[1]));
+  float ms = 0.f;
+  HIPCHK(pb, hipEventElapsedTime(&ms, pb.ev[0], pb.ev[1]));
+  *ms_per_launch = ms / reps;
   return PFM_OK;
 }
 
@@ -1938,6 +1962,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->device_alloc_bytes = pb.dev_alloc_bytes;
   st->self_fft = pb.self_fft ? 1 : 0;
   st->tree_on_device = pb.tree_on_device ? 1 : 0;
+  st->spectral_roots = pb.spec_root ? 1 : 0;
   return PFM_OK;
 }
 

@@ -176,6 +176,11 @@ struct Problem {
   int n_p2p_rowtasks = 0;
   int* d_leaf_near_t0 = nullptr;        // per leaf: its first row task (-1: none)
   cd* d_near_rows = nullptr;            // [task][2] the row tasks' sums (one wave)
+  // fibre roots by their Fourier modes (spec_root: with the own blocks by FFT,
+  // no near pairs and only root-to-root M2L entries)
+  bool spec_root = false;
+  int* d_spec_row = nullptr;            // [M] the root's M2L sum row (-1: none)
+  cd* d_spec_tab = nullptr;             // [M][4][2p+1] per frequency
   cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table

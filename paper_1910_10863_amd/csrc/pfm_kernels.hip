@@ -1829,6 +1829,183 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_apply(const cd* in, cd* out
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) dst[i] = cscale(Z[i], sc);
 }
 
+// ---------------------------------------------------------------------------
+// Fibre roots through the fibre's Fourier modes.  On a circle cut into N
+// equal chords, element e is element 0 turned by t_e = 2 pi e / N about the
+// centre c, and under a turn by t the harmonics of Sec. 3.2 go as
+//   Jm_n(R_t v) = Jm_n(v) e^{-i n t},  Jp_l(R_t v) = Jp_l(v) e^{i l t},
+// with the normal turning along.  So the multipole moments of the whole
+// fibre about its centre (the P2M sums over all its elements) are
+//   M_n = A_n phihat(n mod N) + B_n varphihat(n mod N),
+//   phihat(j) = sum_e phi_e e^{-2 pi i j e / N},
+// A_n, B_n the P2M weights summed over element 0's Gauss points, and a local
+// expansion L about c gives at the midpoints (L2P)
+//   u_e  = sum_l L_l Jp_l(v_0) e^{i l t_e},
+//   dn_e = sum_l L_l (kap/2)(nu_0 Jp_{l-1}(v_0) - conj(nu_0) Jp_{l+1}(v_0)) e^{i l t_e},
+// v_0 = kap (x_0 - c), nu_0 the normal of element 0.  When every pair between
+// fibres and with images is a root-to-root M2L entry (no near pairs, nothing
+// below the roots), this replaces P2M, M2M and the downward pass: the chain
+// is moments by partial DFTs, the root M2L, and a synthesis per fibre, with
+// no translation between levels (so no M2M or L2L truncation either).
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ cd jp_signed(const cd (&jp)[K + 1], int j) {
+  // Jp_{-j} = (-1)^j conj(Jp_j)
+  if (j >= 0) return jp[j];
+  const cd v = cconj(jp[-j]);
+  return (j & 1) ? cscale(v, -1.0) : v;
+}
+
+// tab[f][0][n] = A_n, [1][n] = B_n, [2][l] = Jp_l(v_0),
+// [3][l] = (kap/2)(nu_0 Jp_{l-1}(v_0) - conj(nu_0) Jp_{l+1}(v_0)); n, l = -P..P.
+// One thread per (fibre, order); the exterior wavenumber only.
+template <int P>
+__global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __restrict__ centres,
+                                                     const double* __restrict__ mx, const double* __restrict__ my,
+                                                     const double* __restrict__ tx, const double* __restrict__ ty,
+                                                     const double* __restrict__ h, const double* __restrict__ gl,
+                                                     int G, double kap, double eta, cd* __restrict__ tab) {
+  constexpr int NP = 2 * P + 1, K = P + 1;
+  const int f = blockIdx.x, i = threadIdx.x;
+  if (i >= NP) return;
+  const int n = i - P;
+  const size_t e0 = (size_t)f * N;
+  const double ex = tx[e0], ey = ty[e0], hh = h[e0];
+  const double rx = mx[e0] - centres[2 * f], ry = my[e0] - centres[2 * f + 1];
+  cd jp[K + 1];
+  // P2M weights per unit phi and varphi (as k_p2m: w = h gl_w / 8 carries
+  // the factor i/4 of the representation, sk = kap w / 2):
+  //   A_n = sum_g sk (-tx + i ty) Jm_{n-1} + sk (-tx - i ty) Jm_{n+1},  B_n = sum_g eta w Jm_n
+  cd A = mkc(0, 0), Bn = mkc(0, 0);
+  for (int g = 0; g < G; ++g) {
+    const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
+    jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
+    const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
+             jmp = cconj(jp_signed<K>(jp, n + 1));
+    A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
+    A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
+    Bn = cadd(Bn, cscale(jm0, eta * w));
+  }
+  jplus_seq<K>(kap * rx, kap * ry, jp);
+  const cd nu = mkc(ey, -ex);
+  const cd dl = cscale(csub(cmul(nu, jp_signed<K>(jp, n - 1)), cmul(cconj(nu), jp_signed<K>(jp, n + 1))), 0.5 * kap);
+  cd* T = tab + (size_t)f * 4 * NP;
+  T[i] = A;
+  T[NP + i] = Bn;
+  T[2 * NP + i] = jp_signed<K>(jp, n);
+  T[3 * NP + i] = dl;
+}
+
+constexpr int SPEC_THREADS = 256;
+
+// The roots' exterior moments from the partial DFTs of each fibre's two
+// densities, one workgroup per (fibre, member): the four wavefronts take a
+// quarter of the elements each, lane = order (two slots when 2P + 1 > 64).
+template <int P>
+__global__ void __launch_bounds__(SPEC_THREADS) k_spec_fwd(const cd* __restrict__ psi, long long psi_stride,
+                                                           const cd* __restrict__ tab, int N,
+                                                           cd* __restrict__ mpole, long long mp_stride) {
+  constexpr int NP = 2 * P + 1, NU = (NP + 63) / 64, NW = SPEC_THREADS / 64;
+  extern __shared__ cd spc[];
+  cd* sphi = spc;                      // [N]
+  cd* svp = spc + N;                   // [N]
+  cd* tw = spc + 2 * N;                // [N]: e^{2 pi i j / N}
+  __shared__ cd red[NW][2][NU * 64];
+  const int f = blockIdx.x;
+  psi += blockIdx.y * psi_stride + (size_t)f * 2 * N;
+  mpole += blockIdx.y * mp_stride;
+  for (int i = threadIdx.x; i < N; i += SPEC_THREADS) {
+    sphi[i] = psi[i];
+    svp[i] = psi[N + i];
+    double sv, cv;
+    sincospi(2.0 * (double)i / (double)N, &sv, &cv);
+    tw[i] = mkc(cv, sv);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e0 = (N * w) / NW, e1 = (N * (w + 1)) / NW;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int slot = lane + 64 * u;
+    cd a = mkc(0, 0), b = mkc(0, 0);
+    if (slot < NP) {
+      const int n = slot - P;
+      const int nn = ((n % N) + N) % N;          // e^{-2 pi i n e / N} = conj(tw[(nn e) mod N])
+      int idx = (int)(((long long)nn * e0) % N);
+      for (int e = e0; e < e1; ++e) {
+        const cd t = tw[idx];
+        a = cfma_conj(t, sphi[e], a);
+        b = cfma_conj(t, svp[e], b);
+        idx += nn;
+        if (idx >= N) idx -= N;
+      }
+    }
+    red[w][0][slot] = a;
+    red[w][1][slot] = b;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NP; i += SPEC_THREADS) {
+    cd a = red[0][0][i], b = red[0][1][i];
+    for (int v = 1; v < NW; ++v) {
+      a = cadd(a, red[v][0][i]);
+      b = cadd(b, red[v][1][i]);
+    }
+    const cd* T = tab + (size_t)f * 4 * NP;
+    mpole[((size_t)f * 2) * NP + i] = cadd(cmul(T[i], a), cmul(T[NP + i], b));
+  }
+}
+
+// The far part of every fibre's rows from its root's local expansion (the
+// root's own M2L sum), one workgroup per (fibre, member):
+//   far1 = u_e,  far2 = 2/(i eta (1 + varrho)) dn_e,
+// written to out (add = 0) or added into it (add = 1: out is y).
+template <int P>
+__global__ void __launch_bounds__(SPEC_THREADS) k_spec_inv(const int* __restrict__ row, const cd* __restrict__ part,
+                                                           long long part_stride, const cd* __restrict__ tab, int N,
+                                                           double eta, double varrho, cd* out, long long out_stride,
+                                                           int add) {
+  constexpr int NP = 2 * P + 1;
+  extern __shared__ cd spc[];
+  cd* tw = spc;                        // [N]
+  __shared__ cd sU[NP], sD[NP];
+  const int f = blockIdx.x, r = row[f];
+  part += blockIdx.y * part_stride;
+  out += blockIdx.y * out_stride + (size_t)f * 2 * N;
+  for (int i = threadIdx.x; i < N; i += SPEC_THREADS) {
+    double sv, cv;
+    sincospi(2.0 * (double)i / (double)N, &sv, &cv);
+    tw[i] = mkc(cv, sv);
+  }
+  const cd* T = tab + (size_t)f * 4 * NP;
+  for (int i = threadIdx.x; i < NP; i += SPEC_THREADS) {
+    const cd L = r >= 0 ? part[(size_t)r * NP + i] : mkc(0, 0);
+    sU[i] = cmul(L, T[2 * NP + i]);
+    sD[i] = cmul(L, T[3 * NP + i]);
+  }
+  __syncthreads();
+  const cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
+  const int nm = ((-P % N) + N) % N;
+  for (int e = threadIdx.x; e < N; e += SPEC_THREADS) {
+    cd u = mkc(0, 0), dn = mkc(0, 0);
+    int idx = (int)(((long long)nm * e) % N);
+    for (int i = 0; i < NP; ++i) {
+      const cd t = tw[idx];
+      u = cfma(sU[i], t, u);
+      dn = cfma(sD[i], t, dn);
+      idx += e;
+      if (idx >= N) idx -= N;
+    }
+    const cd f2 = cmul(c, dn);
+    if (add) {
+      out[e] = cadd(out[e], u);
+      out[N + e] = cadd(out[N + e], f2);
+    } else {
+      out[e] = u;
+      out[N + e] = f2;
+    }
+  }
+}
+
 // Batched P2P: the NB members of a batch share one set of near blocks
 // stored without the quasi-periodic phase; member b sees image m of a source
 // through alpha_b^m, applied to the densities as they are staged in LDS.
@@ -2012,6 +2189,9 @@ static hipError_t tables_impl(Problem& pb) {
   if (n_joff > 0)
     hipLaunchKernelGGL(k_jtab<P>, dim3((2 * n_joff + 63) / 64), dim3(64), 0, pb.stream, n_joff,
                        pb.d_joff_xy, pb.k, pb.k1, pb.d_jtab);
+  if (pb.spec_root)
+    hipLaunchKernelGGL(k_spec_tables<P>, dim3(pb.M), dim3(128), 0, pb.stream, pb.N, pb.d_centres, pb.d_mx, pb.d_my,
+                       pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_spec_tab);
   return hipGetLastError();
 }
 
@@ -2024,9 +2204,16 @@ template <int P>
 // With each fibre's own block applied by FFT (pb.self_fft) only the exterior
 // channel carries pairs, so the chain runs channel 0 alone (the upward pass of
 // the test hook keeps both).
+// only >= 0: launch stage `only` alone (0 P2M, 1 M2M, 2 M2L with the lattice
+// sums, 3 downward pass with L2P into the far-field buffer) reps times back
+// to back, for timing one kernel in steady state.
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B,
-                      hipEvent_t join = nullptr, cd* y_join = nullptr, bool near_in_down = false) {
+                      hipEvent_t join = nullptr, cd* y_join = nullptr, bool near_in_down = false, int only = -1,
+                      int reps = 1) {
+  auto times = [&](int stage) { return only < 0 ? 1 : (only == stage ? reps : 0); };
   const HostPlan& hp = pb.hp;
+  // fibre roots by their Fourier modes (no near pairs, only root entries)
+  const bool spec = pb.spec_root && !upward_only;
   int nc = (int)hp.cells.size();
   int n_leaves = (int)hp.leaves.size();
   int n_joff = (int)hp.joff_xy.size() / 2;
@@ -2036,16 +2223,22 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   // one group of two wavefronts per (leaf, channel): two groups (PS = 2)
   // were slower on the square 8x8 block with one channel (21.7 us against
   // 15.5 us in order)
-  hipLaunchKernelGGL((k_p2m<P, 1>), dim3(n_leaves, nch, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
-                     reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl,
-                     pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
+  for (int r = 0; r < times(0); ++r) {
+    if (spec)
+      hipLaunchKernelGGL(k_spec_fwd<P>, dim3(pb.M, B), dim3(SPEC_THREADS), 3 * (size_t)pb.N * sizeof(cd), s, d_psi,
+                         bs.vec, pb.d_spec_tab, pb.N, pb.d_mpole, bs.mpole);
+    else
+      hipLaunchKernelGGL((k_p2m<P, 1>), dim3(n_leaves, nch, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
+                         reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl,
+                         pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (pb.n_up > 0)
+  for (int r = 0; r < times(1) && pb.n_up > 0 && !spec; ++r)
     hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, nch, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
                        pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
-  if (pb.n_mchunks > 0) {
+  for (int r = 0; r < times(2) && pb.n_mchunks > 0; ++r) {
     hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_mchunks, B), dim3(64), 0, s, pb.d_mchunks, pb.d_e_src, pb.d_e_off,
                        pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
                        bs.epart, bs.tab, bs.alpha);
@@ -2064,12 +2257,30 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   if (join) (void)hipStreamWaitEvent(s, join, 0);
-  hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(64 * nch), 0, s, pb.d_ldesc,
-                     reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
-                     pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
-                     y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0,
-                     near_in_down ? pb.d_leaf_near_t0 : nullptr, pb.d_near_rows);
+  for (int r = 0; r < times(3) && spec; ++r)
+    hipLaunchKernelGGL(k_spec_inv<P>, dim3(pb.M, B), dim3(SPEC_THREADS), (size_t)pb.N * sizeof(cd), s,
+                       pb.d_spec_row, pb.d_part, bs.part, pb.d_spec_tab, pb.N, pb.eta, pb.varrho,
+                       y_join ? y_join : pb.d_far, bs.vec, y_join ? 1 : 0);
+  for (int r = 0; r < times(3) && !spec; ++r)
+    hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(64 * nch), 0, s, pb.d_ldesc,
+                       reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
+                       pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
+                       y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0,
+                       near_in_down ? pb.d_leaf_near_t0 : nullptr, pb.d_near_rows);
   if (ev) (void)hipEventRecord(ev[4], s);
+}
+
+// One stage of the chain launched reps times back to back between events
+// e0 and e1 on the handle's stream, after one whole chain that leaves every
+// stage's inputs in place (each stage then rewrites the same outputs).
+template <int P>
+static hipError_t stage_timed_impl(Problem& pb, const cd* d_psi, int stage, int reps, hipEvent_t e0,
+                                   hipEvent_t e1) {
+  fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, 1);
+  (void)hipEventRecord(e0, pb.stream);
+  fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, 1, nullptr, nullptr, false, stage, reps);
+  (void)hipEventRecord(e1, pb.stream);
+  return hipGetLastError();
 }
 
 template <int P>
@@ -2276,6 +2487,9 @@ hipError_t apply_operator(Problem& pb, const cd* d_psi, cd* d_y, hipEvent_t* ev)
   PFM_DISPATCH(apply_impl, pb, d_psi, d_y, ev)
 }
 hipError_t apply_upward(Problem& pb, const cd* d_psi) { PFM_DISPATCH(upward_impl, pb, d_psi, nullptr) }
+hipError_t time_chain_stage(Problem& pb, const cd* d_psi, int stage, int reps, hipEvent_t e0, hipEvent_t e1) {
+  PFM_DISPATCH(stage_timed_impl, pb, d_psi, stage, reps, e0, e1)
+}
 hipError_t apply_operator_mixed(Problem& pb, const cd* d_psi, cd* d_y) {
   PFM_DISPATCH(apply_mixed_impl, pb, d_psi, d_y)
 }

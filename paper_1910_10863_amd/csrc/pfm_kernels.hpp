@@ -32,6 +32,9 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_near_to_c64(Problem& pb);
 // upward pass only (P2M and M2M), for tests
 hipError_t apply_upward(Problem& pb, const cd* d_psi);
+// one stage of the FMM chain (0 P2M, 1 M2M, 2 M2L, 3 downward pass) launched
+// reps times back to back between events e0 and e1
+hipError_t time_chain_stage(Problem& pb, const cd* d_psi, int stage, int reps, hipEvent_t e0, hipEvent_t e1);
 
 // GMRES building blocks (deterministic two-stage reductions)
 hipError_t launch_dots(Problem& pb, const cd* V, long long ldv, int cnt, const cd* w, int n, cd* d_out);

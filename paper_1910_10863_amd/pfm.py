@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
                 ("lattice_m2l_grid", ctypes.c_int), ("workspace_bytes", ctypes.c_double),
                 ("workspace_bound", ctypes.c_int), ("batch_capacity", ctypes.c_int),
                 ("n_device_allocs", ctypes.c_longlong), ("device_alloc_bytes", ctypes.c_double),
-                ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int)]
+                ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int), ("spectral_roots", ctypes.c_int)]
 
 
 FP64 = 0
@@ -85,6 +85,7 @@ EXPORTS = ["pfm_create", "pfm_set_stream", "pfm_set_wave", "pfm_matvec", "pfm_ma
            "pfm_precond_apply", "pfm_fields", "pfm_get_stats", "pfm_matvec_timed", "pfm_last_error", "pfm_destroy",
            "pfm_set_batch", "pfm_matvec_batch", "pfm_rhs_batch", "pfm_solve_batch", "pfm_sweep",
            "pfm_matvec_batch_timed", "pfm_workspace_size", "pfm_bind", "pfm_matvec_static",
+           "pfm_matvec_stage_timed",
            "pfm_test_bessel", "pfm_test_lattice", "pfm_test_moments", "pfm_test_plan_digest"]
 
 
@@ -114,6 +115,7 @@ def lib():
     L.pfm_solve_batch.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
     L.pfm_sweep.argtypes = [P, ctypes.c_int, dp, ctypes.c_int, dp, vp, ctypes.POINTER(Info)]
     L.pfm_matvec_batch_timed.argtypes = [P, vp, vp, ctypes.c_int, dp, dp]
+    L.pfm_matvec_stage_timed.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, dp]
     L.pfm_rhs.argtypes = [P, vp]
     L.pfm_solve.argtypes = [P, vp, vp, ctypes.c_int, ctypes.POINTER(Info)]
     L.pfm_precond_apply.argtypes = [P, vp, vp, ctypes.c_int]
@@ -168,7 +170,7 @@ class Problem:
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
                  direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True,
-                 tree_on_host: bool = False):
+                 tree_on_host: bool = False, spectral_roots: bool = True):
         import torch
         L = lib()
         self._L = L
@@ -180,7 +182,8 @@ class Problem:
         opt = Options(p, leaf_max, mac, g_far, restart, max_iter, tol, wood_margin, precision, inner_tol,
                       max_batch, 1 if use_graph else 0, p2p_blocks_per_cu, p2p_unroll,
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
-                      1 if direct_lattice_m2l else 0, 1 if precond else 0, 0 if self_fft else 1,
+                      1 if direct_lattice_m2l else 0, 1 if precond else 0,
+                      (0 if spectral_roots else 2) if self_fft else 1,
                       1 if tree_on_host else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
@@ -321,6 +324,14 @@ class Problem:
         st = Stats()
         self._check(self._L.pfm_get_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def stage_timed(self, psi, stage: str, reps: int = 200) -> float:
+        """Mean milliseconds of one launch of a chain stage ("p2m", "m2m",
+        "m2l", "down_l2p") repeated reps times back to back."""
+        ms = ctypes.c_double()
+        idx = ["p2m", "m2m", "m2l", "down_l2p"].index(stage)
+        self._check(self._L.pfm_matvec_stage_timed(self._h, _ptr(psi), idx, reps, ctypes.byref(ms)))
+        return ms.value
 
     def plan_digest(self) -> list:
         """Eight 64-bit digests of the plan's tree and lists (pfm_test_plan_digest)."""

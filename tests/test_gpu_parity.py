@@ -119,7 +119,7 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     return np.linalg.norm(y - ref) / np.linalg.norm(ref), prob
 
 
-@pytest.mark.parametrize("self_fft", [True, False])
+@pytest.mark.parametrize("form", ["spectral", "fft_tree", "tree"])
 @pytest.mark.parametrize("key,p,leaf,tol", [
     ("tiny", 40, 32, 1e-10),
     ("tiny", 16, 32, 1e-5),
@@ -129,12 +129,14 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     ("sq2x2close", 40, 16, 1e-10),
     ("sq4x2close", 40, 16, 1e-10),
 ])
-def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, self_fft):
-    """Both forms of a fibre's own image-0 block: applied by FFT (self_fft,
-    the default; only pairs between fibres and with images in the tree) and
-    through the tree like every other pair."""
-    _say("matvec:", key, "p =", p, "leaf =", leaf, "self_fft =", self_fft)
-    err, prob = _matvec_err(pfm, key, p, leaf, self_fft=self_fft)
+def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, form):
+    """The three forms of a fibre's own image-0 block and of the fibre roots:
+    own block by FFT with the roots by Fourier modes when only root-to-root
+    pairs remain (the default), own block by FFT with every other pair in the
+    tree, and every pair in the tree."""
+    self_fft, spectral = form != "tree", form == "spectral"
+    _say("matvec:", key, "p =", p, "leaf =", leaf, "form =", form)
+    err, prob = _matvec_err(pfm, key, p, leaf, self_fft=self_fft, spectral_roots=spectral)
     st = prob.stats()
     _say("  rel err", err, st)
     # the FFT form needs a power of two elements per fibre (sq3x1 has 96)
@@ -143,6 +145,11 @@ def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, self_fft):
     assert st["self_fft"] == (1 if eligible else 0)
     if eligible:
         assert st["n_m2l_int"] == 0 and st["n_near_circulant"] == 0
+    # fibres farther apart than the admissibility ratio allows: only root pairs
+    separated = key in ("tiny", "sq2x2", "hex2x2")
+    assert st["spectral_roots"] == (1 if spectral and eligible and separated else 0)
+    if st["spectral_roots"]:
+        assert st["n_near_pairs"] == 0
     assert err < tol
 
 
