@@ -149,16 +149,20 @@ typedef struct {
  *             fibre only, leaves the FMM altogether.  1: those pairs go
  *             through the tree like the others (near pairs by P2P from the
  *             circulant rows or stored blocks, far pairs by M2L at k and k1).
- *             With 0, when moreover no pair between fibres or with images
- *             needs P2P and every M2L entry joins two fibre roots (fibres
- *             farther apart than the admissibility ratio allows for their
- *             radii), the roots' multipole moments come from each fibre's
- *             discrete Fourier modes (element e is element 0 turned by
- *             2 pi e / N, so the moment of order n is A_n phihat(n) +
- *             B_n varphihat(n)) and the roots' local expansions are
- *             evaluated at the midpoints by a synthesis over the orders:
- *             no P2M at leaves, M2M, L2L or L2P per leaf
- *             (pfm_stats.spectral_roots).  2: as 0 without this.
+ *             With 0, moreover, every fibre root's multipole moments come
+ *             from the fibre's discrete Fourier modes (element e is element
+ *             0 turned by 2 pi e / N, so the moment of order n is
+ *             A_n phihat(n) + B_n varphihat(n)), and every root's local
+ *             expansion is evaluated at the fibre's midpoints by a synthesis
+ *             over the orders (added to the spectrum before the inverse
+ *             transform of the fibre's own block).  A fibre whose cells take
+ *             part only in M2L entries at its root (no near pairs, no entry
+ *             below the root: its neighbours are farther away than the
+ *             admissibility ratio allows for their radii) needs no P2M, M2M,
+ *             L2L or L2P (pfm_stats.spectral_roots, n_spectral_fibres); the
+ *             other fibres keep P2M at their leaves, M2M into their cells
+ *             below the root and the downward pass of those cells'
+ *             expansions.  2: as 0 without this.
  *  precond    0: plain GMRES; 1: pfm_solve runs GMRES (with PFM_MIXED the
  *             inner GMRES of the refinement)
  *             right-preconditioned by the fibres' free-space self blocks of
@@ -178,7 +182,12 @@ typedef struct {
  *             apply (more than 4096 elements per fibre, or a level of one
  *             fibre's tree with more than 512 cells) the host builds it
  *             (pfm_stats.tree_on_device tells which ran).  1: the host
- *             construction (the reference the GPU build is tested against). */
+ *             construction (the reference the GPU build is tested against).
+ *  m2l_vector 0: the M2L entries (eq. 13) that share a translation (an offset
+ *             between cells, or the lattice sum of a fibre offset, Sec. 3.3)
+ *             are applied together as complex matrix products on the matrix
+ *             cores (FP64 v_mfma, 16 entries per product); 1: every entry on
+ *             the vector ALU (pfm_stats.m2l_mfma_items counts the products). */
 typedef struct {
   int p;
   int leaf_max;
@@ -200,6 +209,7 @@ typedef struct {
   int precond;
   int self_mode;
   int tree_on_host;
+  int m2l_vector;
 } pfm_options;
 
 #define PFM_MAX_BATCH 16
@@ -245,7 +255,10 @@ typedef struct {
   double device_alloc_bytes;   /* their total size */
   int self_fft;                /* 1: each fibre's own image-0 block is applied by FFT (self_mode 0) */
   int tree_on_device;          /* 1: the plan's tree and lists were built by the GPU kernels */
-  int spectral_roots;          /* 1: fibre roots' moments and locals by Fourier modes (self_mode 0) */
+  int spectral_roots;          /* 1: fibre roots' moments by Fourier modes (self_mode 0) */
+  int n_spectral_fibres;       /* fibres whose far rows come from their root's local expansion alone */
+  int m2l_mfma_items;          /* M2L matrix products on the matrix cores (m2l_vector = 0) */
+  int m2l_vector_chunks;       /* M2L entry chunks on the vector ALU */
 } pfm_stats;
 
 /* Build the plan: discretisation, quadtrees and interaction lists (on the

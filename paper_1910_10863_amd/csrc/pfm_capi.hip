@@ -168,6 +168,10 @@ void free_all(Problem& pb) {
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
+  dfree(pb.d_spec_rng); dfree(pb.d_dptr); dfree(pb.d_danc);
+  dfree(pb.d_vchunks); dfree(pb.d_mfma_items); dfree(pb.d_mfma_cols);
+  dfree(pb.d_mcell); dfree(pb.d_dldesc);
+  dfree(pb.d_tup_cells); dfree(pb.d_tup_ptr); dfree(pb.d_tup_src); dfree(pb.d_tup_off);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
   pb.graph = nullptr;
@@ -291,6 +295,8 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   if (opt->self_mode < 0 || opt->self_mode > 2) return bail(fail(pb, PFM_EINVAL, "self_mode must be 0, 1 or 2"));
   if (opt->tree_on_host != 0 && opt->tree_on_host != 1)
     return bail(fail(pb, PFM_EINVAL, "tree_on_host must be 0 or 1"));
+  if (opt->m2l_vector != 0 && opt->m2l_vector != 1)
+    return bail(fail(pb, PFM_EINVAL, "m2l_vector must be 0 or 1"));
   if (opt->precond == 1 && (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0))
     return bail(fail(pb, PFM_EINVAL, "precond = 1 needs n_elem a power of two in 8..512"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -491,6 +497,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       pb.p2p_grid = (opt->p2p_blocks_per_cu > 0 ? opt->p2p_blocks_per_cu : (pb.p2p_on_side ? 3 : 2)) * pb.n_cu;
   }
   std::vector<long long> leaf_blk_host;   // per leaf: start of its stored region (entries)
+  std::vector<int> near_t0_host;          // per leaf: its first P2P row task (-1: none)
   // near-block storage of the other pairs: per target leaf its stored pairs
   // one after the other; with equal fibres, a region (the stored blocks of one
   // target leaf) is stored once for every leaf that has the same region
@@ -657,6 +664,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       CK(upload(pb, &pb.d_p2p_rowtasks, rowtasks));
       CK(upload(pb, &pb.d_p2p_rowoff, rowoff));
       CK(upload(pb, &pb.d_leaf_near_t0, near_t0));
+      near_t0_host = near_t0;
       if (pb.self_fft) ws_add(pb, &pb.d_near_rows, 2 * (size_t)std::max(1, pb.n_p2p_rowtasks) * sizeof(cd), 0);
     }
     CK(upload(pb, &pb.d_cols_ptr, cptr));
@@ -782,13 +790,37 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   ws_add(pb, &pb.d_latpart, 0, (size_t)n_roff * ((LAT_RULE_POINTS + 255) / 256) * NT * sizeof(cd));
   ws_add(pb, &pb.d_srule, 2 * (size_t)LAT_RULE_POINTS * sizeof(double), 0);
   (void)n_off;
-  // fibre roots by their Fourier modes: with the own blocks by FFT, when no
-  // pair needs P2P and every M2L entry joins two roots
-  pb.spec_root = pb.self_fft && opt->self_mode == 0 && hp.near_src.empty() && hp.m2li_src.empty();
-  for (int c = 0; c < nc && pb.spec_root; ++c)
-    for (int q = hp.m2l_ptr[c]; q < hp.m2l_ptr[c + 1]; ++q)
-      if (hp.cells[c].level != 0 || hp.cells[hp.m2l_src[q]].level != 0) pb.spec_root = false;
-  if (pb.spec_root) ws_add(pb, &pb.d_spec_tab, (size_t)pb.M * 4 * NP * sizeof(cd), 0);
+  // fibre roots by their Fourier modes (with the own blocks by FFT): a fibre
+  // is a tree fibre when a cell of it below the root is the target or the
+  // source of an M2L entry, or when one of its leaves or cells is in a near
+  // pair; the others are spectral fibres.  Root cells come first in the
+  // level-major order (root of fibre f = cell f), which the moments' DFT
+  // launch relies on.
+  std::vector<char> tree_fib(pb.M, 0);
+  pb.spec_root = pb.self_fft && opt->self_mode == 0;
+  for (int f = 0; f < pb.M && pb.spec_root; ++f)
+    if (hp.root_of_fibre[f] != f) pb.spec_root = false;
+  if (pb.spec_root) {
+    for (int c = 0; c < nc; ++c) {
+      for (int q = hp.m2l_ptr[c]; q < hp.m2l_ptr[c + 1]; ++q) {
+        if (hp.cells[c].level != 0) tree_fib[hp.cells[c].fiber] = 1;
+        const Cell& S = hp.cells[hp.m2l_src[q]];
+        if (S.level != 0) tree_fib[S.fiber] = 1;
+      }
+      for (int q = hp.m2li_ptr[c]; q < hp.m2li_ptr[c + 1]; ++q) {
+        tree_fib[hp.cells[c].fiber] = 1;
+        tree_fib[hp.cells[hp.m2li_src[q]].fiber] = 1;
+      }
+    }
+    for (size_t q = 0; q < hp.near_src.size(); ++q) {
+      tree_fib[hp.cells[hp.leaves[hp.near_tgt[q]]].fiber] = 1;
+      tree_fib[hp.cells[hp.near_src[q]].fiber] = 1;
+    }
+  }
+  if (pb.spec_root) {
+    ws_add(pb, &pb.d_spec_tab, (size_t)pb.M * 4 * NP * sizeof(cd), 0);
+    ws_add(pb, &pb.d_spec_hat, 0, 2 * (size_t)E * sizeof(cd));
+  }
   {
     // M2L work: per (channel, cell) the entries (source cell, table row, image),
     // contiguous, cut into chunks of at most M2L_CHUNK entries (one wavefront
@@ -867,6 +899,34 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     }
     pb.n_chunks = (int)(sums.size() / 4);
     pb.n_mchunks = (int)(mchunks.size() / 4);
+    {
+      // one-entry chunks grouped by translation (channel, table row) for the
+      // matrix cores, 16 entries per item; the other chunks stay with k_m2l
+      std::map<std::pair<int, int>, std::vector<int>> groups;
+      std::vector<int> vch;
+      for (int c = 0; c < pb.n_mchunks; ++c) {
+        const int ch = mchunks[4 * (size_t)c + 1], b = mchunks[4 * (size_t)c + 2], cnt = mchunks[4 * (size_t)c + 3];
+        if (cnt == 0) continue;                      // the lattice convolution's slot
+        if (cnt == 1 && !opt->m2l_vector) groups[{ch, eoff[b]}].push_back(c);
+        else vch.push_back(c);
+      }
+      std::vector<int> items, cols;
+      for (const auto& g : groups)
+        for (size_t j0 = 0; j0 < g.second.size(); j0 += 16) {
+          const int n = (int)std::min<size_t>(16, g.second.size() - j0);
+          items.push_back(g.first.first); items.push_back(g.first.second);
+          items.push_back((int)(cols.size() / 4)); items.push_back(n);
+          for (int j = 0; j < n; ++j) {
+            const int c = g.second[j0 + j], b = mchunks[4 * (size_t)c + 2];
+            cols.push_back(esrc[b]); cols.push_back(c); cols.push_back(em[b]); cols.push_back(0);
+          }
+        }
+      pb.n_vchunks = (int)vch.size();
+      pb.n_mfma_items = (int)(items.size() / 4);
+      if (vch.empty()) vch.assign(1, 0);
+      if (items.empty()) items.assign(4, 0), cols.assign(4, 0);
+      CK(upload(pb, &pb.d_vchunks, vch)); CK(upload(pb, &pb.d_mfma_items, items)); CK(upload(pb, &pb.d_mfma_cols, cols));
+    }
     CK(upload(pb, &pb.d_e_src, esrc)); CK(upload(pb, &pb.d_e_off, eoff)); CK(upload(pb, &pb.d_e_m, em));
     CK(upload(pb, &pb.d_mchunks, mchunks)); CK(upload(pb, &pb.d_chunks, sums)); CK(upload(pb, &pb.d_cc_ptr, ccptr));
     // leaf descriptors of P2M and the downward pass: everything a leaf's
@@ -882,10 +942,24 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       size_t i = (size_t)ch * nc + c;
       return ccptr[i + 1] > ccptr[i] ? ccptr[i] : -1;
     };
+    // the M2L chunks (first, count) of a (channel, cell), count 0 if none
+    auto chunk_rng = [&](int ch, int c) {
+      const int r = sum_row(ch, c);
+      return r < 0 ? std::make_pair(0, 0) : std::make_pair(sums[4 * (size_t)r + 2], sums[4 * (size_t)r + 3]);
+    };
     if (pb.spec_root) {
-      std::vector<int> rows(pb.M);
-      for (int f = 0; f < pb.M; ++f) rows[f] = sum_row(0, hp.root_of_fibre[f]);
-      CK(upload(pb, &pb.d_spec_row, rows));
+      // every fibre's root local expansion (the sum of the root's M2L
+      // chunks) is evaluated at its midpoints by the synthesis of the last
+      // own-block launch
+      std::vector<int> rng(2 * (size_t)pb.M, 0);
+      pb.n_spec = 0;
+      for (int f = 0; f < pb.M; ++f) {
+        const auto cr = chunk_rng(0, hp.root_of_fibre[f]);
+        rng[2 * (size_t)f] = cr.first;
+        rng[2 * (size_t)f + 1] = cr.second;
+        if (!tree_fib[f]) pb.n_spec++;
+      }
+      CK(upload(pb, &pb.d_spec_rng, rng));
     }
     for (int li = 0; li < nl; ++li) {
       const Cell& L = hp.cells[hp.leaves[li]];
@@ -912,6 +986,50 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         trh[t] = hh[e];
       }
     }
+    if (pb.spec_root) {
+      // P2M: the tree fibres' leaves (rows in tree order, offsets from the
+      // leaf's centre).  Downward pass, grouped by fibre: the tree fibres'
+      // leaves with a far part from below the root (M2L chunks of their own
+      // or of an ancestor other than the root, whose expansion the synthesis
+      // evaluates) or with stored near pairs; each with its ancestors'
+      // (chunks, J-table row) without the root
+      std::vector<int> mc;
+      for (int li = 0; li < nl; ++li) {
+        const Cell& L = hp.cells[hp.leaves[li]];
+        if (!tree_fib[L.fiber]) continue;
+        mc.push_back(hp.leaves[li]); mc.push_back(L.ebeg); mc.push_back(L.eend - L.ebeg);
+      }
+      pb.n_mcells = (int)(mc.size() / 3);
+      if (mc.empty()) mc.assign(3, 0);
+      CK(upload(pb, &pb.d_mcell, mc));
+      std::vector<std::vector<int>> by_fib(pb.M);
+      std::vector<int> da;
+      for (int li = 0; li < nl; ++li) {
+        const Cell& L = hp.cells[hp.leaves[li]];
+        if (!tree_fib[L.fiber]) continue;
+        const auto own = chunk_rng(0, hp.leaves[li]);
+        const int a0 = (int)(da.size() / 4);
+        for (int q = hp.anc_ptr[li]; q < hp.anc_ptr[li + 1]; ++q) {
+          const auto ar = chunk_rng(0, hp.anc[q]);
+          if (ar.second == 0 || hp.cells[hp.anc[q]].level == 0) continue;
+          da.push_back(ar.first); da.push_back(ar.second); da.push_back(hp.anc_off[q]); da.push_back(0);
+        }
+        const int a1 = (int)(da.size() / 4);
+        const int t0 = near_t0_host.empty() ? -1 : near_t0_host[li];
+        if (own.second == 0 && a1 == a0 && t0 < 0) continue;
+        std::vector<int>& v = by_fib[L.fiber];
+        v.insert(v.end(), {L.ebeg, L.eend - L.ebeg, own.first, own.second, a0, a1, t0, 0});
+      }
+      std::vector<int> dptr(pb.M + 1, 0), dd;
+      for (int f = 0; f < pb.M; ++f) {
+        dd.insert(dd.end(), by_fib[f].begin(), by_fib[f].end());
+        dptr[f + 1] = (int)(dd.size() / 8);
+      }
+      pb.n_dleaves = dptr[pb.M];
+      if (dd.empty()) dd.assign(8, 0);
+      if (da.empty()) da.assign(4, 0);
+      CK(upload(pb, &pb.d_dptr, dptr)); CK(upload(pb, &pb.d_dldesc, dd)); CK(upload(pb, &pb.d_danc, da));
+    }
     if (lanc.empty()) lanc.assign(2, 0);
     CK(upload(pb, &pb.d_ldesc, ldesc)); CK(upload(pb, &pb.d_lanc, lanc)); CK(upload(pb, &pb.d_tgeo, tgeo)); CK(upload(pb, &pb.d_trh, trh));
     ws_add(pb, &pb.d_part, 0, (size_t)std::max(1, pb.n_chunks) * NP * sizeof(cd));
@@ -929,6 +1047,26 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(pb, &pb.d_up_cells, hp.up_cells)); CK(upload(pb, &pb.d_up_ptr, hp.up_ptr));
     CK(upload(pb, &pb.d_up_src, hp.up_src)); CK(upload(pb, &pb.d_up_off, hp.up_off));
     pb.n_up = (int)hp.up_cells.size();
+    if (pb.spec_root) {
+      // M2M only into the tree fibres' cells below their roots (the roots'
+      // moments come from the DFTs)
+      std::vector<int> uc, up(1, 0), us, uo;
+      for (size_t i = 0; i < hp.up_cells.size(); ++i) {
+        const Cell& C = hp.cells[hp.up_cells[i]];
+        if (C.level == 0 || !tree_fib[C.fiber]) continue;
+        uc.push_back(hp.up_cells[i]);
+        for (int q = hp.up_ptr[i]; q < hp.up_ptr[i + 1]; ++q) {
+          us.push_back(hp.up_src[q]);
+          uo.push_back(hp.up_off[q]);
+        }
+        up.push_back((int)us.size());
+      }
+      pb.n_tup = (int)uc.size();
+      if (uc.empty()) uc.assign(1, 0), up.assign(2, 0);
+      if (us.empty()) us.assign(1, 0), uo.assign(1, 0);
+      CK(upload(pb, &pb.d_tup_cells, uc)); CK(upload(pb, &pb.d_tup_ptr, up));
+      CK(upload(pb, &pb.d_tup_src, us)); CK(upload(pb, &pb.d_tup_off, uo));
+    }
     ws_add(pb, &pb.d_far, 0, 2 * (size_t)E * sizeof(cd));
   }
   {
@@ -1220,6 +1358,7 @@ pfm_status pfm_matvec_static(pfm_problem* h, const void* d_psi, void* d_y) {
       {&pb.d_p2ppart, pb.p2p_split > 1 ? (size_t)pb.p2p_split * 2 * pb.E * sizeof(cd) : sizeof(cd)},
       {&pb.d_lat_xhat, pb.lat_fft ? (size_t)pb.lat_ns * pxy * NP * sizeof(cd) : 0},
       {&pb.d_lat_lhat, pb.lat_fft ? (size_t)pb.lat_ns * pxy * NP * sizeof(cd) : 0},
+      {&pb.d_spec_hat, pb.spec_root ? 2 * (size_t)pb.E * sizeof(cd) : 0},
   };
   size_t total = 0;
   for (const Use& u : use) total += ws_align(u.bytes);
@@ -1963,6 +2102,9 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->self_fft = pb.self_fft ? 1 : 0;
   st->tree_on_device = pb.tree_on_device ? 1 : 0;
   st->spectral_roots = pb.spec_root ? 1 : 0;
+  st->n_spectral_fibres = pb.spec_root ? pb.n_spec : 0;
+  st->m2l_mfma_items = pb.n_mfma_items;
+  st->m2l_vector_chunks = pb.n_vchunks;
   return PFM_OK;
 }
 

@@ -164,6 +164,11 @@ struct Problem {
   int *d_mchunks = nullptr;             // [n_mchunks][4]: cell, channel, first entry, count (<= M2L_CHUNK entries)
   int n_mchunks = 0;
   cd *d_epart = nullptr;                // [n_mchunks][2p+1] M2L result of each entry chunk
+  int *d_vchunks = nullptr;             // the chunks k_m2l takes (vector ALU)
+  int n_vchunks = 0;
+  int *d_mfma_items = nullptr;          // [item][4]: channel, table row, first column, columns (<= 16)
+  int *d_mfma_cols = nullptr;           // [column][4]: source cell, partial slot (chunk), image, 0
+  int n_mfma_items = 0;
   int n_cu = 0;                         // compute units of the device
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
@@ -176,11 +181,27 @@ struct Problem {
   int n_p2p_rowtasks = 0;
   int* d_leaf_near_t0 = nullptr;        // per leaf: its first row task (-1: none)
   cd* d_near_rows = nullptr;            // [task][2] the row tasks' sums (one wave)
-  // fibre roots by their Fourier modes (spec_root: with the own blocks by FFT,
-  // no near pairs and only root-to-root M2L entries)
+  // fibre roots by their Fourier modes (spec_root: with the own blocks by
+  // FFT).  Every fibre's root moments come from the DFTs of its densities
+  // and its root's local expansion is evaluated at its midpoints by a
+  // synthesis over the orders; a spectral fibre (none of its cells below the
+  // root in an M2L entry, none of its elements in a near pair) needs nothing
+  // else; the others (tree fibres) keep P2M at their leaves, M2M into their
+  // cells below the root and the downward pass of those cells' expansions.
   bool spec_root = false;
-  int* d_spec_row = nullptr;            // [M] the root's M2L sum row (-1: none)
+  int n_spec = 0;                       // spectral fibres
   cd* d_spec_tab = nullptr;             // [M][4][2p+1] per frequency
+  cd* d_spec_hat = nullptr;             // [member][M][2N] spectrum of P psi between the own-block launches
+  int n_mcells = 0;                     // the tree fibres' leaves (P2M)
+  int *d_mcell = nullptr;               // [n_mcells][3]: leaf cell, first row (tree order), rows
+  int n_tup = 0;                        // the tree fibres' cells below their roots with leaves under them (M2M)
+  int *d_tup_cells = nullptr, *d_tup_ptr = nullptr, *d_tup_src = nullptr, *d_tup_off = nullptr;
+  int n_dleaves = 0;                    // tree fibres' leaves with a far part from below the root or near rows
+  int *d_dptr = nullptr;                // [M + 1]: those leaves of fibre f are dptr[f] .. dptr[f + 1]
+  int *d_dldesc = nullptr;              // [leaf][8]: first row, rows, own M2L chunks (first, count),
+                                        // ancestor range in d_danc, first near row task (-1: none), 0
+  int *d_danc = nullptr;                // [ancestor][4]: M2L chunks (first, count), J-table row, 0 (no root)
+  int *d_spec_rng = nullptr;            // [M][2]: the root's M2L chunks (first, count)
   cd *d_p2ppart = nullptr;              // [split][member][2E] partial near rows (split > 1)
   // upward: per non-leaf cell the leaves below it; downward: per leaf its
   // ancestors; both with an index into the J translation table

@@ -947,15 +947,16 @@ struct P2MRows {
   double gl[32];
 };
 
+// Accumulates into acc (the first H::NS slots; the caller zeroes them) the
+// raw slot sums of this wavefront's half of the orders over its points;
+// p2m_fold turns them into moments once every point is in.
 template <int P, int W, int NA>
-__device__ __forceinline__ void p2m_half(cd (&out)[NA], int first, int stride, int npts, int G, double kap,
+__device__ __forceinline__ void p2m_half(cd (&acc)[NA], int first, int stride, int npts, int G, double kap,
                                          double eta, const P2MRows& rw) {
   using H = P2MHalf<P, W>;
+  static_assert(H::NS <= NA, "slots");
   constexpr int M1 = H::LO > 0 ? H::LO : 1;   // first order with a +- pair
   // slot of order +m: m - LO (Pm for m >= 1); slot of order -m: NPOS + m - M1 (Qm)
-  cd acc[H::NS];
-#pragma unroll
-  for (int j = 0; j < H::NS; ++j) acc[j] = mkc(0, 0);
   for (int pt = first; pt < npts; pt += stride) {
     int q = pt / G;
     int g = pt - q * G;
@@ -1000,6 +1001,14 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int first, int stride, i
       }
     }
   }
+}
+
+// The slot sums of p2m_half as moments: orders m and -m from the sums P_m
+// and Q_m of their shared products.
+template <int P, int W, int NA>
+__device__ __forceinline__ void p2m_fold(cd (&acc)[NA]) {
+  using H = P2MHalf<P, W>;
+  constexpr int M1 = H::LO > 0 ? H::LO : 1;   // first order with a +- pair
 #pragma unroll
   for (int m = M1; m <= H::HI; ++m) {
     const int jp = m - H::LO, jn = H::NPOS + m - M1;
@@ -1007,8 +1016,6 @@ __device__ __forceinline__ void p2m_half(cd (&out)[NA], int first, int stride, i
     acc[jp] = cadd(pm, qm);
     acc[jn] = cscale(csub(pm, qm), (m & 1) ? -1.0 : 1.0);
   }
-#pragma unroll
-  for (int j = 0; j < H::NS; ++j) out[j] = acc[j];
 }
 
 // Sum over the 64 lanes of a wavefront of NA complex slots held by every
@@ -1052,49 +1059,58 @@ __device__ __forceinline__ cd wave_sum_slots(cd (&a)[NA], int lane) {
 // points g*64 + lane, g*64 + lane + 64 PS, ...  Each wavefront sums its
 // lanes' partial moments by a butterfly across the lanes (no LDS round
 // trips); with PS > 1 the groups' sums meet in LDS in a fixed order.
+// The moments of cell `cell` about its centre for channel ch and batch
+// member `mem`, by the 128 PS threads of the calling workgroup: its `rows`
+// elements are rows rb.. of the geometry arrays (offset from the cell's
+// centre, tangent; chord length; index of phi in Psi), staged in LDS 64 at a
+// time.
 template <int P, int PS>
-__global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
-                                             const double4* __restrict__ tgeo, const double* __restrict__ trh,
-                                             const int* __restrict__ psi_idx, const double* __restrict__ gl,
-                                             int G, int N, double k, double k1, double eta,
-                                             const cd* __restrict__ psi, cd* __restrict__ mpole,
-                                             long long psi_stride, long long mp_stride) {
+__device__ __forceinline__ void p2m_cell(int cell, int rb, int rows, int ch, int mem,
+                                         const double4* __restrict__ tgeo, const double* __restrict__ trh,
+                                         const int* __restrict__ psi_idx, const double* __restrict__ gl, int G,
+                                         int N, double k, double k1, double eta, const cd* __restrict__ psi,
+                                         cd* __restrict__ mpole, long long psi_stride, long long mp_stride) {
   constexpr int NP = 2 * P + 1;
   constexpr int NA = P2MHalf<P, 0>::NS > P2MHalf<P, 1>::NS ? P2MHalf<P, 0>::NS : P2MHalf<P, 1>::NS;
   constexpr int SPL = NA <= 32 ? 2 : 1;         // lanes per slot after the butterfly
-  // the leaf's rows (from its descriptor and the row-ordered geometry) are
-  // loaded once by the first wavefront; the point loop then reads only LDS
+  // each chunk of 64 rows is loaded once by the first wavefront; the point
+  // loop then reads only LDS
   __shared__ P2MRows rw;
   __shared__ cd grp_sum[PS > 1 ? PS - 1 : 1][2][64];
-  psi += blockIdx.z * psi_stride;
-  mpole += blockIdx.z * mp_stride;
-  const int cell = leaves[blockIdx.x];
-  const int rb = ldesc[8 * blockIdx.x], rows = ldesc[8 * blockIdx.x + 1];
-  int ch = blockIdx.y;
+  psi += mem * psi_stride;
+  mpole += mem * mp_stride;
   double kap = ch ? k1 : k;
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int half = wv & 1, grp = wv >> 1;
-  if (wv == 0) {
-    if (lane < rows) {
-      const double4 g = tgeo[rb + lane];
-      const int pi = psi_idx[rb + lane];
-      rw.x[lane] = g.x; rw.y[lane] = g.y; rw.tx[lane] = g.z; rw.ty[lane] = g.w;
-      rw.h[lane] = trh[rb + lane];
-      rw.phi[lane] = psi[pi];
-      rw.vphi[lane] = psi[pi + N];
-    }
-  } else if (wv == 1 && lane < 2 * G) {
-    rw.gl[lane] = gl[lane];
-  }
-  __syncthreads();
-  const int npts = rows * G;
   cd acc[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = mkc(0, 0);
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    const int nr = rows - r0 < 64 ? rows - r0 : 64;
+    if (r0 > 0) __syncthreads();                // the previous chunk is consumed
+    if (wv == 0) {
+      if (lane < nr) {
+        const double4 g = tgeo[rb + r0 + lane];
+        const int pi = psi_idx[rb + r0 + lane];
+        rw.x[lane] = g.x; rw.y[lane] = g.y; rw.tx[lane] = g.z; rw.ty[lane] = g.w;
+        rw.h[lane] = trh[rb + r0 + lane];
+        rw.phi[lane] = psi[pi];
+        rw.vphi[lane] = psi[pi + N];
+      }
+    } else if (wv == 1 && lane < 2 * G && r0 == 0) {
+      rw.gl[lane] = gl[lane];
+    }
+    __syncthreads();
+    const int npts = nr * G;
+    if (half == 0)
+      p2m_half<P, 0, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
+    else
+      p2m_half<P, 1, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
+  }
   if (half == 0)
-    p2m_half<P, 0, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
+    p2m_fold<P, 0, NA>(acc);
   else
-    p2m_half<P, 1, NA>(acc, grp * 64 + lane, 64 * PS, npts, G, kap, eta, rw);
+    p2m_fold<P, 1, NA>(acc);
   cd tot = wave_sum_slots<NA>(acc, lane);
   const int slot = SPL == 2 ? lane >> 1 : lane;
   const bool writer = SPL == 2 ? (lane & 1) == 0 : true;
@@ -1112,6 +1128,17 @@ __global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves
     const int n = slot < npos ? lo + slot : -((lo > 0 ? lo : 1) + (slot - npos));
     mpole[((size_t)cell * 2 + ch) * NP + n + P] = tot;
   }
+}
+
+template <int P, int PS>
+__global__ void __launch_bounds__(128 * PS) k_p2m(const int* __restrict__ leaves, const int* __restrict__ ldesc,
+                                             const double4* __restrict__ tgeo, const double* __restrict__ trh,
+                                             const int* __restrict__ psi_idx, const double* __restrict__ gl,
+                                             int G, int N, double k, double k1, double eta,
+                                             const cd* __restrict__ psi, cd* __restrict__ mpole,
+                                             long long psi_stride, long long mp_stride) {
+  p2m_cell<P, PS>(leaves[blockIdx.x], ldesc[8 * blockIdx.x], ldesc[8 * blockIdx.x + 1], blockIdx.y, blockIdx.z, tgeo,
+                  trh, psi_idx, gl, G, N, k, k1, eta, psi, mpole, psi_stride, mp_stride);
 }
 
 // The value of lane `lane` (wave-uniform) of a complex register, through the
@@ -1214,7 +1241,7 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
                                             const cd* __restrict__ alpha, int m_min,
                                             const cd* __restrict__ mpole, cd* __restrict__ part,
                                             long long mp_stride, long long part_stride, long long tab_stride,
-                                            int alpha_stride) {
+                                            int alpha_stride, const int* __restrict__ ids) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1;
   __shared__ cd sh[NT];
   // batch member: its multipoles, partial sums, lattice rows and image phases
@@ -1222,7 +1249,8 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   part += blockIdx.y * part_stride;
   htab += blockIdx.y * tab_stride;
   alpha += blockIdx.y * alpha_stride;
-  int c = blockIdx.x;
+  // the chunks this launch takes (ids: those not on the matrix cores)
+  int c = ids ? ids[blockIdx.x] : (int)blockIdx.x;
   int ch = chunks[4 * c + 1], b = chunks[4 * c + 2], e = b + chunks[4 * c + 3];
   if (e == b) return;                           // a root's slot for the lattice convolution
   constexpr int NU = (NP + 63) / 64;
@@ -1274,6 +1302,91 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
   for (int i = 0; i < NU; ++i) {
     int l = lane + 64 * i;
     if (l < NP) out[l] = acc[i];
+  }
+}
+
+// M2L entries on the matrix cores.  The one-entry chunks that share a
+// translation (channel and table row: one offset between cells, or one
+// lattice sum of a fibre offset) form one complex matrix product, the
+// Toeplitz matrix T[l][n] = t[n - l] of eq. 13 (index n - l) times the panel
+// of their sources' moments (alpha^m applied), [2p+1 x entries].  An item is
+// one table row with up to 16 of its entries (columns): one workgroup of NR
+// wavefronts per (item, batch member), wavefront w computing the orders
+// l = 16 w .. 16 w + 15 for the item's columns as one 16 x 16 tile of
+// v_mfma_f64_16x16x4 steps over the source orders, four real products per
+// complex step (re re, -im im, re im, im re).  Lane layout of the f64
+// 16 x 16 x 4 product: A[i][k] and B[k][j] in lane i + 16 k and j + 16 k,
+// D[4 r + lane / 16][lane % 16] in accumulator r.  Each entry's result goes
+// to its chunk's partial slot, which k_m2l_sum adds per cell in list order.
+typedef double mfma_v4d __attribute__((ext_vector_type(4)));
+constexpr int MFMA_COLS = 16;
+template <int P>
+__global__ void __launch_bounds__(64 * ((2 * P + 16) / 16)) k_m2l_mfma(
+    const int4* __restrict__ items, const int4* __restrict__ cols, const cd* __restrict__ htab, int n_tab,
+    const cd* __restrict__ alpha, int m_min, const cd* __restrict__ mpole, cd* __restrict__ part,
+    long long mp_stride, long long part_stride, long long tab_stride, int alpha_stride) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NTH = 64 * ((2 * P + 16) / 16);
+  constexpr int KS = (NP + 3) / 4, KP = 4 * KS + 1;   // source order steps; padded LDS row of a column
+  constexpr int NFILL = MFMA_COLS * 4 * KS, PER = (NFILL + NTH - 1) / NTH;
+  __shared__ cd sT[NT];
+  __shared__ cd sB[MFMA_COLS * KP];
+  __shared__ int sSrc[MFMA_COLS];
+  __shared__ cd sPh[MFMA_COLS];
+  mpole += blockIdx.y * mp_stride;
+  part += blockIdx.y * part_stride;
+  htab += blockIdx.y * tab_stride;
+  alpha += blockIdx.y * alpha_stride;
+  const int4 it = items[blockIdx.x];              // channel, table row, first column, columns
+  const int ch = it.x, ncol = it.w;
+  // two rounds of independent loads: the translation row and the columns'
+  // (source cell, phase), then every column's moments at once
+  const cd* t = htab + ((size_t)ch * n_tab + it.y) * NT;
+  for (int i = threadIdx.x; i < NT; i += NTH) sT[i] = t[i];
+  if (threadIdx.x < MFMA_COLS) {
+    int src = 0;
+    cd ph = mkc(0, 0);
+    if ((int)threadIdx.x < ncol) {
+      const int4 c = cols[it.z + threadIdx.x];      // source cell, partial slot, image
+      src = c.x;
+      ph = alpha[c.z - m_min];
+    }
+    sSrc[threadIdx.x] = src;
+    sPh[threadIdx.x] = ph;
+  }
+  __syncthreads();
+  cd v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = threadIdx.x + u * NTH, j = i / (4 * KS), n = i - j * (4 * KS);
+    v[u] = (i < NFILL && j < ncol && n < NP) ? mpole[((size_t)sSrc[j] * 2 + ch) * NP + n] : mkc(0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = threadIdx.x + u * NTH, j = i / (4 * KS), n = i - j * (4 * KS);
+    if (i < NFILL) sB[j * KP + n] = cmul(sPh[j], v[u]);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4, l = 16 * w + i;
+  mfma_v4d dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int n = 4 * ks + kq;
+    const cd a = (l < NP && n < NP) ? sT[n - l + 2 * P] : mkc(0, 0);
+    const cd b = sB[i * KP + n];
+    dre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, dre, 0, 0, 0);
+    dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, dre, 0, 0, 0);
+    dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, dim, 0, 0, 0);
+    dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, dim, 0, 0, 0);
+  }
+  if (i < ncol) {
+    const int slot = cols[it.z + i].y;
+    cd* out = part + (size_t)slot * NP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lo = 16 * w + 4 * r + kq;
+      if (lo < NP) out[lo] = mkc(dre[r], dim[r]);
+    }
   }
 }
 
@@ -1842,11 +1955,12 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_apply(const cd* in, cd* out
 // expansion L about c gives at the midpoints (L2P)
 //   u_e  = sum_l L_l Jp_l(v_0) e^{i l t_e},
 //   dn_e = sum_l L_l (kap/2)(nu_0 Jp_{l-1}(v_0) - conj(nu_0) Jp_{l+1}(v_0)) e^{i l t_e},
-// v_0 = kap (x_0 - c), nu_0 the normal of element 0.  When every pair between
-// fibres and with images is a root-to-root M2L entry (no near pairs, nothing
-// below the roots), this replaces P2M, M2M and the downward pass: the chain
-// is moments by partial DFTs, the root M2L, and a synthesis per fibre, with
-// no translation between levels (so no M2M or L2L truncation either).
+// v_0 = kap (x_0 - c), nu_0 the normal of element 0.  Every root's moments
+// come from the partial DFTs (no M2M truncation).  A fibre whose cells take
+// part only in root-to-root M2L entries (no near pairs, nothing below its
+// root) needs nothing else: its far rows are the synthesis of its root's
+// local expansion (no L2L truncation).  The other fibres keep P2M at their
+// leaves, M2M into their cells below the root and the downward pass.
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ __forceinline__ cd jp_signed(const cd (&jp)[K + 1], int j) {
@@ -1896,114 +2010,268 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
   T[3 * NP + i] = dl;
 }
 
-constexpr int SPEC_THREADS = 256;
-
-// The roots' exterior moments from the partial DFTs of each fibre's two
-// densities, one workgroup per (fibre, member): the four wavefronts take a
-// quarter of the elements each, lane = order (two slots when 2P + 1 > 64).
-template <int P>
-__global__ void __launch_bounds__(SPEC_THREADS) k_spec_fwd(const cd* __restrict__ psi, long long psi_stride,
-                                                           const cd* __restrict__ tab, int N,
-                                                           cd* __restrict__ mpole, long long mp_stride) {
-  constexpr int NP = 2 * P + 1, NU = (NP + 63) / 64, NW = SPEC_THREADS / 64;
-  extern __shared__ cd spc[];
-  cd* sphi = spc;                      // [N]
-  cd* svp = spc + N;                   // [N]
-  cd* tw = spc + 2 * N;                // [N]: e^{2 pi i j / N}
-  __shared__ cd red[NW][2][NU * 64];
-  const int f = blockIdx.x;
-  psi += blockIdx.y * psi_stride + (size_t)f * 2 * N;
-  mpole += blockIdx.y * mp_stride;
-  for (int i = threadIdx.x; i < N; i += SPEC_THREADS) {
-    sphi[i] = psi[i];
-    svp[i] = psi[N + i];
-    double sv, cv;
-    sincospi(2.0 * (double)i / (double)N, &sv, &cv);
-    tw[i] = mkc(cv, sv);
-  }
-  __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e0 = (N * w) / NW, e1 = (N * (w + 1)) / NW;
-#pragma unroll
-  for (int u = 0; u < NU; ++u) {
-    const int slot = lane + 64 * u;
-    cd a = mkc(0, 0), b = mkc(0, 0);
-    if (slot < NP) {
-      const int n = slot - P;
-      const int nn = ((n % N) + N) % N;          // e^{-2 pi i n e / N} = conj(tw[(nn e) mod N])
-      int idx = (int)(((long long)nn * e0) % N);
-      for (int e = e0; e < e1; ++e) {
-        const cd t = tw[idx];
-        a = cfma_conj(t, sphi[e], a);
-        b = cfma_conj(t, svp[e], b);
-        idx += nn;
-        if (idx >= N) idx -= N;
-      }
-    }
-    red[w][0][slot] = a;
-    red[w][1][slot] = b;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < NP; i += SPEC_THREADS) {
-    cd a = red[0][0][i], b = red[0][1][i];
-    for (int v = 1; v < NW; ++v) {
-      a = cadd(a, red[v][0][i]);
-      b = cadd(b, red[v][1][i]);
-    }
-    const cd* T = tab + (size_t)f * 4 * NP;
-    mpole[((size_t)f * 2) * NP + i] = cadd(cmul(T[i], a), cmul(T[NP + i], b));
+// The root's exterior moments of order n = -p..p from the forward DFTs of
+// the fibre's two densities (H: phihat[N], then varphihat[N]) and the
+// fibre's table row T (A_n, then B_n):  M_n = A_n phihat(n mod N) +
+// B_n varphihat(n mod N).  The same arithmetic wherever the DFTs are taken.
+__device__ __forceinline__ void root_moments(const cd* H, int N, int NP, const cd* __restrict__ T,
+                                             cd* __restrict__ out) {
+  const int P = NP >> 1;
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+    const int j = ((i - P) % N + N) % N;
+    out[i] = cadd(cmul(T[i], H[j]), cmul(T[NP + i], H[N + j]));
   }
 }
 
-// The far part of every fibre's rows from its root's local expansion (the
-// root's own M2L sum), one workgroup per (fibre, member):
-//   far1 = u_e,  far2 = 2/(i eta (1 + varrho)) dn_e,
-// written to out (add = 0) or added into it (add = 1: out is y).
-template <int P>
-__global__ void __launch_bounds__(SPEC_THREADS) k_spec_inv(const int* __restrict__ row, const cd* __restrict__ part,
-                                                           long long part_stride, const cd* __restrict__ tab, int N,
-                                                           double eta, double varrho, cd* out, long long out_stride,
-                                                           int add) {
+// With the roots by Fourier modes, each fibre's own-block apply is split
+// around the FMM chain so that one inverse transform serves both.  First
+// launch: workgroup f < M (one per fibre and member) takes the forward
+// transforms of the fibre's densities, writes the root's moments
+// (root_moments) and the spectrum of P psi, (I + L(kappa)) psihat(kappa), to
+// spec; with one wave, the next `ntb` workgroups take the row tasks of the
+// stored near pairs (as k_self_apply) and leave the sums in near_buf; the
+// workgroups after those compute the moments of the tree fibres' leaves
+// (P2M, four groups of two wavefronts per leaf: mcell = [leaf cell, first
+// row, rows] of the row-ordered geometry), which thus run beside the
+// transforms.
+template <int P, typename C>
+__global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ in, cd* __restrict__ spec,
+                                                         long long vec_stride, const cd* __restrict__ coef,
+                                                         const cd* __restrict__ tw, int N, int logN, int M,
+                                                         const int4* __restrict__ tasks,
+                                                         const long long* __restrict__ toff, int ntasks, int ntb,
+                                                         const int* __restrict__ col_psi,
+                                                         const C* __restrict__ blocks, cd* __restrict__ near_buf,
+                                                         const cd* __restrict__ rtab, cd* __restrict__ mpole,
+                                                         long long mp_stride, const int* __restrict__ mcell,
+                                                         const double4* __restrict__ tgeo,
+                                                         const double* __restrict__ trh,
+                                                         const int* __restrict__ psi_idx,
+                                                         const double* __restrict__ gl, int G, double k,
+                                                         double eta) {
+  static_assert(PC_THREADS == 128 * 4, "leaf workgroups run P2M with four groups");
   constexpr int NP = 2 * P + 1;
-  extern __shared__ cd spc[];
-  cd* tw = spc;                        // [N]
-  __shared__ cd sU[NP], sD[NP];
-  const int f = blockIdx.x, r = row[f];
-  part += blockIdx.y * part_stride;
-  out += blockIdx.y * out_stride + (size_t)f * 2 * N;
-  for (int i = threadIdx.x; i < N; i += SPEC_THREADS) {
-    double sv, cv;
-    sincospi(2.0 * (double)i / (double)N, &sv, &cv);
-    tw[i] = mkc(cv, sv);
+  extern __shared__ cd pcs[];
+  if ((int)blockIdx.x >= M + ntb) {
+    const int* mc = mcell + 3 * ((int)blockIdx.x - M - ntb);
+    p2m_cell<P, 4>(mc[0], mc[1], mc[2], 0, blockIdx.y, tgeo, trh, psi_idx, gl, G, N, k, k, eta, in, mpole,
+                   vec_stride, mp_stride);
+    return;
   }
-  const cd* T = tab + (size_t)f * 4 * NP;
-  for (int i = threadIdx.x; i < NP; i += SPEC_THREADS) {
-    const cd L = r >= 0 ? part[(size_t)r * NP + i] : mkc(0, 0);
-    sU[i] = cmul(L, T[2 * NP + i]);
-    sD[i] = cmul(L, T[3 * NP + i]);
+  if ((int)blockIdx.x >= M) {
+    const int t = ((int)blockIdx.x - M) * (PC_THREADS / 64) + (threadIdx.x >> 6);
+    if (t >= ntasks) return;
+    cd a1, a2;
+    p2p_row_sums<C>(tasks[t], toff[t], col_psi, blocks, in, N, threadIdx.x & 63, a1, a2);
+    if ((threadIdx.x & 63) == 0) {
+      near_buf[2 * t] = a1;
+      near_buf[2 * t + 1] = a2;
+    }
+    return;
+  }
+  const int f = blockIdx.x;
+  const size_t mem = (size_t)blockIdx.y * vec_stride;
+  cd* X = pcs;
+  cd* Y = pcs + 2 * N;
+  const cd* src = in + mem + (size_t)f * 2 * N;   // phi_f then varphi_f
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  __syncthreads();
+  const cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
+  root_moments(H, N, NP, rtab + (size_t)f * 4 * NP, mpole + blockIdx.y * mp_stride + (size_t)f * 2 * NP);
+  cd* dst = spec + mem + (size_t)f * 2 * N;
+  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    const cd u = H[kk], v = H[N + kk];
+    dst[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
+    dst[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+  }
+}
+
+// Downward pass and L2P of the tree fibres' leaves with a far part from
+// below their roots (or stored near pairs), exterior channel only, one
+// wavefront per (leaf, member), adding into y after the own-block launch has
+// written it.  As k_down, but the M2L partial expansions are summed here
+// (a cell's chunks are contiguous): the leaf's own (desc[2], desc[3]: first
+// chunk, count) and each ancestor's below the root (anc[desc[4] ..
+// desc[5]]: first chunk, count, J-table row), translated to the leaf by L2L;
+// then L2P at its rows, y1 += u, y2 += 2/(i eta (1 + varrho)) dn, plus the
+// stored near pairs' row sums (near_buf from task desc[6], one wave).
+template <int P>
+__global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc, const int4* __restrict__ anc,
+                                                  const cd* __restrict__ epart, long long ep_stride,
+                                                  const cd* __restrict__ jtab, const double4* __restrict__ tgeo,
+                                                  const int* __restrict__ psi_idx, int N, double k, double eta,
+                                                  double varrho, cd* __restrict__ y, long long y_stride,
+                                                  const cd* __restrict__ near_buf) {
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64, K = P + 1;
+  // the L2P tables are indexed through wz (= 0, a lane value to the
+  // compiler) so that their reads stay in the order loop instead of being
+  // hoisted into registers all at once
+  __shared__ cd sJ[NT], sA[NP], sL[NP], sS[1][3][P + 2], sT[1][3][P + 2];
+  const int wz = threadIdx.x >> 6;
+  epart += blockIdx.y * ep_stride;
+  y += blockIdx.y * y_stride;
+  const int* d = ddesc + 8 * blockIdx.x;
+  const int lane = threadIdx.x;
+  const int rb = d[0], rows = d[1], own0 = d[2], ownc = d[3], a0 = d[4], na = d[5] - d[4], t0 = d[6];
+  double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+  int pi = 0;
+  if (lane < rows) {
+    g = tgeo[rb + lane];
+    pi = psi_idx[rb + lane];
+  }
+  cd acc[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) acc[u] = mkc(0, 0);
+  for (int c = 0; c < ownc; ++c)
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (lane + 64 * u < NP) acc[u] = cadd(acc[u], epart[(size_t)(own0 + c) * NP + lane + 64 * u]);
+  for (int q = 0; q < na; ++q) {                // wave-uniform trip count
+    const int4 an = anc[a0 + q];
+    cd sa[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) sa[u] = mkc(0, 0);
+    for (int c = 0; c < an.y; ++c)
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+        if (lane + 64 * u < NP) sa[u] = cadd(sa[u], epart[(size_t)(an.x + c) * NP + lane + 64 * u]);
+    const cd* tj = jtab + (size_t)an.z * NT;
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (lane + 64 * u < NP) sA[lane + 64 * u] = sa[u];
+#pragma unroll
+    for (int u = 0; u < NTU; ++u)
+      if (lane + 64 * u < NT) sJ[lane + 64 * u] = tj[lane + 64 * u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      int n = min(lane + 64 * u - P, P);      // lanes past the last order repeat it
+      cd sres = acc[u];
+      for (int idx = 0; idx < NP; ++idx) sres = cfma(sA[idx], sJ[idx - n + P], sres);
+      acc[u] = sres;
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < NU; ++u) {
+    int i = lane + 64 * u;
+    if (i < NP) sL[i] = acc[u];
   }
   __syncthreads();
-  const cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
-  const int nm = ((-P % N) + N) % N;
-  for (int e = threadIdx.x; e < N; e += SPEC_THREADS) {
-    cd u = mkc(0, 0), dn = mkc(0, 0);
-    int idx = (int)(((long long)nm * e) % N);
-    for (int i = 0; i < NP; ++i) {
-      const cd t = tw[idx];
-      u = cfma(sU[i], t, u);
-      dn = cfma(sD[i], t, dn);
-      idx += e;
-      if (idx >= N) idx -= N;
-    }
-    const cd f2 = cmul(c, dn);
-    if (add) {
-      out[e] = cadd(out[e], u);
-      out[N + e] = cadd(out[N + e], f2);
-    } else {
-      out[e] = u;
-      out[N + e] = f2;
+  // L2P with orders -n and n folded (as k_down)
+  if (lane <= K) {
+    const int n = lane;
+    const double sg = (n & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int sh = j == 0 ? 0 : (j == 1 ? 1 : -1);
+      const int lp = n + sh, lm = -n + sh;
+      cd c = (lp >= -P && lp <= P) ? sL[P + lp] : mkc(0, 0);
+      cd e = (lm >= -P && lm <= P) ? cscale(sL[P + lm], sg) : mkc(0, 0);
+      cd dd = csub(c, e);
+      sS[wz][j][n] = n ? cadd(c, e) : c;
+      sT[wz][j][n] = n ? mkc(-dd.y, dd.x) : mkc(0, 0);
     }
   }
+  __syncthreads();
+  cd u = mkc(0, 0), dv = mkc(0, 0);
+  if (lane < rows) {
+    double vx = k * g.x, vy = k * g.y;
+    double gs[K + 1];                          // h_n = g_n / n!
+    scaled_h<K>(0.25 * (vx * vx + vy * vy), gs);
+    cd hv = mkc(0.5 * vx, 0.5 * vy);
+    cd uu = mkc(1.0, 0.0);                     // (v/2)^n
+    cd sa = mkc(0, 0), sb = mkc(0, 0);
+#pragma unroll
+    for (int n = 0; n <= K; ++n) {
+      const double x = uu.x * gs[n], yv = uu.y * gs[n];   // Jp_n
+      cd s0 = sS[wz][0][n], tt0 = sT[wz][0][n];
+      cd s1 = sS[wz][1][n], tt1 = sT[wz][1][n];
+      cd s2 = sS[wz][2][n], tt2 = sT[wz][2][n];
+      u.x = fma(s0.x, x, fma(tt0.x, yv, u.x));
+      u.y = fma(s0.y, x, fma(tt0.y, yv, u.y));
+      sa.x = fma(s1.x, x, fma(tt1.x, yv, sa.x));
+      sa.y = fma(s1.y, x, fma(tt1.y, yv, sa.y));
+      sb.x = fma(s2.x, x, fma(tt2.x, yv, sb.x));
+      sb.y = fma(s2.y, x, fma(tt2.y, yv, sb.y));
+      if (n < K) uu = cmul(uu, hv);
+    }
+    cd nu = mkc(g.w, -g.z);
+    dv = cscale(csub(cmul(nu, sa), cmul(cconj(nu), sb)), 0.5 * k);
+  }
+  // the rows of y are read and written after the order loop (read inside the
+  // branch above, their loads would be hoisted over it and hold registers)
+  __syncthreads();
+  if (lane < rows) {
+    cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));
+    cd y1 = y[pi], y2 = y[pi + N];
+    if (t0 >= 0 && near_buf) {
+      y1 = cadd(y1, near_buf[2 * (t0 + lane)]);
+      y2 = cadd(y2, near_buf[2 * (t0 + lane) + 1]);
+    }
+    y[pi] = cadd(y1, u);
+    y[pi + N] = cadd(y2, cmul(c, dv));
+  }
+}
+
+// Last launch, after the M2L: workgroup f (one per fibre and member) sums
+// its root's M2L partial expansions (chunks rrng[f] = first, count: the
+// root's local expansion L), loads the spectrum of P psi and adds N times
+// the coefficients of L's far part,
+//   u_e = sum_l L_l Jp_l(v_0) w^{l e},
+//   far2_e = 2/(i eta (1 + varrho)) sum_l L_l (kap/2)(nu_0 Jp_{l-1} - conj(nu_0) Jp_{l+1}) w^{l e},
+// at mode l mod N (orders that alias add up); one inverse transform then
+// gives y = P psi + far for the fibre's rows (a tree fibre's downward pass,
+// k_down_spec, then adds the far part of its cells below the root).
+template <int P>
+__global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ spec, cd* __restrict__ out,
+                                                         long long vec_stride, const cd* __restrict__ tw, int N,
+                                                         int logN, const int2* __restrict__ rrng,
+                                                         const cd* __restrict__ epart, long long ep_stride,
+                                                         const cd* __restrict__ rtab, double eta, double varrho) {
+  constexpr int NP = 2 * P + 1, NW = PC_THREADS / 64;
+  extern __shared__ cd pcs[];
+  __shared__ cd sLw[NW][NP];
+  const int f = blockIdx.x;
+  const size_t mem = (size_t)blockIdx.y * vec_stride;
+  epart += blockIdx.y * ep_stride;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cd* X = pcs;
+  cd* Y = pcs + 2 * N;
+  const cd* src = spec + mem + (size_t)f * 2 * N;
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  // the root's local expansion: wavefront w adds chunks w, w + NW, ... (lane
+  // = order), then the NW partial sums in order
+  const int2 rr = rrng[f];
+  for (int l = lane; l < NP; l += 64) {
+    cd sacc = mkc(0, 0);
+    for (int c = w; c < rr.y; c += NW) sacc = cadd(sacc, epart[(size_t)(rr.x + c) * NP + l]);
+    sLw[w][l] = sacc;
+  }
+  __syncthreads();
+  if (rr.y > 0) {
+    const int P_ = NP >> 1;
+    const cd* T = rtab + (size_t)f * 4 * NP;
+    const double nn = (double)N;
+    const cd c = mkc(0.0, -2.0 * nn / (eta * (1.0 + varrho)));
+    for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
+      cd su = mkc(0, 0), sd = mkc(0, 0);
+      for (int l = kk - ((kk + P_) / N) * N; l <= P_; l += N) {
+        cd Ll = sLw[0][l + P_];
+#pragma unroll
+        for (int v = 1; v < NW; ++v) Ll = cadd(Ll, sLw[v][l + P_]);
+        su = cfma(Ll, T[2 * NP + l + P_], su);
+        sd = cfma(Ll, T[3 * NP + l + P_], sd);
+      }
+      X[kk] = cadd(X[kk], cscale(su, nn));
+      X[N + kk] = cadd(X[N + kk], cmul(c, sd));
+    }
+    __syncthreads();
+  }
+  const cd* Z = pc_fft(X, Y, 2, N, logN, tw, false);
+  const double sc = 1.0 / N;
+  cd* dst = out + mem + (size_t)f * 2 * N;
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) dst[i] = cscale(Z[i], sc);
 }
 
 // Batched P2P: the NB members of a batch share one set of near blocks
@@ -2207,15 +2475,30 @@ template <int P>
 // only >= 0: launch stage `only` alone (0 P2M, 1 M2M, 2 M2L with the lattice
 // sums, 3 downward pass with L2P into the far-field buffer) reps times back
 // to back, for timing one kernel in steady state.
+// With the roots by Fourier modes (pb.spec_root) the chain covers only the
+// tree fibres' leaves and cells: the roots' moments and the spectral fibres'
+// far rows come from the own-block launches around it (apply_spectral).
 static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* ev, bool upward_only, int B,
                       hipEvent_t join = nullptr, cd* y_join = nullptr, bool near_in_down = false, int only = -1,
                       int reps = 1) {
   auto times = [&](int stage) { return only < 0 ? 1 : (only == stage ? reps : 0); };
   const HostPlan& hp = pb.hp;
-  // fibre roots by their Fourier modes (no near pairs, only root entries)
+  // fibre roots by their Fourier modes: the roots' and leaves' moments come
+  // from the first own-block launch (no P2M here), M2M only into the tree
+  // fibres' cells below their roots, no M2L sums and no downward pass here
+  // (the last own-block launch adds the partials and runs it)
   const bool spec = pb.spec_root && !upward_only;
-  int nc = (int)hp.cells.size();
-  int n_leaves = (int)hp.leaves.size();
+  int n_leaves = spec ? 0 : (int)hp.leaves.size();
+  const int* leaves = pb.d_leaves;
+  const int* ldesc = pb.d_ldesc;
+  const int n_down = spec ? 0 : n_leaves;       // spectral: the downward pass runs in k_self_inv
+  const int* ddesc = pb.d_ldesc;
+  const int* near_t0 = pb.d_leaf_near_t0;
+  const int n_up = spec ? pb.n_tup : pb.n_up;
+  const int* up_cells = spec ? pb.d_tup_cells : pb.d_up_cells;
+  const int* up_ptr = spec ? pb.d_tup_ptr : pb.d_up_ptr;
+  const int* up_src = spec ? pb.d_tup_src : pb.d_up_src;
+  const int* up_off = spec ? pb.d_tup_off : pb.d_up_off;
   int n_joff = (int)hp.joff_xy.size() / 2;
   const BatchStrides bs = batch_strides(pb);
   const int nch = pb.self_fft && !upward_only ? 1 : 2;
@@ -2224,24 +2507,34 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   // were slower on the square 8x8 block with one channel (21.7 us against
   // 15.5 us in order)
   for (int r = 0; r < times(0); ++r) {
-    if (spec)
-      hipLaunchKernelGGL(k_spec_fwd<P>, dim3(pb.M, B), dim3(SPEC_THREADS), 3 * (size_t)pb.N * sizeof(cd), s, d_psi,
-                         bs.vec, pb.d_spec_tab, pb.N, pb.d_mpole, bs.mpole);
-    else
-      hipLaunchKernelGGL((k_p2m<P, 1>), dim3(n_leaves, nch, B), dim3(128), 0, s, pb.d_leaves, pb.d_ldesc,
+    // few leaves (the tree fibres of a mostly spectral block): four groups
+    // of two wavefronts per (leaf, channel), each taking a quarter of the
+    // Gauss points, so that the launch is not one long serial loop per leaf
+    if (n_leaves > 0 && n_leaves * nch * B < 2 * pb.n_cu)
+      hipLaunchKernelGGL((k_p2m<P, 4>), dim3(n_leaves, nch, B), dim3(512), 0, s, leaves, ldesc,
+                         reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl,
+                         pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
+    else if (n_leaves > 0)
+      hipLaunchKernelGGL((k_p2m<P, 1>), dim3(n_leaves, nch, B), dim3(128), 0, s, leaves, ldesc,
                          reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl,
                          pb.opt.g_far, pb.N, pb.k, pb.k1, pb.eta, d_psi, pb.d_mpole, bs.vec, bs.mpole);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  for (int r = 0; r < times(1) && pb.n_up > 0 && !spec; ++r)
-    hipLaunchKernelGGL(k_m2m<P>, dim3(pb.n_up, nch, B), dim3(64 * M2M_WAVES), 0, s, pb.d_up_cells, pb.d_up_ptr,
-                       pb.d_up_src, pb.d_up_off, pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
+  for (int r = 0; r < times(1) && n_up > 0; ++r)
+    hipLaunchKernelGGL(k_m2m<P>, dim3(n_up, nch, B), dim3(64 * M2M_WAVES), 0, s, up_cells, up_ptr, up_src, up_off,
+                       pb.d_jtab, n_joff, pb.d_mpole, bs.mpole);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (upward_only) return;
   for (int r = 0; r < times(2) && pb.n_mchunks > 0; ++r) {
-    hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_mchunks, B), dim3(64), 0, s, pb.d_mchunks, pb.d_e_src, pb.d_e_off,
-                       pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
-                       bs.epart, bs.tab, bs.alpha);
+    if (pb.n_vchunks > 0)
+      hipLaunchKernelGGL(k_m2l<P>, dim3(pb.n_vchunks, B), dim3(64), 0, s, pb.d_mchunks, pb.d_e_src, pb.d_e_off,
+                         pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
+                         bs.epart, bs.tab, bs.alpha, pb.d_vchunks);
+    if (pb.n_mfma_items > 0)
+      hipLaunchKernelGGL(k_m2l_mfma<P>, dim3(pb.n_mfma_items, B), dim3(64 * ((2 * P + 16) / 16)), 0, s,
+                         reinterpret_cast<const int4*>(pb.d_mfma_items),
+                         reinterpret_cast<const int4*>(pb.d_mfma_cols), pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min,
+                         pb.d_mpole, pb.d_epart, bs.mpole, bs.epart, bs.tab, bs.alpha);
     if (pb.lat_fft) {
       const int ns = pb.lat_ns, pxy = pb.lat_px * pb.lat_py;
       constexpr int NP = 2 * P + 1;
@@ -2252,23 +2545,25 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
       hipLaunchKernelGGL(k_lat_inv<P>, dim3(NP, ns, B), dim3(256), 0, s, pb.d_lat_lhat, pb.d_lat_slot, ns,
                          pb.lat_gx, pb.lat_gy, pb.lat_px, pb.lat_py, pb.d_epart, bs.epart);
     }
-    hipLaunchKernelGGL(k_m2l_sum<P>, dim3(pb.n_chunks, B), dim3(256), 0, s, pb.d_chunks, pb.d_epart, pb.d_part,
-                       bs.epart, bs.part);
+    // with the roots by Fourier modes the consumers add the partials themselves
+    if (!spec)
+      hipLaunchKernelGGL(k_m2l_sum<P>, dim3(pb.n_chunks, B), dim3(256), 0, s, pb.d_chunks, pb.d_epart, pb.d_part,
+                         bs.epart, bs.part);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   if (join) (void)hipStreamWaitEvent(s, join, 0);
-  for (int r = 0; r < times(3) && spec; ++r)
-    hipLaunchKernelGGL(k_spec_inv<P>, dim3(pb.M, B), dim3(SPEC_THREADS), (size_t)pb.N * sizeof(cd), s,
-                       pb.d_spec_row, pb.d_part, bs.part, pb.d_spec_tab, pb.N, pb.eta, pb.varrho,
-                       y_join ? y_join : pb.d_far, bs.vec, y_join ? 1 : 0);
-  for (int r = 0; r < times(3) && !spec; ++r)
-    hipLaunchKernelGGL(k_down<P>, dim3(n_leaves, B), dim3(64 * nch), 0, s, pb.d_ldesc,
+  for (int r = 0; r < times(3) && n_down > 0; ++r)
+    hipLaunchKernelGGL(k_down<P>, dim3(n_down, B), dim3(64 * nch), 0, s, ddesc,
                        reinterpret_cast<const int2*>(pb.d_lanc), reinterpret_cast<const double4*>(pb.d_tgeo),
                        pb.d_psi_idx, pb.d_part, pb.d_jtab, n_joff, pb.N, pb.k, pb.k1, pb.eta, pb.varrho,
                        y_join ? y_join : pb.d_far, bs.part, bs.vec, y_join ? 1 : 0,
-                       near_in_down ? pb.d_leaf_near_t0 : nullptr, pb.d_near_rows);
+                       near_in_down ? near_t0 : nullptr, pb.d_near_rows);
   if (ev) (void)hipEventRecord(ev[4], s);
 }
+
+template <int P, typename C>
+static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B,
+                                 int only = -1, int reps = 1);
 
 // One stage of the chain launched reps times back to back between events
 // e0 and e1 on the handle's stream, after one whole chain that leaves every
@@ -2276,6 +2571,14 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
 template <int P>
 static hipError_t stage_timed_impl(Problem& pb, const cd* d_psi, int stage, int reps, hipEvent_t e0,
                                    hipEvent_t e1) {
+  if (pb.spec_root) {
+    // the stages of apply_spectral, with the far-part buffer as the output
+    (void)apply_spectral<P, cd>(pb, pb.d_near, d_psi, pb.d_far, nullptr, 0);
+    (void)hipEventRecord(e0, pb.stream);
+    (void)apply_spectral<P, cd>(pb, pb.d_near, d_psi, pb.d_far, nullptr, 0, stage, reps);
+    (void)hipEventRecord(e1, pb.stream);
+    return hipGetLastError();
+  }
   fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, 1);
   (void)hipEventRecord(e0, pb.stream);
   fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, 1, nullptr, nullptr, false, stage, reps);
@@ -2346,6 +2649,65 @@ static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const c
   }
 }
 
+// The apply with the roots by Fourier modes (pb.spec_root), in order on the
+// caller's stream:
+//   1. k_self_fwd: forward transforms, roots' moments, spectrum of P psi
+//      (one wave: also the stored near pairs' row sums), and in the same
+//      launch P2M at the tree fibres' leaves;
+//   2. M2M into the tree fibres' cells below their roots;
+//   3. M2L with the lattice sums (partial expansions only: the consumers
+//      add them);
+//   4. k_self_inv: y = P psi plus the far part of each fibre's root local
+//      expansion; k_down_spec: the downward pass of the tree fibres' leaves
+//      adds the far part of their cells below the root (one wave: and the
+//      near row sums); a batch: P2P of the stored pairs adds into y.
+// With stage events the same launches are bracketed by ev[0..4] (ev[5] and
+// ev[6] follow at once: the near part and the join are inside stages 1 and
+// 4).  only >= 0 repeats that stage reps times (steady-state timing).
+template <int P, typename C>
+static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B,
+                                 int only, int reps) {
+  auto times = [&](int stage) { return only < 0 ? 1 : (only == stage ? reps : 0); };
+  const int nb = B > 0 ? B : 1;
+  const BatchStrides bs = batch_strides(pb);
+  const int ntask = B == 0 ? pb.n_p2p_rowtasks : 0, tpb = PC_THREADS / 64;
+  const int extra = (ntask + tpb - 1) / tpb;
+  const size_t lds = 4 * (size_t)pb.N * sizeof(cd);
+  constexpr int NP = 2 * P + 1;
+  if (ev) (void)hipEventRecord(ev[0], pb.stream);
+  for (int r = 0; r < times(0); ++r) {
+    const int ntb = B == 0 ? extra : 0;
+    hipLaunchKernelGGL((k_self_fwd<P, C>), dim3(pb.M + ntb + pb.n_mcells, nb), dim3(PC_THREADS), lds, pb.stream,
+                       d_psi, pb.d_spec_hat, bs.vec, pb.d_pc_fwd, pb.d_pc_tw, pb.N, pb.pc_logN, pb.M,
+                       reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, ntask, ntb, pb.d_col_psi,
+                       blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole, pb.d_mcell,
+                       reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl, pb.opt.g_far,
+                       pb.k, pb.eta);
+  }
+  if (ev) (void)hipEventRecord(ev[1], pb.stream);
+  for (int r = 0; r < times(1); ++r) fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, nullptr, false, 1, 1);
+  if (ev) (void)hipEventRecord(ev[2], pb.stream);
+  for (int r = 0; r < times(2); ++r) fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, nullptr, false, 2, 1);
+  if (ev) (void)hipEventRecord(ev[3], pb.stream);
+  for (int r = 0; r < times(3); ++r) {
+    hipLaunchKernelGGL(k_self_inv<P>, dim3(pb.M, nb), dim3(PC_THREADS), lds, pb.stream, pb.d_spec_hat, d_y, bs.vec,
+                       pb.d_pc_tw, pb.N, pb.pc_logN, reinterpret_cast<const int2*>(pb.d_spec_rng), pb.d_epart,
+                       bs.epart, pb.d_spec_tab, pb.eta, pb.varrho);
+    if (pb.n_dleaves > 0)
+      hipLaunchKernelGGL(k_down_spec<P>, dim3(pb.n_dleaves, nb), dim3(64), 0, pb.stream, pb.d_dldesc,
+                         reinterpret_cast<const int4*>(pb.d_danc), pb.d_epart, bs.epart, pb.d_jtab,
+                         reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_psi_idx, pb.N, pb.k, pb.eta, pb.varrho,
+                         d_y, bs.vec, B == 0 ? pb.d_near_rows : nullptr);
+    if (B > 0) launch_p2p_any<P, C>(pb, pb.stream, blocks, d_psi, d_y, B);
+  }
+  if (ev) {
+    (void)hipEventRecord(ev[4], pb.stream);
+    (void)hipEventRecord(ev[5], pb.stream);
+    (void)hipEventRecord(ev[6], pb.stream);
+  }
+  return hipGetLastError();
+}
+
 // The apply with each fibre's own image-0 block applied by FFT (pb.self_fft):
 //   y = P psi + near(psi) + far(psi),
 // P the block-diagonal operator of the fibres' own blocks (identity included),
@@ -2358,6 +2720,7 @@ static void launch_p2p_any(Problem& pb, hipStream_t ps, const C* blocks, const c
 // its buffer, P and P2P write y, and the join kernel adds the far part.
 template <int P, typename C>
 static hipError_t apply_self_fft(Problem& pb, const C* blocks, const cd* d_psi, cd* d_y, hipEvent_t* ev, int B) {
+  if (pb.spec_root) return apply_spectral<P, C>(pb, blocks, d_psi, d_y, ev, B);
   const int nb = B > 0 ? B : 1;
   if (ev) {
     fmm_chain<P>(pb, d_psi, pb.stream, ev, false, nb);

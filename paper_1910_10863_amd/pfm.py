@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
                 ("p2p_blocks_per_cu", ctypes.c_int), ("p2p_unroll", ctypes.c_int),
                 ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
                 ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int),
-                ("self_mode", ctypes.c_int), ("tree_on_host", ctypes.c_int)]
+                ("self_mode", ctypes.c_int), ("tree_on_host", ctypes.c_int),
+                ("m2l_vector", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -73,7 +74,9 @@ class Stats(ctypes.Structure):
                 ("lattice_m2l_grid", ctypes.c_int), ("workspace_bytes", ctypes.c_double),
                 ("workspace_bound", ctypes.c_int), ("batch_capacity", ctypes.c_int),
                 ("n_device_allocs", ctypes.c_longlong), ("device_alloc_bytes", ctypes.c_double),
-                ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int), ("spectral_roots", ctypes.c_int)]
+                ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int), ("spectral_roots", ctypes.c_int),
+                ("n_spectral_fibres", ctypes.c_int), ("m2l_mfma_items", ctypes.c_int),
+                ("m2l_vector_chunks", ctypes.c_int)]
 
 
 FP64 = 0
@@ -170,7 +173,7 @@ class Problem:
                  max_batch: int = 1, use_graph: bool = False, p2p_blocks_per_cu: int = 0, p2p_unroll: int = 0,
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
                  direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True,
-                 tree_on_host: bool = False, spectral_roots: bool = True):
+                 tree_on_host: bool = False, spectral_roots: bool = True, m2l_vector: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -184,7 +187,7 @@ class Problem:
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
                       1 if direct_lattice_m2l else 0, 1 if precond else 0,
                       (0 if spectral_roots else 2) if self_fft else 1,
-                      1 if tree_on_host else 0)
+                      1 if tree_on_host else 0, 1 if m2l_vector else 0)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"

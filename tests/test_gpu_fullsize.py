@@ -174,17 +174,20 @@ def test_self_fft_apply_timed_overlapped_and_tree(pfm, key):
     assert d < 1e-9
 
 
-@pytest.mark.parametrize("key", ["square_4x4", "hexagon_16x16"])
-def test_spectral_roots_vs_tree_roots(pfm, key):
-    """Separated fibres (only root-to-root pairs between fibres and with
-    images): the roots' moments and locals by Fourier modes against the same
-    apply with P2M, M2M and the downward pass through each fibre's tree; they
-    differ by the M2M/L2L truncation at p = 24 only.  The in-order timed apply
-    equals the fused one bit for bit, and the batched apply matches it."""
-    wl = {"square_4x4": W.square_4x4_sweep, "hexagon_16x16": W.hexagon_16x16}[key]()
+@pytest.mark.parametrize("key,n_spec", [("square_4x4", 16), ("hexagon_16x16", 256), ("square_8x8", 58)])
+def test_spectral_roots_vs_tree_roots(pfm, key, n_spec):
+    """The roots' moments by Fourier modes and, for the fibres with only
+    root-to-root pairs, their far rows by a synthesis of the root's local
+    expansion, against the same apply with P2M, M2M and the downward pass
+    through every fibre's tree; they differ by the M2M/L2L truncation at
+    p = 24 only.  On the square 8x8 block six fibres have neighbours close
+    enough to keep their trees.  The in-order timed apply equals the fused
+    one bit for bit, and the batched apply matches it."""
+    wl = {"square_4x4": W.square_4x4_sweep, "hexagon_16x16": W.hexagon_16x16, "square_8x8": W.square_8x8}[key]()
     spec = pfm.Problem.from_workload(wl, max_batch=4)
     tree = pfm.Problem.from_workload(wl, spectral_roots=False)
     assert spec.stats()["spectral_roots"] == 1 and tree.stats()["spectral_roots"] == 0
+    assert spec.stats()["n_spectral_fibres"] == n_spec
     spec.set_wave(2.0, 0.1)
     tree.set_wave(2.0, 0.1)
     psi = torch.tensor(W.random_density(spec.n, 13), device="cuda")
@@ -205,6 +208,37 @@ def test_spectral_roots_vs_tree_roots(pfm, key):
         yi = spec.matvec(xs[i])
         e = float(torch.linalg.vector_norm(yb[i] - yi) / torch.linalg.vector_norm(yi))
         assert e < 1e-13, (i, e)
+
+
+@pytest.mark.parametrize("key", ["square_8x8", "square_4x4"])
+def test_m2l_matrix_cores_vs_vector_fullsize(pfm, key):
+    """At the benchmark sizes, the M2L on the matrix cores against every
+    entry on the vector ALU (the same sums, added in the same order; the
+    products differ by rounding only): single angle and a batch of three.
+    (The hexagon 16x16 block has no M2L entries: its fibres are separated
+    and its lattice M2L is the grid convolution.)"""
+    wl = {"square_4x4": W.square_4x4_sweep, "square_8x8": W.square_8x8}[key]()
+    mf = pfm.Problem.from_workload(wl, max_batch=4)
+    ve = pfm.Problem.from_workload(wl, max_batch=4, m2l_vector=True)
+    st = mf.stats()
+    _say("m2l mfma items", st["m2l_mfma_items"], "vector chunks", st["m2l_vector_chunks"],
+         ve.stats()["m2l_vector_chunks"])
+    assert st["m2l_mfma_items"] > 0
+    psi = torch.tensor(W.random_density(mf.n, 31), device="cuda")
+    for prob in (mf, ve):
+        prob.set_wave(3.0, 0.2)
+    a, b = mf.matvec(psi), ve.matvec(psi)
+    d = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    _say("single angle: rel diff", d)
+    assert d < 1e-13
+    th = [0.1, 0.3, -0.2]
+    xs = torch.stack([torch.tensor(W.random_density(mf.n, 40 + i), device="cuda") for i in range(3)])
+    for prob in (mf, ve):
+        prob.set_batch(3.0, th)
+    ya, yb = mf.matvec_batch(xs), ve.matvec_batch(xs)
+    d = float(((ya - yb).norm(dim=1) / yb.norm(dim=1)).max())
+    _say("batch of three: max rel diff", d)
+    assert d < 1e-13
 
 
 def test_row_windows_equal_cached_rows_square_8x8(pfm):

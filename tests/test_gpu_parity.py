@@ -145,12 +145,35 @@ def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, form):
     assert st["self_fft"] == (1 if eligible else 0)
     if eligible:
         assert st["n_m2l_int"] == 0 and st["n_near_circulant"] == 0
-    # fibres farther apart than the admissibility ratio allows: only root pairs
+    # fibres farther apart than the admissibility ratio allows: only root
+    # pairs, every fibre spectral; close fibres keep their trees
     separated = key in ("tiny", "sq2x2", "hex2x2")
-    assert st["spectral_roots"] == (1 if spectral and eligible and separated else 0)
-    if st["spectral_roots"]:
-        assert st["n_near_pairs"] == 0
+    M = _WL[key][0].M
+    assert st["spectral_roots"] == (1 if spectral and eligible else 0)
+    if st["spectral_roots"] and separated:
+        assert st["n_near_pairs"] == 0 and st["n_spectral_fibres"] == M
+    if st["spectral_roots"] and not separated:
+        assert st["n_near_pairs"] > 0 and st["n_spectral_fibres"] < M
     assert err < tol
+
+
+@pytest.mark.parametrize("form", ["spectral", "tree"])
+@pytest.mark.parametrize("key", ["tiny", "hex2x2", "sq3x1", "sq4x2close"])
+def test_m2l_matrix_cores_vs_dense_oracle(pfm, key, form):
+    """The M2L entries on the matrix cores (products of one translation with
+    up to 16 sources' moments) against the dense oracle and against every
+    entry on the vector ALU: both forms of the own blocks (every pair in the
+    tree: interior and exterior channels, leaf entries with images)."""
+    self_fft = form == "spectral"
+    err_m, prob_m = _matvec_err(pfm, key, 40, 16, self_fft=self_fft)
+    err_v, prob_v = _matvec_err(pfm, key, 40, 16, self_fft=self_fft, m2l_vector=True)
+    sm, sv = prob_m.stats(), prob_v.stats()
+    _say("m2l mfma vs vector:", key, form, err_m, err_v, sm["m2l_mfma_items"], sm["m2l_vector_chunks"],
+         sv["m2l_vector_chunks"])
+    assert sm["m2l_mfma_items"] > 0 and sv["m2l_mfma_items"] == 0
+    assert sv["m2l_vector_chunks"] >= sm["m2l_mfma_items"]
+    assert err_m < 1e-10 and err_v < 1e-10
+    assert abs(err_m - err_v) < 1e-12
 
 
 @pytest.mark.parametrize("key", ["sq3x1", "sq2x2close", "hex2x2"])
