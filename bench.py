@@ -7,9 +7,11 @@ unknowns; p = 24; ka swept over 32 values in [0.5, 6.0] at theta = 0;
 GMRES tolerance 1e-8.
 
 A timed step is one application of the operator (I - A) of eq. (9) to a
-resident complex128 vector: each fibre's own block by FFT, the FMM chain
-(P2M, M2M, M2L, lattice M2L, L2L, L2P) for the pairs between fibres and with
-images, P2P of their stored near blocks, and the row combination.  `value`
+resident complex128 vector: each fibre's own block by FFT, whose transforms
+also give the fibre roots' moments and evaluate the roots' local
+expansions; the FMM chain (P2M, M2M, M2L on the matrix cores with the
+lattice sums, L2L, L2P) where fibres are close; P2P of their stored near
+blocks.  `value`
 is unknowns processed per second.  The ka sweep is solved by GMRES to a true
 relative residual of 1e-8 and reported as solves per second, per-frequency
 setup included; each leg reports its error against a reference checked by
@@ -28,51 +30,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
-PROFILE = os.path.join(ROOT, "profiles", "k_p2m_square_8x8_N512.md")
+FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64, vector and matrix cores alike
+PROFILE = os.path.join(ROOT, "profiles", "k_m2l_mfma_square_8x8_N512.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1910_10863_amd", "csrc", "pfm_kernels.hip")
-MATH_SRC = os.path.join(ROOT, "paper_1910_10863_amd", "csrc", "pfm_math.hpp")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
-def p2m_source_sha256():
-    """Digest of the P2M kernel's source: its part of the kernel file (from
-    its leading comment to the next kernel's) and the math header it uses."""
+def m2l_source_sha256():
+    """Digest of the matrix-core M2L kernel's source: its part of the kernel
+    file, from its leading comment to the next kernel's."""
     import hashlib
     src = open(KERNEL_SRC).read()
-    a = src.index("// P2M: multipole moments at the leaves")
-    b = src.index("// The value of lane `lane`", a)
-    return hashlib.sha256((src[a:b] + open(MATH_SRC).read()).encode()).hexdigest()
+    a = src.index("// M2L entries on the matrix cores.")
+    b = src.index("// The M2L sum of each (channel, cell)", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
 def measured_traffic():
-    """HBM bytes per k_p2m launch from the committed counter summary, or None
-    when the kernel's source has changed since the counters were taken."""
+    """HBM bytes per k_m2l_mfma launch from the committed counter summary, or
+    None when the kernel's source has changed since the counters were taken."""
     try:
         txt = open(PROFILE).read()
         vals = dict(line.split(": ", 1) for line in txt.splitlines()
                     if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
-        if vals.get("kernel_source_sha256", "").strip() != p2m_source_sha256():
+        if vals.get("kernel_source_sha256", "").strip() != m2l_source_sha256():
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def p2m_kernel_flops(st, p, g_far, channels):
-    """Algorithmic FP64 flops of one P2M launch: for every Gauss point of the
-    far rule (E g_far), every wavenumber channel and every order n = -p..p,
-    the three complex multiply-adds of the moment update
-    M_n += w0 Jm_n + wm Jm_{n-1} + wp Jm_{n+1} (24 flops); the Bessel
-    sequence itself is not counted."""
-    return 24.0 * st["E"] * g_far * channels * (2 * p + 1)
+def m2l_kernel_flops(st, p):
+    """Algorithmic FP64 flops of one matrix-core M2L launch: per M2L entry
+    (explicit pairs and the lattice sums of the root pairs) the Toeplitz
+    translation of eq. 13, (2p + 1)^2 complex multiply-adds of 8 flops; the
+    zero padding of the 16 x 16 x 4 products is not counted."""
+    return 8.0 * (2 * p + 1) ** 2 * st["m2l_mfma_entries"]
 
 
-def p2m_kernel_bytes(st, p, channels):
-    """Algorithmic HBM bytes of one P2M launch: per element its geometry
-    (midpoint offset, tangent: 32 B; length: 8 B) and two densities (32 B);
-    per leaf and channel its 2p + 1 complex128 moments written."""
-    return 72.0 * st["E"] + 16.0 * (2 * p + 1) * channels * st["n_leaves"]
+def m2l_kernel_bytes(st, p):
+    """Algorithmic HBM bytes of one matrix-core M2L launch: per entry its
+    source's 2p + 1 complex128 moments read and its 2p + 1 partial local
+    coefficients written; per product the 4p + 1 translation coefficients."""
+    return 32.0 * (2 * p + 1) * st["m2l_mfma_entries"] + 16.0 * (4 * p + 1) * st["m2l_mfma_items"]
 
 
 def cpu_model():
@@ -558,23 +558,26 @@ def main():
     # stage durations from HIP events recorded on the library's stream, each
     # stage alone (in order)
     stages, tot_ms, _ = prob.matvec_timed(psi, reps=max(10, min(args.steps, 50)))
-    # Dominant kernel: P2M, the longest launch of the apply's critical path
-    # (the FMM chain; each fibre's own block by FFT and the P2P of the few
-    # stored pairs run beside it on the side stream).  It is bound by FP64
-    # arithmetic: Bessel sequences and multiply-adds per Gauss point and order.
-    channels = 1 if st["self_fft"] else 2
-    # each chain kernel launched back to back in steady state (HIP events
-    # around the repeated launches on the library's stream), the figure a
-    # kernel trace's average duration gives
+    # Each stage launched back to back in steady state (HIP events around
+    # the repeated launches on the library's stream), the figure a kernel
+    # trace's average duration gives.  With the roots by Fourier modes the
+    # stages are: forward transforms of the own blocks with the roots'
+    # moments and P2M at the tree fibres' leaves ("p2m"), M2M ("m2m"), M2L
+    # ("m2l": on this block the one matrix-core launch), inverse transforms
+    # with the roots' far part and the tree fibres' downward pass
+    # ("down_l2p").  Roofline kernel: the M2L on the matrix cores, the one
+    # dense contraction of the apply.
     steady = {s: prob.stage_timed(psi, s, reps=max(50, min(args.steps, 200)))
               for s in ("p2m", "m2m", "m2l", "down_l2p")}
-    k_ms = steady["p2m"]
-    lf = p2m_kernel_flops(st, p, 4, channels)
-    lb = p2m_kernel_bytes(st, p, channels)
+    assert st["m2l_vector_chunks"] == 0 and not st["lattice_m2l_grid"], "M2L stage is not the matrix-core launch alone"
+    k_ms = steady["m2l"]
+    lf = m2l_kernel_flops(st, p)
+    lb = m2l_kernel_bytes(st, p)
     fl = lf / (k_ms * 1e-3) / 1e12
     bw = lb / (k_ms * 1e-3) / 1e9
-    roof = {"bound": "alu", "achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": fl / FP64_PEAK_TFLOPS, "flops_per_launch": lf,
+    roof = {"bound": "mfma", "achieved": fl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": fl / FP64_PEAK_TFLOPS, "flops_per_launch": lf, "entries": st["m2l_mfma_entries"],
+            "products": st["m2l_mfma_items"],
             "hbm": {"achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bw / HBM_PEAK_GBS,
                     "bytes_per_launch": lb}}
 
@@ -701,7 +704,7 @@ def main():
         "median_ms_per_apply": median_ms,
         "stages_ms": stages,
         "stage_steady_ms": steady,
-        "roofline": dict(kernel=f"k_p2m (multipole moments, {channels} channel(s))", **roof,
+        "roofline": dict(kernel="k_m2l_mfma (M2L products on v_mfma_f64_16x16x4, FP64)", **roof,
                          traffic=measured_traffic(), launch_ms=k_ms),
         "sweep": sweep,
         "mixed_precision": mixed,
@@ -712,7 +715,8 @@ def main():
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_near_stored", "n_near_circulant",
                                     "p2p_window_leaves", "p2p_window_max", "n_root_offsets", "lattice_q",
-                                    "self_fft")},
+                                    "self_fft", "spectral_roots", "n_spectral_fibres", "m2l_mfma_items",
+                                    "m2l_mfma_entries", "m2l_vector_chunks")},
         "wall_s": wall,
     }
     print(json.dumps(out), flush=True)

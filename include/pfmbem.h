@@ -259,6 +259,7 @@ typedef struct {
   int n_spectral_fibres;       /* fibres whose far rows come from their root's local expansion alone */
   int m2l_mfma_items;          /* M2L matrix products on the matrix cores (m2l_vector = 0) */
   int m2l_vector_chunks;       /* M2L entry chunks on the vector ALU */
+  int m2l_mfma_entries;        /* M2L entries in those products (columns) */
 } pfm_stats;
 
 /* Build the plan: discretisation, quadtrees and interaction lists (on the
@@ -367,7 +368,12 @@ pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
  * pass with L2P, near part (each fibre's own block by FFT and P2P of the
  * stored pairs), join of near and far parts], and of the whole apply in
  * *total_ms.  The stages write the far part to a buffer of their own and a
- * join kernel adds it (pfm_matvec fuses the join into the downward pass). */
+ * join kernel adds it (pfm_matvec fuses the join into the downward pass).
+ * With the roots by Fourier modes (pfm_stats.spectral_roots) the launches
+ * are those of pfm_matvec, bracketed: [forward transforms of the own blocks
+ * with the roots' moments and P2M at the tree fibres' leaves, M2M, M2L,
+ * inverse transforms with the roots' far part and the tree fibres'
+ * downward pass (and near rows), 0, 0]. */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);
 
@@ -410,7 +416,8 @@ pfm_status pfm_sweep(pfm_problem* pb, int n_ka, const double* ka, int B, const d
                      pfm_info* infos);
 
 /* One stage of the FMM chain of the current wave (0 P2M, 1 M2M, 2 M2L
- * with the lattice sums, 3 downward pass with L2P) launched reps times back
+ * with the lattice sums, 3 downward pass with L2P; with the roots by
+ * Fourier modes the stages of pfm_matvec_timed) launched reps times back
  * to back on the bound stream after one whole chain for d_psi, which leaves
  * every stage's inputs in place; *ms_per_launch = the mean duration of one
  * launch (HIP events around the reps launches).  For measuring a kernel

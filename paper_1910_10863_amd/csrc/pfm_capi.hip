@@ -923,6 +923,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         }
       pb.n_vchunks = (int)vch.size();
       pb.n_mfma_items = (int)(items.size() / 4);
+      pb.n_mfma_cols = (int)(cols.size() / 4);
       if (vch.empty()) vch.assign(1, 0);
       if (items.empty()) items.assign(4, 0), cols.assign(4, 0);
       CK(upload(pb, &pb.d_vchunks, vch)); CK(upload(pb, &pb.d_mfma_items, items)); CK(upload(pb, &pb.d_mfma_cols, cols));
@@ -2105,6 +2106,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->n_spectral_fibres = pb.spec_root ? pb.n_spec : 0;
   st->m2l_mfma_items = pb.n_mfma_items;
   st->m2l_vector_chunks = pb.n_vchunks;
+  st->m2l_mfma_entries = pb.n_mfma_cols;
   return PFM_OK;
 }
 

@@ -168,7 +168,7 @@ struct Problem {
   int n_vchunks = 0;
   int *d_mfma_items = nullptr;          // [item][4]: channel, table row, first column, columns (<= 16)
   int *d_mfma_cols = nullptr;           // [column][4]: source cell, partial slot (chunk), image, 0
-  int n_mfma_items = 0;
+  int n_mfma_items = 0, n_mfma_cols = 0;
   int n_cu = 0;                         // compute units of the device
   int p2p_grid = 0;                     // workgroups of the P2P launch (0: one per work item)
   int p2p_split = 1;                    // column splits per target leaf
