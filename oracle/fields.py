@@ -25,8 +25,13 @@ from .geometry import gauss_points
 from .system import Problem, split_density
 
 
-def bragg(pb: Problem, psi, n_orders: int, G: int = 8):
+def bragg(pb: Problem, psi, n_orders: int, G: int | None = None):
+    """Bragg orders, their wavenumbers and amplitudes R_n, T_n.  The boundary
+    integrals use the 8-point Gauss rule on every chord, or for the Nystrom
+    boundary (nystrom.py, nodes and trapezoid weights) the nodes themselves."""
     bd = pb.bd
+    if G is None:
+        G = 1 if getattr(bd, "speed", None) is not None else 8
     phi_d, vphi = split_density(pb, psi)
     gp, gw = gauss_points(bd, G)
     n = np.arange(-n_orders, n_orders + 1)
