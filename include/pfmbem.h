@@ -82,6 +82,22 @@ typedef enum { PFM_FP64 = 0, PFM_MIXED = 1 } pfm_precision;
  * circulant self rows, self_mode 0 and precond = 1 need PFM_CIRCLE. */
 typedef enum { PFM_CIRCLE = 0, PFM_ROUND_SQUARE = 1 } pfm_shape;
 
+/* Discretisation of the boundary integral equations of Sec. 2 (eqs. 6-9).
+ * PFM_CHORDS: N straight chords per fibre between the nodes, constant
+ * densities collocated at the chord midpoints, Gauss-Legendre rules on the
+ * chords with exact integrals for the self and neighbouring elements (the
+ * element method).  PFM_NYSTROM: the spectral Nystrom method of Kress (the
+ * paper's refs. 2 and 4): densities at the N nodes t_e = 2 pi e / N of the
+ * parametrisation, the trapezoidal rule for the smooth kernels (other fibres,
+ * periodic images), and for each fibre's own operators Kress's logarithmic
+ * splitting with the hypersingular operator by Maue's identity and
+ * trigonometric differentiation; it converges exponentially in N where the
+ * element method converges at first order.  PFM_NYSTROM needs PFM_CIRCLE
+ * fibres with N a power of two, 8 <= N <= 512 (each fibre's own block is
+ * applied by FFT: self_mode 0 or 2, store_self_blocks 0); g_far is taken as
+ * 1 (the point rule at the nodes). */
+typedef enum { PFM_CHORDS = 0, PFM_NYSTROM = 1 } pfm_discretisation;
+
 typedef struct {
   int lattice;
   double a;
@@ -183,6 +199,7 @@ typedef struct {
  *             fibre's tree with more than 512 cells) the host builds it
  *             (pfm_stats.tree_on_device tells which ran).  1: the host
  *             construction (the reference the GPU build is tested against).
+ *  discretisation  PFM_CHORDS or PFM_NYSTROM (pfm_discretisation).
  *  m2l_vector 0: the M2L entries (eq. 13) that share a translation (an offset
  *             between cells, or the lattice sum of a fibre offset, Sec. 3.3)
  *             are applied together as complex matrix products on the matrix
@@ -210,6 +227,7 @@ typedef struct {
   int self_mode;
   int tree_on_host;
   int m2l_vector;
+  int discretisation;      /* pfm_discretisation */
 } pfm_options;
 
 #define PFM_MAX_BATCH 16

@@ -164,7 +164,7 @@ void free_all(Problem& pb) {
   dfree(pb.d_near_blk); dfree(pb.d_leaf_blk); dfree(pb.d_cols_ptr); dfree(pb.d_col_psi); dfree(pb.d_col_m);
   dfree(pb.d_p2p_items); dfree(pb.d_p2p_rowtasks); dfree(pb.d_p2p_rowoff); dfree(pb.d_leaf_near_t0);
   dfree(pb.d_ccols_ptr); dfree(pb.d_ccol_psi); dfree(pb.d_ccol_loc); dfree(pb.d_cwin); dfree(pb.d_circ);
-  dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x);
+  dfree(pb.d_pc_fwd); dfree(pb.d_pc_inv); dfree(pb.d_pc_tw); dfree(pb.d_pc_x); dfree(pb.d_kress);
   dfree(pb.d_lat_cell); dfree(pb.d_lat_slot); dfree(pb.d_lat_key); dfree(pb.d_lat_shat); dfree(pb.d_lat_xhat);
   dfree(pb.d_lat_lhat);
   dfree(pb.d_near_uniq); dfree(pb.d_near_cp_src); dfree(pb.d_near_cp_dst); dfree(pb.d_near_cp_len);
@@ -297,6 +297,13 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "tree_on_host must be 0 or 1"));
   if (opt->m2l_vector != 0 && opt->m2l_vector != 1)
     return bail(fail(pb, PFM_EINVAL, "m2l_vector must be 0 or 1"));
+  if (opt->discretisation != PFM_CHORDS && opt->discretisation != PFM_NYSTROM)
+    return bail(fail(pb, PFM_EINVAL, "discretisation must be PFM_CHORDS or PFM_NYSTROM"));
+  if (opt->discretisation == PFM_NYSTROM &&
+      (geo->shape != PFM_CIRCLE || geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0 ||
+       opt->self_mode == 1 || opt->store_self_blocks))
+    return bail(fail(pb, PFM_EINVAL, "PFM_NYSTROM needs circles, N a power of two in 8..512, self_mode 0 or 2 "
+                                     "and store_self_blocks 0"));
   if (opt->precond == 1 && (geo->n_elem < 8 || geo->n_elem > 512 || (geo->n_elem & (geo->n_elem - 1)) != 0))
     return bail(fail(pb, PFM_EINVAL, "precond = 1 needs n_elem a power of two in 8..512"));
   if (opt->max_batch < 0 || opt->max_batch > PFM_MAX_BATCH || (opt->use_graph != 0 && opt->use_graph != 1))
@@ -323,6 +330,9 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   // of two it is applied by the FFTs of the preconditioner's transforms.
   pb.self_fft = opt->self_mode != 1 && !opt->store_self_blocks && geo->shape == PFM_CIRCLE && pb.N >= 8 &&
                 pb.N <= 512 && (pb.N & (pb.N - 1)) == 0;
+  // Nystrom: the point rule at the nodes for every smooth kernel
+  pb.nystrom = opt->discretisation == PFM_NYSTROM;
+  if (pb.nystrom) pb.opt.g_far = 1;
 
   pb.rho_f = mat->rho_fiber;
   pb.c_f = mat->c_fiber;
@@ -746,6 +756,17 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(pb, &pb.d_pc_tw, tw));
     pb.pc_logN = 0;
     while ((1 << pb.pc_logN) < pb.N) ++pb.pc_logN;
+  }
+  if (pb.nystrom) {
+    // Kress's logarithmic weights R(t_d), t_d = 2 pi d / N, of the spectral
+    // Nystrom rule for the log-singular kernels (the paper's refs. 2 and 4)
+    std::vector<double> R(pb.N);
+    for (int d = 0; d < pb.N; ++d) {
+      double acc = 0.0;
+      for (int m = 1; m < pb.N / 2; ++m) acc += std::cos(2.0 * M_PI * (double)m * d / pb.N) / m;
+      R[d] = -(4.0 * M_PI / pb.N) * acc - (4.0 * M_PI / ((double)pb.N * pb.N)) * (d % 2 ? -1.0 : 1.0);
+    }
+    CK(upload(pb, &pb.d_kress, R));
   }
   CK(upload(pb, &pb.d_root_pair_off, hp.root_pair_off));
   CK(upload(pb, &pb.d_root_mrange, hp.root_off_mrange));

@@ -268,6 +268,10 @@ struct Problem {
   // applied by FFT as a block-circulant operator; the tree holds only the
   // pairs between fibres and with images, and only the exterior channel
   bool self_fft = false;
+  // spectral Nystrom discretisation (PFM_NYSTROM): nodes as points, trapezoid
+  // weights as lengths, each fibre's own block from Kress's quadrature
+  bool nystrom = false;
+  double *d_kress = nullptr;            // [N] logarithmic weights R(2 pi d / N)
   bool tree_on_device = false;          // the plan was built by the GPU kernels
   int device = 0;                       // the GPU the handle was created on
   void* static_scratch = nullptr;       // that GPU's address of the fixed scratch array (pfm_matvec_static)

@@ -39,7 +39,11 @@ __device__ inline void boundary_point(int shape, double r, double t, double& x, 
   }
 }
 
-__global__ void k_discretise(int E, int N, int shape, const double* __restrict__ centres,
+// nystrom = 0: chord e between the nodes at t_e and t_{e+1} (midpoint, unit
+// tangent, length).  nystrom = 1 (circles): the node at t_e itself as the
+// point, the circle's unit tangent, and the trapezoid weight r 2 pi / N as
+// the length; both chord ends are the node (the tree's tight radii).
+__global__ void k_discretise(int E, int N, int shape, int nystrom, const double* __restrict__ centres,
                              const double* __restrict__ radii, double* mx, double* my,
                              double* tx, double* ty, double* h, double* ends) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,6 +51,21 @@ __global__ void k_discretise(int E, int N, int shape, const double* __restrict__
   int f = e / N, l = e - f * N;
   double t0 = 2.0 * PI * l / N, t1 = 2.0 * PI * (l + 1) / N;
   double cx = centres[2 * f], cy = centres[2 * f + 1], r = radii[f];
+  if (nystrom) {
+    double sv, cv;
+    sincospi(2.0 * (double)l / (double)N, &sv, &cv);
+    const double px = cx + r * cv, py = cy + r * sv;
+    mx[e] = px;
+    my[e] = py;
+    tx[e] = -sv;
+    ty[e] = cv;
+    h[e] = 2.0 * PI * r / N;
+    if (ends) {
+      ends[4 * e + 0] = ends[4 * e + 2] = px;
+      ends[4 * e + 1] = ends[4 * e + 3] = py;
+    }
+    return;
+  }
   double ux, uy, vx, vy;
   boundary_point(shape, r, t0, ux, uy);
   boundary_point(shape, r, t1, vx, vy);
@@ -70,7 +89,8 @@ __global__ void k_discretise(int E, int N, int shape, const double* __restrict__
 hipError_t launch_discretise(Problem& pb, double* d_ends) {
   int E = pb.E;
   hipLaunchKernelGGL(k_discretise, dim3((E + 255) / 256), dim3(256), 0, pb.stream, E, pb.N, pb.shape,
-                     pb.d_centres, pb.d_radii, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, d_ends);
+                     pb.nystrom ? 1 : 0, pb.d_centres, pb.d_radii, pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h,
+                     d_ends);
   return hipGetLastError();
 }
 
@@ -247,6 +267,8 @@ __global__ void k_copy_blocks(const long long* __restrict__ src, const long long
   for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < len[c]; i += gridDim.y * blockDim.x) d[i] = s[i];
 }
 
+static hipError_t launch_circ_rows_nys(Problem& pb);
+
 hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   const HostPlan& hp = pb.hp;
   int npairs = (int)hp.near_src.size();
@@ -274,6 +296,8 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   if (npairs > 0 && pb.n_near_copies > 0)
     hipLaunchKernelGGL(k_copy_blocks, dim3(pb.n_near_copies, (4 * lm * lm + 255) / 256), dim3(256), 0, pb.stream,
                        pb.d_near_cp_src, pb.d_near_cp_dst, pb.d_near_cp_len, pb.d_near);
+  if (pb.nystrom)
+    return launch_circ_rows_nys(pb);
   if (pb.n_near_circ > 0 || pb.opt.precond || pb.self_fft)
     hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + 127) / 128, pb.M), dim3(128), 0, pb.stream, A, pb.d_circ);
   return hipGetLastError();
@@ -345,6 +369,121 @@ __device__ cd* pc_fft(cd* X, cd* Y, int nv, int N, int logN, const cd* __restric
     Y = t;
   }
   return X;
+}
+
+// Circulant rows of the Nystrom discretisation (circles): the 2x2 blocks of
+// (I - A) without the identity for node 0 of fibre f and its node d (image
+// 0), d = 0..N-1, laid out as k_circ_rows.  On a circle of radius r every
+// operator of Kress's quadrature depends on d only: with t = 2 pi d / N,
+// R_d = kress[d] the logarithmic weight, lg = ln(4 sin^2(t/2)), the distance
+// rho = 2 r |sin(t/2)|, and per wavenumber kap (k outside, k1 inside)
+//   S   = R_d F1 + (2 pi/N)(F - F1 lg),  F = (i/4) H0(kap rho) r,       F1 = -J0 r / (4 pi)
+//   D   ...                             F = (i kap/4) H1 (x - y).nt / rho, F1 = -(kap/4 pi) J1 (x - y).nt / rho
+//   K   ...                             F = -(i kap/4) H1 (x - y).nu / rho r, F1 its J1 part
+//   S0  ...                             F = (i/4) H0,   F1 = -J0 / (4 pi)   (for T)
+//   Snu ...                             F = (i/4) H0 r cos t, F1 = -J0 r cos t / (4 pi)
+// with (x - y).nt = -2 r^2 sin^2(t/2), (x - y).nu = 2 r sin^2(t/2), and at
+// d = 0 the limits F - F1 lg -> (i/4 - C/(2 pi) - ln(kap r/2)/(2 pi)) r for S
+// and Snu (without r for S0) and -1/(4 pi) for D and K (curvature 1/r).
+// T = (1/r) D S0 D + kap^2 Snu by Maue's identity, with D the trigonometric
+// differentiation: the circulant (1/r) D S0 D has the eigenvalues
+// -q^2 lambda_S0(q) / r (q signed, 0 on the Nyquist mode), lambda(q) =
+// sum_d row(d) w^{q d}; its row is (1/N) sum_q lambda(q) w^{-q d}.  One
+// workgroup per fibre; the two S0 rows go through the block's transforms.
+__global__ void __launch_bounds__(PC_THREADS) k_circ_rows_nys(int N, int logN, const double* __restrict__ radii,
+                                                              double k, double k1, double eta, double varrho,
+                                                              const double* __restrict__ kress,
+                                                              const cd* __restrict__ tw, cd* __restrict__ circ) {
+  extern __shared__ cd pcs[];
+  const int f = blockIdx.x;
+  const double r = radii[f];
+  cd* X = pcs;                   // [2][N]: the S0 rows at k and k1
+  cd* Y = pcs + 2 * N;
+  const double w2 = 2.0 * PI / N;
+  for (int d = threadIdx.x; d < N; d += blockDim.x) {
+    double sv, cv, s2, c2;
+    sincospi((double)d / (double)N, &s2, &c2);         // sin(t/2), cos(t/2)
+    sincospi(2.0 * (double)d / (double)N, &sv, &cv);   // sin t, cos t
+    const double R = kress[d];
+    for (int ch = 0; ch < 2; ++ch) {
+      const double kap = ch ? k1 : k;
+      cd S0;
+      if (d == 0) {
+        const cd lnk = mkc(-EULER_GAMMA / (2.0 * PI) - log(0.5 * kap * r) / (2.0 * PI), 0.25);
+        S0 = cadd(mkc(-R / (4.0 * PI), 0.0), cscale(lnk, w2));
+      } else {
+        const double rho = 2.0 * r * fabs(s2), lg = log(4.0 * s2 * s2);
+        cd H0, H1;
+        hankel01(kap * rho, H0, H1);
+        const cd F = mkc(-0.25 * H0.y, 0.25 * H0.x);               // (i/4) H0
+        const double F1 = -H0.x / (4.0 * PI);                      // -J0 / (4 pi)
+        S0 = cadd(mkc(R * F1, 0.0), cscale(csub(F, mkc(F1 * lg, 0.0)), w2));
+      }
+      X[ch * N + d] = S0;
+    }
+  }
+  __syncthreads();
+  cd* L = pc_fft(X, Y, 2, N, logN, tw, false);           // eigenvalues of S0
+  for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+    const int q = i & (N - 1);
+    const int qs = 2 * q == N ? 0 : (2 * q < N ? q : q - N);
+    L[i] = cscale(L[i], -(double)qs * (double)qs / r);
+  }
+  __syncthreads();
+  const cd* Z = pc_fft(L, L == X ? Y : X, 2, N, logN, tw, true);   // N x rows of (1/r) D S0 D
+  const cd c = mkc(0.0, -2.0 / (eta * (1.0 + varrho)));            // 2 / (i eta (1 + varrho))
+  const cd mieta = mkc(0.0, -eta);
+  cd* row = circ + (size_t)f * 8 * N;
+  for (int d = threadIdx.x; d < N; d += blockDim.x) {
+    double sv, cv, s2, c2;
+    sincospi((double)d / (double)N, &s2, &c2);
+    sincospi(2.0 * (double)d / (double)N, &sv, &cv);
+    const double R = kress[d];
+    cd S[2], Dv[2], Kv[2], T[2];
+    for (int ch = 0; ch < 2; ++ch) {
+      const double kap = ch ? k1 : k;
+      cd Snu;
+      if (d == 0) {
+        const cd lnk = mkc(-EULER_GAMMA / (2.0 * PI) - log(0.5 * kap * r) / (2.0 * PI), 0.25);
+        S[ch] = cadd(mkc(-R * r / (4.0 * PI), 0.0), cscale(lnk, w2 * r));
+        Snu = S[ch];
+        Dv[ch] = Kv[ch] = mkc(-w2 / (4.0 * PI), 0.0);
+      } else {
+        const double rho = 2.0 * r * fabs(s2), lg = log(4.0 * s2 * s2);
+        cd H0, H1;
+        hankel01(kap * rho, H0, H1);
+        const double J0 = H0.x, J1r = H1.x / rho;
+        const cd F = mkc(-0.25 * H0.y * r, 0.25 * H0.x * r);         // (i/4) H0 r
+        const double F1 = -J0 * r / (4.0 * PI);
+        S[ch] = cadd(mkc(R * F1, 0.0), cscale(csub(F, mkc(F1 * lg, 0.0)), w2));
+        const cd Fn = cscale(F, cv);                                  // times cos t
+        Snu = cadd(mkc(R * F1 * cv, 0.0), cscale(csub(Fn, mkc(F1 * cv * lg, 0.0)), w2));
+        const double dnt = -2.0 * r * r * s2 * s2, dnu = 2.0 * r * s2 * s2;
+        const cd ikH1 = mkc(-0.25 * kap * H1.y, 0.25 * kap * H1.x);  // (i kap/4) H1
+        const cd FD = cscale(ikH1, dnt / rho);
+        const double F1D = -(kap / (4.0 * PI)) * J1r * dnt;
+        Dv[ch] = cadd(mkc(R * F1D, 0.0), cscale(csub(FD, mkc(F1D * lg, 0.0)), w2));
+        const cd FK = cscale(ikH1, -dnu * r / rho);
+        const double F1K = (kap / (4.0 * PI)) * J1r * dnu * r;
+        Kv[ch] = cadd(mkc(R * F1K, 0.0), cscale(csub(FK, mkc(F1K * lg, 0.0)), w2));
+      }
+      T[ch] = cadd(cscale(Z[ch * N + d], 1.0 / N), cscale(Snu, kap * kap));
+    }
+    const cd B11 = csub(Dv[0], Dv[1]);
+    const cd B12 = cmul(mieta, csub(S[0], S[1]));
+    const cd B21 = cmul(c, csub(T[0], cscale(T[1], varrho)));
+    const cd B22 = cmul(cmul(c, mieta), csub(Kv[0], cscale(Kv[1], varrho)));
+    row[d] = row[d + N] = B11;
+    row[2 * N + d] = row[3 * N + d] = B12;
+    row[4 * N + d] = row[5 * N + d] = B21;
+    row[6 * N + d] = row[7 * N + d] = B22;
+  }
+}
+
+static hipError_t launch_circ_rows_nys(Problem& pb) {
+  hipLaunchKernelGGL(k_circ_rows_nys, dim3(pb.M), dim3(PC_THREADS), 4 * (size_t)pb.N * sizeof(cd), pb.stream, pb.N,
+                     pb.pc_logN, pb.d_radii, pb.k, pb.k1, pb.eta, pb.varrho, pb.d_kress, pb.d_pc_tw, pb.d_circ);
+  return hipGetLastError();
 }
 
 // L(kappa) of fibre blockIdx.x for the two row components 2 blockIdx.y and
@@ -823,7 +962,7 @@ hipError_t launch_rhs(Problem& pb, double theta, cd* d_b) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_fields(int E, int N, int n_orders, const double* mx,
                                                 const double* my, const double* tx, const double* ty,
-                                                const double* h, const double* gl8, double k,
+                                                const double* h, const double* gl8, int G, double k,
                                                 double th, double H, double eta, const cd* psi,
                                                 cd* out) {
   int n = (int)blockIdx.x - n_orders;
@@ -835,8 +974,8 @@ __global__ void __launch_bounds__(256) k_fields(int E, int N, int n_orders, cons
     int f = e / N, l = e - f * N;
     cd ph = psi[2 * f * N + l], vp = psi[2 * f * N + N + l];
     double n1 = ty[e], n2 = -tx[e];
-    for (int g = 0; g < 8; ++g) {
-      double s = 0.5 * h[e] * gl8[g], w = 0.5 * h[e] * gl8[8 + g];
+    for (int g = 0; g < G; ++g) {
+      double s = 0.5 * h[e] * gl8[g], w = 0.5 * h[e] * gl8[G + g];
       double y1 = mx[e] + s * tx[e], y2 = my[e] + s * ty[e];
       // T: e^{-i(gam y1 + kap y2)} [ (gam n1 + kap n2) phi + eta varphi ]
       cd argT = cmul_i(mkc(-(gam.x * y1 + kap * y2), -gam.y * y1));
@@ -867,9 +1006,10 @@ __global__ void __launch_bounds__(256) k_fields(int E, int N, int n_orders, cons
 }
 
 hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out) {
+  // the 8-point Gauss rule on every chord, or the Nystrom nodes (point rule)
   hipLaunchKernelGGL(k_fields, dim3(2 * n_orders + 1), dim3(256), 0, pb.stream, pb.E, pb.N, n_orders,
-                     pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl16 + 32, pb.k, pb.theta,
-                     pb.H, pb.eta, d_psi, d_out);
+                     pb.d_mx, pb.d_my, pb.d_tx, pb.d_ty, pb.d_h, pb.nystrom ? pb.d_gl : pb.d_gl16 + 32,
+                     pb.nystrom ? 1 : 8, pb.k, pb.theta, pb.H, pb.eta, d_psi, d_out);
   return hipGetLastError();
 }
 
