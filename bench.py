@@ -406,6 +406,60 @@ def bandgap_leg(n_freq):
     return out
 
 
+def nystrom_leg(n_ka):
+    """The spectral Nystrom discretisation (Kress; the paper's refs. 2 and 4)
+    beside the chords on the square 8x8 block: at n_ka frequencies of the
+    sweep (theta = 0), GMRES to 1e-12 with p = 32 and leaf 64, the
+    propagating Bragg amplitudes (reflected and transmitted; the period 8a
+    lets up to |q| = 7 of the orders -10..10 propagate at ka = 6) against those
+    of the Nystrom solve at 128 nodes per fibre, which agree with the 64-node
+    ones to the figure reported; time to solution per frequency (its set-up
+    included) and the apply's time per variant."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1910_10863_amd import pfm
+    wl = W.square_8x8()
+    kas = [wl.ka[int(i)] for i in np.linspace(0, len(wl.ka) - 1, n_ka)]
+    variants = [("nystrom", 32), ("nystrom", 64), ("nystrom", 128), ("nystrom", 512), ("chords", 512)]
+    amps, out = {}, {"p": 32, "leaf_max": 64, "tol": 1e-12, "ka": kas, "variants": {}}
+    for kind, n in variants:
+        wl.n_elem = n
+        pr = pfm.Problem.from_workload(wl, p=32, leaf_max=64, tol=1e-12, restart=200, max_iter=4000,
+                                       nystrom=kind == "nystrom")
+        a, its, flux, fails = [], [], [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ka in kas:
+            pr.set_wave(ka, 0.0)
+            x, info = pr.solve()
+            R, T, _, en = pr.fields(x, 10)
+            prop = np.abs(2 * math.pi * np.arange(-10, 11) / (wl.M_H * wl.a)) < ka / wl.a
+            a.append(np.concatenate([R[prop], T[prop], np.zeros(2 * int((~prop).sum()))]))
+            flux.append(abs(en))
+            its.append(info["iters"])
+            fails += info["status"] != 0
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        psi = torch.tensor(W.random_density(pr.n, 5), device="cuda")
+        pr.set_wave(kas[len(kas) // 2], 0.0)
+        ms = time_matvec(pr.matvec, psi, pr.empty(), 50)
+        pr.close()
+        key = f"{kind}_N{n}"
+        amps[key] = np.array(a)
+        out["variants"][key] = {"unknowns": 2 * wl.M * n, "ms_per_solve": 1e3 * t / len(kas),
+                                "mean_iters": float(np.mean(its)), "failed": fails, "apply_ms": ms,
+                                "max_flux_residual": float(np.max(flux))}
+    ref = amps["nystrom_N128"]
+    scale = np.max(np.abs(ref), axis=1)
+    for key, v in out["variants"].items():
+        v["max_amplitude_err_vs_nystrom_N128"] = float(np.max(np.max(np.abs(amps[key] - ref), axis=1) / scale))
+    out["nystrom_N64_vs_N128"] = out["variants"]["nystrom_N64"]["max_amplitude_err_vs_nystrom_N128"]
+    print(f"nystrom leg: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def golden_members(x, kas, th):
     """Sweep solutions x [n_ka][B][n] at the members with stored dense LU
     solutions of the oracle (square 4x4 block, tests/golden/)."""
@@ -484,10 +538,11 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: the workload's)")
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
-    ap.add_argument("--legs", default="sweep,mixed,batched,warm,bandgap",
+    ap.add_argument("--legs", default="sweep,mixed,batched,warm,bandgap,nystrom",
                     help="comma list of the legs besides the timed apply: sweep (square 8x8 ka sweep), "
                          "mixed (hexagon 16x16 mixed precision), batched (square 4x4 band sweep), "
-                         "warm (learned warm start), bandgap (ETC curves of Sec. 4); empty: none")
+                         "warm (learned warm start), bandgap (ETC curves of Sec. 4), nystrom (spectral "
+                         "Nystrom beside the chords on the square 8x8 block); empty: none")
     ap.add_argument("--bandgap-freqs", type=int, default=150)
     ap.add_argument("--no-tune", action="store_true", help="batched leg without the autotuner")
     ap.add_argument("--warm-train-groups", type=int, default=2500,
@@ -681,6 +736,10 @@ def main():
     if "bandgap" in legs and args.bandgap_freqs > 0:
         bandgap = bandgap_leg(args.bandgap_freqs)
 
+    nystrom = None
+    if "nystrom" in legs:
+        nystrom = nystrom_leg(4)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ka_mat, theta, args.cpu_targets)
@@ -711,6 +770,7 @@ def main():
         "batched_sweep": batched,
         "warm_start": warm_leg,
         "bandgap": bandgap,
+        "nystrom": nystrom,
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_near_stored", "n_near_circulant",

@@ -229,20 +229,35 @@ def layer_rows(pb: Problem, targets):
             {f"ext_{names[c]}": ext[c] for c in range(4)})
 
 
+def operator_rows(pb: Problem, targets):
+    """Rows of (I - A) of eq. 9 in the Nystrom discretisation for the nodes
+    `targets`: (R1, R2), each [len(targets), 2E], the row-1 and row-2
+    equations (as system.operator_rows)."""
+    bd = pb.bd
+    targets = np.asarray(targets)
+    inn, ext = layer_rows(pb, targets)
+    R1 = np.zeros((len(targets), pb.n), dtype=np.complex128)
+    R2 = np.zeros_like(R1)
+    c = 2.0 / (1j * pb.eta * (1.0 + pb.varrho))
+    allp, allv = col_phi(bd, np.arange(bd.E)), col_varphi(bd, np.arange(bd.E))
+    R1[:, allp] = ext["ext_D"] - inn["int_D"]
+    R1[:, allv] = -1j * pb.eta * (ext["ext_S"] - inn["int_S"])
+    R2[:, allp] = c * (ext["ext_T"] - pb.varrho * inn["int_T"])
+    R2[:, allv] = c * (-1j * pb.eta) * (ext["ext_K"] - pb.varrho * inn["int_K"])
+    r = np.arange(len(targets))
+    R1[r, col_phi(bd, targets)] += 1.0
+    R2[r, col_varphi(bd, targets)] += 1.0
+    return R1, R2
+
+
 def dense_matrix(pb: Problem) -> np.ndarray:
     """(I - A) of eq. 9 in the Nystrom discretisation (rows as system.operator_rows)."""
     bd = pb.bd
     tg = np.arange(bd.E)
-    inn, ext = layer_rows(pb, tg)
+    R1, R2 = operator_rows(pb, tg)
     A = np.zeros((pb.n, pb.n), dtype=np.complex128)
-    c = 2.0 / (1j * pb.eta * (1.0 + pb.varrho))
-    cp, cv = col_phi(bd, tg), col_varphi(bd, tg)
-    A[np.ix_(cp, cp)] = ext["ext_D"] - inn["int_D"]
-    A[np.ix_(cp, cv)] = -1j * pb.eta * (ext["ext_S"] - inn["int_S"])
-    A[np.ix_(cv, cp)] = c * (ext["ext_T"] - pb.varrho * inn["int_T"])
-    A[np.ix_(cv, cv)] = c * (-1j * pb.eta) * (ext["ext_K"] - pb.varrho * inn["int_K"])
-    A[cp, cp] += 1.0
-    A[cv, cv] += 1.0
+    A[col_phi(bd, tg)] = R1
+    A[col_varphi(bd, tg)] = R2
     return A
 
 

@@ -1009,16 +1009,18 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       }
     }
     if (pb.spec_root) {
-      // P2M: the tree fibres' leaves (rows in tree order, offsets from the
-      // leaf's centre).  Downward pass, grouped by fibre: the tree fibres'
-      // leaves with a far part from below the root (M2L chunks of their own
-      // or of an ancestor other than the root, whose expansion the synthesis
-      // evaluates) or with stored near pairs; each with its ancestors'
-      // (chunks, J-table row) without the root
+      // P2M: the tree fibres' leaves below the root (rows in tree order,
+      // offsets from the leaf's centre; a root's moments come from the
+      // transforms, also when the root is a leaf).  Downward pass, grouped by
+      // fibre: the tree fibres' leaves with a far part from below the root
+      // (M2L chunks of their own or of an ancestor other than the root, whose
+      // expansion the synthesis evaluates) or with stored near pairs; each
+      // with its ancestors' (chunks, J-table row) without the root.  A leaf
+      // that is its fibre's root keeps only its near rows here.
       std::vector<int> mc;
       for (int li = 0; li < nl; ++li) {
         const Cell& L = hp.cells[hp.leaves[li]];
-        if (!tree_fib[L.fiber]) continue;
+        if (!tree_fib[L.fiber] || L.level == 0) continue;
         mc.push_back(hp.leaves[li]); mc.push_back(L.ebeg); mc.push_back(L.eend - L.ebeg);
       }
       pb.n_mcells = (int)(mc.size() / 3);
@@ -1029,7 +1031,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       for (int li = 0; li < nl; ++li) {
         const Cell& L = hp.cells[hp.leaves[li]];
         if (!tree_fib[L.fiber]) continue;
-        const auto own = chunk_rng(0, hp.leaves[li]);
+        const auto own = L.level == 0 ? std::make_pair(0, 0) : chunk_rng(0, hp.leaves[li]);
         const int a0 = (int)(da.size() / 4);
         for (int q = hp.anc_ptr[li]; q < hp.anc_ptr[li + 1]; ++q) {
           const auto ar = chunk_rng(0, hp.anc[q]);

@@ -55,6 +55,31 @@ def test_square_8x8_rows(pfm, ka):
     assert err < 1e-8
 
 
+def test_square_8x8_one_leaf_per_fibre_rows(pfm):
+    """64 chords per fibre with leaf 64: every fibre is one leaf, and the
+    fibres with close neighbours have roots that are leaves with near pairs
+    (their far part must come from the roots' synthesis alone).  Rows of
+    those fibres and of others against the oracle."""
+    from oracle import system as sy
+    wl = W.square_8x8()
+    wl.n_elem = 64
+    ka = 3.338709677419355
+    prob = pfm.Problem.from_workload(wl, p=32, leaf_max=64)
+    prob.set_wave(ka, 0.0)
+    st = prob.stats()
+    assert st["spectral_roots"] == 1 and 0 < st["n_spectral_fibres"] < 64 and st["n_near_pairs"] > 0
+    psi = W.random_density(prob.n, 17)
+    y = prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy()
+    pb = sy.problem_from_workload(wl, ka, 0.0)
+    tg = np.array([25, 33, 52, 53, 2, 60]) * 64 + np.array([3, 40, 10, 60, 5, 33])
+    R1, R2 = sy.operator_rows(pb, tg)
+    r = np.concatenate([R1 @ psi, R2 @ psi])
+    g = np.concatenate([y[sy.col_phi(pb.bd, tg)], y[sy.col_varphi(pb.bd, tg)]])
+    err = np.max(np.abs(g - r)) / np.sqrt(np.mean(np.abs(r) ** 2))
+    _say("square 8x8, one leaf per fibre: max row error / rms", err)
+    assert err < 1e-10
+
+
 def test_hexagon_16x16_rows(pfm):
     wl = W.hexagon_16x16()
     _say("hexagon 16x16 rows")

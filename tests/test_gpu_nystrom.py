@@ -203,3 +203,52 @@ def test_nystrom_rejects_what_it_cannot_do(pfm):
     wl = W.tiny()
     with pytest.raises(pfm.PfmError):
         pfm.Problem.from_workload(wl, nystrom=True, self_fft=False)
+
+
+@pytest.mark.parametrize("n_elem,ka", [(64, 3.338709677419355), (128, 3.338709677419355), (512, 6.0)])
+def test_nystrom_square_8x8_rows(pfm, n_elem, ka):
+    """The square 8x8 block (64 fibres, seeded radii) at node counts the
+    Nystrom benchmark leg uses and at the benchmark's 512, in its launch
+    configuration (p = 32, leaf 64; at 64 nodes every fibre is one leaf):
+    sampled rows of the oracle's Nystrom system applied to a random
+    density, among them rows of the fibres with close neighbours."""
+    from oracle import nystrom as ny
+    from oracle import system as sy
+    wl = W.square_8x8()
+    wl.n_elem = n_elem
+    prob = pfm.Problem.from_workload(wl, p=32, leaf_max=64, nystrom=True)
+    prob.set_wave(ka, 0.0)
+    psi = W.random_density(prob.n, 13)
+    y = prob.matvec(torch.tensor(psi, device="cuda")).cpu().numpy()
+    pb = ny.problem_from_workload(wl, ka, 0.0)
+    rng = np.random.default_rng(13)
+    close = np.array([25, 33, 52, 53]) * n_elem + n_elem // 3     # pairs of fibres 0.33a and 0.34a apart
+    tg = np.unique(np.concatenate([rng.choice(pb.bd.E, 6, replace=False), close]))
+    R1, R2 = ny.operator_rows(pb, tg)
+    r = np.concatenate([R1 @ psi, R2 @ psi])
+    g = np.concatenate([y[sy.col_phi(pb.bd, tg)], y[sy.col_varphi(pb.bd, tg)]])
+    err = np.max(np.abs(g - r)) / np.sqrt(np.mean(np.abs(r) ** 2))
+    _say("nystrom square 8x8 rows:", n_elem, ka, err, prob.stats()["n_spectral_fibres"])
+    assert err < 1e-9
+
+
+def test_nystrom_square_8x8_converges(pfm):
+    """Spectral convergence on the square 8x8 block: the propagating Bragg
+    amplitudes of the device solves at 64 and 128 nodes per fibre agree to
+    1e-9, and the flux balances."""
+    wl = W.square_8x8()
+    ka, H = 3.338709677419355, wl.M_H * wl.a
+    q = np.arange(-10, 11)
+    prop = np.abs(2 * math.pi * q / H) < ka / wl.a          # theta = 0
+    amps = []
+    for n in (64, 128):
+        wl.n_elem = n
+        prob = pfm.Problem.from_workload(wl, p=32, leaf_max=64, nystrom=True, tol=1e-12, restart=200)
+        prob.set_wave(ka, 0.0)
+        x, info = prob.solve()
+        assert info["status"] == 0
+        R, T, etc, en = prob.fields(x, 10)        # period 8: orders up to +-4 propagate
+        amps.append(np.concatenate([R[prop], T[prop]]))
+        _say("  nystrom square 8x8 N =", n, "iters", info["iters"], "energy", en)
+        assert abs(en) < 1e-9
+    assert np.max(np.abs(amps[0] - amps[1])) < 1e-9

@@ -128,6 +128,10 @@ def _matvec_err(pfm, key, p, leaf, seed=5, **kw):
     ("sq3x1", 40, 16, 1e-10),
     ("sq2x2close", 40, 16, 1e-10),
     ("sq4x2close", 40, 16, 1e-10),
+    # one leaf per fibre with close neighbours: the root is a leaf with near
+    # pairs (its far part comes from the roots' synthesis alone)
+    ("sq2x2close", 40, 64, 1e-10),
+    ("sq4x2close", 40, 64, 1e-10),
 ])
 def test_matvec_vs_dense_oracle(pfm, key, p, leaf, tol, form):
     """The three forms of a fibre's own image-0 block and of the fibre roots:
