@@ -460,6 +460,55 @@ def nystrom_leg(n_ka):
     return out
 
 
+def tree_leg():
+    """The two basic-tree shapes of the hexagonal lattice (Sec. 3.1: the
+    square tree and the triangle quadtree of Fig. 5) on the hexagon 16x16
+    block (ka = 2, theta = pi/6) in the tree form (every pair, own fibres
+    included, through the tree): per shape and leaf size the apply's time,
+    plan sizes, and the decay of the apply's error with p against the p = 40
+    apply of the same tree (the measured rate per order is the tau of
+    Table 1, which the paper derives for its own admissibility rule)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1910_10863_amd import pfm
+    wl = W.hexagon_16x16()
+    ka, th = 2.0, math.pi / 6
+    psi = torch.tensor(W.random_density(2 * wl.M * wl.n_elem, 5), device="cuda")
+    out = {"workload": wl.name, "ka": ka, "theta": th, "form": "every pair in the tree", "shapes": {}}
+    for tri in (False, True):
+        name = "triangle" if tri else "square"
+        res = {}
+        for leaf in (64, 32):
+            ref = None
+            errs = {}
+            for p in (40, 8, 12, 16, 20, 24, 32):
+                pr = pfm.Problem.from_workload(wl, p=p, leaf_max=leaf, restart=20, self_fft=False,
+                                               triangle_tree=tri)
+                pr.set_wave(ka, th)
+                y = pr.matvec(psi)
+                if p == 40:
+                    ref = y.clone()
+                else:
+                    errs[p] = float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref))
+                if p == 24:
+                    st = pr.stats()
+                    ms = time_matvec(pr.matvec, psi, pr.empty(), 50)
+                    res[f"leaf{leaf}"] = {"apply_ms_p24": ms, "cells": st["n_cells"], "leaves": st["n_leaves"],
+                                          "m2l_entries": st["n_m2l_ext"] + st["n_m2l_int"],
+                                          "near_pairs": st["n_near_pairs"], "near_entries": st["n_near_entries"]}
+                pr.close()
+            ps = sorted(errs)
+            rate = (errs[ps[-2]] / errs[ps[0]]) ** (1.0 / (ps[-2] - ps[0]))
+            res[f"leaf{leaf}"].update({"err_vs_p40": errs, "rate_per_order_p8_p24": rate})
+        out["shapes"][name] = res
+        print(f"tree leg {name}: {res}", file=sys.stderr, flush=True)
+    out["table1_tau_context"] = {"square_L0": 0.6009, "square_L1": 0.7071, "triangle_L0": 0.6663,
+                                 "triangle_L1": 0.7559}
+    return out
+
+
 def golden_members(x, kas, th):
     """Sweep solutions x [n_ka][B][n] at the members with stored dense LU
     solutions of the oracle (square 4x4 block, tests/golden/)."""
@@ -538,11 +587,12 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: the workload's)")
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=24)
-    ap.add_argument("--legs", default="sweep,mixed,batched,warm,bandgap,nystrom",
+    ap.add_argument("--legs", default="sweep,mixed,batched,warm,bandgap,nystrom,tree",
                     help="comma list of the legs besides the timed apply: sweep (square 8x8 ka sweep), "
                          "mixed (hexagon 16x16 mixed precision), batched (square 4x4 band sweep), "
                          "warm (learned warm start), bandgap (ETC curves of Sec. 4), nystrom (spectral "
-                         "Nystrom beside the chords on the square 8x8 block); empty: none")
+                         "Nystrom beside the chords on the square 8x8 block), tree (square and triangle trees "
+                         "of the hexagonal lattice); empty: none")
     ap.add_argument("--bandgap-freqs", type=int, default=150)
     ap.add_argument("--no-tune", action="store_true", help="batched leg without the autotuner")
     ap.add_argument("--warm-train-groups", type=int, default=2500,
@@ -740,6 +790,10 @@ def main():
     if "nystrom" in legs:
         nystrom = nystrom_leg(4)
 
+    tree = None
+    if "tree" in legs:
+        tree = tree_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, ka_mat, theta, args.cpu_targets)
@@ -771,6 +825,7 @@ def main():
         "warm_start": warm_leg,
         "bandgap": bandgap,
         "nystrom": nystrom,
+        "tree_shapes": tree,
         "cpu_baseline": cpu,
         "plan": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l_ext", "n_m2l_int",
                                     "n_near_pairs", "n_near_entries", "n_near_stored", "n_near_circulant",

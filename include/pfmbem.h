@@ -98,6 +98,17 @@ typedef enum { PFM_CIRCLE = 0, PFM_ROUND_SQUARE = 1 } pfm_shape;
  * 1 (the point rule at the nodes). */
 typedef enum { PFM_CHORDS = 0, PFM_NYSTROM = 1 } pfm_discretisation;
 
+/* Shape of each fibre's basic tree (Sec. 3.1).  PFM_TREE_SQUARE: the root is
+ * the square of side a centred on the fibre, cut into quadrants.
+ * PFM_TREE_TRIANGLE (hexagonal lattice only, Fig. 5): the root is the
+ * fibre's hexagonal lattice cell (inradius a/2), cut into six equilateral
+ * triangles, each cut into four by its edge midpoints; cell centres are the
+ * centroids.  An element belongs to the cell holding its midpoint (node for
+ * PFM_NYSTROM).  The admissibility test is the same radius test on either
+ * tree.  The triangle tree is built on the host (pfm_stats.tree_on_device
+ * is 0). */
+typedef enum { PFM_TREE_SQUARE = 0, PFM_TREE_TRIANGLE = 1 } pfm_tree_shape;
+
 typedef struct {
   int lattice;
   double a;
@@ -200,6 +211,7 @@ typedef struct {
  *             (pfm_stats.tree_on_device tells which ran).  1: the host
  *             construction (the reference the GPU build is tested against).
  *  discretisation  PFM_CHORDS or PFM_NYSTROM (pfm_discretisation).
+ *  tree_shape PFM_TREE_SQUARE or PFM_TREE_TRIANGLE (pfm_tree_shape).
  *  m2l_vector 0: the M2L entries (eq. 13) that share a translation (an offset
  *             between cells, or the lattice sum of a fibre offset, Sec. 3.3)
  *             are applied together as complex matrix products on the matrix
@@ -228,6 +240,7 @@ typedef struct {
   int tree_on_host;
   int m2l_vector;
   int discretisation;      /* pfm_discretisation */
+  int tree_shape;          /* pfm_tree_shape */
 } pfm_options;
 
 #define PFM_MAX_BATCH 16

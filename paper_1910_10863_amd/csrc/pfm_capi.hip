@@ -297,6 +297,10 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     return bail(fail(pb, PFM_EINVAL, "tree_on_host must be 0 or 1"));
   if (opt->m2l_vector != 0 && opt->m2l_vector != 1)
     return bail(fail(pb, PFM_EINVAL, "m2l_vector must be 0 or 1"));
+  if (opt->tree_shape != PFM_TREE_SQUARE && opt->tree_shape != PFM_TREE_TRIANGLE)
+    return bail(fail(pb, PFM_EINVAL, "tree_shape must be PFM_TREE_SQUARE or PFM_TREE_TRIANGLE"));
+  if (opt->tree_shape == PFM_TREE_TRIANGLE && geo->lattice != PFM_HEXAGON)
+    return bail(fail(pb, PFM_EINVAL, "PFM_TREE_TRIANGLE needs the hexagonal lattice"));
   if (opt->discretisation != PFM_CHORDS && opt->discretisation != PFM_NYSTROM)
     return bail(fail(pb, PFM_EINVAL, "discretisation must be PFM_CHORDS or PFM_NYSTROM"));
   if (opt->discretisation == PFM_NYSTROM &&
@@ -412,7 +416,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   CK(hipMemcpy(my.data(), pb.d_my, E * sizeof(double), hipMemcpyDeviceToHost));
   bool planned = false;
   pb.tree_on_device = false;
-  if (!opt->tree_on_host) {
+  if (!opt->tree_on_host && opt->tree_shape == PFM_TREE_SQUARE) {
     std::string why;
     planned = build_device_plan(pb, pb.d_mx, pb.d_my, d_ends, why);
     pb.tree_on_device = planned;

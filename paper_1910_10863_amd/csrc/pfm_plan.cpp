@@ -66,6 +66,8 @@ namespace {
 
 struct TCell {
   double cx, cy, half, rho = 0.0;
+  int shape = 0;               // 0 square, 1 hexagon (triangle-tree root), 2 triangle
+  double vx[3] = {0, 0, 0}, vy[3] = {0, 0, 0};   // a triangle's corners
   int level, fiber;
   int parent = -1;
   std::vector<int> kids;       // tmp ids
@@ -99,7 +101,83 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
   tc.reserve(M * 64);
   std::vector<int> roots(M);
 
-  std::function<void(int)> split = [&](int id) {
+  std::function<void(int)> split;
+  // Triangle quadtree of the hexagonal lattice (Sec. 3.1, Fig. 5): the
+  // root is the fibre's hexagonal lattice cell, cut into six equilateral
+  // triangles (centre and two neighbouring corners); a triangle is cut into
+  // four by its edge midpoints (three corner triangles and the inverted
+  // middle one).  An element goes where its midpoint lies: the sextant of its
+  // angle about the centre, then by barycentric coordinates (corner i when
+  // l_i >= 1/2, else the middle).  A cell's centre is its centroid (the
+  // hexagon's is the fibre centre).
+  auto add_tri = [&](int parent, const double* x, const double* y) {
+    TCell c;
+    c.shape = 2;
+    for (int v = 0; v < 3; ++v) {
+      c.vx[v] = x[v];
+      c.vy[v] = y[v];
+    }
+    c.cx = (x[0] + x[1] + x[2]) / 3.0;
+    c.cy = (y[0] + y[1] + y[2]) / 3.0;
+    c.half = 0.5 * std::hypot(x[1] - x[0], y[1] - y[0]);
+    c.level = tc[parent].level + 1;
+    c.fiber = tc[parent].fiber;
+    c.parent = parent;
+    tc.push_back(c);
+    return (int)tc.size() - 1;
+  };
+  std::function<void(int)> split_triangles = [&](int id) {
+    std::vector<int> kid(6, -1), elems = tc[id].elems;
+    const TCell p = tc[id];
+    for (int e : elems) {
+      const double px = mid[2 * e], py = mid[2 * e + 1];
+      int q;
+      double x[3], y[3];
+      if (p.shape == 1) {
+        // sextant s between the corners at angles 60 s and 60 (s + 1) degrees
+        double ang = std::atan2(py - p.cy, px - p.cx);
+        if (ang < 0) ang += 2.0 * PI;
+        q = std::min(5, (int)std::floor(ang / (PI / 3.0)));
+        const double R = p.half;            // circumradius of the hexagon
+        x[0] = p.cx; y[0] = p.cy;
+        x[1] = p.cx + R * std::cos(q * PI / 3.0); y[1] = p.cy + R * std::sin(q * PI / 3.0);
+        x[2] = p.cx + R * std::cos((q + 1) * PI / 3.0); y[2] = p.cy + R * std::sin((q + 1) * PI / 3.0);
+      } else {
+        const double d1x = p.vx[1] - p.vx[0], d1y = p.vy[1] - p.vy[0];
+        const double d2x = p.vx[2] - p.vx[0], d2y = p.vy[2] - p.vy[0];
+        const double det = d1x * d2y - d1y * d2x;
+        const double ex = px - p.vx[0], ey = py - p.vy[0];
+        const double l1 = (ex * d2y - ey * d2x) / det, l2 = (d1x * ey - d1y * ex) / det;
+        const double l0 = 1.0 - l1 - l2;
+        q = l0 >= 0.5 ? 0 : (l1 >= 0.5 ? 1 : (l2 >= 0.5 ? 2 : 3));
+        double mx_[3], my_[3];      // midpoints of the edges opposite corner i
+        for (int i = 0; i < 3; ++i) {
+          mx_[i] = 0.5 * (p.vx[(i + 1) % 3] + p.vx[(i + 2) % 3]);
+          my_[i] = 0.5 * (p.vy[(i + 1) % 3] + p.vy[(i + 2) % 3]);
+        }
+        if (q < 3) {
+          // corner q with the midpoints of its two edges, in the parent's orientation
+          for (int i = 0; i < 3; ++i) {
+            x[i] = i == q ? p.vx[i] : mx_[3 - q - i];
+            y[i] = i == q ? p.vy[i] : my_[3 - q - i];
+          }
+        } else {
+          for (int i = 0; i < 3; ++i) {
+            x[i] = mx_[i];
+            y[i] = my_[i];
+          }
+        }
+      }
+      if (kid[q] < 0) kid[q] = add_tri(id, x, y);
+      tc[kid[q]].elems.push_back(e);
+    }
+    for (int q = 0; q < 6; ++q)
+      if (kid[q] >= 0) tc[id].kids.push_back(kid[q]);
+    std::vector<int> kids = tc[id].kids;
+    for (int k : kids) split(k);
+  };
+
+  split = [&](int id) {
     // tight radius
     double rho = 0.0;
     for (int e : tc[id].elems) {
@@ -111,6 +189,10 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
     }
     tc[id].rho = rho;
     if ((int)tc[id].elems.size() <= leaf_max || tc[id].level >= 24) return;
+    if (tc[id].shape != 0) {
+      split_triangles(id);
+      return;
+    }
     int kid[4] = {-1, -1, -1, -1};
     std::vector<int> elems = tc[id].elems;
     for (int e : elems) {
@@ -139,6 +221,10 @@ bool build_host_plan(Problem& pb, const std::vector<double>& mid, const std::vec
     r.cx = pb.centres[2 * f];
     r.cy = pb.centres[2 * f + 1];
     r.half = 0.5 * pb.a;
+    if (pb.opt.tree_shape == 1) {
+      r.shape = 1;
+      r.half = pb.a / std::sqrt(3.0);       // corners of the hexagonal cell (inradius a / 2)
+    }
     r.level = 0;
     r.fiber = f;
     for (int e = 0; e < N; ++e) r.elems.push_back(f * N + e);

@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("store_self_blocks", ctypes.c_int), ("p2p_cached_rows", ctypes.c_int),
                 ("direct_lattice_m2l", ctypes.c_int), ("precond", ctypes.c_int),
                 ("self_mode", ctypes.c_int), ("tree_on_host", ctypes.c_int),
-                ("m2l_vector", ctypes.c_int), ("discretisation", ctypes.c_int)]
+                ("m2l_vector", ctypes.c_int), ("discretisation", ctypes.c_int),
+                ("tree_shape", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -81,6 +82,8 @@ class Stats(ctypes.Structure):
 
 CHORDS = 0
 NYSTROM = 1
+TREE_SQUARE = 0
+TREE_TRIANGLE = 1
 FP64 = 0
 MIXED = 1
 
@@ -176,7 +179,7 @@ class Problem:
                  store_self_blocks: bool = False, p2p_cached_rows: bool = False,
                  direct_lattice_m2l: bool = False, precond: bool = False, self_fft: bool = True,
                  tree_on_host: bool = False, spectral_roots: bool = True, m2l_vector: bool = False,
-                 nystrom: bool = False):
+                 nystrom: bool = False, triangle_tree: bool = False):
         import torch
         L = lib()
         self._L = L
@@ -190,7 +193,8 @@ class Problem:
                       1 if store_self_blocks else 0, 1 if p2p_cached_rows else 0,
                       1 if direct_lattice_m2l else 0, 1 if precond else 0,
                       (0 if spectral_roots else 2) if self_fft else 1,
-                      1 if tree_on_host else 0, 1 if m2l_vector else 0, NYSTROM if nystrom else CHORDS)
+                      1 if tree_on_host else 0, 1 if m2l_vector else 0, NYSTROM if nystrom else CHORDS,
+                      TREE_TRIANGLE if triangle_tree else TREE_SQUARE)
         code = L.pfm_create(ctypes.byref(geo), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(self._h))
         if code != 0:
             msg = L.pfm_last_error(self._h).decode() if self._h else "?"
