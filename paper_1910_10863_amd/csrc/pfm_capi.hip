@@ -1114,7 +1114,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
   ws_add(pb, &pb.d_ir_aug, 0, n * sizeof(cd));
   ws_add(pb, &pb.d_cperp, 0, n * sizeof(cd));
   ws_add(pb, &pb.d_gout, 0, n * sizeof(cd));
-  pb.red_blocks = (int)std::min<size_t>(512, (n + 255) / 256);
+  pb.red_blocks = reduction_blocks((long long)n);
   ws_add(pb, &pb.d_npart, 0, ((n + 63) / 64) * sizeof(double));
   ws_add(pb, &pb.d_dcoef, 0, (2 * (size_t)pb.opt.restart + 4) * sizeof(cd));
   // restart + 1 columns: DCGS2 leaves the last reorthogonalisation of a cycle in column restart

@@ -3008,6 +3008,10 @@ constexpr int RED_THREADS = 256;
 constexpr int DOT_PER_LANE = 4;                 // w elements a lane keeps in registers
 constexpr int DOT_CHUNK = 64 * DOT_PER_LANE;      // elements of one block's chunk
 
+// blocks of the dot kernels along a vector of n elements (one chunk each up
+// to 512 blocks)
+int reduction_blocks(long long n) { return (int)std::min<long long>(512, (n + DOT_CHUNK - 1) / DOT_CHUNK); }
+
 constexpr int DOT_VPW = 2;                      // vectors a wave reduces at once
 constexpr int DOT_VPB = DOT_VPW * (RED_THREADS / 64);   // vectors per block
 

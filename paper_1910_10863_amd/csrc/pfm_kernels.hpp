@@ -15,6 +15,7 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free);
 // per-fibre block preconditioner: coefficients from the circulant rows, and
 // out = P^{-1} in (inverse) or P in, for B stacked vectors of 2 M N
 hipError_t launch_precond_setup(Problem& pb);
+int reduction_blocks(long long n);
 hipError_t launch_precond(Problem& pb, const cd* in, cd* out, bool inverse, int B = 1, hipStream_t st = nullptr);
 hipError_t launch_rhs(Problem& pb, double theta, cd* d_b);
 hipError_t launch_fields(Problem& pb, const cd* d_psi, int n_orders, cd* d_out);
