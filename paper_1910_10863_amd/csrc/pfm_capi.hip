@@ -935,20 +935,25 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         if (cnt == 1 && !opt->m2l_vector) groups[{ch, eoff[b]}].push_back(c);
         else vch.push_back(c);
       }
+      // columns stored 16 per item (unused ones repeat the item's first, so
+      // that their source and image stay valid indices)
       std::vector<int> items, cols;
+      int n_cols = 0;
       for (const auto& g : groups)
         for (size_t j0 = 0; j0 < g.second.size(); j0 += 16) {
           const int n = (int)std::min<size_t>(16, g.second.size() - j0);
           items.push_back(g.first.first); items.push_back(g.first.second);
           items.push_back((int)(cols.size() / 4)); items.push_back(n);
-          for (int j = 0; j < n; ++j) {
-            const int c = g.second[j0 + j], b = mchunks[4 * (size_t)c + 2];
+          for (int j = 0; j < 16; ++j) {
+            const int c = g.second[j0 + (j < n ? j : 0)];
+            const int b = mchunks[4 * (size_t)c + 2];
             cols.push_back(esrc[b]); cols.push_back(c); cols.push_back(em[b]); cols.push_back(0);
           }
+          n_cols += n;
         }
       pb.n_vchunks = (int)vch.size();
       pb.n_mfma_items = (int)(items.size() / 4);
-      pb.n_mfma_cols = (int)(cols.size() / 4);
+      pb.n_mfma_cols = n_cols;
       if (vch.empty()) vch.assign(1, 0);
       if (items.empty()) items.assign(4, 0), cols.assign(4, 0);
       CK(upload(pb, &pb.d_vchunks, vch)); CK(upload(pb, &pb.d_mfma_items, items)); CK(upload(pb, &pb.d_mfma_cols, cols));

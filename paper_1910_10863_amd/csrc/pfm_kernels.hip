@@ -1449,84 +1449,97 @@ __global__ void __launch_bounds__(64) k_m2l(const int* __restrict__ chunks, cons
 // translation (channel and table row: one offset between cells, or one
 // lattice sum of a fibre offset) form one complex matrix product, the
 // Toeplitz matrix T[l][n] = t[n - l] of eq. 13 (index n - l) times the panel
-// of their sources' moments (alpha^m applied), [2p+1 x entries].  An item is
-// one table row with up to 16 of its entries (columns): one workgroup of NR
-// wavefronts per (item, batch member), wavefront w computing the orders
-// l = 16 w .. 16 w + 15 for the item's columns as one 16 x 16 tile of
+// of their sources' moments, [2p+1 x entries], each result column then
+// multiplied by its image phase alpha^m.  An item is one table row with up
+// to 16 of its entries (columns, stored 16 per item, the unused ones
+// repeating the first): one workgroup per (item, batch member) with NR =
+// (2p + 15) / 16 wavefronts on the matrix cores, wavefront w computing the
+// orders l = 16 w .. 16 w + 15 for the item's columns as one 16 x 16 tile of
 // v_mfma_f64_16x16x4 steps over the source orders, four real products per
-// complex step (re re, -im im, re im, im re).  Lane layout of the f64
-// 16 x 16 x 4 product: A[i][k] and B[k][j] in lane i + 16 k and j + 16 k,
-// D[4 r + lane / 16][lane % 16] in accumulator r.  Each entry's result goes
-// to its chunk's partial slot, which k_m2l_sum adds per cell in list order.
+// complex step (re re, -im im, re im, im re).  When 2p + 1 = 16 NR + 1 (p =
+// 8, 16, 24, 32, 40) one more wavefront computes the last order l = 2p
+// (t[n] against every column) on the vector ALU meanwhile.  Lane layout of
+// the f64 16 x 16 x 4 product: A[i][k] and B[k][j] in lane i + 16 k and
+// j + 16 k, D[4 r + lane / 16][lane % 16] in accumulator r.  Loads come in
+// two rounds: the item and its columns, then the translation row, every
+// column's moments and the phases.  Each entry's result goes to its chunk's
+// partial slot.
 typedef double mfma_v4d __attribute__((ext_vector_type(4)));
 constexpr int MFMA_COLS = 16;
 template <int P>
-__global__ void __launch_bounds__(64 * ((2 * P + 16) / 16)) k_m2l_mfma(
+constexpr int m2l_mfma_tiles() { return (2 * P + 15) / 16; }
+template <int P>
+constexpr int m2l_mfma_waves() { return m2l_mfma_tiles<P>() + (16 * m2l_mfma_tiles<P>() < 2 * P + 1 ? 1 : 0); }
+template <int P>
+__global__ void __launch_bounds__(64 * m2l_mfma_waves<P>()) k_m2l_mfma(
     const int4* __restrict__ items, const int4* __restrict__ cols, const cd* __restrict__ htab, int n_tab,
     const cd* __restrict__ alpha, int m_min, const cd* __restrict__ mpole, cd* __restrict__ part,
     long long mp_stride, long long part_stride, long long tab_stride, int alpha_stride) {
-  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NTH = 64 * ((2 * P + 16) / 16);
+  constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NR = m2l_mfma_tiles<P>(), NTH = 64 * m2l_mfma_waves<P>();
   constexpr int KS = (NP + 3) / 4, KP = 4 * KS + 1;   // source order steps; padded LDS row of a column
   constexpr int NFILL = MFMA_COLS * 4 * KS, PER = (NFILL + NTH - 1) / NTH;
   __shared__ cd sT[NT];
   __shared__ cd sB[MFMA_COLS * KP];
-  __shared__ int sSrc[MFMA_COLS];
-  __shared__ cd sPh[MFMA_COLS];
+  __shared__ int4 sCol[MFMA_COLS];
+  __shared__ int4 sIt;
   mpole += blockIdx.y * mp_stride;
   part += blockIdx.y * part_stride;
   htab += blockIdx.y * tab_stride;
   alpha += blockIdx.y * alpha_stride;
-  const int4 it = items[blockIdx.x];              // channel, table row, first column, columns
-  const int ch = it.x, ncol = it.w;
-  // two rounds of independent loads: the translation row and the columns'
-  // (source cell, phase), then every column's moments at once
-  const cd* t = htab + ((size_t)ch * n_tab + it.y) * NT;
-  for (int i = threadIdx.x; i < NT; i += NTH) sT[i] = t[i];
-  if (threadIdx.x < MFMA_COLS) {
-    int src = 0;
-    cd ph = mkc(0, 0);
-    if ((int)threadIdx.x < ncol) {
-      const int4 c = cols[it.z + threadIdx.x];      // source cell, partial slot, image
-      src = c.x;
-      ph = alpha[c.z - m_min];
-    }
-    sSrc[threadIdx.x] = src;
-    sPh[threadIdx.x] = ph;
-  }
+  if (threadIdx.x < MFMA_COLS) sCol[threadIdx.x] = cols[(size_t)MFMA_COLS * blockIdx.x + threadIdx.x];
+  if (threadIdx.x == MFMA_COLS) sIt = items[blockIdx.x];    // channel, table row, -, columns
   __syncthreads();
+  const int4 it = sIt;
+  const int ch = it.x, ncol = it.w;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4, l = 16 * w + i;
+  const int4 mycol = sCol[i];
+  const cd ph = alpha[mycol.z - m_min];               // this lane's column phase, used at the store
+  const cd* t = htab + ((size_t)ch * n_tab + it.y) * NT;
+  for (int q = threadIdx.x; q < NT; q += NTH) sT[q] = t[q];
   cd v[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int i = threadIdx.x + u * NTH, j = i / (4 * KS), n = i - j * (4 * KS);
-    v[u] = (i < NFILL && j < ncol && n < NP) ? mpole[((size_t)sSrc[j] * 2 + ch) * NP + n] : mkc(0, 0);
+    const int q = threadIdx.x + u * NTH, j = min(q / (4 * KS), MFMA_COLS - 1), n = q - j * (4 * KS);
+    v[u] = (q < NFILL && j < ncol && n < NP) ? mpole[((size_t)sCol[j].x * 2 + ch) * NP + n] : mkc(0, 0);
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int i = threadIdx.x + u * NTH, j = i / (4 * KS), n = i - j * (4 * KS);
-    if (i < NFILL) sB[j * KP + n] = cmul(sPh[j], v[u]);
+    const int q = threadIdx.x + u * NTH, j = q / (4 * KS), n = q - j * (4 * KS);
+    if (q < NFILL) sB[j * KP + n] = v[u];
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = lane & 15, kq = lane >> 4, l = 16 * w + i;
-  mfma_v4d dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+  if (w < NR) {
+    mfma_v4d dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int n = 4 * ks + kq;
-    const cd a = (l < NP && n < NP) ? sT[n - l + 2 * P] : mkc(0, 0);
-    const cd b = sB[i * KP + n];
-    dre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, dre, 0, 0, 0);
-    dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, dre, 0, 0, 0);
-    dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, dim, 0, 0, 0);
-    dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, dim, 0, 0, 0);
-  }
-  if (i < ncol) {
-    const int slot = cols[it.z + i].y;
-    cd* out = part + (size_t)slot * NP;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lo = 16 * w + 4 * r + kq;
-      if (lo < NP) out[lo] = mkc(dre[r], dim[r]);
+    for (int ks = 0; ks < KS; ++ks) {
+      const int n = 4 * ks + kq;
+      const cd a = (l < NP && n < NP) ? sT[n - l + 2 * P] : mkc(0, 0);
+      const cd b = sB[i * KP + n];
+      dre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, dim, 0, 0, 0);
     }
+    if (i < ncol) {
+      cd* out = part + (size_t)mycol.y * NP;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lo = 16 * w + 4 * r + kq;
+        if (lo < NP) out[lo] = cmul(ph, mkc(dre[r], dim[r]));
+      }
+    }
+  } else {
+    // the last order (l = 2p: t[n] against column i), lanes kq = 0..3
+    // taking n = kq, kq + 4, ..., then added across the column's four lanes
+    cd tail = mkc(0, 0);
+    for (int n = kq; n < NP; n += 4) tail = cfma(sT[n], sB[i * KP + n], tail);
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      tail.x += __shfl_xor(tail.x, o, 64);
+      tail.y += __shfl_xor(tail.y, o, 64);
+    }
+    if (i < ncol && kq == 0) part[(size_t)mycol.y * NP + NP - 1] = cmul(ph, tail);
   }
 }
 
@@ -2671,7 +2684,7 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                          pb.d_e_m, pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min, pb.d_mpole, pb.d_epart, bs.mpole,
                          bs.epart, bs.tab, bs.alpha, pb.d_vchunks);
     if (pb.n_mfma_items > 0)
-      hipLaunchKernelGGL(k_m2l_mfma<P>, dim3(pb.n_mfma_items, B), dim3(64 * ((2 * P + 16) / 16)), 0, s,
+      hipLaunchKernelGGL(k_m2l_mfma<P>, dim3(pb.n_mfma_items, B), dim3(64 * m2l_mfma_waves<P>()), 0, s,
                          reinterpret_cast<const int4*>(pb.d_mfma_items),
                          reinterpret_cast<const int4*>(pb.d_mfma_cols), pb.d_htab, pb.n_tab, pb.d_alpha, hp.m_min,
                          pb.d_mpole, pb.d_epart, bs.mpole, bs.epart, bs.tab, bs.alpha);
