@@ -2240,6 +2240,22 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
   }
 }
 
+// acc += the partial expansions of chunks c0 .. c0 + cnt - 1 (coefficient l
+// of chunk c at part[c NP + l]), added in chunk order with eight chunks'
+// loads in flight at once
+template <int NP>
+__device__ __forceinline__ cd add_chunks(cd acc, const cd* __restrict__ part, int c0, int cnt, int l) {
+  for (int c = 0; c < cnt; c += 8) {
+    cd v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = c + q < cnt ? part[(size_t)(c0 + c + q) * NP + l] : mkc(0, 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (c + q < cnt) acc = cadd(acc, v[q]);
+  }
+  return acc;
+}
+
 // Downward pass and L2P of the tree fibres' leaves with a far part from
 // below their roots (or stored near pairs), exterior channel only, one
 // wavefront per (leaf, member), adding into y after the own-block launch has
@@ -2276,19 +2292,17 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
   cd acc[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) acc[u] = mkc(0, 0);
-  for (int c = 0; c < ownc; ++c)
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
-      if (lane + 64 * u < NP) acc[u] = cadd(acc[u], epart[(size_t)(own0 + c) * NP + lane + 64 * u]);
+  for (int u = 0; u < NU; ++u)
+    if (lane + 64 * u < NP) acc[u] = add_chunks<NP>(acc[u], epart, own0, ownc, lane + 64 * u);
   for (int q = 0; q < na; ++q) {                // wave-uniform trip count
     const int4 an = anc[a0 + q];
     cd sa[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) sa[u] = mkc(0, 0);
-    for (int c = 0; c < an.y; ++c)
 #pragma unroll
-      for (int u = 0; u < NU; ++u)
-        if (lane + 64 * u < NP) sa[u] = cadd(sa[u], epart[(size_t)(an.x + c) * NP + lane + 64 * u]);
+    for (int u = 0; u < NU; ++u)
+      if (lane + 64 * u < NP) sa[u] = add_chunks<NP>(sa[u], epart, an.x, an.y, lane + 64 * u);
     const cd* tj = jtab + (size_t)an.z * NT;
 #pragma unroll
     for (int u = 0; u < NU; ++u)
@@ -2398,7 +2412,14 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ 
   const int2 rr = rrng[f];
   for (int l = lane; l < NP; l += 64) {
     cd sacc = mkc(0, 0);
-    for (int c = w; c < rr.y; c += NW) sacc = cadd(sacc, epart[(size_t)(rr.x + c) * NP + l]);
+    for (int c = w; c < rr.y; c += 8 * NW) {   // eight chunks' loads in flight, added in order
+      cd v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = c + q * NW < rr.y ? epart[(size_t)(rr.x + c + q * NW) * NP + l] : mkc(0, 0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (c + q * NW < rr.y) sacc = cadd(sacc, v[q]);
+    }
     sLw[w][l] = sacc;
   }
   __syncthreads();
