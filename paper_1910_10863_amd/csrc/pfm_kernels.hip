@@ -2163,24 +2163,11 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
   T[3 * NP + i] = dl;
 }
 
-// The root's exterior moments of order n = -p..p from the forward DFTs of
-// the fibre's two densities (H: phihat[N], then varphihat[N]) and the
-// fibre's table row T (A_n, then B_n):  M_n = A_n phihat(n mod N) +
-// B_n varphihat(n mod N).  The same arithmetic wherever the DFTs are taken.
-__device__ __forceinline__ void root_moments(const cd* H, int N, int NP, const cd* __restrict__ T,
-                                             cd* __restrict__ out) {
-  const int P = NP >> 1;
-  for (int i = threadIdx.x; i < NP; i += blockDim.x) {
-    const int j = ((i - P) % N + N) % N;
-    out[i] = cadd(cmul(T[i], H[j]), cmul(T[NP + i], H[N + j]));
-  }
-}
-
 // With the roots by Fourier modes, each fibre's own-block apply is split
 // around the FMM chain so that one inverse transform serves both.  First
 // launch: workgroup f < M (one per fibre and member) takes the forward
-// transforms of the fibre's densities, writes the root's moments
-// (root_moments) and the spectrum of P psi, (I + L(kappa)) psihat(kappa), to
+// transforms of the fibre's densities, writes the root's moments and the
+// spectrum of P psi, (I + L(kappa)) psihat(kappa), to
 // spec; with one wave, the next `ntb` workgroups take the row tasks of the
 // stored near pairs (as k_self_apply) and leave the sums in near_buf; the
 // workgroups after those compute the moments of the tree fibres' leaves
@@ -2228,15 +2215,34 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
   cd* Y = pcs + 2 * N;
   const cd* src = in + mem + (size_t)f * 2 * N;   // phi_f then varphi_f
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  // the mode blocks and the table row do not depend on the transforms: their
+  // loads are issued now and land while the transforms run (N <= 512 =
+  // PC_THREADS: one mode per thread)
+  const int kk = threadIdx.x;
+  cd c0 = mkc(0, 0), c1 = c0, c2 = c0, c3 = c0, ta = c0, tb = c0;
+  if (kk < N) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    c0 = c[0]; c1 = c[1]; c2 = c[2]; c3 = c[3];
+  }
+  const cd* T = rtab + (size_t)f * 4 * NP;
+  if (kk < NP) {
+    ta = T[kk];
+    tb = T[NP + kk];
+  }
   __syncthreads();
   const cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
-  root_moments(H, N, NP, rtab + (size_t)f * 4 * NP, mpole + blockIdx.y * mp_stride + (size_t)f * 2 * NP);
+  // the root's exterior moments of order n = kk - p from the two densities'
+  // transforms and the fibre's table row (A_n, B_n): M_n = A_n phihat(n mod N)
+  // + B_n varphihat(n mod N)
+  if (kk < NP) {
+    const int j = ((kk - P) % N + N) % N;
+    mpole[blockIdx.y * mp_stride + (size_t)f * 2 * NP + kk] = cadd(cmul(ta, H[j]), cmul(tb, H[N + j]));
+  }
   cd* dst = spec + mem + (size_t)f * 2 * N;
-  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
-    const cd* c = coef + ((size_t)f * N + kk) * 4;
+  if (kk < N) {
     const cd u = H[kk], v = H[N + kk];
-    dst[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
-    dst[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+    dst[kk] = cadd(cmul(c0, u), cmul(c1, v));
+    dst[N + kk] = cadd(cmul(c2, u), cmul(c3, v));
   }
 }
 
@@ -2289,14 +2295,18 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
     g = tgeo[rb + lane];
     pi = psi_idx[rb + lane];
   }
+  // the ancestors' descriptors (at most 64) come in with the leaf's own chunks
+  __shared__ int4 sAn[64];
+  if (lane < na) sAn[lane] = anc[a0 + lane];
   cd acc[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) acc[u] = mkc(0, 0);
 #pragma unroll
   for (int u = 0; u < NU; ++u)
     if (lane + 64 * u < NP) acc[u] = add_chunks<NP>(acc[u], epart, own0, ownc, lane + 64 * u);
+  __syncthreads();
   for (int q = 0; q < na; ++q) {                // wave-uniform trip count
-    const int4 an = anc[a0 + q];
+    const int4 an = sAn[q];
     cd sa[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) sa[u] = mkc(0, 0);
@@ -2399,6 +2409,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ 
   constexpr int NP = 2 * P + 1, NW = PC_THREADS / 64;
   extern __shared__ cd pcs[];
   __shared__ cd sLw[NW][NP];
+  __shared__ cd sT23[2][NP];
   const int f = blockIdx.x;
   const size_t mem = (size_t)blockIdx.y * vec_stride;
   epart += blockIdx.y * ep_stride;
@@ -2407,6 +2418,8 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ 
   cd* Y = pcs + 2 * N;
   const cd* src = spec + mem + (size_t)f * 2 * N;
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  // the synthesis rows of the fibre's table, loaded with the spectrum
+  for (int i = threadIdx.x; i < 2 * NP; i += blockDim.x) sT23[i / NP][i % NP] = rtab[(size_t)f * 4 * NP + 2 * NP + i];
   // the root's local expansion: wavefront w adds chunks w, w + NW, ... (lane
   // = order), then the NW partial sums in order
   const int2 rr = rrng[f];
@@ -2425,7 +2438,6 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ 
   __syncthreads();
   if (rr.y > 0) {
     const int P_ = NP >> 1;
-    const cd* T = rtab + (size_t)f * 4 * NP;
     const double nn = (double)N;
     const cd c = mkc(0.0, -2.0 * nn / (eta * (1.0 + varrho)));
     for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
@@ -2434,8 +2446,8 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_inv(const cd* __restrict__ 
         cd Ll = sLw[0][l + P_];
 #pragma unroll
         for (int v = 1; v < NW; ++v) Ll = cadd(Ll, sLw[v][l + P_]);
-        su = cfma(Ll, T[2 * NP + l + P_], su);
-        sd = cfma(Ll, T[3 * NP + l + P_], sd);
+        su = cfma(Ll, sT23[0][l + P_], su);
+        sd = cfma(Ll, sT23[1][l + P_], sd);
       }
       X[kk] = cadd(X[kk], cscale(su, nn));
       X[N + kk] = cadd(X[N + kk], cmul(c, sd));
