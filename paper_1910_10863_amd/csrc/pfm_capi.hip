@@ -1033,6 +1033,7 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         mc.push_back(hp.leaves[li]); mc.push_back(L.ebeg); mc.push_back(L.eend - L.ebeg);
       }
       pb.n_mcells = (int)(mc.size() / 3);
+      ws_add(pb, &pb.d_p2m_tab, (size_t)std::max(1, pb.n_mcells) * (pb.opt.p + 1) * 64 * 2 * sizeof(cd), 0);
       if (mc.empty()) mc.assign(3, 0);
       CK(upload(pb, &pb.d_mcell, mc));
       std::vector<std::vector<int>> by_fib(pb.M);

@@ -2163,17 +2163,110 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
   T[3 * NP + i] = dl;
 }
 
+// P2M weights of the tree fibres' leaves (mcell = [leaf cell, first row,
+// rows]): tab[((c 64 + e) (p + 1) + n) 2 + {0, 1}] = A_n, B_n (n = 0..p) of
+// the leaf's element e about the leaf centre (as k_spec_tables, exterior
+// wavenumber), so that M_n(leaf) = sum_e A_n phi_e + B_n varphi_e.  The
+// negative orders follow from Jm_{-j} = (-1)^j conj(Jm_j) with the real
+// weight of B and the conjugate pair of weights in A: A_{-n} = (-1)^{n+1}
+// conj(A_n), B_{-n} = (-1)^n conj(B_n).  One thread per (element, order)
+// pair of a leaf.
+template <int P>
+__global__ void __launch_bounds__(256) k_p2m_tables(const int* __restrict__ mcell, const double4* __restrict__ tgeo,
+                                                    const double* __restrict__ trh, const double* __restrict__ gl,
+                                                    int G, double kap, double eta, cd* __restrict__ tab) {
+  constexpr int NH = P + 1, K = P + 1;
+  const int c = blockIdx.x, rb = mcell[3 * c + 1], rows = mcell[3 * c + 2];
+  for (int q = threadIdx.x; q < NH * 64; q += blockDim.x) {
+    const int e = q / NH, n = q - e * NH;
+    cd A = mkc(0, 0), Bn = mkc(0, 0);
+    if (e < rows) {
+      const double4 g4 = tgeo[rb + e];
+      const double rx = g4.x, ry = g4.y, ex = g4.z, ey = g4.w, hh = trh[rb + e];
+      cd jp[K + 1];
+      for (int g = 0; g < G; ++g) {
+        const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
+        jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
+        const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
+                 jmp = cconj(jp_signed<K>(jp, n + 1));
+        A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
+        A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
+        Bn = cadd(Bn, cscale(jm0, eta * w));
+      }
+    }
+    cd* t = tab + (((size_t)c * 64 + e) * NH + n) * 2;
+    t[0] = A;
+    t[1] = Bn;
+  }
+}
+
+// A tree fibre's leaf moments from its P2M weights (k_p2m_tables): lane m
+// of every wavefront takes the orders m and -m (m <= p), wavefront w the
+// elements 8 w .. 8 w + 7, and the eight wavefronts' sums meet in LDS in a
+// fixed order.  The weights' loads go out before the densities' (which wait
+// for the rows' indices).
+template <int P>
+__device__ __forceinline__ void p2m_table_cell(int cell, int rb, int rows, const cd* __restrict__ tab,
+                                               const int* __restrict__ psi_idx, int N, const cd* __restrict__ psi,
+                                               cd* __restrict__ mpole) {
+  constexpr int NH = P + 1, NW = PC_THREADS / 64, EPW = 64 / NW;
+  static_assert(NH <= 64, "one order per lane");
+  __shared__ cd sPh[64], sVp[64], sPos[NW][NH], sNeg[NW][NH];
+  const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
+  cd a[EPW], b[EPW];
+#pragma unroll
+  for (int q = 0; q < EPW; ++q) {
+    const int e = w * EPW + q;
+    const cd* t = tab + ((size_t)e * NH + m) * 2;
+    a[q] = m < NH && e < rows ? t[0] : mkc(0, 0);
+    b[q] = m < NH && e < rows ? t[1] : mkc(0, 0);
+  }
+  if (w == 0) {
+    cd ph = mkc(0, 0), vp = mkc(0, 0);
+    if (m < rows) {
+      const int pi = psi_idx[rb + m];
+      ph = psi[pi];
+      vp = psi[pi + N];
+    }
+    sPh[m] = ph;
+    sVp[m] = vp;
+  }
+  __syncthreads();
+  cd pos = mkc(0, 0), neg = mkc(0, 0);     // M_m and (-1)^m M_{-m} over this wavefront's elements
+#pragma unroll
+  for (int q = 0; q < EPW; ++q) {
+    const cd ph = sPh[w * EPW + q], vp = sVp[w * EPW + q];
+    pos = cadd(pos, cadd(cmul(a[q], ph), cmul(b[q], vp)));
+    neg = cadd(neg, csub(cmul(cconj(b[q]), vp), cmul(cconj(a[q]), ph)));
+  }
+  if (m < NH) {
+    sPos[w][m] = pos;
+    sNeg[w][m] = neg;
+  }
+  __syncthreads();
+  if (w == 0 && m < NH) {
+    cd tp = sPos[0][m], tn = sNeg[0][m];
+#pragma unroll
+    for (int v = 1; v < NW; ++v) {
+      tp = cadd(tp, sPos[v][m]);
+      tn = cadd(tn, sNeg[v][m]);
+    }
+    cd* out = mpole + (size_t)cell * 2 * (2 * P + 1) + P;
+    out[m] = tp;
+    if (m > 0) out[-m] = (m & 1) ? cscale(tn, -1.0) : tn;
+  }
+}
+
 // With the roots by Fourier modes, each fibre's own-block apply is split
 // around the FMM chain so that one inverse transform serves both.  First
-// launch: workgroup f < M (one per fibre and member) takes the forward
-// transforms of the fibre's densities, writes the root's moments and the
-// spectrum of P psi, (I + L(kappa)) psihat(kappa), to
-// spec; with one wave, the next `ntb` workgroups take the row tasks of the
-// stored near pairs (as k_self_apply) and leave the sums in near_buf; the
-// workgroups after those compute the moments of the tree fibres' leaves
-// (P2M, four groups of two wavefronts per leaf: mcell = [leaf cell, first
+// launch: the first workgroups compute the moments of the tree fibres'
+// leaves from their P2M weights (p2m_table_cell; mcell = [leaf cell, first
 // row, rows] of the row-ordered geometry), which thus run beside the
-// transforms.
+// transforms; the next M (one per fibre and member) take the forward
+// transforms of the fibre's densities and write the root's moments and the
+// spectrum of P psi, (I + L(kappa)) psihat(kappa), to spec; with one wave,
+// the last `ntb` workgroups take the row tasks of the stored near pairs (as
+// k_self_apply) and leave the sums in near_buf.
 template <int P, typename C>
 __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ in, cd* __restrict__ spec,
                                                          long long vec_stride, const cd* __restrict__ coef,
@@ -2184,22 +2277,22 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
                                                          const C* __restrict__ blocks, cd* __restrict__ near_buf,
                                                          const cd* __restrict__ rtab, cd* __restrict__ mpole,
                                                          long long mp_stride, const int* __restrict__ mcell,
-                                                         const double4* __restrict__ tgeo,
-                                                         const double* __restrict__ trh,
                                                          const int* __restrict__ psi_idx,
-                                                         const double* __restrict__ gl, int G, double k,
-                                                         double eta) {
-  static_assert(PC_THREADS == 128 * 4, "leaf workgroups run P2M with four groups");
+                                                         const cd* __restrict__ p2m_tab) {
   constexpr int NP = 2 * P + 1;
   extern __shared__ cd pcs[];
-  if ((int)blockIdx.x >= M + ntb) {
-    const int* mc = mcell + 3 * ((int)blockIdx.x - M - ntb);
-    p2m_cell<P, 4>(mc[0], mc[1], mc[2], 0, blockIdx.y, tgeo, trh, psi_idx, gl, G, N, k, k, eta, in, mpole,
-                   vec_stride, mp_stride);
+  // workgroups: the leaves' P2M first (the longest), then the fibres, then
+  // the row tasks
+  const int nmc = (int)gridDim.x - M - ntb;
+  if ((int)blockIdx.x < nmc) {
+    const int c = blockIdx.x;
+    const int* mc = mcell + 3 * c;
+    p2m_table_cell<P>(mc[0], mc[1], mc[2], p2m_tab + (size_t)c * (P + 1) * 64 * 2, psi_idx, N,
+                      in + (size_t)blockIdx.y * vec_stride, mpole + blockIdx.y * mp_stride);
     return;
   }
-  if ((int)blockIdx.x >= M) {
-    const int t = ((int)blockIdx.x - M) * (PC_THREADS / 64) + (threadIdx.x >> 6);
+  if ((int)blockIdx.x >= nmc + M) {
+    const int t = ((int)blockIdx.x - nmc - M) * (PC_THREADS / 64) + (threadIdx.x >> 6);
     if (t >= ntasks) return;
     cd a1, a2;
     p2p_row_sums<C>(tasks[t], toff[t], col_psi, blocks, in, N, threadIdx.x & 63, a1, a2);
@@ -2209,7 +2302,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
     }
     return;
   }
-  const int f = blockIdx.x;
+  const int f = (int)blockIdx.x - nmc;
   const size_t mem = (size_t)blockIdx.y * vec_stride;
   cd* X = pcs;
   cd* Y = pcs + 2 * N;
@@ -2646,6 +2739,10 @@ static hipError_t tables_impl(Problem& pb) {
   if (pb.spec_root)
     hipLaunchKernelGGL(k_spec_tables<P>, dim3(pb.M), dim3(128), 0, pb.stream, pb.N, pb.d_centres, pb.d_mx, pb.d_my,
                        pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_spec_tab);
+  if (pb.spec_root && pb.n_mcells > 0)
+    hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells), dim3(256), 0, pb.stream, pb.d_mcell,
+                       reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_gl, pb.opt.g_far, pb.k, pb.eta,
+                       pb.d_p2m_tab);
   return hipGetLastError();
 }
 
@@ -2866,9 +2963,8 @@ static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, 
     hipLaunchKernelGGL((k_self_fwd<P, C>), dim3(pb.M + ntb + pb.n_mcells, nb), dim3(PC_THREADS), lds, pb.stream,
                        d_psi, pb.d_spec_hat, bs.vec, pb.d_pc_fwd, pb.d_pc_tw, pb.N, pb.pc_logN, pb.M,
                        reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, ntask, ntb, pb.d_col_psi,
-                       blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole, pb.d_mcell,
-                       reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_psi_idx, pb.d_gl, pb.opt.g_far,
-                       pb.k, pb.eta);
+                       blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole, pb.d_mcell, pb.d_psi_idx,
+                       pb.d_p2m_tab);
   }
   if (ev) (void)hipEventRecord(ev[1], pb.stream);
   for (int r = 0; r < times(1); ++r) fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, nullptr, false, 1, 1);
