@@ -1513,7 +1513,7 @@ pfm_status gmres_lockstep(Problem& pb, int B, Apply&& apply, const cd* b, cd* x,
   const int m = pb.opt.restart;
   const long long hs = 2 * m + 8;           // d_hcol stride per member
   const long long hs2 = 2 * m + 4;          // column stride per member in d_hall
-  const int LOOK = 2;                        // iterations per read-back group
+  const int LOOK = 4;                        // iterations per read-back group
   cd* V = pb.d_V;
   cd* W = pb.d_w;
   cd* R = pb.d_r;

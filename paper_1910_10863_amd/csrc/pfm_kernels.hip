@@ -3154,7 +3154,7 @@ constexpr int DOT_CHUNK = 64 * DOT_PER_LANE;      // elements of one block's chu
 // to 512 blocks)
 int reduction_blocks(long long n) { return (int)std::min<long long>(512, (n + DOT_CHUNK - 1) / DOT_CHUNK); }
 
-constexpr int DOT_VPW = 2;                      // vectors a wave reduces at once
+constexpr int DOT_VPW = 1;                      // vectors a wave reduces at once
 constexpr int DOT_VPB = DOT_VPW * (RED_THREADS / 64);   // vectors per block
 
 // partial[(z * cnt + i) * gridDim.x + blockIdx.x] = sum over the chunks of
