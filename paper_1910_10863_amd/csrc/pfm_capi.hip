@@ -171,7 +171,6 @@ void free_all(Problem& pb) {
   dfree(pb.d_spec_rng); dfree(pb.d_dptr); dfree(pb.d_danc);
   dfree(pb.d_vchunks); dfree(pb.d_mfma_items); dfree(pb.d_mfma_cols);
   dfree(pb.d_mcell); dfree(pb.d_dldesc);
-  dfree(pb.d_tup_cells); dfree(pb.d_tup_ptr); dfree(pb.d_tup_src); dfree(pb.d_tup_off);
   dfree(pb.d_alpha_one); dfree(pb.d_gin); dfree(pb.d_gout); dfree(pb.d_p2ppart);
   if (pb.graph) (void)hipGraphExecDestroy(pb.graph);
   pb.graph = nullptr;
@@ -1026,15 +1025,23 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
       // expansion the synthesis evaluates) or with stored near pairs; each
       // with its ancestors' (chunks, J-table row) without the root.  A leaf
       // that is its fibre's root keeps only its near rows here.
+      // Every cell of a tree fibre below its root gets its moments directly
+      // from per-frequency P2M weights of its elements (cells between the
+      // leaves and the root first: they have the most elements), so that no
+      // M2M runs: [cell, first row, rows, first table row]
       std::vector<int> mc;
-      for (int li = 0; li < nl; ++li) {
-        const Cell& L = hp.cells[hp.leaves[li]];
-        if (!tree_fib[L.fiber] || L.level == 0) continue;
-        mc.push_back(hp.leaves[li]); mc.push_back(L.ebeg); mc.push_back(L.eend - L.ebeg);
-      }
-      pb.n_mcells = (int)(mc.size() / 3);
-      ws_add(pb, &pb.d_p2m_tab, (size_t)std::max(1, pb.n_mcells) * (pb.opt.p + 1) * 64 * 2 * sizeof(cd), 0);
-      if (mc.empty()) mc.assign(3, 0);
+      int trows = 0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int c = 0; c < nc; ++c) {
+          const Cell& C = hp.cells[c];
+          if (!tree_fib[C.fiber] || C.level == 0 || (pass == 0) == (C.leaf != 0)) continue;
+          const int rows = C.eend - C.ebeg;     // <= N <= 512 (the own blocks by FFT)
+          mc.push_back(c); mc.push_back(C.ebeg); mc.push_back(rows); mc.push_back(trows);
+          trows += rows;
+        }
+      pb.n_mcells = (int)(mc.size() / 4);
+      ws_add(pb, &pb.d_p2m_tab, (size_t)std::max(1, trows) * (pb.opt.p + 1) * 2 * sizeof(cd), 0);
+      if (mc.empty()) mc.assign(4, 0);
       CK(upload(pb, &pb.d_mcell, mc));
       std::vector<std::vector<int>> by_fib(pb.M);
       std::vector<int> da;
@@ -1081,26 +1088,6 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
     CK(upload(pb, &pb.d_up_cells, hp.up_cells)); CK(upload(pb, &pb.d_up_ptr, hp.up_ptr));
     CK(upload(pb, &pb.d_up_src, hp.up_src)); CK(upload(pb, &pb.d_up_off, hp.up_off));
     pb.n_up = (int)hp.up_cells.size();
-    if (pb.spec_root) {
-      // M2M only into the tree fibres' cells below their roots (the roots'
-      // moments come from the DFTs)
-      std::vector<int> uc, up(1, 0), us, uo;
-      for (size_t i = 0; i < hp.up_cells.size(); ++i) {
-        const Cell& C = hp.cells[hp.up_cells[i]];
-        if (C.level == 0 || !tree_fib[C.fiber]) continue;
-        uc.push_back(hp.up_cells[i]);
-        for (int q = hp.up_ptr[i]; q < hp.up_ptr[i + 1]; ++q) {
-          us.push_back(hp.up_src[q]);
-          uo.push_back(hp.up_off[q]);
-        }
-        up.push_back((int)us.size());
-      }
-      pb.n_tup = (int)uc.size();
-      if (uc.empty()) uc.assign(1, 0), up.assign(2, 0);
-      if (us.empty()) us.assign(1, 0), uo.assign(1, 0);
-      CK(upload(pb, &pb.d_tup_cells, uc)); CK(upload(pb, &pb.d_tup_ptr, up));
-      CK(upload(pb, &pb.d_tup_src, us)); CK(upload(pb, &pb.d_tup_off, uo));
-    }
     ws_add(pb, &pb.d_far, 0, 2 * (size_t)E * sizeof(cd));
   }
   {

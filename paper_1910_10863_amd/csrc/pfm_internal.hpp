@@ -195,8 +195,6 @@ struct Problem {
   int n_mcells = 0;                     // the tree fibres' leaves (P2M)
   int *d_mcell = nullptr;               // [n_mcells]
   cd* d_p2m_tab = nullptr;              // [n_mcells][p+1][64][2] the leaves' P2M weights, per frequency[3]: leaf cell, first row (tree order), rows
-  int n_tup = 0;                        // the tree fibres' cells below their roots with leaves under them (M2M)
-  int *d_tup_cells = nullptr, *d_tup_ptr = nullptr, *d_tup_src = nullptr, *d_tup_off = nullptr;
   int n_dleaves = 0;                    // tree fibres' leaves with a far part from below the root or near rows
   int *d_dptr = nullptr;                // [M + 1]: those leaves of fibre f are dptr[f] .. dptr[f + 1]
   int *d_dldesc = nullptr;              // [leaf][8]: first row, rows, own M2L chunks (first, count),

@@ -2163,81 +2163,93 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
   T[3 * NP + i] = dl;
 }
 
-// P2M weights of the tree fibres' leaves (mcell = [leaf cell, first row,
-// rows]): tab[((c 64 + e) (p + 1) + n) 2 + {0, 1}] = A_n, B_n (n = 0..p) of
-// the leaf's element e about the leaf centre (as k_spec_tables, exterior
-// wavenumber), so that M_n(leaf) = sum_e A_n phi_e + B_n varphi_e.  The
-// negative orders follow from Jm_{-j} = (-1)^j conj(Jm_j) with the real
-// weight of B and the conjugate pair of weights in A: A_{-n} = (-1)^{n+1}
-// conj(A_n), B_{-n} = (-1)^n conj(B_n).  One thread per (element, order)
-// pair of a leaf.
+// P2M weights of the tree fibres' cells below their roots (mcell = [cell,
+// first row, rows, first table row]: the leaves and the cells between them
+// and the root): tab[((toff + e) (p + 1) + n) 2 + {0, 1}] = A_n, B_n (n =
+// 0..p) of the cell's element e (tree order) about the cell centre (as
+// k_spec_tables, exterior wavenumber), so that M_n(cell) = sum_e A_n phi_e
+// + B_n varphi_e.  The negative orders follow from Jm_{-j} = (-1)^j
+// conj(Jm_j) with the real weight of B and the conjugate pair of weights in
+// A: A_{-n} = (-1)^{n+1} conj(A_n), B_{-n} = (-1)^n conj(B_n).  One thread
+// per (element, order) pair of a cell.
 template <int P>
-__global__ void __launch_bounds__(256) k_p2m_tables(const int* __restrict__ mcell, const double4* __restrict__ tgeo,
-                                                    const double* __restrict__ trh, const double* __restrict__ gl,
+__global__ void __launch_bounds__(256) k_p2m_tables(const int4* __restrict__ mcell, const int* __restrict__ elem_of,
+                                                    const double* __restrict__ cx, const double* __restrict__ cy,
+                                                    const double* __restrict__ mx, const double* __restrict__ my,
+                                                    const double* __restrict__ tx, const double* __restrict__ ty,
+                                                    const double* __restrict__ h, const double* __restrict__ gl,
                                                     int G, double kap, double eta, cd* __restrict__ tab) {
   constexpr int NH = P + 1, K = P + 1;
-  const int c = blockIdx.x, rb = mcell[3 * c + 1], rows = mcell[3 * c + 2];
-  for (int q = threadIdx.x; q < NH * 64; q += blockDim.x) {
+  const int4 mc = mcell[blockIdx.x];
+  const int cell = mc.x, rb = mc.y, rows = mc.z, toff = mc.w;
+  const double ox = cx[cell], oy = cy[cell];
+  for (int q = threadIdx.x; q < NH * rows; q += blockDim.x) {
     const int e = q / NH, n = q - e * NH;
+    const int en = elem_of[rb + e];
+    const double rx = mx[en] - ox, ry = my[en] - oy, ex = tx[en], ey = ty[en], hh = h[en];
     cd A = mkc(0, 0), Bn = mkc(0, 0);
-    if (e < rows) {
-      const double4 g4 = tgeo[rb + e];
-      const double rx = g4.x, ry = g4.y, ex = g4.z, ey = g4.w, hh = trh[rb + e];
-      cd jp[K + 1];
-      for (int g = 0; g < G; ++g) {
-        const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
-        jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
-        const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
-                 jmp = cconj(jp_signed<K>(jp, n + 1));
-        A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
-        A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
-        Bn = cadd(Bn, cscale(jm0, eta * w));
-      }
+    cd jp[K + 1];
+    for (int g = 0; g < G; ++g) {
+      const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
+      jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
+      const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
+               jmp = cconj(jp_signed<K>(jp, n + 1));
+      A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
+      A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
+      Bn = cadd(Bn, cscale(jm0, eta * w));
     }
-    cd* t = tab + (((size_t)c * 64 + e) * NH + n) * 2;
+    cd* t = tab + (((size_t)toff + e) * NH + n) * 2;
     t[0] = A;
     t[1] = Bn;
   }
 }
 
-// A tree fibre's leaf moments from its P2M weights (k_p2m_tables): lane m
-// of every wavefront takes the orders m and -m (m <= p), wavefront w the
-// elements 8 w .. 8 w + 7, and the eight wavefronts' sums meet in LDS in a
-// fixed order.  The weights' loads go out before the densities' (which wait
-// for the rows' indices).
+// A tree fibre's cell moments from its P2M weights (k_p2m_tables): lane m of
+// every wavefront takes the orders m and -m (m <= p), wavefront w a
+// contiguous eighth of the cell's elements (eight at a time, the next
+// eight's weights loaded while the current ones are used), and the eight
+// wavefronts' sums meet in LDS in a fixed order.  The first weights' loads
+// go out before the densities' (which wait for the rows' indices).
+// The densities are staged in stage[0 .. 2 rows) (the launch's dynamic LDS:
+// a cell has at most N elements, the launch holds 4N).
 template <int P>
 __device__ __forceinline__ void p2m_table_cell(int cell, int rb, int rows, const cd* __restrict__ tab,
                                                const int* __restrict__ psi_idx, int N, const cd* __restrict__ psi,
-                                               cd* __restrict__ mpole) {
-  constexpr int NH = P + 1, NW = PC_THREADS / 64, EPW = 64 / NW;
+                                               cd* __restrict__ mpole, cd* stage) {
+  constexpr int NH = P + 1, NW = PC_THREADS / 64;
   static_assert(NH <= 64, "one order per lane");
-  __shared__ cd sPh[64], sVp[64], sPos[NW][NH], sNeg[NW][NH];
+  __shared__ cd sPos[NW][NH], sNeg[NW][NH];
+  cd* sPh = stage;
+  cd* sVp = stage + rows;
   const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
-  cd a[EPW], b[EPW];
+  const int per = (rows + NW - 1) / NW, e0 = min(rows, w * per), e1 = min(rows, e0 + per);
+  cd a[8], b[8];
+  auto load = [&](int e) {
 #pragma unroll
-  for (int q = 0; q < EPW; ++q) {
-    const int e = w * EPW + q;
-    const cd* t = tab + ((size_t)e * NH + m) * 2;
-    a[q] = m < NH && e < rows ? t[0] : mkc(0, 0);
-    b[q] = m < NH && e < rows ? t[1] : mkc(0, 0);
-  }
-  if (w == 0) {
-    cd ph = mkc(0, 0), vp = mkc(0, 0);
-    if (m < rows) {
-      const int pi = psi_idx[rb + m];
-      ph = psi[pi];
-      vp = psi[pi + N];
+    for (int q = 0; q < 8; ++q) {
+      const bool ok = m < NH && e + q < e1;
+      const cd* t = tab + ((size_t)(e + q) * NH + m) * 2;
+      a[q] = ok ? t[0] : mkc(0, 0);
+      b[q] = ok ? t[1] : mkc(0, 0);
     }
-    sPh[m] = ph;
-    sVp[m] = vp;
+  };
+  load(e0);
+  for (int t = threadIdx.x; t < rows; t += PC_THREADS) {
+    const int pi = psi_idx[rb + t];
+    sPh[t] = psi[pi];
+    sVp[t] = psi[pi + N];
   }
   __syncthreads();
   cd pos = mkc(0, 0), neg = mkc(0, 0);     // M_m and (-1)^m M_{-m} over this wavefront's elements
+  for (int e = e0; e < e1; e += 8) {
 #pragma unroll
-  for (int q = 0; q < EPW; ++q) {
-    const cd ph = sPh[w * EPW + q], vp = sVp[w * EPW + q];
-    pos = cadd(pos, cadd(cmul(a[q], ph), cmul(b[q], vp)));
-    neg = cadd(neg, csub(cmul(cconj(b[q]), vp), cmul(cconj(a[q]), ph)));
+    for (int q = 0; q < 8; ++q)
+      if (e + q < e1) {
+        const cd ph = sPh[e + q], vp = sVp[e + q];
+        pos = cadd(pos, cadd(cmul(a[q], ph), cmul(b[q], vp)));
+        neg = cadd(neg, csub(cmul(cconj(b[q]), vp), cmul(cconj(a[q]), ph)));
+      }
+    if (e + 8 < e1) load(e + 8);
   }
   if (m < NH) {
     sPos[w][m] = pos;
@@ -2260,9 +2272,9 @@ __device__ __forceinline__ void p2m_table_cell(int cell, int rb, int rows, const
 // With the roots by Fourier modes, each fibre's own-block apply is split
 // around the FMM chain so that one inverse transform serves both.  First
 // launch: the first workgroups compute the moments of the tree fibres'
-// leaves from their P2M weights (p2m_table_cell; mcell = [leaf cell, first
-// row, rows] of the row-ordered geometry), which thus run beside the
-// transforms; the next M (one per fibre and member) take the forward
+// cells below their roots from their P2M weights (p2m_table_cell; mcell =
+// [cell, first row, rows, first table row] in the tree order), which thus
+// run beside the transforms; the next M (one per fibre and member) take the forward
 // transforms of the fibre's densities and write the root's moments and the
 // spectrum of P psi, (I + L(kappa)) psihat(kappa), to spec; with one wave,
 // the last `ntb` workgroups take the row tasks of the stored near pairs (as
@@ -2276,19 +2288,18 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
                                                          const int* __restrict__ col_psi,
                                                          const C* __restrict__ blocks, cd* __restrict__ near_buf,
                                                          const cd* __restrict__ rtab, cd* __restrict__ mpole,
-                                                         long long mp_stride, const int* __restrict__ mcell,
+                                                         long long mp_stride, const int4* __restrict__ mcell,
                                                          const int* __restrict__ psi_idx,
                                                          const cd* __restrict__ p2m_tab) {
   constexpr int NP = 2 * P + 1;
   extern __shared__ cd pcs[];
-  // workgroups: the leaves' P2M first (the longest), then the fibres, then
-  // the row tasks
+  // workgroups: the tree fibres' cells' P2M first (the longest), then the
+  // fibres, then the row tasks
   const int nmc = (int)gridDim.x - M - ntb;
   if ((int)blockIdx.x < nmc) {
-    const int c = blockIdx.x;
-    const int* mc = mcell + 3 * c;
-    p2m_table_cell<P>(mc[0], mc[1], mc[2], p2m_tab + (size_t)c * (P + 1) * 64 * 2, psi_idx, N,
-                      in + (size_t)blockIdx.y * vec_stride, mpole + blockIdx.y * mp_stride);
+    const int4 mc = mcell[blockIdx.x];
+    p2m_table_cell<P>(mc.x, mc.y, mc.z, p2m_tab + (size_t)mc.w * (P + 1) * 2, psi_idx, N,
+                      in + (size_t)blockIdx.y * vec_stride, mpole + blockIdx.y * mp_stride, pcs);
     return;
   }
   if ((int)blockIdx.x >= nmc + M) {
@@ -2740,9 +2751,9 @@ static hipError_t tables_impl(Problem& pb) {
     hipLaunchKernelGGL(k_spec_tables<P>, dim3(pb.M), dim3(128), 0, pb.stream, pb.N, pb.d_centres, pb.d_mx, pb.d_my,
                        pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_spec_tab);
   if (pb.spec_root && pb.n_mcells > 0)
-    hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells), dim3(256), 0, pb.stream, pb.d_mcell,
-                       reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_trh, pb.d_gl, pb.opt.g_far, pb.k, pb.eta,
-                       pb.d_p2m_tab);
+    hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells), dim3(256), 0, pb.stream,
+                       reinterpret_cast<const int4*>(pb.d_mcell), pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my,
+                       pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_p2m_tab);
   return hipGetLastError();
 }
 
@@ -2766,10 +2777,10 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
                       int reps = 1) {
   auto times = [&](int stage) { return only < 0 ? 1 : (only == stage ? reps : 0); };
   const HostPlan& hp = pb.hp;
-  // fibre roots by their Fourier modes: the roots' and leaves' moments come
-  // from the first own-block launch (no P2M here), M2M only into the tree
-  // fibres' cells below their roots, no M2L sums and no downward pass here
-  // (the last own-block launch adds the partials and runs it)
+  // fibre roots by their Fourier modes: every cell's moments come from the
+  // first own-block launch (no P2M or M2M here), no M2L sums and no
+  // downward pass here (the last own-block launch adds the partials and runs
+  // it)
   const bool spec = pb.spec_root && !upward_only;
   int n_leaves = spec ? 0 : (int)hp.leaves.size();
   const int* leaves = pb.d_leaves;
@@ -2777,11 +2788,11 @@ static void fmm_chain(Problem& pb, const cd* d_psi, hipStream_t s, hipEvent_t* e
   const int n_down = spec ? 0 : n_leaves;       // spectral: the downward pass runs in k_self_inv
   const int* ddesc = pb.d_ldesc;
   const int* near_t0 = pb.d_leaf_near_t0;
-  const int n_up = spec ? pb.n_tup : pb.n_up;
-  const int* up_cells = spec ? pb.d_tup_cells : pb.d_up_cells;
-  const int* up_ptr = spec ? pb.d_tup_ptr : pb.d_up_ptr;
-  const int* up_src = spec ? pb.d_tup_src : pb.d_up_src;
-  const int* up_off = spec ? pb.d_tup_off : pb.d_up_off;
+  const int n_up = spec ? 0 : pb.n_up;           // spectral: every moment comes from the first launch
+  const int* up_cells = pb.d_up_cells;
+  const int* up_ptr = pb.d_up_ptr;
+  const int* up_src = pb.d_up_src;
+  const int* up_off = pb.d_up_off;
   int n_joff = (int)hp.joff_xy.size() / 2;
   const BatchStrides bs = batch_strides(pb);
   const int nch = pb.self_fft && !upward_only ? 1 : 2;
@@ -2963,7 +2974,8 @@ static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, 
     hipLaunchKernelGGL((k_self_fwd<P, C>), dim3(pb.M + ntb + pb.n_mcells, nb), dim3(PC_THREADS), lds, pb.stream,
                        d_psi, pb.d_spec_hat, bs.vec, pb.d_pc_fwd, pb.d_pc_tw, pb.N, pb.pc_logN, pb.M,
                        reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, ntask, ntb, pb.d_col_psi,
-                       blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole, pb.d_mcell, pb.d_psi_idx,
+                       blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole,
+                       reinterpret_cast<const int4*>(pb.d_mcell), pb.d_psi_idx,
                        pb.d_p2m_tab);
   }
   if (ev) (void)hipEventRecord(ev[1], pb.stream);
