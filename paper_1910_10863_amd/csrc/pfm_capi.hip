@@ -1067,6 +1067,13 @@ pfm_status pfm_create(const pfm_geometry* geo, const pfm_material* mat, const pf
         dptr[f + 1] = (int)(dd.size() / 8);
       }
       pb.n_dleaves = dptr[pb.M];
+      // each down leaf's first row in the per-frequency L2P table (desc[7])
+      int lrows = 0;
+      for (int q = 0; q < pb.n_dleaves; ++q) {
+        dd[8 * (size_t)q + 7] = lrows;
+        lrows += dd[8 * (size_t)q + 1];
+      }
+      ws_add(pb, &pb.d_l2p_tab, (size_t)std::max(1, lrows) * (pb.opt.p + 2) * sizeof(cd), 0);
       if (dd.empty()) dd.assign(8, 0);
       if (da.empty()) da.assign(4, 0);
       CK(upload(pb, &pb.d_dptr, dptr)); CK(upload(pb, &pb.d_dldesc, dd)); CK(upload(pb, &pb.d_danc, da));

@@ -192,9 +192,10 @@ struct Problem {
   int n_spec = 0;                       // spectral fibres
   cd* d_spec_tab = nullptr;             // [M][4][2p+1] per frequency
   cd* d_spec_hat = nullptr;             // [member][M][2N] spectrum of P psi between the own-block launches
-  int n_mcells = 0;                     // the tree fibres' leaves (P2M)
-  int *d_mcell = nullptr;               // [n_mcells]
-  cd* d_p2m_tab = nullptr;              // [n_mcells][p+1][64][2] the leaves' P2M weights, per frequency[3]: leaf cell, first row (tree order), rows
+  int n_mcells = 0;                     // the tree fibres' cells below their roots (P2M from weights)
+  int *d_mcell = nullptr;               // [n_mcells][4]: cell, first row (tree order), rows, first table row
+  cd* d_p2m_tab = nullptr;              // [table rows][p+1][2] the cells' P2M weights, per frequency
+  cd* d_l2p_tab = nullptr;              // [down-leaf rows][p+2]: Jp_n(kap (x_e - O_leaf)), n = 0..p+1, per frequency
   int n_dleaves = 0;                    // tree fibres' leaves with a far part from below the root or near rows
   int *d_dptr = nullptr;                // [M + 1]: those leaves of fibre f are dptr[f] .. dptr[f + 1]
   int *d_dldesc = nullptr;              // [leaf][8]: first row, rows, own M2L chunks (first, count),

@@ -2204,6 +2204,31 @@ __global__ void __launch_bounds__(256) k_p2m_tables(const int4* __restrict__ mce
   }
 }
 
+// L2P values of the down leaves' rows (ddesc[8 q] = rb, rows, ..., ddesc[8 q
+// + 7] = first table row): tab[(toff + e) (p + 2) + n] = Jp_n(kap (x_e -
+// O_leaf)), n = 0..p+1, from the row's offset to its leaf centre (tgeo), as
+// k_down_spec's L2P would compute them at every apply.  One thread per row.
+template <int P>
+__global__ void __launch_bounds__(64) k_l2p_tables(const int* __restrict__ ddesc, const double4* __restrict__ tgeo,
+                                                   double k, cd* __restrict__ tab) {
+  constexpr int K = P + 1;
+  const int* d = ddesc + 8 * blockIdx.x;
+  const int rb = d[0], rows = d[1], toff = d[7];
+  const int lane = threadIdx.x;
+  if (lane >= rows) return;
+  const double4 g = tgeo[rb + lane];
+  const double vx = k * g.x, vy = k * g.y;
+  double gs[K + 1];                          // h_n = g_n / n!
+  scaled_h<K>(0.25 * (vx * vx + vy * vy), gs);
+  const cd hv = mkc(0.5 * vx, 0.5 * vy);
+  cd uu = mkc(1.0, 0.0);                     // (v/2)^n
+  cd* t = tab + (size_t)(toff + lane) * (K + 1);
+  for (int n = 0; n <= K; ++n) {
+    t[n] = mkc(uu.x * gs[n], uu.y * gs[n]);
+    if (n < K) uu = cmul(uu, hv);
+  }
+}
+
 // A tree fibre's cell moments from its P2M weights (k_p2m_tables): lane m of
 // every wavefront takes the orders m and -m (m <= p), wavefront w a
 // contiguous eighth of the cell's elements (eight at a time, the next
@@ -2373,7 +2398,8 @@ __device__ __forceinline__ cd add_chunks(cd acc, const cd* __restrict__ part, in
 // (a cell's chunks are contiguous): the leaf's own (desc[2], desc[3]: first
 // chunk, count) and each ancestor's below the root (anc[desc[4] ..
 // desc[5]]: first chunk, count, J-table row), translated to the leaf by L2L;
-// then L2P at its rows, y1 += u, y2 += 2/(i eta (1 + varrho)) dn, plus the
+// then L2P at its rows from their per-frequency values Jp_n (k_l2p_tables:
+// table rows from desc[7]), y1 += u, y2 += 2/(i eta (1 + varrho)) dn, plus the
 // stored near pairs' row sums (near_buf from task desc[6], one wave).
 template <int P>
 __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc, const int4* __restrict__ anc,
@@ -2381,7 +2407,7 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
                                                   const cd* __restrict__ jtab, const double4* __restrict__ tgeo,
                                                   const int* __restrict__ psi_idx, int N, double k, double eta,
                                                   double varrho, cd* __restrict__ y, long long y_stride,
-                                                  const cd* __restrict__ near_buf) {
+                                                  const cd* __restrict__ near_buf, const cd* __restrict__ l2p_tab) {
   constexpr int NP = 2 * P + 1, NT = 4 * P + 1, NU = (NP + 63) / 64, NTU = (NT + 63) / 64, K = P + 1;
   // the L2P tables are indexed through wz (= 0, a lane value to the
   // compiler) so that their reads stay in the order loop instead of being
@@ -2392,7 +2418,7 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
   y += blockIdx.y * y_stride;
   const int* d = ddesc + 8 * blockIdx.x;
   const int lane = threadIdx.x;
-  const int rb = d[0], rows = d[1], own0 = d[2], ownc = d[3], a0 = d[4], na = d[5] - d[4], t0 = d[6];
+  const int rb = d[0], rows = d[1], own0 = d[2], ownc = d[3], a0 = d[4], na = d[5] - d[4], t0 = d[6], toff = d[7];
   double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
   int pi = 0;
   if (lane < rows) {
@@ -2457,15 +2483,12 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
   __syncthreads();
   cd u = mkc(0, 0), dv = mkc(0, 0);
   if (lane < rows) {
-    double vx = k * g.x, vy = k * g.y;
-    double gs[K + 1];                          // h_n = g_n / n!
-    scaled_h<K>(0.25 * (vx * vx + vy * vy), gs);
-    cd hv = mkc(0.5 * vx, 0.5 * vy);
-    cd uu = mkc(1.0, 0.0);                     // (v/2)^n
+    const cd* jt = l2p_tab + (size_t)(toff + lane) * (K + 1);   // Jp_n of this row (k_l2p_tables)
     cd sa = mkc(0, 0), sb = mkc(0, 0);
 #pragma unroll
     for (int n = 0; n <= K; ++n) {
-      const double x = uu.x * gs[n], yv = uu.y * gs[n];   // Jp_n
+      const cd jn = jt[n];
+      const double x = jn.x, yv = jn.y;                            // Jp_n
       cd s0 = sS[wz][0][n], tt0 = sT[wz][0][n];
       cd s1 = sS[wz][1][n], tt1 = sT[wz][1][n];
       cd s2 = sS[wz][2][n], tt2 = sT[wz][2][n];
@@ -2475,7 +2498,6 @@ __global__ void __launch_bounds__(64) k_down_spec(const int* __restrict__ ddesc,
       sa.y = fma(s1.y, x, fma(tt1.y, yv, sa.y));
       sb.x = fma(s2.x, x, fma(tt2.x, yv, sb.x));
       sb.y = fma(s2.y, x, fma(tt2.y, yv, sb.y));
-      if (n < K) uu = cmul(uu, hv);
     }
     cd nu = mkc(g.w, -g.z);
     dv = cscale(csub(cmul(nu, sa), cmul(cconj(nu), sb)), 0.5 * k);
@@ -2750,6 +2772,9 @@ static hipError_t tables_impl(Problem& pb) {
   if (pb.spec_root)
     hipLaunchKernelGGL(k_spec_tables<P>, dim3(pb.M), dim3(128), 0, pb.stream, pb.N, pb.d_centres, pb.d_mx, pb.d_my,
                        pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_spec_tab);
+  if (pb.spec_root && pb.n_dleaves > 0)
+    hipLaunchKernelGGL(k_l2p_tables<P>, dim3(pb.n_dleaves), dim3(64), 0, pb.stream, pb.d_dldesc,
+                       reinterpret_cast<const double4*>(pb.d_tgeo), pb.k, pb.d_l2p_tab);
   if (pb.spec_root && pb.n_mcells > 0)
     hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells), dim3(256), 0, pb.stream,
                        reinterpret_cast<const int4*>(pb.d_mcell), pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my,
@@ -2991,7 +3016,7 @@ static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, 
       hipLaunchKernelGGL(k_down_spec<P>, dim3(pb.n_dleaves, nb), dim3(64), 0, pb.stream, pb.d_dldesc,
                          reinterpret_cast<const int4*>(pb.d_danc), pb.d_epart, bs.epart, pb.d_jtab,
                          reinterpret_cast<const double4*>(pb.d_tgeo), pb.d_psi_idx, pb.N, pb.k, pb.eta, pb.varrho,
-                         d_y, bs.vec, B == 0 ? pb.d_near_rows : nullptr);
+                         d_y, bs.vec, B == 0 ? pb.d_near_rows : nullptr, pb.d_l2p_tab);
     if (B > 0) launch_p2p_any<P, C>(pb, pb.stream, blocks, d_psi, d_y, B);
   }
   if (ev) {
