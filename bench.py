@@ -667,9 +667,10 @@ def main():
     # the repeated launches on the library's stream), the figure a kernel
     # trace's average duration gives.  With the roots by Fourier modes the
     # stages are: forward transforms of the own blocks with the roots'
-    # moments and P2M at the tree fibres' leaves ("p2m"), M2M ("m2m"), M2L
-    # ("m2l": on this block the one matrix-core launch), inverse transforms
-    # with the roots' far part and the tree fibres' downward pass
+    # moments and the other tree-fibre cells' moments from their P2M weights
+    # ("p2m"), M2M ("m2m": empty, every moment comes from the first launch),
+    # M2L ("m2l": on this block the one matrix-core launch), inverse
+    # transforms with the roots' far part and the tree fibres' downward pass
     # ("down_l2p").  Roofline kernel: the M2L on the matrix cores, the one
     # dense contraction of the apply.
     steady = {s: prob.stage_timed(psi, s, reps=max(50, min(args.steps, 200)))

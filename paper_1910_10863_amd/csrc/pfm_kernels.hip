@@ -2171,7 +2171,8 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
 // + B_n varphi_e.  The negative orders follow from Jm_{-j} = (-1)^j
 // conj(Jm_j) with the real weight of B and the conjugate pair of weights in
 // A: A_{-n} = (-1)^{n+1} conj(A_n), B_{-n} = (-1)^n conj(B_n).  One thread
-// per (element, order) pair of a cell.
+// per (element, block of eight orders) of a cell, one Bessel sequence per
+// Gauss point for its orders.
 template <int P>
 __global__ void __launch_bounds__(256) k_p2m_tables(const int4* __restrict__ mcell, const int* __restrict__ elem_of,
                                                     const double* __restrict__ cx, const double* __restrict__ cy,
@@ -2179,28 +2180,38 @@ __global__ void __launch_bounds__(256) k_p2m_tables(const int4* __restrict__ mce
                                                     const double* __restrict__ tx, const double* __restrict__ ty,
                                                     const double* __restrict__ h, const double* __restrict__ gl,
                                                     int G, double kap, double eta, cd* __restrict__ tab) {
-  constexpr int NH = P + 1, K = P + 1;
+  constexpr int NH = P + 1, K = P + 1, OB = 8, NB = (NH + OB - 1) / OB;   // orders per thread, order blocks
   const int4 mc = mcell[blockIdx.x];
   const int cell = mc.x, rb = mc.y, rows = mc.z, toff = mc.w;
   const double ox = cx[cell], oy = cy[cell];
-  for (int q = threadIdx.x; q < NH * rows; q += blockDim.x) {
-    const int e = q / NH, n = q - e * NH;
+  for (int q = threadIdx.x; q < NB * rows; q += blockDim.x) {
+    const int e = q / NB, n0 = (q - e * NB) * OB;
     const int en = elem_of[rb + e];
     const double rx = mx[en] - ox, ry = my[en] - oy, ex = tx[en], ey = ty[en], hh = h[en];
-    cd A = mkc(0, 0), Bn = mkc(0, 0);
+    cd A[OB], Bn[OB];
+#pragma unroll
+    for (int o = 0; o < OB; ++o) A[o] = Bn[o] = mkc(0, 0);
     cd jp[K + 1];
     for (int g = 0; g < G; ++g) {
       const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
-      jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
-      const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
-               jmp = cconj(jp_signed<K>(jp, n + 1));
-      A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
-      A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
-      Bn = cadd(Bn, cscale(jm0, eta * w));
+      jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);   // once for the thread's orders
+#pragma unroll
+      for (int o = 0; o < OB; ++o) {
+        const int n = min(n0 + o, P);
+        const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
+                 jmp = cconj(jp_signed<K>(jp, n + 1));
+        A[o] = cfma(mkc(-sk * ex, sk * ey), jmm, A[o]);
+        A[o] = cfma(mkc(-sk * ex, -sk * ey), jmp, A[o]);
+        Bn[o] = cadd(Bn[o], cscale(jm0, eta * w));
+      }
     }
-    cd* t = tab + (((size_t)toff + e) * NH + n) * 2;
-    t[0] = A;
-    t[1] = Bn;
+#pragma unroll
+    for (int o = 0; o < OB; ++o)
+      if (n0 + o < NH) {
+        cd* t = tab + (((size_t)toff + e) * NH + n0 + o) * 2;
+        t[0] = A[o];
+        t[1] = Bn[o];
+      }
   }
 }
 
