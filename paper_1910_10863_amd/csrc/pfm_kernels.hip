@@ -3508,14 +3508,14 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots2(const cd* __restrict__ V,
 // the update coefficients (coef: [0, j) a/gamma, [j, 2j) b/gamma, 2j s/gamma,
 // 2j+1 1/gamma) and the raw column j of d_hall (slots [0, j) a, [j, 2j) b,
 // 2j s, 2j+1 gamma).  NV = 1 (end of a cycle, x_0 = u_j): a and gamma only.
-__global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, int j, int NV, cd* hcol,
-                                                    long long hsb, cd* coef, long long csb) {
-  __shared__ double s_a2[256];
-  __shared__ cd s_ab[256];
-  const int b = blockIdx.x, cnt = j + 1;
-  fin += (size_t)b * NV * cnt;
-  hcol += b * hsb;
-  coef += b * csb;
+// gamma, s and the update coefficients of one member from its reduced dots
+// fin (coef: [0, j) a/gamma, [j, 2j) b/gamma, 2j s/gamma, 2j+1 1/gamma) and,
+// when hcol is given, the raw column j of d_hall (slots [0, j) a, [j, 2j) b,
+// 2j s, 2j+1 gamma), by the 256 threads of the calling workgroup.  NV = 1
+// (end of a cycle, x_0 = u_j): a and gamma only.
+__device__ __forceinline__ void dcgs_coefficients(const cd* __restrict__ fin, int j, int NV, cd* hcol, cd* coef,
+                                                  double* s_a2, cd* s_ab) {
+  const int cnt = j + 1;
   double q2 = 0.0;
   cd ab = mkc(0, 0);
   for (int i = threadIdx.x; i < j; i += 256) {
@@ -3536,38 +3536,55 @@ __global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, 
   const double gamma = sqrt(g2 > 1e-300 ? g2 : 1e-300);
   const double ig = 1.0 / gamma;
   for (int i = threadIdx.x; i < j; i += 256) {
-    hcol[i] = fin[i];
     coef[i] = cscale(fin[i], ig);
+    if (hcol) hcol[i] = fin[i];
     if (NV == 2) {
-      hcol[j + i] = fin[cnt + i];
       coef[j + i] = cscale(fin[cnt + i], ig);
+      if (hcol) hcol[j + i] = fin[cnt + i];
     }
   }
   if (threadIdx.x == 0) {
-    hcol[2 * j + 1] = mkc(gamma, 0.0);
+    if (hcol) hcol[2 * j + 1] = mkc(gamma, 0.0);
     if (NV == 2) {
       const cd sv = cscale(csub(fin[cnt + j], s_ab[0]), ig);
-      hcol[2 * j] = sv;
+      if (hcol) hcol[2 * j] = sv;
       coef[2 * j] = cscale(sv, ig);
       coef[2 * j + 1] = mkc(ig, 0.0);
     }
   }
 }
 
+// One block per member, from the reduced dots fin[member][NV cnt]: the
+// coefficients into coef and the raw column into d_hall (the end of a cycle).
+__global__ void __launch_bounds__(256) k_dcgs_coeff(const cd* __restrict__ fin, int j, int NV, cd* hcol,
+                                                    long long hsb, cd* coef, long long csb) {
+  __shared__ double s_a2[256];
+  __shared__ cd s_ab[256];
+  const int b = blockIdx.x;
+  dcgs_coefficients(fin + (size_t)b * NV * (j + 1), j, NV, hcol + b * hsb, coef + b * csb, s_a2, s_ab);
+}
+
 // v_j = u_j / gamma - V_{j-1} (a / gamma) into slot j; w = w / gamma - V_{j-1} (b / gamma)
-// - (s / gamma) v_j.  A workgroup covers
-// 64 elements; its four wavefronts take the basis vectors i = wv, wv + 4, ...
-// (four times the loads in flight of one wavefront per element block), and
-// their partial sums are added in wavefront order.
+// - (s / gamma) v_j.  Every workgroup first forms the coefficients from the
+// reduced dots fin[member][2 cnt] in LDS (dcgs_coefficients; workgroup 0
+// also writes the raw column j of d_hall), which spares a launch.  A
+// workgroup covers 64 elements; its four wavefronts take the basis vectors
+// i = wv, wv + 4, ... (four times the loads in flight of one wavefront per
+// element block), and their partial sums are added in wavefront order.
 constexpr int UPD_ELEMS = 64;
 __global__ void __launch_bounds__(256) k_dcgs_update(cd* V, long long ldv, long long vsb, int j, cd* w,
-                                                     long long wsb, const cd* __restrict__ coef, long long csb,
-                                                     int n) {
+                                                     long long wsb, const cd* __restrict__ fin, cd* hcol,
+                                                     long long hsb, int n) {
   __shared__ cd pv[4][UPD_ELEMS], pw[4][UPD_ELEMS];
+  __shared__ cd coef[2 * 200 + 2];
+  __shared__ double s_a2[256];
+  __shared__ cd s_ab[256];
   const int b = blockIdx.y;
   V += b * vsb;
   w += b * wsb;
-  coef += b * csb;
+  dcgs_coefficients(fin + (size_t)b * 2 * (j + 1), j, 2, blockIdx.x == 0 ? hcol + b * hsb : nullptr, coef, s_a2,
+                    s_ab);
+  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = blockIdx.x * UPD_ELEMS + lane;
   const bool in = t < n;
@@ -3601,17 +3618,14 @@ hipError_t launch_dcgs_step(Problem& pb, int B, cd* V, long long ldv, long long 
   const int cnt = j + 1;
   const int nblk = pb.red_blocks;
   const long long hcs = (long long)B * hsb;                 // column stride in d_hall
-  const long long csb = 2LL * pb.opt.restart + 4;
   cd* fin = pb.d_red + (size_t)B * 2 * cnt * nblk;          // [B][2 cnt] reduced dots
   hipLaunchKernelGGL(k_dots2<2>, dim3(nblk, (cnt + DOT_VPB - 1) / DOT_VPB, B), dim3(RED_THREADS), 0, pb.stream,
                      V, ldv, vsb, cnt, W, wsb, n, pb.d_red);
   hipLaunchKernelGGL(k_dots_final, dim3(2 * cnt, B), dim3(RED_THREADS), 0, pb.stream, pb.d_red, nblk, 2 * cnt, fin,
                      2LL * cnt);
-  hipLaunchKernelGGL(k_dcgs_coeff, dim3(B), dim3(256), 0, pb.stream, fin, j, 2, pb.d_hall + (size_t)j * hcs, hsb,
-                     pb.d_dcoef, csb);
   const int nup = (n + UPD_ELEMS - 1) / UPD_ELEMS;
-  hipLaunchKernelGGL(k_dcgs_update, dim3(nup, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, pb.d_dcoef, csb,
-                     n);
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nup, B), dim3(256), 0, pb.stream, V, ldv, vsb, j, W, wsb, fin,
+                     pb.d_hall + (size_t)j * hcs, hsb, n);
   return hipGetLastError();
 }
 
