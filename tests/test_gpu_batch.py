@@ -34,6 +34,9 @@ _WL = {
     "tiny": W.tiny(),
     "sq2x2": W.small_square(2, 2, 64, 0.3, 2.0, math.pi / 6),
     "hex2x2": W.small_square(2, 2, 64, 0.3, 3.0, 0.3, lattice=W.HEXAGON),
+    # close fibres: tree fibres beside spectral ones, the cells' P2M weights
+    # and the downward pass's L2P values shared by the members
+    "sq2x2close": W.small_square(2, 2, 64, 0.45, 2.0, 0.4),
 }
 _TH = [0.0, 0.3, -0.5, 1.2, 0.7, -1.1, 0.05, 1.45, -0.2, 0.9, 0.4, -0.8, 1.0, -1.3, 0.15, 0.6]
 
@@ -47,7 +50,8 @@ def _dense(key, ka, th):
 
 
 @pytest.mark.parametrize("key,ka,B", [("tiny", 2.0, 1), ("tiny", 2.0, 3), ("sq2x2", 2.0, 4),
-                                      ("hex2x2", 3.0, 8), ("sq2x2", 5.0, 16), ("hex2x2", 1.0, 5)])
+                                      ("hex2x2", 3.0, 8), ("sq2x2", 5.0, 16), ("hex2x2", 1.0, 5),
+                                      ("sq2x2close", 2.0, 6)])
 def test_batch_matvec_matches_single_angle(pfm, key, ka, B):
     wl = _WL[key]
     th = _TH[:B]
@@ -67,14 +71,15 @@ def test_batch_matvec_matches_single_angle(pfm, key, ka, B):
         assert rerr < 1e-13 * np.linalg.norm(rhs_b[b]), (b, rerr)
 
 
-def test_batch_matvec_vs_dense_oracle(pfm):
+@pytest.mark.parametrize("key", ["sq2x2", "sq2x2close"])
+def test_batch_matvec_vs_dense_oracle(pfm, key):
     th = [0.2, -0.6, 1.1]
-    pb = pfm.Problem.from_workload(_WL["sq2x2"], p=40, leaf_max=16, max_batch=4)
+    pb = pfm.Problem.from_workload(_WL[key], p=40, leaf_max=16, max_batch=4)
     pb.set_batch(2.0, th)
     psi = torch.tensor(np.stack([W.random_density(pb.n, 7 + b) for b in range(3)]), device="cuda")
     y = pb.matvec_batch(psi).cpu().numpy()
     for b in range(3):
-        A, _ = _dense("sq2x2", 2.0, th[b])
+        A, _ = _dense(key, 2.0, th[b])
         ref = A @ psi[b].cpu().numpy()
         err = np.linalg.norm(y[b] - ref) / np.linalg.norm(ref)
         _say("  member", b, "rel err vs dense", err)
