@@ -263,6 +263,33 @@ def test_fields_vs_oracle(pfm):
     assert abs(en - fl.energy_residual(pb, psi, n_orders=6)) < 1e-12
 
 
+@pytest.mark.parametrize("p", [8, 12, 16, 20, 32])
+def test_m2l_matrix_cores_every_order(pfm, p):
+    """The matrix-core M2L at every supported expansion order: with the last
+    order on the vector ALU (p = 8, 16, 32: 2p + 1 = 16 q + 1) and without
+    (p = 12, 20), single angle and a batch of two, against the same apply
+    with every entry on the vector ALU (same truncation: rounding only),
+    on a block with close fibres (in-tree entries, leaf and cell moments
+    from their weights) and with separated ones (root pairs only)."""
+    for key in ("sq2x2close", "hex2x2"):
+        wl, ka, th = _WL[key]
+        ys = []
+        for vec in (False, True):
+            prob = pfm.Problem.from_workload(wl, p=p, leaf_max=16, m2l_vector=vec, max_batch=2)
+            psi = torch.tensor(np.stack([W.random_density(prob.n, 31 + b) for b in range(2)]), device="cuda")
+            prob.set_wave(ka, th)
+            y1 = prob.matvec(psi[0].contiguous()).cpu().numpy()
+            prob.set_batch(ka, [th, th + 0.4])
+            yb = prob.matvec_batch(psi).cpu().numpy()
+            ys.append((y1, yb))
+            if not vec:
+                assert prob.stats()["m2l_mfma_items"] > 0
+        d1 = np.linalg.norm(ys[0][0] - ys[1][0]) / np.linalg.norm(ys[1][0])
+        db = np.linalg.norm(ys[0][1] - ys[1][1]) / np.linalg.norm(ys[1][1])
+        _say("m2l every order:", key, "p", p, d1, db)
+        assert d1 < 1e-12 and db < 1e-12
+
+
 # ---- mixed precision: complex64 near field inside FP64 iterative refinement ----
 
 @pytest.mark.parametrize("key", ["tiny", "sq2x2", "hex2x2", "sq2x2close"])
