@@ -187,9 +187,11 @@ typedef struct {
  *             below the root: its neighbours are farther away than the
  *             admissibility ratio allows for their radii) needs no P2M, M2M,
  *             L2L or L2P (pfm_stats.spectral_roots, n_spectral_fibres); the
- *             other fibres keep P2M at their leaves, M2M into their cells
- *             below the root and the downward pass of those cells'
- *             expansions.  2: as 0 without this.
+ *             other fibres' cells below the root take their moments
+ *             straight from per-frequency P2M weights of their elements (no
+ *             M2M), and their leaves run the downward pass of those cells'
+ *             expansions (L2P from per-frequency Bessel values of each
+ *             row).  2: as 0 without this.
  *  precond    0: plain GMRES; 1: pfm_solve runs GMRES (with PFM_MIXED the
  *             inner GMRES of the refinement)
  *             right-preconditioned by the fibres' free-space self blocks of
@@ -402,9 +404,10 @@ pfm_status pfm_get_stats(const pfm_problem* pb, pfm_stats* st);
  * join kernel adds it (pfm_matvec fuses the join into the downward pass).
  * With the roots by Fourier modes (pfm_stats.spectral_roots) the launches
  * are those of pfm_matvec, bracketed: [forward transforms of the own blocks
- * with the roots' moments and P2M at the tree fibres' leaves, M2M, M2L,
- * inverse transforms with the roots' far part and the tree fibres'
- * downward pass (and near rows), 0, 0]. */
+ * with the roots' moments and the other tree-fibre cells' moments from
+ * their P2M weights, M2M (no launch), M2L, inverse transforms with the
+ * roots' far part and the tree fibres' downward pass (and near rows),
+ * 0, 0]. */
 pfm_status pfm_matvec_timed(pfm_problem* pb, const void* d_psi, void* d_y,
                             int reps, double* stage_ms, double* total_ms);
 
