@@ -625,8 +625,7 @@ __global__ void k_jtab(int n_off, const double* __restrict__ off, double k, doub
 // lattice sums of the top-level M2L (Sec. 3.3):
 //   S_nu(o) = sum_{m outside [m_lo, m_hi]} alpha^m Hp_nu(k (o - m h))
 // direct for |m| <= q, tails for |m| > q as contour integrals in s
-// (t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik, dt/mu = 2 ds / sqrt(s^2 - 2ik)),
-// one workgroup per fibre offset, one thread per order nu.
+// (t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik, dt/mu = 2 ds / sqrt(s^2 - 2ik)).
 // ---------------------------------------------------------------------------
 // Tails of the lattice sums (both sides |m| > q), from the corrected contour
 // integrals: for the rule point s with t = +-s sqrt(s^2 - 2ik), mu = s^2 - ik,
@@ -634,9 +633,12 @@ __global__ void k_jtab(int n_off, const double* __restrict__ off, double k, doub
 //   down: exp(i X t - mu Y - (q+1)(i beta + mu H)) / (1 - e^{-i beta - mu H}),
 // times 2 w / sqrt(s^2 - 2ik) and the order factors (-i(t +- mu)/k)^nu
 // (nu >= 0) or (i(t -+ mu)/k)^|nu| (nu < 0).  One thread per rule point
-// carries all orders by running products; each order is summed over the
-// wavefront by cross-lane sums and over the block in LDS.  Partial sums per
-// (member, offset, rule block) are added by k_lattice_direct.
+// carries all orders by running products.  The sums over the workgroup's 256
+// points go through LDS a few orders at a time: every thread stores its terms
+// of LT_NB orders (both signs), then 32 threads per term add eight points
+// each and a 32-lane butterfly finishes the sum (far fewer cross-lane moves
+// than a full-wave butterfly per order).  Partial sums per (member, offset,
+// rule block) are added by k_lattice_direct.
 // sum of a complex value over the 64 lanes of a wavefront (every lane gets it)
 __device__ __forceinline__ cd wave_sum(cd v) {
 #pragma unroll
@@ -648,15 +650,15 @@ __device__ __forceinline__ cd wave_sum(cd v) {
 }
 
 constexpr int LAT_MAX_NT = 4 * 40 + 1;
+constexpr int LT_NB = 4;                 // orders per LDS round of k_lattice_tails
 
 __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const double* __restrict__ roff,
                                                        double k, double H, const double* __restrict__ betas,
                                                        int q, const double* __restrict__ rule, int n_rule,
                                                        cd* __restrict__ partial) {
-  __shared__ cd sred[4][LAT_MAX_NT];
+  __shared__ cd sv[2 * LT_NB][256];
   const int NT = 4 * P + 1;
   const int o = blockIdx.x, rb = blockIdx.y, mb = blockIdx.z;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double beta = betas[mb];
   const double ox = roff[2 * o], oy = roff[2 * o + 1];
   const double invk = 1.0 / k;
@@ -693,26 +695,37 @@ __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const 
       ydn[br] = cscale(mkc(-tpm.y, tpm.x), invk);     //  i (t + mu) / k
     }
   }
-  for (int nu = 0; nu <= 2 * P; ++nu) {
-    cd vp = cadd(cadd(aup[0], adn[0]), cadd(aup[1], adn[1]));
-    vp = wave_sum(vp);
-    if (lane == 0) sred[w][2 * P + nu] = vp;
-    if (nu > 0) {
-      cd vn = cadd(cadd(bup[0], bdn[0]), cadd(bup[1], bdn[1]));
-      vn = wave_sum(vn);
-      if (lane == 0) sred[w][2 * P - nu] = vn;
-    }
-    for (int br = 0; br < 2; ++br) {
-      aup[br] = cmul(aup[br], zup[br]);
-      adn[br] = cmul(adn[br], zdn[br]);
-      bup[br] = cmul(bup[br], yup[br]);
-      bdn[br] = cmul(bdn[br], ydn[br]);
-    }
-  }
-  __syncthreads();
   cd* out = partial + (((size_t)mb * n_roff + o) * gridDim.y + rb) * NT;
-  for (int t = threadIdx.x; t < NT; t += 256)
-    out[t] = cadd(cadd(sred[0][t], sred[1][t]), cadd(sred[2][t], sred[3][t]));
+  const int term = threadIdx.x >> 5, seg = threadIdx.x & 31;
+  for (int nu0 = 0; nu0 <= 2 * P; nu0 += LT_NB) {
+#pragma unroll
+    for (int j = 0; j < LT_NB; ++j) {
+      // order nu0 + j: term 2j holds +nu, term 2j + 1 holds -nu
+      sv[2 * j][threadIdx.x] = cadd(cadd(aup[0], adn[0]), cadd(aup[1], adn[1]));
+      sv[2 * j + 1][threadIdx.x] = cadd(cadd(bup[0], bdn[0]), cadd(bup[1], bdn[1]));
+      for (int br = 0; br < 2; ++br) {
+        aup[br] = cmul(aup[br], zup[br]);
+        adn[br] = cmul(adn[br], zdn[br]);
+        bup[br] = cmul(bup[br], yup[br]);
+        bdn[br] = cmul(bdn[br], ydn[br]);
+      }
+    }
+    __syncthreads();
+    cd a = sv[term][seg];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) a = cadd(a, sv[term][seg + 32 * r]);
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      a.x += __shfl_xor(a.x, off, 64);
+      a.y += __shfl_xor(a.y, off, 64);
+    }
+    const int nu = nu0 + (term >> 1);
+    if (seg == 0 && nu <= 2 * P) {
+      if (!(term & 1)) out[2 * P + nu] = a;
+      else if (nu > 0) out[2 * P - nu] = a;
+    }
+    __syncthreads();
+  }
 }
 
 // Direct part of the lattice sums, the images |m| <= q outside the explicit
@@ -720,52 +733,78 @@ __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const 
 //   S_nu(o) = sum_m alpha^m Hp_nu(k (o - m H e_y)),  Hp_nu(v) = H_|nu|(|v|) e^{i nu arg v}
 //             (times (-1)^nu for nu < 0),
 // plus the tails of k_lattice_tails times 1/(i pi).  One workgroup per
-// (offset, member), one thread per order.
-__global__ void k_lattice_direct(int P, int n_roff, const double* __restrict__ roff,
-                                 const int* __restrict__ mrange, double k, double H,
-                                 const double* __restrict__ betas, int q, int n_rblk,
-                                 const cd* __restrict__ partial, cd* out, long long out_stride) {
-  int o = blockIdx.x, mb = blockIdx.y;
-  int NT = 4 * P + 1;
-  double beta = betas[mb];
-  double ox = roff[2 * o], oy = roff[2 * o + 1];
-  int mlo = mrange[2 * o], mhi = mrange[2 * o + 1];
-  const cd* part = partial + ((size_t)mb * n_roff + o) * n_rblk * NT;
-  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
-    int nu = t - 2 * P;
-    int an = nu < 0 ? -nu : nu;
-    cd acc = mkc(0, 0);
-    for (int m = -q; m <= q; ++m) {
-      if (m >= mlo && m <= mhi) continue;
-      double vx = ox, vy = oy - m * H;
-      double r = sqrt(vx * vx + vy * vy);
-      double x = k * r;
-      cd H0, H1;
-      hankel01(x, H0, H1);
-      cd Hn = H0;
-      if (an >= 1) {
-        cd Hp = H0, Hc = H1;
-        for (int n = 1; n < an; ++n) {
-          cd Hx = csub(cscale(Hc, 2.0 * n / x), Hp);
-          Hp = Hc;
-          Hc = Hx;
-        }
-        Hn = Hc;
+// (offset, member).  The images go in chunks of LD_CH: one thread per image
+// evaluates H_0, H_1 and the upward recurrence to H_{2P}, its angle and
+// alpha^m into LDS; then one thread per order adds the chunk's images in
+// increasing m.
+constexpr int LD_CH = 16;
+
+__global__ void __launch_bounds__(128) k_lattice_direct(int P, int n_roff, const double* __restrict__ roff,
+                                                        const int* __restrict__ mrange, double k, double H,
+                                                        const double* __restrict__ betas, int q, int n_rblk,
+                                                        const cd* __restrict__ partial, cd* out,
+                                                        long long out_stride) {
+  __shared__ cd sH[LD_CH][2 * 40 + 1];
+  __shared__ cd sAl[LD_CH];
+  __shared__ double sTh[LD_CH];
+  const int o = blockIdx.x, mb = blockIdx.y;
+  const int NT = 4 * P + 1;
+  const double beta = betas[mb];
+  const double ox = roff[2 * o], oy = roff[2 * o + 1];
+  const int mlo = mrange[2 * o], mhi = mrange[2 * o + 1];
+  const int nex = mhi >= mlo ? mhi - mlo + 1 : 0;     // excluded images (inside [-q, q])
+  const int n_img = 2 * q + 1 - nex;
+  cd acc[2] = {mkc(0, 0), mkc(0, 0)};                 // orders threadIdx.x, threadIdx.x + 128
+  for (int c0 = 0; c0 < n_img; c0 += LD_CH) {
+    const int cnt = min(LD_CH, n_img - c0);
+    if ((int)threadIdx.x < cnt) {
+      int m = -q + c0 + (int)threadIdx.x;
+      if (nex > 0 && m >= mlo) m += nex;
+      const double vx = ox, vy = oy - m * H;
+      const double x = k * sqrt(vx * vx + vy * vy);
+      cd Hp, Hc;
+      hankel01(x, Hp, Hc);
+      cd* hr = sH[threadIdx.x];
+      hr[0] = Hp;
+      if (P > 0) hr[1] = Hc;
+      for (int n = 1; n < 2 * P; ++n) {
+        cd Hx = csub(cscale(Hc, 2.0 * n / x), Hp);
+        Hp = Hc;
+        Hc = Hx;
+        hr[n + 1] = Hc;
       }
-      double th = atan2(vy, vx);
-      double s, c;
-      sincos(nu * th, &s, &c);
-      cd v = cmul(Hn, mkc(c, s));
-      if (nu < 0 && (an & 1)) v = cscale(v, -1.0);
+      sTh[threadIdx.x] = atan2(vy, vx);
       double sb, cb;
       sincos(m * beta, &sb, &cb);
-      acc = cfma(mkc(cb, sb), v, acc);
+      sAl[threadIdx.x] = mkc(cb, sb);
     }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+      const int t = threadIdx.x + 128 * h;
+      if (t >= NT) break;
+      const int nu = t - 2 * P;
+      const int an = nu < 0 ? -nu : nu;
+      cd a = acc[h];
+      for (int j = 0; j < cnt; ++j) {
+        double s, c;
+        sincos(nu * sTh[j], &s, &c);
+        cd v = cmul(sH[j][an], mkc(c, s));
+        if (nu < 0 && (an & 1)) v = cscale(v, -1.0);
+        a = cfma(sAl[j], v, a);
+      }
+      acc[h] = a;
+    }
+    __syncthreads();
+  }
+  const cd* part = partial + ((size_t)mb * n_roff + o) * n_rblk * NT;
+  for (int h = 0; h < 2; ++h) {
+    const int t = threadIdx.x + 128 * h;
+    if (t >= NT) break;
     cd tail = mkc(0, 0);
     for (int rb = 0; rb < n_rblk; ++rb) tail = cadd(tail, part[(size_t)rb * NT + t]);
     // 1/(i pi) * tail
     tail = mkc(tail.y / PI, -tail.x / PI);
-    out[mb * out_stride + (size_t)o * NT + t] = cadd(acc, tail);
+    out[mb * out_stride + (size_t)o * NT + t] = cadd(acc[h], tail);
   }
 }
 
