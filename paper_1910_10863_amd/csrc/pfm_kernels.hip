@@ -245,12 +245,59 @@ __global__ void __launch_bounds__(128) k_near_blocks(NearArgs A) {
 // element d (image 0) for d = 0..N-1, which is the block of any element a
 // with element (a + d) mod N.  Layout [f][B11, B12, B21, B22][2N], entry d
 // stored at d and at d + N so that the index (b - a) + N needs no wrap.
-__global__ void __launch_bounds__(128) k_circ_rows(NearArgs A, cd* __restrict__ circ) {
+// 32 lanes per entry: lane bit 4 picks the wavenumber (k or k1), bits 0..3
+// the Gauss point of the source element's rule (16 points for the two
+// neighbours on each side, g_far <= 16 otherwise, the closed form for the
+// element itself); the points are summed by a 16-lane butterfly.
+constexpr int CR_ENTRIES = 8;            // entries per 256-thread workgroup
+
+__global__ void __launch_bounds__(256) k_circ_rows(NearArgs A, cd* __restrict__ circ) {
   const int f = blockIdx.y, N = A.N;
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= N) return;
-  cd B11, B12, B21, B22;
-  near_entry(A, f * N, f * N + d, 0, mkc(1, 0), B11, B12, B21, B22);
+  const int d = blockIdx.x * CR_ENTRIES + (threadIdx.x >> 5);
+  const int sub = threadIdx.x & 31, kw = sub >> 4, g = sub & 15;
+  if (d >= N) return;                    // the entry's 32 lanes leave together
+  const int ea = f * N, eb = f * N + d;
+  const double kap = kw ? A.k1 : A.k;
+  const double x = A.mx[ea], y = A.my[ea];
+  const double nux = A.ty[ea], nuy = -A.tx[ea];
+  const double cxm = A.mx[eb], cym = A.my[eb];
+  const double tx = A.tx[eb], ty = A.ty[eb], hh = A.h[eb];
+  const int dl = min(d, N - d);
+  cd S = mkc(0, 0), D = S, K = S, T = S;
+  if (dl == 0) {
+    if (g == 0) self_terms(kap, hh, S, T);
+  } else {
+    const double* gl = dl <= 2 ? A.gl16 : A.gl;
+    const int G = dl <= 2 ? 16 : A.g_far;
+    if (g < G) {
+      const double sg = 0.5 * hh * gl[g], w = 0.5 * hh * gl[G + g];
+      cd s_, d_, k_, t_;
+      kern_sdkt(kap, x - (cxm + sg * tx), y - (cym + sg * ty), nux, nuy, ty, -tx, s_, d_, k_, t_);
+      S = cscale(s_, w);
+      D = cscale(d_, w);
+      K = cscale(k_, w);
+      T = cscale(t_, w);
+    }
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    S.x += __shfl_xor(S.x, off, 64); S.y += __shfl_xor(S.y, off, 64);
+    D.x += __shfl_xor(D.x, off, 64); D.y += __shfl_xor(D.y, off, 64);
+    K.x += __shfl_xor(K.x, off, 64); K.y += __shfl_xor(K.y, off, 64);
+    T.x += __shfl_xor(T.x, off, 64); T.y += __shfl_xor(T.y, off, 64);
+  }
+  // the interior (k1) sums of lane 16 to lane 0
+  const cd S1 = mkc(__shfl_xor(S.x, 16, 64), __shfl_xor(S.y, 16, 64));
+  const cd D1 = mkc(__shfl_xor(D.x, 16, 64), __shfl_xor(D.y, 16, 64));
+  const cd K1 = mkc(__shfl_xor(K.x, 16, 64), __shfl_xor(K.y, 16, 64));
+  const cd T1 = mkc(__shfl_xor(T.x, 16, 64), __shfl_xor(T.y, 16, 64));
+  if (sub != 0) return;
+  const cd c = mkc(0.0, -2.0 / (A.eta * (1.0 + A.varrho)));     // 2 / (i eta (1 + varrho))
+  const cd mieta = mkc(0.0, -A.eta);                              // -i eta
+  const cd B11 = csub(D, D1);
+  const cd B12 = cmul(mieta, csub(S, S1));
+  const cd B21 = cmul(c, csub(T, cscale(T1, A.varrho)));
+  const cd B22 = cmul(cmul(c, mieta), csub(K, cscale(K1, A.varrho)));
   cd* row = circ + (size_t)f * 8 * N;
   row[d] = row[d + N] = B11;
   row[2 * N + d] = row[3 * N + d] = B12;
@@ -299,7 +346,8 @@ hipError_t launch_near_blocks(Problem& pb, bool phase_free) {
   if (pb.nystrom)
     return launch_circ_rows_nys(pb);
   if (pb.n_near_circ > 0 || pb.opt.precond || pb.self_fft)
-    hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + 127) / 128, pb.M), dim3(128), 0, pb.stream, A, pb.d_circ);
+    hipLaunchKernelGGL(k_circ_rows, dim3((pb.N + CR_ENTRIES - 1) / CR_ENTRIES, pb.M), dim3(256), 0, pb.stream, A,
+                       pb.d_circ);
   return hipGetLastError();
 }
 
