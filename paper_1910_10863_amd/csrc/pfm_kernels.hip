@@ -662,6 +662,7 @@ __global__ void k_jtab(int n_off, const double* __restrict__ off, double k, doub
   jplus_seq<2 * P>(kap * off[2 * o], kap * off[2 * o + 1], jp);
   cd* out = tab + (size_t)i * NT + 2 * P;
   double sgn = 1.0;
+#pragma unroll
   for (int n = 0; n <= 2 * P; ++n) {
     out[n] = jp[n];
     out[-n] = cscale(cconj(jp[n]), sgn);
@@ -2210,9 +2211,19 @@ __device__ __forceinline__ cd jp_signed(const cd (&jp)[K + 1], int j) {
   return (j & 1) ? cscale(v, -1.0) : v;
 }
 
+// the same from a sequence Jp_0..Jp_K held in LDS
+template <int K>
+__device__ __forceinline__ cd jp_lds(const cd* jp, int j) {
+  if (j >= 0) return jp[j];
+  const cd v = cconj(jp[-j]);
+  return (j & 1) ? cscale(v, -1.0) : v;
+}
+
 // tab[f][0][n] = A_n, [1][n] = B_n, [2][l] = Jp_l(v_0),
 // [3][l] = (kap/2)(nu_0 Jp_{l-1}(v_0) - conj(nu_0) Jp_{l+1}(v_0)); n, l = -P..P.
-// One thread per (fibre, order); the exterior wavenumber only.
+// One workgroup per fibre: the Bessel sequences at the G Gauss points and
+// at the element's centre once each into LDS, then one thread per order;
+// the exterior wavenumber only.
 template <int P>
 __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __restrict__ centres,
                                                      const double* __restrict__ mx, const double* __restrict__ my,
@@ -2220,33 +2231,41 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
                                                      const double* __restrict__ h, const double* __restrict__ gl,
                                                      int G, double kap, double eta, cd* __restrict__ tab) {
   constexpr int NP = 2 * P + 1, K = P + 1;
+  __shared__ cd sJ[17][K + 1];             // Jp_0..Jp_K at the G <= 16 points and at the element's centre
   const int f = blockIdx.x, i = threadIdx.x;
-  if (i >= NP) return;
-  const int n = i - P;
   const size_t e0 = (size_t)f * N;
   const double ex = tx[e0], ey = ty[e0], hh = h[e0];
   const double rx = mx[e0] - centres[2 * f], ry = my[e0] - centres[2 * f + 1];
-  cd jp[K + 1];
+  // one Bessel sequence per thread 0..G (thread G: the centre), shared by the orders
+  if (i <= G) {
+    cd jp[K + 1];
+    const double s = i < G ? 0.5 * hh * gl[i] : 0.0;
+    jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
+#pragma unroll
+    for (int j = 0; j <= K; ++j) sJ[i][j] = jp[j];
+  }
+  __syncthreads();
+  if (i >= NP) return;
+  const int n = i - P;
   // P2M weights per unit phi and varphi (as k_p2m: w = h gl_w / 8 carries
   // the factor i/4 of the representation, sk = kap w / 2):
   //   A_n = sum_g sk (-tx + i ty) Jm_{n-1} + sk (-tx - i ty) Jm_{n+1},  B_n = sum_g eta w Jm_n
   cd A = mkc(0, 0), Bn = mkc(0, 0);
   for (int g = 0; g < G; ++g) {
-    const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
-    jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);
-    const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
-             jmp = cconj(jp_signed<K>(jp, n + 1));
+    const double w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
+    const cd jm0 = cconj(jp_lds<K>(sJ[g], n)), jmm = cconj(jp_lds<K>(sJ[g], n - 1)),
+             jmp = cconj(jp_lds<K>(sJ[g], n + 1));
     A = cfma(mkc(-sk * ex, sk * ey), jmm, A);
     A = cfma(mkc(-sk * ex, -sk * ey), jmp, A);
     Bn = cadd(Bn, cscale(jm0, eta * w));
   }
-  jplus_seq<K>(kap * rx, kap * ry, jp);
   const cd nu = mkc(ey, -ex);
-  const cd dl = cscale(csub(cmul(nu, jp_signed<K>(jp, n - 1)), cmul(cconj(nu), jp_signed<K>(jp, n + 1))), 0.5 * kap);
+  const cd dl = cscale(csub(cmul(nu, jp_lds<K>(sJ[G], n - 1)), cmul(cconj(nu), jp_lds<K>(sJ[G], n + 1))),
+                       0.5 * kap);
   cd* T = tab + (size_t)f * 4 * NP;
   T[i] = A;
   T[NP + i] = Bn;
-  T[2 * NP + i] = jp_signed<K>(jp, n);
+  T[2 * NP + i] = jp_lds<K>(sJ[G], n);
   T[3 * NP + i] = dl;
 }
 
@@ -2259,46 +2278,71 @@ __global__ void __launch_bounds__(128) k_spec_tables(int N, const double* __rest
 // conj(Jm_j) with the real weight of B and the conjugate pair of weights in
 // A: A_{-n} = (-1)^{n+1} conj(A_n), B_{-n} = (-1)^n conj(B_n).  One thread
 // per (element, block of eight orders) of a cell, one Bessel sequence per
-// Gauss point for its orders.
+// Gauss point for its orders; the block's first order is a template
+// constant so that the sequence stays in registers.  Workgroups of 64
+// threads, P2M_TAB_SPLIT of them per cell.
+constexpr int P2M_TAB_OB = 8;            // orders per thread
+constexpr int P2M_TAB_SPLIT = 8;         // workgroups per cell
+
+template <int P, int N0>
+__device__ __forceinline__ void p2m_table_orders(double rx, double ry, double ex, double ey, double hh,
+                                                 const double* __restrict__ gl, int G, double kap, double eta,
+                                                 cd* __restrict__ t) {
+  constexpr int NH = P + 1, K = P + 1, OB = P2M_TAB_OB;
+  cd A[OB], Bn[OB];
+#pragma unroll
+  for (int o = 0; o < OB; ++o) A[o] = Bn[o] = mkc(0, 0);
+  cd jp[K + 1];
+  for (int g = 0; g < G; ++g) {
+    const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
+    jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);   // once for the thread's orders
+#pragma unroll
+    for (int o = 0; o < OB; ++o) {
+      const int n = N0 + o < P ? N0 + o : P;
+      const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
+               jmp = cconj(jp_signed<K>(jp, n + 1));
+      A[o] = cfma(mkc(-sk * ex, sk * ey), jmm, A[o]);
+      A[o] = cfma(mkc(-sk * ex, -sk * ey), jmp, A[o]);
+      Bn[o] = cadd(Bn[o], cscale(jm0, eta * w));
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < OB; ++o)
+    if (N0 + o < NH) {
+      t[2 * (N0 + o)] = A[o];
+      t[2 * (N0 + o) + 1] = Bn[o];
+    }
+}
+
+template <int P, int B>
+__device__ __forceinline__ void p2m_table_block(int blk, double rx, double ry, double ex, double ey, double hh,
+                                                const double* __restrict__ gl, int G, double kap, double eta,
+                                                cd* __restrict__ t) {
+  constexpr int NB = (P + 1 + P2M_TAB_OB - 1) / P2M_TAB_OB;
+  if constexpr (B < NB) {
+    if (blk == B)
+      p2m_table_orders<P, B * P2M_TAB_OB>(rx, ry, ex, ey, hh, gl, G, kap, eta, t);
+    else
+      p2m_table_block<P, B + 1>(blk, rx, ry, ex, ey, hh, gl, G, kap, eta, t);
+  }
+}
+
 template <int P>
-__global__ void __launch_bounds__(256) k_p2m_tables(const int4* __restrict__ mcell, const int* __restrict__ elem_of,
-                                                    const double* __restrict__ cx, const double* __restrict__ cy,
-                                                    const double* __restrict__ mx, const double* __restrict__ my,
-                                                    const double* __restrict__ tx, const double* __restrict__ ty,
-                                                    const double* __restrict__ h, const double* __restrict__ gl,
-                                                    int G, double kap, double eta, cd* __restrict__ tab) {
-  constexpr int NH = P + 1, K = P + 1, OB = 8, NB = (NH + OB - 1) / OB;   // orders per thread, order blocks
+__global__ void __launch_bounds__(64) k_p2m_tables(const int4* __restrict__ mcell, const int* __restrict__ elem_of,
+                                                   const double* __restrict__ cx, const double* __restrict__ cy,
+                                                   const double* __restrict__ mx, const double* __restrict__ my,
+                                                   const double* __restrict__ tx, const double* __restrict__ ty,
+                                                   const double* __restrict__ h, const double* __restrict__ gl,
+                                                   int G, double kap, double eta, cd* __restrict__ tab) {
+  constexpr int NH = P + 1, NB = (NH + P2M_TAB_OB - 1) / P2M_TAB_OB;   // order blocks
   const int4 mc = mcell[blockIdx.x];
   const int cell = mc.x, rb = mc.y, rows = mc.z, toff = mc.w;
   const double ox = cx[cell], oy = cy[cell];
-  for (int q = threadIdx.x; q < NB * rows; q += blockDim.x) {
-    const int e = q / NB, n0 = (q - e * NB) * OB;
+  for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < NB * rows; q += gridDim.y * blockDim.x) {
+    const int e = q / NB, blk = q - e * NB;
     const int en = elem_of[rb + e];
-    const double rx = mx[en] - ox, ry = my[en] - oy, ex = tx[en], ey = ty[en], hh = h[en];
-    cd A[OB], Bn[OB];
-#pragma unroll
-    for (int o = 0; o < OB; ++o) A[o] = Bn[o] = mkc(0, 0);
-    cd jp[K + 1];
-    for (int g = 0; g < G; ++g) {
-      const double s = 0.5 * hh * gl[g], w = 0.125 * hh * gl[G + g], sk = 0.5 * kap * w;
-      jplus_seq<K>(kap * (rx + s * ex), kap * (ry + s * ey), jp);   // once for the thread's orders
-#pragma unroll
-      for (int o = 0; o < OB; ++o) {
-        const int n = min(n0 + o, P);
-        const cd jm0 = cconj(jp_signed<K>(jp, n)), jmm = cconj(jp_signed<K>(jp, n - 1)),
-                 jmp = cconj(jp_signed<K>(jp, n + 1));
-        A[o] = cfma(mkc(-sk * ex, sk * ey), jmm, A[o]);
-        A[o] = cfma(mkc(-sk * ex, -sk * ey), jmp, A[o]);
-        Bn[o] = cadd(Bn[o], cscale(jm0, eta * w));
-      }
-    }
-#pragma unroll
-    for (int o = 0; o < OB; ++o)
-      if (n0 + o < NH) {
-        cd* t = tab + (((size_t)toff + e) * NH + n0 + o) * 2;
-        t[0] = A[o];
-        t[1] = Bn[o];
-      }
+    p2m_table_block<P, 0>(blk, mx[en] - ox, my[en] - oy, tx[en], ty[en], h[en], gl, G, kap, eta,
+                          tab + ((size_t)toff + e) * NH * 2);
   }
 }
 
@@ -2874,7 +2918,7 @@ static hipError_t tables_impl(Problem& pb) {
     hipLaunchKernelGGL(k_l2p_tables<P>, dim3(pb.n_dleaves), dim3(64), 0, pb.stream, pb.d_dldesc,
                        reinterpret_cast<const double4*>(pb.d_tgeo), pb.k, pb.d_l2p_tab);
   if (pb.spec_root && pb.n_mcells > 0)
-    hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells), dim3(256), 0, pb.stream,
+    hipLaunchKernelGGL(k_p2m_tables<P>, dim3(pb.n_mcells, P2M_TAB_SPLIT), dim3(64), 0, pb.stream,
                        reinterpret_cast<const int4*>(pb.d_mcell), pb.d_elem_of, pb.d_cx, pb.d_cy, pb.d_mx, pb.d_my,
                        pb.d_tx, pb.d_ty, pb.d_h, pb.d_gl, pb.opt.g_far, pb.k, pb.eta, pb.d_p2m_tab);
   return hipGetLastError();
