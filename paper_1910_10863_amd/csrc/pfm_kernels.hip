@@ -583,13 +583,30 @@ __global__ void __launch_bounds__(PC_THREADS) k_pc_apply(const cd* in, cd* out, 
   cd* Y = pcs + 2 * N;
   const cd* src = in + mem + (size_t)f * 2 * N;  // phi_f then varphi_f
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  // with one mode per thread (N <= PC_THREADS) the mode block's loads are
+  // issued now and land while the forward transforms run
+  const bool one = N <= (int)blockDim.x;
+  const int kk = threadIdx.x;
+  cd c0 = mkc(0, 0), c1 = c0, c2 = c0, c3 = c0;
+  if (one && kk < N) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    c0 = c[0]; c1 = c[1]; c2 = c[2]; c3 = c[3];
+  }
   __syncthreads();
   cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
-  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
-    const cd* c = coef + ((size_t)f * N + kk) * 4;
-    const cd u = H[kk], v = H[N + kk];
-    H[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
-    H[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+  if (one) {
+    if (kk < N) {
+      const cd u = H[kk], v = H[N + kk];
+      H[kk] = cadd(cmul(c0, u), cmul(c1, v));
+      H[N + kk] = cadd(cmul(c2, u), cmul(c3, v));
+    }
+  } else {
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+      const cd* c = coef + ((size_t)f * N + m) * 4;
+      const cd u = H[m], v = H[N + m];
+      H[m] = cadd(cmul(c[0], u), cmul(c[1], v));
+      H[N + m] = cadd(cmul(c[2], u), cmul(c[3], v));
+    }
   }
   __syncthreads();
   const cd* Z = pc_fft(H, H == X ? Y : X, 2, N, logN, tw, false);
@@ -2168,13 +2185,30 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_apply(const cd* in, cd* out
   cd* Y = pcs + 2 * N;
   const cd* src = in + (size_t)f * 2 * N;  // phi_f then varphi_f
   for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) X[i] = src[i];
+  // with one mode per thread (N <= PC_THREADS) the mode block's loads are
+  // issued now and land while the forward transforms run
+  const bool one = N <= (int)blockDim.x;
+  const int kk = threadIdx.x;
+  cd c0 = mkc(0, 0), c1 = c0, c2 = c0, c3 = c0;
+  if (one && kk < N) {
+    const cd* c = coef + ((size_t)f * N + kk) * 4;
+    c0 = c[0]; c1 = c[1]; c2 = c[2]; c3 = c[3];
+  }
   __syncthreads();
   cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
-  for (int kk = threadIdx.x; kk < N; kk += blockDim.x) {
-    const cd* c = coef + ((size_t)f * N + kk) * 4;
-    const cd u = H[kk], v = H[N + kk];
-    H[kk] = cadd(cmul(c[0], u), cmul(c[1], v));
-    H[N + kk] = cadd(cmul(c[2], u), cmul(c[3], v));
+  if (one) {
+    if (kk < N) {
+      const cd u = H[kk], v = H[N + kk];
+      H[kk] = cadd(cmul(c0, u), cmul(c1, v));
+      H[N + kk] = cadd(cmul(c2, u), cmul(c3, v));
+    }
+  } else {
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+      const cd* c = coef + ((size_t)f * N + m) * 4;
+      const cd u = H[m], v = H[N + m];
+      H[m] = cadd(cmul(c[0], u), cmul(c[1], v));
+      H[N + m] = cadd(cmul(c[2], u), cmul(c[3], v));
+    }
   }
   __syncthreads();
   const cd* Z = pc_fft(H, H == X ? Y : X, 2, N, logN, tw, false);
