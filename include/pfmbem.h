@@ -293,6 +293,10 @@ typedef struct {
   int m2l_mfma_items;          /* M2L matrix products on the matrix cores (m2l_vector = 0) */
   int m2l_vector_chunks;       /* M2L entry chunks on the vector ALU */
   int m2l_mfma_entries;        /* M2L entries in those products (columns) */
+  int precond_in_apply;        /* 1: a preconditioned solve applies P^{-1} inside the apply's forward
+                                  transforms (roots by Fourier modes, and no tree fibres, stored near
+                                  pairs or other reader of the densities): one launch fewer per
+                                  iteration; 0: a separate launch before each apply */
 } pfm_stats;
 
 /* Build the plan: discretisation, quadtrees and interaction lists (on the

@@ -1475,6 +1475,15 @@ struct GmresStats {
 
 // Batched apply of the current batch: from the captured graph (fixed in/out
 // buffers, copies around it) or launched kernel by kernel.
+// Whether right preconditioning can run inside the apply: with the roots by
+// Fourier modes the fibres' forward transforms are the only reader of the
+// densities unless a fibre has tree work (cells below its root, down leaves)
+// or there are stored near pairs (row tasks, batched P2P); then P^{-1} z is
+// needed only as its spectrum, the mode blocks of P^{-1} times that of z.
+bool pc_fusable(const Problem& pb) {
+  return pb.spec_root && pb.n_mcells == 0 && pb.n_dleaves == 0 && pb.n_p2p_rowtasks == 0 && pb.n_p2p_items == 0;
+}
+
 hipError_t batch_apply(Problem& pb, const cd* in, cd* out) {
   if (!pb.graph) return apply_operator_batch(pb, in, out, nullptr);
   const size_t bytes = (size_t)pb.B * 2 * pb.E * sizeof(cd);
@@ -1902,7 +1911,14 @@ pfm_status pfm_solve(pfm_problem* h, const void* d_b_in, void* d_x_io, int use_x
       // the reported residual are those of the unpreconditioned system.  A
       // start vector or an augmenting guess u enters as P u, since
       // (I - A) P^{-1} (P u) = (I - A) u.
+      const bool fused = pc_fusable(pb);
       auto apply_pc = [&](const cd* in, cd* out) -> hipError_t {
+        if (fused) {
+          pb.pc_fused_inv = pb.d_pc_inv;
+          hipError_t e = apply_operator(pb, in, out, nullptr);
+          pb.pc_fused_inv = nullptr;
+          return e;
+        }
         hipError_t e = launch_precond(pb, in, pb.d_pc_x, true);
         if (e == hipSuccess) e = apply_operator(pb, pb.d_pc_x, out, nullptr);
         return e;
@@ -1973,7 +1989,15 @@ pfm_status pfm_solve_batch(pfm_problem* h, const void* d_b_in, void* d_x_io, int
     // depend on the angle), and the preconditioner runs ahead of the
     // (possibly graph-replayed) batched apply
     cd* x = (cd*)d_x_io;
+    // (a replayed graph holds its launches' arguments: it keeps the separate launch)
+    const bool fused = !pb.graph && pc_fusable(pb);
     auto apply_pc = [&](const cd* in, cd* out) -> hipError_t {
+      if (fused) {
+        pb.pc_fused_inv = pb.d_pc_inv;
+        hipError_t e = batch_apply(pb, in, out);
+        pb.pc_fused_inv = nullptr;
+        return e;
+      }
       hipError_t e = launch_precond(pb, in, pb.d_pc_x, true, pb.B);
       if (e == hipSuccess) e = batch_apply(pb, pb.d_pc_x, out);
       return e;
@@ -2130,6 +2154,7 @@ pfm_status pfm_get_stats(const pfm_problem* h, pfm_stats* st) {
   st->self_fft = pb.self_fft ? 1 : 0;
   st->tree_on_device = pb.tree_on_device ? 1 : 0;
   st->spectral_roots = pb.spec_root ? 1 : 0;
+  st->precond_in_apply = pb.opt.precond && pc_fusable(pb) ? 1 : 0;
   st->n_spectral_fibres = pb.spec_root ? pb.n_spec : 0;
   st->m2l_mfma_items = pb.n_mfma_items;
   st->m2l_vector_chunks = pb.n_vchunks;

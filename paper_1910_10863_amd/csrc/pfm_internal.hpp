@@ -129,6 +129,10 @@ struct Problem {
   // block-Jacobi preconditioner (options.precond): for each fibre and Fourier
   // mode kappa of the element index, the 2x2 block of P and of P^{-1}
   cd *d_pc_fwd = nullptr, *d_pc_inv = nullptr;   // [fibre][kappa][4]
+  // right preconditioning inside the apply: P^{-1}'s mode blocks while a
+  // preconditioned GMRES applies its operator, nullptr otherwise (see
+  // pc_fusable)
+  const cd* pc_fused_inv = nullptr;
   cd *d_pc_tw = nullptr;                // [N]: exp(2 pi i j / N)
   cd *d_pc_x = nullptr;                 // [2 M N]: P^{-1} v inside the preconditioned apply
   int pc_logN = 0;

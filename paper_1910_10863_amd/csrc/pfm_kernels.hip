@@ -2491,7 +2491,8 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
                                                          const cd* __restrict__ rtab, cd* __restrict__ mpole,
                                                          long long mp_stride, const int4* __restrict__ mcell,
                                                          const int* __restrict__ psi_idx,
-                                                         const cd* __restrict__ p2m_tab) {
+                                                         const cd* __restrict__ p2m_tab,
+                                                         const cd* __restrict__ pinv) {
   constexpr int NP = 2 * P + 1;
   extern __shared__ cd pcs[];
   // workgroups: the tree fibres' cells' P2M first (the longest), then the
@@ -2534,8 +2535,25 @@ __global__ void __launch_bounds__(PC_THREADS) k_self_fwd(const cd* __restrict__ 
     ta = T[kk];
     tb = T[NP + kk];
   }
+  // right preconditioning fused into the apply (pinv != nullptr, only when
+  // no kernel of the apply reads the densities themselves): the input is
+  // z and the operator acts on P^{-1} z, whose spectrum is the fibre's mode
+  // blocks of P^{-1} times that of z
+  cd q0 = mkc(0, 0), q1 = q0, q2 = q0, q3 = q0;
+  if (pinv && kk < N) {
+    const cd* q = pinv + ((size_t)f * N + kk) * 4;
+    q0 = q[0]; q1 = q[1]; q2 = q[2]; q3 = q[3];
+  }
   __syncthreads();
-  const cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
+  cd* H = pc_fft(X, Y, 2, N, logN, tw, true);
+  if (pinv) {
+    if (kk < N) {
+      const cd u = H[kk], v = H[N + kk];
+      H[kk] = cadd(cmul(q0, u), cmul(q1, v));
+      H[N + kk] = cadd(cmul(q2, u), cmul(q3, v));
+    }
+    __syncthreads();
+  }
   // the root's exterior moments of order n = kk - p from the two densities'
   // transforms and the fibre's table row (A_n, B_n): M_n = A_n phihat(n mod N)
   // + B_n varphihat(n mod N)
@@ -3177,7 +3195,7 @@ static hipError_t apply_spectral(Problem& pb, const C* blocks, const cd* d_psi, 
                        reinterpret_cast<const int4*>(pb.d_p2p_rowtasks), pb.d_p2p_rowoff, ntask, ntb, pb.d_col_psi,
                        blocks, pb.d_near_rows, pb.d_spec_tab, pb.d_mpole, bs.mpole,
                        reinterpret_cast<const int4*>(pb.d_mcell), pb.d_psi_idx,
-                       pb.d_p2m_tab);
+                       pb.d_p2m_tab, pb.pc_fused_inv);
   }
   if (ev) (void)hipEventRecord(ev[1], pb.stream);
   for (int r = 0; r < times(1); ++r) fmm_chain<P>(pb, d_psi, pb.stream, nullptr, false, nb, nullptr, nullptr, false, 1, 1);

@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("n_device_allocs", ctypes.c_longlong), ("device_alloc_bytes", ctypes.c_double),
                 ("self_fft", ctypes.c_int), ("tree_on_device", ctypes.c_int), ("spectral_roots", ctypes.c_int),
                 ("n_spectral_fibres", ctypes.c_int), ("m2l_mfma_items", ctypes.c_int),
-                ("m2l_vector_chunks", ctypes.c_int), ("m2l_mfma_entries", ctypes.c_int)]
+                ("m2l_vector_chunks", ctypes.c_int), ("m2l_mfma_entries", ctypes.c_int),
+                ("precond_in_apply", ctypes.c_int)]
 
 
 CHORDS = 0

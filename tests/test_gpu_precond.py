@@ -154,6 +154,32 @@ def test_precond_square_8x8_full_size(pfm):
     assert res[True][1] < res[False][1]
 
 
+@pytest.mark.parametrize("key,fused", [("sq2x2", 1), ("hex2x2", 1), ("sq2x2close", 0)])
+def test_precond_inside_apply(pfm, key, fused):
+    """With the roots by Fourier modes and no tree fibres or stored near
+    pairs, a preconditioned solve applies P^{-1} in the forward transforms of
+    the apply (no separate launch); close fibres keep the separate launch.
+    Either way the preconditioned solve matches dense LU, and the fused one
+    the unpreconditioned solve's solution."""
+    from oracle import system as sy
+    wl, ka, th = _WL[key]
+    pb = sy.problem_from_workload(wl, ka, th)
+    ref = np.linalg.solve(sy.dense_matrix(pb), sy.rhs(pb))
+    xs = {}
+    for pc in (False, True):
+        prob = pfm.Problem.from_workload(wl, p=40, leaf_max=16, tol=1e-12, restart=100, precond=pc)
+        prob.set_wave(ka, th)
+        assert prob.stats()["precond_in_apply"] == (fused if pc else 0)
+        x, info = prob.solve()
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-12
+        xs[pc] = x.cpu().numpy()
+        prob.close()
+    err = np.linalg.norm(xs[True] - ref) / np.linalg.norm(ref)
+    diff = np.linalg.norm(xs[True] - xs[False]) / np.linalg.norm(xs[False])
+    _say("precond inside apply:", key, fused, "err vs LU", err, "vs plain", diff)
+    assert err < 1e-8 and diff < 1e-9
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_precond_batch_solve_vs_dense_lu(pfm, use_graph):
     """Batched solves share P across the angles of a frequency (the blocks
