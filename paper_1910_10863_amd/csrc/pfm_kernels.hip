@@ -715,7 +715,8 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
-constexpr int LAT_MAX_NT = 4 * 40 + 1;
+constexpr int LAT_MAX_P = 40;           // largest expansion order (the options accept p <= 40)
+constexpr int LAT_MAX_NT = 4 * LAT_MAX_P + 1;
 constexpr int LT_NB = 4;                 // orders per LDS round of k_lattice_tails
 
 __global__ void __launch_bounds__(256) k_lattice_tails(int P, int n_roff, const double* __restrict__ roff,
@@ -810,7 +811,7 @@ __global__ void __launch_bounds__(128) k_lattice_direct(int P, int n_roff, const
                                                         const double* __restrict__ betas, int q, int n_rblk,
                                                         const cd* __restrict__ partial, cd* out,
                                                         long long out_stride) {
-  __shared__ cd sH[LD_CH][2 * 40 + 1];
+  __shared__ cd sH[LD_CH][2 * LAT_MAX_P + 1];
   __shared__ cd sAl[LD_CH];
   __shared__ double sTh[LD_CH];
   const int o = blockIdx.x, mb = blockIdx.y;
